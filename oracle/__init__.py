@@ -1,0 +1,340 @@
+"""CPU oracle for the weighted SIPG convection-diffusion-reaction operator of
+Muething, Piatkowski & Bastian, "High-performance Implementation of
+Matrix-free High-order Discontinuous Galerkin Methods" (arXiv 1711.10885).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by the
+CPU-baseline leg of the benchmark, never by the product library.  It shares no
+code with the HIP path; both sides receive the same plain arrays from the
+seeded input generators.
+
+Contents
+--------
+* ``apply`` / ``apply_rows`` -- y = A x of eq. (blf), Sec. 2.2, by the plain
+  quadrature definition (C, ``dg_oracle.c``), Algorithm 1 of Sec. 3.6 order.
+* ``rhs`` / ``l2err`` -- load vector (f, phi_j) of the right-hand-side
+  functional (Sec. 2.2, g = 0) and the L2 error of a coefficient vector.
+* ``gauss`` / ``basis`` -- the 1D Gauss rule and orthonormal Legendre basis
+  (Sec. 3.1; "L2-orthogonal Legendre polynomials" of Sec. 2.2).
+* ``assemble`` -- the sparse matrix of the operator by probing ``apply`` with
+  coloured unit vectors (the DG coupling is face-local, Sec. 2.2).
+* ``block_diagonal`` -- the per-cell diagonal blocks A_TT of the same operator.
+* ``gmres`` -- restarted, right-preconditioned GMRES in float64 (numpy).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "dg_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libdg_oracle.so")
+
+VOLUME, INTERIOR, BOUNDARY = 1, 2, 4
+ALL_TERMS = VOLUME | INTERIOR | BOUNDARY
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (-O2, OpenMP, no intrinsics)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-D_GNU_SOURCE",
+               _SRC, "-o", tmp, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [
+        ("ncell", ctypes.c_int32 * 3),
+        ("nodes", ctypes.POINTER(ctypes.c_double) * 3),
+        ("k", ctypes.c_int32),
+        ("K", ctypes.c_double * 9),
+        ("kappa", ctypes.POINTER(ctypes.c_double)),
+        ("b_const", ctypes.c_double * 3),
+        ("b_sin", ctypes.c_double * 3),
+        ("b_axis", ctypes.c_int32 * 3),
+        ("c", ctypes.c_double),
+        ("sigma", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.POINTER(_Problem)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.oracle_apply.argtypes = [P, dp, dp, ctypes.c_int, ctypes.c_int]
+        lib.oracle_apply_rows.argtypes = [P, dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64,
+                                          dp, ctypes.c_int, ctypes.c_int]
+        lib.oracle_rhs.argtypes = [P, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_int32), dp,
+                                   ctypes.c_int]
+        lib.oracle_l2err2.argtypes = [P, dp, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_int32)]
+        lib.oracle_l2err2.restype = ctypes.c_double
+        lib.oracle_gauss.argtypes = [ctypes.c_int, dp, dp]
+        lib.oracle_basis.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp]
+        lib.oracle_ndof.argtypes = [P]
+        lib.oracle_ndof.restype = ctypes.c_int64
+        lib.oracle_num_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class _Marshalled:
+    """Keeps the numpy arrays referenced by a _Problem alive."""
+
+    def __init__(self, prob):
+        self.nodes = [np.ascontiguousarray(prob.nodes[a], dtype=np.float64) for a in range(3)]
+        self.kappa = (None if prob.kappa is None
+                      else np.ascontiguousarray(prob.kappa, dtype=np.float64).ravel())
+        s = _Problem()
+        for a in range(3):
+            s.ncell[a] = int(prob.ncell[a])
+            s.nodes[a] = _dptr(self.nodes[a])
+            s.b_const[a] = float(prob.b_const[a])
+            s.b_sin[a] = float(prob.b_sin[a])
+            s.b_axis[a] = int(prob.b_axis[a])
+        s.k = int(prob.k)
+        K = np.asarray(prob.K, dtype=np.float64).reshape(9)
+        for i in range(9):
+            s.K[i] = float(K[i])
+        s.kappa = _dptr(self.kappa) if self.kappa is not None else ctypes.POINTER(ctypes.c_double)()
+        s.c = float(prob.c)
+        s.sigma = float(prob.sigma)
+        self.struct = s
+
+
+def default_threads() -> int:
+    return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+
+def ndof(prob) -> int:
+    n = prob.k + 1
+    return int(prob.ncell[0] * prob.ncell[1] * prob.ncell[2] * n ** 3)
+
+
+def apply(prob, x: np.ndarray, terms: int = ALL_TERMS, nthreads: int | None = None) -> np.ndarray:
+    """y = A x (eq. (blf) with tensor Gauss quadrature, Algorithm 1)."""
+    lib = _load()
+    m = _Marshalled(prob)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    if x.size != ndof(prob):
+        raise ValueError("x has wrong size")
+    y = np.empty_like(x)
+    rc = lib.oracle_apply(ctypes.byref(m.struct), _dptr(x), _dptr(y), int(terms),
+                          int(nthreads or default_threads()))
+    if rc != 0:
+        raise ValueError("oracle_apply rejected the problem")
+    return y
+
+
+def apply_rows(prob, x: np.ndarray, cells, terms: int = ALL_TERMS,
+               nthreads: int | None = None) -> np.ndarray:
+    """Rows of A x for the listed cells; shape (len(cells), n^3)."""
+    lib = _load()
+    m = _Marshalled(prob)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    if x.size != ndof(prob):
+        raise ValueError("x has wrong size")
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    nb = (prob.k + 1) ** 3
+    y = np.empty((cells.size, nb), dtype=np.float64)
+    rc = lib.oracle_apply_rows(ctypes.byref(m.struct), _dptr(x),
+                               cells.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                               int(cells.size), _dptr(y), int(terms),
+                               int(nthreads or default_threads()))
+    if rc != 0:
+        raise ValueError("oracle_apply_rows rejected its arguments")
+    return y
+
+
+def _terms(terms):
+    alpha = np.ascontiguousarray([t[0] for t in terms], dtype=np.float64)
+    kinds = np.ascontiguousarray([t[1] for t in terms], dtype=np.int32).reshape(-1, 3)
+    return alpha, kinds
+
+
+def rhs(prob, source_terms, nthreads: int | None = None) -> np.ndarray:
+    """Load vector f_{T,j} = (f, phi_j)_T for f = sum alpha * g1(x) g2(y) g3(z)."""
+    lib = _load()
+    m = _Marshalled(prob)
+    alpha, kinds = _terms(source_terms)
+    f = np.empty(ndof(prob), dtype=np.float64)
+    rc = lib.oracle_rhs(ctypes.byref(m.struct), int(alpha.size), _dptr(alpha),
+                        kinds.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dptr(f),
+                        int(nthreads or default_threads()))
+    if rc != 0:
+        raise ValueError("oracle_rhs rejected the problem")
+    return f
+
+
+def l2err(prob, x: np.ndarray, exact_terms) -> float:
+    lib = _load()
+    m = _Marshalled(prob)
+    alpha, kinds = _terms(exact_terms)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    e2 = lib.oracle_l2err2(ctypes.byref(m.struct), _dptr(x), int(alpha.size), _dptr(alpha),
+                           kinds.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), )
+    return float(np.sqrt(e2))
+
+
+def gauss(m: int):
+    lib = _load()
+    xi = np.empty(m)
+    w = np.empty(m)
+    if lib.oracle_gauss(int(m), _dptr(xi), _dptr(w)) != 0:
+        raise ValueError("bad m")
+    return xi, w
+
+
+def basis(k: int, t: float):
+    lib = _load()
+    v = np.empty(k + 1)
+    d = np.empty(k + 1)
+    lib.oracle_basis(int(k), float(t), _dptr(v), _dptr(d))
+    return v, d
+
+
+def _cell_colour3(prob):
+    """Colour of each cell under i_a mod 3 in every direction (27 colours):
+    cells of one colour share no face neighbour, so probing one colour at a
+    time separates the columns of every face-coupled pair."""
+    N1, N2, N3 = prob.ncell
+    i1, i2, i3 = np.meshgrid(np.arange(N1), np.arange(N2), np.arange(N3), indexing="ij")
+    col = (i1 % 3) + 3 * (i2 % 3) + 9 * (i3 % 3)
+    return col.transpose(2, 1, 0).ravel()  # cell id order: axis 1 fastest
+
+
+def assemble(prob, terms: int = ALL_TERMS, nthreads: int | None = None):
+    """Sparse matrix of the operator, column by column from ``apply``.
+
+    Column (T, j) of A is supported on T and its face neighbours.  All cells of
+    one i mod 3 colour are probed with e_j at once; the rows of each probed
+    cell's 3x3x3 neighbourhood are then attributed to it unambiguously."""
+    import scipy.sparse as sp
+
+    nb = (prob.k + 1) ** 3
+    N1, N2, N3 = prob.ncell
+    ncells = N1 * N2 * N3
+    col = _cell_colour3(prob)
+    cid = np.arange(ncells)
+    ci = np.stack([cid % N1, (cid // N1) % N2, cid // (N1 * N2)], axis=1)
+    rows_all, cols_all, vals_all = [], [], []
+    for colour in range(27):
+        probed = np.nonzero(col == colour)[0]
+        if probed.size == 0:
+            continue
+        for j in range(nb):
+            x = np.zeros(ncells * nb)
+            x[probed * nb + j] = 1.0
+            y = apply(prob, x, terms, nthreads).reshape(ncells, nb)
+            # each row cell R takes its value from the probed cell in its
+            # neighbourhood (at most one per colour, by construction)
+            for d in ((0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1),
+                      (0, 0, -1)):
+                nbr = ci[probed] + np.array(d)
+                ok = np.all((nbr >= 0) & (nbr < np.array([N1, N2, N3])), axis=1)
+                src = probed[ok]
+                dst = nbr[ok, 0] + N1 * (nbr[ok, 1] + N2 * nbr[ok, 2])
+                blk = y[dst]  # (len, nb)
+                r = (dst[:, None] * nb + np.arange(nb)[None, :]).ravel()
+                c = np.repeat(src * nb + j, nb)
+                v = blk.ravel()
+                nz = v != 0.0
+                rows_all.append(r[nz])
+                cols_all.append(c[nz])
+                vals_all.append(v[nz])
+    n = ncells * nb
+    return sp.csr_matrix((np.concatenate(vals_all), (np.concatenate(rows_all),
+                                                     np.concatenate(cols_all))), shape=(n, n))
+
+
+def block_diagonal(prob, nthreads: int | None = None) -> np.ndarray:
+    """Diagonal blocks A_TT (ncells, n^3, n^3): a_h(phi_j, phi_i) for i, j in T.
+
+    Face neighbours differ in exactly one index by one, so the two parity
+    classes of i1+i2+i3 never touch: probing one class at a time with e_j
+    leaves, in the rows of a probed cell, exactly column j of its block."""
+    nb = (prob.k + 1) ** 3
+    N1, N2, N3 = prob.ncell
+    ncells = N1 * N2 * N3
+    cid = np.arange(ncells)
+    par = ((cid % N1) + ((cid // N1) % N2) + (cid // (N1 * N2))) % 2
+    B = np.zeros((ncells, nb, nb))
+    for p in (0, 1):
+        probed = np.nonzero(par == p)[0]
+        for j in range(nb):
+            x = np.zeros(ncells * nb)
+            x[probed * nb + j] = 1.0
+            y = apply(prob, x, ALL_TERMS, nthreads).reshape(ncells, nb)
+            B[probed, :, j] = y[probed]
+    return B
+
+
+def gmres(matvec, b: np.ndarray, x0=None, tol: float = 1e-8, restart: int = 30,
+          maxit: int = 10000, precond=None):
+    """Restarted GMRES(restart) with right preconditioning, float64.
+
+    Arnoldi with modified Gram-Schmidt and Givens rotations (Saad, Iterative
+    Methods for Sparse Linear Systems, Alg. 6.9/9.5).  Stops when the true
+    residual ||b - A x|| / ||b|| <= tol, checked at every restart.
+    Returns (x, iterations, relative residual)."""
+    M = precond if precond is not None else (lambda v: v)
+    x = np.zeros_like(b) if x0 is None else x0.astype(np.float64).copy()
+    bnorm = np.linalg.norm(b)
+    if bnorm == 0.0:
+        return np.zeros_like(b), 0, 0.0
+    it = 0
+    while True:
+        r = b - matvec(x)
+        beta = np.linalg.norm(r)
+        if beta / bnorm <= tol or it >= maxit:
+            return x, it, beta / bnorm
+        V = [r / beta]
+        Z = []
+        H = np.zeros((restart + 1, restart))
+        cs = np.zeros(restart)
+        sn = np.zeros(restart)
+        g = np.zeros(restart + 1)
+        g[0] = beta
+        j_done = 0
+        for j in range(restart):
+            z = M(V[j])
+            Z.append(z)
+            w = matvec(z)
+            for i in range(j + 1):
+                H[i, j] = np.dot(w, V[i])
+                w = w - H[i, j] * V[i]
+            hn = np.linalg.norm(w)
+            H[j + 1, j] = hn
+            for i in range(j):
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t
+            den = np.hypot(H[j, j], H[j + 1, j])
+            cs[j], sn[j] = H[j, j] / den, H[j + 1, j] / den
+            H[j, j] = den
+            H[j + 1, j] = 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            it += 1
+            j_done = j + 1
+            if abs(g[j + 1]) / bnorm <= tol or it >= maxit or hn == 0.0:
+                break
+            V.append(w / hn)
+        y = np.linalg.solve(np.triu(H[:j_done, :j_done]), g[:j_done])
+        for i in range(j_done):
+            x = x + y[i] * Z[i]

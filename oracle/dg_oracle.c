@@ -1,0 +1,571 @@
+/*
+ * dg_oracle.c -- plain, slow, obviously correct CPU oracle for the matrix-free
+ * weighted SIPG operator of Muething, Piatkowski & Bastian (arXiv 1711.10885).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path links, loads or calls
+ * this file; only tests/, the smoke check and the CPU-baseline leg of the
+ * benchmark do.  It shares no code, header, table or constant with the HIP
+ * library.
+ *
+ * What it computes: y = A x with A_ij = a_h^Q(phi_j, phi_i), the bilinear form
+ * of eq. (blf) in Sec. 2.2, with every volume and face integral replaced by the
+ * tensor Gauss rule with m = k+1 points per direction (Problem A of Sec. 5.1
+ * uses q = 2p, i.e. n = m = p+1).  Sum factorization (Sec. 3.5) is an exact
+ * re-bracketing of these quadrature sums, so the oracle does NOT use it: at
+ * every quadrature point the finite element function and its gradient are
+ * evaluated by the full sum over all n^3 shape functions (eq. (evalfe) read
+ * literally), and every test function is integrated point by point
+ * (eq. (evalblf) read literally).  Cost O(n^3 m^3) per cell.
+ *
+ * Readings of the paper taken here (each listed in the design notes):
+ *  - reference cube [0,1]^3, orthonormal Legendre basis
+ *      theta_j(t) = sqrt(2j+1) P_j(2t-1)          (Sec. 2.2 "L2-orthogonal
+ *      Legendre polynomials", Sec. 3.1 tensor product shape functions);
+ *  - weighted average {v}_w = w- v- + w+ v+ (the printed minus sign in Sec. 2.2
+ *    contradicts the convex weights given right after it);
+ *  - penalty gamma_F = sigma * <delta-,delta+> / min(h_a-, h_a+) on interior
+ *    faces (sigma absorbs alpha*p*(p+d-1); |F|/min|T| = 1/min h_a on a tensor
+ *    grid), gamma_F = sigma * delta- / h_a- on boundary faces;
+ *  - every boundary face is homogeneous Dirichlet (g = 0), so the boundary
+ *    upwind term is Phi(u,0,b_nu) (F^{DO} sum of eq. (blf)) and the boundary
+ *    consistency/symmetry/penalty terms use [[v]] = {v} = v-;
+ *  - D = kappa_T K with K constant SPD and kappa_T > 0 constant per cell;
+ *  - b_r(x) = b_const[r] + b_sin[r] * sin(pi * x_{b_axis[r]}).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_MAXN 11 /* k <= 10 */
+
+typedef struct {
+  int32_t ncell[3];
+  const double *nodes[3]; /* length ncell[a]+1, strictly increasing */
+  int32_t k;
+  double K[9]; /* row-major, constant SPD */
+  const double *kappa; /* per cell (axis-1 fastest) or NULL for 1 */
+  double b_const[3];
+  double b_sin[3];
+  int32_t b_axis[3];
+  double c;
+  double sigma;
+} or_problem;
+
+/* term mask for or_apply: which sums of eq. (blf) to include */
+#define OR_VOLUME 1
+#define OR_INTERIOR 2
+#define OR_BOUNDARY 4
+
+/* ------------------------------------------------------------------------ */
+/* 1D building blocks                                                       */
+/* ------------------------------------------------------------------------ */
+
+/* Legendre polynomials P_0..P_k and their derivatives at s in [-1,1] by the
+ * three-term recurrence (j+1) P_{j+1} = (2j+1) s P_j - j P_{j-1} and
+ * P'_{j+1} = P'_{j-1} + (2j+1) P_j. */
+static void legendre_all(int k, double s, double *P, double *dP) {
+  P[0] = 1.0;
+  dP[0] = 0.0;
+  if (k >= 1) {
+    P[1] = s;
+    dP[1] = 1.0;
+  }
+  for (int j = 1; j < k; ++j) {
+    P[j + 1] = ((2.0 * j + 1.0) * s * P[j] - j * P[j - 1]) / (j + 1.0);
+    dP[j + 1] = dP[j - 1] + (2.0 * j + 1.0) * P[j];
+  }
+}
+
+/* m-point Gauss-Legendre rule on [0,1] (Sec. 3.1, tensor Gauss quadrature):
+ * nodes are the roots of P_m(2t-1), found by Newton's method; weights
+ * 2/((1-s^2) P_m'(s)^2) on [-1,1], halved for [0,1].  Ascending order. */
+int oracle_gauss(int m, double *xi, double *w) {
+  if (m < 1 || m > 64) return -1;
+  double P[66], dP[66];
+  for (int i = 0; i < m; ++i) {
+    /* root number i counted from s = +1 downwards */
+    double s = cos(M_PI * (i + 0.75) / (m + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      legendre_all(m, s, P, dP);
+      double ds = P[m] / dP[m];
+      s -= ds;
+      if (fabs(ds) < 1e-16) break;
+    }
+    legendre_all(m, s, P, dP);
+    double ws = 2.0 / ((1.0 - s * s) * dP[m] * dP[m]);
+    /* store ascending in t = (1+s)/2 */
+    xi[m - 1 - i] = 0.5 * (1.0 + s);
+    w[m - 1 - i] = 0.5 * ws;
+  }
+  return 0;
+}
+
+/* Orthonormal Legendre basis on [0,1] and its derivative at t:
+ * theta_j(t) = sqrt(2j+1) P_j(2t-1), theta_j'(t) = 2 sqrt(2j+1) P_j'(2t-1). */
+void oracle_basis(int k, double t, double *val, double *der) {
+  double P[OR_MAXN + 1], dP[OR_MAXN + 1];
+  legendre_all(k, 2.0 * t - 1.0, P, dP);
+  for (int j = 0; j <= k; ++j) {
+    double sc = sqrt(2.0 * j + 1.0);
+    val[j] = sc * P[j];
+    der[j] = 2.0 * sc * dP[j];
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Per-problem tables                                                       */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  int n, m;
+  double xi[OR_MAXN], w[OR_MAXN];
+  double V[OR_MAXN][OR_MAXN]; /* V[q][j] = theta_j(xi_q)  */
+  double D[OR_MAXN][OR_MAXN]; /* D[q][j] = theta_j'(xi_q) */
+  double V0[OR_MAXN], V1[OR_MAXN]; /* theta_j(0), theta_j(1)   */
+  double D0[OR_MAXN], D1[OR_MAXN]; /* theta_j'(0), theta_j'(1) */
+} or_tables;
+
+static void make_tables(int k, or_tables *t) {
+  t->n = k + 1;
+  t->m = k + 1;
+  oracle_gauss(t->m, t->xi, t->w);
+  for (int q = 0; q < t->m; ++q) oracle_basis(k, t->xi[q], t->V[q], t->D[q]);
+  oracle_basis(k, 0.0, t->V0, t->D0);
+  oracle_basis(k, 1.0, t->V1, t->D1);
+}
+
+static double coef_b(const or_problem *p, int r, const double *xp) {
+  return p->b_const[r] + p->b_sin[r] * sin(M_PI * xp[p->b_axis[r]]);
+}
+
+static double cell_kappa(const or_problem *p, int64_t c) {
+  return p->kappa ? p->kappa[c] : 1.0;
+}
+
+static int64_t cell_id(const or_problem *p, const int *i) {
+  return (int64_t)i[0] + (int64_t)p->ncell[0] * ((int64_t)i[1] + (int64_t)p->ncell[1] * i[2]);
+}
+
+static void cell_geom(const or_problem *p, const int *i, double *o, double *h) {
+  for (int a = 0; a < 3; ++a) {
+    o[a] = p->nodes[a][i[a]];
+    h[a] = p->nodes[a][i[a] + 1] - p->nodes[a][i[a]];
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Volume term of eq. (blf):  (D grad u - b u, grad v)_T + (c u, v)_T       */
+/* evaluated by the tensor Gauss rule (eq. (evalblf), eq. (gauss_points)).  */
+/* ------------------------------------------------------------------------ */
+static void volume_cell(const or_problem *p, const or_tables *t, const int *ic,
+                        const double *xT, double *yT) {
+  const int n = t->n, m = t->m;
+  double o[3], h[3];
+  cell_geom(p, ic, o, h);
+  const double vol = h[0] * h[1] * h[2];
+  const double kap = cell_kappa(p, cell_id(p, ic));
+  for (int q3 = 0; q3 < m; ++q3)
+    for (int q2 = 0; q2 < m; ++q2)
+      for (int q1 = 0; q1 < m; ++q1) {
+        const int q[3] = {q1, q2, q3};
+        /* u and its physical gradient at the point: full sum over shape
+         * functions phi_j = theta_j1 theta_j2 theta_j3 (eq. (evalfe)). */
+        double u = 0.0, g[3] = {0.0, 0.0, 0.0};
+        for (int j3 = 0; j3 < n; ++j3)
+          for (int j2 = 0; j2 < n; ++j2)
+            for (int j1 = 0; j1 < n; ++j1) {
+              const double xj = xT[j1 + n * (j2 + n * j3)];
+              const double v1 = t->V[q1][j1], v2 = t->V[q2][j2], v3 = t->V[q3][j3];
+              const double d1 = t->D[q1][j1], d2 = t->D[q2][j2], d3 = t->D[q3][j3];
+              u += xj * v1 * v2 * v3;
+              g[0] += xj * d1 * v2 * v3 / h[0];
+              g[1] += xj * v1 * d2 * v3 / h[1];
+              g[2] += xj * v1 * v2 * d3 / h[2];
+            }
+        double xp[3];
+        for (int a = 0; a < 3; ++a) xp[a] = o[a] + h[a] * t->xi[q[a]];
+        double F[3];
+        for (int r = 0; r < 3; ++r) {
+          double s = 0.0;
+          for (int c = 0; c < 3; ++c) s += kap * p->K[3 * r + c] * g[c];
+          F[r] = s - coef_b(p, r, xp) * u;
+        }
+        const double W = t->w[q1] * t->w[q2] * t->w[q3] * vol;
+        /* integrate against every test function */
+        for (int j3 = 0; j3 < n; ++j3)
+          for (int j2 = 0; j2 < n; ++j2)
+            for (int j1 = 0; j1 < n; ++j1) {
+              const double v1 = t->V[q1][j1], v2 = t->V[q2][j2], v3 = t->V[q3][j3];
+              const double d1 = t->D[q1][j1], d2 = t->D[q2][j2], d3 = t->D[q3][j3];
+              const double phi = v1 * v2 * v3;
+              const double gphi[3] = {d1 * v2 * v3 / h[0], v1 * d2 * v3 / h[1],
+                                      v1 * v2 * d3 / h[2]};
+              yT[j1 + n * (j2 + n * j3)] +=
+                  W * (F[0] * gphi[0] + F[1] * gphi[1] + F[2] * gphi[2] + p->c * u * phi);
+            }
+      }
+}
+
+/* Value and physical gradient of the shape function j of a cell at the face
+ * point with reference coordinate e on axis a (e in {0,1}) and Gauss nodes
+ * qt[0], qt[1] on the two tangential axes tb < tc. */
+static void shape_on_face(const or_tables *t, int a, int e, int tb, int tc, int qb, int qc,
+                          const int *j, const double *h, double *phi, double *gphi) {
+  double val[3], der[3];
+  val[a] = e ? t->V1[j[a]] : t->V0[j[a]];
+  der[a] = e ? t->D1[j[a]] : t->D0[j[a]];
+  val[tb] = t->V[qb][j[tb]];
+  der[tb] = t->D[qb][j[tb]];
+  val[tc] = t->V[qc][j[tc]];
+  der[tc] = t->D[qc][j[tc]];
+  *phi = val[0] * val[1] * val[2];
+  gphi[0] = der[0] * val[1] * val[2] / h[0];
+  gphi[1] = val[0] * der[1] * val[2] / h[1];
+  gphi[2] = val[0] * val[1] * der[2] / h[2];
+}
+
+/* u and physical gradient of the FE function of one cell at a face point */
+static void eval_on_face(const or_tables *t, int a, int e, int tb, int tc, int qb, int qc,
+                         const double *h, const double *xT, double *u, double *g) {
+  const int n = t->n;
+  *u = 0.0;
+  g[0] = g[1] = g[2] = 0.0;
+  for (int j3 = 0; j3 < n; ++j3)
+    for (int j2 = 0; j2 < n; ++j2)
+      for (int j1 = 0; j1 < n; ++j1) {
+        const int j[3] = {j1, j2, j3};
+        double phi, gphi[3];
+        shape_on_face(t, a, e, tb, tc, qb, qc, j, h, &phi, gphi);
+        const double xj = xT[j1 + n * (j2 + n * j3)];
+        *u += xj * phi;
+        for (int r = 0; r < 3; ++r) g[r] += xj * gphi[r];
+      }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Interior face F between Tm = T^-(F) (index i_a) and Tp = T^+(F) (index    */
+/* i_a+1), normal nu = +e_a (Sec. 2.2).  Terms of eq. (blf):                 */
+/*   (Phi(u-,u+,b.nu), [[v]])_F - (nu.{D grad u}_w, [[v]])_F                 */
+/*   - (nu.{D grad v}_w, [[u]])_F + gamma_F ([[u]], [[v]])_F                 */
+/* with [[v]] = v- - v+, {v}_w = w- v- + w+ v+, w- = d+/(d-+d+),              */
+/* w+ = d-/(d-+d+), d = nu^T D nu, gamma_F = sigma <d-,d+> / min(h_a-,h_a+),  */
+/* Phi = u- b.nu if b.nu >= 0 else u+ b.nu.                                  */
+/* Contributions are added to ym (rows of Tm) if ym != NULL and to yp (rows  */
+/* of Tp) if yp != NULL.                                                     */
+/* ------------------------------------------------------------------------ */
+static void interior_face(const or_problem *p, const or_tables *t, int a, const int *im,
+                          const double *xm, const double *xp_, double *ym, double *yp) {
+  const int n = t->n, m = t->m;
+  const int tb = (a == 0) ? 1 : 0, tc = (a == 2) ? 1 : 2;
+  int ip[3] = {im[0], im[1], im[2]};
+  ip[a] += 1;
+  double om[3], hm[3], op[3], hp[3];
+  cell_geom(p, im, om, hm);
+  cell_geom(p, ip, op, hp);
+  const double km = cell_kappa(p, cell_id(p, im)), kp = cell_kappa(p, cell_id(p, ip));
+  const double Kaa = p->K[4 * a];
+  const double dm = km * Kaa, dp = kp * Kaa;
+  const double wm = dp / (dm + dp), wp = dm / (dm + dp);
+  const double hmin = hm[a] < hp[a] ? hm[a] : hp[a];
+  const double gamma = p->sigma * (2.0 * dm * dp / (dm + dp)) / hmin;
+  const double area = hm[tb] * hm[tc];
+  for (int qc = 0; qc < m; ++qc)
+    for (int qb = 0; qb < m; ++qb) {
+      double um, gm[3], up, gp[3];
+      eval_on_face(t, a, 1, tb, tc, qb, qc, hm, xm, &um, gm);
+      eval_on_face(t, a, 0, tb, tc, qb, qc, hp, xp_, &up, gp);
+      /* physical face point (on the plane x_a = node) */
+      double X[3];
+      X[a] = op[a];
+      X[tb] = om[tb] + hm[tb] * t->xi[qb];
+      X[tc] = om[tc] + hm[tc] * t->xi[qc];
+      const double bnu = coef_b(p, a, X);
+      const double Phi = (bnu >= 0.0) ? bnu * um : bnu * up;
+      const double J = um - up;
+      double Dgm = 0.0, Dgp = 0.0; /* nu . (D grad u^-), nu . (D grad u^+) */
+      for (int s = 0; s < 3; ++s) {
+        Dgm += km * p->K[3 * a + s] * gm[s];
+        Dgp += kp * p->K[3 * a + s] * gp[s];
+      }
+      const double avg = wm * Dgm + wp * Dgp;
+      const double W = t->w[qb] * t->w[qc] * area;
+      for (int j3 = 0; j3 < n; ++j3)
+        for (int j2 = 0; j2 < n; ++j2)
+          for (int j1 = 0; j1 < n; ++j1) {
+            const int j[3] = {j1, j2, j3};
+            const int jj = j1 + n * (j2 + n * j3);
+            if (ym) {
+              /* test function on T^-: [[v]] = v, {D grad v}_w = w- D- grad v */
+              double phi, gphi[3];
+              shape_on_face(t, a, 1, tb, tc, qb, qc, j, hm, &phi, gphi);
+              double Dgv = 0.0;
+              for (int s = 0; s < 3; ++s) Dgv += km * p->K[3 * a + s] * gphi[s];
+              ym[jj] += W * (Phi * phi - avg * phi - wm * Dgv * J + gamma * J * phi);
+            }
+            if (yp) {
+              /* test function on T^+: [[v]] = -v, {D grad v}_w = w+ D+ grad v */
+              double phi, gphi[3];
+              shape_on_face(t, a, 0, tb, tc, qb, qc, j, hp, &phi, gphi);
+              double Dgv = 0.0;
+              for (int s = 0; s < 3; ++s) Dgv += kp * p->K[3 * a + s] * gphi[s];
+              yp[jj] += W * (-Phi * phi + avg * phi - wp * Dgv * J - gamma * J * phi);
+            }
+          }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Boundary face of cell T on the side e (0: x_a = lower end, 1: upper) of    */
+/* axis a; outer normal nu = (2e-1) e_a.  Homogeneous Dirichlet: terms       */
+/*   (Phi(u,0,b.nu), v)_F - (nu.D grad u, v)_F - (nu.D grad v, u)_F           */
+/*   + gamma_F (u, v)_F,    gamma_F = sigma d- / h_a,  d- = nu^T D nu.        */
+/* ------------------------------------------------------------------------ */
+static void boundary_face(const or_problem *p, const or_tables *t, int a, int e, const int *ic,
+                          const double *xT, double *yT) {
+  const int n = t->n, m = t->m;
+  const int tb = (a == 0) ? 1 : 0, tc = (a == 2) ? 1 : 2;
+  double o[3], h[3];
+  cell_geom(p, ic, o, h);
+  const double kap = cell_kappa(p, cell_id(p, ic));
+  const double nsign = e ? 1.0 : -1.0;
+  const double delta = kap * p->K[4 * a];
+  const double gamma = p->sigma * delta / h[a];
+  const double area = h[tb] * h[tc];
+  for (int qc = 0; qc < m; ++qc)
+    for (int qb = 0; qb < m; ++qb) {
+      double u, g[3];
+      eval_on_face(t, a, e, tb, tc, qb, qc, h, xT, &u, g);
+      double X[3];
+      X[a] = o[a] + (e ? h[a] : 0.0);
+      X[tb] = o[tb] + h[tb] * t->xi[qb];
+      X[tc] = o[tc] + h[tc] * t->xi[qc];
+      const double bnu = nsign * coef_b(p, a, X);
+      const double Phi = (bnu >= 0.0) ? bnu * u : 0.0;
+      double Dg = 0.0;
+      for (int s = 0; s < 3; ++s) Dg += kap * p->K[3 * a + s] * g[s];
+      Dg *= nsign;
+      const double W = t->w[qb] * t->w[qc] * area;
+      for (int j3 = 0; j3 < n; ++j3)
+        for (int j2 = 0; j2 < n; ++j2)
+          for (int j1 = 0; j1 < n; ++j1) {
+            const int j[3] = {j1, j2, j3};
+            double phi, gphi[3];
+            shape_on_face(t, a, e, tb, tc, qb, qc, j, h, &phi, gphi);
+            double Dgv = 0.0;
+            for (int s = 0; s < 3; ++s) Dgv += kap * p->K[3 * a + s] * gphi[s];
+            Dgv *= nsign;
+            yT[j1 + n * (j2 + n * j3)] += W * (Phi * phi - Dg * phi - Dgv * u + gamma * u * phi);
+          }
+    }
+}
+
+static int check_problem(const or_problem *p) {
+  if (!p || p->k < 1 || p->k > 10) return -1;
+  for (int a = 0; a < 3; ++a) {
+    if (p->ncell[a] < 1 || !p->nodes[a]) return -1;
+    if (p->b_axis[a] < 0 || p->b_axis[a] > 2) return -1;
+  }
+  return 0;
+}
+
+int64_t oracle_ndof(const or_problem *p) {
+  const int64_t n = p->k + 1;
+  return (int64_t)p->ncell[0] * p->ncell[1] * p->ncell[2] * n * n * n;
+}
+
+/* ------------------------------------------------------------------------ */
+/* y = A x, Algorithm 1 of Sec. 3.6: volume per cell, every interior face    */
+/* once with its result scattered to both neighbours, every boundary face.   */
+/* Faces are visited in two passes per axis (even and odd lower index), so   */
+/* that faces processed concurrently never share a cell.                     */
+/* ------------------------------------------------------------------------ */
+int oracle_apply(const or_problem *p, const double *x, double *y, int terms, int nthreads) {
+  if (check_problem(p)) return -1;
+  or_tables t;
+  make_tables(p->k, &t);
+  const int64_t nb = (int64_t)t.n * t.n * t.n;
+  const int N1 = p->ncell[0], N2 = p->ncell[1], N3 = p->ncell[2];
+  const int64_t ncells = (int64_t)N1 * N2 * N3;
+  if (nthreads <= 0) nthreads = 1;
+  memset(y, 0, sizeof(double) * ncells * nb);
+  if (terms & OR_VOLUME) {
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads)
+    for (int64_t c = 0; c < ncells; ++c) {
+      const int ic[3] = {(int)(c % N1), (int)((c / N1) % N2), (int)(c / ((int64_t)N1 * N2))};
+      volume_cell(p, &t, ic, x + c * nb, y + c * nb);
+    }
+  }
+  if (terms & OR_INTERIOR) {
+    for (int a = 0; a < 3; ++a)
+      for (int parity = 0; parity < 2; ++parity) {
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads)
+        for (int64_t c = 0; c < ncells; ++c) {
+          const int ic[3] = {(int)(c % N1), (int)((c / N1) % N2), (int)(c / ((int64_t)N1 * N2))};
+          if (ic[a] % 2 != parity || ic[a] + 1 >= p->ncell[a]) continue;
+          int jc[3] = {ic[0], ic[1], ic[2]};
+          jc[a] += 1;
+          const int64_t cp = cell_id(p, jc);
+          interior_face(p, &t, a, ic, x + c * nb, x + cp * nb, y + c * nb, y + cp * nb);
+        }
+      }
+  }
+  if (terms & OR_BOUNDARY) {
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads)
+    for (int64_t c = 0; c < ncells; ++c) {
+      const int ic[3] = {(int)(c % N1), (int)((c / N1) % N2), (int)(c / ((int64_t)N1 * N2))};
+      for (int a = 0; a < 3; ++a) {
+        if (ic[a] == 0) boundary_face(p, &t, a, 0, ic, x + c * nb, y + c * nb);
+        if (ic[a] == p->ncell[a] - 1) boundary_face(p, &t, a, 1, ic, x + c * nb, y + c * nb);
+      }
+    }
+  }
+  return 0;
+}
+
+/* Rows of y = A x belonging to selected cells only: for each listed cell T,
+ * its volume term plus the contribution of each of its six faces to the test
+ * functions of T (the same face terms as above, restricted to one side).
+ * y_rows has ncsel * n^3 entries in the order of `cells`. */
+int oracle_apply_rows(const or_problem *p, const double *x, const int64_t *cells, int64_t ncsel,
+                      double *y_rows, int terms, int nthreads) {
+  if (check_problem(p)) return -1;
+  or_tables t;
+  make_tables(p->k, &t);
+  const int64_t nb = (int64_t)t.n * t.n * t.n;
+  const int N1 = p->ncell[0], N2 = p->ncell[1], N3 = p->ncell[2];
+  const int64_t ncells = (int64_t)N1 * N2 * N3;
+  if (nthreads <= 0) nthreads = 1;
+  for (int64_t s = 0; s < ncsel; ++s)
+    if (cells[s] < 0 || cells[s] >= ncells) return -1;
+  memset(y_rows, 0, sizeof(double) * ncsel * nb);
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+  for (int64_t s = 0; s < ncsel; ++s) {
+    const int64_t c = cells[s];
+    const int ic[3] = {(int)(c % N1), (int)((c / N1) % N2), (int)(c / ((int64_t)N1 * N2))};
+    double *yT = y_rows + s * nb;
+    if (terms & OR_VOLUME) volume_cell(p, &t, ic, x + c * nb, yT);
+    for (int a = 0; a < 3; ++a) {
+      /* lower face of T */
+      if (ic[a] == 0) {
+        if (terms & OR_BOUNDARY) boundary_face(p, &t, a, 0, ic, x + c * nb, yT);
+      } else if (terms & OR_INTERIOR) {
+        int jm[3] = {ic[0], ic[1], ic[2]};
+        jm[a] -= 1;
+        interior_face(p, &t, a, jm, x + cell_id(p, jm) * nb, x + c * nb, NULL, yT);
+      }
+      /* upper face of T */
+      if (ic[a] == p->ncell[a] - 1) {
+        if (terms & OR_BOUNDARY) boundary_face(p, &t, a, 1, ic, x + c * nb, yT);
+      } else if (terms & OR_INTERIOR) {
+        int jp[3] = {ic[0], ic[1], ic[2]};
+        jp[a] += 1;
+        interior_face(p, &t, a, ic, x + c * nb, x + cell_id(p, jp) * nb, yT, NULL);
+      }
+    }
+  }
+  (void)N3;
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Right-hand side functional l_h(v) of Sec. 2.2 with g = 0 and no Neumann   */
+/* faces: f_{T,j} = (f, phi_j)_T by the same Gauss rule.  The source f is a  */
+/* sum of separable terms f(x) = sum_t alpha_t prod_r g_{t,r}(x_r) with      */
+/* g(kind 0) = 1, g(kind 1) = sin(pi x), g(kind 2) = cos(pi x).              */
+/* ------------------------------------------------------------------------ */
+static double sep_fn(int kind, double x) {
+  if (kind == 1) return sin(M_PI * x);
+  if (kind == 2) return cos(M_PI * x);
+  return 1.0;
+}
+
+static double sep_eval(int nterms, const double *alpha, const int32_t *kinds, const double *X) {
+  double f = 0.0;
+  for (int s = 0; s < nterms; ++s)
+    f += alpha[s] * sep_fn(kinds[3 * s], X[0]) * sep_fn(kinds[3 * s + 1], X[1]) *
+         sep_fn(kinds[3 * s + 2], X[2]);
+  return f;
+}
+
+int oracle_rhs(const or_problem *p, int nterms, const double *alpha, const int32_t *kinds,
+               double *f, int nthreads) {
+  if (check_problem(p)) return -1;
+  or_tables t;
+  make_tables(p->k, &t);
+  const int n = t.n, m = t.m;
+  const int64_t nb = (int64_t)n * n * n;
+  const int N1 = p->ncell[0], N2 = p->ncell[1], N3 = p->ncell[2];
+  const int64_t ncells = (int64_t)N1 * N2 * N3;
+  if (nthreads <= 0) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads)
+  for (int64_t c = 0; c < ncells; ++c) {
+    const int ic[3] = {(int)(c % N1), (int)((c / N1) % N2), (int)(c / ((int64_t)N1 * N2))};
+    double o[3], h[3];
+    cell_geom(p, ic, o, h);
+    double *fT = f + c * nb;
+    memset(fT, 0, sizeof(double) * nb);
+    for (int q3 = 0; q3 < m; ++q3)
+      for (int q2 = 0; q2 < m; ++q2)
+        for (int q1 = 0; q1 < m; ++q1) {
+          const double X[3] = {o[0] + h[0] * t.xi[q1], o[1] + h[1] * t.xi[q2],
+                               o[2] + h[2] * t.xi[q3]};
+          const double W = t.w[q1] * t.w[q2] * t.w[q3] * h[0] * h[1] * h[2];
+          const double fx = sep_eval(nterms, alpha, kinds, X);
+          for (int j3 = 0; j3 < n; ++j3)
+            for (int j2 = 0; j2 < n; ++j2)
+              for (int j1 = 0; j1 < n; ++j1)
+                fT[j1 + n * (j2 + n * j3)] += W * fx * t.V[q1][j1] * t.V[q2][j2] * t.V[q3][j3];
+        }
+  }
+  (void)N3;
+  return 0;
+}
+
+/* Squared L2 error ||u_h - u||^2 over the mesh for a separable-sum exact
+ * solution u, with a (k+3)-point Gauss rule per direction (exact for the
+ * polynomial part, accurate for the smooth part). */
+double oracle_l2err2(const or_problem *p, const double *x, int nterms, const double *alpha,
+                     const int32_t *kinds) {
+  if (check_problem(p)) return -1.0;
+  const int n = p->k + 1, mq = p->k + 3;
+  double xi[OR_MAXN + 2], w[OR_MAXN + 2];
+  oracle_gauss(mq, xi, w);
+  double V[OR_MAXN + 2][OR_MAXN], Dd[OR_MAXN];
+  for (int q = 0; q < mq; ++q) oracle_basis(p->k, xi[q], V[q], Dd);
+  const int64_t nb = (int64_t)n * n * n;
+  const int N1 = p->ncell[0], N2 = p->ncell[1], N3 = p->ncell[2];
+  const int64_t ncells = (int64_t)N1 * N2 * N3;
+  double err = 0.0;
+  for (int64_t c = 0; c < ncells; ++c) {
+    const int ic[3] = {(int)(c % N1), (int)((c / N1) % N2), (int)(c / ((int64_t)N1 * N2))};
+    double o[3], h[3];
+    cell_geom(p, ic, o, h);
+    const double *xT = x + c * nb;
+    for (int q3 = 0; q3 < mq; ++q3)
+      for (int q2 = 0; q2 < mq; ++q2)
+        for (int q1 = 0; q1 < mq; ++q1) {
+          double uh = 0.0;
+          for (int j3 = 0; j3 < n; ++j3)
+            for (int j2 = 0; j2 < n; ++j2)
+              for (int j1 = 0; j1 < n; ++j1)
+                uh += xT[j1 + n * (j2 + n * j3)] * V[q1][j1] * V[q2][j2] * V[q3][j3];
+          const double X[3] = {o[0] + h[0] * xi[q1], o[1] + h[1] * xi[q2], o[2] + h[2] * xi[q3]};
+          const double d = uh - sep_eval(nterms, alpha, kinds, X);
+          err += w[q1] * w[q2] * w[q3] * h[0] * h[1] * h[2] * d * d;
+        }
+  }
+  (void)N3;
+  return err;
+}
+
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

@@ -1,0 +1,229 @@
+"""Seeded synthetic inputs for the DG operator workloads.
+
+This module only generates inputs (meshes, coefficients, vectors, manufactured
+sources).  It contains none of the discretisation's arithmetic, imports
+nothing from the HIP library or the oracle, and is the one module both of them
+are fed from.  Every random array is drawn with ``numpy.random.default_rng``
+(PCG64) from a fixed seed.
+
+Workloads (sizes from the benchmark configuration, coefficients as read from
+the paper's model problem, Sec. 2.1, and Problem A of Sec. 5.1):
+
+* ``poisson_k2_8``   K = I, b = 0, c = 0, k = 2, 8^3 uniform cubes, penalty
+  sigma = 3k(k+1) (gamma = sigma/h), x ~ U[-1, 1] seed 1 (13,824 DOF).
+* ``cdr_k7_32``      k = 7, 32^3 tensor cuboids with per-axis spacings drawn
+  U[0.5h, 1.5h] (seed 2) and rescaled to [0,1]; K = Q diag(1, 0.1, 0.01) Q^T,
+  Q = Rz(pi/6) Ry(pi/4) Rx(pi/3); b = (sin pi y, sin pi z, sin pi x); c = 1;
+  sigma = 2k(k+2); x ~ U[-1, 1] seed 3 (16,777,216 DOF).
+* ``cdr_sweep(k)``   uniform N^3 cubes with N = round((2e7)^(1/3)/(k+1)),
+  coefficients as ``cdr_k7_32``, x seed 300+k.
+* ``mixed_k5_48``    k = 5, 48^3, K = I, b = (1, .5, .25), c = 0.1,
+  sigma = 2k(k+2); source of the manufactured u = sin(pi x) sin(pi y) sin(pi z).
+* ``learned_k3_64``  k = 3, 64^3, kappa_T = exp(g(center_T)), g a seeded smooth
+  random field (random Fourier features, M = 128, length scale 0.1, seed 5),
+  b = (1, .5, .25), c = 0.1, sigma = 2k(k+2), f = 1.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field, replace
+import math
+
+import numpy as np
+
+
+@dataclass
+class Problem:
+    ncell: tuple
+    nodes: tuple  # three float64 arrays of length ncell[a]+1
+    k: int
+    K: np.ndarray  # (3,3) SPD
+    kappa: np.ndarray | None = None  # per cell, axis-1 fastest
+    b_const: tuple = (0.0, 0.0, 0.0)
+    b_sin: tuple = (0.0, 0.0, 0.0)
+    b_axis: tuple = (0, 1, 2)
+    c: float = 0.0
+    sigma: float = 1.0
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def ncells(self) -> int:
+        return int(self.ncell[0] * self.ncell[1] * self.ncell[2])
+
+    @property
+    def ndof(self) -> int:
+        return self.ncells * (self.k + 1) ** 3
+
+    def with_(self, **kw) -> "Problem":
+        return replace(self, **kw)
+
+
+def uniform_nodes(N: int) -> np.ndarray:
+    return np.linspace(0.0, 1.0, N + 1)
+
+
+def random_nodes(N: int, rng, lo: float = 0.5, hi: float = 1.5) -> np.ndarray:
+    """Spacings U[lo*h, hi*h], rescaled so the axis spans [0, 1]."""
+    s = rng.uniform(lo, hi, N)
+    nodes = np.concatenate([[0.0], np.cumsum(s)])
+    nodes /= nodes[-1]
+    nodes[-1] = 1.0
+    return nodes
+
+
+def _rot(axis: int, ang: float) -> np.ndarray:
+    c, s = math.cos(ang), math.sin(ang)
+    R = np.eye(3)
+    i, j = [(1, 2), (0, 2), (0, 1)][axis]
+    R[i, i] = c
+    R[j, j] = c
+    R[i, j] = -s if axis != 1 else s
+    R[j, i] = s if axis != 1 else -s
+    return R
+
+
+def anisotropic_K(eigs=(1.0, 0.1, 0.01)) -> np.ndarray:
+    """K = Q diag(eigs) Q^T with Q = Rz(pi/6) Ry(pi/4) Rx(pi/3): a full tensor."""
+    Q = _rot(2, math.pi / 6) @ _rot(1, math.pi / 4) @ _rot(0, math.pi / 3)
+    K = Q @ np.diag(eigs) @ Q.T
+    return 0.5 * (K + K.T)
+
+
+def random_spd(rng, lo: float = 0.2, hi: float = 2.0) -> np.ndarray:
+    Q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    K = Q @ np.diag(rng.uniform(lo, hi, 3)) @ Q.T
+    return 0.5 * (K + K.T)
+
+
+SINE_CYCLIC = dict(b_const=(0.0, 0.0, 0.0), b_sin=(1.0, 1.0, 1.0), b_axis=(1, 2, 0))
+
+
+def paper_sigma(k: int) -> float:
+    """alpha * p (p + d - 1) with alpha = 2, d = 3 (penalty of Sec. 2.2)."""
+    return 2.0 * k * (k + 2)
+
+
+def poisson_k2_8() -> Problem:
+    k, N = 2, 8
+    return Problem(ncell=(N, N, N), nodes=(uniform_nodes(N),) * 3, k=k, K=np.eye(3),
+                   sigma=3.0 * k * (k + 1), name="poisson_k2_8", meta={"x_seed": 1})
+
+
+def cdr_k7_32(N: int = 32, k: int = 7) -> Problem:
+    rng = np.random.default_rng(2)
+    nodes = tuple(random_nodes(N, rng) for _ in range(3))
+    return Problem(ncell=(N, N, N), nodes=nodes, k=k, K=anisotropic_K(), c=1.0,
+                   sigma=paper_sigma(k), name=f"cdr_k{k}_{N}", meta={"x_seed": 3},
+                   **SINE_CYCLIC)
+
+
+def sweep_N(k: int) -> int:
+    return int(round((2e7) ** (1.0 / 3.0) / (k + 1)))
+
+
+def cdr_sweep(k: int) -> Problem:
+    N = sweep_N(k)
+    return Problem(ncell=(N, N, N), nodes=(uniform_nodes(N),) * 3, k=k, K=anisotropic_K(),
+                   c=1.0, sigma=paper_sigma(k), name=f"cdr_sweep_k{k}_{N}",
+                   meta={"x_seed": 300 + k}, **SINE_CYCLIC)
+
+
+B_CONST = dict(b_const=(1.0, 0.5, 0.25), b_sin=(0.0, 0.0, 0.0), b_axis=(0, 1, 2))
+
+
+def mixed_k5_48(N: int = 48, k: int = 5) -> Problem:
+    return Problem(ncell=(N, N, N), nodes=(uniform_nodes(N),) * 3, k=k, K=np.eye(3), c=0.1,
+                   sigma=paper_sigma(k), name=f"mixed_k{k}_{N}", **B_CONST)
+
+
+def smooth_field(centers: np.ndarray, seed: int = 5, M: int = 128, ell: float = 0.1):
+    """g(x) = sqrt(2/M) sum_j cos(w_j . x + phi_j), w_j ~ N(0, ell^-2 I),
+    phi_j ~ U[0, 2 pi): a stationary Gaussian random field of unit variance."""
+    rng = np.random.default_rng(seed)
+    w = rng.standard_normal((M, 3)) / ell
+    ph = rng.uniform(0.0, 2.0 * math.pi, M)
+    return math.sqrt(2.0 / M) * np.cos(centers @ w.T + ph[None, :]).sum(axis=1)
+
+
+def cell_centers(nodes) -> np.ndarray:
+    c = [0.5 * (nd[1:] + nd[:-1]) for nd in nodes]
+    C3, C2, C1 = np.meshgrid(c[2], c[1], c[0], indexing="ij")
+    return np.stack([C1.ravel(), C2.ravel(), C3.ravel()], axis=1)  # axis-1 fastest
+
+
+def learned_k3_64(N: int = 64, k: int = 3, log_sigma: float = 1.0) -> Problem:
+    nodes = (uniform_nodes(N),) * 3
+    kappa = np.exp(log_sigma * smooth_field(cell_centers(nodes)))
+    return Problem(ncell=(N, N, N), nodes=nodes, k=k, K=np.eye(3), kappa=kappa, c=0.1,
+                   sigma=paper_sigma(k), name=f"learned_k{k}_{N}", **B_CONST)
+
+
+def random_problem(seed: int, ncell=(3, 2, 2), k: int = 2, b: str = "sine",
+                   kappa: bool = True, c: float | None = None) -> Problem:
+    """Small random problem: nonuniform tensor grid, random SPD K, random
+    per-cell kappa, b constant or sine-cyclic, random c."""
+    rng = np.random.default_rng(seed)
+    nodes = tuple(random_nodes(ncell[a], rng) for a in range(3))
+    K = random_spd(rng)
+    kap = rng.uniform(0.3, 3.0, int(np.prod(ncell))) if kappa else None
+    if b == "sine":
+        bk = dict(b_const=tuple(rng.uniform(-0.5, 0.5, 3)), b_sin=tuple(rng.uniform(0.5, 2, 3)),
+                  b_axis=(1, 2, 0))
+    elif b == "const":
+        bk = dict(b_const=tuple(rng.uniform(-2, 2, 3)), b_sin=(0.0, 0.0, 0.0), b_axis=(0, 1, 2))
+    else:
+        bk = dict(b_const=(0.0, 0.0, 0.0), b_sin=(0.0, 0.0, 0.0), b_axis=(0, 1, 2))
+    cc = float(rng.uniform(0.1, 2.0)) if c is None else float(c)
+    return Problem(ncell=tuple(ncell), nodes=nodes, k=k, K=K, kappa=kap, c=cc,
+                   sigma=paper_sigma(k), name=f"random_{seed}", **bk)
+
+
+def random_vector(n: int, seed: int, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
+    return np.random.default_rng(seed).uniform(lo, hi, n)
+
+
+def workload_vector(prob: Problem) -> np.ndarray:
+    return random_vector(prob.ndof, int(prob.meta.get("x_seed", 0)))
+
+
+# ---------------------------------------------------------------------------
+# Manufactured solution u = sin(pi x) sin(pi y) sin(pi z) for
+# -div(K grad u) + div(b u) + c u = f with constant K, constant b, constant c
+# (strong form of the model problem, Sec. 2.1).  Functions are lists of
+# separable terms (alpha, (kind1, kind2, kind3)), kind 0 = 1, 1 = sin(pi .),
+# 2 = cos(pi .).
+# ---------------------------------------------------------------------------
+SIN, COS, ONE = 1, 2, 0
+
+
+def manufactured_u():
+    return [(1.0, (SIN, SIN, SIN))]
+
+
+def manufactured_source(K, b, c):
+    """f = -sum_rs K_rs d_r d_s u + b . grad u + c u for u = prod sin(pi x_a).
+
+    d_r d_r u = -pi^2 u;  d_r d_s u (r != s) = pi^2 cos cos sin (in r, s);
+    d_r u = pi cos(pi x_r) prod_{a != r} sin(pi x_a)."""
+    K = np.asarray(K, dtype=np.float64)
+    terms = []
+    pi2 = math.pi ** 2
+    diag = sum(K[r, r] for r in range(3))
+    terms.append((pi2 * diag + c, (SIN, SIN, SIN)))
+    for r in range(3):
+        for s in range(3):
+            if r != s and K[r, s] != 0.0:
+                kinds = [SIN, SIN, SIN]
+                kinds[r] = COS
+                kinds[s] = COS
+                terms.append((-pi2 * K[r, s], tuple(kinds)))
+    for r in range(3):
+        if b[r] != 0.0:
+            kinds = [SIN, SIN, SIN]
+            kinds[r] = COS
+            terms.append((math.pi * b[r], tuple(kinds)))
+    return terms
+
+
+def constant_source(value: float = 1.0):
+    return [(float(value), (ONE, ONE, ONE))]

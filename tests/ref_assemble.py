@@ -1,0 +1,166 @@
+"""Brute-force dense assembly of the weighted SIPG operator, for tiny meshes.
+
+An independent second route to the matrix of eq. (blf) (Sec. 2.2): numpy only,
+basis values from ``numpy.polynomial.legendre`` (not from the oracle), Gauss
+nodes from ``numpy.polynomial.legendre.leggauss``, and the face terms written
+generically in jump/average form for every (trial side, test side) pair instead
+of the per-side expansions the oracle uses.  Dense matrices: a few hundred DOF
+at most.
+"""
+from __future__ import annotations
+
+import numpy as np
+from numpy.polynomial import legendre as L
+
+
+def _basis_1d(k: int, t: np.ndarray):
+    """theta_j(t) = sqrt(2j+1) P_j(2t-1) and its t-derivative, shape (len(t), k+1)."""
+    s = 2.0 * np.asarray(t, dtype=np.float64) - 1.0
+    V = np.empty((s.size, k + 1))
+    D = np.empty((s.size, k + 1))
+    for j in range(k + 1):
+        c = np.zeros(j + 1)
+        c[j] = np.sqrt(2 * j + 1)
+        V[:, j] = L.legval(s, c)
+        D[:, j] = 2.0 * L.legval(s, L.legder(c))
+    return V, D
+
+
+def _gauss01(m: int):
+    x, w = L.leggauss(m)
+    return 0.5 * (x + 1.0), 0.5 * w
+
+
+def _tensor_shape(vals, ders, h):
+    """Given per-axis (npts_a, n) value/derivative tables on a tensor grid of
+    points, return phi (P, n^3) and grad (P, n^3, 3) with axis 1 fastest in both
+    the point and the shape-function numbering."""
+    n = vals[0].shape[1]
+    P = [v.shape[0] for v in vals]
+    phi = np.einsum("ai,bj,ck->cbakji", vals[0], vals[1], vals[2]).reshape(P[0] * P[1] * P[2], n ** 3)
+    g1 = np.einsum("ai,bj,ck->cbakji", ders[0], vals[1], vals[2]).reshape(-1, n ** 3) / h[0]
+    g2 = np.einsum("ai,bj,ck->cbakji", vals[0], ders[1], vals[2]).reshape(-1, n ** 3) / h[1]
+    g3 = np.einsum("ai,bj,ck->cbakji", vals[0], vals[1], ders[2]).reshape(-1, n ** 3) / h[2]
+    return phi, np.stack([g1, g2, g3], axis=-1)
+
+
+def _b(prob, X):
+    b = np.empty_like(X)
+    for r in range(3):
+        b[:, r] = prob.b_const[r] + prob.b_sin[r] * np.sin(np.pi * X[:, prob.b_axis[r]])
+    return b
+
+
+def assemble_dense(prob) -> np.ndarray:
+    k = prob.k
+    n = k + 1
+    nb = n ** 3
+    N = prob.ncell
+    nc = N[0] * N[1] * N[2]
+    A = np.zeros((nc * nb, nc * nb))
+    xi, w = _gauss01(k + 1)
+    Vq, Dq = _basis_1d(k, xi)
+    V0, D0 = _basis_1d(k, np.array([0.0]))
+    V1, D1 = _basis_1d(k, np.array([1.0]))
+    K = np.asarray(prob.K, dtype=np.float64)
+    kap = np.ones(nc) if prob.kappa is None else np.asarray(prob.kappa).ravel()
+
+    def cid(i):
+        return i[0] + N[0] * (i[1] + N[1] * i[2])
+
+    def geom(i):
+        o = np.array([prob.nodes[a][i[a]] for a in range(3)])
+        h = np.array([prob.nodes[a][i[a] + 1] - prob.nodes[a][i[a]] for a in range(3)])
+        return o, h
+
+    def blk(c):
+        return slice(c * nb, (c + 1) * nb)
+
+    cells = [(i1, i2, i3) for i3 in range(N[2]) for i2 in range(N[1]) for i1 in range(N[0])]
+    # ---- volume: (D grad u - b u, grad v)_T + (c u, v)_T ----
+    for i in cells:
+        o, h = geom(i)
+        c = cid(i)
+        phi, g = _tensor_shape([Vq] * 3, [Dq] * 3, h)
+        Wq = np.einsum("a,b,c->cba", w, w, w).ravel() * np.prod(h)
+        Xq = np.stack(np.meshgrid(o[0] + h[0] * xi, o[1] + h[1] * xi, o[2] + h[2] * xi,
+                                  indexing="ij"), axis=-1).transpose(2, 1, 0, 3).reshape(-1, 3)
+        bq = _b(prob, Xq)
+        Dg = kap[c] * np.einsum("rs,pjs->pjr", K, g)           # D grad phi_j
+        flux = Dg - bq[:, None, :] * phi[:, :, None]              # (P, j, 3)
+        A[blk(c), blk(c)] += np.einsum("p,pjr,pir->ij", Wq, flux, g)
+        A[blk(c), blk(c)] += prob.c * np.einsum("p,pj,pi->ij", Wq, phi, phi)
+
+    # ---- faces ----
+    def face_tables(a, e, h):
+        """phi, grad on the face x_a = e (reference) at tangential Gauss nodes."""
+        vals, ders = [Vq, Vq, Vq], [Dq, Dq, Dq]
+        vals = list(vals)
+        ders = list(ders)
+        vals[a] = V1 if e == 1 else V0
+        ders[a] = D1 if e == 1 else D0
+        return _tensor_shape(vals, ders, h)
+
+    def face_weights(a, h):
+        ws = [w, w, w]
+        ws[a] = np.array([1.0])
+        W = np.einsum("a,b,c->cba", ws[0], ws[1], ws[2]).ravel()
+        t = [b for b in range(3) if b != a]
+        return W * h[t[0]] * h[t[1]]
+
+    def face_points(a, o, h, xa):
+        pts = [o[b] + h[b] * xi for b in range(3)]
+        pts[a] = np.array([xa])
+        return np.stack(np.meshgrid(*pts, indexing="ij"), axis=-1).transpose(2, 1, 0, 3).reshape(-1, 3)
+
+    for i in cells:
+        for a in range(3):
+            o, h = geom(i)
+            c = cid(i)
+            if i[a] + 1 < N[a]:
+                ip = list(i)
+                ip[a] += 1
+                op, hp = geom(ip)
+                cp = cid(ip)
+                W = face_weights(a, h)
+                X = face_points(a, o, h, op[a])
+                bnu = _b(prob, X)[:, a]
+                dm, dp = kap[c] * K[a, a], kap[cp] * K[a, a]
+                wm, wp = dp / (dm + dp), dm / (dm + dp)
+                gam = prob.sigma * (2 * dm * dp / (dm + dp)) / min(h[a], hp[a])
+                side = {0: (c, *face_tables(a, 1, h), kap[c]), 1: (cp, *face_tables(a, 0, hp), kap[cp])}
+                for su in (0, 1):        # trial function side (0: minus, 1: plus)
+                    for sv in (0, 1):    # test function side
+                        cu, phu, gu, ku = side[su]
+                        cv, phv, gv, kv = side[sv]
+                        um = phu if su == 0 else 0 * phu
+                        up = phu if su == 1 else 0 * phu
+                        jump_u = um - up
+                        avg_u = (wm if su == 0 else wp) * ku * np.einsum("s,pjs->pj", K[a], gu)
+                        Phi = np.where(bnu[:, None] >= 0, bnu[:, None] * um, bnu[:, None] * up)
+                        jump_v = phv if sv == 0 else -phv
+                        avg_v = (wm if sv == 0 else wp) * kv * np.einsum("s,pis->pi", K[a], gv)
+                        M = (np.einsum("p,pj,pi->ij", W, Phi, jump_v)
+                             - np.einsum("p,pj,pi->ij", W, avg_u, jump_v)
+                             - np.einsum("p,pi,pj->ij", W, avg_v, jump_u)
+                             + gam * np.einsum("p,pj,pi->ij", W, jump_u, jump_v))
+                        A[blk(cv), blk(cu)] += M
+            for e in (0, 1):
+                at_bnd = (i[a] == 0) if e == 0 else (i[a] == N[a] - 1)
+                if not at_bnd:
+                    continue
+                W = face_weights(a, h)
+                X = face_points(a, o, h, o[a] + (h[a] if e == 1 else 0.0))
+                nsg = 1.0 if e == 1 else -1.0
+                bnu = nsg * _b(prob, X)[:, a]
+                delta = kap[c] * K[a, a]
+                gam = prob.sigma * delta / h[a]
+                ph, g = face_tables(a, e, h)
+                Dn = nsg * kap[c] * np.einsum("s,pjs->pj", K[a], g)
+                Phi = np.where(bnu[:, None] >= 0, bnu[:, None] * ph, 0.0)
+                M = (np.einsum("p,pj,pi->ij", W, Phi, ph)
+                     - np.einsum("p,pj,pi->ij", W, Dn, ph)
+                     - np.einsum("p,pi,pj->ij", W, Dn, ph)
+                     + gam * np.einsum("p,pj,pi->ij", W, ph, ph))
+                A[blk(c), blk(c)] += M
+    return A
