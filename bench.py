@@ -1,0 +1,172 @@
+#!/usr/bin/env python3
+"""Benchmark: matrix-free WSIPG operator application y = A x on one MI355X.
+
+Workload (default): convection-diffusion-reaction, degree k = 7, 32^3
+axis-aligned cuboids with per-axis spacings U[0.5h, 1.5h], anisotropic K
+(eigenvalues 1, 0.1, 0.01), b = (sin pi y, sin pi z, sin pi x), c = 1,
+16,777,216 DOF, FP64.  Inputs are seeded and synthetic and resident in HBM
+before timing starts.
+
+One step = one y = A x (volume and face terms of every cell).  W untimed
+warm-up steps, then K timed steps bracketed by device synchronisation; each
+launch is also bracketed by HIP events on the stream the kernel runs on, which
+gives the average kernel duration used for the roofline.
+
+Prints ONE JSON line.  Algorithmic FLOPs use the per-DOF lower bound of
+Sec. 3.6 (FLOPDOF_vol + FLOPDOF_face for d = 3); peak is the MI355X FP64
+vector rate (256 CUs x 2.4 GHz x 128 FLOP/clk = 78.6 TFLOP/s).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DG apply GDOF/s & % FP64 peak; time-to-1e-8 solve, plain vs mixed/learned"
+FP64_PEAK_TFLOPS = 78.6
+
+
+def flop_per_dof(k: int, d: int = 3) -> float:
+    """FLOPDOF_vol + FLOPDOF_face of Sec. 3.6 (lower bound, n = m = k+1)."""
+    vol = 4 * (d + 1) * d * (k + 1) + 2 * d * d + 5 * d + 3
+    face = 8 * (d + 1) * d * d + d * (2 * d * d + 8 * d + 18) / (k + 1)
+    return vol + face
+
+
+def make_workload(name: str):
+    from paper_1711_10885_amd import workloads as W
+    if name == "cdr_k7_32":
+        return W.cdr_k7_32()
+    if name == "poisson_k2_8":
+        return W.poisson_k2_8()
+    if name.startswith("sweep_k"):
+        return W.cdr_sweep(int(name[len("sweep_k"):]))
+    if name == "mixed_k5_48":
+        return W.mixed_k5_48()
+    if name == "learned_k3_64":
+        return W.learned_k3_64()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def describe(prob) -> str:
+    N = prob.ncell
+    return (f"{prob.name}: WSIPG CDR apply, k={prob.k}, {N[0]}x{N[1]}x{N[2]} cells, "
+            f"{prob.ndof} DOF, FP64")
+
+
+def cpu_baseline(prob, x, budget_s: float = 12.0):
+    """The CPU oracle as it stands on a bounded sample of cells of the same
+    workload (rows of A x for the sampled cells), on all host threads."""
+    import numpy as np
+    import oracle
+    threads = oracle.default_threads()
+    rng = np.random.default_rng(1234)
+    probe = rng.choice(prob.ncells, size=min(prob.ncells, 2 * threads), replace=False)
+    t0 = time.perf_counter()
+    oracle.apply_rows(prob, x, probe, nthreads=threads)
+    t_probe = max(time.perf_counter() - t0, 1e-6)
+    ncs = int(min(prob.ncells, max(threads, probe.size * budget_s / t_probe)))
+    cells = rng.choice(prob.ncells, size=ncs, replace=False)
+    t0 = time.perf_counter()
+    oracle.apply_rows(prob, x, cells, nthreads=threads)
+    dt = time.perf_counter() - t0
+    nb = (prob.k + 1) ** 3
+    return {"value": ncs * nb / dt / 1e9, "unit": "GDOF/s", "cores": threads, "kind": "oracle",
+            "sample": f"rows of A x for {ncs} random cells of the same workload "
+                      f"({ncs * nb} DOF, {dt:.1f} s, plain quadrature oracle)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="cdr_k7_32")
+    ap.add_argument("--variant", type=int, default=0, help="0 tuned kernel, 1 reference kernel")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1711_10885_amd import binding, workloads as W
+
+    torch.cuda.set_device(0)
+    prob = make_workload(args.workload)
+    x_host = W.workload_vector(prob)
+    dg = binding.DG(prob)
+    dg.set_kernel(args.variant)
+    x = torch.from_numpy(x_host).cuda()
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        dg.apply(x, y, stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for s, e in ev:
+        s.record(stream)
+        dg.apply(x, y, stream)
+        e.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = [s.elapsed_time(e) for s, e in ev]
+    ms_step = wall * 1e3 / args.steps
+    avg_kernel_ms = float(np.mean(kern_ms))
+    fpd = flop_per_dof(prob.k)
+    achieved = fpd * prob.ndof / (avg_kernel_ms * 1e-3) / 1e12
+
+    # spot parity on a few cells (the tests do the full check)
+    parity = None
+    try:
+        import oracle
+        cells = np.array([0, prob.ncells // 2 + 3, prob.ncells - 1])
+        ref = oracle.apply_rows(prob, x_host, cells)
+        got = y.cpu().numpy().reshape(prob.ncells, -1)[cells]
+        parity = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    except Exception as ex:  # noqa: BLE001
+        print(f"spot parity skipped: {ex}", file=sys.stderr)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(prob, x_host, args.cpu_budget)
+
+    out = {
+        "metric": METRIC,
+        "value": prob.ndof / (ms_step * 1e-3) / 1e9,
+        "unit": "GDOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": describe(prob), "k": prob.k, "ncell": list(prob.ncell),
+                   "ndof": prob.ndof, "kernel_variant": args.variant,
+                   "flop_per_dof_formula": fpd},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "avg_kernel_ms": avg_kernel_ms},
+        "cpu_baseline": cpu,
+        "parity_spot_rel": parity,
+    }
+    print(json.dumps(out), flush=True)
+    dg.close()
+
+
+if __name__ == "__main__":
+    main()

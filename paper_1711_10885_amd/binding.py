@@ -1,0 +1,171 @@
+"""ctypes binding of libdgmf (the C ABI of include/dg.h).
+
+Argument marshalling only: every step of the operator and the solvers runs in
+the HIP library.  torch supplies device memory and streams.  If the library is
+not built, ``load()`` raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdgmf.so")
+
+DG_OK, DG_EINVAL, DG_ENOMEM, DG_EHIP, DG_ENOTCONV, DG_ENAN = 0, -1, -2, -3, -4, -5
+DG_WITH_FP32, DG_WITH_BLOCK_JACOBI = 1, 2
+DG_KERNEL_AUTO, DG_KERNEL_REFERENCE = 0, 1
+
+_STATUS = {DG_EINVAL: "DG_EINVAL", DG_ENOMEM: "DG_ENOMEM", DG_EHIP: "DG_EHIP",
+           DG_ENOTCONV: "DG_ENOTCONV", DG_ENAN: "DG_ENAN"}
+
+# every symbol include/dg.h declares
+EXPORTS = ["dg_setup", "dg_apply", "dg_set_kernel", "dg_ndof", "dg_degree", "dg_last_error",
+           "dg_destroy"]
+
+
+class DGError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [
+        ("ncell", ctypes.c_int32 * 3),
+        ("nodes", ctypes.POINTER(ctypes.c_double) * 3),
+        ("k", ctypes.c_int32),
+        ("K", ctypes.c_double * 9),
+        ("kappa", ctypes.POINTER(ctypes.c_double)),
+        ("b_const", ctypes.c_double * 3),
+        ("b_sin", ctypes.c_double * 3),
+        ("b_axis", ctypes.c_int32 * 3),
+        ("c", ctypes.c_double),
+        ("sigma", ctypes.c_double),
+        ("flags", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Open libdgmf.so.  Raises if it is missing (build it first)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run __graft_entry__.build() "
+                           "(the HIP library is the only compute path)")
+    lib = ctypes.CDLL(path)
+    vp = ctypes.c_void_p
+    H = ctypes.c_void_p
+    lib.dg_setup.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(H)]
+    lib.dg_setup.restype = ctypes.c_int
+    lib.dg_apply.argtypes = [H, vp, vp, vp]
+    lib.dg_apply.restype = ctypes.c_int
+    lib.dg_set_kernel.argtypes = [H, ctypes.c_int32]
+    lib.dg_set_kernel.restype = ctypes.c_int
+    lib.dg_ndof.argtypes = [H]
+    lib.dg_ndof.restype = ctypes.c_int64
+    lib.dg_degree.argtypes = [H]
+    lib.dg_degree.restype = ctypes.c_int32
+    lib.dg_last_error.argtypes = []
+    lib.dg_last_error.restype = ctypes.c_char_p
+    lib.dg_destroy.argtypes = [H]
+    lib.dg_destroy.restype = None
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != DG_OK:
+        raise DGError(rc, load().dg_last_error().decode())
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check_vec(t, n, dtype, name):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must live on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name} must be contiguous with {n} entries")
+
+
+class DG:
+    """Handle on one problem (mesh, degree, coefficients) on the current GPU."""
+
+    def __init__(self, prob, flags: int = 0):
+        lib = load()
+        import torch
+        torch.cuda.current_device()  # make sure the device context exists
+        self._keep = [np.ascontiguousarray(prob.nodes[a], dtype=np.float64) for a in range(3)]
+        kap = None if prob.kappa is None else np.ascontiguousarray(prob.kappa, dtype=np.float64).ravel()
+        self._keep.append(kap)
+        s = _Problem()
+        for a in range(3):
+            s.ncell[a] = int(prob.ncell[a])
+            s.nodes[a] = _dptr(self._keep[a])
+            s.b_const[a] = float(prob.b_const[a])
+            s.b_sin[a] = float(prob.b_sin[a])
+            s.b_axis[a] = int(prob.b_axis[a])
+        s.k = int(prob.k)
+        K = np.asarray(prob.K, dtype=np.float64).reshape(9)
+        for i in range(9):
+            s.K[i] = float(K[i])
+        s.kappa = _dptr(kap) if kap is not None else ctypes.POINTER(ctypes.c_double)()
+        s.c = float(prob.c)
+        s.sigma = float(prob.sigma)
+        s.flags = int(flags)
+        h = ctypes.c_void_p()
+        _check(lib.dg_setup(ctypes.byref(s), ctypes.byref(h)))
+        self._h = h
+        self.prob = prob
+        self.ndof = int(lib.dg_ndof(h))
+        self.k = int(lib.dg_degree(h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().dg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_kernel(self, variant: int):
+        _check(load().dg_set_kernel(self._h, int(variant)))
+
+    def apply(self, x, y=None, stream=None):
+        """y := A x on the GPU (float64, cell-block layout of include/dg.h)."""
+        import torch
+        _check_vec(x, self.ndof, torch.float64, "x")
+        if y is None:
+            y = torch.empty_like(x)
+        _check_vec(y, self.ndof, torch.float64, "y")
+        _check(load().dg_apply(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                               _stream_ptr(stream)))
+        return y

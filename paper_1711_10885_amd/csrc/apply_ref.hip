@@ -1,0 +1,300 @@
+// Reference-layout FP64 apply kernel: one workgroup per cell, every tensor of
+// the sum factorization staged in LDS, one thread per output entry of each 1D
+// contraction.  Simple and general in k; the tuned kernels are checked against
+// the oracle exactly like this one.
+//
+// Per cell T (owner computes, so no two workgroups write the same entry):
+//  * volume term of eq. (blf), Algorithm 1 steps 1-3: u and grad u at the
+//    (k+1)^3 Gauss points by 1D contractions (eq. (evalfe), eq.
+//    (sum_fact_kernel)), the pointwise flux x^(r) of eq. (gauss_points), and
+//    the transposed contractions of eq. (evalblf);
+//  * each of the six faces (steps 4-6 / 8-10): the normal direction is
+//    contracted first (traces of u and d_a u, Sec. 3.4), then the two
+//    tangential directions; the pointwise upwind, weighted-average and penalty
+//    terms; the transposed tangential contractions; and the normal direction
+//    last, into the test functions of T only.
+#include "dg_internal.h"
+
+namespace dgmf {
+
+template <int N>
+struct RefTab {
+  double V[N][N], D[N][N], w[N], ev[2][N], ed[2][N];
+};
+
+struct RefMesh {
+  int ncell[3];
+  const double *h[3], *bvol[3], *bnode[3], *kappa;
+  double K[9], c, sigma;
+  int b_axis[3];
+};
+
+constexpr int kRefThreads = 256;
+
+// out[i] (+)= sum_t A(q_i, t) in[i | axis <- t]  on an N^DIM block in LDS,
+// A = M[q][t] (TRANS = false, evaluation) or M[t][q] (TRANS = true,
+// integration against the test functions).
+template <int N, int DIM, bool TRANS>
+__device__ inline void contract(double *out, const double *in, const double (*M)[N], int stride,
+                                const double *in2 = nullptr, const double (*M2)[N] = nullptr,
+                                bool acc = false) {
+  constexpr int NT = (DIM == 3) ? N * N * N : N * N;
+  for (int i = threadIdx.x; i < NT; i += kRefThreads) {
+    const int qi = (i / stride) % N;
+    const int base = i - qi * stride;
+    double s = acc ? out[i] : 0.0;
+    for (int t = 0; t < N; ++t) {
+      const double a = TRANS ? M[t][qi] : M[qi][t];
+      s = fma(a, in[base + t * stride], s);
+    }
+    if (in2)
+      for (int t = 0; t < N; ++t) {
+        const double a = TRANS ? M2[t][qi] : M2[qi][t];
+        s = fma(a, in2[base + t * stride], s);
+      }
+    out[i] = s;
+  }
+}
+
+template <int N>
+__global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__restrict__ x,
+                                                                double *__restrict__ y,
+                                                                RefMesh M, RefTab<N> T) {
+  constexpr int NB = N * N * N, NF = N * N;
+  __shared__ double sV[N][N], sD[N][N], sw[N], sev[2][N], sed[2][N];
+  __shared__ double X[NB], Y[NB], B0[NB], B1[NB], B2[NB], B3[NB], B4[NB], B5[NB], B6[NB];
+  __shared__ double F[16][NF];
+  const int tid = threadIdx.x;
+  const int cell = blockIdx.x;
+  const int N1 = M.ncell[0], N2 = M.ncell[1];
+  const int ic[3] = {cell % N1, (cell / N1) % N2, cell / (N1 * N2)};
+  const int cstride[3] = {1, N1, N1 * N2};
+
+  for (int i = tid; i < NF; i += kRefThreads) {
+    sV[i / N][i % N] = T.V[i / N][i % N];
+    sD[i / N][i % N] = T.D[i / N][i % N];
+  }
+  if (tid < N) {
+    sw[tid] = T.w[tid];
+    sev[0][tid] = T.ev[0][tid];
+    sev[1][tid] = T.ev[1][tid];
+    sed[0][tid] = T.ed[0][tid];
+    sed[1][tid] = T.ed[1][tid];
+  }
+  const double *xT = x + size_t(cell) * NB;
+  for (int i = tid; i < NB; i += kRefThreads) X[i] = xT[i];
+  __syncthreads();
+
+  const double h[3] = {M.h[0][ic[0]], M.h[1][ic[1]], M.h[2][ic[2]]};
+  const double kap = M.kappa ? M.kappa[cell] : 1.0;
+  const double vol = h[0] * h[1] * h[2];
+
+  // ---------------- volume: forward (u, d1 u, d2 u, d3 u at points) --------
+  contract<N, 3, false>(B0, X, sV, 1);  // V1 x
+  contract<N, 3, false>(B1, X, sD, 1);  // D1 x
+  __syncthreads();
+  contract<N, 3, false>(B2, B0, sV, N);  // V2 V1 x
+  contract<N, 3, false>(B3, B1, sV, N);  // V2 D1 x
+  contract<N, 3, false>(B4, B0, sD, N);  // D2 V1 x
+  __syncthreads();
+  contract<N, 3, false>(B0, B2, sV, NF);  // u
+  contract<N, 3, false>(B1, B3, sV, NF);  // d^1 u (reference)
+  contract<N, 3, false>(B5, B4, sV, NF);  // d^2 u
+  contract<N, 3, false>(B6, B2, sD, NF);  // d^3 u
+  __syncthreads();
+  // ---------------- volume: pointwise flux (eq. (gauss_points)) ------------
+  for (int i = tid; i < NB; i += kRefThreads) {
+    const int q1 = i % N, q2 = (i / N) % N, q3 = i / NF;
+    const double u = B0[i];
+    const double g[3] = {B1[i] / h[0], B5[i] / h[1], B6[i] / h[2]};
+    const int qq[3] = {q1, q2, q3};
+    const double W = sw[q1] * sw[q2] * sw[q3] * vol;
+    double Fr[3];
+    for (int r = 0; r < 3; ++r) {
+      const int ax = M.b_axis[r];
+      const double br = M.bvol[r][ic[ax] * N + qq[ax]];
+      Fr[r] = kap * (M.K[3 * r] * g[0] + M.K[3 * r + 1] * g[1] + M.K[3 * r + 2] * g[2]) - br * u;
+    }
+    B0[i] = W * M.c * u;
+    B1[i] = W * Fr[0] / h[0];
+    B5[i] = W * Fr[1] / h[1];
+    B6[i] = W * Fr[2] / h[2];
+  }
+  __syncthreads();
+  // ---------------- volume: transposed contractions (eq. (evalblf)) --------
+  contract<N, 3, true>(B2, B0, sV, NF, B6, sD);  // along 3: V^T x0 + D^T x3
+  contract<N, 3, true>(B3, B1, sV, NF);          // V^T x1
+  contract<N, 3, true>(B4, B5, sV, NF);          // V^T x2
+  __syncthreads();
+  contract<N, 3, true>(B0, B2, sV, N, B4, sD);  // along 2
+  contract<N, 3, true>(B1, B3, sV, N);
+  __syncthreads();
+  contract<N, 3, true>(Y, B0, sV, 1, B1, sD);  // along 1
+  __syncthreads();
+
+  // ---------------- faces --------------------------------------------------
+  double *Uo = F[0], *Do = F[1], *Un = F[2], *Dn = F[3];
+  double *S0 = F[4], *S1 = F[5], *S2 = F[6], *S3 = F[7];
+  double *uo = F[8], *un = F[9], *gao = F[10], *gan = F[11];
+  double *gbo = F[12], *gbn = F[13], *gco = F[14], *gcn = F[15];
+  for (int f = 0; f < 6; ++f) {
+    const int a = f >> 1, e = f & 1;  // e = 1: upper face x_a = 1 (outer normal +e_a)
+    const int b = (a == 0) ? 1 : 0, c = (a == 2) ? 1 : 2;
+    const int st[3] = {1, N, NF};
+    const int sa = st[a], sb = st[b], sc = st[c];
+    const bool interior = e ? (ic[a] + 1 < M.ncell[a]) : (ic[a] > 0);
+    const int nbcell = interior ? cell + (e ? cstride[a] : -cstride[a]) : cell;
+    const double *xN = x + size_t(nbcell) * NB;
+    // normal direction first: modal traces on the 2D (jb, jc) grid
+    for (int i = tid; i < NF; i += kRefThreads) {
+      const int jb = i % N, jc = i / N;
+      const int base = jb * sb + jc * sc;
+      double uo_ = 0, do_ = 0, un_ = 0, dn_ = 0;
+      for (int ja = 0; ja < N; ++ja) {
+        uo_ = fma(sev[e][ja], X[base + ja * sa], uo_);
+        do_ = fma(sed[e][ja], X[base + ja * sa], do_);
+      }
+      if (interior)
+        for (int ja = 0; ja < N; ++ja) {
+          const double v = xN[base + ja * sa];
+          un_ = fma(sev[1 - e][ja], v, un_);
+          dn_ = fma(sed[1 - e][ja], v, dn_);
+        }
+      Uo[i] = uo_;
+      Do[i] = do_;
+      Un[i] = un_;
+      Dn[i] = dn_;
+    }
+    __syncthreads();
+    // tangential evaluation: first b (stride 1 in the 2D grid), then c
+    contract<N, 2, false>(S0, Uo, sV, 1);
+    contract<N, 2, false>(S1, Uo, sD, 1);
+    contract<N, 2, false>(S2, Un, sV, 1);
+    contract<N, 2, false>(S3, Un, sD, 1);
+    __syncthreads();
+    contract<N, 2, false>(uo, S0, sV, N);
+    contract<N, 2, false>(gbo, S1, sV, N);
+    contract<N, 2, false>(gco, S0, sD, N);
+    contract<N, 2, false>(un, S2, sV, N);
+    contract<N, 2, false>(gbn, S3, sV, N);
+    contract<N, 2, false>(gcn, S2, sD, N);
+    __syncthreads();
+    contract<N, 2, false>(S0, Do, sV, 1);
+    contract<N, 2, false>(S1, Dn, sV, 1);
+    __syncthreads();
+    contract<N, 2, false>(gao, S0, sV, N);
+    contract<N, 2, false>(gan, S1, sV, N);
+    __syncthreads();
+    // pointwise face terms (Sec. 2.2): upwind flux, weighted average,
+    // penalty, written with the outer normal n_T = sgn e_a of cell T
+    {
+      const double sgn = e ? 1.0 : -1.0;
+      const double hn = interior ? (a == 0 ? M.h[0][ic[0] + (e ? 1 : -1)]
+                                   : a == 1 ? M.h[1][ic[1] + (e ? 1 : -1)]
+                                            : M.h[2][ic[2] + (e ? 1 : -1)])
+                                 : h[a];
+      const double kn = interior ? (M.kappa ? M.kappa[nbcell] : 1.0) : 0.0;
+      const double Kaa = M.K[4 * a];
+      const double dT = kap * Kaa, dN = kn * Kaa;
+      const double wT = interior ? dN / (dT + dN) : 1.0;
+      const double wN = interior ? dT / (dT + dN) : 0.0;
+      const double gamma = interior ? M.sigma * (2.0 * dT * dN / (dT + dN)) / fmin(h[a], hn)
+                                    : M.sigma * dT / h[a];
+      const double area = h[b] * h[c];
+      const double Kab = M.K[3 * a + b], Kac = M.K[3 * a + c];
+      for (int i = tid; i < NF; i += kRefThreads) {
+        const int qb = i % N, qc = i / N;
+        // normal flux component (K grad u)_a of own / neighbour traces
+        const double KgT = Kaa * gao[i] / h[a] + Kab * gbo[i] / h[b] + Kac * gco[i] / h[c];
+        const double KgN = Kaa * gan[i] / hn + Kab * gbn[i] / h[b] + Kac * gcn[i] / h[c];
+        const double avg = sgn * (wT * kap * KgT + wN * kn * KgN);  // {D grad u}_w . n_T
+        const double J = uo[i] - un[i];
+        // b_a at the face point: b_a depends on the coordinate b_axis[a]
+        const int ax = M.b_axis[a];
+        double ba;
+        if (ax == a)
+          ba = M.bnode[a][ic[a] + e];
+        else if (ax == b)
+          ba = M.bvol[a][ic[b] * N + qb];
+        else
+          ba = M.bvol[a][ic[c] * N + qc];
+        const double bout = sgn * ba;
+        const double Phi = bout >= 0.0 ? bout * uo[i] : bout * un[i];
+        const double W = sw[qb] * sw[qc] * area;
+        const double RV = W * (Phi - avg + gamma * J);
+        const double RT = -W * wT * kap * J * sgn;  // times (K grad phi)_a
+        S0[i] = RV;
+        S1[i] = RT * Kab / h[b];
+        S2[i] = RT * Kac / h[c];
+        S3[i] = RT * Kaa / h[a];
+      }
+    }
+    __syncthreads();
+    // transposed tangential contractions: along c, then b
+    contract<N, 2, true>(uo, S0, sV, N, S2, sD);  // value x V_c + (d_c part) x D_c
+    contract<N, 2, true>(un, S1, sV, N);          // d_b part
+    contract<N, 2, true>(gao, S3, sV, N);         // d_a part
+    __syncthreads();
+    contract<N, 2, true>(Uo, uo, sV, 1, un, sD);  // R_v
+    contract<N, 2, true>(Do, gao, sV, 1);         // R_d
+    __syncthreads();
+    // normal direction last: y(ja,jb,jc) += theta_ja(e) R_v + theta'_ja(e) R_d
+    for (int i = tid; i < NB; i += kRefThreads) {
+      const int j[3] = {i % N, (i / N) % N, i / NF};
+      const int i2 = j[b] + N * j[c];
+      Y[i] += sev[e][j[a]] * Uo[i2] + sed[e][j[a]] * Do[i2];
+    }
+    __syncthreads();
+  }
+  double *yT = y + size_t(cell) * NB;
+  for (int i = tid; i < NB; i += kRefThreads) yT[i] = Y[i];
+}
+
+template <int N>
+static hipError_t launch_ref_n(const dg_handle *h, const double *x, double *y, hipStream_t s) {
+  RefTab<N> T;
+  for (int q = 0; q < N; ++q) {
+    for (int j = 0; j < N; ++j) {
+      T.V[q][j] = h->tab.V[q][j];
+      T.D[q][j] = h->tab.D[q][j];
+    }
+    T.w[q] = h->tab.w[q];
+    T.ev[0][q] = h->tab.e0v[q];
+    T.ev[1][q] = h->tab.e1v[q];
+    T.ed[0][q] = h->tab.e0d[q];
+    T.ed[1][q] = h->tab.e1d[q];
+  }
+  RefMesh M;
+  for (int a = 0; a < 3; ++a) {
+    M.ncell[a] = h->mesh.ncell[a];
+    M.h[a] = h->mesh.h[a];
+    M.bvol[a] = h->mesh.bvol[a];
+    M.bnode[a] = h->mesh.bnode[a];
+    M.b_axis[a] = h->mesh.b_axis[a];
+  }
+  M.kappa = h->mesh.kappa;
+  for (int i = 0; i < 9; ++i) M.K[i] = h->mesh.K[i];
+  M.c = h->mesh.c;
+  M.sigma = h->mesh.sigma;
+  hipLaunchKernelGGL(apply_ref_kernel<N>, dim3(unsigned(h->ncells)), dim3(kRefThreads), 0, s, x, y,
+                     M, T);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_ref_f64(const dg_handle *h, const double *x, double *y, hipStream_t s) {
+  switch (h->k + 1) {
+    case 2: return launch_ref_n<2>(h, x, y, s);
+    case 3: return launch_ref_n<3>(h, x, y, s);
+    case 4: return launch_ref_n<4>(h, x, y, s);
+    case 5: return launch_ref_n<5>(h, x, y, s);
+    case 6: return launch_ref_n<6>(h, x, y, s);
+    case 7: return launch_ref_n<7>(h, x, y, s);
+    case 8: return launch_ref_n<8>(h, x, y, s);
+    case 9: return launch_ref_n<9>(h, x, y, s);
+    case 10: return launch_ref_n<10>(h, x, y, s);
+    case 11: return launch_ref_n<11>(h, x, y, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace dgmf

@@ -1,0 +1,265 @@
+// Host side of libdgmf: problem validation, 1D tables, device tables, errors.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dg_internal.h"
+
+namespace dgmf {
+
+static thread_local std::string g_last_error;
+
+dg_status set_error(dg_status s, const std::string &msg) {
+  g_last_error = msg;
+  return s;
+}
+
+dg_status hip_error(hipError_t e, const char *what) {
+  return set_error(e == hipErrorOutOfMemory ? DG_ENOMEM : DG_EHIP,
+                   std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Legendre P_m and P_m' at s in [-1,1] (Bonnet recurrence).
+static void legendre_pm(int m, double s, double &p, double &dp) {
+  double p0 = 1.0, p1 = s;
+  if (m == 0) {
+    p = 1.0;
+    dp = 0.0;
+    return;
+  }
+  for (int j = 2; j <= m; ++j) {
+    const double p2 = ((2 * j - 1) * s * p1 - (j - 1) * p0) / j;
+    p0 = p1;
+    p1 = p2;
+  }
+  p = p1;
+  dp = m * (s * p1 - p0) / (s * s - 1.0);
+}
+
+// m-point Gauss-Legendre rule on [0,1] (tensor Gauss quadrature of Sec. 3.1),
+// nodes ascending, weights summing to one.
+static void gauss01(int m, double *xi, double *w) {
+  for (int i = 0; i < (m + 1) / 2; ++i) {
+    // Tricomi's initial guess for the i-th largest root
+    double s = (1.0 - (m - 1.0) / (8.0 * m * m * m)) * std::cos(M_PI * (4.0 * i + 3.0) / (4.0 * m + 2.0));
+    double p = 0, dp = 0;
+    for (int it = 0; it < 64; ++it) {
+      legendre_pm(m, s, p, dp);
+      const double ds = p / dp;
+      s -= ds;
+      if (std::fabs(ds) <= 1e-17) break;
+    }
+    legendre_pm(m, s, p, dp);
+    const double wt = 1.0 / ((1.0 - s * s) * dp * dp);  // 2/(...) on [-1,1], halved
+    xi[m - 1 - i] = 0.5 + 0.5 * s;
+    w[m - 1 - i] = wt;
+    xi[i] = 0.5 - 0.5 * s;
+    w[i] = wt;
+  }
+  if (m % 2 == 1) xi[m / 2] = 0.5;  // exact midpoint
+}
+
+// theta_j(t) = sqrt(2j+1) P_j(2t-1) and its derivative, j = 0..k.
+static void legendre_basis(int k, double t, double *v, double *d) {
+  const double s = 2.0 * t - 1.0;
+  double P[kMaxN + 1], dP[kMaxN + 1];
+  P[0] = 1.0;
+  dP[0] = 0.0;
+  if (k >= 1) {
+    P[1] = s;
+    dP[1] = 1.0;
+  }
+  for (int j = 2; j <= k; ++j) {
+    P[j] = ((2 * j - 1) * s * P[j - 1] - (j - 1) * P[j - 2]) / j;
+    dP[j] = j * P[j - 1] + s * dP[j - 1];  // P_j' = j P_{j-1} + s P_{j-1}'
+  }
+  for (int j = 0; j <= k; ++j) {
+    const double sc = std::sqrt(2.0 * j + 1.0);
+    v[j] = sc * P[j];
+    d[j] = 2.0 * sc * dP[j];
+  }
+}
+
+static void build_tables(int k, Tables &t) {
+  std::memset(&t, 0, sizeof(t));
+  t.n = k + 1;
+  gauss01(k + 1, t.xi, t.w);
+  for (int q = 0; q <= k; ++q) legendre_basis(k, t.xi[q], t.V[q], t.D[q]);
+  legendre_basis(k, 0.0, t.e0v, t.e0d);
+  legendre_basis(k, 1.0, t.e1v, t.e1d);
+}
+
+static bool is_spd(const double *K) {
+  double mx = 0.0;
+  for (int i = 0; i < 9; ++i) {
+    if (!std::isfinite(K[i])) return false;
+    mx = std::fmax(mx, std::fabs(K[i]));
+  }
+  if (mx == 0.0) return false;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < i; ++j)
+      if (std::fabs(K[3 * i + j] - K[3 * j + i]) > 1e-12 * mx) return false;
+  double L[9] = {0};
+  for (int j = 0; j < 3; ++j) {
+    double s = K[4 * j];
+    for (int p = 0; p < j; ++p) s -= L[3 * j + p] * L[3 * j + p];
+    if (!(s > 1e-14 * mx)) return false;
+    L[4 * j] = std::sqrt(s);
+    for (int i = j + 1; i < 3; ++i) {
+      double t = K[3 * i + j];
+      for (int p = 0; p < j; ++p) t -= L[3 * i + p] * L[3 * j + p];
+      L[3 * i + j] = t / L[4 * j];
+    }
+  }
+  return true;
+}
+
+}  // namespace dgmf
+
+using namespace dgmf;
+
+extern "C" const char *dg_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" int64_t dg_ndof(const dg_handle *h) { return h ? h->ndof : -1; }
+
+extern "C" int32_t dg_degree(const dg_handle *h) { return h ? h->k : -1; }
+
+extern "C" dg_status dg_set_kernel(dg_handle *h, int32_t variant) {
+  if (!h) return set_error(DG_EINVAL, "dg_set_kernel: handle is NULL");
+  if (variant != DG_KERNEL_AUTO && variant != DG_KERNEL_REFERENCE)
+    return set_error(DG_EINVAL, "dg_set_kernel: unknown variant");
+  h->variant = variant;
+  return DG_OK;
+}
+
+extern "C" void dg_destroy(dg_handle *h) {
+  if (!h) return;
+  int cur = 0;
+  if (hipGetDevice(&cur) == hipSuccess && cur != h->device) (void)hipSetDevice(h->device);
+  if (h->dev_block) (void)hipFree(h->dev_block);
+  if (cur != h->device) (void)hipSetDevice(cur);
+  delete h;
+}
+
+extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
+  if (!out) return set_error(DG_EINVAL, "dg_setup: out is NULL");
+  *out = nullptr;
+  if (!p) return set_error(DG_EINVAL, "dg_setup: problem is NULL");
+  if (p->k < 1 || p->k > 10) return set_error(DG_EINVAL, "dg_setup: k must be in 1..10");
+  int64_t ncells = 1;
+  for (int a = 0; a < 3; ++a) {
+    if (p->ncell[a] < 1) return set_error(DG_EINVAL, "dg_setup: ncell must be >= 1");
+    if (!p->nodes[a]) return set_error(DG_EINVAL, "dg_setup: nodes pointer is NULL");
+    for (int i = 0; i <= p->ncell[a]; ++i)
+      if (!std::isfinite(p->nodes[a][i]))
+        return set_error(DG_EINVAL, "dg_setup: nodes must be finite");
+    for (int i = 0; i < p->ncell[a]; ++i)
+      if (!(p->nodes[a][i + 1] > p->nodes[a][i]))
+        return set_error(DG_EINVAL, "dg_setup: nodes must be strictly increasing");
+    if (p->b_axis[a] < 0 || p->b_axis[a] > 2)
+      return set_error(DG_EINVAL, "dg_setup: b_axis must be 0, 1 or 2");
+    if (!std::isfinite(p->b_const[a]) || !std::isfinite(p->b_sin[a]))
+      return set_error(DG_EINVAL, "dg_setup: b must be finite");
+    ncells *= p->ncell[a];
+  }
+  if (!is_spd(p->K)) return set_error(DG_EINVAL, "dg_setup: K must be symmetric positive definite");
+  if (!std::isfinite(p->c)) return set_error(DG_EINVAL, "dg_setup: c must be finite");
+  if (!(p->sigma > 0.0) || !std::isfinite(p->sigma))
+    return set_error(DG_EINVAL, "dg_setup: sigma must be positive");
+  if (p->kappa)
+    for (int64_t c = 0; c < ncells; ++c)
+      if (!(p->kappa[c] > 0.0) || !std::isfinite(p->kappa[c]))
+        return set_error(DG_EINVAL, "dg_setup: kappa must be positive and finite");
+  const int n = p->k + 1;
+  if (ncells > (int64_t(1) << 31) / 2) return set_error(DG_EINVAL, "dg_setup: too many cells");
+
+  dg_handle *h = new dg_handle();
+  std::memset(&h->prob, 0, sizeof(h->prob));
+  h->prob = *p;
+  for (int a = 0; a < 3; ++a) h->prob.nodes[a] = nullptr;
+  h->prob.kappa = nullptr;
+  h->k = p->k;
+  h->ncells = ncells;
+  h->ndof = ncells * n * n * n;
+  h->dev_block = nullptr;
+  h->variant = DG_KERNEL_AUTO;
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return set_error(DG_EHIP, "dg_setup: no HIP device");
+  }
+  build_tables(p->k, h->tab);
+
+  // host staging of every device table, then one allocation + one copy
+  const int m = n;
+  std::vector<double> host;
+  size_t off_h[3], off_bv[3], off_bn[3], off_kappa = 0;
+  for (int a = 0; a < 3; ++a) {
+    off_h[a] = host.size();
+    for (int i = 0; i < p->ncell[a]; ++i) host.push_back(p->nodes[a][i + 1] - p->nodes[a][i]);
+  }
+  for (int r = 0; r < 3; ++r) {
+    const int ax = p->b_axis[r];
+    off_bv[r] = host.size();
+    for (int i = 0; i < p->ncell[ax]; ++i) {
+      const double o = p->nodes[ax][i], hh = p->nodes[ax][i + 1] - p->nodes[ax][i];
+      for (int q = 0; q < m; ++q)
+        host.push_back(p->b_const[r] + p->b_sin[r] * std::sin(M_PI * (o + hh * h->tab.xi[q])));
+    }
+    off_bn[r] = host.size();
+    for (int i = 0; i <= p->ncell[ax]; ++i)
+      host.push_back(p->b_const[r] + p->b_sin[r] * std::sin(M_PI * p->nodes[ax][i]));
+  }
+  if (p->kappa) {
+    off_kappa = host.size();
+    host.insert(host.end(), p->kappa, p->kappa + ncells);
+  }
+  hipError_t e = hipMalloc(&h->dev_block, host.size() * sizeof(double));
+  if (e != hipSuccess) {
+    delete h;
+    return hip_error(e, "dg_setup: hipMalloc");
+  }
+  e = hipMemcpy(h->dev_block, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    dg_destroy(h);
+    return hip_error(e, "dg_setup: hipMemcpy");
+  }
+  double *base = static_cast<double *>(h->dev_block);
+  DevMesh &M = h->mesh;
+  for (int a = 0; a < 3; ++a) {
+    M.ncell[a] = p->ncell[a];
+    M.h[a] = base + off_h[a];
+    M.bvol[a] = base + off_bv[a];
+    M.bnode[a] = base + off_bn[a];
+    M.b_axis[a] = p->b_axis[a];
+  }
+  M.kappa = p->kappa ? base + off_kappa : nullptr;
+  std::memcpy(M.K, p->K, sizeof(M.K));
+  M.c = p->c;
+  M.sigma = p->sigma;
+  *out = h;
+  return DG_OK;
+}
+
+static bool overlaps(const void *a, const void *b, size_t bytes) {
+  const char *pa = static_cast<const char *>(a), *pb = static_cast<const char *>(b);
+  return pa < pb + bytes && pb < pa + bytes;
+}
+
+extern "C" dg_status dg_apply(dg_handle *h, const double *x, double *y, void *stream) {
+  if (!h) return set_error(DG_EINVAL, "dg_apply: handle is NULL");
+  if (!x || !y) return set_error(DG_EINVAL, "dg_apply: x or y is NULL");
+  if (overlaps(x, y, size_t(h->ndof) * sizeof(double)))
+    return set_error(DG_EINVAL, "dg_apply: x and y overlap");
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != h->device) {
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_error(e, "dg_apply: hipSetDevice");
+  }
+  hipError_t e = launch_apply_ref_f64(h, x, y, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_error(e, "dg_apply: kernel launch");
+  return DG_OK;
+}

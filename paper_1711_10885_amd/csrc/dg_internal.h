@@ -1,0 +1,59 @@
+// Internal declarations of libdgmf (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "dg.h"
+
+namespace dgmf {
+
+constexpr int kMaxN = 11;  // k <= 10
+
+// 1D tables on the reference interval [0,1] for one degree (Sec. 3.2,
+// eq. (gradient_matrices); face tables B^(q) of Sec. 3.4):
+//   V[q][j] = theta_j(xi_q), D[q][j] = theta_j'(xi_q),
+//   e0v/e1v = theta_j(0/1), e0d/e1d = theta_j'(0/1), w = Gauss weights.
+struct Tables {
+  int n;
+  double xi[kMaxN], w[kMaxN];
+  double V[kMaxN][kMaxN], D[kMaxN][kMaxN];
+  double e0v[kMaxN], e1v[kMaxN], e0d[kMaxN], e1d[kMaxN];
+};
+
+// Geometry/coefficient tables in device memory, shared by all kernels.
+struct DevMesh {
+  int ncell[3];
+  double *h[3];       // cell extents per axis, ncell[a]
+  double *bvol[3];    // b_r at volume Gauss coordinates: [ncell[b_axis[r]] * m]
+  double *bnode[3];   // b_r at nodes of axis b_axis[r]: [ncell[b_axis[r]] + 1]
+  double *kappa;      // per cell or nullptr (= 1)
+  double K[9];
+  double c, sigma;
+  int b_axis[3];
+};
+
+}  // namespace dgmf
+
+struct dg_handle {
+  int device;
+  int k;
+  int64_t ncells, ndof;
+  dg_problem prob;  // host copy (pointers cleared)
+  dgmf::Tables tab;
+  dgmf::DevMesh mesh;
+  void *dev_block;  // single allocation backing the DevMesh arrays
+  int variant;      // DG_KERNEL_*
+};
+
+namespace dgmf {
+
+dg_status set_error(dg_status s, const std::string &msg);
+dg_status hip_error(hipError_t e, const char *what);
+
+// Kernel launchers, dispatching on k.
+hipError_t launch_apply_ref_f64(const dg_handle *h, const double *x, double *y, hipStream_t s);
+
+}  // namespace dgmf

@@ -1,0 +1,96 @@
+"""The C-ABI library: loads, exports every symbol include/dg.h declares, and
+rejects invalid problems before touching the GPU (CPU only)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1711_10885_amd import binding, workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_1711_10885_amd import build
+        build.build()
+    return binding.load()
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "dg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dg_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_binding_exports():
+    assert _declared() == sorted(binding.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def _struct(prob, **over):
+    s = binding._Problem()
+    keep = [np.ascontiguousarray(prob.nodes[a], dtype=np.float64) for a in range(3)]
+    for a in range(3):
+        s.ncell[a] = prob.ncell[a]
+        s.nodes[a] = keep[a].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        s.b_axis[a] = prob.b_axis[a]
+    s.k = prob.k
+    for i, v in enumerate(np.asarray(prob.K).ravel()):
+        s.K[i] = v
+    s.c = prob.c
+    s.sigma = prob.sigma
+    for key, val in over.items():
+        if key == "K":
+            for i, v in enumerate(np.asarray(val).ravel()):
+                s.K[i] = v
+        elif key == "b_axis0":
+            s.b_axis[0] = val
+        else:
+            setattr(s, key, val)
+    return s, keep
+
+
+@pytest.mark.parametrize("over,msg", [
+    (dict(k=0), "k must be"),
+    (dict(k=11), "k must be"),
+    (dict(sigma=0.0), "sigma"),
+    (dict(K=np.diag([1.0, -1.0, 1.0])), "positive definite"),
+    (dict(K=np.array([[1, 0.5, 0], [0, 1, 0], [0, 0, 1.0]])), "symmetric"),
+    (dict(b_axis0=3), "b_axis"),
+    (dict(c=float("nan")), "c must be finite"),
+])
+def test_setup_rejects_invalid_problems(over, msg):
+    lib = _lib()
+    s, keep = _struct(workloads.poisson_k2_8(), **over)
+    h = ctypes.c_void_p()
+    rc = lib.dg_setup(ctypes.byref(s), ctypes.byref(h))
+    assert rc == binding.DG_EINVAL
+    assert msg in lib.dg_last_error().decode()
+    assert not h.value
+
+
+def test_setup_rejects_non_increasing_nodes():
+    lib = _lib()
+    p = workloads.poisson_k2_8()
+    bad = p.with_(nodes=(p.nodes[0], np.concatenate([[0.0, 0.5, 0.4], p.nodes[1][3:]]), p.nodes[2]))
+    s, keep = _struct(bad)
+    h = ctypes.c_void_p()
+    assert lib.dg_setup(ctypes.byref(s), ctypes.byref(h)) == binding.DG_EINVAL
+    assert "increasing" in lib.dg_last_error().decode()
+
+
+def test_null_arguments():
+    lib = _lib()
+    h = ctypes.c_void_p()
+    assert lib.dg_setup(None, ctypes.byref(h)) == binding.DG_EINVAL
+    assert lib.dg_apply(None, None, None, None) == binding.DG_EINVAL
+    assert lib.dg_ndof(None) == -1
+    lib.dg_destroy(None)

@@ -1,0 +1,113 @@
+"""GPU parity of the FP64 apply against the CPU oracle, through the C ABI.
+
+Bar: relative error <= 1e-12 in both the 2-norm and the max-norm
+(||y - y_o|| <= 1e-12 ||y_o||, max|y - y_o| <= 1e-12 max|y_o|).
+Both kernel variants are checked on the same seeded inputs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1711_10885_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+VARIANTS = [0, 1]  # DG_KERNEL_AUTO, DG_KERNEL_REFERENCE
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _gpu_apply(prob, x, variant, repeat=1):
+    torch = _torch()
+    from paper_1711_10885_amd import binding
+    with binding.DG(prob) as dg:
+        dg.set_kernel(variant)
+        xd = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+        outs = [dg.apply(xd).cpu().numpy() for _ in range(repeat)]
+    torch.cuda.synchronize()
+    return outs if repeat > 1 else outs[0]
+
+
+def _check(y, ref, what):
+    e2 = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+    emax = np.abs(y - ref).max() / np.abs(ref).max()
+    print(f"{what}: rel2 {e2:.2e} relmax {emax:.2e}", flush=True)
+    assert e2 <= TOL and emax <= TOL, (what, e2, emax)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_poisson_k2_8_full(variant):
+    p = W.poisson_k2_8()
+    x = W.workload_vector(p)
+    _check(_gpu_apply(p, x, variant), oracle.apply(p, x), f"poisson_k2_8 v{variant}")
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("k", range(1, 11))
+def test_random_small_every_degree(variant, k):
+    ncell = (4, 3, 2) if k <= 5 else (3, 2, 2)
+    p = W.random_problem(100 + k, ncell=ncell, k=k, b="sine" if k % 2 else "const")
+    x = W.random_vector(p.ndof, 200 + k)
+    _check(_gpu_apply(p, x, variant), oracle.apply(p, x), f"random k={k} {ncell} v{variant}")
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("ncell", [(1, 1, 1), (5, 1, 1), (1, 4, 1), (1, 1, 3), (2, 3, 5)])
+def test_degenerate_meshes(variant, ncell):
+    p = W.random_problem(300, ncell=ncell, k=3, b="sine")
+    x = W.random_vector(p.ndof, 301)
+    _check(_gpu_apply(p, x, variant), oracle.apply(p, x), f"mesh {ncell} v{variant}")
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("terms", ["b_axis_self", "no_kappa_zero_b", "diag_K"])
+def test_coefficient_kinds(variant, terms):
+    p = W.random_problem(400, ncell=(3, 3, 2), k=4, b="sine")
+    if terms == "b_axis_self":  # b_a depends on x_a itself (node tables on faces)
+        p = p.with_(b_axis=(0, 1, 2))
+    elif terms == "no_kappa_zero_b":
+        p = p.with_(kappa=None, b_const=(0, 0, 0), b_sin=(0, 0, 0))
+    else:
+        p = p.with_(K=np.diag([2.0, 0.5, 1.5]))
+    x = W.random_vector(p.ndof, 401)
+    _check(_gpu_apply(p, x, variant), oracle.apply(p, x), f"{terms} v{variant}")
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_cdr_k7_32_sampled_rows(variant):
+    """Full-size k = 7, 32^3 workload in the benchmarked launch configuration;
+    the oracle computes the rows of sampled cells one by one (all corners,
+    edge/face cells and random interior cells)."""
+    p = W.cdr_k7_32()
+    x = W.workload_vector(p)
+    y = _gpu_apply(p, x, variant).reshape(p.ncells, -1)
+    N = p.ncell[0]
+    rng = np.random.default_rng(9)
+    corners = [i + N * (j + N * k) for i in (0, N - 1) for j in (0, N - 1) for k in (0, N - 1)]
+    cells = np.unique(np.concatenate([corners, rng.integers(0, p.ncells, 56)]))
+    ref = oracle.apply_rows(p, x, cells)
+    _check(y[cells], ref, f"cdr_k7_32 sampled v{variant}")
+
+
+def test_deterministic_and_variants_agree():
+    p = W.random_problem(500, ncell=(4, 4, 4), k=5, b="sine")
+    x = W.random_vector(p.ndof, 501)
+    a1, a2 = _gpu_apply(p, x, 0, repeat=2)
+    assert np.array_equal(a1, a2)
+    r = _gpu_apply(p, x, 1)
+    assert np.abs(a1 - r).max() <= 1e-13 * np.abs(r).max()
+
+
+def test_aliasing_rejected():
+    torch = _torch()
+    from paper_1711_10885_amd import binding
+    p = W.poisson_k2_8()
+    with binding.DG(p) as dg:
+        x = torch.zeros(dg.ndof, dtype=torch.float64, device="cuda")
+        with pytest.raises(binding.DGError, match="overlap"):
+            dg.apply(x, x)
