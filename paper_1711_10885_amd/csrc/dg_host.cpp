@@ -213,6 +213,8 @@ extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
     for (int i = 0; i <= p->ncell[ax]; ++i)
       host.push_back(p->b_const[r] + p->b_sin[r] * std::sin(M_PI * p->nodes[ax][i]));
   }
+  const size_t off_w = host.size();
+  host.insert(host.end(), h->tab.w, h->tab.w + m);
   if (p->kappa) {
     off_kappa = host.size();
     host.insert(host.end(), p->kappa, p->kappa + ncells);
@@ -237,6 +239,7 @@ extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
     M.b_axis[a] = p->b_axis[a];
   }
   M.kappa = p->kappa ? base + off_kappa : nullptr;
+  M.w = base + off_w;
   std::memcpy(M.K, p->K, sizeof(M.K));
   M.c = p->c;
   M.sigma = p->sigma;
@@ -259,7 +262,9 @@ extern "C" dg_status dg_apply(dg_handle *h, const double *x, double *y, void *st
     hipError_t e = hipSetDevice(h->device);
     if (e != hipSuccess) return hip_error(e, "dg_apply: hipSetDevice");
   }
-  hipError_t e = launch_apply_ref_f64(h, x, y, static_cast<hipStream_t>(stream));
+  hipError_t e = (h->variant == DG_KERNEL_REFERENCE)
+                     ? launch_apply_ref_f64(h, x, y, static_cast<hipStream_t>(stream))
+                     : launch_apply_fused_f64(h, x, y, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_error(e, "dg_apply: kernel launch");
   return DG_OK;
 }

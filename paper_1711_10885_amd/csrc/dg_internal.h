@@ -30,6 +30,7 @@ struct DevMesh {
   double *bvol[3];    // b_r at volume Gauss coordinates: [ncell[b_axis[r]] * m]
   double *bnode[3];   // b_r at nodes of axis b_axis[r]: [ncell[b_axis[r]] + 1]
   double *kappa;      // per cell or nullptr (= 1)
+  double *w;          // Gauss weights on [0,1] (for lane-dependent lookups)
   double K[9];
   double c, sigma;
   int b_axis[3];
@@ -55,5 +56,6 @@ dg_status hip_error(hipError_t e, const char *what);
 
 // Kernel launchers, dispatching on k.
 hipError_t launch_apply_ref_f64(const dg_handle *h, const double *x, double *y, hipStream_t s);
+hipError_t launch_apply_fused_f64(const dg_handle *h, const double *x, double *y, hipStream_t s);
 
 }  // namespace dgmf
