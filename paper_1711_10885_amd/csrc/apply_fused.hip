@@ -39,6 +39,7 @@ template <int N>
 struct FTab {
   double V[N][N], D[N][N];  // V[q][j] = theta_j(xi_q), D[q][j] = theta_j'(xi_q)
   double ev[2][N], ed[2][N];  // theta_j(e), theta_j'(e) for e = 0, 1
+  double w[N];                // Gauss weights on [0,1]
 };
 
 struct FMesh {
@@ -60,12 +61,13 @@ struct FCfg {
   static constexpr int THREADS = ((CPB * LANES + 63) / 64) * 64;
   // per-cell LDS (doubles) of each exchange round
   static constexpr int R1 = 2 * NN * PS + 16 * N * PS;
-  static constexpr int R2A = 3 * NN * PS + 6 * N * PS;
-  static constexpr int R2B = 8 * NN + 24 * N * PS;
-  static constexpr int R3 = 3 * NN * PS + 6 * NN + 6 * N * PS;
-  static constexpr int R4 = 2 * NN * PS + 4 * NN;
+  static constexpr int R2 = 3 * NN * PS + 4 * N * PS;
+  static constexpr int R2Z = 4 * NN;
+  static constexpr int R3 = 14 * N * PS;
+  static constexpr int R4 = 3 * NN * PS + 4 * NN + 4 * N * PS;
+  static constexpr int R5 = 2 * NN * PS + 4 * NN;
   static constexpr int mx(int a, int b) { return a > b ? a : b; }
-  static constexpr int REGION = mx(mx(mx(R1, R2A), mx(R2B, R3)), R4);
+  static constexpr int REGION = mx(mx(mx(R1, R2), mx(R2Z, R3)), mx(R4, R5));
 };
 
 // out[q] = sum_t M[q][t] in[t]
@@ -100,74 +102,88 @@ __device__ __forceinline__ double dotv(const double (&v)[N], const double *in) {
   return s;
 }
 
-// Per-cell geometry and coefficients used by the face terms.
+// Per-cell geometry used by the face terms.
 struct FaceGeo {
-  double h[3];
+  double h0, h1, h2;
   double kap;
-  int ic[3];
+  int i0, i1, i2;
 };
 
-// Pointwise face terms of eq. (blf) seen from cell T with outer normal
-// n_T = sgn e_a: upwind flux, weighted average of the normal diffusive flux,
-// symmetry term and penalty.  Inputs are the reference-coordinate values
-// (u, d_b u, d_c u, d_a u) of the own (o) and neighbour (n) traces at one
-// face point; outputs the four test-function coefficients:
-//   RV (times phi), Pb (times theta'_jb), Pc (times theta'_jc),
-//   Pa (times theta'_ja(e)) -- all in reference scaling.
-struct FaceCoef {
-  double sgn, wT, wN, kT, kN, gamma, inv_ha, inv_hn, inv_hb, inv_hc, area, Kaa, Kab, Kac;
+__device__ __forceinline__ double sel3(int a, double v0, double v1, double v2) {
+  return a == 0 ? v0 : (a == 1 ? v1 : v2);
+}
+__device__ __forceinline__ int seli3(int a, int v0, int v1, int v2) {
+  return a == 0 ? v0 : (a == 1 ? v1 : v2);
+}
+
+// Constants of the face terms of eq. (blf) for the face of cell T normal to
+// axis a on side e (outer normal n_T = sgn e_a), tangential axes b < c.
+// With reference-coordinate traces of the own (o) and neighbour (n) side,
+//   {D grad u}_w . n_T = cTa ga_o + cTb gb_o + cTc gc_o + cNa ga_n + cNb gb_n + cNc gc_n
+// (weights w = delta-ratio of Sec. 2.2, delta = kappa K_aa), and the symmetry
+// term of a test function of T is Z * (cTa th'_a th_b th_c + cTb th_a th'_b th_c
+// + cTc th_a th_b th'_c) with Z = -W [[u]].  Boundary faces: w_T = 1, w_N = 0,
+// neighbour traces zero (homogeneous Dirichlet), gamma = sigma delta / h_a.
+struct FC {
+  double cTa, cTb, cTc, cNa, cNb, cNc, gamma, sgn;
 };
 
-__device__ __forceinline__ void face_point(const FaceCoef &F, double uo, double gbo, double gco,
-                                           double gao, double un, double gbn, double gcn,
-                                           double gan, double ba, double W, double &RV,
-                                           double &Pb, double &Pc, double &Pa) {
-  const double KgT = F.Kaa * gao * F.inv_ha + F.Kab * gbo * F.inv_hb + F.Kac * gco * F.inv_hc;
-  const double KgN = F.Kaa * gan * F.inv_hn + F.Kab * gbn * F.inv_hb + F.Kac * gcn * F.inv_hc;
-  const double avg = F.sgn * (F.wT * F.kT * KgT + F.wN * F.kN * KgN);
+__device__ __forceinline__ FC face_coef(const FMesh &M, const FaceGeo &G, int cell, int a, int e) {
+  const int b = (a == 0) ? 1 : 0, c = (a == 2) ? 1 : 2;
+  const int ia = seli3(a, G.i0, G.i1, G.i2);
+  const int na = seli3(a, M.ncell[0], M.ncell[1], M.ncell[2]);
+  const bool in = e ? (ia + 1 < na) : (ia > 0);
+  const int cst = seli3(a, 1, M.ncell[0], M.ncell[0] * M.ncell[1]);
+  const int ncl = in ? (e ? cell + cst : cell - cst) : cell;
+  const double *ha_tab = a == 0 ? M.h[0] : (a == 1 ? M.h[1] : M.h[2]);
+  const double ha = sel3(a, G.h0, G.h1, G.h2);
+  const double hb = sel3(b, G.h0, G.h1, G.h2);
+  const double hc = sel3(c, G.h0, G.h1, G.h2);
+  const double hn = in ? ha_tab[ia + (e ? 1 : -1)] : ha;
+  const double kn = in ? (M.kappa ? M.kappa[ncl] : 1.0) : 0.0;
+  const double Kaa = sel3(a, M.K[0], M.K[4], M.K[8]);
+  const double Kab = a == 0 ? M.K[1] : M.K[3 * a];          // K[a][b], b = 0 unless a = 0
+  const double Kac = a == 2 ? M.K[7] : M.K[3 * a + 2];      // K[a][c], c = 2 unless a = 2
+  const double dT = G.kap * Kaa, dN = kn * Kaa;
+  FC F;
+  F.sgn = e ? 1.0 : -1.0;
+  const double wT = in ? dN / (dT + dN) : 1.0;
+  const double wN = in ? dT / (dT + dN) : 0.0;
+  F.gamma = in ? M.sigma * (2.0 * dT * dN / (dT + dN)) / fmin(ha, hn) : M.sigma * dT / ha;
+  const double sT = F.sgn * wT * G.kap, sN = F.sgn * wN * kn;
+  F.cTa = sT * Kaa / ha;
+  F.cTb = sT * Kab / hb;
+  F.cTc = sT * Kac / hc;
+  F.cNa = in ? sN * Kaa / hn : 0.0;
+  F.cNb = sN * Kab / hb;
+  F.cNc = sN * Kac / hc;
+  return F;
+}
+
+// Pointwise face flux at one face point: RV multiplies the test function,
+// Z = -W [[u]] the symmetry-term combination above.
+__device__ __forceinline__ void face_flux(const FC &F, double uo, double un, double avg, double ba,
+                                          double W, double &RV, double &Z) {
   const double J = uo - un;
   const double bout = F.sgn * ba;
   const double Phi = bout >= 0.0 ? bout * uo : bout * un;
   RV = W * (Phi - avg + F.gamma * J);
-  const double RT = -W * F.wT * F.kT * J * F.sgn;
-  Pb = RT * F.Kab * F.inv_hb;
-  Pc = RT * F.Kac * F.inv_hc;
-  Pa = RT * F.Kaa * F.inv_ha;
-}
-
-__device__ __forceinline__ FaceCoef make_face(const FMesh &M, const FaceGeo &G, int a, int e,
-                                              bool interior, double hn, double kn) {
-  const int b = (a == 0) ? 1 : 0, c = (a == 2) ? 1 : 2;
-  FaceCoef F;
-  F.sgn = e ? 1.0 : -1.0;
-  const double Kaa = M.K[4 * a];
-  const double dT = G.kap * Kaa, dN = kn * Kaa;
-  F.kT = G.kap;
-  F.kN = interior ? kn : 0.0;
-  F.wT = interior ? dN / (dT + dN) : 1.0;
-  F.wN = interior ? dT / (dT + dN) : 0.0;
-  F.gamma = interior ? M.sigma * (2.0 * dT * dN / (dT + dN)) / fmin(G.h[a], hn)
-                     : M.sigma * dT / G.h[a];
-  F.inv_ha = 1.0 / G.h[a];
-  F.inv_hn = interior ? 1.0 / hn : 0.0;
-  F.inv_hb = 1.0 / G.h[b];
-  F.inv_hc = 1.0 / G.h[c];
-  F.area = G.h[b] * G.h[c];
-  F.Kaa = Kaa;
-  F.Kab = M.K[3 * a + b];
-  F.Kac = M.K[3 * a + c];
-  return F;
+  Z = -W * J;
 }
 
 // b_a at a point of the face normal to a (side e) with tangential Gauss
 // indices qb, qc.
 __device__ __forceinline__ double face_b(const FMesh &M, const FaceGeo &G, int N, int a, int e,
                                          int qb, int qc) {
-  const int b = (a == 0) ? 1 : 0, c = (a == 2) ? 1 : 2;
   const int ax = M.b_axis[a];
-  if (ax == a) return M.bnode[a][G.ic[a] + e];
-  if (ax == b) return M.bvol[a][G.ic[b] * N + qb];
-  return M.bvol[a][G.ic[c] * N + qc];
+  const double *bv = a == 0 ? M.bvol[0] : (a == 1 ? M.bvol[1] : M.bvol[2]);
+  const double *bn = a == 0 ? M.bnode[0] : (a == 1 ? M.bnode[1] : M.bnode[2]);
+  if (ax == a) return bn[seli3(a, G.i0, G.i1, G.i2) + e];
+  // b = 0 unless a = 0; c = 2 unless a = 2
+  const int b = (a == 0) ? 1 : 0;
+  if (ax == b) return bv[seli3(b, G.i0, G.i1, G.i2) * N + qb];
+  const int c = (a == 2) ? 1 : 2;
+  return bv[seli3(c, G.i0, G.i1, G.i2) * N + qc];
 }
 
 __device__ __forceinline__ int cell_of_logical(int L, const FMesh &M) {
@@ -203,54 +219,60 @@ __global__ __launch_bounds__(FCfg<N>::THREADS) void apply_fused_kernel(
   double *R = lds + (slot ? cl : 0) * C::REGION;
 
   FaceGeo G;
-  G.ic[0] = cell % M.ncell[0];
-  G.ic[1] = (cell / M.ncell[0]) % M.ncell[1];
-  G.ic[2] = cell / (M.ncell[0] * M.ncell[1]);
-  G.h[0] = M.h[0][G.ic[0]];
-  G.h[1] = M.h[1][G.ic[1]];
-  G.h[2] = M.h[2][G.ic[2]];
+  G.i0 = cell % M.ncell[0];
+  G.i1 = (cell / M.ncell[0]) % M.ncell[1];
+  G.i2 = cell / (M.ncell[0] * M.ncell[1]);
+  G.h0 = M.h[0][G.i0];
+  G.h1 = M.h[1][G.i1];
+  G.h2 = M.h[2][G.i2];
   G.kap = M.kappa ? M.kappa[cell] : 1.0;
-  const int cstride[3] = {1, M.ncell[0], M.ncell[0] * M.ncell[1]};
-
-  // neighbour data of the six faces f = 2a + e
-  bool fin[6];
-  double fh[6], fk[6];
-  int fcell[6];
-#pragma unroll
-  for (int f = 0; f < 6; ++f) {
-    const int a = f >> 1, e = f & 1;
-    fin[f] = e ? (G.ic[a] + 1 < M.ncell[a]) : (G.ic[a] > 0);
-    fcell[f] = fin[f] ? cell + (e ? cstride[a] : -cstride[a]) : cell;
-    fh[f] = fin[f] ? M.h[a][G.ic[a] + (e ? 1 : -1)] : G.h[a];
-    fk[f] = fin[f] ? (M.kappa ? M.kappa[fcell[f]] : 1.0) : 0.0;
-  }
 
   // ------------------------------------------------------------------------
-  // P0: global loads.  Lane (j2,j3) = (alpha,beta) owns the x pencil along 1.
+  // Round 1.  Lane (j2,j3) = (alpha,beta) owns the x pencil along axis 1.
+  // Writes: Tv, Td as B-pencils (q1 + N j3) along j2, and 16 modal face
+  // trace fields, each N pencils of its first tangential axis (lane
+  // (alpha,beta) writes element alpha of pencil beta):
+  //   x faces (a=0): grid (j2,j3), fid = 4e + {0:U_o, 1:Dn_o, 2:U_n, 3:Dn_n}
+  //   y nb    (a=1): grid (j1,j3), fid = 8 + 2e + {U_n, Dn_n}
+  //   z nb    (a=2): grid (j1,j2), fid = 12 + 2e + {U_n, Dn_n}
+  // U = trace of u, Dn = trace of d_a u (normal direction contracted first).
   // ------------------------------------------------------------------------
-  double X[N];
+  constexpr int B_OFF = 0;
+  constexpr int F1_OFF = 2 * NN * PS;
+  const int w1 = beta * PS + alpha;
   {
+    double X[N];
     const double *xp = x + size_t(cell) * NNN + NN * beta + N * alpha;
 #pragma unroll
     for (int t = 0; t < N; ++t) X[t] = xp[t];
-  }
-  // own x-face traces (e = 0, 1): value and normal derivative
-  double uxo[2], dxo[2];
+    if (slot) {
 #pragma unroll
-  for (int e = 0; e < 2; ++e) {
-    uxo[e] = dotv<N>(T.ev[e], X);
-    dxo[e] = dotv<N>(T.ed[e], X);
+      for (int e = 0; e < 2; ++e) {
+        R[F1_OFF + (4 * e + 0) * N * PS + w1] = dotv<N>(T.ev[e], X);
+        R[F1_OFF + (4 * e + 1) * N * PS + w1] = dotv<N>(T.ed[e], X);
+      }
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        double sv = 0.0, sd = 0.0;
+#pragma unroll
+        for (int t = 0; t < N; ++t) {
+          sv = fma(T.V[q][t], X[t], sv);
+          sd = fma(T.D[q][t], X[t], sd);
+        }
+        R[B_OFF + (q + N * beta) * PS + alpha] = sv;
+        R[B_OFF + NN * PS + (q + N * beta) * PS + alpha] = sd;
+      }
+    }
   }
-  // neighbour traces, normal direction contracted from global memory
-  double unb[6], dnb[6];
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
     const int a = f >> 1, e = f & 1;
+    const int ia = a == 0 ? G.i0 : (a == 1 ? G.i1 : G.i2);
+    const bool in = e ? (ia + 1 < M.ncell[a]) : (ia > 0);
+    const int cst = (a == 0) ? 1 : (a == 1) ? M.ncell[0] : M.ncell[0] * M.ncell[1];
     double v[N];
-    if (fin[f]) {
-      const double *xn = x + size_t(fcell[f]) * NNN;
-      // pencil along the normal axis a; lane (alpha, beta) indexes the two
-      // tangential axes in increasing order
+    if (in) {
+      const double *xn = x + size_t(e ? cell + cst : cell - cst) * NNN;
       const int base = (a == 0) ? (N * alpha + NN * beta)
                        : (a == 1) ? (alpha + NN * beta) : (alpha + N * beta);
       const int st = (a == 0) ? 1 : (a == 1) ? N : NN;
@@ -260,47 +282,16 @@ __global__ __launch_bounds__(FCfg<N>::THREADS) void apply_fused_kernel(
 #pragma unroll
       for (int t = 0; t < N; ++t) v[t] = 0.0;
     }
-    unb[f] = dotv<N>(T.ev[1 - e], v);
-    dnb[f] = dotv<N>(T.ed[1 - e], v);
-  }
-  // volume step A
-  double Tv[N], Td[N];
-  mv<N>(T.V, X, Tv);
-  mv<N>(T.D, X, Td);
-
-  // ------------------------------------------------------------------------
-  // R1: volume A->B exchange and first tangential sweep of the face traces.
-  // Face field fid (16 of them) is stored as N pencils of the first
-  // tangential axis; lane (alpha, beta) writes element alpha of pencil beta:
-  //   x faces (a=0): grid (j2,j3), fid = 4e + 2s + {0:U,1:Dn}, s = 0 own, 1 nb
-  //   y nb    (a=1): grid (j1,j3), fid = 8 + 2e + {U,Dn}
-  //   z nb    (a=2): grid (j1,j2), fid = 12 + 2e + {U,Dn}
-  // ------------------------------------------------------------------------
-  constexpr int B_OFF = 0;                 // Tv, Td B-pencils (q1 + N j3) along j2
-  constexpr int F1_OFF = 2 * NN * PS;
-  if (slot) {
-#pragma unroll
-    for (int q = 0; q < N; ++q) {
-      R[B_OFF + (q + N * beta) * PS + alpha] = Tv[q];
-      R[B_OFF + NN * PS + (q + N * beta) * PS + alpha] = Td[q];
-    }
-    const int w1 = beta * PS + alpha;
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      R[F1_OFF + (4 * e + 0) * N * PS + w1] = uxo[e];
-      R[F1_OFF + (4 * e + 1) * N * PS + w1] = dxo[e];
-      R[F1_OFF + (4 * e + 2) * N * PS + w1] = unb[e];
-      R[F1_OFF + (4 * e + 3) * N * PS + w1] = dnb[e];
-      R[F1_OFF + (8 + 2 * e) * N * PS + w1] = unb[2 + e];
-      R[F1_OFF + (9 + 2 * e) * N * PS + w1] = dnb[2 + e];
-      R[F1_OFF + (12 + 2 * e) * N * PS + w1] = unb[4 + e];
-      R[F1_OFF + (13 + 2 * e) * N * PS + w1] = dnb[4 + e];
+    const int fid = (a == 0) ? (4 * e + 2) : (a == 1 ? 8 + 2 * e : 12 + 2 * e);
+    if (slot) {
+      R[F1_OFF + fid * N * PS + w1] = dotv<N>(T.ev[1 - e], v);
+      R[F1_OFF + (fid + 1) * N * PS + w1] = dotv<N>(T.ed[1 - e], v);
     }
   }
   __syncthreads();
   // volume step B: lane (q1, j3) = (alpha, beta)
   double vv[N], dv[N], vd[N];
-  double uyo[2], gyo[2], dyo[2];  // own y traces on (q1, j3)
+  double yS[2], yA[2];  // own y-face value trace and flux part on (q1, j3)
   {
     double P[N], Q[N];
 #pragma unroll
@@ -313,40 +304,75 @@ __global__ __launch_bounds__(FCfg<N>::THREADS) void apply_fused_kernel(
     mv<N>(T.D, P, vd);
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-      uyo[e] = dotv<N>(T.ev[e], P);
-      gyo[e] = dotv<N>(T.ev[e], Q);
-      dyo[e] = dotv<N>(T.ed[e], P);
+      const FC F = face_coef(M, G, cell, 1, e);
+      yS[e] = dotv<N>(T.ev[e], P);
+      // b = axis 0 derivative from Td, normal derivative from theta'
+      yA[e] = F.cTb * dotv<N>(T.ev[e], Q) + F.cTa * dotv<N>(T.ed[e], P);
     }
   }
-  // face tasks of the first tangential sweep: 8 face-sides x N pencils.
-  // face-side fs: 0..3 x faces (e = fs>>1, s = fs&1), 4..5 y nb (e), 6..7 z nb (e)
-  constexpr int NT1 = 8 * N;
+  // First tangential sweep of the face traces.  Tasks:
+  //   t <  2N : x face e = t/N, pencil j3 = t%N  -> Sv_o, Sv_n, A1 (own + nb flux part)
+  //   t <  4N : y nb  e, pencil j3               -> Sv_n, A1_n
+  //   t <  6N : z nb  e, pencil j2               -> Sv_n, A1_n
+  // with Sv = V U and A1 = cSa V Dn + cSb D U along the first tangential axis.
+  constexpr int NT1 = 6 * N;
   constexpr int NR1 = (NT1 + C::LANES - 1) / C::LANES;
   double S1[NR1][3][N];
 #pragma unroll
   for (int r = 0; r < NR1; ++r) {
     const int task = p + r * C::LANES;
     if (task < NT1) {
-      const int fs = task / N, pi = task % N;
-      const int fidU = (fs < 4) ? (2 * fs) : (fs < 6 ? 8 + 2 * (fs - 4) : 12 + 2 * (fs - 6));
+      const int kind = task / (2 * N), e = (task / N) & 1, pi = task % N;
+      const int a = kind;
+      const FC F = face_coef(M, G, cell, a, e);
+      const int fid = (kind == 0) ? (4 * e + 2) : (kind == 1 ? 8 + 2 * e : 12 + 2 * e);
       double U[N], Dn[N];
 #pragma unroll
       for (int t = 0; t < N; ++t) {
-        U[t] = R[F1_OFF + fidU * N * PS + pi * PS + t];
-        Dn[t] = R[F1_OFF + (fidU + 1) * N * PS + pi * PS + t];
+        U[t] = R[F1_OFF + fid * N * PS + pi * PS + t];
+        Dn[t] = R[F1_OFF + (fid + 1) * N * PS + pi * PS + t];
       }
-      mv<N>(T.V, U, S1[r][0]);
-      mv<N>(T.D, U, S1[r][1]);
-      mv<N>(T.V, Dn, S1[r][2]);
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        double sv = 0.0, sd = 0.0, sn = 0.0;
+#pragma unroll
+        for (int t = 0; t < N; ++t) {
+          sv = fma(T.V[q][t], U[t], sv);
+          sd = fma(T.D[q][t], U[t], sd);
+          sn = fma(T.V[q][t], Dn[t], sn);
+        }
+        S1[r][1][q] = sv;                       // Sv_n
+        S1[r][2][q] = F.cNa * sn + F.cNb * sd;  // A1_n
+      }
+      if (kind == 0) {
+#pragma unroll
+        for (int t = 0; t < N; ++t) {
+          U[t] = R[F1_OFF + (4 * e) * N * PS + pi * PS + t];
+          Dn[t] = R[F1_OFF + (4 * e + 1) * N * PS + pi * PS + t];
+        }
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+          double sv = 0.0, sd = 0.0, sn = 0.0;
+#pragma unroll
+          for (int t = 0; t < N; ++t) {
+            sv = fma(T.V[q][t], U[t], sv);
+            sd = fma(T.D[q][t], U[t], sd);
+            sn = fma(T.V[q][t], Dn[t], sn);
+          }
+          S1[r][0][q] = sv;                                     // Sv_o
+          S1[r][2][q] += F.cTa * sn + F.cTb * sd;               // + A1_o
+        }
+      }
     }
   }
   __syncthreads();
 
   // ------------------------------------------------------------------------
-  // R2a: volume B->C exchange and z-neighbour second tangential sweep input.
+  // Round 2.  Volume B->C exchange; z-neighbour second tangential sweep.
   // ------------------------------------------------------------------------
-  constexpr int C_OFF = 0;                    // vv, dv, vd C-pencils (q1 + N q2) along j3
-  constexpr int Z2_OFF = 3 * NN * PS;         // z nb (e, {Sv,Sd,Sn}) pencils along j2, index q1
+  constexpr int C_OFF = 0;                 // vv, dv, vd C-pencils (q1 + N q2) along j3
+  constexpr int Z2_OFF = 3 * NN * PS;      // z nb (e, {Sv_n, A1_n}) pencils along j2, index q1
+  constexpr int ZN_OFF = 0;                // (e, {u_n, avg_n}) on (q1 + N q2), after C reads
   if (slot) {
 #pragma unroll
     for (int q = 0; q < N; ++q) {
@@ -357,73 +383,56 @@ __global__ __launch_bounds__(FCfg<N>::THREADS) void apply_fused_kernel(
 #pragma unroll
     for (int r = 0; r < NR1; ++r) {
       const int task = p + r * C::LANES;
-      if (task < NT1) {
-        const int fs = task / N, pi = task % N;  // pi = j2 (second tangential)
-        if (fs >= 6) {
-          const int e = fs - 6;
+      if (task >= 4 * N && task < NT1) {
+        const int e = (task / N) & 1, pi = task % N;  // pi = j2
 #pragma unroll
-          for (int g = 0; g < 3; ++g)
+        for (int g = 0; g < 2; ++g)
 #pragma unroll
-            for (int q = 0; q < N; ++q) R[Z2_OFF + (3 * e + g) * N * PS + q * PS + pi] = S1[r][g][q];
-        }
+          for (int q = 0; q < N; ++q)
+            R[Z2_OFF + (2 * e + g) * N * PS + q * PS + pi] = S1[r][1 + g][q];
       }
     }
   }
   __syncthreads();
-  // volume step C: lane (q1, q2) = (alpha, beta)
-  double U[N], G1[N], G2[N], G3[N];
-  double zo[2][4];  // own z traces at (q1, q2): u, d1, d2, d3 (reference)
-  {
-    double P[N], Q[N], S[N];
+  double Pc[N], Qc[N], Sc[N];  // C-stage input pencils of lane (q1, q2)
 #pragma unroll
-    for (int t = 0; t < N; ++t) {
-      P[t] = R[C_OFF + p * PS + t];
-      Q[t] = R[C_OFF + NN * PS + p * PS + t];
-      S[t] = R[C_OFF + 2 * NN * PS + p * PS + t];
-    }
-    mv<N>(T.V, P, U);
-    mv<N>(T.V, Q, G1);
-    mv<N>(T.V, S, G2);
-    mv<N>(T.D, P, G3);
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      zo[e][0] = dotv<N>(T.ev[e], P);
-      zo[e][1] = dotv<N>(T.ev[e], Q);
-      zo[e][2] = dotv<N>(T.ev[e], S);
-      zo[e][3] = dotv<N>(T.ed[e], P);
-    }
+  for (int t = 0; t < N; ++t) {
+    Pc[t] = R[C_OFF + p * PS + t];
+    Qc[t] = R[C_OFF + NN * PS + p * PS + t];
+    Sc[t] = R[C_OFF + 2 * NN * PS + p * PS + t];
   }
-  // z-neighbour second sweep tasks (e, q1): values at (q1, all q2)
+  // z-neighbour second sweep tasks (e, q1): u_n and the neighbour part of the
+  // averaged normal flux at (q1, all q2); c = axis 1
   constexpr int NT2Z = 2 * N;
   constexpr int NR2Z = (NT2Z + C::LANES - 1) / C::LANES;
-  double Zn[NR2Z][4][N];
+  double Zn[NR2Z][2][N];
 #pragma unroll
   for (int r = 0; r < NR2Z; ++r) {
     const int task = p + r * C::LANES;
     if (task < NT2Z) {
       const int e = task / N, pi = task % N;  // pi = q1
-      double Sv[N], Sd[N], Sn[N];
+      const FC F = face_coef(M, G, cell, 2, e);
+      double Sv[N], A1[N];
 #pragma unroll
       for (int t = 0; t < N; ++t) {
-        Sv[t] = R[Z2_OFF + (3 * e + 0) * N * PS + pi * PS + t];
-        Sd[t] = R[Z2_OFF + (3 * e + 1) * N * PS + pi * PS + t];
-        Sn[t] = R[Z2_OFF + (3 * e + 2) * N * PS + pi * PS + t];
+        Sv[t] = R[Z2_OFF + (2 * e + 0) * N * PS + pi * PS + t];
+        A1[t] = R[Z2_OFF + (2 * e + 1) * N * PS + pi * PS + t];
       }
-      mv<N>(T.V, Sv, Zn[r][0]);  // u
-      mv<N>(T.V, Sd, Zn[r][1]);  // d1 (axis b = 0)
-      mv<N>(T.D, Sv, Zn[r][2]);  // d2 (axis c = 1)
-      mv<N>(T.V, Sn, Zn[r][3]);  // d3 (normal)
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        double u = 0.0, a1 = 0.0, dc = 0.0;
+#pragma unroll
+        for (int t = 0; t < N; ++t) {
+          u = fma(T.V[q][t], Sv[t], u);
+          a1 = fma(T.V[q][t], A1[t], a1);
+          dc = fma(T.D[q][t], Sv[t], dc);
+        }
+        Zn[r][0][q] = u;
+        Zn[r][1][q] = a1 + F.cNc * dc;
+      }
     }
   }
   __syncthreads();
-
-  // ------------------------------------------------------------------------
-  // R2b: z-neighbour point values to the volume lanes; x and y face second
-  // tangential sweep inputs (pencils along j3 at fixed first tangential q).
-  //   x: face-side fs = 2e + s, grid (q2, j3); y: fs = 4 + 2e + s, grid (q1, j3)
-  // ------------------------------------------------------------------------
-  constexpr int ZN_OFF = 0;                  // (e, g) on (q1 + N q2)
-  constexpr int XY_OFF = 8 * NN;             // (fs, g) pencils along j3, index = first tangential q
   if (slot) {
 #pragma unroll
     for (int r = 0; r < NR2Z; ++r) {
@@ -431,145 +440,201 @@ __global__ __launch_bounds__(FCfg<N>::THREADS) void apply_fused_kernel(
       if (task < NT2Z) {
         const int e = task / N, pi = task % N;
 #pragma unroll
-        for (int g = 0; g < 4; ++g)
+        for (int g = 0; g < 2; ++g)
 #pragma unroll
-          for (int q = 0; q < N; ++q) R[ZN_OFF + (4 * e + g) * NN + pi + N * q] = Zn[r][g][q];
+          for (int q = 0; q < N; ++q) R[ZN_OFF + (2 * e + g) * NN + pi + N * q] = Zn[r][g][q];
       }
     }
-    // x faces (own and nb) and y nb from the first sweep tasks
+  }
+  // volume pointwise flux (eq. (gauss_points)) streamed over q3 straight into
+  // the C'-stage accumulators (eq. (evalblf))
+  double Wvv[N], Wdv[N], Wvd[N];
 #pragma unroll
-    for (int r = 0; r < NR1; ++r) {
-      const int task = p + r * C::LANES;
-      if (task < NT1) {
-        const int fs = task / N, pi = task % N;  // pi = j3
-        if (fs < 6) {
-          // x: fs 0..3 -> xy face-side fs; y nb: fs 4,5 -> e = fs-4, s = 1
-          const int xs = (fs < 4) ? fs : (4 + 2 * (fs - 4) + 1);
+  for (int j = 0; j < N; ++j) Wvv[j] = Wdv[j] = Wvd[j] = 0.0;
+  {
+    const double vol = G.h0 * G.h1 * G.h2;
+    const double wab = M.w[alpha] * M.w[beta] * vol;
+    const double ih0 = 1.0 / G.h0, ih1 = 1.0 / G.h1, ih2 = 1.0 / G.h2;
+    const double ihv[3] = {ih0, ih1, ih2};
+    // Kh[r][s] = kappa K_rs / (h_r h_s): D in reference derivatives
+    double Kh[9];
 #pragma unroll
-          for (int g = 0; g < 3; ++g)
+    for (int r = 0; r < 3; ++r)
 #pragma unroll
-            for (int q = 0; q < N; ++q)
-              R[XY_OFF + (3 * xs + g) * N * PS + q * PS + pi] = S1[r][g][q];
-        }
-      }
+      for (int s2 = 0; s2 < 3; ++s2) Kh[3 * r + s2] = G.kap * M.K[3 * r + s2] * ihv[r] * ihv[s2];
+    // b_r / h_r along the pencil: per-lane constant unless b_r varies along axis 3
+    double bh[3];
+    const double *bzt[3];
+    bool bz[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const int ax = M.b_axis[r];
+      bz[r] = (ax == 2);
+      const int ia = ax == 0 ? G.i0 : (ax == 1 ? G.i1 : G.i2);
+      const int qa = (ax == 0) ? alpha : beta;
+      bh[r] = bz[r] ? 0.0 : M.bvol[r][ia * N + qa] * ihv[r];
+      bzt[r] = M.bvol[r] + G.i2 * N;
     }
-    // own y traces from the volume lanes (q1, j3) = (alpha, beta)
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const int xs = 4 + 2 * e;
-      R[XY_OFF + (3 * xs + 0) * N * PS + alpha * PS + beta] = uyo[e];
-      R[XY_OFF + (3 * xs + 1) * N * PS + alpha * PS + beta] = gyo[e];
-      R[XY_OFF + (3 * xs + 2) * N * PS + alpha * PS + beta] = dyo[e];
+    for (int q3 = 0; q3 < N; ++q3) {
+      double u = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
+#pragma unroll
+      for (int t = 0; t < N; ++t) {
+        u = fma(T.V[q3][t], Pc[t], u);
+        g0 = fma(T.V[q3][t], Qc[t], g0);
+        g1 = fma(T.V[q3][t], Sc[t], g1);
+        g2 = fma(T.D[q3][t], Pc[t], g2);
+      }
+      const double W = wab * T.w[q3];
+      const double b0 = bz[0] ? bzt[0][q3] * ih0 : bh[0];
+      const double b1 = bz[1] ? bzt[1][q3] * ih1 : bh[1];
+      const double b2 = bz[2] ? bzt[2][q3] * ih2 : bh[2];
+      const double x0 = W * M.c * u;
+      const double x1 = W * (Kh[0] * g0 + Kh[1] * g1 + Kh[2] * g2 - b0 * u);
+      const double x2 = W * (Kh[3] * g0 + Kh[4] * g1 + Kh[5] * g2 - b1 * u);
+      const double x3 = W * (Kh[6] * g0 + Kh[7] * g1 + Kh[8] * g2 - b2 * u);
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        Wvv[j] = fma(T.V[q3][j], x0, Wvv[j]);
+        Wvv[j] = fma(T.D[q3][j], x3, Wvv[j]);
+        Wdv[j] = fma(T.V[q3][j], x1, Wdv[j]);
+        Wvd[j] = fma(T.V[q3][j], x2, Wvd[j]);
+      }
     }
   }
   __syncthreads();
-  // volume lane (q1, q2): pointwise volume flux and z-face terms, then C'
-  double Wvv[N], Wdv[N], Wvd[N];
+  // z faces (a = 2, b = 0, c = 1) at the point (q1, q2): own traces from the
+  // C-stage input pencils; integration merged into the C'-stage accumulators
   {
-    const double vol = G.h[0] * G.h[1] * G.h[2];
-    const double wa = M.w[alpha], wb = M.w[beta];
-    const double ih0 = 1.0 / G.h[0], ih1 = 1.0 / G.h[1], ih2 = 1.0 / G.h[2];
-    double x0[N], x1[N], x2[N], x3[N];
-    const int bax0 = M.b_axis[0], bax1 = M.b_axis[1], bax2 = M.b_axis[2];
-#pragma unroll
-    for (int q3 = 0; q3 < N; ++q3) {
-      const double u = U[q3];
-      const double g0 = G1[q3] * ih0, g1 = G2[q3] * ih1, g2 = G3[q3] * ih2;
-      const double W = wa * wb * M.w[q3] * vol;
-      const int qq0 = bax0 == 0 ? alpha : (bax0 == 1 ? beta : q3);
-      const int qq1 = bax1 == 0 ? alpha : (bax1 == 1 ? beta : q3);
-      const int qq2 = bax2 == 0 ? alpha : (bax2 == 1 ? beta : q3);
-      const double b0 = M.bvol[0][G.ic[bax0] * N + qq0];
-      const double b1 = M.bvol[1][G.ic[bax1] * N + qq1];
-      const double b2 = M.bvol[2][G.ic[bax2] * N + qq2];
-      const double F0 = G.kap * (M.K[0] * g0 + M.K[1] * g1 + M.K[2] * g2) - b0 * u;
-      const double F1 = G.kap * (M.K[3] * g0 + M.K[4] * g1 + M.K[5] * g2) - b1 * u;
-      const double F2 = G.kap * (M.K[6] * g0 + M.K[7] * g1 + M.K[8] * g2) - b2 * u;
-      x0[q3] = W * M.c * u;
-      x1[q3] = W * F0 * ih0;
-      x2[q3] = W * F1 * ih1;
-      x3[q3] = W * F2 * ih2;
-    }
-    mtv<N, false>(T.V, x0, Wvv);
-    mtv<N, true>(T.D, x3, Wvv);
-    mtv<N, false>(T.V, x1, Wdv);
-    mtv<N, false>(T.V, x2, Wvd);
-    // z faces (a = 2, b = 0, c = 1) at the point (q1, q2)
+    const double wab = M.w[alpha] * M.w[beta] * G.h0 * G.h1;
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-      const int f = 4 + e;
-      const FaceCoef F = make_face(M, G, 2, e, fin[f], fh[f], fk[f]);
-      const double un = R[ZN_OFF + (4 * e + 0) * NN + p];
-      const double gbn = R[ZN_OFF + (4 * e + 1) * NN + p];
-      const double gcn = R[ZN_OFF + (4 * e + 2) * NN + p];
-      const double gan = R[ZN_OFF + (4 * e + 3) * NN + p];
+      const FC F = face_coef(M, G, cell, 2, e);
+      const double uo = dotv<N>(T.ev[e], Pc);
+      const double avg = F.cTb * dotv<N>(T.ev[e], Qc) + F.cTc * dotv<N>(T.ev[e], Sc) +
+                         F.cTa * dotv<N>(T.ed[e], Pc) + R[ZN_OFF + (2 * e + 1) * NN + p];
+      const double un = R[ZN_OFF + (2 * e + 0) * NN + p];
       const double ba = face_b(M, G, N, 2, e, alpha, beta);
-      double RV, Pb, Pc, Pa;
-      face_point(F, zo[e][0], zo[e][1], zo[e][2], zo[e][3], un, gbn, gcn, gan, ba,
-                 wa * wb * F.area, RV, Pb, Pc, Pa);
+      double RV, Z;
+      face_flux(F, uo, un, avg, ba, wab, RV, Z);
 #pragma unroll
       for (int j = 0; j < N; ++j) {
         Wvv[j] = fma(T.ev[e][j], RV, Wvv[j]);
-        Wvv[j] = fma(T.ed[e][j], Pa, Wvv[j]);
-        Wdv[j] = fma(T.ev[e][j], Pb, Wdv[j]);
-        Wvd[j] = fma(T.ev[e][j], Pc, Wvd[j]);
+        Wvv[j] = fma(T.ed[e][j], F.cTa * Z, Wvv[j]);
+        Wdv[j] = fma(T.ev[e][j], F.cTb * Z, Wdv[j]);
+        Wvd[j] = fma(T.ev[e][j], F.cTc * Z, Wvd[j]);
       }
-    }
-  }
-  // x and y face tasks: (face-pair fp = 0,1 x (e); 2,3 y (e)) x N pencils
-  constexpr int NT2 = 4 * N;
-  constexpr int NR2 = (NT2 + C::LANES - 1) / C::LANES;
-  double Qf[NR2][3][N];
-#pragma unroll
-  for (int r = 0; r < NR2; ++r) {
-    const int task = p + r * C::LANES;
-    if (task < NT2) {
-      const int fp = task / N, pi = task % N;  // pi = first tangential q (q2 for x, q1 for y)
-      const int a = (fp < 2) ? 0 : 1, e = fp & 1;
-      const int f = 2 * a + e;
-      const int xso = (a == 0 ? 0 : 4) + 2 * e, xsn = xso + 1;
-      double val[2][4][N];  // side, {u, gb, gc, ga}, q3
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        const int xs = s ? xsn : xso;
-        double Sv[N], Sd[N], Sn[N];
-#pragma unroll
-        for (int t = 0; t < N; ++t) {
-          Sv[t] = R[XY_OFF + (3 * xs + 0) * N * PS + pi * PS + t];
-          Sd[t] = R[XY_OFF + (3 * xs + 1) * N * PS + pi * PS + t];
-          Sn[t] = R[XY_OFF + (3 * xs + 2) * N * PS + pi * PS + t];
-        }
-        mv<N>(T.V, Sv, val[s][0]);
-        mv<N>(T.V, Sd, val[s][1]);
-        mv<N>(T.D, Sv, val[s][2]);
-        mv<N>(T.V, Sn, val[s][3]);
-      }
-      const FaceCoef F = make_face(M, G, a, e, fin[f], fh[f], fk[f]);
-      const double wp = M.w[pi] * F.area;
-      double RVv[N], Pbv[N], Pcv[N], Pav[N];
-#pragma unroll
-      for (int q = 0; q < N; ++q) {
-        const double ba = face_b(M, G, N, a, e, pi, q);
-        face_point(F, val[0][0][q], val[0][1][q], val[0][2][q], val[0][3][q], val[1][0][q],
-                   val[1][1][q], val[1][2][q], val[1][3][q], ba, wp * M.w[q], RVv[q], Pbv[q],
-                   Pcv[q], Pav[q]);
-      }
-      // transposed sweep along q3 (the second tangential axis, c = 2)
-      mtv<N, false>(T.V, RVv, Qf[r][0]);
-      mtv<N, true>(T.D, Pcv, Qf[r][0]);
-      mtv<N, false>(T.V, Pbv, Qf[r][1]);
-      mtv<N, false>(T.V, Pav, Qf[r][2]);
     }
   }
   __syncthreads();
 
   // ------------------------------------------------------------------------
-  // R3: volume C'->B' exchange; y-face results to the volume lanes (q1, j3);
-  // x-face results as pencils along q2 at fixed j3.
+  // Round 3.  x and y faces: second tangential sweep (along axis 3), pointwise
+  // face terms and the first transposed sweep.  Inputs: pencils along j3 at
+  // fixed first tangential q:
+  //   x e: {Sv_o, Sv_n, A1} on (q2, j3), fields 3e + g
+  //   y e: {Sv_o, A1_o, Sv_n, A1_n} on (q1, j3), fields 6 + 4e + g
+  // ------------------------------------------------------------------------
+  constexpr int XY_OFF = 0;
+  if (slot) {
+#pragma unroll
+    for (int r = 0; r < NR1; ++r) {
+      const int task = p + r * C::LANES;
+      if (task < 4 * N) {
+        const int kind = task / (2 * N), e = (task / N) & 1, pi = task % N;  // pi = j3
+        if (kind == 0) {
+#pragma unroll
+          for (int g = 0; g < 3; ++g)
+#pragma unroll
+            for (int q = 0; q < N; ++q) R[XY_OFF + (3 * e + g) * N * PS + q * PS + pi] = S1[r][g][q];
+        } else {
+#pragma unroll
+          for (int g = 0; g < 2; ++g)
+#pragma unroll
+            for (int q = 0; q < N; ++q)
+              R[XY_OFF + (6 + 4 * e + 2 + g) * N * PS + q * PS + pi] = S1[r][1 + g][q];
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      R[XY_OFF + (6 + 4 * e + 0) * N * PS + alpha * PS + beta] = yS[e];
+      R[XY_OFF + (6 + 4 * e + 1) * N * PS + alpha * PS + beta] = yA[e];
+    }
+  }
+  __syncthreads();
+  // tasks (face pair fp: 0,1 x e; 2,3 y e) x N pencils; each produces the
+  // transposed-sweep results Q1 = V^T RV + cTc D^T Z and VZ = V^T Z over j3
+  constexpr int NT2 = 4 * N;
+  constexpr int NR2 = (NT2 + C::LANES - 1) / C::LANES;
+  double Qf[NR2][2][N];
+#pragma unroll
+  for (int r = 0; r < NR2; ++r) {
+    const int task = p + r * C::LANES;
+    if (task < NT2) {
+      const int fp = task / N, pi = task % N;  // pi = first tangential q (q2 for x, q1 for y)
+      const int a = fp >> 1, e = fp & 1;
+      const FC F = face_coef(M, G, cell, a, e);
+      double So[N], Sn[N], A1[N], A2[N];
+      if (a == 0) {
+#pragma unroll
+        for (int t = 0; t < N; ++t) {
+          So[t] = R[XY_OFF + (3 * e + 0) * N * PS + pi * PS + t];
+          Sn[t] = R[XY_OFF + (3 * e + 1) * N * PS + pi * PS + t];
+          A1[t] = R[XY_OFF + (3 * e + 2) * N * PS + pi * PS + t];
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < N; ++t) {
+          So[t] = R[XY_OFF + (6 + 4 * e + 0) * N * PS + pi * PS + t];
+          A1[t] = R[XY_OFF + (6 + 4 * e + 1) * N * PS + pi * PS + t] +
+                  R[XY_OFF + (6 + 4 * e + 3) * N * PS + pi * PS + t];
+          Sn[t] = R[XY_OFF + (6 + 4 * e + 2) * N * PS + pi * PS + t];
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < N; ++t) A2[t] = F.cTc * So[t] + F.cNc * Sn[t];
+      const double hb = a == 0 ? G.h1 : G.h0;
+      const double wp = M.w[pi] * hb * G.h2;
+      double VR[N], DZ[N], VZ[N];
+#pragma unroll
+      for (int j = 0; j < N; ++j) VR[j] = DZ[j] = VZ[j] = 0.0;
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        double uo = 0, un = 0, avg = 0;
+#pragma unroll
+        for (int t = 0; t < N; ++t) {
+          uo = fma(T.V[q][t], So[t], uo);
+          un = fma(T.V[q][t], Sn[t], un);
+          avg = fma(T.V[q][t], A1[t], avg);
+          avg = fma(T.D[q][t], A2[t], avg);
+        }
+        const double ba = face_b(M, G, N, a, e, pi, q);
+        double RV, Z;
+        face_flux(F, uo, un, avg, ba, wp * T.w[q], RV, Z);
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          VR[j] = fma(T.V[q][j], RV, VR[j]);
+          DZ[j] = fma(T.D[q][j], Z, DZ[j]);
+          VZ[j] = fma(T.V[q][j], Z, VZ[j]);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        Qf[r][0][j] = VR[j] + F.cTc * DZ[j];
+        Qf[r][1][j] = VZ[j];
+      }
+    }
+  }
+  __syncthreads();
+
+  // ------------------------------------------------------------------------
+  // Round 4.  Volume C'->B' exchange; y-face results to the volume lanes
+  // (q1, j3); x-face results as pencils along q2 at fixed j3.
   // ------------------------------------------------------------------------
   constexpr int BP_OFF = 0;                  // Wvv, Wdv, Wvd B'-pencils (q1 + N j3) along q2
-  constexpr int Y3_OFF = 3 * NN * PS;        // (e, g) on (q1 + N j3)
-  constexpr int X3_OFF = Y3_OFF + 6 * NN;    // (e, g) pencils along q2, index j3
+  constexpr int Y3_OFF = 3 * NN * PS;        // y (e, {Q1, VZ}) on (q1 + N j3)
+  constexpr int X3_OFF = Y3_OFF + 4 * NN;    // x (e, {Q1, VZ}) pencils along q2, index j3
   if (slot) {
 #pragma unroll
     for (int j = 0; j < N; ++j) {
@@ -585,21 +650,21 @@ __global__ __launch_bounds__(FCfg<N>::THREADS) void apply_fused_kernel(
         const int e = fp & 1;
         if (fp >= 2) {
 #pragma unroll
-          for (int g = 0; g < 3; ++g)
+          for (int g = 0; g < 2; ++g)
 #pragma unroll
-            for (int j = 0; j < N; ++j) R[Y3_OFF + (3 * e + g) * NN + pi + N * j] = Qf[r][g][j];
+            for (int j = 0; j < N; ++j) R[Y3_OFF + (2 * e + g) * NN + pi + N * j] = Qf[r][g][j];
         } else {
 #pragma unroll
-          for (int g = 0; g < 3; ++g)
+          for (int g = 0; g < 2; ++g)
 #pragma unroll
             for (int j = 0; j < N; ++j)
-              R[X3_OFF + (3 * e + g) * N * PS + j * PS + pi] = Qf[r][g][j];
+              R[X3_OFF + (2 * e + g) * N * PS + j * PS + pi] = Qf[r][g][j];
         }
       }
     }
   }
   __syncthreads();
-  // volume step B': lane (q1, j3) = (alpha, beta)
+  // volume step B': lane (q1, j3) = (alpha, beta), plus the y-face merge
   double Vv[N], Vd[N];
   {
     double P[N], Q[N], S[N];
@@ -614,14 +679,14 @@ __global__ __launch_bounds__(FCfg<N>::THREADS) void apply_fused_kernel(
     mtv<N, false>(T.V, Q, Vd);
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-      const double q1v = R[Y3_OFF + (3 * e + 0) * NN + p];
-      const double qbv = R[Y3_OFF + (3 * e + 1) * NN + p];
-      const double qav = R[Y3_OFF + (3 * e + 2) * NN + p];
+      const FC F = face_coef(M, G, cell, 1, e);
+      const double q1v = R[Y3_OFF + (2 * e + 0) * NN + p];
+      const double vz = R[Y3_OFF + (2 * e + 1) * NN + p];
 #pragma unroll
       for (int j = 0; j < N; ++j) {
         Vv[j] = fma(T.ev[e][j], q1v, Vv[j]);
-        Vv[j] = fma(T.ed[e][j], qav, Vv[j]);
-        Vd[j] = fma(T.ev[e][j], qbv, Vd[j]);
+        Vv[j] = fma(T.ed[e][j], F.cTa * vz, Vv[j]);
+        Vd[j] = fma(T.ev[e][j], F.cTb * vz, Vd[j]);
       }
     }
   }
@@ -634,25 +699,34 @@ __global__ __launch_bounds__(FCfg<N>::THREADS) void apply_fused_kernel(
     const int task = p + r * C::LANES;
     if (task < NT3) {
       const int e = task / N, pi = task % N;  // pi = j3
-      double Q1[N], Qb[N], Qa[N];
+      const FC F = face_coef(M, G, cell, 0, e);
+      double Q1[N], VZ[N];
 #pragma unroll
       for (int t = 0; t < N; ++t) {
-        Q1[t] = R[X3_OFF + (3 * e + 0) * N * PS + pi * PS + t];
-        Qb[t] = R[X3_OFF + (3 * e + 1) * N * PS + pi * PS + t];
-        Qa[t] = R[X3_OFF + (3 * e + 2) * N * PS + pi * PS + t];
+        Q1[t] = R[X3_OFF + (2 * e + 0) * N * PS + pi * PS + t];
+        VZ[t] = R[X3_OFF + (2 * e + 1) * N * PS + pi * PS + t];
       }
-      mtv<N, false>(T.V, Q1, Rx[r][0]);
-      mtv<N, true>(T.D, Qb, Rx[r][0]);
-      mtv<N, false>(T.V, Qa, Rx[r][1]);
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        double rv = 0.0, rb = 0.0, rd = 0.0;
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+          rv = fma(T.V[q][j], Q1[q], rv);
+          rb = fma(T.D[q][j], VZ[q], rb);
+          rd = fma(T.V[q][j], VZ[q], rd);
+        }
+        Rx[r][0][j] = rv + F.cTb * rb;
+        Rx[r][1][j] = F.cTa * rd;
+      }
     }
   }
   __syncthreads();
 
   // ------------------------------------------------------------------------
-  // R4: volume B'->A' exchange; x-face results to the volume lanes (j2, j3).
+  // Round 5.  Volume B'->A' exchange; x-face results to the volume lanes.
   // ------------------------------------------------------------------------
   constexpr int AP_OFF = 0;                  // Vv, Vd A'-pencils (j2 + N j3) along q1
-  constexpr int X4_OFF = 2 * NN * PS;        // (e, g) on (j2 + N j3)
+  constexpr int X4_OFF = 2 * NN * PS;        // (e, {R_v, R_d}) on (j2 + N j3)
   if (slot) {
 #pragma unroll
     for (int j = 0; j < N; ++j) {
@@ -672,7 +746,7 @@ __global__ __launch_bounds__(FCfg<N>::THREADS) void apply_fused_kernel(
     }
   }
   __syncthreads();
-  // volume step A': lane (j2, j3) = (alpha, beta)
+  // volume step A': lane (j2, j3) = (alpha, beta), plus the x-face merge
   if (active) {
     double P[N], Q[N], Yv[N];
 #pragma unroll
@@ -711,6 +785,7 @@ static hipError_t launch_fused_n(const dg_handle *h, const double *x, double *y,
     T.ev[1][q] = h->tab.e1v[q];
     T.ed[0][q] = h->tab.e0d[q];
     T.ed[1][q] = h->tab.e1d[q];
+    T.w[q] = h->tab.w[q];
   }
   FMesh M;
   for (int a = 0; a < 3; ++a) {
