@@ -3,48 +3,70 @@
 //
 // Mapping.  A cell is handled by N^2 lanes ("pencil slots"); lane p = a + N b
 // owns one 1D pencil of N values at a time and contracts it against the 1D
-// matrices of Sec. 3.2 (eq. (gradient_matrices)) held in scalar registers
-// (kernel-argument tables, compile-time indices), which is the sum
-// factorization kernel of eq. (sum_fact_kernel) with the tensor rotation
-// fused into the LDS exchange between directions.  Tensors pass through LDS
-// only to change the pencil direction; each exchange uses pencils padded to
-// N+1 doubles.
+// matrices of Sec. 3.2 (eq. (gradient_matrices)), which is the sum
+// factorization kernel of eq. (sum_fact_kernel) with the tensor rotation fused
+// into the LDS exchange between directions.  Tensors pass through LDS only to
+// change the pencil direction (pencils padded to N+1 doubles).
+//
+// Each 1D contraction uses the point symmetry of the Gauss rule and the parity
+// of the Legendre basis (theta_j(1-t) = (-1)^j theta_j(t)): only rows
+// q < ceil(N/2) of V = theta(xi) and D = theta'(xi) are stored and every
+// contraction splits into even and odd columns, halving its multiply-adds.
+// The tables live in the constant address space and are read with scalar
+// loads; each stage re-derives its table pointer through an empty asm so that
+// the compiler keeps table values short-lived instead of spilling them.
 //
 // Volume (Algorithm 1, steps 1-3), evaluation tree with a shared first sweep:
 //   A  (axis 1, lanes (j2,j3)):  x -> V1 x, D1 x
 //   B  (axis 2, lanes (q1,j3)):  -> V2V1x, V2D1x, D2V1x
-//   C  (axis 3, lanes (q1,q2)):  -> u, d1u, d2u, d3u at the Gauss points
-//   pointwise flux x^(r) of eq. (gauss_points), then the transposed sweeps
-//   C' (axis 3), B' (axis 2), A' (axis 1) of eq. (evalblf).
+//   C  (axis 3, lanes (q1,q2)):  -> u, d1u, d2u, d3u at the Gauss points,
+//   the pointwise flux x^(r) of eq. (gauss_points) and the transposed sweep
+//   C' (axis 3) in one streamed loop, then B' (axis 2), A' (axis 1) of
+//   eq. (evalblf).
 //
 // Faces (steps 4-6 / 8-10): the normal direction is contracted first on both
 // sides (Sec. 3.4/3.5: traces of u and of d_a u), then the two tangential
 // directions; pointwise flux; transposed tangential sweeps; normal direction
-// last.  Own-side work is merged into the volume tensors where the normal
-// axis is still modal there:
-//   z faces: own traces come from the C-stage input pencils, own integration
-//            is added to the C'-stage output pencils;
-//   y faces: own traces come from the B-stage input pencils (already
-//            evaluated along axis 1), own integration is added to the B'-stage
-//            output (the A' sweep then does the axis-1 integration);
+// last.  The averaged normal flux is linear in the traces with constants per
+// face, so the traces are combined into one "flux pencil" before evaluation.
+// Own-side work is merged into the volume tensors where the face normal axis
+// is still modal:
+//   z faces: own traces from the C-stage input pencils, integration added to
+//            the C'-stage accumulators;
+//   y faces: own traces from the B-stage input pencils (already evaluated
+//            along axis 1), integration added to the B'-stage output;
 //   x faces: own traces from the x pencils, integration added to the A'
 //            output.
 // Neighbour traces are contracted in the normal direction straight from
 // global memory (the pencil along the face normal is loaded by one lane).
+#include <vector>
+
 #include "dg_internal.h"
 
 namespace dgmf {
 
+typedef const __attribute__((address_space(4))) double *cptr;
+
+// Re-derive a table pointer: an empty asm makes loads through the result
+// distinct from earlier ones, so table values are reloaded per stage.
+__device__ __forceinline__ cptr fresh(cptr p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
+// Device table layout (doubles), H = ceil(N/2):
+//   V rows 0..H-1 [H*N] | D rows 0..H-1 [H*N] | theta(1) [N] | theta'(1) [N] | w 0..H-1 [H]
 template <int N>
-struct FTab {
-  double V[N][N], D[N][N];  // V[q][j] = theta_j(xi_q), D[q][j] = theta_j'(xi_q)
-  double ev[2][N], ed[2][N];  // theta_j(e), theta_j'(e) for e = 0, 1
-  double w[N];                // Gauss weights on [0,1]
+struct TabOff {
+  static constexpr int H = (N + 1) / 2;
+  static constexpr int V = 0, D = H * N, E1 = 2 * H * N, F1 = 2 * H * N + N, W = 2 * H * N + 2 * N;
+  static constexpr int SIZE = W + H;
 };
 
 struct FMesh {
   int ncell[3];
   const double *h[3], *bvol[3], *bnode[3], *kappa, *w;
+  const double *tab;
   double K[9], c, sigma;
   int b_axis[3];
   int tz;          // depth (cells along axis 3) of the tiles of the cell order
@@ -59,6 +81,7 @@ struct FCfg {
   static constexpr int LANES = NN;
   static constexpr int CPB = (NN <= 64) ? (64 / NN) : 1;
   static constexpr int THREADS = ((CPB * LANES + 63) / 64) * 64;
+  static constexpr int FCW = 8;  // doubles per face-constant record
   // per-cell LDS (doubles) of each exchange round
   static constexpr int R1 = 2 * NN * PS + 16 * N * PS;
   static constexpr int R2 = 3 * NN * PS + 4 * N * PS;
@@ -67,42 +90,102 @@ struct FCfg {
   static constexpr int R4 = 3 * NN * PS + 4 * NN + 4 * N * PS;
   static constexpr int R5 = 2 * NN * PS + 4 * NN;
   static constexpr int mx(int a, int b) { return a > b ? a : b; }
-  static constexpr int REGION = mx(mx(mx(R1, R2), mx(R2Z, R3)), mx(R4, R5));
+  static constexpr int EXCH = mx(mx(mx(R1, R2), mx(R2Z, R3)), mx(R4, R5));
+  static constexpr int REGION = EXCH + 6 * FCW;
 };
 
-// out[q] = sum_t M[q][t] in[t]
-template <int N>
-__device__ __forceinline__ void mv(const double (&M)[N][N], const double *in, double *out) {
+// ---- even-odd 1D contractions --------------------------------------------
+
+// out[q] = sum_j M[q][j] in[j], M = V (ISD false) or D (ISD true)
+template <int N, bool ISD>
+__device__ __forceinline__ void eo_mv(cptr M, const double *in, double *out) {
 #pragma unroll
-  for (int q = 0; q < N; ++q) {
-    double s = 0.0;
+  for (int q = 0; q < N / 2; ++q) {
+    double E = 0.0, O = 0.0;
 #pragma unroll
-    for (int t = 0; t < N; ++t) s = fma(M[q][t], in[t], s);
-    out[q] = s;
+    for (int j = 0; j < N; j += 2) E = fma(M[q * N + j], in[j], E);
+#pragma unroll
+    for (int j = 1; j < N; j += 2) O = fma(M[q * N + j], in[j], O);
+    out[q] = E + O;
+    out[N - 1 - q] = ISD ? (O - E) : (E - O);
+  }
+  if (N & 1) {
+    constexpr int m = N / 2;
+    double S = 0.0;
+#pragma unroll
+    for (int j = ISD ? 1 : 0; j < N; j += 2) S = fma(M[m * N + j], in[j], S);
+    out[m] = S;
   }
 }
 
 // out[j] (+)= sum_q M[q][j] in[q]
-template <int N, bool ACC>
-__device__ __forceinline__ void mtv(const double (&M)[N][N], const double *in, double *out) {
+template <int N, bool ISD, bool ACC>
+__device__ __forceinline__ void eo_mtv(cptr M, const double *in, double *out) {
+  constexpr int H2 = N / 2;
+  double s[H2 > 0 ? H2 : 1], d[H2 > 0 ? H2 : 1];
+#pragma unroll
+  for (int q = 0; q < H2; ++q) {
+    s[q] = in[q] + in[N - 1 - q];
+    d[q] = in[q] - in[N - 1 - q];
+  }
 #pragma unroll
   for (int j = 0; j < N; ++j) {
-    double s = ACC ? out[j] : 0.0;
+    const bool useS = ISD ? ((j & 1) != 0) : ((j & 1) == 0);
+    double acc = ACC ? out[j] : 0.0;
 #pragma unroll
-    for (int q = 0; q < N; ++q) s = fma(M[q][j], in[q], s);
-    out[j] = s;
+    for (int q = 0; q < H2; ++q) acc = fma(M[q * N + j], useS ? s[q] : d[q], acc);
+    if ((N & 1) && useS) acc = fma(M[(N / 2) * N + j], in[N / 2], acc);
+    out[j] = acc;
   }
 }
 
+// sum_j theta_j(1) in[j] and sum_j theta_j(0) in[j]
 template <int N>
-__device__ __forceinline__ double dotv(const double (&v)[N], const double *in) {
-  double s = 0.0;
+__device__ __forceinline__ void tr_val(cptr E1, const double *in, double &v1, double &v0) {
+  double E = 0.0, O = 0.0;
 #pragma unroll
-  for (int t = 0; t < N; ++t) s = fma(v[t], in[t], s);
-  return s;
+  for (int j = 0; j < N; j += 2) E = fma(E1[j], in[j], E);
+#pragma unroll
+  for (int j = 1; j < N; j += 2) O = fma(E1[j], in[j], O);
+  v1 = E + O;
+  v0 = E - O;
 }
 
-// Per-cell geometry used by the face terms.
+// sum_j theta_j'(1) in[j] and sum_j theta_j'(0) in[j]
+template <int N>
+__device__ __forceinline__ void tr_der(cptr F1, const double *in, double &d1, double &d0) {
+  double E = 0.0, O = 0.0;
+#pragma unroll
+  for (int j = 0; j < N; j += 2) E = fma(F1[j], in[j], E);
+#pragma unroll
+  for (int j = 1; j < N; j += 2) O = fma(F1[j], in[j], O);
+  d1 = E + O;
+  d0 = O - E;
+}
+
+// out[j] += theta_j(1) a1 + theta_j(0) a0 + theta_j'(1) b1 + theta_j'(0) b0
+template <int N>
+__device__ __forceinline__ void tr_acc(cptr E1, cptr F1, double a1, double a0, double b1,
+                                       double b0, double *out) {
+  const double ap = a1 + a0, am = a1 - a0, bp = b1 + b0, bm = b1 - b0;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const bool ev = (j & 1) == 0;
+    out[j] = fma(E1[j], ev ? ap : am, out[j]);
+    out[j] = fma(F1[j], ev ? bm : bp, out[j]);
+  }
+}
+
+// out[j] += theta_j(1) a1 + theta_j(0) a0
+template <int N>
+__device__ __forceinline__ void tr_acc_v(cptr E1, double a1, double a0, double *out) {
+  const double ap = a1 + a0, am = a1 - a0;
+#pragma unroll
+  for (int j = 0; j < N; ++j) out[j] = fma(E1[j], (j & 1) == 0 ? ap : am, out[j]);
+}
+
+// ---- per-cell geometry and face constants ---------------------------------
+
 struct FaceGeo {
   double h0, h1, h2;
   double kap;
@@ -120,10 +203,11 @@ __device__ __forceinline__ int seli3(int a, int v0, int v1, int v2) {
 // axis a on side e (outer normal n_T = sgn e_a), tangential axes b < c.
 // With reference-coordinate traces of the own (o) and neighbour (n) side,
 //   {D grad u}_w . n_T = cTa ga_o + cTb gb_o + cTc gc_o + cNa ga_n + cNb gb_n + cNc gc_n
-// (weights w = delta-ratio of Sec. 2.2, delta = kappa K_aa), and the symmetry
-// term of a test function of T is Z * (cTa th'_a th_b th_c + cTb th_a th'_b th_c
-// + cTc th_a th_b th'_c) with Z = -W [[u]].  Boundary faces: w_T = 1, w_N = 0,
-// neighbour traces zero (homogeneous Dirichlet), gamma = sigma delta / h_a.
+// (weights: delta ratio of Sec. 2.2 with delta = kappa K_aa), and the
+// symmetry term of a test function of T is
+//   Z (cTa th'_a th_b th_c + cTb th_a th'_b th_c + cTc th_a th_b th'_c),  Z = -W [[u]].
+// Boundary faces: w_T = 1, w_N = 0, neighbour traces zero (homogeneous
+// Dirichlet), gamma = sigma delta / h_a.
 struct FC {
   double cTa, cTb, cTc, cNa, cNb, cNc, gamma, sgn;
 };
@@ -142,8 +226,8 @@ __device__ __forceinline__ FC face_coef(const FMesh &M, const FaceGeo &G, int ce
   const double hn = in ? ha_tab[ia + (e ? 1 : -1)] : ha;
   const double kn = in ? (M.kappa ? M.kappa[ncl] : 1.0) : 0.0;
   const double Kaa = sel3(a, M.K[0], M.K[4], M.K[8]);
-  const double Kab = a == 0 ? M.K[1] : M.K[3 * a];          // K[a][b], b = 0 unless a = 0
-  const double Kac = a == 2 ? M.K[7] : M.K[3 * a + 2];      // K[a][c], c = 2 unless a = 2
+  const double Kab = a == 0 ? M.K[1] : (a == 1 ? M.K[3] : M.K[6]);  // K[a][b]
+  const double Kac = a == 0 ? M.K[2] : (a == 1 ? M.K[5] : M.K[7]);  // K[a][c]
   const double dT = G.kap * Kaa, dN = kn * Kaa;
   FC F;
   F.sgn = e ? 1.0 : -1.0;
@@ -160,8 +244,22 @@ __device__ __forceinline__ FC face_coef(const FMesh &M, const FaceGeo &G, int ce
   return F;
 }
 
+__device__ __forceinline__ FC load_fc(const double *R, int f) {
+  FC F;
+  F.cTa = R[8 * f + 0];
+  F.cTb = R[8 * f + 1];
+  F.cTc = R[8 * f + 2];
+  F.cNa = R[8 * f + 3];
+  F.cNb = R[8 * f + 4];
+  F.cNc = R[8 * f + 5];
+  F.gamma = R[8 * f + 6];
+  F.sgn = R[8 * f + 7];
+  return F;
+}
+
 // Pointwise face flux at one face point: RV multiplies the test function,
-// Z = -W [[u]] the symmetry-term combination above.
+// Z = -W [[u]] the symmetry-term combination above.  Upwind flux of Sec. 2.2
+// with the outward normal velocity b . n_T.
 __device__ __forceinline__ void face_flux(const FC &F, double uo, double un, double avg, double ba,
                                           double W, double &RV, double &Z) {
   const double J = uo - un;
@@ -179,7 +277,6 @@ __device__ __forceinline__ double face_b(const FMesh &M, const FaceGeo &G, int N
   const double *bv = a == 0 ? M.bvol[0] : (a == 1 ? M.bvol[1] : M.bvol[2]);
   const double *bn = a == 0 ? M.bnode[0] : (a == 1 ? M.bnode[1] : M.bnode[2]);
   if (ax == a) return bn[seli3(a, G.i0, G.i1, G.i2) + e];
-  // b = 0 unless a = 0; c = 2 unless a = 2
   const int b = (a == 0) ? 1 : 0;
   if (ax == b) return bv[seli3(b, G.i0, G.i1, G.i2) * N + qb];
   const int c = (a == 2) ? 1 : 2;
@@ -201,9 +298,11 @@ __device__ __forceinline__ int cell_of_logical(int L, const FMesh &M) {
 
 template <int N>
 __global__ __launch_bounds__(FCfg<N>::THREADS) void apply_fused_kernel(
-    const double *__restrict__ x, double *__restrict__ y, FMesh M, FTab<N> T) {
+    const double *__restrict__ x, double *__restrict__ y, FMesh M) {
   using C = FCfg<N>;
+  using TO = TabOff<N>;
   constexpr int NN = C::NN, PS = C::PS, NNN = N * N * N;
+  constexpr int H2 = N / 2;
   __shared__ double lds[C::CPB * C::REGION];
 
   const int tid = threadIdx.x;
@@ -217,6 +316,8 @@ __global__ __launch_bounds__(FCfg<N>::THREADS) void apply_fused_kernel(
   const bool active = slot && L < M.ncells;
   const int cell = active ? cell_of_logical(L, M) : 0;
   double *R = lds + (slot ? cl : 0) * C::REGION;
+  double *RFC = R + C::EXCH;  // per-cell face constants
+  const cptr tab0 = (cptr)M.tab;
 
   FaceGeo G;
   G.i0 = cell % M.ncell[0];
@@ -226,6 +327,20 @@ __global__ __launch_bounds__(FCfg<N>::THREADS) void apply_fused_kernel(
   G.h1 = M.h[1][G.i1];
   G.h2 = M.h[2][G.i2];
   G.kap = M.kappa ? M.kappa[cell] : 1.0;
+
+  // face constants of the six faces f = 2a + e
+  if (slot)
+    for (int f = p; f < 6; f += C::LANES) {
+      const FC F = face_coef(M, G, cell, f >> 1, f & 1);
+      RFC[8 * f + 0] = F.cTa;
+      RFC[8 * f + 1] = F.cTb;
+      RFC[8 * f + 2] = F.cTc;
+      RFC[8 * f + 3] = F.cNa;
+      RFC[8 * f + 4] = F.cNb;
+      RFC[8 * f + 5] = F.cNc;
+      RFC[8 * f + 6] = F.gamma;
+      RFC[8 * f + 7] = F.sgn;
+    }
 
   // ------------------------------------------------------------------------
   // Round 1.  Lane (j2,j3) = (alpha,beta) owns the x pencil along axis 1.
@@ -241,32 +356,33 @@ __global__ __launch_bounds__(FCfg<N>::THREADS) void apply_fused_kernel(
   constexpr int F1_OFF = 2 * NN * PS;
   const int w1 = beta * PS + alpha;
   {
+    const cptr tb = fresh(tab0);
     double X[N];
     const double *xp = x + size_t(cell) * NNN + NN * beta + N * alpha;
 #pragma unroll
     for (int t = 0; t < N; ++t) X[t] = xp[t];
+    double Tv[N], Td[N];
+    eo_mv<N, false>(tb + TO::V, X, Tv);
+    eo_mv<N, true>(tb + TO::D, X, Td);
+    double u1, u0, d1, d0;
+    tr_val<N>(tb + TO::E1, X, u1, u0);
+    tr_der<N>(tb + TO::F1, X, d1, d0);
     if (slot) {
-#pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        R[F1_OFF + (4 * e + 0) * N * PS + w1] = dotv<N>(T.ev[e], X);
-        R[F1_OFF + (4 * e + 1) * N * PS + w1] = dotv<N>(T.ed[e], X);
-      }
+      R[F1_OFF + 0 * N * PS + w1] = u0;
+      R[F1_OFF + 1 * N * PS + w1] = d0;
+      R[F1_OFF + 4 * N * PS + w1] = u1;
+      R[F1_OFF + 5 * N * PS + w1] = d1;
 #pragma unroll
       for (int q = 0; q < N; ++q) {
-        double sv = 0.0, sd = 0.0;
-#pragma unroll
-        for (int t = 0; t < N; ++t) {
-          sv = fma(T.V[q][t], X[t], sv);
-          sd = fma(T.D[q][t], X[t], sd);
-        }
-        R[B_OFF + (q + N * beta) * PS + alpha] = sv;
-        R[B_OFF + NN * PS + (q + N * beta) * PS + alpha] = sd;
+        R[B_OFF + (q + N * beta) * PS + alpha] = Tv[q];
+        R[B_OFF + NN * PS + (q + N * beta) * PS + alpha] = Td[q];
       }
     }
   }
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
     const int a = f >> 1, e = f & 1;
+    const cptr tb = fresh(tab0);
     const int ia = a == 0 ? G.i0 : (a == 1 ? G.i1 : G.i2);
     const bool in = e ? (ia + 1 < M.ncell[a]) : (ia > 0);
     const int cst = (a == 0) ? 1 : (a == 1) ? M.ncell[0] : M.ncell[0] * M.ncell[1];
@@ -282,10 +398,14 @@ __global__ __launch_bounds__(FCfg<N>::THREADS) void apply_fused_kernel(
 #pragma unroll
       for (int t = 0; t < N; ++t) v[t] = 0.0;
     }
+    // neighbour trace at its reference coordinate 1 - e
+    double u1, u0, d1, d0;
+    tr_val<N>(tb + TO::E1, v, u1, u0);
+    tr_der<N>(tb + TO::F1, v, d1, d0);
     const int fid = (a == 0) ? (4 * e + 2) : (a == 1 ? 8 + 2 * e : 12 + 2 * e);
     if (slot) {
-      R[F1_OFF + fid * N * PS + w1] = dotv<N>(T.ev[1 - e], v);
-      R[F1_OFF + (fid + 1) * N * PS + w1] = dotv<N>(T.ed[1 - e], v);
+      R[F1_OFF + fid * N * PS + w1] = e ? u0 : u1;
+      R[F1_OFF + (fid + 1) * N * PS + w1] = e ? d0 : d1;
     }
   }
   __syncthreads();
@@ -293,28 +413,31 @@ __global__ __launch_bounds__(FCfg<N>::THREADS) void apply_fused_kernel(
   double vv[N], dv[N], vd[N];
   double yS[2], yA[2];  // own y-face value trace and flux part on (q1, j3)
   {
+    const cptr tb = fresh(tab0);
     double P[N], Q[N];
 #pragma unroll
     for (int t = 0; t < N; ++t) {
       P[t] = R[B_OFF + p * PS + t];
       Q[t] = R[B_OFF + NN * PS + p * PS + t];
     }
-    mv<N>(T.V, P, vv);
-    mv<N>(T.V, Q, dv);
-    mv<N>(T.D, P, vd);
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const FC F = face_coef(M, G, cell, 1, e);
-      yS[e] = dotv<N>(T.ev[e], P);
-      // b = axis 0 derivative from Td, normal derivative from theta'
-      yA[e] = F.cTb * dotv<N>(T.ev[e], Q) + F.cTa * dotv<N>(T.ed[e], P);
-    }
+    eo_mv<N, false>(tb + TO::V, P, vv);
+    eo_mv<N, false>(tb + TO::V, Q, dv);
+    eo_mv<N, true>(tb + TO::D, P, vd);
+    double u1, u0, g1, g0, d1, d0;
+    tr_val<N>(tb + TO::E1, P, u1, u0);
+    tr_val<N>(tb + TO::E1, Q, g1, g0);
+    tr_der<N>(tb + TO::F1, P, d1, d0);
+    const FC F0 = load_fc(RFC, 2), F1 = load_fc(RFC, 3);
+    yS[0] = u0;
+    yS[1] = u1;
+    yA[0] = F0.cTb * g0 + F0.cTa * d0;
+    yA[1] = F1.cTb * g1 + F1.cTa * d1;
   }
   // First tangential sweep of the face traces.  Tasks:
   //   t <  2N : x face e = t/N, pencil j3 = t%N  -> Sv_o, Sv_n, A1 (own + nb flux part)
   //   t <  4N : y nb  e, pencil j3               -> Sv_n, A1_n
   //   t <  6N : z nb  e, pencil j2               -> Sv_n, A1_n
-  // with Sv = V U and A1 = cSa V Dn + cSb D U along the first tangential axis.
+  // with Sv = V U and A1 = V (cSa Dn) + D (cSb U) along the first tangential axis.
   constexpr int NT1 = 6 * N;
   constexpr int NR1 = (NT1 + C::LANES - 1) / C::LANES;
   double S1[NR1][3][N];
@@ -322,47 +445,34 @@ __global__ __launch_bounds__(FCfg<N>::THREADS) void apply_fused_kernel(
   for (int r = 0; r < NR1; ++r) {
     const int task = p + r * C::LANES;
     if (task < NT1) {
+      const cptr tb = fresh(tab0);
       const int kind = task / (2 * N), e = (task / N) & 1, pi = task % N;
-      const int a = kind;
-      const FC F = face_coef(M, G, cell, a, e);
+      const FC F = load_fc(RFC, 2 * kind + e);
       const int fid = (kind == 0) ? (4 * e + 2) : (kind == 1 ? 8 + 2 * e : 12 + 2 * e);
-      double U[N], Dn[N];
+      double U[N], Ub[N], Dc[N];
 #pragma unroll
       for (int t = 0; t < N; ++t) {
         U[t] = R[F1_OFF + fid * N * PS + pi * PS + t];
-        Dn[t] = R[F1_OFF + (fid + 1) * N * PS + pi * PS + t];
+        Ub[t] = F.cNb * U[t];
+        Dc[t] = F.cNa * R[F1_OFF + (fid + 1) * N * PS + pi * PS + t];
       }
-#pragma unroll
-      for (int q = 0; q < N; ++q) {
-        double sv = 0.0, sd = 0.0, sn = 0.0;
-#pragma unroll
-        for (int t = 0; t < N; ++t) {
-          sv = fma(T.V[q][t], U[t], sv);
-          sd = fma(T.D[q][t], U[t], sd);
-          sn = fma(T.V[q][t], Dn[t], sn);
-        }
-        S1[r][1][q] = sv;                       // Sv_n
-        S1[r][2][q] = F.cNa * sn + F.cNb * sd;  // A1_n
-      }
+      eo_mv<N, false>(tb + TO::V, U, S1[r][1]);  // Sv_n
       if (kind == 0) {
+        double Uo[N];
 #pragma unroll
         for (int t = 0; t < N; ++t) {
-          U[t] = R[F1_OFF + (4 * e) * N * PS + pi * PS + t];
-          Dn[t] = R[F1_OFF + (4 * e + 1) * N * PS + pi * PS + t];
+          Uo[t] = R[F1_OFF + (4 * e) * N * PS + pi * PS + t];
+          const double Do = R[F1_OFF + (4 * e + 1) * N * PS + pi * PS + t];
+          Ub[t] = fma(F.cTb, Uo[t], Ub[t]);
+          Dc[t] = fma(F.cTa, Do, Dc[t]);
         }
-#pragma unroll
-        for (int q = 0; q < N; ++q) {
-          double sv = 0.0, sd = 0.0, sn = 0.0;
-#pragma unroll
-          for (int t = 0; t < N; ++t) {
-            sv = fma(T.V[q][t], U[t], sv);
-            sd = fma(T.D[q][t], U[t], sd);
-            sn = fma(T.V[q][t], Dn[t], sn);
-          }
-          S1[r][0][q] = sv;                                     // Sv_o
-          S1[r][2][q] += F.cTa * sn + F.cTb * sd;               // + A1_o
-        }
+        eo_mv<N, false>(tb + TO::V, Uo, S1[r][0]);  // Sv_o
       }
+      double A[N];
+      eo_mv<N, false>(tb + TO::V, Dc, S1[r][2]);
+      eo_mv<N, true>(tb + TO::D, Ub, A);
+#pragma unroll
+      for (int q = 0; q < N; ++q) S1[r][2][q] += A[q];  // A1
     }
   }
   __syncthreads();
@@ -410,26 +520,20 @@ __global__ __launch_bounds__(FCfg<N>::THREADS) void apply_fused_kernel(
   for (int r = 0; r < NR2Z; ++r) {
     const int task = p + r * C::LANES;
     if (task < NT2Z) {
+      const cptr tb = fresh(tab0);
       const int e = task / N, pi = task % N;  // pi = q1
-      const FC F = face_coef(M, G, cell, 2, e);
-      double Sv[N], A1[N];
+      const FC F = load_fc(RFC, 4 + e);
+      double Sv[N], A1[N], dc[N];
 #pragma unroll
       for (int t = 0; t < N; ++t) {
         Sv[t] = R[Z2_OFF + (2 * e + 0) * N * PS + pi * PS + t];
         A1[t] = R[Z2_OFF + (2 * e + 1) * N * PS + pi * PS + t];
       }
+      eo_mv<N, false>(tb + TO::V, Sv, Zn[r][0]);
+      eo_mv<N, false>(tb + TO::V, A1, Zn[r][1]);
+      eo_mv<N, true>(tb + TO::D, Sv, dc);
 #pragma unroll
-      for (int q = 0; q < N; ++q) {
-        double u = 0.0, a1 = 0.0, dc = 0.0;
-#pragma unroll
-        for (int t = 0; t < N; ++t) {
-          u = fma(T.V[q][t], Sv[t], u);
-          a1 = fma(T.V[q][t], A1[t], a1);
-          dc = fma(T.D[q][t], Sv[t], dc);
-        }
-        Zn[r][0][q] = u;
-        Zn[r][1][q] = a1 + F.cNc * dc;
-      }
+      for (int q = 0; q < N; ++q) Zn[r][1][q] = fma(F.cNc, dc[q], Zn[r][1][q]);
     }
   }
   __syncthreads();
@@ -446,23 +550,25 @@ __global__ __launch_bounds__(FCfg<N>::THREADS) void apply_fused_kernel(
       }
     }
   }
-  // volume pointwise flux (eq. (gauss_points)) streamed over q3 straight into
-  // the C'-stage accumulators (eq. (evalblf))
+  // volume pointwise flux (eq. (gauss_points)) streamed over the point pairs
+  // (q3, N-1-q3) straight into the C'-stage accumulators (eq. (evalblf))
   double Wvv[N], Wdv[N], Wvd[N];
 #pragma unroll
   for (int j = 0; j < N; ++j) Wvv[j] = Wdv[j] = Wvd[j] = 0.0;
   {
+    const cptr tb = fresh(tab0);
+    const cptr V = tb + TO::V, D = tb + TO::D, Wt = tb + TO::W;
     const double vol = G.h0 * G.h1 * G.h2;
     const double wab = M.w[alpha] * M.w[beta] * vol;
     const double ih0 = 1.0 / G.h0, ih1 = 1.0 / G.h1, ih2 = 1.0 / G.h2;
     const double ihv[3] = {ih0, ih1, ih2};
-    // Kh[r][s] = kappa K_rs / (h_r h_s): D in reference derivatives
+    // Kh[r][s] = kappa K_rs / (h_r h_s): D acting on reference derivatives
     double Kh[9];
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
       for (int s2 = 0; s2 < 3; ++s2) Kh[3 * r + s2] = G.kap * M.K[3 * r + s2] * ihv[r] * ihv[s2];
-    // b_r / h_r along the pencil: per-lane constant unless b_r varies along axis 3
+    // b_r / h_r: per-lane constant unless b_r varies along axis 3
     double bh[3];
     const double *bzt[3];
     bool bz[3];
@@ -475,30 +581,70 @@ __global__ __launch_bounds__(FCfg<N>::THREADS) void apply_fused_kernel(
       bh[r] = bz[r] ? 0.0 : M.bvol[r][ia * N + qa] * ihv[r];
       bzt[r] = M.bvol[r] + G.i2 * N;
     }
-#pragma unroll
-    for (int q3 = 0; q3 < N; ++q3) {
-      double u = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
-#pragma unroll
-      for (int t = 0; t < N; ++t) {
-        u = fma(T.V[q3][t], Pc[t], u);
-        g0 = fma(T.V[q3][t], Qc[t], g0);
-        g1 = fma(T.V[q3][t], Sc[t], g1);
-        g2 = fma(T.D[q3][t], Pc[t], g2);
-      }
-      const double W = wab * T.w[q3];
+    auto flux = [&](double u, double g0, double g1, double g2, int q3, double W, double &x0,
+                    double &x1, double &x2, double &x3) {
       const double b0 = bz[0] ? bzt[0][q3] * ih0 : bh[0];
       const double b1 = bz[1] ? bzt[1][q3] * ih1 : bh[1];
       const double b2 = bz[2] ? bzt[2][q3] * ih2 : bh[2];
-      const double x0 = W * M.c * u;
-      const double x1 = W * (Kh[0] * g0 + Kh[1] * g1 + Kh[2] * g2 - b0 * u);
-      const double x2 = W * (Kh[3] * g0 + Kh[4] * g1 + Kh[5] * g2 - b1 * u);
-      const double x3 = W * (Kh[6] * g0 + Kh[7] * g1 + Kh[8] * g2 - b2 * u);
+      x0 = W * M.c * u;
+      x1 = W * (Kh[0] * g0 + Kh[1] * g1 + Kh[2] * g2 - b0 * u);
+      x2 = W * (Kh[3] * g0 + Kh[4] * g1 + Kh[5] * g2 - b1 * u);
+      x3 = W * (Kh[6] * g0 + Kh[7] * g1 + Kh[8] * g2 - b2 * u);
+    };
+#pragma unroll
+    for (int h = 0; h < H2; ++h) {
+      double Eu = 0, Ou = 0, E0 = 0, O0 = 0, E1 = 0, O1 = 0, E2 = 0, O2 = 0;
+#pragma unroll
+      for (int t = 0; t < N; t += 2) {
+        Eu = fma(V[h * N + t], Pc[t], Eu);
+        E0 = fma(V[h * N + t], Qc[t], E0);
+        E1 = fma(V[h * N + t], Sc[t], E1);
+        E2 = fma(D[h * N + t], Pc[t], E2);
+      }
+#pragma unroll
+      for (int t = 1; t < N; t += 2) {
+        Ou = fma(V[h * N + t], Pc[t], Ou);
+        O0 = fma(V[h * N + t], Qc[t], O0);
+        O1 = fma(V[h * N + t], Sc[t], O1);
+        O2 = fma(D[h * N + t], Pc[t], O2);
+      }
+      const double W = wab * Wt[h];
+      double a0, a1, a2, a3, m0, m1, m2, m3;
+      flux(Eu + Ou, E0 + O0, E1 + O1, E2 + O2, h, W, a0, a1, a2, a3);
+      flux(Eu - Ou, E0 - O0, E1 - O1, O2 - E2, N - 1 - h, W, m0, m1, m2, m3);
+      const double s0 = a0 + m0, d0 = a0 - m0, s1 = a1 + m1, d1 = a1 - m1;
+      const double s2 = a2 + m2, d2 = a2 - m2, s3 = a3 + m3, d3 = a3 - m3;
 #pragma unroll
       for (int j = 0; j < N; ++j) {
-        Wvv[j] = fma(T.V[q3][j], x0, Wvv[j]);
-        Wvv[j] = fma(T.D[q3][j], x3, Wvv[j]);
-        Wdv[j] = fma(T.V[q3][j], x1, Wdv[j]);
-        Wvd[j] = fma(T.V[q3][j], x2, Wvd[j]);
+        const bool ev = (j & 1) == 0;
+        Wvv[j] = fma(V[h * N + j], ev ? s0 : d0, Wvv[j]);
+        Wvv[j] = fma(D[h * N + j], ev ? d3 : s3, Wvv[j]);
+        Wdv[j] = fma(V[h * N + j], ev ? s1 : d1, Wdv[j]);
+        Wvd[j] = fma(V[h * N + j], ev ? s2 : d2, Wvd[j]);
+      }
+    }
+    if (N & 1) {
+      constexpr int m = N / 2;
+      double u = 0, g0 = 0, g1 = 0, g2 = 0;
+#pragma unroll
+      for (int t = 0; t < N; t += 2) {
+        u = fma(V[m * N + t], Pc[t], u);
+        g0 = fma(V[m * N + t], Qc[t], g0);
+        g1 = fma(V[m * N + t], Sc[t], g1);
+      }
+#pragma unroll
+      for (int t = 1; t < N; t += 2) g2 = fma(D[m * N + t], Pc[t], g2);
+      double x0, x1, x2, x3;
+      flux(u, g0, g1, g2, m, wab * Wt[m], x0, x1, x2, x3);
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        if ((j & 1) == 0) {
+          Wvv[j] = fma(V[m * N + j], x0, Wvv[j]);
+          Wdv[j] = fma(V[m * N + j], x1, Wdv[j]);
+          Wvd[j] = fma(V[m * N + j], x2, Wvd[j]);
+        } else {
+          Wvv[j] = fma(D[m * N + j], x3, Wvv[j]);
+        }
       }
     }
   }
@@ -506,25 +652,30 @@ __global__ __launch_bounds__(FCfg<N>::THREADS) void apply_fused_kernel(
   // z faces (a = 2, b = 0, c = 1) at the point (q1, q2): own traces from the
   // C-stage input pencils; integration merged into the C'-stage accumulators
   {
+    const cptr tb = fresh(tab0);
     const double wab = M.w[alpha] * M.w[beta] * G.h0 * G.h1;
+    double u[2], gb[2], gc[2], ga[2];
+    tr_val<N>(tb + TO::E1, Pc, u[1], u[0]);
+    tr_val<N>(tb + TO::E1, Qc, gb[1], gb[0]);
+    tr_val<N>(tb + TO::E1, Sc, gc[1], gc[0]);
+    tr_der<N>(tb + TO::F1, Pc, ga[1], ga[0]);
+    double RV[2], Za[2], Zb[2], Zc[2];
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-      const FC F = face_coef(M, G, cell, 2, e);
-      const double uo = dotv<N>(T.ev[e], Pc);
-      const double avg = F.cTb * dotv<N>(T.ev[e], Qc) + F.cTc * dotv<N>(T.ev[e], Sc) +
-                         F.cTa * dotv<N>(T.ed[e], Pc) + R[ZN_OFF + (2 * e + 1) * NN + p];
+      const FC F = load_fc(RFC, 4 + e);
+      const double avg = F.cTb * gb[e] + F.cTc * gc[e] + F.cTa * ga[e] +
+                         R[ZN_OFF + (2 * e + 1) * NN + p];
       const double un = R[ZN_OFF + (2 * e + 0) * NN + p];
       const double ba = face_b(M, G, N, 2, e, alpha, beta);
-      double RV, Z;
-      face_flux(F, uo, un, avg, ba, wab, RV, Z);
-#pragma unroll
-      for (int j = 0; j < N; ++j) {
-        Wvv[j] = fma(T.ev[e][j], RV, Wvv[j]);
-        Wvv[j] = fma(T.ed[e][j], F.cTa * Z, Wvv[j]);
-        Wdv[j] = fma(T.ev[e][j], F.cTb * Z, Wdv[j]);
-        Wvd[j] = fma(T.ev[e][j], F.cTc * Z, Wvd[j]);
-      }
+      double Z;
+      face_flux(F, u[e], un, avg, ba, wab, RV[e], Z);
+      Za[e] = F.cTa * Z;
+      Zb[e] = F.cTb * Z;
+      Zc[e] = F.cTc * Z;
     }
+    tr_acc<N>(tb + TO::E1, tb + TO::F1, RV[1], RV[0], Za[1], Za[0], Wvv);
+    tr_acc_v<N>(tb + TO::E1, Zb[1], Zb[0], Wdv);
+    tr_acc_v<N>(tb + TO::E1, Zc[1], Zc[0], Wvd);
   }
   __syncthreads();
 
@@ -572,9 +723,11 @@ __global__ __launch_bounds__(FCfg<N>::THREADS) void apply_fused_kernel(
   for (int r = 0; r < NR2; ++r) {
     const int task = p + r * C::LANES;
     if (task < NT2) {
+      const cptr tb = fresh(tab0);
+      const cptr V = tb + TO::V, D = tb + TO::D, Wt = tb + TO::W;
       const int fp = task / N, pi = task % N;  // pi = first tangential q (q2 for x, q1 for y)
       const int a = fp >> 1, e = fp & 1;
-      const FC F = face_coef(M, G, cell, a, e);
+      const FC F = load_fc(RFC, fp);
       double So[N], Sn[N], A1[N], A2[N];
       if (a == 0) {
 #pragma unroll
@@ -600,28 +753,63 @@ __global__ __launch_bounds__(FCfg<N>::THREADS) void apply_fused_kernel(
 #pragma unroll
       for (int j = 0; j < N; ++j) VR[j] = DZ[j] = VZ[j] = 0.0;
 #pragma unroll
-      for (int q = 0; q < N; ++q) {
-        double uo = 0, un = 0, avg = 0;
+      for (int h = 0; h < H2; ++h) {
+        double Eo = 0, Oo = 0, En = 0, On = 0, Ea = 0, Oa = 0, Ed = 0, Od = 0;
 #pragma unroll
-        for (int t = 0; t < N; ++t) {
-          uo = fma(T.V[q][t], So[t], uo);
-          un = fma(T.V[q][t], Sn[t], un);
-          avg = fma(T.V[q][t], A1[t], avg);
-          avg = fma(T.D[q][t], A2[t], avg);
+        for (int t = 0; t < N; t += 2) {
+          Eo = fma(V[h * N + t], So[t], Eo);
+          En = fma(V[h * N + t], Sn[t], En);
+          Ea = fma(V[h * N + t], A1[t], Ea);
+          Ed = fma(D[h * N + t], A2[t], Ed);
         }
-        const double ba = face_b(M, G, N, a, e, pi, q);
-        double RV, Z;
-        face_flux(F, uo, un, avg, ba, wp * T.w[q], RV, Z);
+#pragma unroll
+        for (int t = 1; t < N; t += 2) {
+          Oo = fma(V[h * N + t], So[t], Oo);
+          On = fma(V[h * N + t], Sn[t], On);
+          Oa = fma(V[h * N + t], A1[t], Oa);
+          Od = fma(D[h * N + t], A2[t], Od);
+        }
+        const double W = wp * Wt[h];
+        double RVa, Za, RVm, Zm;
+        face_flux(F, Eo + Oo, En + On, Ea + Oa + Ed + Od, face_b(M, G, N, a, e, pi, h), W, RVa,
+                  Za);
+        face_flux(F, Eo - Oo, En - On, Ea - Oa + Od - Ed,
+                  face_b(M, G, N, a, e, pi, N - 1 - h), W, RVm, Zm);
+        const double sr = RVa + RVm, dr = RVa - RVm, sz = Za + Zm, dz = Za - Zm;
 #pragma unroll
         for (int j = 0; j < N; ++j) {
-          VR[j] = fma(T.V[q][j], RV, VR[j]);
-          DZ[j] = fma(T.D[q][j], Z, DZ[j]);
-          VZ[j] = fma(T.V[q][j], Z, VZ[j]);
+          const bool ev = (j & 1) == 0;
+          VR[j] = fma(V[h * N + j], ev ? sr : dr, VR[j]);
+          DZ[j] = fma(D[h * N + j], ev ? dz : sz, DZ[j]);
+          VZ[j] = fma(V[h * N + j], ev ? sz : dz, VZ[j]);
+        }
+      }
+      if (N & 1) {
+        constexpr int m = N / 2;
+        double uo = 0, un = 0, av = 0;
+#pragma unroll
+        for (int t = 0; t < N; t += 2) {
+          uo = fma(V[m * N + t], So[t], uo);
+          un = fma(V[m * N + t], Sn[t], un);
+          av = fma(V[m * N + t], A1[t], av);
+        }
+#pragma unroll
+        for (int t = 1; t < N; t += 2) av = fma(D[m * N + t], A2[t], av);
+        double RVm, Zm;
+        face_flux(F, uo, un, av, face_b(M, G, N, a, e, pi, m), wp * Wt[m], RVm, Zm);
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          if ((j & 1) == 0) {
+            VR[j] = fma(V[m * N + j], RVm, VR[j]);
+            VZ[j] = fma(V[m * N + j], Zm, VZ[j]);
+          } else {
+            DZ[j] = fma(D[m * N + j], Zm, DZ[j]);
+          }
         }
       }
 #pragma unroll
       for (int j = 0; j < N; ++j) {
-        Qf[r][0][j] = VR[j] + F.cTc * DZ[j];
+        Qf[r][0][j] = fma(F.cTc, DZ[j], VR[j]);
         Qf[r][1][j] = VZ[j];
       }
     }
@@ -667,6 +855,7 @@ __global__ __launch_bounds__(FCfg<N>::THREADS) void apply_fused_kernel(
   // volume step B': lane (q1, j3) = (alpha, beta), plus the y-face merge
   double Vv[N], Vd[N];
   {
+    const cptr tb = fresh(tab0);
     double P[N], Q[N], S[N];
 #pragma unroll
     for (int t = 0; t < N; ++t) {
@@ -674,21 +863,14 @@ __global__ __launch_bounds__(FCfg<N>::THREADS) void apply_fused_kernel(
       Q[t] = R[BP_OFF + NN * PS + p * PS + t];
       S[t] = R[BP_OFF + 2 * NN * PS + p * PS + t];
     }
-    mtv<N, false>(T.V, P, Vv);
-    mtv<N, true>(T.D, S, Vv);
-    mtv<N, false>(T.V, Q, Vd);
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const FC F = face_coef(M, G, cell, 1, e);
-      const double q1v = R[Y3_OFF + (2 * e + 0) * NN + p];
-      const double vz = R[Y3_OFF + (2 * e + 1) * NN + p];
-#pragma unroll
-      for (int j = 0; j < N; ++j) {
-        Vv[j] = fma(T.ev[e][j], q1v, Vv[j]);
-        Vv[j] = fma(T.ed[e][j], F.cTa * vz, Vv[j]);
-        Vd[j] = fma(T.ev[e][j], F.cTb * vz, Vd[j]);
-      }
-    }
+    eo_mtv<N, false, false>(tb + TO::V, P, Vv);
+    eo_mtv<N, true, true>(tb + TO::D, S, Vv);
+    eo_mtv<N, false, false>(tb + TO::V, Q, Vd);
+    const FC F0 = load_fc(RFC, 2), F1 = load_fc(RFC, 3);
+    const double q0 = R[Y3_OFF + 0 * NN + p], z0 = R[Y3_OFF + 1 * NN + p];
+    const double q1 = R[Y3_OFF + 2 * NN + p], z1 = R[Y3_OFF + 3 * NN + p];
+    tr_acc<N>(tb + TO::E1, tb + TO::F1, q1, q0, F1.cTa * z1, F0.cTa * z0, Vv);
+    tr_acc_v<N>(tb + TO::E1, F1.cTb * z1, F0.cTb * z0, Vd);
   }
   // x-face tasks: transposed sweep along q2 -> (R_v, R_d) on (j2, j3)
   constexpr int NT3 = 2 * N;
@@ -698,25 +880,22 @@ __global__ __launch_bounds__(FCfg<N>::THREADS) void apply_fused_kernel(
   for (int r = 0; r < NR3; ++r) {
     const int task = p + r * C::LANES;
     if (task < NT3) {
+      const cptr tb = fresh(tab0);
       const int e = task / N, pi = task % N;  // pi = j3
-      const FC F = face_coef(M, G, cell, 0, e);
-      double Q1[N], VZ[N];
+      const FC F = load_fc(RFC, e);
+      double Q1[N], VZ[N], rb[N];
 #pragma unroll
       for (int t = 0; t < N; ++t) {
         Q1[t] = R[X3_OFF + (2 * e + 0) * N * PS + pi * PS + t];
         VZ[t] = R[X3_OFF + (2 * e + 1) * N * PS + pi * PS + t];
       }
+      eo_mtv<N, false, false>(tb + TO::V, Q1, Rx[r][0]);
+      eo_mtv<N, true, false>(tb + TO::D, VZ, rb);
+      eo_mtv<N, false, false>(tb + TO::V, VZ, Rx[r][1]);
 #pragma unroll
       for (int j = 0; j < N; ++j) {
-        double rv = 0.0, rb = 0.0, rd = 0.0;
-#pragma unroll
-        for (int q = 0; q < N; ++q) {
-          rv = fma(T.V[q][j], Q1[q], rv);
-          rb = fma(T.D[q][j], VZ[q], rb);
-          rd = fma(T.V[q][j], VZ[q], rd);
-        }
-        Rx[r][0][j] = rv + F.cTb * rb;
-        Rx[r][1][j] = F.cTa * rd;
+        Rx[r][0][j] = fma(F.cTb, rb[j], Rx[r][0][j]);
+        Rx[r][1][j] *= F.cTa;
       }
     }
   }
@@ -748,24 +927,18 @@ __global__ __launch_bounds__(FCfg<N>::THREADS) void apply_fused_kernel(
   __syncthreads();
   // volume step A': lane (j2, j3) = (alpha, beta), plus the x-face merge
   if (active) {
+    const cptr tb = fresh(tab0);
     double P[N], Q[N], Yv[N];
 #pragma unroll
     for (int t = 0; t < N; ++t) {
       P[t] = R[AP_OFF + p * PS + t];
       Q[t] = R[AP_OFF + NN * PS + p * PS + t];
     }
-    mtv<N, false>(T.V, P, Yv);
-    mtv<N, true>(T.D, Q, Yv);
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const double rv = R[X4_OFF + (2 * e + 0) * NN + p];
-      const double rd = R[X4_OFF + (2 * e + 1) * NN + p];
-#pragma unroll
-      for (int j = 0; j < N; ++j) {
-        Yv[j] = fma(T.ev[e][j], rv, Yv[j]);
-        Yv[j] = fma(T.ed[e][j], rd, Yv[j]);
-      }
-    }
+    eo_mtv<N, false, false>(tb + TO::V, P, Yv);
+    eo_mtv<N, true, true>(tb + TO::D, Q, Yv);
+    const double rv0 = R[X4_OFF + 0 * NN + p], rd0 = R[X4_OFF + 1 * NN + p];
+    const double rv1 = R[X4_OFF + 2 * NN + p], rd1 = R[X4_OFF + 3 * NN + p];
+    tr_acc<N>(tb + TO::E1, tb + TO::F1, rv1, rv0, rd1, rd0, Yv);
     double *yp = y + size_t(cell) * NNN + NN * beta + N * alpha;
 #pragma unroll
     for (int t = 0; t < N; ++t) yp[t] = Yv[t];
@@ -775,18 +948,6 @@ __global__ __launch_bounds__(FCfg<N>::THREADS) void apply_fused_kernel(
 template <int N>
 static hipError_t launch_fused_n(const dg_handle *h, const double *x, double *y, hipStream_t s) {
   using C = FCfg<N>;
-  FTab<N> T;
-  for (int q = 0; q < N; ++q) {
-    for (int j = 0; j < N; ++j) {
-      T.V[q][j] = h->tab.V[q][j];
-      T.D[q][j] = h->tab.D[q][j];
-    }
-    T.ev[0][q] = h->tab.e0v[q];
-    T.ev[1][q] = h->tab.e1v[q];
-    T.ed[0][q] = h->tab.e0d[q];
-    T.ed[1][q] = h->tab.e1d[q];
-    T.w[q] = h->tab.w[q];
-  }
   FMesh M;
   for (int a = 0; a < 3; ++a) {
     M.ncell[a] = h->mesh.ncell[a];
@@ -797,6 +958,7 @@ static hipError_t launch_fused_n(const dg_handle *h, const double *x, double *y,
   }
   M.kappa = h->mesh.kappa;
   M.w = h->mesh.w;
+  M.tab = h->mesh.eo_tab;
   for (int i = 0; i < 9; ++i) M.K[i] = h->mesh.K[i];
   M.c = h->mesh.c;
   M.sigma = h->mesh.sigma;
@@ -807,8 +969,21 @@ static hipError_t launch_fused_n(const dg_handle *h, const double *x, double *y,
   const int nblocks = int((h->ncells + C::CPB - 1) / C::CPB);
   M.groups = (nblocks + 7) / 8;
   hipLaunchKernelGGL(apply_fused_kernel<N>, dim3(unsigned(8 * M.groups)), dim3(C::THREADS), 0, s,
-                     x, y, M, T);
+                     x, y, M);
   return hipGetLastError();
+}
+
+// Host side of the even-odd table layout of TabOff<N>.
+void build_eo_table(const Tables &t, std::vector<double> &out) {
+  const int N = t.n, H = (N + 1) / 2;
+  out.clear();
+  for (int q = 0; q < H; ++q)
+    for (int j = 0; j < N; ++j) out.push_back(t.V[q][j]);
+  for (int q = 0; q < H; ++q)
+    for (int j = 0; j < N; ++j) out.push_back(t.D[q][j]);
+  for (int j = 0; j < N; ++j) out.push_back(t.e1v[j]);
+  for (int j = 0; j < N; ++j) out.push_back(t.e1d[j]);
+  for (int q = 0; q < H; ++q) out.push_back(t.w[q]);
 }
 
 hipError_t launch_apply_fused_f64(const dg_handle *h, const double *x, double *y, hipStream_t s) {
