@@ -12,9 +12,9 @@
 // of the Legendre basis (theta_j(1-t) = (-1)^j theta_j(t)): only rows
 // q < ceil(N/2) of V = theta(xi) and D = theta'(xi) are stored and every
 // contraction splits into even and odd columns, halving its multiply-adds.
-// The tables live in the constant address space and are read with scalar
-// loads; each stage re-derives its table pointer through an empty asm so that
-// the compiler keeps table values short-lived instead of spilling them.
+// The tables are compile-time constants (gl_tables.inc, correctly rounded),
+// so the compiler materialises each coefficient into scalar registers where
+// it is used instead of holding a whole table live.
 //
 // Volume (Algorithm 1, steps 1-3), evaluation tree with a shared first sweep:
 //   A  (axis 1, lanes (j2,j3)):  x -> V1 x, D1 x
@@ -42,19 +42,26 @@
 #include <vector>
 
 #include "dg_internal.h"
+#include "gl_tables.inc"
 
 namespace dgmf {
 
-typedef const __attribute__((address_space(4))) double *cptr;
+// View of the compile-time table GLTab<N> at an offset; indices are resolved
+// at compile time after unrolling.
+template <int N>
+struct CT {
+  int off;
+  __device__ constexpr double operator[](int i) const { return GLTab<N>::v[off + i]; }
+  __device__ constexpr CT operator+(int o) const { return CT{off + o}; }
+};
+#define cptr CT<N>
 
-// Re-derive a table pointer: an empty asm makes loads through the result
-// distinct from earlier ones, so table values are reloaded per stage.
-__device__ __forceinline__ cptr fresh(cptr p) {
-  asm volatile("" : "+s"(p));
+template <int N>
+__device__ __forceinline__ CT<N> fresh(CT<N> p) {
   return p;
 }
 
-// Device table layout (doubles), H = ceil(N/2):
+// Table layout (doubles), H = ceil(N/2):
 //   V rows 0..H-1 [H*N] | D rows 0..H-1 [H*N] | theta(1) [N] | theta'(1) [N] | w 0..H-1 [H]
 template <int N>
 struct TabOff {
@@ -66,7 +73,6 @@ struct TabOff {
 struct FMesh {
   int ncell[3];
   const double *h[3], *bvol[3], *bnode[3], *kappa, *w;
-  const double *tab;
   double K[9], c, sigma;
   int b_axis[3];
   int tz;          // depth (cells along axis 3) of the tiles of the cell order
@@ -81,13 +87,14 @@ struct FCfg {
   static constexpr int LANES = NN;
   static constexpr int CPB = (NN <= 64) ? (64 / NN) : 1;
   static constexpr int THREADS = ((CPB * LANES + 63) / 64) * 64;
+  static constexpr int WAVES_PER_SIMD = (N <= 8) ? 2 : 1;  // register budget target
   static constexpr int FCW = 8;  // doubles per face-constant record
   // per-cell LDS (doubles) of each exchange round
   static constexpr int R1 = 2 * NN * PS + 16 * N * PS;
   static constexpr int R2 = 3 * NN * PS + 4 * N * PS;
   static constexpr int R2Z = 4 * NN;
-  static constexpr int R3 = 14 * N * PS;
-  static constexpr int R4 = 3 * NN * PS + 4 * NN + 4 * N * PS;
+  static constexpr int R3 = 4 * NN + 14 * N * PS + 3 * NN * PS;
+  static constexpr int R4 = 4 * NN + 4 * N * PS;
   static constexpr int R5 = 2 * NN * PS + 4 * NN;
   static constexpr int mx(int a, int b) { return a > b ? a : b; }
   static constexpr int EXCH = mx(mx(mx(R1, R2), mx(R2Z, R3)), mx(R4, R5));
@@ -297,7 +304,8 @@ __device__ __forceinline__ int cell_of_logical(int L, const FMesh &M) {
 }
 
 template <int N>
-__global__ __launch_bounds__(FCfg<N>::THREADS) void apply_fused_kernel(
+__global__ __launch_bounds__(FCfg<N>::THREADS)
+__attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_kernel(
     const double *__restrict__ x, double *__restrict__ y, FMesh M) {
   using C = FCfg<N>;
   using TO = TabOff<N>;
@@ -317,7 +325,7 @@ __global__ __launch_bounds__(FCfg<N>::THREADS) void apply_fused_kernel(
   const int cell = active ? cell_of_logical(L, M) : 0;
   double *R = lds + (slot ? cl : 0) * C::REGION;
   double *RFC = R + C::EXCH;  // per-cell face constants
-  const cptr tab0 = (cptr)M.tab;
+  const CT<N> tab0{0};
 
   FaceGeo G;
   G.i0 = cell % M.ncell[0];
@@ -550,6 +558,38 @@ __global__ __launch_bounds__(FCfg<N>::THREADS) void apply_fused_kernel(
       }
     }
   }
+  // Second tangential sweep inputs of the x and y faces (pencils along j3 at
+  // fixed first tangential q), written over the consumed C-stage pencils:
+  //   x e: {Sv_o, Sv_n, A1} on (q2, j3), fields 3e + g
+  //   y e: {Sv_o, A1_o, Sv_n, A1_n} on (q1, j3), fields 6 + 4e + g
+  constexpr int XY_OFF = 4 * NN;   // after the z-neighbour point values
+  if (slot) {
+#pragma unroll
+    for (int r = 0; r < NR1; ++r) {
+      const int task = p + r * C::LANES;
+      if (task < 4 * N) {
+        const int kind = task / (2 * N), e = (task / N) & 1, pi = task % N;  // pi = j3
+        if (kind == 0) {
+#pragma unroll
+          for (int g = 0; g < 3; ++g)
+#pragma unroll
+            for (int q = 0; q < N; ++q) R[XY_OFF + (3 * e + g) * N * PS + q * PS + pi] = S1[r][g][q];
+        } else {
+#pragma unroll
+          for (int g = 0; g < 2; ++g)
+#pragma unroll
+            for (int q = 0; q < N; ++q)
+              R[XY_OFF + (6 + 4 * e + 2 + g) * N * PS + q * PS + pi] = S1[r][1 + g][q];
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      R[XY_OFF + (6 + 4 * e + 0) * N * PS + alpha * PS + beta] = yS[e];
+      R[XY_OFF + (6 + 4 * e + 1) * N * PS + alpha * PS + beta] = yA[e];
+    }
+  }
+  __syncthreads();
   // volume pointwise flux (eq. (gauss_points)) streamed over the point pairs
   // (q3, N-1-q3) straight into the C'-stage accumulators (eq. (evalblf))
   double Wvv[N], Wdv[N], Wvd[N];
@@ -648,7 +688,7 @@ __global__ __launch_bounds__(FCfg<N>::THREADS) void apply_fused_kernel(
       }
     }
   }
-  __syncthreads();
+  __builtin_amdgcn_sched_barrier(0);
   // z faces (a = 2, b = 0, c = 1) at the point (q1, q2): own traces from the
   // C-stage input pencils; integration merged into the C'-stage accumulators
   {
@@ -677,43 +717,18 @@ __global__ __launch_bounds__(FCfg<N>::THREADS) void apply_fused_kernel(
     tr_acc_v<N>(tb + TO::E1, Zb[1], Zb[0], Wdv);
     tr_acc_v<N>(tb + TO::E1, Zc[1], Zc[0], Wvd);
   }
-  __syncthreads();
 
-  // ------------------------------------------------------------------------
-  // Round 3.  x and y faces: second tangential sweep (along axis 3), pointwise
-  // face terms and the first transposed sweep.  Inputs: pencils along j3 at
-  // fixed first tangential q:
-  //   x e: {Sv_o, Sv_n, A1} on (q2, j3), fields 3e + g
-  //   y e: {Sv_o, A1_o, Sv_n, A1_n} on (q1, j3), fields 6 + 4e + g
-  // ------------------------------------------------------------------------
-  constexpr int XY_OFF = 0;
+  // C'-stage results as B'-pencils (q1 + N j3) along q2, beyond the x/y inputs
+  constexpr int BP_OFF = 4 * NN + 14 * N * PS;
   if (slot) {
 #pragma unroll
-    for (int r = 0; r < NR1; ++r) {
-      const int task = p + r * C::LANES;
-      if (task < 4 * N) {
-        const int kind = task / (2 * N), e = (task / N) & 1, pi = task % N;  // pi = j3
-        if (kind == 0) {
-#pragma unroll
-          for (int g = 0; g < 3; ++g)
-#pragma unroll
-            for (int q = 0; q < N; ++q) R[XY_OFF + (3 * e + g) * N * PS + q * PS + pi] = S1[r][g][q];
-        } else {
-#pragma unroll
-          for (int g = 0; g < 2; ++g)
-#pragma unroll
-            for (int q = 0; q < N; ++q)
-              R[XY_OFF + (6 + 4 * e + 2 + g) * N * PS + q * PS + pi] = S1[r][1 + g][q];
-        }
-      }
-    }
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      R[XY_OFF + (6 + 4 * e + 0) * N * PS + alpha * PS + beta] = yS[e];
-      R[XY_OFF + (6 + 4 * e + 1) * N * PS + alpha * PS + beta] = yA[e];
+    for (int j = 0; j < N; ++j) {
+      R[BP_OFF + (alpha + N * j) * PS + beta] = Wvv[j];
+      R[BP_OFF + NN * PS + (alpha + N * j) * PS + beta] = Wdv[j];
+      R[BP_OFF + 2 * NN * PS + (alpha + N * j) * PS + beta] = Wvd[j];
     }
   }
-  __syncthreads();
+  __builtin_amdgcn_sched_barrier(0);
   // tasks (face pair fp: 0,1 x e; 2,3 y e) x N pencils; each produces the
   // transposed-sweep results Q1 = V^T RV + cTc D^T Z and VZ = V^T Z over j3
   constexpr int NT2 = 4 * N;
@@ -820,16 +835,10 @@ __global__ __launch_bounds__(FCfg<N>::THREADS) void apply_fused_kernel(
   // Round 4.  Volume C'->B' exchange; y-face results to the volume lanes
   // (q1, j3); x-face results as pencils along q2 at fixed j3.
   // ------------------------------------------------------------------------
-  constexpr int BP_OFF = 0;                  // Wvv, Wdv, Wvd B'-pencils (q1 + N j3) along q2
-  constexpr int Y3_OFF = 3 * NN * PS;        // y (e, {Q1, VZ}) on (q1 + N j3)
+  // (the B'-pencils were written before the x/y tasks, at BP_OFF)
+  constexpr int Y3_OFF = 0;                  // y (e, {Q1, VZ}) on (q1 + N j3)
   constexpr int X3_OFF = Y3_OFF + 4 * NN;    // x (e, {Q1, VZ}) pencils along q2, index j3
   if (slot) {
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-      R[BP_OFF + (alpha + N * j) * PS + beta] = Wvv[j];
-      R[BP_OFF + NN * PS + (alpha + N * j) * PS + beta] = Wdv[j];
-      R[BP_OFF + 2 * NN * PS + (alpha + N * j) * PS + beta] = Wvd[j];
-    }
 #pragma unroll
     for (int r = 0; r < NR2; ++r) {
       const int task = p + r * C::LANES;
@@ -958,7 +967,6 @@ static hipError_t launch_fused_n(const dg_handle *h, const double *x, double *y,
   }
   M.kappa = h->mesh.kappa;
   M.w = h->mesh.w;
-  M.tab = h->mesh.eo_tab;
   for (int i = 0; i < 9; ++i) M.K[i] = h->mesh.K[i];
   M.c = h->mesh.c;
   M.sigma = h->mesh.sigma;
@@ -971,19 +979,6 @@ static hipError_t launch_fused_n(const dg_handle *h, const double *x, double *y,
   hipLaunchKernelGGL(apply_fused_kernel<N>, dim3(unsigned(8 * M.groups)), dim3(C::THREADS), 0, s,
                      x, y, M);
   return hipGetLastError();
-}
-
-// Host side of the even-odd table layout of TabOff<N>.
-void build_eo_table(const Tables &t, std::vector<double> &out) {
-  const int N = t.n, H = (N + 1) / 2;
-  out.clear();
-  for (int q = 0; q < H; ++q)
-    for (int j = 0; j < N; ++j) out.push_back(t.V[q][j]);
-  for (int q = 0; q < H; ++q)
-    for (int j = 0; j < N; ++j) out.push_back(t.D[q][j]);
-  for (int j = 0; j < N; ++j) out.push_back(t.e1v[j]);
-  for (int j = 0; j < N; ++j) out.push_back(t.e1d[j]);
-  for (int q = 0; q < H; ++q) out.push_back(t.w[q]);
 }
 
 hipError_t launch_apply_fused_f64(const dg_handle *h, const double *x, double *y, hipStream_t s) {

@@ -215,11 +215,6 @@ extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
   }
   const size_t off_w = host.size();
   host.insert(host.end(), h->tab.w, h->tab.w + m);
-  std::vector<double> eo;
-  build_eo_table(h->tab, eo);
-  while (host.size() % 8) host.push_back(0.0);  // 64-byte alignment for scalar loads
-  const size_t off_eo = host.size();
-  host.insert(host.end(), eo.begin(), eo.end());
   if (p->kappa) {
     off_kappa = host.size();
     host.insert(host.end(), p->kappa, p->kappa + ncells);
@@ -245,7 +240,6 @@ extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
   }
   M.kappa = p->kappa ? base + off_kappa : nullptr;
   M.w = base + off_w;
-  M.eo_tab = base + off_eo;
   std::memcpy(M.K, p->K, sizeof(M.K));
   M.c = p->c;
   M.sigma = p->sigma;

@@ -32,7 +32,6 @@ struct DevMesh {
   double *bnode[3];   // b_r at nodes of axis b_axis[r]: [ncell[b_axis[r]] + 1]
   double *kappa;      // per cell or nullptr (= 1)
   double *w;          // Gauss weights on [0,1] (for lane-dependent lookups)
-  double *eo_tab;     // half-row tables of the fused kernels (see build_eo_table)
   double K[9];
   double c, sigma;
   int b_axis[3];
@@ -58,7 +57,6 @@ dg_status hip_error(hipError_t e, const char *what);
 
 // Kernel launchers, dispatching on k.
 hipError_t launch_apply_ref_f64(const dg_handle *h, const double *x, double *y, hipStream_t s);
-void build_eo_table(const Tables &t, std::vector<double> &out);
 hipError_t launch_apply_fused_f64(const dg_handle *h, const double *x, double *y, hipStream_t s);
 
 }  // namespace dgmf
