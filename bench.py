@@ -90,6 +90,8 @@ def main():
     ap.add_argument("--variant", type=int, default=0, help="0 tuned kernel, 1 reference kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -126,6 +128,14 @@ def main():
     avg_kernel_ms = float(np.mean(kern_ms))
     fpd = flop_per_dof(prob.k)
     achieved = fpd * prob.ndof / (avg_kernel_ms * 1e-3) / 1e12
+
+    if args.copy_probe_mib:
+        src = torch.empty(args.copy_probe_mib * 2 ** 20 // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
 
     # spot parity on a few cells (the tests do the full check)
     parity = None

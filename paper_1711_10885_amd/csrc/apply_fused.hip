@@ -63,11 +63,13 @@ __device__ __forceinline__ CT<N> fresh(CT<N> p) {
 
 // Table layout (doubles), H = ceil(N/2):
 //   V rows 0..H-1 [H*N] | D rows 0..H-1 [H*N] | theta(1) [N] | theta'(1) [N] | w 0..H-1 [H]
+//   | g [N], g_j = sqrt(2(2j+1)): theta_j' = sum_{k<j, j-k odd} g_k g_j theta_k
 template <int N>
 struct TabOff {
   static constexpr int H = (N + 1) / 2;
   static constexpr int V = 0, D = H * N, E1 = 2 * H * N, F1 = 2 * H * N + N, W = 2 * H * N + 2 * N;
-  static constexpr int SIZE = W + H;
+  static constexpr int G = W + H;
+  static constexpr int SIZE = G + N;
 };
 
 struct FMesh {
@@ -189,6 +191,37 @@ __device__ __forceinline__ void tr_acc_v(cptr E1, double a1, double a0, double *
   const double ap = a1 + a0, am = a1 - a0;
 #pragma unroll
   for (int j = 0; j < N; ++j) out[j] = fma(E1[j], (j & 1) == 0 ? ap : am, out[j]);
+}
+
+// Modal derivative of a coefficient pencil (Legendre derivative identity):
+//   out_k = g_k sum_{j>k, j-k odd} g_j in_j      (coefficients of d/dt),
+// so that D in = V (G in) and a sum V a + D b is one contraction V (a + G b).
+template <int N>
+__device__ __forceinline__ void gmod(cptr g, const double *in, double *out) {
+  double se = 0.0, so = 0.0;  // suffix sums over even / odd j
+#pragma unroll
+  for (int k = N - 1; k >= 0; --k) {
+    out[k] = g[k] * ((k & 1) ? se : so);
+    if (k & 1)
+      so = fma(g[k], in[k], so);
+    else
+      se = fma(g[k], in[k], se);
+  }
+}
+
+// Transposed modal derivative: out_j = g_j sum_{k<j, j-k odd} g_k in_k, so
+// that D^T r = G^T (V^T r).
+template <int N>
+__device__ __forceinline__ void gmodT(cptr g, const double *in, double *out) {
+  double pe = 0.0, po = 0.0;  // prefix sums over even / odd k
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    out[j] = g[j] * ((j & 1) ? pe : po);
+    if (j & 1)
+      po = fma(g[j], in[j], po);
+    else
+      pe = fma(g[j], in[j], pe);
+  }
 }
 
 // ---- per-cell geometry and face constants ---------------------------------
@@ -445,7 +478,8 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
   //   t <  2N : x face e = t/N, pencil j3 = t%N  -> Sv_o, Sv_n, A1 (own + nb flux part)
   //   t <  4N : y nb  e, pencil j3               -> Sv_n, A1_n
   //   t <  6N : z nb  e, pencil j2               -> Sv_n, A1_n
-  // with Sv = V U and A1 = V (cSa Dn) + D (cSb U) along the first tangential axis.
+  // with Sv = V U and A1 = V (cSa Dn) + D (cSb U) = V (cSa Dn + G cSb U) along
+  // the first tangential axis (G the modal derivative).
   constexpr int NT1 = 6 * N;
   constexpr int NR1 = (NT1 + C::LANES - 1) / C::LANES;
   double S1[NR1][3][N];
@@ -476,11 +510,11 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
         }
         eo_mv<N, false>(tb + TO::V, Uo, S1[r][0]);  // Sv_o
       }
-      double A[N];
-      eo_mv<N, false>(tb + TO::V, Dc, S1[r][2]);
-      eo_mv<N, true>(tb + TO::D, Ub, A);
+      double GU[N];
+      gmod<N>(tb + TO::G, Ub, GU);
 #pragma unroll
-      for (int q = 0; q < N; ++q) S1[r][2][q] += A[q];  // A1
+      for (int t = 0; t < N; ++t) Dc[t] += GU[t];
+      eo_mv<N, false>(tb + TO::V, Dc, S1[r][2]);  // A1
     }
   }
   __syncthreads();
@@ -531,17 +565,17 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
       const cptr tb = fresh(tab0);
       const int e = task / N, pi = task % N;  // pi = q1
       const FC F = load_fc(RFC, 4 + e);
-      double Sv[N], A1[N], dc[N];
+      double Sv[N], A1[N], GS[N];
 #pragma unroll
       for (int t = 0; t < N; ++t) {
         Sv[t] = R[Z2_OFF + (2 * e + 0) * N * PS + pi * PS + t];
         A1[t] = R[Z2_OFF + (2 * e + 1) * N * PS + pi * PS + t];
       }
+      gmod<N>(tb + TO::G, Sv, GS);
+#pragma unroll
+      for (int t = 0; t < N; ++t) A1[t] = fma(F.cNc, GS[t], A1[t]);
       eo_mv<N, false>(tb + TO::V, Sv, Zn[r][0]);
       eo_mv<N, false>(tb + TO::V, A1, Zn[r][1]);
-      eo_mv<N, true>(tb + TO::D, Sv, dc);
-#pragma unroll
-      for (int q = 0; q < N; ++q) Zn[r][1][q] = fma(F.cNc, dc[q], Zn[r][1][q]);
     }
   }
   __syncthreads();
@@ -760,42 +794,44 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
           Sn[t] = R[XY_OFF + (6 + 4 * e + 2) * N * PS + pi * PS + t];
         }
       }
+      // averaged normal flux pencil: A1 + G (cTc Sv_o + cNc Sv_n)
 #pragma unroll
       for (int t = 0; t < N; ++t) A2[t] = F.cTc * So[t] + F.cNc * Sn[t];
+      {
+        double GA[N];
+        gmod<N>(tb + TO::G, A2, GA);
+#pragma unroll
+        for (int t = 0; t < N; ++t) A1[t] += GA[t];
+      }
       const double hb = a == 0 ? G.h1 : G.h0;
       const double wp = M.w[pi] * hb * G.h2;
-      double VR[N], DZ[N], VZ[N];
+      double VR[N], VZ[N];
 #pragma unroll
-      for (int j = 0; j < N; ++j) VR[j] = DZ[j] = VZ[j] = 0.0;
+      for (int j = 0; j < N; ++j) VR[j] = VZ[j] = 0.0;
 #pragma unroll
       for (int h = 0; h < H2; ++h) {
-        double Eo = 0, Oo = 0, En = 0, On = 0, Ea = 0, Oa = 0, Ed = 0, Od = 0;
+        double Eo = 0, Oo = 0, En = 0, On = 0, Ea = 0, Oa = 0;
 #pragma unroll
         for (int t = 0; t < N; t += 2) {
           Eo = fma(V[h * N + t], So[t], Eo);
           En = fma(V[h * N + t], Sn[t], En);
           Ea = fma(V[h * N + t], A1[t], Ea);
-          Ed = fma(D[h * N + t], A2[t], Ed);
         }
 #pragma unroll
         for (int t = 1; t < N; t += 2) {
           Oo = fma(V[h * N + t], So[t], Oo);
           On = fma(V[h * N + t], Sn[t], On);
           Oa = fma(V[h * N + t], A1[t], Oa);
-          Od = fma(D[h * N + t], A2[t], Od);
         }
         const double W = wp * Wt[h];
         double RVa, Za, RVm, Zm;
-        face_flux(F, Eo + Oo, En + On, Ea + Oa + Ed + Od, face_b(M, G, N, a, e, pi, h), W, RVa,
-                  Za);
-        face_flux(F, Eo - Oo, En - On, Ea - Oa + Od - Ed,
-                  face_b(M, G, N, a, e, pi, N - 1 - h), W, RVm, Zm);
+        face_flux(F, Eo + Oo, En + On, Ea + Oa, face_b(M, G, N, a, e, pi, h), W, RVa, Za);
+        face_flux(F, Eo - Oo, En - On, Ea - Oa, face_b(M, G, N, a, e, pi, N - 1 - h), W, RVm, Zm);
         const double sr = RVa + RVm, dr = RVa - RVm, sz = Za + Zm, dz = Za - Zm;
 #pragma unroll
         for (int j = 0; j < N; ++j) {
           const bool ev = (j & 1) == 0;
           VR[j] = fma(V[h * N + j], ev ? sr : dr, VR[j]);
-          DZ[j] = fma(D[h * N + j], ev ? dz : sz, DZ[j]);
           VZ[j] = fma(V[h * N + j], ev ? sz : dz, VZ[j]);
         }
       }
@@ -808,20 +844,17 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
           un = fma(V[m * N + t], Sn[t], un);
           av = fma(V[m * N + t], A1[t], av);
         }
-#pragma unroll
-        for (int t = 1; t < N; t += 2) av = fma(D[m * N + t], A2[t], av);
         double RVm, Zm;
         face_flux(F, uo, un, av, face_b(M, G, N, a, e, pi, m), wp * Wt[m], RVm, Zm);
 #pragma unroll
-        for (int j = 0; j < N; ++j) {
-          if ((j & 1) == 0) {
-            VR[j] = fma(V[m * N + j], RVm, VR[j]);
-            VZ[j] = fma(V[m * N + j], Zm, VZ[j]);
-          } else {
-            DZ[j] = fma(D[m * N + j], Zm, DZ[j]);
-          }
+        for (int j = 0; j < N; j += 2) {
+          VR[j] = fma(V[m * N + j], RVm, VR[j]);
+          VZ[j] = fma(V[m * N + j], Zm, VZ[j]);
         }
       }
+      // D^T Z = G^T (V^T Z)
+      double DZ[N];
+      gmodT<N>(tb + TO::G, VZ, DZ);
 #pragma unroll
       for (int j = 0; j < N; ++j) {
         Qf[r][0][j] = fma(F.cTc, DZ[j], VR[j]);
@@ -892,19 +925,20 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
       const cptr tb = fresh(tab0);
       const int e = task / N, pi = task % N;  // pi = j3
       const FC F = load_fc(RFC, e);
-      double Q1[N], VZ[N], rb[N];
+      double Q1[N], VZ[N], VV[N], GV[N];
 #pragma unroll
       for (int t = 0; t < N; ++t) {
         Q1[t] = R[X3_OFF + (2 * e + 0) * N * PS + pi * PS + t];
         VZ[t] = R[X3_OFF + (2 * e + 1) * N * PS + pi * PS + t];
       }
+      // R_v = V^T Q1 + cTb D^T VZ = V^T Q1 + cTb G^T (V^T VZ),  R_d = cTa V^T VZ
+      eo_mtv<N, false, false>(tb + TO::V, VZ, VV);
       eo_mtv<N, false, false>(tb + TO::V, Q1, Rx[r][0]);
-      eo_mtv<N, true, false>(tb + TO::D, VZ, rb);
-      eo_mtv<N, false, false>(tb + TO::V, VZ, Rx[r][1]);
+      gmodT<N>(tb + TO::G, VV, GV);
 #pragma unroll
       for (int j = 0; j < N; ++j) {
-        Rx[r][0][j] = fma(F.cTb, rb[j], Rx[r][0][j]);
-        Rx[r][1][j] *= F.cTa;
+        Rx[r][0][j] = fma(F.cTb, GV[j], Rx[r][0][j]);
+        Rx[r][1][j] = F.cTa * VV[j];
       }
     }
   }

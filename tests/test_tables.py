@@ -46,7 +46,13 @@ def test_entries_match_library_and_closed_forms():
         Dr = v[H * n:2 * H * n].reshape(H, n)
         e1 = v[2 * H * n:2 * H * n + n]
         f1 = v[2 * H * n + n:2 * H * n + 2 * n]
-        wh = v[2 * H * n + 2 * n:]
+        wh = v[2 * H * n + 2 * n:2 * H * n + 2 * n + H]
+        g = v[2 * H * n + 2 * n + H:]
+        assert g.size == n
+        # modal derivative: D = V G with G_kj = g_k g_j for k < j, j - k odd
+        G = np.array([[g[k] * g[j] if (k < j and (j - k) % 2) else 0.0 for j in range(n)]
+                      for k in range(n)])
+        assert np.allclose(Vr @ G, Dr, rtol=0, atol=1e-12 * max(1, n * n))
         assert np.allclose(wh, w[:H], rtol=0, atol=1e-15)  # numpy: a few ulps
         for j in range(n):
             c = np.zeros(j + 1)
