@@ -82,6 +82,19 @@ struct FMesh {
   int groups;      // workgroups per XCD slot (grid = 8 * groups)
 };
 
+// Pencil storage for the exchanges that dominate LDS size.  For N = 2, 4, 8 the
+// pencils are unpadded and element t of pencil p is rotated by (p N)/16
+// places, which keeps 16 consecutive lanes reading element t of 16
+// consecutive pencils on distinct banks; other N pad pencils to N+1 doubles.
+template <int N>
+struct PL {
+  static constexpr bool SW = (N == 2 || N == 4 || N == 8);
+  static constexpr int S = SW ? N : N + 1;  // doubles per pencil
+  __device__ static __forceinline__ int at(int p, int t) {
+    return SW ? p * N + ((t + (p * N) / 16) & (N - 1)) : p * (N + 1) + t;
+  }
+};
+
 template <int N>
 struct FCfg {
   static constexpr int NN = N * N;
@@ -92,13 +105,13 @@ struct FCfg {
   static constexpr int WAVES_PER_SIMD = (N <= 8) ? 2 : 1;  // register budget target
   static constexpr int FCW = 8;  // doubles per face-constant record
   // per-cell LDS (doubles) of each exchange round
+  static constexpr int mx(int a, int b) { return a > b ? a : b; }
   static constexpr int R1 = 2 * NN * PS + 16 * N * PS;
   static constexpr int R2 = 3 * NN * PS + 4 * N * PS;
   static constexpr int R2Z = 4 * NN;
-  static constexpr int R3 = 4 * NN + 14 * N * PS + 3 * NN * PS;
+  static constexpr int R3 = 14 * N * PL<N>::S + mx(4 * NN, 3 * NN * PL<N>::S);
   static constexpr int R4 = 4 * NN + 4 * N * PS;
   static constexpr int R5 = 2 * NN * PS + 4 * NN;
-  static constexpr int mx(int a, int b) { return a > b ? a : b; }
   static constexpr int EXCH = mx(mx(mx(R1, R2), mx(R2Z, R3)), mx(R4, R5));
   static constexpr int REGION = EXCH + 6 * FCW;
 };
@@ -524,7 +537,8 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
   // ------------------------------------------------------------------------
   constexpr int C_OFF = 0;                 // vv, dv, vd C-pencils (q1 + N q2) along j3
   constexpr int Z2_OFF = 3 * NN * PS;      // z nb (e, {Sv_n, A1_n}) pencils along j2, index q1
-  constexpr int ZN_OFF = 0;                // (e, {u_n, avg_n}) on (q1 + N q2), after C reads
+  constexpr int XY_OFF = 0;                // x/y second-sweep inputs, after the C reads
+  constexpr int ZN_OFF = XY_OFF + 14 * N * PL<N>::S;  // (e, {u_n, avg_n}) on (q1 + N q2)
   if (slot) {
 #pragma unroll
     for (int q = 0; q < N; ++q) {
@@ -596,7 +610,6 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
   // fixed first tangential q), written over the consumed C-stage pencils:
   //   x e: {Sv_o, Sv_n, A1} on (q2, j3), fields 3e + g
   //   y e: {Sv_o, A1_o, Sv_n, A1_n} on (q1, j3), fields 6 + 4e + g
-  constexpr int XY_OFF = 4 * NN;   // after the z-neighbour point values
   if (slot) {
 #pragma unroll
     for (int r = 0; r < NR1; ++r) {
@@ -607,20 +620,21 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
 #pragma unroll
           for (int g = 0; g < 3; ++g)
 #pragma unroll
-            for (int q = 0; q < N; ++q) R[XY_OFF + (3 * e + g) * N * PS + q * PS + pi] = S1[r][g][q];
+            for (int q = 0; q < N; ++q)
+              R[XY_OFF + (3 * e + g) * N * PL<N>::S + PL<N>::at(q, pi)] = S1[r][g][q];
         } else {
 #pragma unroll
           for (int g = 0; g < 2; ++g)
 #pragma unroll
             for (int q = 0; q < N; ++q)
-              R[XY_OFF + (6 + 4 * e + 2 + g) * N * PS + q * PS + pi] = S1[r][1 + g][q];
+              R[XY_OFF + (6 + 4 * e + 2 + g) * N * PL<N>::S + PL<N>::at(q, pi)] = S1[r][1 + g][q];
         }
       }
     }
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-      R[XY_OFF + (6 + 4 * e + 0) * N * PS + alpha * PS + beta] = yS[e];
-      R[XY_OFF + (6 + 4 * e + 1) * N * PS + alpha * PS + beta] = yA[e];
+      R[XY_OFF + (6 + 4 * e + 0) * N * PL<N>::S + PL<N>::at(alpha, beta)] = yS[e];
+      R[XY_OFF + (6 + 4 * e + 1) * N * PL<N>::S + PL<N>::at(alpha, beta)] = yA[e];
     }
   }
   __syncthreads();
@@ -752,14 +766,18 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
     tr_acc_v<N>(tb + TO::E1, Zc[1], Zc[0], Wvd);
   }
 
-  // C'-stage results as B'-pencils (q1 + N j3) along q2, beyond the x/y inputs
-  constexpr int BP_OFF = 4 * NN + 14 * N * PS;
+  // C'-stage results as B'-pencils (q1 + N j3) along q2, beyond the x/y
+  // inputs and over the consumed z-neighbour values
+  constexpr int BP_OFF = ZN_OFF;
+  constexpr int BPS = NN * PL<N>::S;
+  __syncthreads();
   if (slot) {
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      R[BP_OFF + (alpha + N * j) * PS + beta] = Wvv[j];
-      R[BP_OFF + NN * PS + (alpha + N * j) * PS + beta] = Wdv[j];
-      R[BP_OFF + 2 * NN * PS + (alpha + N * j) * PS + beta] = Wvd[j];
+      const int a = PL<N>::at(alpha + N * j, beta);
+      R[BP_OFF + a] = Wvv[j];
+      R[BP_OFF + BPS + a] = Wdv[j];
+      R[BP_OFF + 2 * BPS + a] = Wvd[j];
     }
   }
   __builtin_amdgcn_sched_barrier(0);
@@ -781,17 +799,17 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
       if (a == 0) {
 #pragma unroll
         for (int t = 0; t < N; ++t) {
-          So[t] = R[XY_OFF + (3 * e + 0) * N * PS + pi * PS + t];
-          Sn[t] = R[XY_OFF + (3 * e + 1) * N * PS + pi * PS + t];
-          A1[t] = R[XY_OFF + (3 * e + 2) * N * PS + pi * PS + t];
+          So[t] = R[XY_OFF + (3 * e + 0) * N * PL<N>::S + PL<N>::at(pi, t)];
+          Sn[t] = R[XY_OFF + (3 * e + 1) * N * PL<N>::S + PL<N>::at(pi, t)];
+          A1[t] = R[XY_OFF + (3 * e + 2) * N * PL<N>::S + PL<N>::at(pi, t)];
         }
       } else {
 #pragma unroll
         for (int t = 0; t < N; ++t) {
-          So[t] = R[XY_OFF + (6 + 4 * e + 0) * N * PS + pi * PS + t];
-          A1[t] = R[XY_OFF + (6 + 4 * e + 1) * N * PS + pi * PS + t] +
-                  R[XY_OFF + (6 + 4 * e + 3) * N * PS + pi * PS + t];
-          Sn[t] = R[XY_OFF + (6 + 4 * e + 2) * N * PS + pi * PS + t];
+          So[t] = R[XY_OFF + (6 + 4 * e + 0) * N * PL<N>::S + PL<N>::at(pi, t)];
+          A1[t] = R[XY_OFF + (6 + 4 * e + 1) * N * PL<N>::S + PL<N>::at(pi, t)] +
+                  R[XY_OFF + (6 + 4 * e + 3) * N * PL<N>::S + PL<N>::at(pi, t)];
+          Sn[t] = R[XY_OFF + (6 + 4 * e + 2) * N * PL<N>::S + PL<N>::at(pi, t)];
         }
       }
       // averaged normal flux pencil: A1 + G (cTc Sv_o + cNc Sv_n)
@@ -901,9 +919,10 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
     double P[N], Q[N], S[N];
 #pragma unroll
     for (int t = 0; t < N; ++t) {
-      P[t] = R[BP_OFF + p * PS + t];
-      Q[t] = R[BP_OFF + NN * PS + p * PS + t];
-      S[t] = R[BP_OFF + 2 * NN * PS + p * PS + t];
+      const int a = PL<N>::at(p, t);
+      P[t] = R[BP_OFF + a];
+      Q[t] = R[BP_OFF + BPS + a];
+      S[t] = R[BP_OFF + 2 * BPS + a];
     }
     eo_mtv<N, false, false>(tb + TO::V, P, Vv);
     eo_mtv<N, true, true>(tb + TO::D, S, Vv);
