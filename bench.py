@@ -59,6 +59,21 @@ def describe(prob) -> str:
             f"{prob.ndof} DOF, FP64")
 
 
+def measured_traffic(workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, only
+    while the kernel source still matches the one the counters were taken on."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"apply_fused_{workload[4:] if workload.startswith('cdr_') else workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = dict(l.strip().split("=", 1) for l in open(path) if "=" in l and not l.startswith("#"))
+    src = os.path.join(ROOT, "paper_1711_10885_amd", "csrc", "apply_fused.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if kv.get("source_sha256_16") != sha or kv.get("workload") != workload:
+        return None
+    return int(kv["hbm_bytes_per_launch"])
+
+
 def cpu_baseline(prob, x, budget_s: float = 12.0):
     """The CPU oracle as it stands on a bounded sample of cells of the same
     workload (rows of A x for the sampled cells), on all host threads."""
@@ -148,6 +163,8 @@ def main():
     except Exception as ex:  # noqa: BLE001
         print(f"spot parity skipped: {ex}", file=sys.stderr)
 
+    traffic = measured_traffic(args.workload) if args.variant == 0 else None
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(prob, x_host, args.cpu_budget)
@@ -169,8 +186,9 @@ def main():
                    "ndof": prob.ndof, "kernel_variant": args.variant,
                    "flop_per_dof_formula": fpd},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                     "avg_kernel_ms": avg_kernel_ms},
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": traffic, "traffic_unit": "HBM bytes per launch",
+                     "algorithmic_bytes": 16 * prob.ndof, "avg_kernel_ms": avg_kernel_ms},
         "cpu_baseline": cpu,
         "parity_spot_rel": parity,
     }
