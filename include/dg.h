@@ -115,6 +115,57 @@ dg_status dg_apply(dg_handle *h, const double *x, double *y, void *hip_stream);
 #define DG_KERNEL_REFERENCE 1
 dg_status dg_set_kernel(dg_handle *h, int32_t variant);
 
+/* ---------------------------------------------------------------------------
+ * Solvers.  The paper motivates the fast operator application as the core of
+ * iterative solvers (Sec. 1) and stops there; dg_solve wraps the operator in
+ * restarted GMRES (right preconditioning, classical Gram-Schmidt applied
+ * twice, Givens rotations) and its variants below.
+ * ------------------------------------------------------------------------- */
+#define DG_GMRES64 0  /* GMRES(m): FP64 operator and FP64 Krylov basis.          */
+#define DG_GMRES_IR 1 /* GMRES-IR: FP64 residual r = f - A u and update          *
+                       * u += ||r|| d in FP64; the correction d solves           *
+                       * A d = r/||r|| by one FP32 GMRES(m) cycle (FP32 operator *
+                       * of dg_apply_f32, FP32 basis) to inner_tol.  Needs       *
+                       * DG_WITH_FP32 at setup.                                  */
+#define DG_FGMRES 2   /* flexible GMRES(m) in FP64: the basis of preconditioned  *
+                       * vectors Z is kept, so the preconditioner may change     *
+                       * between applications (the learned one does).            */
+
+#define DG_PREC_NONE 0
+#define DG_PREC_BLOCK_JACOBI 1 /* inverse cell blocks A_TT (DG_WITH_BLOCK_JACOBI) */
+#define DG_PREC_LEARNED 2      /* cell-patch MLP (DG_FGMRES only), falling back   *
+                                * to block Jacobi on a non-finite output or       *
+                                * stagnation when the handle has it               */
+
+typedef struct {
+  int32_t method;   /* DG_GMRES64 | DG_GMRES_IR | DG_FGMRES          (0)     */
+  int32_t precond;  /* DG_PREC_*                                      (0)     */
+  int32_t restart;  /* m, 1..63                                       (30)    */
+  int32_t maxit;    /* cap on Arnoldi steps (inner steps for IR)      (20000) */
+  double inner_tol; /* GMRES-IR inner relative tolerance              (1e-4)  */
+} dg_solve_opts;
+
+typedef struct {
+  int32_t iters;         /* Arnoldi steps (inner FP32 steps for GMRES-IR)     */
+  int32_t outer;         /* restart cycles (refinement steps for GMRES-IR)    */
+  int32_t applies;       /* FP64 operator applications                         */
+  int32_t applies_f32;   /* FP32 operator applications                         */
+  int32_t fallback_used; /* 1 if the learned preconditioner was replaced      */
+  double rel_resid;      /* ||f - A u||_2 / ||f||_2, FP64, at exit             */
+  double seconds;        /* host wall time of the call                         */
+} dg_solve_stats;
+
+/* Solve A u = f to ||f - A u||_2 <= tol ||f||_2 (true FP64 residual).
+ * f, u: device, ndof doubles, no overlap; u holds the initial guess on entry
+ * and the last iterate on return.  o == NULL selects the defaults shown above;
+ * st may be NULL.  The Krylov workspace ((m+1) ndof values, plus m ndof for
+ * DG_FGMRES) is allocated on first use and kept by the handle.
+ * Synchronises hip_stream.  Returns DG_EINVAL (bad options, or a tier the
+ * handle was not set up for), DG_ENOMEM, DG_EHIP, DG_ENOTCONV (maxit reached;
+ * u is the last iterate and st is filled), DG_ENAN (non-finite value). */
+dg_status dg_solve(dg_handle *h, const double *f, double *u, double tol, const dg_solve_opts *o,
+                   dg_solve_stats *st, void *hip_stream);
+
 /* Number of degrees of freedom of the handle's space (or -1 for NULL). */
 int64_t dg_ndof(const dg_handle *h);
 

@@ -17,13 +17,15 @@ LIB_PATH = os.path.join(HERE, "libdgmf.so")
 DG_OK, DG_EINVAL, DG_ENOMEM, DG_EHIP, DG_ENOTCONV, DG_ENAN = 0, -1, -2, -3, -4, -5
 DG_WITH_FP32, DG_WITH_BLOCK_JACOBI = 1, 2
 DG_KERNEL_AUTO, DG_KERNEL_REFERENCE = 0, 1
+DG_GMRES64, DG_GMRES_IR, DG_FGMRES = 0, 1, 2
+DG_PREC_NONE, DG_PREC_BLOCK_JACOBI, DG_PREC_LEARNED = 0, 1, 2
 
 _STATUS = {DG_EINVAL: "DG_EINVAL", DG_ENOMEM: "DG_ENOMEM", DG_EHIP: "DG_EHIP",
            DG_ENOTCONV: "DG_ENOTCONV", DG_ENAN: "DG_ENAN"}
 
 # every symbol include/dg.h declares
-EXPORTS = ["dg_setup", "dg_apply", "dg_set_kernel", "dg_ndof", "dg_degree", "dg_last_error",
-           "dg_destroy"]
+EXPORTS = ["dg_setup", "dg_apply", "dg_set_kernel", "dg_solve", "dg_ndof", "dg_degree",
+           "dg_last_error", "dg_destroy"]
 
 
 class DGError(RuntimeError):
@@ -48,6 +50,20 @@ class _Problem(ctypes.Structure):
     ]
 
 
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int32), ("precond", ctypes.c_int32), ("restart", ctypes.c_int32),
+                ("maxit", ctypes.c_int32), ("inner_tol", ctypes.c_double)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("outer", ctypes.c_int32), ("applies", ctypes.c_int32),
+                ("applies_f32", ctypes.c_int32), ("fallback_used", ctypes.c_int32),
+                ("rel_resid", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -68,6 +84,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dg_apply.restype = ctypes.c_int
     lib.dg_set_kernel.argtypes = [H, ctypes.c_int32]
     lib.dg_set_kernel.restype = ctypes.c_int
+    lib.dg_solve.argtypes = [H, vp, vp, ctypes.c_double, ctypes.POINTER(SolveOpts),
+                             ctypes.POINTER(SolveStats), vp]
+    lib.dg_solve.restype = ctypes.c_int
     lib.dg_ndof.argtypes = [H]
     lib.dg_ndof.restype = ctypes.c_int64
     lib.dg_degree.argtypes = [H]
@@ -169,3 +188,22 @@ class DG:
         _check(load().dg_apply(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
                                _stream_ptr(stream)))
         return y
+
+    def solve(self, f, u=None, tol: float = 1e-8, method: int = DG_GMRES64,
+              precond: int = DG_PREC_NONE, restart: int = 30, maxit: int = 20000,
+              inner_tol: float = 1e-4, stream=None, check: bool = True):
+        """Solve A u = f (float64 device tensors); u is the initial guess (zero
+        if None).  Returns (u, stats dict, status).  With check=True a status
+        other than DG_OK raises DGError."""
+        import torch
+        _check_vec(f, self.ndof, torch.float64, "f")
+        if u is None:
+            u = torch.zeros_like(f)
+        _check_vec(u, self.ndof, torch.float64, "u")
+        o = SolveOpts(int(method), int(precond), int(restart), int(maxit), float(inner_tol))
+        st = SolveStats()
+        rc = load().dg_solve(self._h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                             float(tol), ctypes.byref(o), ctypes.byref(st), _stream_ptr(stream))
+        if check:
+            _check(rc)
+        return u, st.as_dict(), rc

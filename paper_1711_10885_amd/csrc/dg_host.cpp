@@ -140,6 +140,7 @@ extern "C" void dg_destroy(dg_handle *h) {
   if (!h) return;
   int cur = 0;
   if (hipGetDevice(&cur) == hipSuccess && cur != h->device) (void)hipSetDevice(h->device);
+  release_solver(h);
   if (h->dev_block) (void)hipFree(h->dev_block);
   if (cur != h->device) (void)hipSetDevice(cur);
   delete h;
@@ -187,6 +188,9 @@ extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
   h->ndof = ncells * n * n * n;
   h->dev_block = nullptr;
   h->variant = DG_KERNEL_AUTO;
+  h->ws = nullptr;
+  h->ws_bytes = 0;
+  h->red = nullptr;
   if (hipGetDevice(&h->device) != hipSuccess) {
     delete h;
     return set_error(DG_EHIP, "dg_setup: no HIP device");
@@ -247,6 +251,13 @@ extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
   return DG_OK;
 }
 
+namespace dgmf {
+hipError_t apply_f64(const dg_handle *h, const double *x, double *y, hipStream_t s) {
+  return h->variant == DG_KERNEL_REFERENCE ? launch_apply_ref_f64(h, x, y, s)
+                                           : launch_apply_fused_f64(h, x, y, s);
+}
+}  // namespace dgmf
+
 static bool overlaps(const void *a, const void *b, size_t bytes) {
   const char *pa = static_cast<const char *>(a), *pb = static_cast<const char *>(b);
   return pa < pb + bytes && pb < pa + bytes;
@@ -262,9 +273,7 @@ extern "C" dg_status dg_apply(dg_handle *h, const double *x, double *y, void *st
     hipError_t e = hipSetDevice(h->device);
     if (e != hipSuccess) return hip_error(e, "dg_apply: hipSetDevice");
   }
-  hipError_t e = (h->variant == DG_KERNEL_REFERENCE)
-                     ? launch_apply_ref_f64(h, x, y, static_cast<hipStream_t>(stream))
-                     : launch_apply_fused_f64(h, x, y, static_cast<hipStream_t>(stream));
+  hipError_t e = apply_f64(h, x, y, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_error(e, "dg_apply: kernel launch");
   return DG_OK;
 }

@@ -48,6 +48,10 @@ struct dg_handle {
   dgmf::DevMesh mesh;
   void *dev_block;  // single allocation backing the DevMesh arrays
   int variant;      // DG_KERNEL_*
+  // solver workspace: grown on demand, freed by dg_destroy
+  void *ws;
+  size_t ws_bytes;
+  double *red;      // reduction partials + small device vectors of the Krylov kernels
 };
 
 namespace dgmf {
@@ -58,5 +62,11 @@ dg_status hip_error(hipError_t e, const char *what);
 // Kernel launchers, dispatching on k.
 hipError_t launch_apply_ref_f64(const dg_handle *h, const double *x, double *y, hipStream_t s);
 hipError_t launch_apply_fused_f64(const dg_handle *h, const double *x, double *y, hipStream_t s);
+
+// Operator application through the kernel the handle selects.
+hipError_t apply_f64(const dg_handle *h, const double *x, double *y, hipStream_t s);
+
+// Free the solver resources of a handle (called by dg_destroy).
+void release_solver(dg_handle *h);
 
 }  // namespace dgmf

@@ -1,0 +1,279 @@
+// Krylov building blocks (HBM-bound vector kernels) and the restarted GMRES
+// used by dg_solve.
+//
+// The paper stops at the operator application and motivates it as the core of
+// iterative solvers (Sec. 1); the solver here is restarted GMRES (Saad &
+// Schultz) with right preconditioning and classical Gram-Schmidt applied twice
+// (CGS2).  Every pass over the Krylov basis is one fused kernel that reads each
+// basis vector once:
+//   pass 1: h1 = V^T w
+//   pass 2: w <- w - V h1, then h2 = V^T w and ||w||^2 on the updated w
+//           (same sweep)
+//   pass 3: v_{j+1} = (w - V h2) / h_{j+1,j}, written straight into the basis;
+//           h_{j+1,j}^2 = ||w||^2 - ||h2||^2 since V is orthonormal.
+// The host reads h1, h2 and ||w||^2 once per iteration (one synchronisation).
+// Reductions are two-stage and deterministic: fixed grid, per-block partial
+// sums in a fixed order, then one block per output.
+#include <cmath>
+#include <vector>
+
+#include "krylov.h"
+
+namespace dgmf {
+
+constexpr int kRedThreads = 256;
+
+// Block-wide sums of NV per-thread values; result k in sm[R + k], R = waves*NV.
+template <int NV>
+__device__ __forceinline__ void block_sum(const double (&v)[NV], double *sm) {
+  constexpr int NW = kRedThreads / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double s = v[i];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (lane == 0) sm[wave * NV + i] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double s = 0.0;
+    for (int w = 0; w < NW; ++w) s += sm[w * NV + threadIdx.x];
+    sm[NW * NV + threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+#define GRID_STRIDE(i, n)                                                              \
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < (n); \
+       i += size_t(gridDim.x) * blockDim.x)
+
+// partial[b*nv + k] = sum over block b of V_k[i] w[i]   (V_k = V + k*ld)
+template <typename T, int NVMAX>
+__global__ __launch_bounds__(kRedThreads) void k_multidot(const T *__restrict__ V, size_t ld, int nv,
+                                                           const T *__restrict__ w, size_t n,
+                                                           double *__restrict__ partial) {
+  __shared__ double sm[(kRedThreads / 64 + 1) * NVMAX];
+  double acc[NVMAX];
+#pragma unroll
+  for (int k = 0; k < NVMAX; ++k) acc[k] = 0.0;
+  GRID_STRIDE(i, n) {
+    const double wi = double(w[i]);
+#pragma unroll
+    for (int k = 0; k < NVMAX; ++k)
+      if (k < nv) acc[k] = fma(double(V[k * ld + i]), wi, acc[k]);
+  }
+  block_sum<NVMAX>(acc, sm);
+  if (threadIdx.x < nv) partial[blockIdx.x * nv + threadIdx.x] = sm[(kRedThreads / 64) * NVMAX + threadIdx.x];
+}
+
+// wout <- scale * (w - sum_k h_k V_k); then DOT: partial sums of V_k . wout;
+// NORM: partial sum of wout . wout (stored after the nv dots).
+template <typename T, int NVMAX, bool DOT, bool NORM>
+__global__ __launch_bounds__(kRedThreads) void k_orth(const T *__restrict__ V, size_t ld, int nv,
+                                                       const double *__restrict__ h, const T *w, T *wout,
+                                                       double scale, size_t n, double *__restrict__ partial) {
+  constexpr int NA = NVMAX + 1;
+  __shared__ double sm[(kRedThreads / 64 + 1) * NA];
+  __shared__ double hs[NVMAX];
+  if (threadIdx.x < NVMAX) hs[threadIdx.x] = threadIdx.x < nv ? h[threadIdx.x] : 0.0;
+  __syncthreads();
+  double acc[NA];
+#pragma unroll
+  for (int k = 0; k < NA; ++k) acc[k] = 0.0;
+  GRID_STRIDE(i, n) {
+    double v[NVMAX];
+    double wi = double(w[i]);
+#pragma unroll
+    for (int k = 0; k < NVMAX; ++k)
+      if (k < nv) {
+        v[k] = double(V[k * ld + i]);
+        wi = fma(-hs[k], v[k], wi);
+      }
+    const T wt = T(wi * scale);
+    wout[i] = wt;
+    const double wr = double(wt);
+    if (DOT) {
+#pragma unroll
+      for (int k = 0; k < NVMAX; ++k)
+        if (k < nv) acc[k] = fma(v[k], wr, acc[k]);
+    }
+    if (NORM) acc[NVMAX] = fma(wr, wr, acc[NVMAX]);
+  }
+  if (DOT || NORM) {
+    // pack the norm right after the nv dots (static indices only: no scratch)
+    if (NORM) {
+#pragma unroll
+      for (int k = 0; k < NVMAX; ++k)
+        if (k == (DOT ? nv : 0)) acc[k] = acc[NVMAX];
+    }
+    block_sum<NA>(acc, sm);
+    const int nout = (DOT ? nv : 0) + (NORM ? 1 : 0);
+    if (threadIdx.x < nout) partial[blockIdx.x * nout + threadIdx.x] = sm[(kRedThreads / 64) * NA + threadIdx.x];
+  }
+}
+
+// out[k] = sum_b partial[b*nv + k]   (one block per k, fixed order)
+__global__ __launch_bounds__(kRedThreads) void k_reduce(const double *__restrict__ partial, int nb,
+                                                        int nv, double *__restrict__ out) {
+  __shared__ double sm[kRedThreads / 64 + 1];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kRedThreads) s += partial[b * nv + blockIdx.x];
+  const double v[1] = {s};
+  block_sum<1>(v, sm);
+  if (threadIdx.x == 0) out[blockIdx.x] = sm[kRedThreads / 64];
+}
+
+// y = alpha x   (precision conversion allowed)
+template <typename TI, typename TO>
+__global__ void k_scale(const TI *__restrict__ x, TO *__restrict__ y, double alpha, size_t n) {
+  GRID_STRIDE(i, n) y[i] = TO(alpha * double(x[i]));
+}
+
+// out (+)= sum_k c_k Z_k    (Z_k = Z + k*ld), c in device memory
+template <typename TZ, typename TO, bool ACC>
+__global__ void k_lincomb(TO *__restrict__ out, const TZ *__restrict__ Z, size_t ld, int nz,
+                          const double *__restrict__ c, double scale, size_t n) {
+  __shared__ double cs[kMaxBasis];
+  if (threadIdx.x < kMaxBasis) cs[threadIdx.x] = threadIdx.x < nz ? c[threadIdx.x] * scale : 0.0;
+  __syncthreads();
+  GRID_STRIDE(i, n) {
+    double s = ACC ? double(out[i]) : 0.0;
+    for (int k = 0; k < nz; ++k) s = fma(cs[k], double(Z[k * ld + i]), s);
+    out[i] = TO(s);
+  }
+}
+
+// r <- b - r  (r holds A u on entry), partial ||r||^2
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_residual(const T *__restrict__ b, T *__restrict__ r,
+                                                          size_t n, double *__restrict__ partial) {
+  __shared__ double sm[kRedThreads / 64 + 1];
+  double acc = 0.0;
+  GRID_STRIDE(i, n) {
+    const T v = T(double(b[i]) - double(r[i]));
+    r[i] = v;
+    acc = fma(double(v), double(v), acc);
+  }
+  const double a[1] = {acc};
+  block_sum<1>(a, sm);
+  if (threadIdx.x == 0) partial[blockIdx.x] = sm[kRedThreads / 64];
+}
+
+// y += alpha x   (precision conversion allowed)
+template <typename TX, typename TY>
+__global__ void k_axpy(const TX *__restrict__ x, TY *__restrict__ y, double alpha, size_t n) {
+  GRID_STRIDE(i, n) y[i] = TY(fma(alpha, double(x[i]), double(y[i])));
+}
+
+// partial ||x||^2
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_norm2(const T *__restrict__ x, size_t n,
+                                                       double *__restrict__ partial) {
+  __shared__ double sm[kRedThreads / 64 + 1];
+  double acc = 0.0;
+  GRID_STRIDE(i, n) {
+    const double v = double(x[i]);
+    acc = fma(v, v, acc);
+  }
+  const double a[1] = {acc};
+  block_sum<1>(a, sm);
+  if (threadIdx.x == 0) partial[blockIdx.x] = sm[kRedThreads / 64];
+}
+
+// ---------------------------------------------------------------------------
+// Launch helpers
+// ---------------------------------------------------------------------------
+template <typename T>
+hipError_t kr_multidot(const T *V, size_t ld, int nv, const T *w, size_t n, double *partial,
+                       double *out, hipStream_t s) {
+  const dim3 g(kRedBlocks), b(kRedThreads);
+  if (nv <= 8)
+    hipLaunchKernelGGL((k_multidot<T, 8>), g, b, 0, s, V, ld, nv, w, n, partial);
+  else if (nv <= 16)
+    hipLaunchKernelGGL((k_multidot<T, 16>), g, b, 0, s, V, ld, nv, w, n, partial);
+  else if (nv <= 32)
+    hipLaunchKernelGGL((k_multidot<T, 32>), g, b, 0, s, V, ld, nv, w, n, partial);
+  else
+    hipLaunchKernelGGL((k_multidot<T, 64>), g, b, 0, s, V, ld, nv, w, n, partial);
+  hipLaunchKernelGGL(k_reduce, dim3(nv), b, 0, s, partial, kRedBlocks, nv, out);
+  return hipGetLastError();
+}
+
+template <typename T, bool DOT, bool NORM>
+hipError_t kr_orth(const T *V, size_t ld, int nv, const double *h, const T *w, T *wout, double scale,
+                   size_t n, double *partial, double *out, hipStream_t s) {
+  const dim3 g(kRedBlocks), b(kRedThreads);
+  if (nv <= 8)
+    hipLaunchKernelGGL((k_orth<T, 8, DOT, NORM>), g, b, 0, s, V, ld, nv, h, w, wout, scale, n, partial);
+  else if (nv <= 16)
+    hipLaunchKernelGGL((k_orth<T, 16, DOT, NORM>), g, b, 0, s, V, ld, nv, h, w, wout, scale, n, partial);
+  else if (nv <= 32)
+    hipLaunchKernelGGL((k_orth<T, 32, DOT, NORM>), g, b, 0, s, V, ld, nv, h, w, wout, scale, n, partial);
+  else
+    hipLaunchKernelGGL((k_orth<T, 64, DOT, NORM>), g, b, 0, s, V, ld, nv, h, w, wout, scale, n, partial);
+  const int nout = (DOT ? nv : 0) + (NORM ? 1 : 0);
+  if (nout) hipLaunchKernelGGL(k_reduce, dim3(nout), b, 0, s, partial, kRedBlocks, nout, out);
+  return hipGetLastError();
+}
+
+template <typename TI, typename TO>
+hipError_t kr_scale(const TI *x, TO *y, double alpha, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL((k_scale<TI, TO>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, x, y, alpha, n);
+  return hipGetLastError();
+}
+
+template <typename TZ, typename TO>
+hipError_t kr_lincomb(TO *out, const TZ *Z, size_t ld, int nz, const double *c, double scale,
+                      bool acc, size_t n, hipStream_t s) {
+  if (acc)
+    hipLaunchKernelGGL((k_lincomb<TZ, TO, true>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, out, Z,
+                       ld, nz, c, scale, n);
+  else
+    hipLaunchKernelGGL((k_lincomb<TZ, TO, false>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, out,
+                       Z, ld, nz, c, scale, n);
+  return hipGetLastError();
+}
+
+template <typename TX, typename TY>
+hipError_t kr_axpy(const TX *x, TY *y, double alpha, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL((k_axpy<TX, TY>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, x, y, alpha, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t kr_residual(const T *b, T *r, size_t n, double *partial, double *out, hipStream_t s) {
+  hipLaunchKernelGGL((k_residual<T>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, b, r, n, partial);
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, s, partial, kRedBlocks, 1, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t kr_norm2(const T *x, size_t n, double *partial, double *out, hipStream_t s) {
+  hipLaunchKernelGGL((k_norm2<T>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, x, n, partial);
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, s, partial, kRedBlocks, 1, out);
+  return hipGetLastError();
+}
+
+// explicit instantiations
+template hipError_t kr_multidot<double>(const double *, size_t, int, const double *, size_t, double *, double *, hipStream_t);
+template hipError_t kr_multidot<float>(const float *, size_t, int, const float *, size_t, double *, double *, hipStream_t);
+template hipError_t kr_orth<double, true, true>(const double *, size_t, int, const double *, const double *, double *, double, size_t, double *, double *, hipStream_t);
+template hipError_t kr_orth<double, false, false>(const double *, size_t, int, const double *, const double *, double *, double, size_t, double *, double *, hipStream_t);
+template hipError_t kr_orth<float, true, true>(const float *, size_t, int, const double *, const float *, float *, double, size_t, double *, double *, hipStream_t);
+template hipError_t kr_orth<float, false, false>(const float *, size_t, int, const double *, const float *, float *, double, size_t, double *, double *, hipStream_t);
+template hipError_t kr_scale<double, double>(const double *, double *, double, size_t, hipStream_t);
+template hipError_t kr_scale<float, float>(const float *, float *, double, size_t, hipStream_t);
+template hipError_t kr_scale<double, float>(const double *, float *, double, size_t, hipStream_t);
+template hipError_t kr_scale<float, double>(const float *, double *, double, size_t, hipStream_t);
+template hipError_t kr_lincomb<double, double>(double *, const double *, size_t, int, const double *, double, bool, size_t, hipStream_t);
+template hipError_t kr_lincomb<float, float>(float *, const float *, size_t, int, const double *, double, bool, size_t, hipStream_t);
+template hipError_t kr_lincomb<float, double>(double *, const float *, size_t, int, const double *, double, bool, size_t, hipStream_t);
+template hipError_t kr_axpy<double, double>(const double *, double *, double, size_t, hipStream_t);
+template hipError_t kr_axpy<float, float>(const float *, float *, double, size_t, hipStream_t);
+template hipError_t kr_axpy<float, double>(const float *, double *, double, size_t, hipStream_t);
+template hipError_t kr_residual<double>(const double *, double *, size_t, double *, double *, hipStream_t);
+template hipError_t kr_residual<float>(const float *, float *, size_t, double *, double *, hipStream_t);
+template hipError_t kr_norm2<double>(const double *, size_t, double *, double *, hipStream_t);
+template hipError_t kr_norm2<float>(const float *, size_t, double *, double *, hipStream_t);
+
+}  // namespace dgmf

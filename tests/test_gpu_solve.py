@@ -1,0 +1,156 @@
+"""FP64 GMRES (dg_solve) on the GPU, through the C ABI.
+
+Checks against things the GPU path does not compute itself: the oracle's
+residual ||f - A_oracle u|| / ||f||, a sparse direct solve of the oracle's
+assembled matrix, the oracle's own GMRES(30) iteration count, and the
+discretisation error against a manufactured solution.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1711_10885_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _solve(prob, f, tol, u0=None, check=True, variant=0, **kw):
+    torch = _torch()
+    from paper_1711_10885_amd import binding
+    with binding.DG(prob) as dg:
+        dg.set_kernel(variant)
+        fd = torch.from_numpy(np.ascontiguousarray(f)).cuda()
+        ud = None if u0 is None else torch.from_numpy(np.ascontiguousarray(u0)).cuda()
+        u, st, rc = dg.solve(fd, ud, tol=tol, check=check, **kw)
+        u = u.cpu().numpy()
+    print(f"{prob.name}: rc {rc} {st}", flush=True)
+    return u, st, rc
+
+
+def _oracle_rel_residual(prob, u, f):
+    return np.linalg.norm(f - oracle.apply(prob, u)) / np.linalg.norm(f)
+
+
+@pytest.mark.parametrize("b", ["sine", "const", "none"])
+def test_solution_matches_sparse_direct_solve(b):
+    import scipy.sparse.linalg as spla
+    p = W.random_problem(410, ncell=(3, 3, 2), k=2, b=b)
+    f = W.random_vector(p.ndof, 411)
+    A = oracle.assemble(p).tocsc()
+    ustar = spla.spsolve(A, f)
+    u, st, rc = _solve(p, f, 1e-12)
+    assert rc == 0 and st["rel_resid"] <= 1e-12
+    res = _oracle_rel_residual(p, u, f)
+    assert res <= 5e-12, res
+    cond_bound = np.linalg.norm(u - ustar) / np.linalg.norm(ustar)
+    assert cond_bound <= 1e-8, cond_bound
+
+
+def test_iterations_and_residual_match_oracle_gmres():
+    p = W.poisson_k2_8()
+    f = oracle.rhs(p, W.manufactured_source(p.K, (0.0, 0.0, 0.0), 0.0))
+    tol = 1e-8
+    u, st, rc = _solve(p, f, tol)
+    uo, it_o, rel_o = oracle.gmres(lambda v: oracle.apply(p, v), f, tol=tol, restart=30)
+    print(f"oracle gmres: {it_o} iterations, rel {rel_o:.3e}", flush=True)
+    assert rc == 0
+    # same Krylov method (CGS2 here, MGS in the oracle): equal in exact arithmetic
+    assert abs(st["iters"] - it_o) <= max(2, 0.02 * it_o), (st["iters"], it_o)
+    assert _oracle_rel_residual(p, u, f) <= 1.05 * tol
+    # both iterates solve the system to tol: their difference is small in the A-image
+    d = np.linalg.norm(oracle.apply(p, u - uo)) / np.linalg.norm(f)
+    assert d <= 2.1 * tol, d
+
+
+def test_cdr_random_problem_every_degree_small():
+    for k in (1, 3, 5):
+        p = W.random_problem(420 + k, ncell=(3, 2, 2), k=k, b="sine")
+        f = W.random_vector(p.ndof, 430 + k)
+        u, st, rc = _solve(p, f, 1e-10)
+        assert rc == 0
+        assert _oracle_rel_residual(p, u, f) <= 1.05e-10
+
+
+@pytest.mark.parametrize("restart", [1, 5, 63])
+def test_restart_lengths(restart):
+    p = W.random_problem(440, ncell=(2, 2, 2), k=1, b="none")
+    f = W.random_vector(p.ndof, 441)
+    u, st, rc = _solve(p, f, 1e-8, restart=restart)
+    assert rc == 0 and st["outer"] >= 1
+    assert _oracle_rel_residual(p, u, f) <= 1.05e-8
+
+
+def test_reference_kernel_gives_the_same_solve():
+    p = W.random_problem(450, ncell=(3, 2, 2), k=3, b="sine")
+    f = W.random_vector(p.ndof, 451)
+    u0, s0, _ = _solve(p, f, 1e-10, variant=0)
+    u1, s1, _ = _solve(p, f, 1e-10, variant=1)
+    assert abs(s0["iters"] - s1["iters"]) <= 2
+    assert _oracle_rel_residual(p, u1, f) <= 1.05e-10
+
+
+def test_maxit_reports_not_converged_with_stats():
+    from paper_1711_10885_amd import binding
+    p = W.poisson_k2_8()
+    f = W.random_vector(p.ndof, 460)
+    u, st, rc = _solve(p, f, 1e-12, check=False, maxit=7)
+    assert rc == binding.DG_ENOTCONV
+    assert st["iters"] == 7 and 0 < st["rel_resid"] < 1
+    assert abs(_oracle_rel_residual(p, u, f) - st["rel_resid"]) <= 1e-9
+
+
+def test_zero_rhs_gives_zero_solution():
+    p = W.random_problem(470, ncell=(2, 2, 2), k=2)
+    u, st, rc = _solve(p, np.zeros(p.ndof), 1e-8, u0=W.random_vector(p.ndof, 471))
+    assert rc == 0 and st["iters"] == 0 and not u.any()
+
+
+def test_exact_initial_guess_needs_no_iteration():
+    import scipy.sparse.linalg as spla
+    p = W.random_problem(480, ncell=(2, 2, 2), k=2)
+    f = W.random_vector(p.ndof, 481)
+    ustar = spla.spsolve(oracle.assemble(p).tocsc(), f)
+    u, st, rc = _solve(p, f, 1e-8, u0=ustar)
+    assert rc == 0 and st["iters"] == 0 and st["applies"] == 1
+    assert np.array_equal(u, ustar)
+
+
+def test_non_finite_rhs_is_reported():
+    from paper_1711_10885_amd import binding
+    p = W.random_problem(490, ncell=(2, 2, 2), k=1)
+    f = W.random_vector(p.ndof, 491)
+    f[5] = np.nan
+    _, _, rc = _solve(p, f, 1e-8, check=False)
+    assert rc == binding.DG_ENAN
+
+
+@pytest.mark.parametrize("over", [dict(restart=0), dict(restart=64), dict(maxit=0), dict(method=9),
+                                  dict(precond=9)])
+def test_invalid_options_are_rejected(over):
+    from paper_1711_10885_amd import binding
+    p = W.random_problem(495, ncell=(1, 1, 1), k=1)
+    _, _, rc = _solve(p, W.random_vector(p.ndof, 496), 1e-8, check=False, **over)
+    assert rc == binding.DG_EINVAL
+
+
+def test_manufactured_solution_converges_at_order_k_plus_1():
+    """Discrete solutions of the mixed-tier coefficients (K = I,
+    b = (1, 0.5, 0.25), c = 0.1) against u = sin(pi x) sin(pi y) sin(pi z):
+    the L2 error falls like h^(k+1) (textbook SIPG rate)."""
+    k = 3
+    errs = []
+    for N in (4, 8):
+        p = W.mixed_k5_48(N=N, k=k)
+        f = oracle.rhs(p, W.manufactured_source(p.K, p.b_const, p.c))
+        u, st, rc = _solve(p, f, 1e-11)
+        assert rc == 0
+        errs.append(oracle.l2err(p, u, W.manufactured_u()))
+    order = np.log2(errs[0] / errs[1])
+    print(f"L2 errors {errs}, order {order:.2f}", flush=True)
+    assert abs(order - (k + 1)) <= 0.3
