@@ -74,7 +74,13 @@ typedef enum {
  *              d = kappa K_aa and <.,.> the harmonic mean (Sec. 2.2:
  *              sigma = alpha p (p+d-1), alpha = 2, in the paper).
  *   flags      DG_WITH_FP32: also build the FP32 operator (dg_apply_f32);
- *              DG_WITH_BLOCK_JACOBI: factor the block-Jacobi preconditioner.
+ *              DG_WITH_BLOCK_JACOBI: build the block-Jacobi preconditioner
+ *              (k <= 7): the cell blocks A_TT of the operator (volume term
+ *              and the self-coupling of the six faces) are extracted by
+ *              probing, inverted in FP64 (Gauss-Jordan; coercivity makes every
+ *              block positive real, so no pivoting) and stored in FP32:
+ *              4 ncells (k+1)^6 bytes, plus 8 ncells (k+1)^6 bytes while
+ *              building.
  */
 typedef struct {
   int32_t ncell[3];
@@ -165,6 +171,13 @@ typedef struct {
  * u is the last iterate and st is filled), DG_ENAN (non-finite value). */
 dg_status dg_solve(dg_handle *h, const double *f, double *u, double tol, const dg_solve_opts *o,
                    dg_solve_stats *st, void *hip_stream);
+
+/* z := M^{-1} r for the handle's preconditioner precond: DG_PREC_BLOCK_JACOBI
+ * (needs DG_WITH_BLOCK_JACOBI; z_T = A_TT^{-1} r_T with the FP32 inverse cell
+ * blocks, FP64 accumulation).  r, z: device, ndof doubles, no overlap.
+ * Asynchronous on hip_stream.  DG_EINVAL if the handle has no such
+ * preconditioner. */
+dg_status dg_precond_apply(dg_handle *h, int32_t precond, const double *r, double *z, void *hip_stream);
 
 /* Number of degrees of freedom of the handle's space (or -1 for NULL). */
 int64_t dg_ndof(const dg_handle *h);

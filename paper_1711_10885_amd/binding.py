@@ -24,8 +24,8 @@ _STATUS = {DG_EINVAL: "DG_EINVAL", DG_ENOMEM: "DG_ENOMEM", DG_EHIP: "DG_EHIP",
            DG_ENOTCONV: "DG_ENOTCONV", DG_ENAN: "DG_ENAN"}
 
 # every symbol include/dg.h declares
-EXPORTS = ["dg_setup", "dg_apply", "dg_set_kernel", "dg_solve", "dg_ndof", "dg_degree",
-           "dg_last_error", "dg_destroy"]
+EXPORTS = ["dg_setup", "dg_apply", "dg_set_kernel", "dg_solve", "dg_precond_apply", "dg_ndof",
+           "dg_degree", "dg_last_error", "dg_destroy"]
 
 
 class DGError(RuntimeError):
@@ -87,6 +87,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dg_solve.argtypes = [H, vp, vp, ctypes.c_double, ctypes.POINTER(SolveOpts),
                              ctypes.POINTER(SolveStats), vp]
     lib.dg_solve.restype = ctypes.c_int
+    lib.dg_precond_apply.argtypes = [H, ctypes.c_int32, vp, vp, vp]
+    lib.dg_precond_apply.restype = ctypes.c_int
     lib.dg_ndof.argtypes = [H]
     lib.dg_ndof.restype = ctypes.c_int64
     lib.dg_degree.argtypes = [H]
@@ -188,6 +190,17 @@ class DG:
         _check(load().dg_apply(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
                                _stream_ptr(stream)))
         return y
+
+    def precond_apply(self, r, z=None, precond: int = DG_PREC_BLOCK_JACOBI, stream=None):
+        """z := M^{-1} r for the handle's preconditioner (float64 device tensors)."""
+        import torch
+        _check_vec(r, self.ndof, torch.float64, "r")
+        if z is None:
+            z = torch.empty_like(r)
+        _check_vec(z, self.ndof, torch.float64, "z")
+        _check(load().dg_precond_apply(self._h, int(precond), ctypes.c_void_p(r.data_ptr()),
+                                       ctypes.c_void_p(z.data_ptr()), _stream_ptr(stream)))
+        return z
 
     def solve(self, f, u=None, tol: float = 1e-8, method: int = DG_GMRES64,
               precond: int = DG_PREC_NONE, restart: int = 30, maxit: int = 20000,

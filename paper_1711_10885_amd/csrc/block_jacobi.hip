@@ -1,0 +1,250 @@
+// Block-Jacobi preconditioner: M = blockdiag(A_TT), the cell blocks of the
+// WSIPG operator (volume term plus the self-coupling of the six faces: the
+// operator applied to a function supported on T alone).
+//
+// Build (once, at setup):
+//   1. Extraction by unit probing through the FP64 apply kernel.  Cells are
+//      coloured by the parity of i1+i2+i3, so no two cells of one colour share
+//      a face; x = e_j on every cell of one colour gives, on those cells,
+//      column j of A_TT.  2 (k+1)^3 applications in total.  Column j of each
+//      block is gathered into an FP64 store, column-major per cell.
+//   2. In-place blocked Gauss-Jordan inversion in FP64, one workgroup per
+//      cell, panels of BS rows/columns staged in LDS, without pivoting: the
+//      form is coercive (x^T A x > 0 for x != 0, Sec. 2.2 with the upwind
+//      flux and div b = 0), so every cell block and every Schur complement is
+//      positive real and all pivots are positive.  A non-positive or
+//      non-finite pivot is reported as an error.
+//      Inverting the column-major store treated as row-major gives
+//      (A^T)^{-1} = (A^{-1})^T row-major, i.e. A^{-1} column-major.
+//   3. Conversion to FP32 (the store the solvers read).
+// Apply: z_T = A_TT^{-1} r_T, one thread per row, column-major blocks so that
+// consecutive lanes read consecutive addresses; FP64 accumulation.  HBM-bound:
+// 4 (k+1)^3 bytes of block store per DOF.
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "dg_internal.h"
+
+namespace dgmf {
+
+constexpr int kBjThreads = 256;
+
+// x[c*nb + j] = value on cells of the given colour
+__global__ void k_bj_probe(double *__restrict__ x, int n1, int n2, int64_t ncells, int nb, int j,
+                           int colour, double value) {
+  for (int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; c < ncells;
+       c += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t i1 = c % n1, r = c / n1, i2 = r % n2, i3 = r / n2;
+    if (int((i1 + i2 + i3) & 1) == colour) x[c * nb + j] = value;
+  }
+}
+
+// B[c][j*nb + i] = y[c*nb + i] on cells of the given colour (column j)
+__global__ void k_bj_gather(const double *__restrict__ y, double *__restrict__ B, int n1, int n2,
+                            int64_t ncells, int nb, int j, int colour) {
+  const int64_t total = ncells * nb;
+  for (int64_t g = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; g < total;
+       g += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t c = g / nb;
+    const int i = int(g - c * nb);
+    const int64_t i1 = c % n1, r = c / n1, i2 = r % n2, i3 = r / n2;
+    if (int((i1 + i2 + i3) & 1) == colour) B[c * int64_t(nb) * nb + int64_t(j) * nb + i] = y[g];
+  }
+}
+
+// In-place Gauss-Jordan inversion of one nb x nb block per workgroup (row-major
+// view M[r*nb + c]).  For each pivot block P = [p0, p0+bs):
+//   M_PP <- M_PP^{-1} =: I_P;        M_Pj <- I_P M_Pj            (j not in P)
+//   M_ij <- M_ij - M_iP M_Pj(new);   M_iP <- -M_iP I_P           (i not in P)
+// Dynamic LDS: Rp[BS][nb] (new row panel), Cp[nb][BS] (old column panel),
+// Ip[BS][BS].
+template <int BS>
+__global__ __launch_bounds__(kBjThreads) void k_bj_invert(double *__restrict__ B, int nb, int *bad) {
+  extern __shared__ double lds[];
+  double *Rp = lds, *Cp = lds + BS * nb, *Ip = Cp + size_t(nb) * BS;
+  __shared__ int s_bad;
+  double *M = B + size_t(blockIdx.x) * nb * nb;
+  const int t = threadIdx.x;
+  if (t == 0) s_bad = 0;
+  for (int p0 = 0; p0 < nb; p0 += BS) {
+    const int bs = min(BS, nb - p0);
+    // (a) pivot block into LDS
+    for (int e = t; e < bs * bs; e += kBjThreads) Ip[(e / bs) * BS + e % bs] = M[size_t(p0 + e / bs) * nb + p0 + e % bs];
+    // (d) old column panel (rows outside P)
+    for (int e = t; e < nb * bs; e += kBjThreads) {
+      const int i = e / bs, l = e % bs;
+      Cp[i * BS + l] = M[size_t(i) * nb + p0 + l];
+    }
+    __syncthreads();
+    // (b) invert the pivot block by scalar Gauss-Jordan (no pivoting)
+    for (int k = 0; k < bs; ++k) {
+      double a_rc = 0, a_rk = 0, a_kc = 0, piv = 1;
+      const int r = t / bs, c = t % bs;
+      const bool act = t < bs * bs;
+      if (act) {
+        a_rc = Ip[r * BS + c];
+        a_rk = Ip[r * BS + k];
+        a_kc = Ip[k * BS + c];
+        piv = Ip[k * BS + k];
+      }
+      __syncthreads();
+      if (act) {
+        if (!(piv > 0.0) || !isfinite(piv)) s_bad = 1;
+        const double d = 1.0 / piv;
+        double v;
+        if (r == k)
+          v = (c == k) ? d : a_kc * d;
+        else
+          v = (c == k) ? -a_rk * d : fma(-a_rk * d, a_kc, a_rc);
+        Ip[r * BS + c] = v;
+      }
+      __syncthreads();
+    }
+    // (c) new row panel R = I_P M_P,: for columns outside P (to LDS and memory)
+    for (int e = t; e < bs * nb; e += kBjThreads) {
+      const int k = e / nb, c = e % nb;
+      if (c >= p0 && c < p0 + bs) continue;
+      double s = 0.0;
+      for (int l = 0; l < bs; ++l) s = fma(Ip[k * BS + l], M[size_t(p0 + l) * nb + c], s);
+      Rp[k * nb + c] = s;
+    }
+    __syncthreads();
+    for (int e = t; e < bs * nb; e += kBjThreads) {
+      const int k = e / nb, c = e % nb;
+      if (c >= p0 && c < p0 + bs) continue;
+      M[size_t(p0 + k) * nb + c] = Rp[k * nb + c];
+    }
+    // (e) rank-bs update of the rest, (f) new column panel, (g) pivot block
+    for (int e = t; e < nb * nb; e += kBjThreads) {
+      const int i = e / nb, j = e % nb;
+      if (i >= p0 && i < p0 + bs) continue;
+      if (j >= p0 && j < p0 + bs) {
+        const int l = j - p0;
+        double s = 0.0;
+        for (int m = 0; m < bs; ++m) s = fma(Cp[i * BS + m], Ip[m * BS + l], s);
+        M[size_t(i) * nb + j] = -s;
+      } else {
+        double s = M[size_t(i) * nb + j];
+        for (int l = 0; l < bs; ++l) s = fma(-Cp[i * BS + l], Rp[l * nb + j], s);
+        M[size_t(i) * nb + j] = s;
+      }
+    }
+    for (int e = t; e < bs * bs; e += kBjThreads) M[size_t(p0 + e / bs) * nb + p0 + e % bs] = Ip[(e / bs) * BS + e % bs];
+    __syncthreads();
+  }
+  if (t == 0 && s_bad) atomicOr(bad, 1);
+}
+
+__global__ void k_to_f32(const double *__restrict__ a, float *__restrict__ b, size_t n) {
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+    b[i] = float(a[i]);
+}
+
+// z[c*nb + i] = sum_j Binv[c][j*nb + i] r[c*nb + j]
+template <typename TR, typename TZ>
+__global__ __launch_bounds__(kBjThreads) void k_bj_apply(const float *__restrict__ Binv, const TR *__restrict__ r,
+                                                         TZ *__restrict__ z, int nb, int64_t total) {
+  for (int64_t g = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; g < total;
+       g += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t c = g / nb;
+    const int i = int(g - c * nb);
+    const float *Bc = Binv + c * int64_t(nb) * nb + i;
+    const TR *rc = r + c * nb;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int j = 0;
+    for (; j + 4 <= nb; j += 4) {
+      s0 = fma(double(Bc[size_t(j) * nb]), double(rc[j]), s0);
+      s1 = fma(double(Bc[size_t(j + 1) * nb]), double(rc[j + 1]), s1);
+      s2 = fma(double(Bc[size_t(j + 2) * nb]), double(rc[j + 2]), s2);
+      s3 = fma(double(Bc[size_t(j + 3) * nb]), double(rc[j + 3]), s3);
+    }
+    for (; j < nb; ++j) s0 = fma(double(Bc[size_t(j) * nb]), double(rc[j]), s0);
+    z[g] = TZ((s0 + s1) + (s2 + s3));
+  }
+}
+
+static int grid_for(int64_t work) {
+  const int64_t g = (work + kBjThreads - 1) / kBjThreads;
+  return int(g < 1 ? 1 : (g > (1 << 20) ? (1 << 20) : g));
+}
+
+dg_status build_block_jacobi(dg_handle *h) {
+  const int n = h->k + 1, nb = n * n * n;
+  if (nb > kMaxBjBlock)
+    return set_error(DG_EINVAL, "dg_setup: block Jacobi supports k <= 7 ((k+1)^3 <= 512)");
+  const size_t ndof = size_t(h->ndof), nblk = size_t(h->ncells) * nb * nb;
+  double *x = nullptr, *y = nullptr, *B = nullptr;
+  int *bad = nullptr;
+  hipError_t e;
+  auto fail = [&](hipError_t err, const char *what) {
+    if (x) (void)hipFree(x);
+    if (y) (void)hipFree(y);
+    if (B) (void)hipFree(B);
+    if (bad) (void)hipFree(bad);
+    return hip_error(err, what);
+  };
+  if ((e = hipMalloc(&x, ndof * sizeof(double))) != hipSuccess) return fail(e, "block Jacobi: probe vector");
+  if ((e = hipMalloc(&y, ndof * sizeof(double))) != hipSuccess) return fail(e, "block Jacobi: probe vector");
+  if ((e = hipMalloc(&B, nblk * sizeof(double))) != hipSuccess) return fail(e, "block Jacobi: FP64 blocks");
+  if ((e = hipMalloc(&bad, sizeof(int))) != hipSuccess) return fail(e, "block Jacobi: flag");
+  if ((e = hipMalloc(&h->bj, nblk * sizeof(float))) != hipSuccess) {
+    h->bj = nullptr;
+    return fail(e, "block Jacobi: FP32 blocks");
+  }
+  const hipStream_t s = nullptr;
+  if ((e = hipMemsetAsync(x, 0, ndof * sizeof(double), s)) != hipSuccess) return fail(e, "block Jacobi: memset");
+  if ((e = hipMemsetAsync(bad, 0, sizeof(int), s)) != hipSuccess) return fail(e, "block Jacobi: memset");
+  const int n1 = h->mesh.ncell[0], n2 = h->mesh.ncell[1];
+  const int gc = grid_for(h->ncells), gr = grid_for(int64_t(ndof));
+  for (int colour = 0; colour < 2; ++colour)
+    for (int j = 0; j < nb; ++j) {
+      hipLaunchKernelGGL(k_bj_probe, dim3(gc), dim3(kBjThreads), 0, s, x, n1, n2, int64_t(h->ncells), nb, j,
+                         colour, 1.0);
+      if ((e = apply_f64(h, x, y, s)) != hipSuccess) return fail(e, "block Jacobi: probe apply");
+      hipLaunchKernelGGL(k_bj_gather, dim3(gr), dim3(kBjThreads), 0, s, y, B, n1, n2, int64_t(h->ncells), nb,
+                         j, colour);
+      hipLaunchKernelGGL(k_bj_probe, dim3(gc), dim3(kBjThreads), 0, s, x, n1, n2, int64_t(h->ncells), nb, j,
+                         colour, 0.0);
+    }
+  if ((e = hipGetLastError()) != hipSuccess) return fail(e, "block Jacobi: probing");
+  // panels stay under 64 KiB of LDS: BS = 16 up to (k+1)^3 = 216, else 4
+  if (nb <= 216) {
+    constexpr int BS = 16;
+    const size_t lds = sizeof(double) * (2 * size_t(BS) * nb + BS * BS);
+    hipLaunchKernelGGL((k_bj_invert<BS>), dim3(unsigned(h->ncells)), dim3(kBjThreads), lds, s, B, nb, bad);
+  } else {
+    constexpr int BS = 4;
+    const size_t lds = sizeof(double) * (2 * size_t(BS) * nb + BS * BS);
+    hipLaunchKernelGGL((k_bj_invert<BS>), dim3(unsigned(h->ncells)), dim3(kBjThreads), lds, s, B, nb, bad);
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return fail(e, "block Jacobi: inversion");
+  hipLaunchKernelGGL(k_to_f32, dim3(4096), dim3(kBjThreads), 0, s, B, h->bj, nblk);
+  int hbad = 0;
+  if ((e = hipMemcpy(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost)) != hipSuccess)
+    return fail(e, "block Jacobi: flag readback");
+  (void)hipFree(x);
+  (void)hipFree(y);
+  (void)hipFree(B);
+  (void)hipFree(bad);
+  if (hbad) {
+    (void)hipFree(h->bj);
+    h->bj = nullptr;
+    return set_error(DG_ENAN, "dg_setup: a cell block has a non-positive pivot (the form is not coercive)");
+  }
+  h->bj_nb = nb;
+  return DG_OK;
+}
+
+template <typename TR, typename TZ>
+hipError_t bj_apply(const dg_handle *h, const TR *r, TZ *z, hipStream_t s) {
+  const int64_t total = h->ndof;
+  hipLaunchKernelGGL((k_bj_apply<TR, TZ>), dim3(grid_for(total)), dim3(kBjThreads), 0, s, h->bj, r, z, h->bj_nb,
+                     total);
+  return hipGetLastError();
+}
+
+template hipError_t bj_apply<double, double>(const dg_handle *, const double *, double *, hipStream_t);
+template hipError_t bj_apply<float, float>(const dg_handle *, const float *, float *, hipStream_t);
+
+}  // namespace dgmf

@@ -141,6 +141,7 @@ extern "C" void dg_destroy(dg_handle *h) {
   int cur = 0;
   if (hipGetDevice(&cur) == hipSuccess && cur != h->device) (void)hipSetDevice(h->device);
   release_solver(h);
+  if (h->bj) (void)hipFree(h->bj);
   if (h->dev_block) (void)hipFree(h->dev_block);
   if (cur != h->device) (void)hipSetDevice(cur);
   delete h;
@@ -177,6 +178,10 @@ extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
         return set_error(DG_EINVAL, "dg_setup: kappa must be positive and finite");
   const int n = p->k + 1;
   if (ncells > (int64_t(1) << 31) / 2) return set_error(DG_EINVAL, "dg_setup: too many cells");
+  if (p->flags & ~(DG_WITH_FP32 | DG_WITH_BLOCK_JACOBI))
+    return set_error(DG_EINVAL, "dg_setup: unknown flag bits");
+  if ((p->flags & DG_WITH_BLOCK_JACOBI) && n * n * n > kMaxBjBlock)
+    return set_error(DG_EINVAL, "dg_setup: block Jacobi supports k <= 7");
 
   dg_handle *h = new dg_handle();
   std::memset(&h->prob, 0, sizeof(h->prob));
@@ -191,6 +196,8 @@ extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
   h->ws = nullptr;
   h->ws_bytes = 0;
   h->red = nullptr;
+  h->bj = nullptr;
+  h->bj_nb = 0;
   if (hipGetDevice(&h->device) != hipSuccess) {
     delete h;
     return set_error(DG_EHIP, "dg_setup: no HIP device");
@@ -247,6 +254,14 @@ extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
   std::memcpy(M.K, p->K, sizeof(M.K));
   M.c = p->c;
   M.sigma = p->sigma;
+  if (p->flags & DG_WITH_BLOCK_JACOBI) {
+    const dg_status ds = build_block_jacobi(h);
+    if (ds != DG_OK) {
+      const std::string msg = dg_last_error();
+      dg_destroy(h);
+      return set_error(ds, msg);
+    }
+  }
   *out = h;
   return DG_OK;
 }
@@ -275,5 +290,26 @@ extern "C" dg_status dg_apply(dg_handle *h, const double *x, double *y, void *st
   }
   hipError_t e = apply_f64(h, x, y, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_error(e, "dg_apply: kernel launch");
+  return DG_OK;
+}
+
+extern "C" dg_status dg_precond_apply(dg_handle *h, int32_t precond, const double *r, double *z, void *stream) {
+  if (!h) return set_error(DG_EINVAL, "dg_precond_apply: handle is NULL");
+  if (!r || !z) return set_error(DG_EINVAL, "dg_precond_apply: r or z is NULL");
+  if (overlaps(r, z, size_t(h->ndof) * sizeof(double)))
+    return set_error(DG_EINVAL, "dg_precond_apply: r and z overlap");
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != h->device) {
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_error(e, "dg_precond_apply: hipSetDevice");
+  }
+  hipError_t e;
+  if (precond == DG_PREC_BLOCK_JACOBI) {
+    if (!h->bj) return set_error(DG_EINVAL, "dg_precond_apply: handle was set up without DG_WITH_BLOCK_JACOBI");
+    e = bj_apply<double, double>(h, r, z, static_cast<hipStream_t>(stream));
+  } else {
+    return set_error(DG_EINVAL, "dg_precond_apply: unknown preconditioner");
+  }
+  if (e != hipSuccess) return hip_error(e, "dg_precond_apply: kernel launch");
   return DG_OK;
 }

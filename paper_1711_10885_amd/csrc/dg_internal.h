@@ -11,7 +11,8 @@
 
 namespace dgmf {
 
-constexpr int kMaxN = 11;  // k <= 10
+constexpr int kMaxN = 11;         // k <= 10
+constexpr int kMaxBjBlock = 512;  // block Jacobi for (k+1)^3 <= 512
 
 // 1D tables on the reference interval [0,1] for one degree (Sec. 3.2,
 // eq. (gradient_matrices); face tables B^(q) of Sec. 3.4):
@@ -52,6 +53,9 @@ struct dg_handle {
   void *ws;
   size_t ws_bytes;
   double *red;      // reduction partials + small device vectors of the Krylov kernels
+  // block Jacobi: inverse cell blocks, FP32, column-major per cell (or null)
+  float *bj;
+  int bj_nb;
 };
 
 namespace dgmf {
@@ -65,6 +69,11 @@ hipError_t launch_apply_fused_f64(const dg_handle *h, const double *x, double *y
 
 // Operator application through the kernel the handle selects.
 hipError_t apply_f64(const dg_handle *h, const double *x, double *y, hipStream_t s);
+
+// Block Jacobi: build the inverse cell blocks (setup), z = M^{-1} r.
+dg_status build_block_jacobi(dg_handle *h);
+template <typename TR, typename TZ>
+hipError_t bj_apply(const dg_handle *h, const TR *r, TZ *z, hipStream_t s);
 
 // Free the solver resources of a handle (called by dg_destroy).
 void release_solver(dg_handle *h);

@@ -76,7 +76,10 @@ extern "C" dg_status dg_solve(dg_handle *h, const double *f, double *u, double t
     return set_error(DG_EINVAL, "dg_solve: restart must be in 1..63");
   if (opt.maxit < 1) return set_error(DG_EINVAL, "dg_solve: maxit must be >= 1");
   if (opt.method != DG_GMRES64) return set_error(DG_EINVAL, "dg_solve: unknown method");
-  if (opt.precond != DG_PREC_NONE) return set_error(DG_EINVAL, "dg_solve: unknown preconditioner");
+  if (opt.precond != DG_PREC_NONE && opt.precond != DG_PREC_BLOCK_JACOBI)
+    return set_error(DG_EINVAL, "dg_solve: unknown preconditioner");
+  if (opt.precond == DG_PREC_BLOCK_JACOBI && !h->bj)
+    return set_error(DG_EINVAL, "dg_solve: handle was set up without DG_WITH_BLOCK_JACOBI");
 
   int cur = -1;
   if (hipGetDevice(&cur) != hipSuccess || cur != h->device) {
@@ -86,15 +89,16 @@ extern "C" dg_status dg_solve(dg_handle *h, const double *f, double *u, double t
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int m = opt.restart;
 
-  // workspace: V (m+1) n | w n
+  const bool have_prec = opt.precond != DG_PREC_NONE;
+  // workspace: V (m+1) n | w n | Z n (fixed preconditioner)
   const size_t vb = align256(sizeof(double) * n * (m + 1)), wb = align256(sizeof(double) * n);
-  dg_status ds = ensure_workspace(h, vb + wb);
+  dg_status ds = ensure_workspace(h, vb + wb + (have_prec ? wb : 0));
   if (ds != DG_OK) return ds;
   char *base = static_cast<char *>(h->ws);
   KrylovBufs K;
   K.V = base;
   K.w = base + vb;
-  K.Z = nullptr;
+  K.Z = have_prec ? base + vb + wb : nullptr;
   K.n = n;
   K.restart = m;
   K.flex = false;
@@ -119,9 +123,9 @@ extern "C" dg_status dg_solve(dg_handle *h, const double *f, double *u, double t
     return DG_OK;
   }
   auto op = [h, s](const double *x, double *y) { return apply_f64(h, x, y, s); };
-  auto noprec = [](const double *, double *) { return hipSuccess; };
+  auto prec = [h, s](const double *v, double *z) { return bj_apply<double, double>(h, v, z, s); };
   GmresOut go;
-  e = gmres<double>(K, op, noprec, false, f, u, fnorm, tol, opt.maxit, 0, un2 == 0.0, scratch, small, s, go);
+  e = gmres<double>(K, op, prec, have_prec, f, u, fnorm, tol, opt.maxit, 0, un2 == 0.0, scratch, small, s, go);
   if (e != hipSuccess) return hip_error(e, "dg_solve: GMRES");
   stats.iters = go.iters;
   stats.outer = go.cycles;

@@ -66,6 +66,8 @@ def _struct(prob, **over):
     (dict(K=np.array([[1, 0.5, 0], [0, 1, 0], [0, 0, 1.0]])), "symmetric"),
     (dict(b_axis0=3), "b_axis"),
     (dict(c=float("nan")), "c must be finite"),
+    (dict(flags=8), "unknown flag"),
+    (dict(k=8, flags=2), "block Jacobi supports"),
 ])
 def test_setup_rejects_invalid_problems(over, msg):
     lib = _lib()

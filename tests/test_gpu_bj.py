@@ -1,0 +1,127 @@
+"""Block-Jacobi preconditioner on the GPU, through the C ABI.
+
+The oracle's cell blocks A_TT (its own 2-colour probing of its own apply)
+give z_exact = A_TT^{-1} r_T by a dense FP64 solve.  The GPU stores the
+inverse blocks in FP32 and accumulates in FP64, so each entry of z may differ
+by the FP32 rounding of the inverse: |dz_i| <= u32 (|A_TT^{-1}| |r_T|)_i,
+taken with a factor 2 (u32 = 2^-24) plus a 1e-10 max|z| floor for the FP64
+inversion error.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1711_10885_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _check_blocks(blocks, r, z, what):
+    nb = blocks.shape[1]
+    R = r.reshape(-1, nb)
+    Z = z.reshape(-1, nb)
+    inv = np.linalg.inv(blocks)
+    zx = np.einsum("cij,cj->ci", inv, R)
+    bound = 2 * U32 * np.einsum("cij,cj->ci", np.abs(inv), np.abs(R)) + 1e-10 * np.abs(zx).max()
+    err = np.abs(Z - zx)
+    rel = np.linalg.norm(Z - zx) / np.linalg.norm(zx)
+    print(f"{what}: rel2 {rel:.2e}, worst err/bound {(err / bound).max():.3f}", flush=True)
+    assert np.all(err <= bound), what
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
+def test_inverse_blocks_match_oracle_blocks(k):
+    torch = _torch()
+    from paper_1711_10885_amd import binding
+    p = W.random_problem(500 + k, ncell=(3, 2, 2), k=k, b="sine" if k % 2 else "const")
+    r = W.random_vector(p.ndof, 510 + k)
+    with binding.DG(p, flags=binding.DG_WITH_BLOCK_JACOBI) as dg:
+        z = dg.precond_apply(torch.from_numpy(r).cuda()).cpu().numpy()
+    _check_blocks(oracle.block_diagonal(p), r, z, f"random k={k}")
+
+
+@pytest.mark.parametrize("ncell", [(1, 1, 1), (2, 1, 1), (1, 3, 2)])
+def test_degenerate_meshes(ncell):
+    torch = _torch()
+    from paper_1711_10885_amd import binding
+    p = W.random_problem(520, ncell=ncell, k=2)
+    r = W.random_vector(p.ndof, 521)
+    with binding.DG(p, flags=binding.DG_WITH_BLOCK_JACOBI) as dg:
+        z = dg.precond_apply(torch.from_numpy(r).cuda()).cpu().numpy()
+    _check_blocks(oracle.block_diagonal(p), r, z, f"mesh {ncell}")
+
+
+def test_sampled_cells_of_the_64_cube_k3_workload():
+    """64^3 cells, k = 3, kappa = exp(g) (16.8M DOF): blocks of sampled cells
+    rebuilt by the oracle (unit probes on the sampled cells only)."""
+    torch = _torch()
+    from paper_1711_10885_amd import binding
+    p = W.learned_k3_64()
+    nb = (p.k + 1) ** 3
+    N = p.ncell[0]
+    ids = [0, N - 1, N * N * N - 1, 37 + N * (11 + N * 23), 5 + N * (60 + N * 31)]
+    cells = np.array(sorted(ids), dtype=np.int64)
+    r = W.random_vector(p.ndof, 530)
+    with binding.DG(p, flags=binding.DG_WITH_BLOCK_JACOBI) as dg:
+        z = dg.precond_apply(torch.from_numpy(r).cuda()).cpu().numpy()
+    x = np.zeros(p.ndof)
+    blocks = np.zeros((cells.size, nb, nb))
+    for j in range(nb):
+        x[cells * nb + j] = 1.0
+        blocks[:, :, j] = oracle.apply_rows(p, x, cells)
+        x[cells * nb + j] = 0.0
+    sel = (cells[:, None] * nb + np.arange(nb)[None, :]).ravel()
+    _check_blocks(blocks, r[sel], z[sel], "learned_k3_64 sampled cells")
+
+
+def test_block_jacobi_gmres_needs_fewer_iterations_and_solves():
+    torch = _torch()
+    from paper_1711_10885_amd import binding
+    p = W.random_problem(540, ncell=(4, 4, 3), k=3, b="sine")
+    f = W.random_vector(p.ndof, 541)
+    with binding.DG(p, flags=binding.DG_WITH_BLOCK_JACOBI) as dg:
+        fd = torch.from_numpy(f).cuda()
+        u0, s0, _ = dg.solve(fd, tol=1e-10)
+        u1, s1, _ = dg.solve(fd, tol=1e-10, precond=binding.DG_PREC_BLOCK_JACOBI)
+        u1 = u1.cpu().numpy()
+    print(f"plain {s0}\nblock Jacobi {s1}", flush=True)
+    assert s1["iters"] < s0["iters"]
+    res = np.linalg.norm(f - oracle.apply(p, u1)) / np.linalg.norm(f)
+    assert res <= 1.05e-10, res
+
+
+def test_block_jacobi_gmres_iterations_match_oracle_gmres():
+    """Oracle GMRES(30) right-preconditioned with exact FP64 block solves; the
+    GPU uses FP32 inverse blocks, so counts agree to a few percent only."""
+    torch = _torch()
+    from paper_1711_10885_amd import binding
+    p = W.mixed_k5_48(N=6, k=3)
+    f = oracle.rhs(p, W.manufactured_source(p.K, p.b_const, p.c))
+    nb = (p.k + 1) ** 3
+    inv = np.linalg.inv(oracle.block_diagonal(p))
+    prec = lambda v: np.einsum("cij,cj->ci", inv, v.reshape(-1, nb)).ravel()
+    uo, it_o, rel_o = oracle.gmres(lambda v: oracle.apply(p, v), f, tol=1e-8, precond=prec)
+    with binding.DG(p, flags=binding.DG_WITH_BLOCK_JACOBI) as dg:
+        u, st, _ = dg.solve(torch.from_numpy(f).cuda(), tol=1e-8, precond=binding.DG_PREC_BLOCK_JACOBI)
+    print(f"oracle {it_o} iterations; GPU {st}", flush=True)
+    assert abs(st["iters"] - it_o) <= max(2, 0.05 * it_o)
+
+
+def test_precond_apply_without_block_jacobi_is_rejected():
+    torch = _torch()
+    from paper_1711_10885_amd import binding
+    p = W.random_problem(550, ncell=(1, 1, 1), k=1)
+    with binding.DG(p) as dg:
+        r = torch.zeros(p.ndof, dtype=torch.float64, device="cuda")
+        with pytest.raises(binding.DGError):
+            dg.precond_apply(r)
+        with pytest.raises(binding.DGError):
+            dg.solve(r + 1.0, precond=binding.DG_PREC_BLOCK_JACOBI)
