@@ -73,8 +73,7 @@ typedef enum {
  *              interior faces, sigma * d / h_a on boundary faces, with
  *              d = kappa K_aa and <.,.> the harmonic mean (Sec. 2.2:
  *              sigma = alpha p (p+d-1), alpha = 2, in the paper).
- *   flags      DG_WITH_FP32: also build the FP32 operator (dg_apply_f32);
- *              DG_WITH_BLOCK_JACOBI: build the block-Jacobi preconditioner
+ *   flags      DG_WITH_BLOCK_JACOBI: build the block-Jacobi preconditioner
  *              (k <= 7): the cell blocks A_TT of the operator (volume term
  *              and the self-coupling of the six faces) are extracted by
  *              probing, inverted in FP64 (Gauss-Jordan; coercivity makes every
@@ -96,7 +95,6 @@ typedef struct {
   int32_t flags;
 } dg_problem;
 
-#define DG_WITH_FP32 1
 #define DG_WITH_BLOCK_JACOBI 2
 
 /* Create a handle on the current HIP device: validates the problem, builds
@@ -111,6 +109,15 @@ dg_status dg_setup(const dg_problem *p, dg_handle **out);
  * so no two cells write the same entry).  x, y: device, ndof doubles, must not
  * overlap.  Asynchronous on hip_stream. */
 dg_status dg_apply(dg_handle *h, const double *x, double *y, void *hip_stream);
+
+/* y := A x with FP32 vectors (the operator of the mixed-precision tier): the
+ * 1D contractions, the LDS exchanges and the volume pointwise flux run in
+ * FP32; the face constants (weights, penalty gamma_F) and the pointwise face
+ * flux (jump, weighted average, upwind value, penalty term) are evaluated in
+ * FP64 from the FP32 traces and rounded to FP32 before the transposed
+ * contractions.  Same layout as dg_apply; always the tuned kernel.
+ * x, y: device, ndof floats, must not overlap.  Asynchronous on hip_stream. */
+dg_status dg_apply_f32(dg_handle *h, const float *x, float *y, void *hip_stream);
 
 /* Kernel selection for dg_apply (both compute the same operator and are
  * checked against the same oracle):
@@ -131,8 +138,8 @@ dg_status dg_set_kernel(dg_handle *h, int32_t variant);
 #define DG_GMRES_IR 1 /* GMRES-IR: FP64 residual r = f - A u and update          *
                        * u += ||r|| d in FP64; the correction d solves           *
                        * A d = r/||r|| by one FP32 GMRES(m) cycle (FP32 operator *
-                       * of dg_apply_f32, FP32 basis) to inner_tol.  Needs       *
-                       * DG_WITH_FP32 at setup.                                  */
+                       * of dg_apply_f32, FP32 basis, FP32 preconditioner        *
+                       * input/output) to inner_tol.                             */
 #define DG_FGMRES 2   /* flexible GMRES(m) in FP64: the basis of preconditioned  *
                        * vectors Z is kept, so the preconditioner may change     *
                        * between applications (the learned one does).            */

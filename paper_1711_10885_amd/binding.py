@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdgmf.so")
 
 DG_OK, DG_EINVAL, DG_ENOMEM, DG_EHIP, DG_ENOTCONV, DG_ENAN = 0, -1, -2, -3, -4, -5
-DG_WITH_FP32, DG_WITH_BLOCK_JACOBI = 1, 2
+DG_WITH_BLOCK_JACOBI = 2
 DG_KERNEL_AUTO, DG_KERNEL_REFERENCE = 0, 1
 DG_GMRES64, DG_GMRES_IR, DG_FGMRES = 0, 1, 2
 DG_PREC_NONE, DG_PREC_BLOCK_JACOBI, DG_PREC_LEARNED = 0, 1, 2
@@ -24,7 +24,7 @@ _STATUS = {DG_EINVAL: "DG_EINVAL", DG_ENOMEM: "DG_ENOMEM", DG_EHIP: "DG_EHIP",
            DG_ENOTCONV: "DG_ENOTCONV", DG_ENAN: "DG_ENAN"}
 
 # every symbol include/dg.h declares
-EXPORTS = ["dg_setup", "dg_apply", "dg_set_kernel", "dg_solve", "dg_precond_apply", "dg_ndof",
+EXPORTS = ["dg_setup", "dg_apply", "dg_apply_f32", "dg_set_kernel", "dg_solve", "dg_precond_apply", "dg_ndof",
            "dg_degree", "dg_last_error", "dg_destroy"]
 
 
@@ -82,6 +82,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dg_setup.restype = ctypes.c_int
     lib.dg_apply.argtypes = [H, vp, vp, vp]
     lib.dg_apply.restype = ctypes.c_int
+    lib.dg_apply_f32.argtypes = [H, vp, vp, vp]
+    lib.dg_apply_f32.restype = ctypes.c_int
     lib.dg_set_kernel.argtypes = [H, ctypes.c_int32]
     lib.dg_set_kernel.restype = ctypes.c_int
     lib.dg_solve.argtypes = [H, vp, vp, ctypes.c_double, ctypes.POINTER(SolveOpts),
@@ -189,6 +191,17 @@ class DG:
         _check_vec(y, self.ndof, torch.float64, "y")
         _check(load().dg_apply(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
                                _stream_ptr(stream)))
+        return y
+
+    def apply_f32(self, x, y=None, stream=None):
+        """y := A x with FP32 vectors (mixed-precision operator)."""
+        import torch
+        _check_vec(x, self.ndof, torch.float32, "x")
+        if y is None:
+            y = torch.empty_like(x)
+        _check_vec(y, self.ndof, torch.float32, "y")
+        _check(load().dg_apply_f32(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                   _stream_ptr(stream)))
         return y
 
     def precond_apply(self, r, z=None, precond: int = DG_PREC_BLOCK_JACOBI, stream=None):

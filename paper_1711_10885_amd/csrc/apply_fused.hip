@@ -48,16 +48,16 @@ namespace dgmf {
 
 // View of the compile-time table GLTab<N> at an offset; indices are resolved
 // at compile time after unrolling.
-template <int N>
+template <int N, typename T>
 struct CT {
   int off;
-  __device__ constexpr double operator[](int i) const { return GLTab<N>::v[off + i]; }
+  __device__ constexpr T operator[](int i) const { return T(GLTab<N>::v[off + i]); }
   __device__ constexpr CT operator+(int o) const { return CT{off + o}; }
 };
-#define cptr CT<N>
+#define cptr CT<N, T>
 
-template <int N>
-__device__ __forceinline__ CT<N> fresh(CT<N> p) {
+template <int N, typename T>
+__device__ __forceinline__ CT<N, T> fresh(CT<N, T> p) {
   return p;
 }
 
@@ -119,11 +119,11 @@ struct FCfg {
 // ---- even-odd 1D contractions --------------------------------------------
 
 // out[q] = sum_j M[q][j] in[j], M = V (ISD false) or D (ISD true)
-template <int N, bool ISD>
-__device__ __forceinline__ void eo_mv(cptr M, const double *in, double *out) {
+template <int N, bool ISD, typename T>
+__device__ __forceinline__ void eo_mv(cptr M, const T *in, T *out) {
 #pragma unroll
   for (int q = 0; q < N / 2; ++q) {
-    double E = 0.0, O = 0.0;
+    T E = T(0), O = T(0);
 #pragma unroll
     for (int j = 0; j < N; j += 2) E = fma(M[q * N + j], in[j], E);
 #pragma unroll
@@ -133,7 +133,7 @@ __device__ __forceinline__ void eo_mv(cptr M, const double *in, double *out) {
   }
   if (N & 1) {
     constexpr int m = N / 2;
-    double S = 0.0;
+    T S = T(0);
 #pragma unroll
     for (int j = ISD ? 1 : 0; j < N; j += 2) S = fma(M[m * N + j], in[j], S);
     out[m] = S;
@@ -141,10 +141,10 @@ __device__ __forceinline__ void eo_mv(cptr M, const double *in, double *out) {
 }
 
 // out[j] (+)= sum_q M[q][j] in[q]
-template <int N, bool ISD, bool ACC>
-__device__ __forceinline__ void eo_mtv(cptr M, const double *in, double *out) {
+template <int N, bool ISD, bool ACC, typename T>
+__device__ __forceinline__ void eo_mtv(cptr M, const T *in, T *out) {
   constexpr int H2 = N / 2;
-  double s[H2 > 0 ? H2 : 1], d[H2 > 0 ? H2 : 1];
+  T s[H2 > 0 ? H2 : 1], d[H2 > 0 ? H2 : 1];
 #pragma unroll
   for (int q = 0; q < H2; ++q) {
     s[q] = in[q] + in[N - 1 - q];
@@ -153,7 +153,7 @@ __device__ __forceinline__ void eo_mtv(cptr M, const double *in, double *out) {
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     const bool useS = ISD ? ((j & 1) != 0) : ((j & 1) == 0);
-    double acc = ACC ? out[j] : 0.0;
+    T acc = ACC ? out[j] : T(0);
 #pragma unroll
     for (int q = 0; q < H2; ++q) acc = fma(M[q * N + j], useS ? s[q] : d[q], acc);
     if ((N & 1) && useS) acc = fma(M[(N / 2) * N + j], in[N / 2], acc);
@@ -162,9 +162,9 @@ __device__ __forceinline__ void eo_mtv(cptr M, const double *in, double *out) {
 }
 
 // sum_j theta_j(1) in[j] and sum_j theta_j(0) in[j]
-template <int N>
-__device__ __forceinline__ void tr_val(cptr E1, const double *in, double &v1, double &v0) {
-  double E = 0.0, O = 0.0;
+template <int N, typename T>
+__device__ __forceinline__ void tr_val(cptr E1, const T *in, T &v1, T &v0) {
+  T E = T(0), O = T(0);
 #pragma unroll
   for (int j = 0; j < N; j += 2) E = fma(E1[j], in[j], E);
 #pragma unroll
@@ -174,9 +174,9 @@ __device__ __forceinline__ void tr_val(cptr E1, const double *in, double &v1, do
 }
 
 // sum_j theta_j'(1) in[j] and sum_j theta_j'(0) in[j]
-template <int N>
-__device__ __forceinline__ void tr_der(cptr F1, const double *in, double &d1, double &d0) {
-  double E = 0.0, O = 0.0;
+template <int N, typename T>
+__device__ __forceinline__ void tr_der(cptr F1, const T *in, T &d1, T &d0) {
+  T E = T(0), O = T(0);
 #pragma unroll
   for (int j = 0; j < N; j += 2) E = fma(F1[j], in[j], E);
 #pragma unroll
@@ -186,10 +186,10 @@ __device__ __forceinline__ void tr_der(cptr F1, const double *in, double &d1, do
 }
 
 // out[j] += theta_j(1) a1 + theta_j(0) a0 + theta_j'(1) b1 + theta_j'(0) b0
-template <int N>
-__device__ __forceinline__ void tr_acc(cptr E1, cptr F1, double a1, double a0, double b1,
-                                       double b0, double *out) {
-  const double ap = a1 + a0, am = a1 - a0, bp = b1 + b0, bm = b1 - b0;
+template <int N, typename T>
+__device__ __forceinline__ void tr_acc(cptr E1, cptr F1, T a1, T a0, T b1,
+                                       T b0, T *out) {
+  const T ap = a1 + a0, am = a1 - a0, bp = b1 + b0, bm = b1 - b0;
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     const bool ev = (j & 1) == 0;
@@ -199,9 +199,9 @@ __device__ __forceinline__ void tr_acc(cptr E1, cptr F1, double a1, double a0, d
 }
 
 // out[j] += theta_j(1) a1 + theta_j(0) a0
-template <int N>
-__device__ __forceinline__ void tr_acc_v(cptr E1, double a1, double a0, double *out) {
-  const double ap = a1 + a0, am = a1 - a0;
+template <int N, typename T>
+__device__ __forceinline__ void tr_acc_v(cptr E1, T a1, T a0, T *out) {
+  const T ap = a1 + a0, am = a1 - a0;
 #pragma unroll
   for (int j = 0; j < N; ++j) out[j] = fma(E1[j], (j & 1) == 0 ? ap : am, out[j]);
 }
@@ -209,9 +209,9 @@ __device__ __forceinline__ void tr_acc_v(cptr E1, double a1, double a0, double *
 // Modal derivative of a coefficient pencil (Legendre derivative identity):
 //   out_k = g_k sum_{j>k, j-k odd} g_j in_j      (coefficients of d/dt),
 // so that D in = V (G in) and a sum V a + D b is one contraction V (a + G b).
-template <int N>
-__device__ __forceinline__ void gmod(cptr g, const double *in, double *out) {
-  double se = 0.0, so = 0.0;  // suffix sums over even / odd j
+template <int N, typename T>
+__device__ __forceinline__ void gmod(cptr g, const T *in, T *out) {
+  T se = T(0), so = T(0);  // suffix sums over even / odd j
 #pragma unroll
   for (int k = N - 1; k >= 0; --k) {
     out[k] = g[k] * ((k & 1) ? se : so);
@@ -224,9 +224,9 @@ __device__ __forceinline__ void gmod(cptr g, const double *in, double *out) {
 
 // Transposed modal derivative: out_j = g_j sum_{k<j, j-k odd} g_k in_k, so
 // that D^T r = G^T (V^T r).
-template <int N>
-__device__ __forceinline__ void gmodT(cptr g, const double *in, double *out) {
-  double pe = 0.0, po = 0.0;  // prefix sums over even / odd k
+template <int N, typename T>
+__device__ __forceinline__ void gmodT(cptr g, const T *in, T *out) {
+  T pe = T(0), po = T(0);  // prefix sums over even / odd k
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     out[j] = g[j] * ((j & 1) ? pe : po);
@@ -349,15 +349,16 @@ __device__ __forceinline__ int cell_of_logical(int L, const FMesh &M) {
   return i1 + N1 * (i2 + N2 * i3);
 }
 
-template <int N>
+template <int N, typename T>
 __global__ __launch_bounds__(FCfg<N>::THREADS)
 __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_kernel(
-    const double *__restrict__ x, double *__restrict__ y, FMesh M) {
+    const T *__restrict__ x, T *__restrict__ y, FMesh M) {
   using C = FCfg<N>;
   using TO = TabOff<N>;
   constexpr int NN = C::NN, PS = C::PS, NNN = N * N * N;
   constexpr int H2 = N / 2;
-  __shared__ double lds[C::CPB * C::REGION];
+  __shared__ T lds[C::CPB * C::EXCH];
+  __shared__ double fcs[C::CPB * 6 * C::FCW];  // face constants stay FP64
 
   const int tid = threadIdx.x;
   const int cl = tid / C::LANES;
@@ -369,9 +370,9 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
   const int L = lblock * C::CPB + (slot ? cl : 0);
   const bool active = slot && L < M.ncells;
   const int cell = active ? cell_of_logical(L, M) : 0;
-  double *R = lds + (slot ? cl : 0) * C::REGION;
-  double *RFC = R + C::EXCH;  // per-cell face constants
-  const CT<N> tab0{0};
+  T *R = lds + (slot ? cl : 0) * C::EXCH;
+  double *RFC = fcs + (slot ? cl : 0) * 6 * C::FCW;  // per-cell face constants
+  const CT<N, T> tab0{0};
 
   FaceGeo G;
   G.i0 = cell % M.ncell[0];
@@ -411,14 +412,14 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
   const int w1 = beta * PS + alpha;
   {
     const cptr tb = fresh(tab0);
-    double X[N];
-    const double *xp = x + size_t(cell) * NNN + NN * beta + N * alpha;
+    T X[N];
+    const T *xp = x + size_t(cell) * NNN + NN * beta + N * alpha;
 #pragma unroll
     for (int t = 0; t < N; ++t) X[t] = xp[t];
-    double Tv[N], Td[N];
+    T Tv[N], Td[N];
     eo_mv<N, false>(tb + TO::V, X, Tv);
     eo_mv<N, true>(tb + TO::D, X, Td);
-    double u1, u0, d1, d0;
+    T u1, u0, d1, d0;
     tr_val<N>(tb + TO::E1, X, u1, u0);
     tr_der<N>(tb + TO::F1, X, d1, d0);
     if (slot) {
@@ -440,9 +441,9 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
     const int ia = a == 0 ? G.i0 : (a == 1 ? G.i1 : G.i2);
     const bool in = e ? (ia + 1 < M.ncell[a]) : (ia > 0);
     const int cst = (a == 0) ? 1 : (a == 1) ? M.ncell[0] : M.ncell[0] * M.ncell[1];
-    double v[N];
+    T v[N];
     if (in) {
-      const double *xn = x + size_t(e ? cell + cst : cell - cst) * NNN;
+      const T *xn = x + size_t(e ? cell + cst : cell - cst) * NNN;
       const int base = (a == 0) ? (N * alpha + NN * beta)
                        : (a == 1) ? (alpha + NN * beta) : (alpha + N * beta);
       const int st = (a == 0) ? 1 : (a == 1) ? N : NN;
@@ -450,10 +451,10 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
       for (int t = 0; t < N; ++t) v[t] = xn[base + st * t];
     } else {
 #pragma unroll
-      for (int t = 0; t < N; ++t) v[t] = 0.0;
+      for (int t = 0; t < N; ++t) v[t] = T(0);
     }
     // neighbour trace at its reference coordinate 1 - e
-    double u1, u0, d1, d0;
+    T u1, u0, d1, d0;
     tr_val<N>(tb + TO::E1, v, u1, u0);
     tr_der<N>(tb + TO::F1, v, d1, d0);
     const int fid = (a == 0) ? (4 * e + 2) : (a == 1 ? 8 + 2 * e : 12 + 2 * e);
@@ -464,11 +465,11 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
   }
   __syncthreads();
   // volume step B: lane (q1, j3) = (alpha, beta)
-  double vv[N], dv[N], vd[N];
-  double yS[2], yA[2];  // own y-face value trace and flux part on (q1, j3)
+  T vv[N], dv[N], vd[N];
+  T yS[2], yA[2];  // own y-face value trace and flux part on (q1, j3)
   {
     const cptr tb = fresh(tab0);
-    double P[N], Q[N];
+    T P[N], Q[N];
 #pragma unroll
     for (int t = 0; t < N; ++t) {
       P[t] = R[B_OFF + p * PS + t];
@@ -477,15 +478,15 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
     eo_mv<N, false>(tb + TO::V, P, vv);
     eo_mv<N, false>(tb + TO::V, Q, dv);
     eo_mv<N, true>(tb + TO::D, P, vd);
-    double u1, u0, g1, g0, d1, d0;
+    T u1, u0, g1, g0, d1, d0;
     tr_val<N>(tb + TO::E1, P, u1, u0);
     tr_val<N>(tb + TO::E1, Q, g1, g0);
     tr_der<N>(tb + TO::F1, P, d1, d0);
     const FC F0 = load_fc(RFC, 2), F1 = load_fc(RFC, 3);
     yS[0] = u0;
     yS[1] = u1;
-    yA[0] = F0.cTb * g0 + F0.cTa * d0;
-    yA[1] = F1.cTb * g1 + F1.cTa * d1;
+    yA[0] = T(F0.cTb) * g0 + T(F0.cTa) * d0;
+    yA[1] = T(F1.cTb) * g1 + T(F1.cTa) * d1;
   }
   // First tangential sweep of the face traces.  Tasks:
   //   t <  2N : x face e = t/N, pencil j3 = t%N  -> Sv_o, Sv_n, A1 (own + nb flux part)
@@ -495,7 +496,7 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
   // the first tangential axis (G the modal derivative).
   constexpr int NT1 = 6 * N;
   constexpr int NR1 = (NT1 + C::LANES - 1) / C::LANES;
-  double S1[NR1][3][N];
+  T S1[NR1][3][N];
 #pragma unroll
   for (int r = 0; r < NR1; ++r) {
     const int task = p + r * C::LANES;
@@ -504,26 +505,26 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
       const int kind = task / (2 * N), e = (task / N) & 1, pi = task % N;
       const FC F = load_fc(RFC, 2 * kind + e);
       const int fid = (kind == 0) ? (4 * e + 2) : (kind == 1 ? 8 + 2 * e : 12 + 2 * e);
-      double U[N], Ub[N], Dc[N];
+      T U[N], Ub[N], Dc[N];
 #pragma unroll
       for (int t = 0; t < N; ++t) {
         U[t] = R[F1_OFF + fid * N * PS + pi * PS + t];
-        Ub[t] = F.cNb * U[t];
-        Dc[t] = F.cNa * R[F1_OFF + (fid + 1) * N * PS + pi * PS + t];
+        Ub[t] = T(F.cNb) * U[t];
+        Dc[t] = T(F.cNa) * R[F1_OFF + (fid + 1) * N * PS + pi * PS + t];
       }
       eo_mv<N, false>(tb + TO::V, U, S1[r][1]);  // Sv_n
       if (kind == 0) {
-        double Uo[N];
+        T Uo[N];
 #pragma unroll
         for (int t = 0; t < N; ++t) {
           Uo[t] = R[F1_OFF + (4 * e) * N * PS + pi * PS + t];
-          const double Do = R[F1_OFF + (4 * e + 1) * N * PS + pi * PS + t];
-          Ub[t] = fma(F.cTb, Uo[t], Ub[t]);
-          Dc[t] = fma(F.cTa, Do, Dc[t]);
+          const T Do = R[F1_OFF + (4 * e + 1) * N * PS + pi * PS + t];
+          Ub[t] = fma(T(F.cTb), Uo[t], Ub[t]);
+          Dc[t] = fma(T(F.cTa), Do, Dc[t]);
         }
         eo_mv<N, false>(tb + TO::V, Uo, S1[r][0]);  // Sv_o
       }
-      double GU[N];
+      T GU[N];
       gmod<N>(tb + TO::G, Ub, GU);
 #pragma unroll
       for (int t = 0; t < N; ++t) Dc[t] += GU[t];
@@ -560,7 +561,7 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
     }
   }
   __syncthreads();
-  double Pc[N], Qc[N], Sc[N];  // C-stage input pencils of lane (q1, q2)
+  T Pc[N], Qc[N], Sc[N];  // C-stage input pencils of lane (q1, q2)
 #pragma unroll
   for (int t = 0; t < N; ++t) {
     Pc[t] = R[C_OFF + p * PS + t];
@@ -571,7 +572,7 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
   // averaged normal flux at (q1, all q2); c = axis 1
   constexpr int NT2Z = 2 * N;
   constexpr int NR2Z = (NT2Z + C::LANES - 1) / C::LANES;
-  double Zn[NR2Z][2][N];
+  T Zn[NR2Z][2][N];
 #pragma unroll
   for (int r = 0; r < NR2Z; ++r) {
     const int task = p + r * C::LANES;
@@ -579,7 +580,7 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
       const cptr tb = fresh(tab0);
       const int e = task / N, pi = task % N;  // pi = q1
       const FC F = load_fc(RFC, 4 + e);
-      double Sv[N], A1[N], GS[N];
+      T Sv[N], A1[N], GS[N];
 #pragma unroll
       for (int t = 0; t < N; ++t) {
         Sv[t] = R[Z2_OFF + (2 * e + 0) * N * PS + pi * PS + t];
@@ -587,7 +588,7 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
       }
       gmod<N>(tb + TO::G, Sv, GS);
 #pragma unroll
-      for (int t = 0; t < N; ++t) A1[t] = fma(F.cNc, GS[t], A1[t]);
+      for (int t = 0; t < N; ++t) A1[t] = fma(T(F.cNc), GS[t], A1[t]);
       eo_mv<N, false>(tb + TO::V, Sv, Zn[r][0]);
       eo_mv<N, false>(tb + TO::V, A1, Zn[r][1]);
     }
@@ -640,24 +641,25 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
   __syncthreads();
   // volume pointwise flux (eq. (gauss_points)) streamed over the point pairs
   // (q3, N-1-q3) straight into the C'-stage accumulators (eq. (evalblf))
-  double Wvv[N], Wdv[N], Wvd[N];
+  T Wvv[N], Wdv[N], Wvd[N];
 #pragma unroll
-  for (int j = 0; j < N; ++j) Wvv[j] = Wdv[j] = Wvd[j] = 0.0;
+  for (int j = 0; j < N; ++j) Wvv[j] = Wdv[j] = Wvd[j] = T(0);
   {
     const cptr tb = fresh(tab0);
     const cptr V = tb + TO::V, D = tb + TO::D, Wt = tb + TO::W;
     const double vol = G.h0 * G.h1 * G.h2;
-    const double wab = M.w[alpha] * M.w[beta] * vol;
-    const double ih0 = 1.0 / G.h0, ih1 = 1.0 / G.h1, ih2 = 1.0 / G.h2;
-    const double ihv[3] = {ih0, ih1, ih2};
+    const T wab = T(M.w[alpha] * M.w[beta] * vol);
+    const double ihd[3] = {1.0 / G.h0, 1.0 / G.h1, 1.0 / G.h2};
+    const T ih0 = T(ihd[0]), ih1 = T(ihd[1]), ih2 = T(ihd[2]);
+    const T cc = T(M.c);
     // Kh[r][s] = kappa K_rs / (h_r h_s): D acting on reference derivatives
-    double Kh[9];
+    T Kh[9];
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
-      for (int s2 = 0; s2 < 3; ++s2) Kh[3 * r + s2] = G.kap * M.K[3 * r + s2] * ihv[r] * ihv[s2];
+      for (int s2 = 0; s2 < 3; ++s2) Kh[3 * r + s2] = T(G.kap * M.K[3 * r + s2] * ihd[r] * ihd[s2]);
     // b_r / h_r: per-lane constant unless b_r varies along axis 3
-    double bh[3];
+    T bh[3];
     const double *bzt[3];
     bool bz[3];
 #pragma unroll
@@ -666,22 +668,21 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
       bz[r] = (ax == 2);
       const int ia = ax == 0 ? G.i0 : (ax == 1 ? G.i1 : G.i2);
       const int qa = (ax == 0) ? alpha : beta;
-      bh[r] = bz[r] ? 0.0 : M.bvol[r][ia * N + qa] * ihv[r];
+      bh[r] = bz[r] ? T(0) : T(M.bvol[r][ia * N + qa] * ihd[r]);
       bzt[r] = M.bvol[r] + G.i2 * N;
     }
-    auto flux = [&](double u, double g0, double g1, double g2, int q3, double W, double &x0,
-                    double &x1, double &x2, double &x3) {
-      const double b0 = bz[0] ? bzt[0][q3] * ih0 : bh[0];
-      const double b1 = bz[1] ? bzt[1][q3] * ih1 : bh[1];
-      const double b2 = bz[2] ? bzt[2][q3] * ih2 : bh[2];
-      x0 = W * M.c * u;
+    auto flux = [&](T u, T g0, T g1, T g2, int q3, T W, T &x0, T &x1, T &x2, T &x3) {
+      const T b0 = bz[0] ? T(bzt[0][q3]) * ih0 : bh[0];
+      const T b1 = bz[1] ? T(bzt[1][q3]) * ih1 : bh[1];
+      const T b2 = bz[2] ? T(bzt[2][q3]) * ih2 : bh[2];
+      x0 = W * cc * u;
       x1 = W * (Kh[0] * g0 + Kh[1] * g1 + Kh[2] * g2 - b0 * u);
       x2 = W * (Kh[3] * g0 + Kh[4] * g1 + Kh[5] * g2 - b1 * u);
       x3 = W * (Kh[6] * g0 + Kh[7] * g1 + Kh[8] * g2 - b2 * u);
     };
 #pragma unroll
     for (int h = 0; h < H2; ++h) {
-      double Eu = 0, Ou = 0, E0 = 0, O0 = 0, E1 = 0, O1 = 0, E2 = 0, O2 = 0;
+      T Eu = 0, Ou = 0, E0 = 0, O0 = 0, E1 = 0, O1 = 0, E2 = 0, O2 = 0;
 #pragma unroll
       for (int t = 0; t < N; t += 2) {
         Eu = fma(V[h * N + t], Pc[t], Eu);
@@ -696,12 +697,12 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
         O1 = fma(V[h * N + t], Sc[t], O1);
         O2 = fma(D[h * N + t], Pc[t], O2);
       }
-      const double W = wab * Wt[h];
-      double a0, a1, a2, a3, m0, m1, m2, m3;
+      const T W = wab * Wt[h];
+      T a0, a1, a2, a3, m0, m1, m2, m3;
       flux(Eu + Ou, E0 + O0, E1 + O1, E2 + O2, h, W, a0, a1, a2, a3);
       flux(Eu - Ou, E0 - O0, E1 - O1, O2 - E2, N - 1 - h, W, m0, m1, m2, m3);
-      const double s0 = a0 + m0, d0 = a0 - m0, s1 = a1 + m1, d1 = a1 - m1;
-      const double s2 = a2 + m2, d2 = a2 - m2, s3 = a3 + m3, d3 = a3 - m3;
+      const T s0 = a0 + m0, d0 = a0 - m0, s1 = a1 + m1, d1 = a1 - m1;
+      const T s2 = a2 + m2, d2 = a2 - m2, s3 = a3 + m3, d3 = a3 - m3;
 #pragma unroll
       for (int j = 0; j < N; ++j) {
         const bool ev = (j & 1) == 0;
@@ -713,7 +714,7 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
     }
     if (N & 1) {
       constexpr int m = N / 2;
-      double u = 0, g0 = 0, g1 = 0, g2 = 0;
+      T u = 0, g0 = 0, g1 = 0, g2 = 0;
 #pragma unroll
       for (int t = 0; t < N; t += 2) {
         u = fma(V[m * N + t], Pc[t], u);
@@ -722,7 +723,7 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
       }
 #pragma unroll
       for (int t = 1; t < N; t += 2) g2 = fma(D[m * N + t], Pc[t], g2);
-      double x0, x1, x2, x3;
+      T x0, x1, x2, x3;
       flux(u, g0, g1, g2, m, wab * Wt[m], x0, x1, x2, x3);
 #pragma unroll
       for (int j = 0; j < N; ++j) {
@@ -742,7 +743,7 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
   {
     const cptr tb = fresh(tab0);
     const double wab = M.w[alpha] * M.w[beta] * G.h0 * G.h1;
-    double u[2], gb[2], gc[2], ga[2];
+    T u[2], gb[2], gc[2], ga[2];
     tr_val<N>(tb + TO::E1, Pc, u[1], u[0]);
     tr_val<N>(tb + TO::E1, Qc, gb[1], gb[0]);
     tr_val<N>(tb + TO::E1, Sc, gc[1], gc[0]);
@@ -751,19 +752,19 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
       const FC F = load_fc(RFC, 4 + e);
-      const double avg = F.cTb * gb[e] + F.cTc * gc[e] + F.cTa * ga[e] +
-                         R[ZN_OFF + (2 * e + 1) * NN + p];
+      const double avg = F.cTb * double(gb[e]) + F.cTc * double(gc[e]) + F.cTa * double(ga[e]) +
+                         double(R[ZN_OFF + (2 * e + 1) * NN + p]);
       const double un = R[ZN_OFF + (2 * e + 0) * NN + p];
       const double ba = face_b(M, G, N, 2, e, alpha, beta);
       double Z;
-      face_flux(F, u[e], un, avg, ba, wab, RV[e], Z);
+      face_flux(F, double(u[e]), un, avg, ba, wab, RV[e], Z);
       Za[e] = F.cTa * Z;
       Zb[e] = F.cTb * Z;
       Zc[e] = F.cTc * Z;
     }
-    tr_acc<N>(tb + TO::E1, tb + TO::F1, RV[1], RV[0], Za[1], Za[0], Wvv);
-    tr_acc_v<N>(tb + TO::E1, Zb[1], Zb[0], Wdv);
-    tr_acc_v<N>(tb + TO::E1, Zc[1], Zc[0], Wvd);
+    tr_acc<N>(tb + TO::E1, tb + TO::F1, T(RV[1]), T(RV[0]), T(Za[1]), T(Za[0]), Wvv);
+    tr_acc_v<N>(tb + TO::E1, T(Zb[1]), T(Zb[0]), Wdv);
+    tr_acc_v<N>(tb + TO::E1, T(Zc[1]), T(Zc[0]), Wvd);
   }
 
   // C'-stage results as B'-pencils (q1 + N j3) along q2, beyond the x/y
@@ -785,17 +786,18 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
   // transposed-sweep results Q1 = V^T RV + cTc D^T Z and VZ = V^T Z over j3
   constexpr int NT2 = 4 * N;
   constexpr int NR2 = (NT2 + C::LANES - 1) / C::LANES;
-  double Qf[NR2][2][N];
+  T Qf[NR2][2][N];
 #pragma unroll
   for (int r = 0; r < NR2; ++r) {
     const int task = p + r * C::LANES;
     if (task < NT2) {
       const cptr tb = fresh(tab0);
-      const cptr V = tb + TO::V, D = tb + TO::D, Wt = tb + TO::W;
+      const cptr V = tb + TO::V;
+      const CT<N, double> Wt{TO::W};  // FP64 weights for the FP64 face flux
       const int fp = task / N, pi = task % N;  // pi = first tangential q (q2 for x, q1 for y)
       const int a = fp >> 1, e = fp & 1;
       const FC F = load_fc(RFC, fp);
-      double So[N], Sn[N], A1[N], A2[N];
+      T So[N], Sn[N], A1[N], A2[N];
       if (a == 0) {
 #pragma unroll
         for (int t = 0; t < N; ++t) {
@@ -814,21 +816,21 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
       }
       // averaged normal flux pencil: A1 + G (cTc Sv_o + cNc Sv_n)
 #pragma unroll
-      for (int t = 0; t < N; ++t) A2[t] = F.cTc * So[t] + F.cNc * Sn[t];
+      for (int t = 0; t < N; ++t) A2[t] = T(F.cTc) * So[t] + T(F.cNc) * Sn[t];
       {
-        double GA[N];
+        T GA[N];
         gmod<N>(tb + TO::G, A2, GA);
 #pragma unroll
         for (int t = 0; t < N; ++t) A1[t] += GA[t];
       }
       const double hb = a == 0 ? G.h1 : G.h0;
       const double wp = M.w[pi] * hb * G.h2;
-      double VR[N], VZ[N];
+      T VR[N], VZ[N];
 #pragma unroll
-      for (int j = 0; j < N; ++j) VR[j] = VZ[j] = 0.0;
+      for (int j = 0; j < N; ++j) VR[j] = VZ[j] = T(0);
 #pragma unroll
       for (int h = 0; h < H2; ++h) {
-        double Eo = 0, Oo = 0, En = 0, On = 0, Ea = 0, Oa = 0;
+        T Eo = 0, Oo = 0, En = 0, On = 0, Ea = 0, Oa = 0;
 #pragma unroll
         for (int t = 0; t < N; t += 2) {
           Eo = fma(V[h * N + t], So[t], Eo);
@@ -843,9 +845,11 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
         }
         const double W = wp * Wt[h];
         double RVa, Za, RVm, Zm;
-        face_flux(F, Eo + Oo, En + On, Ea + Oa, face_b(M, G, N, a, e, pi, h), W, RVa, Za);
-        face_flux(F, Eo - Oo, En - On, Ea - Oa, face_b(M, G, N, a, e, pi, N - 1 - h), W, RVm, Zm);
-        const double sr = RVa + RVm, dr = RVa - RVm, sz = Za + Zm, dz = Za - Zm;
+        face_flux(F, double(Eo + Oo), double(En + On), double(Ea + Oa), face_b(M, G, N, a, e, pi, h), W,
+                  RVa, Za);
+        face_flux(F, double(Eo - Oo), double(En - On), double(Ea - Oa), face_b(M, G, N, a, e, pi, N - 1 - h),
+                  W, RVm, Zm);
+        const T sr = T(RVa + RVm), dr = T(RVa - RVm), sz = T(Za + Zm), dz = T(Za - Zm);
 #pragma unroll
         for (int j = 0; j < N; ++j) {
           const bool ev = (j & 1) == 0;
@@ -855,7 +859,7 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
       }
       if (N & 1) {
         constexpr int m = N / 2;
-        double uo = 0, un = 0, av = 0;
+        T uo = 0, un = 0, av = 0;
 #pragma unroll
         for (int t = 0; t < N; t += 2) {
           uo = fma(V[m * N + t], So[t], uo);
@@ -863,19 +867,19 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
           av = fma(V[m * N + t], A1[t], av);
         }
         double RVm, Zm;
-        face_flux(F, uo, un, av, face_b(M, G, N, a, e, pi, m), wp * Wt[m], RVm, Zm);
+        face_flux(F, double(uo), double(un), double(av), face_b(M, G, N, a, e, pi, m), wp * Wt[m], RVm, Zm);
 #pragma unroll
         for (int j = 0; j < N; j += 2) {
-          VR[j] = fma(V[m * N + j], RVm, VR[j]);
-          VZ[j] = fma(V[m * N + j], Zm, VZ[j]);
+          VR[j] = fma(V[m * N + j], T(RVm), VR[j]);
+          VZ[j] = fma(V[m * N + j], T(Zm), VZ[j]);
         }
       }
       // D^T Z = G^T (V^T Z)
-      double DZ[N];
+      T DZ[N];
       gmodT<N>(tb + TO::G, VZ, DZ);
 #pragma unroll
       for (int j = 0; j < N; ++j) {
-        Qf[r][0][j] = fma(F.cTc, DZ[j], VR[j]);
+        Qf[r][0][j] = fma(T(F.cTc), DZ[j], VR[j]);
         Qf[r][1][j] = VZ[j];
       }
     }
@@ -913,10 +917,10 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
   }
   __syncthreads();
   // volume step B': lane (q1, j3) = (alpha, beta), plus the y-face merge
-  double Vv[N], Vd[N];
+  T Vv[N], Vd[N];
   {
     const cptr tb = fresh(tab0);
-    double P[N], Q[N], S[N];
+    T P[N], Q[N], S[N];
 #pragma unroll
     for (int t = 0; t < N; ++t) {
       const int a = PL<N>::at(p, t);
@@ -928,15 +932,15 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
     eo_mtv<N, true, true>(tb + TO::D, S, Vv);
     eo_mtv<N, false, false>(tb + TO::V, Q, Vd);
     const FC F0 = load_fc(RFC, 2), F1 = load_fc(RFC, 3);
-    const double q0 = R[Y3_OFF + 0 * NN + p], z0 = R[Y3_OFF + 1 * NN + p];
-    const double q1 = R[Y3_OFF + 2 * NN + p], z1 = R[Y3_OFF + 3 * NN + p];
-    tr_acc<N>(tb + TO::E1, tb + TO::F1, q1, q0, F1.cTa * z1, F0.cTa * z0, Vv);
-    tr_acc_v<N>(tb + TO::E1, F1.cTb * z1, F0.cTb * z0, Vd);
+    const T q0 = R[Y3_OFF + 0 * NN + p], z0 = R[Y3_OFF + 1 * NN + p];
+    const T q1 = R[Y3_OFF + 2 * NN + p], z1 = R[Y3_OFF + 3 * NN + p];
+    tr_acc<N>(tb + TO::E1, tb + TO::F1, q1, q0, T(F1.cTa) * z1, T(F0.cTa) * z0, Vv);
+    tr_acc_v<N>(tb + TO::E1, T(F1.cTb) * z1, T(F0.cTb) * z0, Vd);
   }
   // x-face tasks: transposed sweep along q2 -> (R_v, R_d) on (j2, j3)
   constexpr int NT3 = 2 * N;
   constexpr int NR3 = (NT3 + C::LANES - 1) / C::LANES;
-  double Rx[NR3][2][N];
+  T Rx[NR3][2][N];
 #pragma unroll
   for (int r = 0; r < NR3; ++r) {
     const int task = p + r * C::LANES;
@@ -944,7 +948,7 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
       const cptr tb = fresh(tab0);
       const int e = task / N, pi = task % N;  // pi = j3
       const FC F = load_fc(RFC, e);
-      double Q1[N], VZ[N], VV[N], GV[N];
+      T Q1[N], VZ[N], VV[N], GV[N];
 #pragma unroll
       for (int t = 0; t < N; ++t) {
         Q1[t] = R[X3_OFF + (2 * e + 0) * N * PS + pi * PS + t];
@@ -956,8 +960,8 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
       gmodT<N>(tb + TO::G, VV, GV);
 #pragma unroll
       for (int j = 0; j < N; ++j) {
-        Rx[r][0][j] = fma(F.cTb, GV[j], Rx[r][0][j]);
-        Rx[r][1][j] = F.cTa * VV[j];
+        Rx[r][0][j] = fma(T(F.cTb), GV[j], Rx[r][0][j]);
+        Rx[r][1][j] = T(F.cTa) * VV[j];
       }
     }
   }
@@ -990,7 +994,7 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
   // volume step A': lane (j2, j3) = (alpha, beta), plus the x-face merge
   if (active) {
     const cptr tb = fresh(tab0);
-    double P[N], Q[N], Yv[N];
+    T P[N], Q[N], Yv[N];
 #pragma unroll
     for (int t = 0; t < N; ++t) {
       P[t] = R[AP_OFF + p * PS + t];
@@ -998,17 +1002,17 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
     }
     eo_mtv<N, false, false>(tb + TO::V, P, Yv);
     eo_mtv<N, true, true>(tb + TO::D, Q, Yv);
-    const double rv0 = R[X4_OFF + 0 * NN + p], rd0 = R[X4_OFF + 1 * NN + p];
-    const double rv1 = R[X4_OFF + 2 * NN + p], rd1 = R[X4_OFF + 3 * NN + p];
+    const T rv0 = R[X4_OFF + 0 * NN + p], rd0 = R[X4_OFF + 1 * NN + p];
+    const T rv1 = R[X4_OFF + 2 * NN + p], rd1 = R[X4_OFF + 3 * NN + p];
     tr_acc<N>(tb + TO::E1, tb + TO::F1, rv1, rv0, rd1, rd0, Yv);
-    double *yp = y + size_t(cell) * NNN + NN * beta + N * alpha;
+    T *yp = y + size_t(cell) * NNN + NN * beta + N * alpha;
 #pragma unroll
     for (int t = 0; t < N; ++t) yp[t] = Yv[t];
   }
 }
 
-template <int N>
-static hipError_t launch_fused_n(const dg_handle *h, const double *x, double *y, hipStream_t s) {
+template <int N, typename T>
+static hipError_t launch_fused_n(const dg_handle *h, const T *x, T *y, hipStream_t s) {
   using C = FCfg<N>;
   FMesh M;
   for (int a = 0; a < 3; ++a) {
@@ -1029,12 +1033,13 @@ static hipError_t launch_fused_n(const dg_handle *h, const double *x, double *y,
   M.tz = h->mesh.ncell[2] < 4 ? h->mesh.ncell[2] : 4;
   const int nblocks = int((h->ncells + C::CPB - 1) / C::CPB);
   M.groups = (nblocks + 7) / 8;
-  hipLaunchKernelGGL(apply_fused_kernel<N>, dim3(unsigned(8 * M.groups)), dim3(C::THREADS), 0, s,
+  hipLaunchKernelGGL((apply_fused_kernel<N, T>), dim3(unsigned(8 * M.groups)), dim3(C::THREADS), 0, s,
                      x, y, M);
   return hipGetLastError();
 }
 
-hipError_t launch_apply_fused_f64(const dg_handle *h, const double *x, double *y, hipStream_t s) {
+template <typename T>
+static hipError_t launch_fused(const dg_handle *h, const T *x, T *y, hipStream_t s) {
   switch (h->k + 1) {
     case 2: return launch_fused_n<2>(h, x, y, s);
     case 3: return launch_fused_n<3>(h, x, y, s);
@@ -1048,6 +1053,14 @@ hipError_t launch_apply_fused_f64(const dg_handle *h, const double *x, double *y
     case 11: return launch_fused_n<11>(h, x, y, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_apply_fused_f64(const dg_handle *h, const double *x, double *y, hipStream_t s) {
+  return launch_fused<double>(h, x, y, s);
+}
+
+hipError_t launch_apply_fused_f32(const dg_handle *h, const float *x, float *y, hipStream_t s) {
+  return launch_fused<float>(h, x, y, s);
 }
 
 }  // namespace dgmf

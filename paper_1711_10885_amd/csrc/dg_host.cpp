@@ -178,7 +178,7 @@ extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
         return set_error(DG_EINVAL, "dg_setup: kappa must be positive and finite");
   const int n = p->k + 1;
   if (ncells > (int64_t(1) << 31) / 2) return set_error(DG_EINVAL, "dg_setup: too many cells");
-  if (p->flags & ~(DG_WITH_FP32 | DG_WITH_BLOCK_JACOBI))
+  if (p->flags & ~DG_WITH_BLOCK_JACOBI)
     return set_error(DG_EINVAL, "dg_setup: unknown flag bits");
   if ((p->flags & DG_WITH_BLOCK_JACOBI) && n * n * n > kMaxBjBlock)
     return set_error(DG_EINVAL, "dg_setup: block Jacobi supports k <= 7");
@@ -311,5 +311,20 @@ extern "C" dg_status dg_precond_apply(dg_handle *h, int32_t precond, const doubl
     return set_error(DG_EINVAL, "dg_precond_apply: unknown preconditioner");
   }
   if (e != hipSuccess) return hip_error(e, "dg_precond_apply: kernel launch");
+  return DG_OK;
+}
+
+extern "C" dg_status dg_apply_f32(dg_handle *h, const float *x, float *y, void *stream) {
+  if (!h) return set_error(DG_EINVAL, "dg_apply_f32: handle is NULL");
+  if (!x || !y) return set_error(DG_EINVAL, "dg_apply_f32: x or y is NULL");
+  if (overlaps(x, y, size_t(h->ndof) * sizeof(float)))
+    return set_error(DG_EINVAL, "dg_apply_f32: x and y overlap");
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != h->device) {
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_error(e, "dg_apply_f32: hipSetDevice");
+  }
+  hipError_t e = launch_apply_fused_f32(h, x, y, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_error(e, "dg_apply_f32: kernel launch");
   return DG_OK;
 }

@@ -66,6 +66,7 @@ dg_status hip_error(hipError_t e, const char *what);
 // Kernel launchers, dispatching on k.
 hipError_t launch_apply_ref_f64(const dg_handle *h, const double *x, double *y, hipStream_t s);
 hipError_t launch_apply_fused_f64(const dg_handle *h, const double *x, double *y, hipStream_t s);
+hipError_t launch_apply_fused_f32(const dg_handle *h, const float *x, float *y, hipStream_t s);
 
 // Operator application through the kernel the handle selects.
 hipError_t apply_f64(const dg_handle *h, const double *x, double *y, hipStream_t s);

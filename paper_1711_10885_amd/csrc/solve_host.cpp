@@ -5,6 +5,7 @@
 // (the Hessenberg column and the Givens rotations live on the host).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <string>
@@ -75,7 +76,9 @@ extern "C" dg_status dg_solve(dg_handle *h, const double *f, double *u, double t
   if (opt.restart < 1 || opt.restart > kMaxBasis - 1)
     return set_error(DG_EINVAL, "dg_solve: restart must be in 1..63");
   if (opt.maxit < 1) return set_error(DG_EINVAL, "dg_solve: maxit must be >= 1");
-  if (opt.method != DG_GMRES64) return set_error(DG_EINVAL, "dg_solve: unknown method");
+  if (opt.method != DG_GMRES64 && opt.method != DG_GMRES_IR) return set_error(DG_EINVAL, "dg_solve: unknown method");
+  if (opt.method == DG_GMRES_IR && !(opt.inner_tol > 0.0 && opt.inner_tol < 1.0))
+    return set_error(DG_EINVAL, "dg_solve: inner_tol must be in (0, 1)");
   if (opt.precond != DG_PREC_NONE && opt.precond != DG_PREC_BLOCK_JACOBI)
     return set_error(DG_EINVAL, "dg_solve: unknown preconditioner");
   if (opt.precond == DG_PREC_BLOCK_JACOBI && !h->bj)
@@ -90,15 +93,21 @@ extern "C" dg_status dg_solve(dg_handle *h, const double *f, double *u, double t
   const int m = opt.restart;
 
   const bool have_prec = opt.precond != DG_PREC_NONE;
-  // workspace: V (m+1) n | w n | Z n (fixed preconditioner)
-  const size_t vb = align256(sizeof(double) * n * (m + 1)), wb = align256(sizeof(double) * n);
-  dg_status ds = ensure_workspace(h, vb + wb + (have_prec ? wb : 0));
+  const bool ir = opt.method == DG_GMRES_IR;
+  // workspace, FP64 GMRES:  V (m+1) n | w n | Z n (fixed preconditioner)
+  //            GMRES-IR:    r n (FP64) | V (m+1) n | w n | Z n | d n | r n (FP32)
+  const size_t es = ir ? sizeof(float) : sizeof(double);
+  const size_t vb = align256(es * n * (m + 1)), wb = align256(es * n), rb = ir ? align256(sizeof(double) * n) : 0;
+  dg_status ds = ensure_workspace(h, rb + vb + wb + (have_prec ? wb : 0) + (ir ? 2 * wb : 0));
   if (ds != DG_OK) return ds;
   char *base = static_cast<char *>(h->ws);
+  double *r64 = ir ? reinterpret_cast<double *>(base) : nullptr;
   KrylovBufs K;
-  K.V = base;
-  K.w = base + vb;
-  K.Z = have_prec ? base + vb + wb : nullptr;
+  K.V = base + rb;
+  K.w = base + rb + vb;
+  K.Z = have_prec ? base + rb + vb + wb : nullptr;
+  float *d32 = ir ? reinterpret_cast<float *>(base + rb + vb + wb + (have_prec ? wb : 0)) : nullptr;
+  float *r32 = ir ? reinterpret_cast<float *>(base + rb + vb + 2 * wb + (have_prec ? wb : 0)) : nullptr;
   K.n = n;
   K.restart = m;
   K.flex = false;
@@ -122,19 +131,71 @@ extern "C" dg_status dg_solve(dg_handle *h, const double *f, double *u, double t
     }
     return DG_OK;
   }
-  auto op = [h, s](const double *x, double *y) { return apply_f64(h, x, y, s); };
-  auto prec = [h, s](const double *v, double *z) { return bj_apply<double, double>(h, v, z, s); };
   GmresOut go;
-  e = gmres<double>(K, op, prec, have_prec, f, u, fnorm, tol, opt.maxit, 0, un2 == 0.0, scratch, small, s, go);
-  if (e != hipSuccess) return hip_error(e, "dg_solve: GMRES");
-  stats.iters = go.iters;
-  stats.outer = go.cycles;
-  stats.applies = go.applies;
-  stats.rel_resid = go.rel;
+  if (!ir) {
+    auto op = [h, s](const double *x, double *y) { return apply_f64(h, x, y, s); };
+    auto prec = [h, s](const double *v, double *z) { return bj_apply<double, double>(h, v, z, s); };
+    e = gmres<double>(K, op, prec, have_prec, f, u, fnorm, tol, opt.maxit, 0, un2 == 0.0, scratch, small, s, go);
+    if (e != hipSuccess) return hip_error(e, "dg_solve: GMRES");
+    stats.iters = go.iters;
+    stats.outer = go.cycles;
+    stats.applies = go.applies;
+    stats.rel_resid = go.rel;
+  } else {
+    // GMRES-IR: FP64 residual and update, FP32 correction by one inner cycle
+    auto op = [h, s](const float *x, float *y) { return launch_apply_fused_f32(h, x, y, s); };
+    auto prec = [h, s](const float *v, float *z) { return bj_apply<float, float>(h, v, z, s); };
+    go = GmresOut();
+    bool first = true;
+    for (;;) {
+      double rn2 = 0.0;
+      if (first && un2 == 0.0) {
+        e = kr_scale<double, double>(f, r64, 1.0, n, s);
+        rn2 = fn2;
+      } else {
+        e = apply_f64(h, u, r64, s);
+        ++stats.applies;
+        if (e == hipSuccess) e = kr_residual<double>(f, r64, n, scratch, small, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(&rn2, small, sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+      }
+      first = false;
+      if (e != hipSuccess) return hip_error(e, "dg_solve: IR residual");
+      const double rn = std::sqrt(rn2);
+      if (!std::isfinite(rn)) {
+        go.nan = true;
+        break;
+      }
+      stats.rel_resid = rn / fnorm;
+      if (stats.rel_resid <= tol) {
+        go.converged = true;
+        break;
+      }
+      if (stats.iters >= opt.maxit) break;
+      ++stats.outer;
+      // inner problem A d = r / ||r|| in FP32, zero initial guess
+      e = kr_scale<double, float>(r64, r32, 1.0 / rn, n, s);
+      if (e == hipSuccess) e = kr_scale<float, float>(r32, d32, 0.0, n, s);
+      if (e != hipSuccess) return hip_error(e, "dg_solve: IR scaling");
+      GmresOut gi;
+      e = gmres<float>(K, op, prec, have_prec, r32, d32, 1.0, opt.inner_tol,
+                       std::min(m, opt.maxit - stats.iters), 1, true, scratch, small, s, gi);
+      if (e != hipSuccess) return hip_error(e, "dg_solve: inner GMRES");
+      stats.iters += gi.iters;
+      stats.applies_f32 += gi.applies;
+      if (gi.nan) {
+        go.nan = true;
+        break;
+      }
+      // u += ||r|| d
+      if ((e = kr_axpy<float, double>(d32, u, rn, n, s)) != hipSuccess) return hip_error(e, "dg_solve: IR update");
+    }
+  }
   stats.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (st) *st = stats;
   if (go.nan) return set_error(DG_ENAN, "dg_solve: non-finite value in the iteration");
   if (!go.converged)
-    return set_error(DG_ENOTCONV, "dg_solve: maxit reached at relative residual " + std::to_string(go.rel));
+    return set_error(DG_ENOTCONV,
+                     "dg_solve: maxit reached at relative residual " + std::to_string(stats.rel_resid));
   return DG_OK;
 }
