@@ -146,9 +146,11 @@ dg_status dg_set_kernel(dg_handle *h, int32_t variant);
 
 #define DG_PREC_NONE 0
 #define DG_PREC_BLOCK_JACOBI 1 /* inverse cell blocks A_TT (DG_WITH_BLOCK_JACOBI) */
-#define DG_PREC_LEARNED 2      /* cell-patch MLP (DG_FGMRES only), falling back   *
-                                * to block Jacobi on a non-finite output or       *
-                                * stagnation when the handle has it               */
+#define DG_PREC_LEARNED 2      /* block Jacobi plus the cell-patch network        *
+                                * (DG_FGMRES only); falls back to block Jacobi   *
+                                * alone on a non-finite value in a cycle or when *
+                                * the true residual falls by less than 10 % over *
+                                * ten cycles                                      */
 
 typedef struct {
   int32_t method;   /* DG_GMRES64 | DG_GMRES_IR | DG_FGMRES          (0)     */
@@ -179,12 +181,88 @@ typedef struct {
 dg_status dg_solve(dg_handle *h, const double *f, double *u, double tol, const dg_solve_opts *o,
                    dg_solve_stats *st, void *hip_stream);
 
-/* z := M^{-1} r for the handle's preconditioner precond: DG_PREC_BLOCK_JACOBI
- * (needs DG_WITH_BLOCK_JACOBI; z_T = A_TT^{-1} r_T with the FP32 inverse cell
- * blocks, FP64 accumulation).  r, z: device, ndof doubles, no overlap.
- * Asynchronous on hip_stream.  DG_EINVAL if the handle has no such
- * preconditioner. */
+/* z := M^{-1} r for the handle's preconditioner precond:
+ *   DG_PREC_BLOCK_JACOBI (needs DG_WITH_BLOCK_JACOBI): z_T = A_TT^{-1} r_T with
+ *     the FP32 inverse cell blocks, FP64 accumulation;
+ *   DG_PREC_LEARNED (needs block Jacobi and a trained or loaded network):
+ *     z_T = q_T + s_T N(p_T / s_T), q = BJ r, see dg_learned_train.
+ * r, z: device, ndof doubles, no overlap.  Asynchronous on hip_stream.
+ * DG_EINVAL if the handle has no such preconditioner. */
 dg_status dg_precond_apply(dg_handle *h, int32_t precond, const double *r, double *z, void *hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned cell-patch preconditioner (extension beyond the paper).
+ *
+ * With q = BJ r (q_T = A_TT^{-1} r_T), p_T is the patch of q: its
+ * coefficients on T and on the six face neighbours in the order T, -x, +x,
+ * -y, +y, -z, +z (zero where a neighbour is outside the domain), 7 (k+1)^3
+ * values; s_T = ||p_T||_2.  The network N is an MLP
+ * in = 7 (k+1)^3 -> 256 -> 256 -> out = (k+1)^3 with ReLU after the two
+ * hidden layers and biases on all three, run with BF16 weights and
+ * activations and FP32 accumulation (MFMA).  The preconditioner adds its
+ * correction to block Jacobi:  z_T = q_T + s_T N(p_T / s_T).
+ *
+ * Parameter layout (public, FP32, row-major, n = dg_learned_nparams):
+ *   W1 [256 x in] | b1 [256] | W2 [256 x 256] | b2 [256] | W3 [out x 256] | b3 [out]
+ * (layer l computes h_l = W_l h_{l-1} + b_l).  Supported for k <= 7.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t npairs; /* training patches                                    (100000) */
+  int32_t nrhs;   /* random exact solutions u* the pairs come from       (8)      */
+  int32_t epochs; /* passes over the training split (90 %)               (20)     */
+  int32_t batch;  /* minibatch rows, multiple of 64                      (1024)   */
+  float lr;       /* Adam step size (beta1 0.9, beta2 0.999, eps 1e-8)   (1e-3)   */
+  uint64_t seed;  /* seeds initialisation, data and shuffling            (6)      */
+  int32_t max_steps; /* largest GMRES step count j of the pairs         (0)      */
+} dg_learn_opts;
+
+typedef struct {
+  int32_t epochs, steps;   /* epochs run, optimiser steps taken                  */
+  double train_loss;       /* mean loss of the last epoch                        */
+  double val_loss;         /* validation loss (10 % split) after training        */
+  double val_loss_initial; /* validation loss of the initial network (= block    *
+                            * Jacobi, the last layer starts at zero)             */
+  double seconds;          /* total host wall time                               */
+  double seconds_data;     /* of which: generating the training pairs            */
+} dg_learn_stats;
+
+/* Train the network on the GPU (needs DG_WITH_BLOCK_JACOBI).
+ * Pairs come from the solver itself: for nrhs random exact solutions u*
+ * (seeded counter-based draws), f = A u*; block-Jacobi GMRES from u = 0
+ * stopped after j = 0, 1, 2, 4, ..., max_steps steps gives u_j (u_0 = 0), and
+ * the exact pair (r_j = f - A u_j, e_j = u* - u_j) is sampled at uniformly
+ * drawn cells, in equal numbers per (u*, j).  With q_j = BJ r_j: input
+ * p_T / s_T (patch of q_j), target (e_j - q_j)_T / s_T, loss: mean squared error
+ * over the out outputs of each row.  W1, W2 start He-normal, W3 and biases
+ * at zero (so the untrained preconditioner is block Jacobi).  Adam with FP32
+ * master weights.  opts == NULL selects the defaults; st may be NULL.
+ * Synchronises hip_stream.  DG_EINVAL, DG_ENOMEM, DG_EHIP, DG_ENAN (loss not
+ * finite). */
+dg_status dg_learned_train(dg_handle *h, const dg_learn_opts *opts, dg_learn_stats *st, void *hip_stream);
+
+/* Parameter count of the public layout above (-1 for NULL or k > 7). */
+int64_t dg_learned_nparams(const dg_handle *h);
+
+/* Load / read the FP32 parameters (host arrays of n = dg_learned_nparams
+ * values).  Loading resets the optimiser state and marks the network ready.
+ * Synchronous.  DG_EINVAL on a wrong n. */
+dg_status dg_learned_set_params(dg_handle *h, const float *params, int64_t n);
+dg_status dg_learned_get_params(dg_handle *h, float *params, int64_t n);
+
+/* The network on caller rows (for checks and inference outside the solver).
+ * X: device, B x in floats (rounded to BF16 on entry); T: device, B x out
+ * targets; B a positive multiple of 64.
+ *   dg_mlp_forward: Y (device, B x out floats) = N(X).
+ *   dg_mlp_grad:    gradients of the loss (mean over B x out squared errors)
+ *                   with respect to every parameter, in the public layout, to
+ *                   the host array grad (n values); *loss (host) if non-NULL.
+ *   dg_mlp_step:    forward, backward and one Adam step with step size lr.
+ * Synchronise hip_stream. */
+dg_status dg_mlp_forward(dg_handle *h, const float *X, int32_t B, float *Y, void *hip_stream);
+dg_status dg_mlp_grad(dg_handle *h, const float *X, const float *T, int32_t B, float *grad, int64_t n,
+                      double *loss, void *hip_stream);
+dg_status dg_mlp_step(dg_handle *h, const float *X, const float *T, int32_t B, float lr, double *loss,
+                      void *hip_stream);
 
 /* Number of degrees of freedom of the handle's space (or -1 for NULL). */
 int64_t dg_ndof(const dg_handle *h);

@@ -24,8 +24,10 @@ _STATUS = {DG_EINVAL: "DG_EINVAL", DG_ENOMEM: "DG_ENOMEM", DG_EHIP: "DG_EHIP",
            DG_ENOTCONV: "DG_ENOTCONV", DG_ENAN: "DG_ENAN"}
 
 # every symbol include/dg.h declares
-EXPORTS = ["dg_setup", "dg_apply", "dg_apply_f32", "dg_set_kernel", "dg_solve", "dg_precond_apply", "dg_ndof",
-           "dg_degree", "dg_last_error", "dg_destroy"]
+EXPORTS = ["dg_setup", "dg_apply", "dg_apply_f32", "dg_set_kernel", "dg_solve", "dg_precond_apply",
+           "dg_learned_train", "dg_learned_nparams", "dg_learned_set_params", "dg_learned_get_params",
+           "dg_mlp_forward", "dg_mlp_grad", "dg_mlp_step", "dg_ndof", "dg_degree", "dg_last_error",
+           "dg_destroy"]
 
 
 class DGError(RuntimeError):
@@ -64,6 +66,21 @@ class SolveStats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class LearnOpts(ctypes.Structure):
+    _fields_ = [("npairs", ctypes.c_int32), ("nrhs", ctypes.c_int32), ("epochs", ctypes.c_int32),
+                ("batch", ctypes.c_int32), ("lr", ctypes.c_float), ("seed", ctypes.c_uint64),
+                ("max_steps", ctypes.c_int32)]
+
+
+class LearnStats(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("steps", ctypes.c_int32), ("train_loss", ctypes.c_double),
+                ("val_loss", ctypes.c_double), ("val_loss_initial", ctypes.c_double),
+                ("seconds", ctypes.c_double), ("seconds_data", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -91,6 +108,22 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dg_solve.restype = ctypes.c_int
     lib.dg_precond_apply.argtypes = [H, ctypes.c_int32, vp, vp, vp]
     lib.dg_precond_apply.restype = ctypes.c_int
+    fp = ctypes.POINTER(ctypes.c_float)
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.dg_learned_train.argtypes = [H, ctypes.POINTER(LearnOpts), ctypes.POINTER(LearnStats), vp]
+    lib.dg_learned_train.restype = ctypes.c_int
+    lib.dg_learned_nparams.argtypes = [H]
+    lib.dg_learned_nparams.restype = ctypes.c_int64
+    lib.dg_learned_set_params.argtypes = [H, fp, ctypes.c_int64]
+    lib.dg_learned_set_params.restype = ctypes.c_int
+    lib.dg_learned_get_params.argtypes = [H, fp, ctypes.c_int64]
+    lib.dg_learned_get_params.restype = ctypes.c_int
+    lib.dg_mlp_forward.argtypes = [H, vp, ctypes.c_int32, vp, vp]
+    lib.dg_mlp_forward.restype = ctypes.c_int
+    lib.dg_mlp_grad.argtypes = [H, vp, vp, ctypes.c_int32, fp, ctypes.c_int64, dp, vp]
+    lib.dg_mlp_grad.restype = ctypes.c_int
+    lib.dg_mlp_step.argtypes = [H, vp, vp, ctypes.c_int32, ctypes.c_float, dp, vp]
+    lib.dg_mlp_step.restype = ctypes.c_int
     lib.dg_ndof.argtypes = [H]
     lib.dg_ndof.restype = ctypes.c_int64
     lib.dg_degree.argtypes = [H]
@@ -233,3 +266,54 @@ class DG:
         if check:
             _check(rc)
         return u, st.as_dict(), rc
+
+    # ---- learned preconditioner -------------------------------------------
+    def learned_nparams(self) -> int:
+        return int(load().dg_learned_nparams(self._h))
+
+    def learned_train(self, npairs=100000, nrhs=8, epochs=20, batch=1024, lr=1e-3, seed=6, max_steps=0,
+                      stream=None):
+        """Train the cell-patch network on the GPU; returns the stats dict."""
+        o = LearnOpts(int(npairs), int(nrhs), int(epochs), int(batch), float(lr), int(seed), int(max_steps))
+        st = LearnStats()
+        _check(load().dg_learned_train(self._h, ctypes.byref(o), ctypes.byref(st), _stream_ptr(stream)))
+        return st.as_dict()
+
+    def learned_set_params(self, params: np.ndarray):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        _check(load().dg_learned_set_params(self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                            int(p.size)))
+
+    def learned_get_params(self) -> np.ndarray:
+        n = self.learned_nparams()
+        p = np.empty(n, dtype=np.float32)
+        _check(load().dg_learned_get_params(self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), n))
+        return p
+
+    def mlp_forward(self, X, stream=None):
+        """Network outputs for rows X (float32 device tensor, B x in)."""
+        import torch
+        B = X.shape[0]
+        Y = torch.empty((B, self.k_nb()), dtype=torch.float32, device=X.device)
+        _check(load().dg_mlp_forward(self._h, ctypes.c_void_p(X.data_ptr()), int(B),
+                                     ctypes.c_void_p(Y.data_ptr()), _stream_ptr(stream)))
+        return Y
+
+    def mlp_grad(self, X, T, stream=None):
+        """(loss, gradient in the public parameter layout) for rows X, targets T."""
+        n = self.learned_nparams()
+        g = np.empty(n, dtype=np.float32)
+        loss = ctypes.c_double()
+        _check(load().dg_mlp_grad(self._h, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(T.data_ptr()),
+                                  int(X.shape[0]), g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), n,
+                                  ctypes.byref(loss), _stream_ptr(stream)))
+        return loss.value, g
+
+    def mlp_step(self, X, T, lr=1e-3, stream=None):
+        loss = ctypes.c_double()
+        _check(load().dg_mlp_step(self._h, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(T.data_ptr()),
+                                  int(X.shape[0]), float(lr), ctypes.byref(loss), _stream_ptr(stream)))
+        return loss.value
+
+    def k_nb(self) -> int:
+        return (self.k + 1) ** 3

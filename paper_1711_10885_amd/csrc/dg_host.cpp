@@ -141,6 +141,7 @@ extern "C" void dg_destroy(dg_handle *h) {
   int cur = 0;
   if (hipGetDevice(&cur) == hipSuccess && cur != h->device) (void)hipSetDevice(h->device);
   release_solver(h);
+  release_learned(h);
   if (h->bj) (void)hipFree(h->bj);
   if (h->dev_block) (void)hipFree(h->dev_block);
   if (cur != h->device) (void)hipSetDevice(cur);
@@ -198,6 +199,7 @@ extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
   h->red = nullptr;
   h->bj = nullptr;
   h->bj_nb = 0;
+  h->mlp = nullptr;
   if (hipGetDevice(&h->device) != hipSuccess) {
     delete h;
     return set_error(DG_EHIP, "dg_setup: no HIP device");
@@ -307,6 +309,10 @@ extern "C" dg_status dg_precond_apply(dg_handle *h, int32_t precond, const doubl
   if (precond == DG_PREC_BLOCK_JACOBI) {
     if (!h->bj) return set_error(DG_EINVAL, "dg_precond_apply: handle was set up without DG_WITH_BLOCK_JACOBI");
     e = bj_apply<double, double>(h, r, z, static_cast<hipStream_t>(stream));
+  } else if (precond == DG_PREC_LEARNED) {
+    if (!learned_ready(h))
+      return set_error(DG_EINVAL, "dg_precond_apply: no trained or loaded network (or no block Jacobi)");
+    e = learned_apply<double>(h, r, z, static_cast<hipStream_t>(stream));
   } else {
     return set_error(DG_EINVAL, "dg_precond_apply: unknown preconditioner");
   }

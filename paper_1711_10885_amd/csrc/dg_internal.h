@@ -13,6 +13,9 @@ namespace dgmf {
 
 constexpr int kMaxN = 11;         // k <= 10
 constexpr int kMaxBjBlock = 512;  // block Jacobi for (k+1)^3 <= 512
+constexpr int kMlpHidden = 256;   // hidden width of the cell-patch network
+constexpr int64_t kMlpChunk = 65536;  // cells per inference chunk
+struct Mlp;
 
 // 1D tables on the reference interval [0,1] for one degree (Sec. 3.2,
 // eq. (gradient_matrices); face tables B^(q) of Sec. 3.4):
@@ -56,6 +59,8 @@ struct dg_handle {
   // block Jacobi: inverse cell blocks, FP32, column-major per cell (or null)
   float *bj;
   int bj_nb;
+  // learned cell-patch preconditioner (or null)
+  dgmf::Mlp *mlp;
 };
 
 namespace dgmf {
@@ -76,7 +81,14 @@ dg_status build_block_jacobi(dg_handle *h);
 template <typename TR, typename TZ>
 hipError_t bj_apply(const dg_handle *h, const TR *r, TZ *z, hipStream_t s);
 
-// Free the solver resources of a handle (called by dg_destroy).
+// Learned preconditioner: z = BJ r + s_T MLP(p_T / s_T); ready once trained
+// or loaded (and block Jacobi is present).
+template <typename TR>
+hipError_t learned_apply(dg_handle *h, const TR *r, TR *z, hipStream_t s);
+bool learned_ready(const dg_handle *h);
+
+// Free the solver / learned resources of a handle (called by dg_destroy).
 void release_solver(dg_handle *h);
+void release_learned(dg_handle *h);
 
 }  // namespace dgmf

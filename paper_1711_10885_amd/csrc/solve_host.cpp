@@ -9,6 +9,7 @@
 #include <chrono>
 #include <cmath>
 #include <string>
+#include <vector>
 
 #include "dg_internal.h"
 #include "krylov.h"
@@ -76,13 +77,18 @@ extern "C" dg_status dg_solve(dg_handle *h, const double *f, double *u, double t
   if (opt.restart < 1 || opt.restart > kMaxBasis - 1)
     return set_error(DG_EINVAL, "dg_solve: restart must be in 1..63");
   if (opt.maxit < 1) return set_error(DG_EINVAL, "dg_solve: maxit must be >= 1");
-  if (opt.method != DG_GMRES64 && opt.method != DG_GMRES_IR) return set_error(DG_EINVAL, "dg_solve: unknown method");
+  if (opt.method != DG_GMRES64 && opt.method != DG_GMRES_IR && opt.method != DG_FGMRES)
+    return set_error(DG_EINVAL, "dg_solve: unknown method");
   if (opt.method == DG_GMRES_IR && !(opt.inner_tol > 0.0 && opt.inner_tol < 1.0))
     return set_error(DG_EINVAL, "dg_solve: inner_tol must be in (0, 1)");
-  if (opt.precond != DG_PREC_NONE && opt.precond != DG_PREC_BLOCK_JACOBI)
+  if (opt.precond != DG_PREC_NONE && opt.precond != DG_PREC_BLOCK_JACOBI && opt.precond != DG_PREC_LEARNED)
     return set_error(DG_EINVAL, "dg_solve: unknown preconditioner");
-  if (opt.precond == DG_PREC_BLOCK_JACOBI && !h->bj)
+  if (opt.precond != DG_PREC_NONE && !h->bj)
     return set_error(DG_EINVAL, "dg_solve: handle was set up without DG_WITH_BLOCK_JACOBI");
+  if (opt.precond == DG_PREC_LEARNED && opt.method != DG_FGMRES)
+    return set_error(DG_EINVAL, "dg_solve: the learned preconditioner needs DG_FGMRES");
+  if (opt.precond == DG_PREC_LEARNED && !learned_ready(h))
+    return set_error(DG_EINVAL, "dg_solve: no trained or loaded network");
 
   int cur = -1;
   if (hipGetDevice(&cur) != hipSuccess || cur != h->device) {
@@ -94,23 +100,26 @@ extern "C" dg_status dg_solve(dg_handle *h, const double *f, double *u, double t
 
   const bool have_prec = opt.precond != DG_PREC_NONE;
   const bool ir = opt.method == DG_GMRES_IR;
+  const bool flex = opt.method == DG_FGMRES;
   // workspace, FP64 GMRES:  V (m+1) n | w n | Z n (fixed preconditioner)
+  //            FGMRES:      V (m+1) n | w n | Z m n
   //            GMRES-IR:    r n (FP64) | V (m+1) n | w n | Z n | d n | r n (FP32)
   const size_t es = ir ? sizeof(float) : sizeof(double);
   const size_t vb = align256(es * n * (m + 1)), wb = align256(es * n), rb = ir ? align256(sizeof(double) * n) : 0;
-  dg_status ds = ensure_workspace(h, rb + vb + wb + (have_prec ? wb : 0) + (ir ? 2 * wb : 0));
+  const size_t zb = flex ? align256(es * n * m) : (have_prec ? wb : 0);
+  dg_status ds = ensure_workspace(h, rb + vb + wb + zb + (ir ? 2 * wb : 0));
   if (ds != DG_OK) return ds;
   char *base = static_cast<char *>(h->ws);
   double *r64 = ir ? reinterpret_cast<double *>(base) : nullptr;
   KrylovBufs K;
   K.V = base + rb;
   K.w = base + rb + vb;
-  K.Z = have_prec ? base + rb + vb + wb : nullptr;
-  float *d32 = ir ? reinterpret_cast<float *>(base + rb + vb + wb + (have_prec ? wb : 0)) : nullptr;
-  float *r32 = ir ? reinterpret_cast<float *>(base + rb + vb + 2 * wb + (have_prec ? wb : 0)) : nullptr;
+  K.Z = (have_prec || flex) ? base + rb + vb + wb : nullptr;
+  float *d32 = ir ? reinterpret_cast<float *>(base + rb + vb + wb + zb) : nullptr;
+  float *r32 = ir ? reinterpret_cast<float *>(base + rb + vb + 2 * wb + zb) : nullptr;
   K.n = n;
   K.restart = m;
-  K.flex = false;
+  K.flex = flex;
   double *scratch = h->red, *small = h->red + size_t(kRedBlocks) * kMaxBasis;
 
   dg_solve_stats stats{};
@@ -132,7 +141,51 @@ extern "C" dg_status dg_solve(dg_handle *h, const double *f, double *u, double t
     return DG_OK;
   }
   GmresOut go;
-  if (!ir) {
+  if (flex) {
+    // FGMRES(m), one cycle per call so that the true residual of every cycle
+    // can decide the fallback to block Jacobi
+    bool learned = opt.precond == DG_PREC_LEARNED;
+    auto op = [h, s](const double *x, double *y) { return apply_f64(h, x, y, s); };
+    auto prec = [h, s, &learned, &opt](const double *v, double *z) {
+      if (learned) return learned_apply<double>(h, v, z, s);
+      if (opt.precond == DG_PREC_BLOCK_JACOBI) return bj_apply<double, double>(h, v, z, s);
+      return kr_scale<double, double>(v, z, 1.0, size_t(h->ndof), s);
+    };
+    bool zero = un2 == 0.0;
+    std::vector<double> hist;  // true residual at the start of each cycle
+    for (;;) {
+      GmresOut gc;
+      e = gmres<double>(K, op, prec, true, f, u, fnorm, tol, opt.maxit - stats.iters, 1, zero, scratch, small, s, gc);
+      if (e != hipSuccess) return hip_error(e, "dg_solve: FGMRES");
+      zero = false;
+      stats.iters += gc.iters;
+      stats.outer += gc.cycles;
+      stats.applies += gc.applies;
+      stats.rel_resid = gc.rel;
+      if (gc.nan) {
+        if (!learned) {
+          go.nan = true;
+          break;
+        }
+        learned = false;  // the cycle was abandoned before its update
+        stats.fallback_used = 1;
+        continue;
+      }
+      if (gc.converged) {
+        go.converged = true;
+        break;
+      }
+      // at maxit the next call only measures the true residual (no cycle)
+      if (gc.cycles == 0) break;
+      hist.push_back(gc.rel);
+      // stagnation of the learned preconditioner: less than 10 % over the
+      // last 10 cycles -> block Jacobi alone from here on
+      if (learned && hist.size() > 10 && hist.back() > 0.9 * hist[hist.size() - 11]) {
+        learned = false;
+        stats.fallback_used = 1;
+      }
+    }
+  } else if (!ir) {
     auto op = [h, s](const double *x, double *y) { return apply_f64(h, x, y, s); };
     auto prec = [h, s](const double *v, double *z) { return bj_apply<double, double>(h, v, z, s); };
     e = gmres<double>(K, op, prec, have_prec, f, u, fnorm, tol, opt.maxit, 0, un2 == 0.0, scratch, small, s, go);
