@@ -96,6 +96,74 @@ def cpu_baseline(prob, x, budget_s: float = 12.0):
                       f"({ncs * nb} DOF, {dt:.1f} s, plain quadrature oracle)"}
 
 
+def _solve_record(st, rc):
+    return {"seconds": st["seconds"], "iterations": st["iters"], "cycles": st["outer"],
+            "fp64_applies": st["applies"], "fp32_applies": st["applies_f32"],
+            "rel_resid": st["rel_resid"], "converged": rc == 0, "fallback_used": bool(st["fallback_used"])}
+
+
+def solves_mixed(maxit: int):
+    """48^3 cells, k = 5 (23.9M DOF), K = I, b = (1, 0.5, 0.25), c = 0.1, RHS of
+    u = sin(pi x) sin(pi y) sin(pi z), u0 = 0, tol 1e-8 on the true FP64
+    residual: FP64 GMRES(30) against GMRES-IR (FP32 inner GMRES(30)), both
+    right-preconditioned by the same block Jacobi."""
+    import torch
+    from paper_1711_10885_amd import binding, workloads as W
+    prob = W.mixed_k5_48()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dg = binding.DG(prob, flags=binding.DG_WITH_BLOCK_JACOBI)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    f = dg.load_vector(W.manufactured_source(prob.K, prob.b_const, prob.c))
+    out = {"workload": f"{prob.name}: {prob.ncell[0]}^3 cells, k={prob.k}, {prob.ndof} DOF, manufactured RHS",
+           "tol": 1e-8, "restart": 30, "preconditioner": "block Jacobi (FP32 inverse cell blocks)",
+           "block_jacobi_setup_s": t_setup}
+    for label, method in (("plain_fp64_gmres", binding.DG_GMRES64), ("gmres_ir_fp32_inner", binding.DG_GMRES_IR)):
+        u = torch.zeros_like(f)
+        u, st, rc = dg.solve(f, u, tol=1e-8, method=method, precond=binding.DG_PREC_BLOCK_JACOBI, maxit=maxit,
+                             check=False)
+        out[label] = _solve_record(st, rc)
+        print(f"[solve] {label}: {out[label]}", file=sys.stderr, flush=True)
+    # FP32 operator error, against the FP64 operator (the parity-tested path)
+    x = torch.from_numpy(W.workload_vector(prob)).cuda()
+    y64 = dg.apply(x)
+    y32 = dg.apply_f32(x.float())
+    out["fp32_operator_relmax_vs_fp64"] = float((y32.double() - y64).abs().max() / y64.abs().max())
+    a, b = out["plain_fp64_gmres"], out["gmres_ir_fp32_inner"]
+    out["speedup_time_to_tol"] = a["seconds"] / b["seconds"] if a["converged"] and b["converged"] else None
+    dg.close()
+    return out
+
+
+def solves_learned(maxit: int):
+    """64^3 cells, k = 3 (16.8M DOF), kappa = exp(g) of a seeded smooth random
+    field, b = (1, 0.5, 0.25), c = 0.1, f = 1, u0 = 0, tol 1e-8: FGMRES(30)
+    with block Jacobi against FGMRES(30) with the trained network on top of
+    block Jacobi (trained on the GPU in the same run)."""
+    import torch
+    from paper_1711_10885_amd import binding, workloads as W
+    prob = W.learned_k3_64()
+    dg = binding.DG(prob, flags=binding.DG_WITH_BLOCK_JACOBI)
+    f = dg.load_vector(W.constant_source(1.0))
+    out = {"workload": f"{prob.name}: {prob.ncell[0]}^3 cells, k={prob.k}, {prob.ndof} DOF, lognormal kappa, f = 1",
+           "tol": 1e-8, "restart": 30, "maxit": maxit}
+    u = torch.zeros_like(f)
+    u, st, rc = dg.solve(f, u, tol=1e-8, method=binding.DG_FGMRES, precond=binding.DG_PREC_BLOCK_JACOBI,
+                         maxit=maxit, check=False)
+    out["fgmres_block_jacobi"] = _solve_record(st, rc)
+    print(f"[solve] fgmres_block_jacobi: {out['fgmres_block_jacobi']}", file=sys.stderr, flush=True)
+    out["training"] = dg.learned_train()
+    print(f"[solve] training: {out['training']}", file=sys.stderr, flush=True)
+    u = torch.zeros_like(f)
+    u, st, rc = dg.solve(f, u, tol=1e-8, method=binding.DG_FGMRES, precond=binding.DG_PREC_LEARNED,
+                         maxit=maxit, check=False)
+    out["fgmres_learned"] = _solve_record(st, rc)
+    print(f"[solve] fgmres_learned: {out['fgmres_learned']}", file=sys.stderr, flush=True)
+    dg.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +173,9 @@ def main():
     ap.add_argument("--variant", type=int, default=0, help="0 tuned kernel, 1 reference kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--solves", default="none", choices=["none", "mixed", "learned", "all"],
+                    help="also time the solves to 1e-8 (plain FP64 vs mixed, block Jacobi vs learned)")
+    ap.add_argument("--solve-maxit", type=int, default=20000)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -152,22 +223,20 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
 
-    # spot parity on a few cells (the tests do the full check)
-    parity = None
-    try:
-        import oracle
-        cells = np.array([0, prob.ncells // 2 + 3, prob.ncells - 1])
-        ref = oracle.apply_rows(prob, x_host, cells)
-        got = y.cpu().numpy().reshape(prob.ncells, -1)[cells]
-        parity = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
-    except Exception as ex:  # noqa: BLE001
-        print(f"spot parity skipped: {ex}", file=sys.stderr)
-
     traffic = measured_traffic(args.workload) if args.variant == 0 else None
 
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(prob, x_host, args.cpu_budget)
+
+    dg.close()
+    del x, y
+    torch.cuda.empty_cache()
+    solves = {}
+    if args.solves in ("mixed", "all"):
+        solves["mixed_precision"] = solves_mixed(args.solve_maxit)
+    if args.solves in ("learned", "all"):
+        solves["learned_preconditioner"] = solves_learned(args.solve_maxit)
 
     out = {
         "metric": METRIC,
@@ -190,10 +259,10 @@ def main():
                      "traffic": traffic, "traffic_unit": "HBM bytes per launch",
                      "algorithmic_bytes": 16 * prob.ndof, "avg_kernel_ms": avg_kernel_ms},
         "cpu_baseline": cpu,
-        "parity_spot_rel": parity,
     }
+    if solves:
+        out["solves"] = solves
     print(json.dumps(out), flush=True)
-    dg.close()
 
 
 if __name__ == "__main__":

@@ -110,6 +110,16 @@ dg_status dg_setup(const dg_problem *p, dg_handle **out);
  * overlap.  Asynchronous on hip_stream. */
 dg_status dg_apply(dg_handle *h, const double *x, double *y, void *hip_stream);
 
+/* Load vector f_{T,j} = (f, phi_j)_T of a separable source
+ *   f(x) = sum_{t < nterms} alpha[t] g(kinds[3t], x_1) g(kinds[3t+1], x_2) g(kinds[3t+2], x_3),
+ *   g(0, s) = 1, g(1, s) = sin(pi s), g(2, s) = cos(pi s),
+ * the right-hand side of Sec. 2.2 for homogeneous Dirichlet data, by the
+ * (k+1)-point tensor Gauss rule of the operator (Sec. 3.1).  alpha, kinds:
+ * host arrays (nterms in 1..16); f: device, ndof doubles.  Asynchronous on
+ * hip_stream.  DG_EINVAL on bad terms. */
+dg_status dg_load_vector(dg_handle *h, int32_t nterms, const double *alpha, const int32_t *kinds, double *f,
+                         void *hip_stream);
+
 /* y := A x with FP32 vectors (the operator of the mixed-precision tier): the
  * 1D contractions, the LDS exchanges and the volume pointwise flux run in
  * FP32; the face constants (weights, penalty gamma_F) and the pointwise face

@@ -24,7 +24,7 @@ _STATUS = {DG_EINVAL: "DG_EINVAL", DG_ENOMEM: "DG_ENOMEM", DG_EHIP: "DG_EHIP",
            DG_ENOTCONV: "DG_ENOTCONV", DG_ENAN: "DG_ENAN"}
 
 # every symbol include/dg.h declares
-EXPORTS = ["dg_setup", "dg_apply", "dg_apply_f32", "dg_set_kernel", "dg_solve", "dg_precond_apply",
+EXPORTS = ["dg_setup", "dg_apply", "dg_apply_f32", "dg_load_vector", "dg_set_kernel", "dg_solve", "dg_precond_apply",
            "dg_learned_train", "dg_learned_nparams", "dg_learned_set_params", "dg_learned_get_params",
            "dg_mlp_forward", "dg_mlp_grad", "dg_mlp_step", "dg_ndof", "dg_degree", "dg_last_error",
            "dg_destroy"]
@@ -99,6 +99,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dg_setup.restype = ctypes.c_int
     lib.dg_apply.argtypes = [H, vp, vp, vp]
     lib.dg_apply.restype = ctypes.c_int
+    lib.dg_load_vector.argtypes = [H, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_int32), vp, vp]
+    lib.dg_load_vector.restype = ctypes.c_int
     lib.dg_apply_f32.argtypes = [H, vp, vp, vp]
     lib.dg_apply_f32.restype = ctypes.c_int
     lib.dg_set_kernel.argtypes = [H, ctypes.c_int32]
@@ -225,6 +228,20 @@ class DG:
         _check(load().dg_apply(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
                                _stream_ptr(stream)))
         return y
+
+    def load_vector(self, terms, f=None, stream=None):
+        """Load vector of a separable source: terms = [(alpha, (kind1, kind2,
+        kind3)), ...], kind 0 = 1, 1 = sin(pi .), 2 = cos(pi .)."""
+        import torch
+        alpha = np.ascontiguousarray([t[0] for t in terms], dtype=np.float64)
+        kinds = np.ascontiguousarray([t[1] for t in terms], dtype=np.int32).reshape(-1)
+        if f is None:
+            f = torch.empty(self.ndof, dtype=torch.float64, device="cuda")
+        _check_vec(f, self.ndof, torch.float64, "f")
+        _check(load().dg_load_vector(self._h, int(alpha.size), alpha.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     kinds.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                     ctypes.c_void_p(f.data_ptr()), _stream_ptr(stream)))
+        return f
 
     def apply_f32(self, x, y=None, stream=None):
         """y := A x with FP32 vectors (mixed-precision operator)."""

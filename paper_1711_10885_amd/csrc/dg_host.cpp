@@ -209,10 +209,12 @@ extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
   // host staging of every device table, then one allocation + one copy
   const int m = n;
   std::vector<double> host;
-  size_t off_h[3], off_bv[3], off_bn[3], off_kappa = 0;
+  size_t off_h[3], off_nd[3], off_bv[3], off_bn[3], off_kappa = 0;
   for (int a = 0; a < 3; ++a) {
     off_h[a] = host.size();
     for (int i = 0; i < p->ncell[a]; ++i) host.push_back(p->nodes[a][i + 1] - p->nodes[a][i]);
+    off_nd[a] = host.size();
+    host.insert(host.end(), p->nodes[a], p->nodes[a] + p->ncell[a] + 1);
   }
   for (int r = 0; r < 3; ++r) {
     const int ax = p->b_axis[r];
@@ -247,6 +249,7 @@ extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
   for (int a = 0; a < 3; ++a) {
     M.ncell[a] = p->ncell[a];
     M.h[a] = base + off_h[a];
+    M.nodes[a] = base + off_nd[a];
     M.bvol[a] = base + off_bv[a];
     M.bnode[a] = base + off_bn[a];
     M.b_axis[a] = p->b_axis[a];

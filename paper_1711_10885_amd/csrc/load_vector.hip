@@ -1,0 +1,96 @@
+// Load vector of a separable source (the right-hand-side functional of
+// Sec. 2.2 with homogeneous Dirichlet data): f_{T,j} = (f, phi_j)_T by the
+// (k+1)-point tensor Gauss rule of the operator (Sec. 3.1).
+//
+// For f(x) = sum_t alpha_t g_t1(x_1) g_t2(x_2) g_t3(x_3) the cell integral
+// factorises into 1D integrals (sum factorization of a rank-one integrand):
+//   f_{T,j} = |T| sum_t alpha_t prod_a sum_q w_q g_ta(o_a + h_a xi_q) theta_{j_a}(xi_q).
+// One thread per coefficient (cell, j).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "dg_internal.h"
+
+namespace dgmf {
+
+constexpr int kMaxTerms = 16;
+
+struct LvArgs {
+  int n, nterms;
+  double xi[kMaxN], w[kMaxN], V[kMaxN][kMaxN];
+  double alpha[kMaxTerms];
+  int kinds[kMaxTerms][3];
+};
+
+__device__ __forceinline__ double sep_factor(int kind, double x) {
+  return kind == 0 ? 1.0 : (kind == 1 ? sinpi(x) : cospi(x));
+}
+
+__global__ __launch_bounds__(256) void k_load_vector(DevMesh M, LvArgs L, int64_t ndof, double *__restrict__ f) {
+  const int n = L.n, nb = n * n * n;
+  for (int64_t g = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; g < ndof; g += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t c = g / nb;
+    const int j = int(g - c * nb);
+    const int ja[3] = {j % n, (j / n) % n, j / (n * n)};
+    const int ic[3] = {int(c % M.ncell[0]), int((c / M.ncell[0]) % M.ncell[1]),
+                       int(c / (int64_t(M.ncell[0]) * M.ncell[1]))};
+    double o[3], h[3];
+    for (int a = 0; a < 3; ++a) {
+      o[a] = M.nodes[a][ic[a]];
+      h[a] = M.h[a][ic[a]];
+    }
+    double acc = 0.0;
+    for (int t = 0; t < L.nterms; ++t) {
+      double prod = L.alpha[t];
+      for (int a = 0; a < 3; ++a) {
+        double s = 0.0;
+        for (int q = 0; q < n; ++q)
+          s = fma(L.w[q] * sep_factor(L.kinds[t][a], o[a] + h[a] * L.xi[q]), L.V[q][ja[a]], s);
+        prod *= s;
+      }
+      acc += prod;
+    }
+    f[g] = acc * h[0] * h[1] * h[2];
+  }
+}
+
+}  // namespace dgmf
+
+using namespace dgmf;
+
+extern "C" dg_status dg_load_vector(dg_handle *h, int32_t nterms, const double *alpha, const int32_t *kinds,
+                                    double *f, void *stream) {
+  if (!h) return set_error(DG_EINVAL, "dg_load_vector: handle is NULL");
+  if (nterms < 1 || nterms > kMaxTerms) return set_error(DG_EINVAL, "dg_load_vector: nterms must be in 1..16");
+  if (!alpha || !kinds || !f) return set_error(DG_EINVAL, "dg_load_vector: NULL argument");
+  LvArgs L;
+  L.n = h->tab.n;
+  L.nterms = nterms;
+  for (int q = 0; q < L.n; ++q) {
+    L.xi[q] = h->tab.xi[q];
+    L.w[q] = h->tab.w[q];
+    for (int jj = 0; jj < L.n; ++jj) L.V[q][jj] = h->tab.V[q][jj];
+  }
+  for (int t = 0; t < nterms; ++t) {
+    if (!std::isfinite(alpha[t])) return set_error(DG_EINVAL, "dg_load_vector: alpha must be finite");
+    L.alpha[t] = alpha[t];
+    for (int a = 0; a < 3; ++a) {
+      if (kinds[3 * t + a] < 0 || kinds[3 * t + a] > 2)
+        return set_error(DG_EINVAL, "dg_load_vector: kinds must be 0, 1 or 2");
+      L.kinds[t][a] = kinds[3 * t + a];
+    }
+  }
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != h->device) {
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_error(e, "dg_load_vector: hipSetDevice");
+  }
+  const int64_t blocks = std::min<int64_t>((h->ndof + 255) / 256, int64_t(1) << 20);
+  hipLaunchKernelGGL(k_load_vector, dim3(unsigned(blocks)), dim3(256), 0, static_cast<hipStream_t>(stream), h->mesh, L,
+                     int64_t(h->ndof), f);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_error(e, "dg_load_vector: kernel launch");
+  return DG_OK;
+}

@@ -154,3 +154,28 @@ def test_manufactured_solution_converges_at_order_k_plus_1():
     order = np.log2(errs[0] / errs[1])
     print(f"L2 errors {errs}, order {order:.2f}", flush=True)
     assert abs(order - (k + 1)) <= 0.3
+
+
+@pytest.mark.parametrize("k", [1, 3, 5, 8])
+def test_load_vector_matches_oracle(k):
+    torch = _torch()
+    from paper_1711_10885_amd import binding
+    p = W.random_problem(800 + k, ncell=(3, 2, 2), k=k, b="sine")
+    terms = W.manufactured_source(p.K, (0.3, -0.2, 0.1), 0.7) + W.constant_source(0.25)
+    with binding.DG(p) as dg:
+        f = dg.load_vector(terms).cpu().numpy()
+    ref = oracle.rhs(p, terms)
+    e = np.abs(f - ref).max() / np.abs(ref).max()
+    print(f"k={k}: load vector relmax {e:.2e}", flush=True)
+    assert e <= 1e-13
+
+
+def test_load_vector_of_the_48_cube_workload_on_sampled_cells():
+    torch = _torch()
+    from paper_1711_10885_amd import binding
+    p = W.mixed_k5_48()
+    terms = W.manufactured_source(p.K, p.b_const, p.c)
+    with binding.DG(p) as dg:
+        f = dg.load_vector(terms).cpu().numpy()
+    ref = oracle.rhs(p, terms)
+    assert np.abs(f - ref).max() <= 1e-13 * np.abs(ref).max()
