@@ -16,10 +16,14 @@
 //      non-finite pivot is reported as an error.
 //      Inverting the column-major store treated as row-major gives
 //      (A^T)^{-1} = (A^{-1})^T row-major, i.e. A^{-1} column-major.
-//   3. Conversion to FP32 (the store the solvers read).
-// Apply: z_T = A_TT^{-1} r_T, one thread per row, column-major blocks so that
-// consecutive lanes read consecutive addresses; FP64 accumulation.  HBM-bound:
-// 4 (k+1)^3 bytes of block store per DOF.
+//   3. Conversion to FP32 (the store the FP64 solvers read) and to FP16 with
+//      one scale per cell (max |entry|), the store of the FP32 inner solve of
+//      GMRES-IR.
+// Apply: z_T = A_TT^{-1} r_T with column-major blocks; each thread owns VR
+// consecutive rows of one cell and reads VR entries of a column with one
+// 16-byte load (VR = 4 in FP32, 8 in FP16; one row per thread when (k+1)^3
+// is not a multiple of VR); FP64 accumulation.  HBM-bound: 4 (FP32) or 2
+// (FP16) (k+1)^3 bytes of block store per DOF.
 #include <hip/hip_runtime.h>
 
 #include <string>
@@ -164,6 +168,54 @@ __global__ __launch_bounds__(kBjThreads) void k_bj_apply(const float *__restrict
   }
 }
 
+// VR rows per thread, one 16-byte load per column; sc: per-cell scale or null
+template <typename TR, typename TZ, typename TB, int VR>
+__global__ __launch_bounds__(kBjThreads) void k_bj_apply_vec(const TB *__restrict__ Binv, const float *__restrict__ sc,
+                                                             const TR *__restrict__ r, TZ *__restrict__ z, int nb,
+                                                             int64_t ncells) {
+  typedef TB bvec __attribute__((ext_vector_type(VR)));
+  const int per = nb / VR;
+  const int64_t total = ncells * per;
+  for (int64_t g = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; g < total;
+       g += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t c = g / per;
+    const int i0 = int(g - c * per) * VR;
+    const TB *Bc = Binv + c * int64_t(nb) * nb + i0;
+    const TR *rc = r + c * nb;
+    double acc[VR];
+#pragma unroll
+    for (int e = 0; e < VR; ++e) acc[e] = 0.0;
+    for (int j = 0; j < nb; ++j) {
+      const bvec col = *reinterpret_cast<const bvec *>(Bc + size_t(j) * nb);
+      const double rj = double(rc[j]);
+#pragma unroll
+      for (int e = 0; e < VR; ++e) acc[e] = fma(double(col[e]), rj, acc[e]);
+    }
+    const double s = sc ? double(sc[c]) : 1.0;
+#pragma unroll
+    for (int e = 0; e < VR; ++e) z[c * nb + i0 + e] = TZ(acc[e] * s);
+  }
+}
+
+// FP16 copy with one scale per cell: h = fp16(b / sc_c), sc_c = max |b| over the block
+__global__ __launch_bounds__(kBjThreads) void k_to_f16_scaled(const double *__restrict__ B, int nb,
+                                                              _Float16 *__restrict__ H, float *__restrict__ sc) {
+  __shared__ double red[kBjThreads / 64];
+  const size_t nn = size_t(nb) * nb;
+  const double *Bc = B + blockIdx.x * nn;
+  double mx = 0.0;
+  for (size_t i = threadIdx.x; i < nn; i += kBjThreads) mx = fmax(mx, fabs(Bc[i]));
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  double m = 0.0;
+  for (int w = 0; w < kBjThreads / 64; ++w) m = fmax(m, red[w]);
+  const float s = m > 0.0 ? float(m) : 1.0f;
+  const double inv = 1.0 / double(s);
+  for (size_t i = threadIdx.x; i < nn; i += kBjThreads) H[blockIdx.x * nn + i] = _Float16(Bc[i] * inv);
+  if (threadIdx.x == 0) sc[blockIdx.x] = s;
+}
+
 static int grid_for(int64_t work) {
   const int64_t g = (work + kBjThreads - 1) / kBjThreads;
   return int(g < 1 ? 1 : (g > (1 << 20) ? (1 << 20) : g));
@@ -220,6 +272,16 @@ dg_status build_block_jacobi(dg_handle *h) {
   }
   if ((e = hipGetLastError()) != hipSuccess) return fail(e, "block Jacobi: inversion");
   hipLaunchKernelGGL(k_to_f32, dim3(4096), dim3(kBjThreads), 0, s, B, h->bj, nblk);
+  if ((e = hipMalloc(&h->bj16, nblk * sizeof(_Float16))) != hipSuccess) {
+    h->bj16 = nullptr;
+    return fail(e, "block Jacobi: FP16 blocks");
+  }
+  if ((e = hipMalloc(&h->bj16_scale, size_t(h->ncells) * sizeof(float))) != hipSuccess) {
+    h->bj16_scale = nullptr;
+    return fail(e, "block Jacobi: FP16 scales");
+  }
+  hipLaunchKernelGGL(k_to_f16_scaled, dim3(unsigned(h->ncells)), dim3(kBjThreads), 0, s, B, nb, h->bj16,
+                     h->bj16_scale);
   int hbad = 0;
   if ((e = hipMemcpy(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost)) != hipSuccess)
     return fail(e, "block Jacobi: flag readback");
@@ -230,6 +292,10 @@ dg_status build_block_jacobi(dg_handle *h) {
   if (hbad) {
     (void)hipFree(h->bj);
     h->bj = nullptr;
+    (void)hipFree(h->bj16);
+    h->bj16 = nullptr;
+    (void)hipFree(h->bj16_scale);
+    h->bj16_scale = nullptr;
     return set_error(DG_ENAN, "dg_setup: a cell block has a non-positive pivot (the form is not coercive)");
   }
   h->bj_nb = nb;
@@ -237,14 +303,22 @@ dg_status build_block_jacobi(dg_handle *h) {
 }
 
 template <typename TR, typename TZ>
-hipError_t bj_apply(const dg_handle *h, const TR *r, TZ *z, hipStream_t s) {
-  const int64_t total = h->ndof;
-  hipLaunchKernelGGL((k_bj_apply<TR, TZ>), dim3(grid_for(total)), dim3(kBjThreads), 0, s, h->bj, r, z, h->bj_nb,
-                     total);
+hipError_t bj_apply(const dg_handle *h, const TR *r, TZ *z, hipStream_t s, bool half_store) {
+  const int nb = h->bj_nb;
+  if (half_store && h->bj16 && nb % 8 == 0) {
+    hipLaunchKernelGGL((k_bj_apply_vec<TR, TZ, _Float16, 8>), dim3(grid_for(h->ncells * (nb / 8))), dim3(kBjThreads),
+                       0, s, h->bj16, h->bj16_scale, r, z, nb, int64_t(h->ncells));
+  } else if (nb % 4 == 0) {
+    hipLaunchKernelGGL((k_bj_apply_vec<TR, TZ, float, 4>), dim3(grid_for(h->ncells * (nb / 4))), dim3(kBjThreads), 0,
+                       s, h->bj, nullptr, r, z, nb, int64_t(h->ncells));
+  } else {
+    const int64_t total = h->ndof;
+    hipLaunchKernelGGL((k_bj_apply<TR, TZ>), dim3(grid_for(total)), dim3(kBjThreads), 0, s, h->bj, r, z, nb, total);
+  }
   return hipGetLastError();
 }
 
-template hipError_t bj_apply<double, double>(const dg_handle *, const double *, double *, hipStream_t);
-template hipError_t bj_apply<float, float>(const dg_handle *, const float *, float *, hipStream_t);
+template hipError_t bj_apply<double, double>(const dg_handle *, const double *, double *, hipStream_t, bool);
+template hipError_t bj_apply<float, float>(const dg_handle *, const float *, float *, hipStream_t, bool);
 
 }  // namespace dgmf

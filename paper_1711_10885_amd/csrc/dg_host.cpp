@@ -143,6 +143,8 @@ extern "C" void dg_destroy(dg_handle *h) {
   release_solver(h);
   release_learned(h);
   if (h->bj) (void)hipFree(h->bj);
+  if (h->bj16) (void)hipFree(h->bj16);
+  if (h->bj16_scale) (void)hipFree(h->bj16_scale);
   if (h->dev_block) (void)hipFree(h->dev_block);
   if (cur != h->device) (void)hipSetDevice(cur);
   delete h;
@@ -198,6 +200,8 @@ extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
   h->ws_bytes = 0;
   h->red = nullptr;
   h->bj = nullptr;
+  h->bj16 = nullptr;
+  h->bj16_scale = nullptr;
   h->bj_nb = 0;
   h->mlp = nullptr;
   if (hipGetDevice(&h->device) != hipSuccess) {

@@ -59,6 +59,8 @@ struct dg_handle {
   double *red;      // reduction partials + small device vectors of the Krylov kernels
   // block Jacobi: inverse cell blocks, FP32, column-major per cell (or null)
   float *bj;
+  _Float16 *bj16;      // the same blocks in FP16, scaled per cell (inner FP32 solves)
+  float *bj16_scale;
   int bj_nb;
   // learned cell-patch preconditioner (or null)
   dgmf::Mlp *mlp;
@@ -80,7 +82,7 @@ hipError_t apply_f64(const dg_handle *h, const double *x, double *y, hipStream_t
 // Block Jacobi: build the inverse cell blocks (setup), z = M^{-1} r.
 dg_status build_block_jacobi(dg_handle *h);
 template <typename TR, typename TZ>
-hipError_t bj_apply(const dg_handle *h, const TR *r, TZ *z, hipStream_t s);
+hipError_t bj_apply(const dg_handle *h, const TR *r, TZ *z, hipStream_t s, bool half_store = false);
 
 // Learned preconditioner: z = BJ r + s_T MLP(p_T / s_T); ready once trained
 // or loaded (and block Jacobi is present).

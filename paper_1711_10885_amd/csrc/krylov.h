@@ -14,6 +14,7 @@ namespace dgmf {
 
 constexpr int kRedBlocks = 1024;  // fixed reduction grid (deterministic sums)
 constexpr int kMaxBasis = 64;     // restart <= kMaxBasis - 1
+constexpr size_t kBasisAlign = 64;  // basis vectors start 16-byte (and 256-byte) aligned
 
 template <typename T>
 hipError_t kr_multidot(const T *V, size_t ld, int nv, const T *w, size_t n, double *partial,
@@ -35,10 +36,11 @@ hipError_t kr_norm2(const T *x, size_t n, double *partial, double *out, hipStrea
 
 // Device buffers of one GMRES instance (owned by the handle).
 struct KrylovBufs {
-  void *V = nullptr;   // (restart+1) x n basis
-  void *Z = nullptr;   // restart x n (flexible) or n (fixed preconditioner)
+  void *V = nullptr;   // (restart+1) x ld basis
+  void *Z = nullptr;   // restart x ld (flexible) or n (fixed preconditioner)
   void *w = nullptr;   // n
   size_t n = 0;
+  size_t ld = 0;       // basis stride: n rounded up to kBasisAlign entries
   int restart = 0;
   bool flex = false;
 };
@@ -66,7 +68,7 @@ template <typename T, typename Op, typename Prec>
 hipError_t gmres(KrylovBufs &K, Op &&op, Prec &&prec, bool have_prec, const T *b, T *u, double bnorm,
                  double tol, int maxit, int max_cycles, bool zero_guess, double *scratch, double *small,
                  hipStream_t s, GmresOut &out) {
-  const size_t n = K.n;
+  const size_t n = K.n, ld = K.ld;
   const int m = K.restart;
   T *V = static_cast<T *>(K.V);
   T *Z = static_cast<T *>(K.Z);
@@ -107,15 +109,15 @@ hipError_t gmres(KrylovBufs &K, Op &&op, Prec &&prec, bool have_prec, const T *b
     g[0] = beta;
     int jdone = 0;
     for (int j = 0; j < m && out.iters < maxit; ++j) {
-      T *vj = V + size_t(j) * n;
-      T *zj = have_prec ? (K.flex ? Z + size_t(j) * n : Z) : vj;
+      T *vj = V + size_t(j) * ld;
+      T *zj = have_prec ? (K.flex ? Z + size_t(j) * ld : Z) : vj;
       if (have_prec && (e = prec(vj, zj)) != hipSuccess) return e;
       if ((e = op(zj, w)) != hipSuccess) return e;
       ++out.applies;
       const int nv = j + 1;
       // CGS2: h1 = V^T w; w -= V h1; h2 = V^T w, ||w||^2
-      if ((e = kr_multidot<T>(V, n, nv, w, n, scratch, h1, s)) != hipSuccess) return e;
-      if ((e = kr_orth<T, true, true>(V, n, nv, h1, w, w, 1.0, n, scratch, h2, s)) != hipSuccess) return e;
+      if ((e = kr_multidot<T>(V, ld, nv, w, n, scratch, h1, s)) != hipSuccess) return e;
+      if ((e = kr_orth<T, true, true>(V, ld, nv, h1, w, w, 1.0, n, scratch, h2, s)) != hipSuccess) return e;
       if ((e = hipMemcpyAsync(hb.data(), small, sizeof(double) * (kMaxBasis + nv + 1),
                               hipMemcpyDeviceToHost, s)) != hipSuccess)
         return e;
@@ -155,7 +157,7 @@ hipError_t gmres(KrylovBufs &K, Op &&op, Prec &&prec, bool have_prec, const T *b
       if (std::fabs(g[j + 1]) <= tol * bnorm || breakdown) break;
       // v_{j+1} = (w - V h2) / hn  (not needed after the last step of a cycle)
       if (j + 1 < m && out.iters < maxit &&
-          (e = kr_orth<T, false, false>(V, n, nv, h2, w, V + size_t(j + 1) * n, 1.0 / hn, n, scratch,
+          (e = kr_orth<T, false, false>(V, ld, nv, h2, w, V + size_t(j + 1) * ld, 1.0 / hn, n, scratch,
                                         nullptr, s)) != hipSuccess)
         return e;
     }
@@ -170,11 +172,11 @@ hipError_t gmres(KrylovBufs &K, Op &&op, Prec &&prec, bool have_prec, const T *b
       return e;
     if (have_prec && !K.flex) {
       // u += M^{-1} (V y)
-      if ((e = kr_lincomb<T, T>(w, V, n, jdone, yd, 1.0, false, n, s)) != hipSuccess) return e;
+      if ((e = kr_lincomb<T, T>(w, V, ld, jdone, yd, 1.0, false, n, s)) != hipSuccess) return e;
       if ((e = prec(w, Z)) != hipSuccess) return e;
       if ((e = kr_axpy<T, T>(Z, u, 1.0, n, s)) != hipSuccess) return e;
     } else {
-      if ((e = kr_lincomb<T, T>(u, have_prec ? Z : V, n, jdone, yd, 1.0, true, n, s)) != hipSuccess)
+      if ((e = kr_lincomb<T, T>(u, have_prec ? Z : V, ld, jdone, yd, 1.0, true, n, s)) != hipSuccess)
         return e;
     }
     // y is read by the update kernel: keep the host copy alive until then

@@ -47,16 +47,40 @@ __device__ __forceinline__ void block_sum(const double (&v)[NV], double *sm) {
   for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < (n); \
        i += size_t(gridDim.x) * blockDim.x)
 
+// Vectors are streamed with 16-byte loads (VW = 16 / sizeof(T) entries per
+// lane and load); the entries beyond the last full vector (n % VW) are done
+// by a scalar tail.  V_k = V + k*ld, w and wout must be 16-byte aligned and
+// ld a multiple of VW (the solver pads ld).
+template <typename T>
+struct Vec16 {
+  static constexpr int VW = 16 / int(sizeof(T));
+  typedef T type __attribute__((ext_vector_type(16 / sizeof(T))));
+};
+
 // partial[b*nv + k] = sum over block b of V_k[i] w[i]   (V_k = V + k*ld)
 template <typename T, int NVMAX>
 __global__ __launch_bounds__(kRedThreads) void k_multidot(const T *__restrict__ V, size_t ld, int nv,
                                                            const T *__restrict__ w, size_t n,
                                                            double *__restrict__ partial) {
+  using vec = typename Vec16<T>::type;
+  constexpr int VW = Vec16<T>::VW;
   __shared__ double sm[(kRedThreads / 64 + 1) * NVMAX];
   double acc[NVMAX];
 #pragma unroll
   for (int k = 0; k < NVMAX; ++k) acc[k] = 0.0;
-  GRID_STRIDE(i, n) {
+  const size_t nvec = n / VW;
+  GRID_STRIDE(i, nvec) {
+    const vec wv = reinterpret_cast<const vec *>(w)[i];
+#pragma unroll
+    for (int k = 0; k < NVMAX; ++k)
+      if (k < nv) {
+        const vec vv = reinterpret_cast<const vec *>(V + k * ld)[i];
+#pragma unroll
+        for (int e = 0; e < VW; ++e) acc[k] = fma(double(vv[e]), double(wv[e]), acc[k]);
+      }
+  }
+  for (size_t i = nvec * VW + blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n;
+       i += size_t(gridDim.x) * blockDim.x) {
     const double wi = double(w[i]);
 #pragma unroll
     for (int k = 0; k < NVMAX; ++k)
@@ -72,6 +96,8 @@ template <typename T, int NVMAX, bool DOT, bool NORM>
 __global__ __launch_bounds__(kRedThreads) void k_orth(const T *__restrict__ V, size_t ld, int nv,
                                                        const double *__restrict__ h, const T *w, T *wout,
                                                        double scale, size_t n, double *__restrict__ partial) {
+  using vec = typename Vec16<T>::type;
+  constexpr int VW = Vec16<T>::VW;
   constexpr int NA = NVMAX + 1;
   __shared__ double sm[(kRedThreads / 64 + 1) * NA];
   __shared__ double hs[NVMAX];
@@ -80,7 +106,39 @@ __global__ __launch_bounds__(kRedThreads) void k_orth(const T *__restrict__ V, s
   double acc[NA];
 #pragma unroll
   for (int k = 0; k < NA; ++k) acc[k] = 0.0;
-  GRID_STRIDE(i, n) {
+  const size_t nvec = n / VW;
+  GRID_STRIDE(i, nvec) {
+    const vec wv = reinterpret_cast<const vec *>(w)[i];
+    double wi[VW];
+#pragma unroll
+    for (int e = 0; e < VW; ++e) wi[e] = double(wv[e]);
+    vec vv[NVMAX];
+#pragma unroll
+    for (int k = 0; k < NVMAX; ++k)
+      if (k < nv) {
+        vv[k] = reinterpret_cast<const vec *>(V + k * ld)[i];
+#pragma unroll
+        for (int e = 0; e < VW; ++e) wi[e] = fma(-hs[k], double(vv[k][e]), wi[e]);
+      }
+    vec ov;
+#pragma unroll
+    for (int e = 0; e < VW; ++e) ov[e] = T(wi[e] * scale);
+    reinterpret_cast<vec *>(wout)[i] = ov;
+    if (DOT) {
+#pragma unroll
+      for (int k = 0; k < NVMAX; ++k)
+        if (k < nv) {
+#pragma unroll
+          for (int e = 0; e < VW; ++e) acc[k] = fma(double(vv[k][e]), double(ov[e]), acc[k]);
+        }
+    }
+    if (NORM) {
+#pragma unroll
+      for (int e = 0; e < VW; ++e) acc[NVMAX] = fma(double(ov[e]), double(ov[e]), acc[NVMAX]);
+    }
+  }
+  for (size_t i = nvec * VW + blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n;
+       i += size_t(gridDim.x) * blockDim.x) {
     double v[NVMAX];
     double wi = double(w[i]);
 #pragma unroll

@@ -105,8 +105,9 @@ extern "C" dg_status dg_solve(dg_handle *h, const double *f, double *u, double t
   //            FGMRES:      V (m+1) n | w n | Z m n
   //            GMRES-IR:    r n (FP64) | V (m+1) n | w n | Z n | d n | r n (FP32)
   const size_t es = ir ? sizeof(float) : sizeof(double);
-  const size_t vb = align256(es * n * (m + 1)), wb = align256(es * n), rb = ir ? align256(sizeof(double) * n) : 0;
-  const size_t zb = flex ? align256(es * n * m) : (have_prec ? wb : 0);
+  const size_t ld = (n + kBasisAlign - 1) / kBasisAlign * kBasisAlign;
+  const size_t vb = align256(es * ld * (m + 1)), wb = align256(es * n), rb = ir ? align256(sizeof(double) * n) : 0;
+  const size_t zb = flex ? align256(es * ld * m) : (have_prec ? wb : 0);
   dg_status ds = ensure_workspace(h, rb + vb + wb + zb + (ir ? 2 * wb : 0));
   if (ds != DG_OK) return ds;
   char *base = static_cast<char *>(h->ws);
@@ -118,6 +119,7 @@ extern "C" dg_status dg_solve(dg_handle *h, const double *f, double *u, double t
   float *d32 = ir ? reinterpret_cast<float *>(base + rb + vb + wb + zb) : nullptr;
   float *r32 = ir ? reinterpret_cast<float *>(base + rb + vb + 2 * wb + zb) : nullptr;
   K.n = n;
+  K.ld = ld;
   K.restart = m;
   K.flex = flex;
   double *scratch = h->red, *small = h->red + size_t(kRedBlocks) * kMaxBasis;
@@ -197,7 +199,8 @@ extern "C" dg_status dg_solve(dg_handle *h, const double *f, double *u, double t
   } else {
     // GMRES-IR: FP64 residual and update, FP32 correction by one inner cycle
     auto op = [h, s](const float *x, float *y) { return launch_apply_fused_f32(h, x, y, s); };
-    auto prec = [h, s](const float *v, float *z) { return bj_apply<float, float>(h, v, z, s); };
+    // the inner FP32 solve reads the FP16 copy of the inverse blocks
+    auto prec = [h, s](const float *v, float *z) { return bj_apply<float, float>(h, v, z, s, true); };
     go = GmresOut();
     bool first = true;
     for (;;) {
