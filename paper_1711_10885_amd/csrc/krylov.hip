@@ -57,6 +57,16 @@ struct Vec16 {
   typedef T type __attribute__((ext_vector_type(16 / sizeof(T))));
 };
 
+// Basis vectors are processed in chunks of KR_CH (all of them when NVMAX <= 32,
+// else 16; a chunk is re-read for the dot products when there are several).
+#define KR_CH(NVMAX) ((NVMAX) <= 32 ? (NVMAX) : 16)
+#define KR_NC(NVMAX) ((NVMAX) / KR_CH(NVMAX))
+
+// Loads are issued first for all basis vectors of a chunk (branch-free:
+// slots k >= nv re-read V_{nv-1} with coefficient 0, a cache hit), then the
+// arithmetic runs; with the loads behind per-slot branches the compiler
+// serialises load and use and the passes fall to a fraction of the HBM rate.
+
 // partial[b*nv + k] = sum over block b of V_k[i] w[i]   (V_k = V + k*ld)
 template <typename T, int NVMAX>
 __global__ __launch_bounds__(kRedThreads) void k_multidot(const T *__restrict__ V, size_t ld, int nv,
@@ -72,11 +82,19 @@ __global__ __launch_bounds__(kRedThreads) void k_multidot(const T *__restrict__ 
   GRID_STRIDE(i, nvec) {
     const vec wv = reinterpret_cast<const vec *>(w)[i];
 #pragma unroll
-    for (int k = 0; k < NVMAX; ++k)
-      if (k < nv) {
-        const vec vv = reinterpret_cast<const vec *>(V + k * ld)[i];
+    for (int c = 0; c < KR_NC(NVMAX); ++c)
+      if (c * KR_CH(NVMAX) < nv) {
+        vec vv[KR_CH(NVMAX)];
 #pragma unroll
-        for (int e = 0; e < VW; ++e) acc[k] = fma(double(vv[e]), double(wv[e]), acc[k]);
+        for (int k = 0; k < KR_CH(NVMAX); ++k) {
+          const int kk = c * KR_CH(NVMAX) + k;
+          vv[k] = reinterpret_cast<const vec *>(V + (kk < nv ? kk : nv - 1) * ld)[i];
+        }
+#pragma unroll
+        for (int k = 0; k < KR_CH(NVMAX); ++k)
+#pragma unroll
+          for (int e = 0; e < VW; ++e)
+            acc[c * KR_CH(NVMAX) + k] = fma(double(vv[k][e]), double(wv[e]), acc[c * KR_CH(NVMAX) + k]);
       }
   }
   for (size_t i = nvec * VW + blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n;
@@ -86,7 +104,7 @@ __global__ __launch_bounds__(kRedThreads) void k_multidot(const T *__restrict__ 
     for (int k = 0; k < NVMAX; ++k)
       if (k < nv) acc[k] = fma(double(V[k * ld + i]), wi, acc[k]);
   }
-  block_sum<NVMAX>(acc, sm);
+  block_sum<NVMAX>(acc, sm);  // slots k >= nv are never written out
   if (threadIdx.x < nv) partial[blockIdx.x * nv + threadIdx.x] = sm[(kRedThreads / 64) * NVMAX + threadIdx.x];
 }
 
@@ -107,18 +125,27 @@ __global__ __launch_bounds__(kRedThreads) void k_orth(const T *__restrict__ V, s
 #pragma unroll
   for (int k = 0; k < NA; ++k) acc[k] = 0.0;
   const size_t nvec = n / VW;
+  constexpr int CH = KR_CH(NVMAX), NC = KR_NC(NVMAX);
   GRID_STRIDE(i, nvec) {
     const vec wv = reinterpret_cast<const vec *>(w)[i];
     double wi[VW];
 #pragma unroll
     for (int e = 0; e < VW; ++e) wi[e] = double(wv[e]);
-    vec vv[NVMAX];
+    vec vv[CH];
 #pragma unroll
-    for (int k = 0; k < NVMAX; ++k)
-      if (k < nv) {
-        vv[k] = reinterpret_cast<const vec *>(V + k * ld)[i];
+    for (int c = 0; c < NC; ++c)
+      if (c * CH < nv) {
 #pragma unroll
-        for (int e = 0; e < VW; ++e) wi[e] = fma(-hs[k], double(vv[k][e]), wi[e]);
+        for (int k = 0; k < CH; ++k) {
+          const int kk = c * CH + k;
+          vv[k] = reinterpret_cast<const vec *>(V + (kk < nv ? kk : nv - 1) * ld)[i];
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          const double hk = hs[c * CH + k];
+#pragma unroll
+          for (int e = 0; e < VW; ++e) wi[e] = fma(-hk, double(vv[k][e]), wi[e]);
+        }
       }
     vec ov;
 #pragma unroll
@@ -126,10 +153,19 @@ __global__ __launch_bounds__(kRedThreads) void k_orth(const T *__restrict__ V, s
     reinterpret_cast<vec *>(wout)[i] = ov;
     if (DOT) {
 #pragma unroll
-      for (int k = 0; k < NVMAX; ++k)
-        if (k < nv) {
+      for (int c = 0; c < NC; ++c)
+        if (c * CH < nv) {
+          if (NC > 1) {  // one chunk: its vectors are still in registers
 #pragma unroll
-          for (int e = 0; e < VW; ++e) acc[k] = fma(double(vv[k][e]), double(ov[e]), acc[k]);
+            for (int k = 0; k < CH; ++k) {
+              const int kk = c * CH + k;
+              vv[k] = reinterpret_cast<const vec *>(V + (kk < nv ? kk : nv - 1) * ld)[i];
+            }
+          }
+#pragma unroll
+          for (int k = 0; k < CH; ++k)
+#pragma unroll
+            for (int e = 0; e < VW; ++e) acc[c * CH + k] = fma(double(vv[k][e]), double(ov[e]), acc[c * CH + k]);
         }
     }
     if (NORM) {
@@ -158,7 +194,11 @@ __global__ __launch_bounds__(kRedThreads) void k_orth(const T *__restrict__ V, s
     if (NORM) acc[NVMAX] = fma(wr, wr, acc[NVMAX]);
   }
   if (DOT || NORM) {
-    // pack the norm right after the nv dots (static indices only: no scratch)
+    // the slots k >= nv hold products with V_{nv-1}: drop them, then pack
+    // the norm right after the nv dots (static indices only: no scratch)
+#pragma unroll
+    for (int k = 0; k < NVMAX; ++k)
+      if (!DOT || k >= nv) acc[k] = 0.0;
     if (NORM) {
 #pragma unroll
       for (int k = 0; k < NVMAX; ++k)
@@ -241,18 +281,19 @@ __global__ __launch_bounds__(kRedThreads) void k_norm2(const T *__restrict__ x, 
 // ---------------------------------------------------------------------------
 // Launch helpers
 // ---------------------------------------------------------------------------
+#define KR_BUCKETS(X) X(8) X(16) X(24) X(32) X(40) X(48) X(56) X(64)
+
 template <typename T>
-hipError_t kr_multidot(const T *V, size_t ld, int nv, const T *w, size_t n, double *partial,
-                       double *out, hipStream_t s) {
+hipError_t kr_multidot(const T *V, size_t ld, int nv, const T *w, size_t n, double *partial, double *out,
+                       hipStream_t s) {
   const dim3 g(kRedBlocks), b(kRedThreads);
-  if (nv <= 8)
-    hipLaunchKernelGGL((k_multidot<T, 8>), g, b, 0, s, V, ld, nv, w, n, partial);
-  else if (nv <= 16)
-    hipLaunchKernelGGL((k_multidot<T, 16>), g, b, 0, s, V, ld, nv, w, n, partial);
-  else if (nv <= 32)
-    hipLaunchKernelGGL((k_multidot<T, 32>), g, b, 0, s, V, ld, nv, w, n, partial);
-  else
-    hipLaunchKernelGGL((k_multidot<T, 64>), g, b, 0, s, V, ld, nv, w, n, partial);
+  if (nv < 1 || nv > 64) return hipErrorInvalidValue;
+#define KR_MD(B)                                                                                \
+  else if (nv <= B) hipLaunchKernelGGL((k_multidot<T, B>), g, b, 0, s, V, ld, nv, w, n, partial);
+  if (false) {
+  }
+  KR_BUCKETS(KR_MD)
+#undef KR_MD
   hipLaunchKernelGGL(k_reduce, dim3(nv), b, 0, s, partial, kRedBlocks, nv, out);
   return hipGetLastError();
 }
@@ -261,14 +302,14 @@ template <typename T, bool DOT, bool NORM>
 hipError_t kr_orth(const T *V, size_t ld, int nv, const double *h, const T *w, T *wout, double scale,
                    size_t n, double *partial, double *out, hipStream_t s) {
   const dim3 g(kRedBlocks), b(kRedThreads);
-  if (nv <= 8)
-    hipLaunchKernelGGL((k_orth<T, 8, DOT, NORM>), g, b, 0, s, V, ld, nv, h, w, wout, scale, n, partial);
-  else if (nv <= 16)
-    hipLaunchKernelGGL((k_orth<T, 16, DOT, NORM>), g, b, 0, s, V, ld, nv, h, w, wout, scale, n, partial);
-  else if (nv <= 32)
-    hipLaunchKernelGGL((k_orth<T, 32, DOT, NORM>), g, b, 0, s, V, ld, nv, h, w, wout, scale, n, partial);
-  else
-    hipLaunchKernelGGL((k_orth<T, 64, DOT, NORM>), g, b, 0, s, V, ld, nv, h, w, wout, scale, n, partial);
+  if (nv < 1 || nv > 64) return hipErrorInvalidValue;
+#define KR_OR(B)      \
+  else if (nv <= B) \
+    hipLaunchKernelGGL((k_orth<T, B, DOT, NORM>), g, b, 0, s, V, ld, nv, h, w, wout, scale, n, partial);
+  if (false) {
+  }
+  KR_BUCKETS(KR_OR)
+#undef KR_OR
   const int nout = (DOT ? nv : 0) + (NORM ? 1 : 0);
   if (nout) hipLaunchKernelGGL(k_reduce, dim3(nout), b, 0, s, partial, kRedBlocks, nout, out);
   return hipGetLastError();
