@@ -195,7 +195,8 @@ dg_status dg_solve(dg_handle *h, const double *f, double *u, double tol, const d
  *   DG_PREC_BLOCK_JACOBI (needs DG_WITH_BLOCK_JACOBI): z_T = A_TT^{-1} r_T with
  *     the FP32 inverse cell blocks, FP64 accumulation;
  *   DG_PREC_LEARNED (needs block Jacobi and a trained or loaded network):
- *     z_T = q_T + s_T N(p_T / s_T), q = BJ r, see dg_learned_train.
+ *     z_T = q_T + s_T (N(p_T/s_T) - N(-p_T/s_T)) / 2, q = BJ r, see
+ *     dg_learned_train.
  * r, z: device, ndof doubles, no overlap.  Asynchronous on hip_stream.
  * DG_EINVAL if the handle has no such preconditioner. */
 dg_status dg_precond_apply(dg_handle *h, int32_t precond, const double *r, double *z, void *hip_stream);
@@ -209,8 +210,10 @@ dg_status dg_precond_apply(dg_handle *h, int32_t precond, const double *r, doubl
  * values; s_T = ||p_T||_2.  The network N is an MLP
  * in = 7 (k+1)^3 -> 256 -> 256 -> out = (k+1)^3 with ReLU after the two
  * hidden layers and biases on all three, run with BF16 weights and
- * activations and FP32 accumulation (MFMA).  The preconditioner adds its
- * correction to block Jacobi:  z_T = q_T + s_T N(p_T / s_T).
+ * activations and FP32 accumulation (MFMA).  The preconditioner adds the odd
+ * part of the network to block Jacobi:
+ *   z_T = q_T + s_T (N(p_T / s_T) - N(-p_T / s_T)) / 2,
+ * so that z(-r) = -z(r) and z(a r) = a z(r) for a > 0.
  *
  * Parameter layout (public, FP32, row-major, n = dg_learned_nparams):
  *   W1 [256 x in] | b1 [256] | W2 [256 x 256] | b2 [256] | W3 [out x 256] | b3 [out]
@@ -241,7 +244,8 @@ typedef struct {
  * (seeded counter-based draws), f = A u*; block-Jacobi GMRES from u = 0
  * stopped after j = 0, 1, 2, 4, ..., max_steps steps gives u_j (u_0 = 0), and
  * the exact pair (r_j = f - A u_j, e_j = u* - u_j) is sampled at uniformly
- * drawn cells, in equal numbers per (u*, j).  With q_j = BJ r_j: input
+ * drawn cells, in equal numbers per (u*, j); the fields come in sign pairs
+ * (u*, -u*).  With q_j = BJ r_j: input
  * p_T / s_T (patch of q_j), target (e_j - q_j)_T / s_T, loss: mean squared error
  * over the out outputs of each row.  W1, W2 start He-normal, W3 and biases
  * at zero (so the untrained preconditioner is block Jacobi).  Adam with FP32

@@ -15,7 +15,8 @@ the operator, Sec. 1); this module restates their textbook definitions:
 * ``adam`` -- one Adam step (Kingma & Ba, 2015, Algorithm 1).
 * ``patches`` / ``precondition`` -- the patch of a cell (cell and six face
   neighbours, zero outside the domain) of q = BJ r (q_T = A_TT^{-1} r_T),
-  its norm s_T, and z_T = q_T + s_T N(p_T / s_T).
+  its norm s_T, and z_T = q_T + s_T (N(p_T / s_T) - N(-p_T / s_T)) / 2
+  (the odd part of the network, so that z(-r) = -z(r)).
 
 Public parameter layout: W1 [H x in] | b1 [H] | W2 [H x H] | b2 [H] |
 W3 [out x H] | b3 [out], row-major.
@@ -138,13 +139,14 @@ def patches(r: np.ndarray, ncell, k: int, cells):
 
 
 def precondition(params, r: np.ndarray, ncell, k: int, blocks: np.ndarray, rounded: bool = True):
-    """z = q_T + s_T N(p_T / s_T) for every cell, q_T = A_TT^{-1} r_T
-    (blocks: A_TT), p_T the patch of q."""
+    """z = q_T + s_T (N(p_T / s_T) - N(-p_T / s_T)) / 2 for every cell,
+    q_T = A_TT^{-1} r_T (blocks: A_TT), p_T the patch of q."""
     nb = (k + 1) ** 3
     ncells = int(np.prod(ncell))
     q = np.linalg.solve(blocks, np.asarray(r, dtype=np.float64).reshape(ncells, nb)[:, :, None])[:, :, 0]
     P, s = patches(q.ravel(), ncell, k, range(ncells))
     safe = np.where(s > 0, s, 1.0)
-    y, _ = forward(params, P / safe[:, None], k, rounded)
-    corr = np.where(s[:, None] > 0, s[:, None] * y, 0.0)
+    yp, _ = forward(params, P / safe[:, None], k, rounded)
+    ym, _ = forward(params, -P / safe[:, None], k, rounded)
+    corr = np.where(s[:, None] > 0, s[:, None] * 0.5 * (yp - ym), 0.0)
     return (q + corr).ravel()

@@ -1,7 +1,9 @@
 // Learned cell-patch preconditioner: BF16 MLP inference and training kernels
 // (gfx950 MFMA), data generation from the solver's own iterates, and the
-// additive preconditioner  M^{-1} r = q + s_T MLP(p_T / s_T)  per cell T,
-// where q = BJ r is the block-Jacobi-preconditioned residual.
+// additive preconditioner
+//   M^{-1} r = q + s_T (MLP(p_T / s_T) - MLP(-p_T / s_T)) / 2  per cell T,
+// where q = BJ r is the block-Jacobi-preconditioned residual (the odd part
+// of the network keeps M^{-1}(-r) = -M^{-1} r, as for a linear map).
 //
 // The paper stops at the operator (Sec. 1 motivates it as the core of
 // iterative solvers); this network is an extension on top of the solver:
@@ -186,16 +188,21 @@ __global__ void k_targets(const double *__restrict__ e, const double *__restrict
   }
 }
 
-// z_T += s_T * Y_T  (the learned correction added to the block-Jacobi part)
+// z_T += fac s_T Y_T  (the learned correction added to the block-Jacobi part)
 template <typename TZ>
 __global__ void k_scatter(const float *__restrict__ Y, const float *__restrict__ s, int64_t first, int64_t nrows,
-                          int nb, int outp, TZ *__restrict__ z) {
+                          int nb, int outp, double fac, TZ *__restrict__ z) {
   GSTRIDE(g, nrows * nb) {
     const int64_t i = g / nb;
     const int j = int(g - i * nb);
     const int64_t o = (first + i) * nb + j;
-    z[o] = TZ(double(z[o]) + double(s[i]) * double(Y[i * outp + j]));
+    z[o] = TZ(double(z[o]) + fac * double(s[i]) * double(Y[i * outp + j]));
   }
+}
+
+// X <- -X (bf16 sign bit, exact)
+__global__ void k_negate_bf16(uint16_t *__restrict__ X, int64_t n) {
+  GSTRIDE(i, n) X[i] ^= uint16_t(0x8000);
 }
 
 // ---------------------------------------------------------------------------
@@ -344,11 +351,11 @@ __host__ __device__ __forceinline__ double u01(uint64_t seed, uint64_t i) {
 
 // random exact solution: coefficient j of cell c is a centred uniform value
 // damped by 1 / (1 + j1 + j2 + j3) (smoother than white noise)
-__global__ void k_random_field(double *__restrict__ u, int64_t n, int nb, int np1, uint64_t seed) {
+__global__ void k_random_field(double *__restrict__ u, int64_t n, int nb, int np1, uint64_t seed, double sign) {
   GSTRIDE(g, n) {
     const int j = int(g % nb);
     const int j1 = j % np1, j2 = (j / np1) % np1, j3 = j / (np1 * np1);
-    u[g] = (2.0 * u01(seed, uint64_t(g)) - 1.0) / double(1 + j1 + j2 + j3);
+    u[g] = sign * (2.0 * u01(seed, uint64_t(g)) - 1.0) / double(1 + j1 + j2 + j3);
   }
 }
 
@@ -607,9 +614,15 @@ hipError_t learned_apply(dg_handle *h, const TR *r, TR *z, hipStream_t s) {
     const int64_t rp = (rows + 63) / 64 * 64;
     hipLaunchKernelGGL(k_gather<double>, dim3(unsigned((rp * 64 + 255) / 256)), dim3(256), 0, s, q, n1, n2, n3,
                        d.nb, d.inp, nullptr, c0, rows, rp, A.X, A.s);
+    // odd part of the network: (N(x) - N(-x)) / 2, so the correction is
+    // homogeneous of degree one in r (z(-r) = -z(r)) like a linear map
     if ((e = forward(M, A, int(rp), s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_scatter<TR>, dim3(blocks_for(rows * d.nb)), dim3(kT), 0, s, A.Y, A.s, c0, rows, d.nb, d.outp,
-                       z);
+                       0.5, z);
+    hipLaunchKernelGGL(k_negate_bf16, dim3(blocks_for(rp * d.inp)), dim3(kT), 0, s, A.X, rp * d.inp);
+    if ((e = forward(M, A, int(rp), s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scatter<TR>, dim3(blocks_for(rows * d.nb)), dim3(kT), 0, s, A.Y, A.s, c0, rows, d.nb, d.outp,
+                       -0.5, z);
   }
   return hipGetLastError();
 }
@@ -655,8 +668,10 @@ static dg_status make_data(dg_handle *h, const dg_learn_opts &o, uint16_t *Xall,
   int64_t row = 0;
   dg_solve_opts so{DG_GMRES64, DG_PREC_BLOCK_JACOBI, 30, 1, 1e-4};
   for (int q = 0; q < o.nrhs && row < npairs; ++q) {
+    // fields come in sign pairs (u*, -u*): the pairs of -u* are exact too and
+    // teach the network the odd symmetry the preconditioner imposes
     hipLaunchKernelGGL(k_random_field, dim3(blocks_for(int64_t(n))), dim3(kT), 0, s, u_star, int64_t(n), d.nb,
-                       h->k + 1, o.seed * 1000003ull + uint64_t(q));
+                       h->k + 1, o.seed * 1000003ull + uint64_t(q / 2), (q & 1) ? -1.0 : 1.0);
     if ((err = apply_f64(h, u_star, f, s)) != hipSuccess) break;
     for (int jj = 0; jj < nj && row < npairs; ++jj) {
       if ((err = hipMemsetAsync(u, 0, n * sizeof(double), s)) != hipSuccess) break;

@@ -194,3 +194,19 @@ def test_trained_network_beats_block_jacobi_alone():
     assert sl["iters"] <= 0.8 * sb["iters"]
     res = np.linalg.norm(f - oracle.apply(p, u)) / np.linalg.norm(f)
     assert res <= 1.05e-8
+
+
+def test_learned_preconditioner_is_odd():
+    torch = _torch()
+    from paper_1711_10885_amd import binding
+    k = 3
+    p, dg = _handle(k, seed=800, ncell=(4, 3, 3), flags=binding.DG_WITH_BLOCK_JACOBI)
+    with dg:
+        dg.learned_set_params(_params(k, 801))
+        r = torch.from_numpy(W.random_vector(p.ndof, 802)).cuda()
+        z1 = dg.precond_apply(r, precond=binding.DG_PREC_LEARNED)
+        z2 = dg.precond_apply(-r, precond=binding.DG_PREC_LEARNED)
+        z3 = dg.precond_apply(4.0 * r, precond=binding.DG_PREC_LEARNED)
+    n = z1.norm().item()
+    assert (z1 + z2).norm().item() <= 1e-14 * n
+    assert (z3 - 4.0 * z1).norm().item() <= 1e-6 * 4 * n  # patch scaling in FP32

@@ -108,3 +108,18 @@ def test_precondition_with_zero_last_layer_is_block_jacobi():
     z = mlp.precondition(p, r, ncell, k, blocks)
     ref = np.concatenate([np.linalg.solve(blocks[c], r[c * nb:(c + 1) * nb]) for c in range(2)])
     assert np.allclose(z, ref, rtol=1e-13, atol=0)
+
+
+def test_precondition_is_odd_in_the_residual():
+    k = 1
+    ncell = (2, 2, 1)
+    nb = 8
+    rng = np.random.default_rng(60)
+    p = _rand_params(k, 61, scale=0.3)
+    blocks = rng.standard_normal((4, nb, nb)) + 5 * np.eye(nb)
+    r = rng.standard_normal(4 * nb)
+    z1 = mlp.precondition(p, r, ncell, k, blocks)
+    z2 = mlp.precondition(p, -r, ncell, k, blocks)
+    z3 = mlp.precondition(p, 2.5 * r, ncell, k, blocks)
+    assert np.allclose(z2, -z1, rtol=1e-13, atol=0)
+    assert np.allclose(z3, 2.5 * z1, rtol=1e-13, atol=0)   # homogeneous of degree one
