@@ -67,7 +67,7 @@ static int blocks_for(int64_t work) {
 // ---------------------------------------------------------------------------
 enum { EPI_F32 = 0, EPI_BIAS_RELU_BF16 = 1, EPI_BIAS_F32 = 2, EPI_MASK_BF16 = 3 };
 
-template <int EPI>
+template <int EPI, bool NEGA = false>
 __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t *__restrict__ A, int lda,
                                                  const uint16_t *__restrict__ B, int ldb, int K,
                                                  float *__restrict__ Cf, uint16_t *__restrict__ Cb, int ldc,
@@ -83,8 +83,12 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t *__restrict__ A,
   const uint16_t *b1 = b0 + size_t(16) * ldb;
   f32x4 c00 = {0, 0, 0, 0}, c01 = c00, c10 = c00, c11 = c00;
   for (int k = 0; k < K; k += 32) {
-    const bf16x8 fa0 = *reinterpret_cast<const bf16x8 *>(a0 + k);
-    const bf16x8 fa1 = *reinterpret_cast<const bf16x8 *>(a1 + k);
+    bf16x8 fa0 = *reinterpret_cast<const bf16x8 *>(a0 + k);
+    bf16x8 fa1 = *reinterpret_cast<const bf16x8 *>(a1 + k);
+    if (NEGA) {
+      fa0 = -fa0;
+      fa1 = -fa1;
+    }
     const bf16x8 fb0 = *reinterpret_cast<const bf16x8 *>(b0 + k);
     const bf16x8 fb1 = *reinterpret_cast<const bf16x8 *>(b1 + k);
     c00 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa0, fb0, c00, 0, 0, 0);
@@ -115,13 +119,96 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t *__restrict__ A,
       }
 }
 
-template <int EPI>
+// Large-tile variant: block tile 128 x 128, K staged through LDS in steps of
+// 32 (rows padded to 40 entries to spread the fragment reads over the banks),
+// four waves of 64 x 64 (4 x 4 MFMA tiles); the next K tile is fetched into
+// registers while the current one is multiplied.  Requires M % 128 == N % 128
+// == 0, K % 32 == 0, lda, ldb % 8 == 0.
+constexpr int kGBM = 128, kGBN = 128, kGBK = 32, kGLd = 40;
+
+template <int EPI, bool NEGA = false>
+__global__ __launch_bounds__(256) void k_gemm_nt_big(const uint16_t *__restrict__ A, int lda,
+                                                     const uint16_t *__restrict__ B, int ldb, int K,
+                                                     float *__restrict__ Cf, uint16_t *__restrict__ Cb, int ldc,
+                                                     const float *__restrict__ bias, const uint16_t *__restrict__ mask,
+                                                     int ldm, float alpha) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[kGBM * kGLd];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[kGBN * kGLd];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int bm = blockIdx.y * kGBM, bn = blockIdx.x * kGBN;
+  // global -> LDS: thread t moves rows t/4 and t/4 + 64, 8 entries at k = 8 (t % 4)
+  const int lrow = t >> 2, lk = (t & 3) * 8;
+  const uint16_t *ga0 = A + size_t(bm + lrow) * lda + lk, *ga1 = ga0 + size_t(64) * lda;
+  const uint16_t *gb0 = B + size_t(bn + lrow) * ldb + lk, *gb1 = gb0 + size_t(64) * ldb;
+  typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+  // NEGA: the A operand enters with flipped signs (bf16 sign bit, exact)
+  const u16x8 sgn = NEGA ? u16x8(uint16_t(0x8000)) : u16x8(uint16_t(0));
+  u16x8 ra0 = *reinterpret_cast<const u16x8 *>(ga0) ^ sgn, ra1 = *reinterpret_cast<const u16x8 *>(ga1) ^ sgn;
+  u16x8 rb0 = *reinterpret_cast<const u16x8 *>(gb0), rb1 = *reinterpret_cast<const u16x8 *>(gb1);
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int fr = lane & 15, fk = (lane >> 4) * 8;
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+  for (int k0 = 0; k0 < K; k0 += kGBK) {
+    *reinterpret_cast<u16x8 *>(As + lrow * kGLd + lk) = ra0;
+    *reinterpret_cast<u16x8 *>(As + (lrow + 64) * kGLd + lk) = ra1;
+    *reinterpret_cast<u16x8 *>(Bs + lrow * kGLd + lk) = rb0;
+    *reinterpret_cast<u16x8 *>(Bs + (lrow + 64) * kGLd + lk) = rb1;
+    __syncthreads();
+    if (k0 + kGBK < K) {  // prefetch the next K tile while this one is multiplied
+      ra0 = *reinterpret_cast<const u16x8 *>(ga0 + k0 + kGBK) ^ sgn;
+      ra1 = *reinterpret_cast<const u16x8 *>(ga1 + k0 + kGBK) ^ sgn;
+      rb0 = *reinterpret_cast<const u16x8 *>(gb0 + k0 + kGBK);
+      rb1 = *reinterpret_cast<const u16x8 *>(gb1 + k0 + kGBK);
+    }
+    bf16x8 fa[4], fb[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      fa[i] = *reinterpret_cast<const bf16x8 *>(As + (wm + 16 * i + fr) * kGLd + fk);
+      fb[i] = *reinterpret_cast<const bf16x8 *>(Bs + (wn + 16 * i + fr) * kGLd + fk);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = bm + wm + 16 * i + (lane >> 4) * 4 + q;
+        const int n = bn + wn + 16 * j + fr;
+        const float v = alpha * acc[i][j][q];
+        const size_t o = size_t(m) * ldc + n;
+        if (EPI == EPI_F32) {
+          Cf[o] = v;
+        } else if (EPI == EPI_BIAS_F32) {
+          Cf[o] = v + bias[n];
+        } else if (EPI == EPI_BIAS_RELU_BF16) {
+          Cb[o] = f2bf(fmaxf(v + bias[n], 0.0f));
+        } else {
+          Cb[o] = f2bf(bf2f(mask[size_t(m) * ldm + n]) > 0.0f ? v : 0.0f);
+        }
+      }
+}
+
+template <int EPI, bool NEGA = false>
 static hipError_t gemm(const uint16_t *A, int lda, const uint16_t *B, int ldb, int M, int N, int K, float *Cf,
                        uint16_t *Cb, int ldc, const float *bias, const uint16_t *mask, int ldm, float alpha,
                        hipStream_t s) {
   if (M % 64 || N % 64 || K % 32 || lda % 8 || ldb % 8) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_gemm_nt<EPI>), dim3(N / 64, M / 64), dim3(256), 0, s, A, lda, B, ldb, K, Cf, Cb, ldc,
-                     bias, mask, ldm, alpha);
+  if (M % kGBM == 0 && N % kGBN == 0)
+    hipLaunchKernelGGL((k_gemm_nt_big<EPI, NEGA>), dim3(N / kGBN, M / kGBM), dim3(256), 0, s, A, lda, B, ldb, K, Cf,
+                       Cb, ldc, bias, mask, ldm, alpha);
+  else
+    hipLaunchKernelGGL((k_gemm_nt<EPI, NEGA>), dim3(N / 64, M / 64), dim3(256), 0, s, A, lda, B, ldb, K, Cf, Cb,
+                       ldc, bias, mask, ldm, alpha);
   return hipGetLastError();
 }
 
@@ -153,23 +240,44 @@ __global__ __launch_bounds__(256) void k_gather(const TR *__restrict__ r, int n1
     if (e ? ia + 1 >= na : ia == 0) return -1;
     return e ? c + st : c - st;
   };
+  if (nb <= 64) {
+    // lane j owns coefficient j of each of the 7 patch cells (coalesced rows)
+    double v[7];
+    double ss = 0.0;
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+      const int64_t cn = nbr(q);
+      v[q] = (lane < nb && cn >= 0) ? double(r[cn * nb + lane]) : 0.0;
+      ss = fma(v[q], v[q], ss);
+    }
+    for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
+    const double sn = std::sqrt(ss);
+    const double inv = sn > 0.0 ? 1.0 / sn : 0.0;
+    if (lane < nb) {
+#pragma unroll
+      for (int q = 0; q < 7; ++q) xr[q * nb + lane] = f2bf(float(v[q] * inv));
+    }
+    for (int t = 7 * nb + lane; t < inp; t += 64) xr[t] = 0;
+    if (lane == 0) s[row] = float(sn);
+    return;
+  }
   double ss = 0.0;
-  for (int t = lane; t < 7 * nb; t += 64) {
-    const int64_t cn = nbr(t / nb);
-    const double v = cn >= 0 ? double(r[cn * nb + t % nb]) : 0.0;
-    ss = fma(v, v, ss);
+  for (int q = 0; q < 7; ++q) {
+    const int64_t cn = nbr(q);
+    if (cn < 0) continue;
+    for (int j = lane; j < nb; j += 64) {
+      const double v = double(r[cn * nb + j]);
+      ss = fma(v, v, ss);
+    }
   }
   for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
   const double sn = std::sqrt(ss);
   const double inv = sn > 0.0 ? 1.0 / sn : 0.0;
-  for (int t = lane; t < inp; t += 64) {
-    double v = 0.0;
-    if (t < 7 * nb) {
-      const int64_t cn = nbr(t / nb);
-      v = cn >= 0 ? double(r[cn * nb + t % nb]) : 0.0;
-    }
-    xr[t] = f2bf(float(v * inv));
+  for (int q = 0; q < 7; ++q) {
+    const int64_t cn = nbr(q);
+    for (int j = lane; j < nb; j += 64) xr[q * nb + j] = f2bf(cn >= 0 ? float(double(r[cn * nb + j]) * inv) : 0.0f);
   }
+  for (int t = 7 * nb + lane; t < inp; t += 64) xr[t] = 0;
   if (lane == 0) s[row] = float(sn);
 }
 
@@ -200,10 +308,6 @@ __global__ void k_scatter(const float *__restrict__ Y, const float *__restrict__
   }
 }
 
-// X <- -X (bf16 sign bit, exact)
-__global__ void k_negate_bf16(uint16_t *__restrict__ X, int64_t n) {
-  GSTRIDE(i, n) X[i] ^= uint16_t(0x8000);
-}
 
 // ---------------------------------------------------------------------------
 // Training kernels
@@ -524,13 +628,15 @@ static dg_status acts_for(dg_handle *h, int64_t rows, bool train, Acts &A) {
   return DG_OK;
 }
 
-// forward for rows (multiple of 64) of A.X -> A.H1, A.H2, A.Y
-static hipError_t forward(Mlp *M, const Acts &A, int rows, hipStream_t s) {
+// forward for rows (multiple of 64) of A.X (or -A.X) -> A.H1, A.H2, A.Y
+static hipError_t forward(Mlp *M, const Acts &A, int rows, hipStream_t s, bool neg_x = false) {
   const MlpDims &d = M->d;
   hipError_t e;
-  if ((e = gemm<EPI_BIAS_RELU_BF16>(A.X, d.inp, M->wt + d.oc_W1, d.inp, rows, d.hid, d.inp, nullptr, A.H1, d.hid,
-                                    M->master + d.ob1, nullptr, 0, 1.0f, s)) != hipSuccess)
-    return e;
+  e = neg_x ? gemm<EPI_BIAS_RELU_BF16, true>(A.X, d.inp, M->wt + d.oc_W1, d.inp, rows, d.hid, d.inp, nullptr, A.H1,
+                                             d.hid, M->master + d.ob1, nullptr, 0, 1.0f, s)
+            : gemm<EPI_BIAS_RELU_BF16>(A.X, d.inp, M->wt + d.oc_W1, d.inp, rows, d.hid, d.inp, nullptr, A.H1, d.hid,
+                                       M->master + d.ob1, nullptr, 0, 1.0f, s);
+  if (e != hipSuccess) return e;
   if ((e = gemm<EPI_BIAS_RELU_BF16>(A.H1, d.hid, M->wt + d.oc_W2, d.hid, rows, d.hid, d.hid, nullptr, A.H2, d.hid,
                                     M->master + d.ob2, nullptr, 0, 1.0f, s)) != hipSuccess)
     return e;
@@ -619,8 +725,7 @@ hipError_t learned_apply(dg_handle *h, const TR *r, TR *z, hipStream_t s) {
     if ((e = forward(M, A, int(rp), s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_scatter<TR>, dim3(blocks_for(rows * d.nb)), dim3(kT), 0, s, A.Y, A.s, c0, rows, d.nb, d.outp,
                        0.5, z);
-    hipLaunchKernelGGL(k_negate_bf16, dim3(blocks_for(rp * d.inp)), dim3(kT), 0, s, A.X, rp * d.inp);
-    if ((e = forward(M, A, int(rp), s)) != hipSuccess) return e;
+    if ((e = forward(M, A, int(rp), s, true)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_scatter<TR>, dim3(blocks_for(rows * d.nb)), dim3(kT), 0, s, A.Y, A.s, c0, rows, d.nb, d.outp,
                        -0.5, z);
   }

@@ -42,8 +42,10 @@ def _handle(k, seed=700, ncell=(2, 2, 2), flags=0):
     return p, binding.DG(p, flags=flags)
 
 
-@pytest.mark.parametrize("k", [1, 2, 3])
-def test_forward_matches_oracle(k):
+@pytest.mark.parametrize("k,B", [(1, 192), (2, 192), (3, 192), (3, 512), (1, 384)])
+def test_forward_matches_oracle(k, B):
+    """B = 192: the 64 x 64-tile GEMM kernel; B a multiple of 128: the
+    LDS-staged 128 x 128-tile kernel for the 256-wide layers."""
     torch = _torch()
     p, dg = _handle(k)
     with dg:
@@ -51,7 +53,7 @@ def test_forward_matches_oracle(k):
         dg.learned_set_params(params)
         assert np.array_equal(dg.learned_get_params(), params)
         nin, nout = mlp.sizes(k)
-        X = np.random.default_rng(720 + k).standard_normal((192, nin)).astype(np.float32)
+        X = np.random.default_rng(720 + k).standard_normal((B, nin)).astype(np.float32)
         Y = dg.mlp_forward(torch.from_numpy(X).cuda()).cpu().numpy()
     ref, _ = mlp.forward(params.astype(np.float64), X.astype(np.float64), k)
     e = _rel(Y, ref)
@@ -59,14 +61,14 @@ def test_forward_matches_oracle(k):
     assert e <= 1e-3
 
 
-@pytest.mark.parametrize("k", [1, 3])
-def test_gradients_match_oracle(k):
+@pytest.mark.parametrize("k,B", [(1, 128), (3, 128), (3, 192)])
+def test_gradients_match_oracle(k, B):
     torch = _torch()
     p, dg = _handle(k)
     nin, nout = mlp.sizes(k)
     rng = np.random.default_rng(730 + k)
-    X = rng.standard_normal((128, nin)).astype(np.float32)
-    T = rng.standard_normal((128, nout)).astype(np.float32)
+    X = rng.standard_normal((B, nin)).astype(np.float32)
+    T = rng.standard_normal((B, nout)).astype(np.float32)
     params = _params(k, 740 + k)
     with dg:
         dg.learned_set_params(params)
@@ -105,11 +107,14 @@ def test_adam_step_matches_oracle():
     assert np.all(np.abs(step) <= lr * (1 + 1e-6) + np.spacing(np.abs(params).astype(np.float32)))
 
 
-def test_learned_preconditioner_matches_oracle():
+@pytest.mark.parametrize("ncell", [(3, 2, 2), (8, 4, 4)])
+def test_learned_preconditioner_matches_oracle(ncell):
+    """12 cells run the 64 x 64-tile GEMM, 128 cells the 128 x 128-tile one
+    (both with the sign-flipped pass of the odd part)."""
     torch = _torch()
     from paper_1711_10885_amd import binding
     k = 2
-    p, dg = _handle(k, seed=760, ncell=(3, 2, 2), flags=binding.DG_WITH_BLOCK_JACOBI)
+    p, dg = _handle(k, seed=760, ncell=ncell, flags=binding.DG_WITH_BLOCK_JACOBI)
     params = _params(k, 761)
     r = W.random_vector(p.ndof, 762)
     with dg:
