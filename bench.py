@@ -15,7 +15,8 @@ gives the average kernel duration used for the roofline.
 By default the run also times the solves (the second half of the metric):
 plain FP64 GMRES(30) against GMRES-IR to 1e-8 on the 48^3 k=5 workload, and
 block-Jacobi FGMRES(30) against the learned preconditioner on the 64^3 k=3
-workload for a fixed step budget (--solves none skips them).
+workload for a fixed step budget (--solves none skips them; the degree-sweep
+workloads skip them unless asked).
 
 Prints ONE JSON line.  Algorithmic FLOPs use the per-DOF lower bound of
 Sec. 3.6 (FLOPDOF_vol + FLOPDOF_face for d = 3); peak is the MI355X FP64
@@ -196,8 +197,9 @@ def main():
     ap.add_argument("--variant", type=int, default=0, help="0 tuned kernel, 1 reference kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
-    ap.add_argument("--solves", default="all", choices=["none", "mixed", "learned", "all"],
-                    help="also time the solves to 1e-8 (plain FP64 vs mixed, block Jacobi vs learned)")
+    ap.add_argument("--solves", default=None, choices=["none", "mixed", "learned", "all"],
+                    help="also time the solves to 1e-8 (plain FP64 vs mixed, block Jacobi vs learned); "
+                         "default: all for the headline workload, none for the others")
     ap.add_argument("--solve-maxit", type=int, default=20000,
                     help="Arnoldi-step cap of the mixed-precision comparison")
     ap.add_argument("--learned-maxit", type=int, default=5000,
@@ -205,6 +207,8 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
+    if args.solves is None:
+        args.solves = "all" if args.workload == "cdr_k7_32" else "none"
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)

@@ -1011,6 +1011,226 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
   }
 }
 
+// ---------------------------------------------------------------------------
+// One cell per lane (k = 1): the whole 2x2x2 cell lives in registers, so
+// there is no LDS exchange and no barrier.  Same operator, same face
+// constants and flux as the pencil kernel; the volume uses the direct tensor
+// sums (N^3 terms per point value, which for N = 2 is no more work than the
+// factorised sweeps) and the faces contract the normal direction first.
+// Cells are taken in natural order inside contiguous per-XCD ranges, so the
+// face neighbours of a range are mostly L2 hits.
+// ---------------------------------------------------------------------------
+template <int N, typename T>
+struct LaneTab {
+  static constexpr int H = (N + 1) / 2;
+  static __device__ __forceinline__ T V(int q, int j) {
+    const double v = GLTab<N>::v[TabOff<N>::V + (q < H ? q : N - 1 - q) * N + j];
+    return T((q < H || (j & 1) == 0) ? v : -v);  // theta_j(1-t) = (-1)^j theta_j(t)
+  }
+  static __device__ __forceinline__ T D(int q, int j) {
+    const double v = GLTab<N>::v[TabOff<N>::D + (q < H ? q : N - 1 - q) * N + j];
+    return T((q < H || (j & 1) == 1) ? v : -v);  // theta_j'(1-t) = (-1)^(j+1) theta_j'(t)
+  }
+  static __device__ __forceinline__ T E(int e, int j) {  // theta_j(e), e = 0, 1
+    const double v = GLTab<N>::v[TabOff<N>::E1 + j];
+    return T((e == 1 || (j & 1) == 0) ? v : -v);
+  }
+  static __device__ __forceinline__ T F(int e, int j) {  // theta_j'(e)
+    const double v = GLTab<N>::v[TabOff<N>::F1 + j];
+    return T((e == 1 || (j & 1) == 1) ? v : -v);
+  }
+  static __device__ __forceinline__ double W(int q) { return GLTab<N>::v[TabOff<N>::W + (q < H ? q : N - 1 - q)]; }
+};
+
+template <int N, typename T>
+__global__ __launch_bounds__(256) void apply_lane_kernel(const T *__restrict__ x, T *__restrict__ y, FMesh M) {
+  constexpr int NN = N * N, NNN = N * N * N;
+  using TB = LaneTab<N, T>;
+  const int wg = blockIdx.x;
+  const int lblock = (wg & 7) * M.groups + (wg >> 3);
+  const int cell = lblock * 256 + int(threadIdx.x);
+  if (cell >= M.ncells) return;
+  FaceGeo G;
+  G.i0 = cell % M.ncell[0];
+  G.i1 = (cell / M.ncell[0]) % M.ncell[1];
+  G.i2 = cell / (M.ncell[0] * M.ncell[1]);
+  G.h0 = M.h[0][G.i0];
+  G.h1 = M.h[1][G.i1];
+  G.h2 = M.h[2][G.i2];
+  G.kap = M.kappa ? M.kappa[cell] : 1.0;
+  T X[NNN], Y[NNN];
+  {
+    const T *xp = x + size_t(cell) * NNN;
+#pragma unroll
+    for (int j = 0; j < NNN; ++j) {
+      X[j] = xp[j];
+      Y[j] = T(0);
+    }
+  }
+  // ---- volume (Alg. 1 steps 1-3) ----
+  {
+    const double vol = G.h0 * G.h1 * G.h2;
+    const double ihd[3] = {1.0 / G.h0, 1.0 / G.h1, 1.0 / G.h2};
+    const int ic[3] = {G.i0, G.i1, G.i2};
+    T Kh[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) Kh[3 * r + c] = T(G.kap * M.K[3 * r + c] * ihd[r] * ihd[c]);
+    const T cc = T(M.c);
+#pragma unroll
+    for (int q3 = 0; q3 < N; ++q3)
+#pragma unroll
+      for (int q2 = 0; q2 < N; ++q2)
+#pragma unroll
+        for (int q1 = 0; q1 < N; ++q1) {
+          T u = 0, g1 = 0, g2 = 0, g3 = 0;
+#pragma unroll
+          for (int j3 = 0; j3 < N; ++j3)
+#pragma unroll
+            for (int j2 = 0; j2 < N; ++j2)
+#pragma unroll
+              for (int j1 = 0; j1 < N; ++j1) {
+                const T xv = X[j1 + N * j2 + NN * j3];
+                const T v1 = TB::V(q1, j1), v2 = TB::V(q2, j2), v3 = TB::V(q3, j3);
+                u = fma(v1 * v2 * v3, xv, u);
+                g1 = fma(TB::D(q1, j1) * v2 * v3, xv, g1);
+                g2 = fma(v1 * TB::D(q2, j2) * v3, xv, g2);
+                g3 = fma(v1 * v2 * TB::D(q3, j3), xv, g3);
+              }
+          const int qa[3] = {q1, q2, q3};
+          T bh[3];
+#pragma unroll
+          for (int r = 0; r < 3; ++r) {
+            const int ax = M.b_axis[r];
+            const int qx = ax == 0 ? qa[0] : (ax == 1 ? qa[1] : qa[2]);
+            const int ix = ax == 0 ? ic[0] : (ax == 1 ? ic[1] : ic[2]);
+            bh[r] = T(M.bvol[r][ix * N + qx] * ihd[r]);
+          }
+          const T W = T(TB::W(q1) * TB::W(q2) * TB::W(q3) * vol);
+          const T f0 = W * cc * u;
+          const T f1 = W * (Kh[0] * g1 + Kh[1] * g2 + Kh[2] * g3 - bh[0] * u);
+          const T f2 = W * (Kh[3] * g1 + Kh[4] * g2 + Kh[5] * g3 - bh[1] * u);
+          const T f3 = W * (Kh[6] * g1 + Kh[7] * g2 + Kh[8] * g3 - bh[2] * u);
+#pragma unroll
+          for (int j3 = 0; j3 < N; ++j3)
+#pragma unroll
+            for (int j2 = 0; j2 < N; ++j2)
+#pragma unroll
+              for (int j1 = 0; j1 < N; ++j1) {
+                const T v1 = TB::V(q1, j1), v2 = TB::V(q2, j2), v3 = TB::V(q3, j3);
+                T acc = Y[j1 + N * j2 + NN * j3];
+                acc = fma(v1 * v2 * v3, f0, acc);
+                acc = fma(TB::D(q1, j1) * v2 * v3, f1, acc);
+                acc = fma(v1 * TB::D(q2, j2) * v3, f2, acc);
+                acc = fma(v1 * v2 * TB::D(q3, j3), f3, acc);
+                Y[j1 + N * j2 + NN * j3] = acc;
+              }
+        }
+  }
+  // ---- faces (Alg. 1 steps 4-10), owner computes ----
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const int a = f >> 1, e = f & 1;
+    const int b = (a == 0) ? 1 : 0, c = (a == 2) ? 1 : 2;
+    const FC F = face_coef(M, G, cell, a, e);
+    const int ia = a == 0 ? G.i0 : (a == 1 ? G.i1 : G.i2);
+    const bool in = e ? (ia + 1 < M.ncell[a]) : (ia > 0);
+    const int cst = (a == 0) ? 1 : (a == 1) ? M.ncell[0] : M.ncell[0] * M.ncell[1];
+    T XN[NNN];
+    {
+      const T *xn = x + size_t(in ? (e ? cell + cst : cell - cst) : cell) * NNN;
+#pragma unroll
+      for (int j = 0; j < NNN; ++j) XN[j] = in ? xn[j] : T(0);
+    }
+    const int sa = a == 0 ? 1 : (a == 1 ? N : NN), sb = b == 0 ? 1 : (b == 1 ? N : NN), sc = c == 1 ? N : NN;
+    // normal direction first: traces of u and d_a u on the face, coefficients in (jb, jc)
+    T To[NN], Tdo[NN], Tn[NN], Tdn[NN];
+#pragma unroll
+    for (int jc = 0; jc < N; ++jc)
+#pragma unroll
+      for (int jb = 0; jb < N; ++jb) {
+        T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+#pragma unroll
+        for (int ja = 0; ja < N; ++ja) {
+          const int j = ja * sa + jb * sb + jc * sc;
+          s0 = fma(TB::E(e, ja), X[j], s0);
+          s1 = fma(TB::F(e, ja), X[j], s1);
+          s2 = fma(TB::E(1 - e, ja), XN[j], s2);
+          s3 = fma(TB::F(1 - e, ja), XN[j], s3);
+        }
+        To[jb + N * jc] = s0;
+        Tdo[jb + N * jc] = s1;
+        Tn[jb + N * jc] = s2;
+        Tdn[jb + N * jc] = s3;
+      }
+    const double hb = b == 0 ? G.h0 : G.h1;
+    const double hc = c == 1 ? G.h1 : G.h2;
+    T Rv[NN], Rd[NN];
+#pragma unroll
+    for (int i = 0; i < NN; ++i) Rv[i] = Rd[i] = T(0);
+    const T cTa = T(F.cTa), cTb = T(F.cTb), cTc = T(F.cTc);
+#pragma unroll
+    for (int qc = 0; qc < N; ++qc)
+#pragma unroll
+      for (int qb = 0; qb < N; ++qb) {
+        T uo = 0, gao = 0, gbo = 0, gco = 0, un = 0, gan = 0, gbn = 0, gcn = 0;
+#pragma unroll
+        for (int jc = 0; jc < N; ++jc)
+#pragma unroll
+          for (int jb = 0; jb < N; ++jb) {
+            const T vv = TB::V(qb, jb) * TB::V(qc, jc);
+            const T dv = TB::D(qb, jb) * TB::V(qc, jc), vd = TB::V(qb, jb) * TB::D(qc, jc);
+            const int i = jb + N * jc;
+            uo = fma(vv, To[i], uo);
+            gao = fma(vv, Tdo[i], gao);
+            gbo = fma(dv, To[i], gbo);
+            gco = fma(vd, To[i], gco);
+            un = fma(vv, Tn[i], un);
+            gan = fma(vv, Tdn[i], gan);
+            gbn = fma(dv, Tn[i], gbn);
+            gcn = fma(vd, Tn[i], gcn);
+          }
+        // pointwise face flux in FP64 (penalty, weighted average, upwind)
+        const double avg = F.cTa * double(gao) + F.cTb * double(gbo) + F.cTc * double(gco) +
+                           F.cNa * double(gan) + F.cNb * double(gbn) + F.cNc * double(gcn);
+        const double W = TB::W(qb) * TB::W(qc) * hb * hc;
+        double RV, Z;
+        face_flux(F, double(uo), double(un), avg, face_b(M, G, N, a, e, qb, qc), W, RV, Z);
+        const T rv = T(RV), z = T(Z);
+#pragma unroll
+        for (int jc = 0; jc < N; ++jc)
+#pragma unroll
+          for (int jb = 0; jb < N; ++jb) {
+            const T vv = TB::V(qb, jb) * TB::V(qc, jc);
+            const T dv = TB::D(qb, jb) * TB::V(qc, jc), vd = TB::V(qb, jb) * TB::D(qc, jc);
+            const int i = jb + N * jc;
+            Rv[i] = fma(vv, rv, Rv[i]);
+            Rv[i] = fma(cTb * dv + cTc * vd, z, Rv[i]);
+            Rd[i] = fma(cTa * vv, z, Rd[i]);
+          }
+      }
+    // normal direction last: theta(e) for the value part, theta'(e) for d_a
+#pragma unroll
+    for (int jc = 0; jc < N; ++jc)
+#pragma unroll
+      for (int jb = 0; jb < N; ++jb)
+#pragma unroll
+        for (int ja = 0; ja < N; ++ja) {
+          const int j = ja * sa + jb * sb + jc * sc;
+          Y[j] = fma(TB::E(e, ja), Rv[jb + N * jc], Y[j]);
+          Y[j] = fma(TB::F(e, ja), Rd[jb + N * jc], Y[j]);
+        }
+    // materialise Y here (no instruction is emitted), so that this face's
+    // accumulators die before the next face instead of all six staying live
+#pragma unroll
+    for (int j = 0; j < NNN; ++j) asm volatile("" : "+v"(Y[j]));
+  }
+  T *yp = y + size_t(cell) * NNN;
+#pragma unroll
+  for (int j = 0; j < NNN; ++j) yp[j] = Y[j];
+}
+
 template <int N, typename T>
 static hipError_t launch_fused_n(const dg_handle *h, const T *x, T *y, hipStream_t s) {
   using C = FCfg<N>;
@@ -1031,6 +1251,12 @@ static hipError_t launch_fused_n(const dg_handle *h, const T *x, T *y, hipStream
   // tiles of up to 4 cells along axis 3: z neighbours are adjacent in the
   // processing order, y neighbours 4*N1 cells apart
   M.tz = h->mesh.ncell[2] < 4 ? h->mesh.ncell[2] : 4;
+  if (N == 2) {  // k = 1: one cell per lane
+    const int nblocks = int((h->ncells + 255) / 256);
+    M.groups = (nblocks + 7) / 8;
+    hipLaunchKernelGGL((apply_lane_kernel<2, T>), dim3(unsigned(8 * M.groups)), dim3(256), 0, s, x, y, M);
+    return hipGetLastError();
+  }
   const int nblocks = int((h->ncells + C::CPB - 1) / C::CPB);
   M.groups = (nblocks + 7) / 8;
   hipLaunchKernelGGL((apply_fused_kernel<N, T>), dim3(unsigned(8 * M.groups)), dim3(C::THREADS), 0, s,
