@@ -148,9 +148,10 @@ extern "C" dg_status dg_solve(dg_handle *h, const double *f, double *u, double t
     // can decide the fallback to block Jacobi
     bool learned = opt.precond == DG_PREC_LEARNED;
     auto op = [h, s](const double *x, double *y) { return apply_f64(h, x, y, s); };
+    // after a fallback the learned preconditioner continues as block Jacobi
     auto prec = [h, s, &learned, &opt](const double *v, double *z) {
       if (learned) return learned_apply<double>(h, v, z, s);
-      if (opt.precond == DG_PREC_BLOCK_JACOBI) return bj_apply<double, double>(h, v, z, s);
+      if (opt.precond != DG_PREC_NONE) return bj_apply<double, double>(h, v, z, s);
       return kr_scale<double, double>(v, z, 1.0, size_t(h->ndof), s);
     };
     bool zero = un2 == 0.0;

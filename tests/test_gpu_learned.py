@@ -154,10 +154,17 @@ def test_non_finite_network_falls_back_to_block_jacobi():
     params = _params(k, 782)
     params[-1] = np.nan  # last output bias
     with binding.DG(p, flags=binding.DG_WITH_BLOCK_JACOBI) as dg:
+        fd = torch.from_numpy(f).cuda()
+        ub, sb, _ = dg.solve(fd, tol=1e-9, method=binding.DG_FGMRES, precond=binding.DG_PREC_BLOCK_JACOBI)
         dg.learned_set_params(params)
-        u, st, rc = dg.solve(torch.from_numpy(f).cuda(), tol=1e-9, method=binding.DG_FGMRES,
-                             precond=binding.DG_PREC_LEARNED)
+        u, st, rc = dg.solve(fd, tol=1e-9, method=binding.DG_FGMRES, precond=binding.DG_PREC_LEARNED)
     assert rc == 0 and st["fallback_used"] == 1
+    # the first step yields a non-finite Hessenberg column, the cycle is
+    # dropped before any update, and FGMRES restarts from u = 0 with block
+    # Jacobi: the same iteration as block Jacobi alone (not an
+    # unpreconditioned one)
+    assert st["iters"] == sb["iters"], (st, sb)
+    assert torch.allclose(u, ub, rtol=0, atol=1e-12 * ub.abs().max().item())
     res = np.linalg.norm(f - oracle.apply(p, u.cpu().numpy())) / np.linalg.norm(f)
     assert res <= 1.05e-9
 
