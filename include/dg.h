@@ -79,7 +79,13 @@ typedef enum {
  *              probing, inverted in FP64 (Gauss-Jordan; coercivity makes every
  *              block positive real, so no pivoting) and stored in FP32:
  *              4 ncells (k+1)^6 bytes, plus 8 ncells (k+1)^6 bytes while
- *              building.
+ *              building.  Cells whose blocks are equal by construction (the
+ *              same spacings of the cell and of its face neighbours along
+ *              each axis, the same kappa on the cell and its neighbours, all
+ *              to about 1e-11 relative, the same boundary faces, and b
+ *              without a sine part) share one stored block when that at
+ *              least halves the store: a uniform mesh with constant
+ *              coefficients has 27 blocks.
  */
 typedef struct {
   int32_t ncell[3];
@@ -283,6 +289,11 @@ int64_t dg_ndof(const dg_handle *h);
 
 /* Polynomial degree of the handle (or -1 for NULL). */
 int32_t dg_degree(const dg_handle *h);
+
+/* Number of inverse cell blocks the block-Jacobi preconditioner stores: the
+ * number of cells, or the number of cell classes when cells share their
+ * block (see DG_WITH_BLOCK_JACOBI); 0 without block Jacobi, -1 for NULL. */
+int64_t dg_bj_nblocks(const dg_handle *h);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *dg_last_error(void);

@@ -26,8 +26,8 @@ _STATUS = {DG_EINVAL: "DG_EINVAL", DG_ENOMEM: "DG_ENOMEM", DG_EHIP: "DG_EHIP",
 # every symbol include/dg.h declares
 EXPORTS = ["dg_setup", "dg_apply", "dg_apply_f32", "dg_load_vector", "dg_set_kernel", "dg_solve", "dg_precond_apply",
            "dg_learned_train", "dg_learned_nparams", "dg_learned_set_params", "dg_learned_get_params",
-           "dg_mlp_forward", "dg_mlp_grad", "dg_mlp_step", "dg_ndof", "dg_degree", "dg_last_error",
-           "dg_destroy"]
+           "dg_mlp_forward", "dg_mlp_grad", "dg_mlp_step", "dg_ndof", "dg_degree", "dg_bj_nblocks",
+           "dg_last_error", "dg_destroy"]
 
 
 class DGError(RuntimeError):
@@ -131,6 +131,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dg_ndof.restype = ctypes.c_int64
     lib.dg_degree.argtypes = [H]
     lib.dg_degree.restype = ctypes.c_int32
+    lib.dg_bj_nblocks.argtypes = [H]
+    lib.dg_bj_nblocks.restype = ctypes.c_int64
     lib.dg_last_error.argtypes = []
     lib.dg_last_error.restype = ctypes.c_char_p
     lib.dg_destroy.argtypes = [H]
@@ -253,6 +255,10 @@ class DG:
         _check(load().dg_apply_f32(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
                                    _stream_ptr(stream)))
         return y
+
+    def bj_nblocks(self) -> int:
+        """Inverse cell blocks stored by block Jacobi (ncells, or fewer when shared)."""
+        return int(load().dg_bj_nblocks(self._h))
 
     def precond_apply(self, r, z=None, precond: int = DG_PREC_BLOCK_JACOBI, stream=None):
         """z := M^{-1} r for the handle's preconditioner (float64 device tensors)."""

@@ -24,9 +24,25 @@
 // 16-byte load (VR = 4 in FP32, 8 in FP16; one row per thread when (k+1)^3
 // is not a multiple of VR); FP64 accumulation.  HBM-bound: 4 (FP32) or 2
 // (FP16) (k+1)^3 bytes of block store per DOF.
+//
+// Shared blocks: A_TT is a function of the cell's spacings, its face
+// neighbours' spacings along each axis (the penalty), kappa on the cell and
+// its neighbours (weights and penalty), which faces lie on the boundary, and
+// b at the cell's quadrature points (Sec. 2.2).  Cells equal in all of these
+// (to about 1e-11 relative) have equal blocks, so one block per class is
+// probed, inverted and stored
+// (on a uniform mesh with constant coefficients: 27 classes, one per
+// combination of boundary faces).  The apply then walks groups of kBjGroup
+// cells of one class: each block column is loaded once per group and used
+// for all its cells, and the small class store stays in cache, so the apply
+// moves little more than r and z.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <string>
+#include <type_traits>
+#include <unordered_map>
+#include <vector>
 
 #include "dg_internal.h"
 
@@ -44,16 +60,18 @@ __global__ void k_bj_probe(double *__restrict__ x, int n1, int n2, int64_t ncell
   }
 }
 
-// B[c][j*nb + i] = y[c*nb + i] on cells of the given colour (column j)
-__global__ void k_bj_gather(const double *__restrict__ y, double *__restrict__ B, int n1, int n2,
-                            int64_t ncells, int nb, int j, int colour) {
+// B[slot][j*nb + i] = y[c*nb + i] on cells of the given colour (column j);
+// slot = c, or slot[c] when blocks are shared (-1: not stored)
+__global__ void k_bj_gather(const double *__restrict__ y, double *__restrict__ B, const int32_t *__restrict__ slot,
+                            int n1, int n2, int64_t ncells, int nb, int j, int colour) {
   const int64_t total = ncells * nb;
   for (int64_t g = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; g < total;
        g += int64_t(gridDim.x) * blockDim.x) {
     const int64_t c = g / nb;
     const int i = int(g - c * nb);
     const int64_t i1 = c % n1, r = c / n1, i2 = r % n2, i3 = r / n2;
-    if (int((i1 + i2 + i3) & 1) == colour) B[c * int64_t(nb) * nb + int64_t(j) * nb + i] = y[g];
+    const int64_t b = slot ? int64_t(slot[c]) : c;
+    if (int((i1 + i2 + i3) & 1) == colour && b >= 0) B[b * int64_t(nb) * nb + int64_t(j) * nb + i] = y[g];
   }
 }
 
@@ -197,6 +215,65 @@ __global__ __launch_bounds__(kBjThreads) void k_bj_apply_vec(const TB *__restric
   }
 }
 
+// shared blocks: thread (group, VR rows) applies the group's block to its
+// kBjGroup cells; padding entries (-1) read the group's first cell and
+// write nothing.  TA: accumulation type.
+template <typename TR, typename TZ, typename TA, int VR>
+__global__ __launch_bounds__(kBjThreads) void k_bj_apply_grp(const float *__restrict__ Binv,
+                                                             const int32_t *__restrict__ cells,
+                                                             const int32_t *__restrict__ gblock,
+                                                             const TR *__restrict__ r, TZ *__restrict__ z, int nb,
+                                                             int64_t ngroups) {
+  const int per = nb / VR;
+  const int64_t total = ngroups * per;
+  for (int64_t g = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; g < total;
+       g += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t grp = g / per;
+    const int i0 = int(g - grp * per) * VR;
+    const float *Bc = Binv + int64_t(gblock[grp]) * nb * nb + i0;
+    const int32_t *cg = cells + grp * kBjGroup;
+    const int32_t c0 = cg[0];
+    int64_t off[kBjGroup];
+    bool live[kBjGroup];
+#pragma unroll
+    for (int q = 0; q < kBjGroup; ++q) {
+      const int32_t c = cg[q];
+      live[q] = c >= 0;
+      off[q] = int64_t(c >= 0 ? c : c0) * nb;
+    }
+    TA acc[kBjGroup][VR];
+#pragma unroll
+    for (int q = 0; q < kBjGroup; ++q)
+#pragma unroll
+      for (int e = 0; e < VR; ++e) acc[q][e] = TA(0);
+    for (int j = 0; j < nb; ++j) {
+      float col[VR];
+      if constexpr (VR == 4) {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        const f4 v = *reinterpret_cast<const f4 *>(Bc + size_t(j) * nb);
+        col[0] = v[0];
+        col[1] = v[1];
+        col[2] = v[2];
+        col[3] = v[3];
+      } else {
+#pragma unroll
+        for (int e = 0; e < VR; ++e) col[e] = Bc[size_t(j) * nb + e];
+      }
+#pragma unroll
+      for (int q = 0; q < kBjGroup; ++q) {
+        const TA rj = TA(r[off[q] + j]);
+#pragma unroll
+        for (int e = 0; e < VR; ++e) acc[q][e] = fma(TA(col[e]), rj, acc[q][e]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kBjGroup; ++q)
+      if (live[q])
+#pragma unroll
+        for (int e = 0; e < VR; ++e) z[off[q] + i0 + e] = TZ(acc[q][e]);
+  }
+}
+
 // FP16 copy with one scale per cell: h = fp16(b / sc_c), sc_c = max |b| over the block
 __global__ __launch_bounds__(kBjThreads) void k_to_f16_scaled(const double *__restrict__ B, int nb,
                                                               _Float16 *__restrict__ H, float *__restrict__ sc) {
@@ -221,19 +298,72 @@ static int grid_for(int64_t work) {
   return int(g < 1 ? 1 : (g > (1 << 20) ? (1 << 20) : g));
 }
 
-dg_status build_block_jacobi(dg_handle *h) {
+// Key entry rounded to 36 significant bits: the node differences of a
+// uniform mesh differ in their last bits from cell to cell, and blocks whose
+// inputs agree to about 1e-11 agree far below the FP32 rounding of the
+// stored inverse.  Negative values (-1 marks a boundary face) pass unchanged.
+static double key_round(double v) {
+  if (!(v > 0.0)) return v;
+  int e = 0;
+  const double m = std::frexp(v, &e);
+  return std::ldexp(std::nearbyint(std::ldexp(m, 36)), e - 36);
+}
+
+// Classes of cells with equal blocks (see the top of this file); cls[c] is
+// the class of cell c, rep[class] its first cell.
+static void cell_classes(const dg_problem *p, std::vector<int32_t> &cls, std::vector<int64_t> &rep) {
+  const int n1 = p->ncell[0], n2 = p->ncell[1], n3 = p->ncell[2];
+  const int64_t ncells = int64_t(n1) * n2 * n3;
+  const int64_t stride[3] = {1, n1, int64_t(n1) * n2};
+  cls.resize(size_t(ncells));
+  rep.clear();
+  std::unordered_map<std::string, int32_t> ids;
+  double key[19];
+  for (int64_t c = 0; c < ncells; ++c) {
+    const int i[3] = {int(c % n1), int((c / n1) % n2), int(c / stride[2])};
+    int nk = 0;
+    for (int a = 0; a < 3; ++a) {
+      const double *X = p->nodes[a];
+      key[nk++] = i[a] > 0 ? X[i[a]] - X[i[a] - 1] : -1.0;
+      key[nk++] = X[i[a] + 1] - X[i[a]];
+      key[nk++] = i[a] + 1 < p->ncell[a] ? X[i[a] + 2] - X[i[a] + 1] : -1.0;
+    }
+    if (p->kappa) {
+      key[nk++] = p->kappa[c];
+      for (int a = 0; a < 3; ++a) {
+        key[nk++] = i[a] > 0 ? p->kappa[c - stride[a]] : -1.0;
+        key[nk++] = i[a] + 1 < p->ncell[a] ? p->kappa[c + stride[a]] : -1.0;
+      }
+    }
+    // a sine part of b_r makes it depend on the coordinate along b_axis[r]
+    for (int r = 0; r < 3; ++r)
+      if (p->b_sin[r] != 0.0) key[nk++] = p->nodes[p->b_axis[r]][i[p->b_axis[r]]];
+    for (int t = 0; t < nk; ++t) key[t] = key_round(key[t]);
+    auto it = ids.emplace(std::string(reinterpret_cast<const char *>(key), size_t(nk) * sizeof(double)),
+                          int32_t(rep.size()));
+    if (it.second) rep.push_back(c);
+    cls[size_t(c)] = it.first->second;
+  }
+}
+
+dg_status build_block_jacobi(dg_handle *h, const dg_problem *p) {
   const int n = h->k + 1, nb = n * n * n;
   if (nb > kMaxBjBlock)
     return set_error(DG_EINVAL, "dg_setup: block Jacobi supports k <= 7 ((k+1)^3 <= 512)");
-  const size_t ndof = size_t(h->ndof), nblk = size_t(h->ncells) * nb * nb;
+  std::vector<int32_t> cls;
+  std::vector<int64_t> rep;
+  cell_classes(p, cls, rep);
+  const int64_t ncls = int64_t(rep.size());
+  const bool share = 2 * ncls <= h->ncells;
+  const int64_t nblocks = share ? ncls : h->ncells;
+  const size_t ndof = size_t(h->ndof), nblk = size_t(nblocks) * nb * nb;
   double *x = nullptr, *y = nullptr, *B = nullptr;
   int *bad = nullptr;
+  int32_t *slot = nullptr;
   hipError_t e;
   auto fail = [&](hipError_t err, const char *what) {
-    if (x) (void)hipFree(x);
-    if (y) (void)hipFree(y);
-    if (B) (void)hipFree(B);
-    if (bad) (void)hipFree(bad);
+    for (void *q : {(void *)x, (void *)y, (void *)B, (void *)bad, (void *)slot})
+      if (q) (void)hipFree(q);
     return hip_error(err, what);
   };
   if ((e = hipMalloc(&x, ndof * sizeof(double))) != hipSuccess) return fail(e, "block Jacobi: probe vector");
@@ -243,6 +373,39 @@ dg_status build_block_jacobi(dg_handle *h) {
   if ((e = hipMalloc(&h->bj, nblk * sizeof(float))) != hipSuccess) {
     h->bj = nullptr;
     return fail(e, "block Jacobi: FP32 blocks");
+  }
+  if (share) {
+    // probe store slot of each cell: its class for the class's first cell
+    std::vector<int32_t> hs(static_cast<size_t>(h->ncells));
+    for (int64_t c = 0; c < h->ncells; ++c) hs[size_t(c)] = rep[size_t(cls[size_t(c)])] == c ? cls[size_t(c)] : -1;
+    // groups of kBjGroup cells of one class, cells in ascending order
+    std::vector<int64_t> cnt(size_t(ncls), 0), first(size_t(ncls) + 1, 0);
+    for (int32_t k : cls) ++cnt[size_t(k)];
+    for (int64_t k = 0; k < ncls; ++k)
+      first[size_t(k) + 1] = first[size_t(k)] + (cnt[size_t(k)] + kBjGroup - 1) / kBjGroup;
+    const int64_t ngroups = first[size_t(ncls)];
+    std::vector<int32_t> hc(static_cast<size_t>(ngroups) * kBjGroup, -1), hg(static_cast<size_t>(ngroups));
+    std::vector<int64_t> fill(size_t(ncls), 0);
+    for (int64_t c = 0; c < h->ncells; ++c) {
+      const int32_t k = cls[size_t(c)];
+      hc[size_t(first[size_t(k)] * kBjGroup + fill[size_t(k)]++)] = int32_t(c);
+    }
+    for (int64_t k = 0; k < ncls; ++k)
+      for (int64_t g = first[size_t(k)]; g < first[size_t(k) + 1]; ++g) hg[size_t(g)] = int32_t(k);
+    if ((e = hipMalloc(&slot, hs.size() * sizeof(int32_t))) != hipSuccess) return fail(e, "block Jacobi: slots");
+    if ((e = hipMalloc(&h->bj_cells, hc.size() * sizeof(int32_t))) != hipSuccess) {
+      h->bj_cells = nullptr;
+      return fail(e, "block Jacobi: cell groups");
+    }
+    if ((e = hipMalloc(&h->bj_gblock, hg.size() * sizeof(int32_t))) != hipSuccess) {
+      h->bj_gblock = nullptr;
+      return fail(e, "block Jacobi: cell groups");
+    }
+    if ((e = hipMemcpy(slot, hs.data(), hs.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(h->bj_cells, hc.data(), hc.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(h->bj_gblock, hg.data(), hg.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess)
+      return fail(e, "block Jacobi: cell groups");
+    h->bj_ngroups = ngroups;
   }
   const hipStream_t s = nullptr;
   if ((e = hipMemsetAsync(x, 0, ndof * sizeof(double), s)) != hipSuccess) return fail(e, "block Jacobi: memset");
@@ -254,7 +417,7 @@ dg_status build_block_jacobi(dg_handle *h) {
       hipLaunchKernelGGL(k_bj_probe, dim3(gc), dim3(kBjThreads), 0, s, x, n1, n2, int64_t(h->ncells), nb, j,
                          colour, 1.0);
       if ((e = apply_f64(h, x, y, s)) != hipSuccess) return fail(e, "block Jacobi: probe apply");
-      hipLaunchKernelGGL(k_bj_gather, dim3(gr), dim3(kBjThreads), 0, s, y, B, n1, n2, int64_t(h->ncells), nb,
+      hipLaunchKernelGGL(k_bj_gather, dim3(gr), dim3(kBjThreads), 0, s, y, B, slot, n1, n2, int64_t(h->ncells), nb,
                          j, colour);
       hipLaunchKernelGGL(k_bj_probe, dim3(gc), dim3(kBjThreads), 0, s, x, n1, n2, int64_t(h->ncells), nb, j,
                          colour, 0.0);
@@ -264,48 +427,52 @@ dg_status build_block_jacobi(dg_handle *h) {
   if (nb <= 216) {
     constexpr int BS = 16;
     const size_t lds = sizeof(double) * (2 * size_t(BS) * nb + BS * BS);
-    hipLaunchKernelGGL((k_bj_invert<BS>), dim3(unsigned(h->ncells)), dim3(kBjThreads), lds, s, B, nb, bad);
+    hipLaunchKernelGGL((k_bj_invert<BS>), dim3(unsigned(nblocks)), dim3(kBjThreads), lds, s, B, nb, bad);
   } else {
     constexpr int BS = 4;
     const size_t lds = sizeof(double) * (2 * size_t(BS) * nb + BS * BS);
-    hipLaunchKernelGGL((k_bj_invert<BS>), dim3(unsigned(h->ncells)), dim3(kBjThreads), lds, s, B, nb, bad);
+    hipLaunchKernelGGL((k_bj_invert<BS>), dim3(unsigned(nblocks)), dim3(kBjThreads), lds, s, B, nb, bad);
   }
   if ((e = hipGetLastError()) != hipSuccess) return fail(e, "block Jacobi: inversion");
   hipLaunchKernelGGL(k_to_f32, dim3(4096), dim3(kBjThreads), 0, s, B, h->bj, nblk);
-  if ((e = hipMalloc(&h->bj16, nblk * sizeof(_Float16))) != hipSuccess) {
-    h->bj16 = nullptr;
-    return fail(e, "block Jacobi: FP16 blocks");
+  if (!share) {
+    // FP16 store for the FP32 inner solves (shared blocks stay in FP32: the
+    // class store is small and read from cache)
+    if ((e = hipMalloc(&h->bj16, nblk * sizeof(_Float16))) != hipSuccess) {
+      h->bj16 = nullptr;
+      return fail(e, "block Jacobi: FP16 blocks");
+    }
+    if ((e = hipMalloc(&h->bj16_scale, size_t(nblocks) * sizeof(float))) != hipSuccess) {
+      h->bj16_scale = nullptr;
+      return fail(e, "block Jacobi: FP16 scales");
+    }
+    hipLaunchKernelGGL(k_to_f16_scaled, dim3(unsigned(nblocks)), dim3(kBjThreads), 0, s, B, nb, h->bj16,
+                       h->bj16_scale);
   }
-  if ((e = hipMalloc(&h->bj16_scale, size_t(h->ncells) * sizeof(float))) != hipSuccess) {
-    h->bj16_scale = nullptr;
-    return fail(e, "block Jacobi: FP16 scales");
-  }
-  hipLaunchKernelGGL(k_to_f16_scaled, dim3(unsigned(h->ncells)), dim3(kBjThreads), 0, s, B, nb, h->bj16,
-                     h->bj16_scale);
   int hbad = 0;
   if ((e = hipMemcpy(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost)) != hipSuccess)
     return fail(e, "block Jacobi: flag readback");
-  (void)hipFree(x);
-  (void)hipFree(y);
-  (void)hipFree(B);
-  (void)hipFree(bad);
-  if (hbad) {
-    (void)hipFree(h->bj);
-    h->bj = nullptr;
-    (void)hipFree(h->bj16);
-    h->bj16 = nullptr;
-    (void)hipFree(h->bj16_scale);
-    h->bj16_scale = nullptr;
-    return set_error(DG_ENAN, "dg_setup: a cell block has a non-positive pivot (the form is not coercive)");
-  }
+  for (void *q : {(void *)x, (void *)y, (void *)B, (void *)bad, (void *)slot})
+    if (q) (void)hipFree(q);
   h->bj_nb = nb;
+  h->bj_nblocks = nblocks;
+  if (hbad) return set_error(DG_ENAN, "dg_setup: a cell block has a non-positive pivot (the form is not coercive)");
   return DG_OK;
 }
 
 template <typename TR, typename TZ>
 hipError_t bj_apply(const dg_handle *h, const TR *r, TZ *z, hipStream_t s, bool half_store) {
   const int nb = h->bj_nb;
-  if (half_store && h->bj16 && nb % 8 == 0) {
+  if (h->bj_cells) {
+    // shared blocks; FP32 accumulation for the FP32 inner solves
+    using TA = typename std::conditional<std::is_same<TZ, float>::value, float, double>::type;
+    if (nb % 4 == 0)
+      hipLaunchKernelGGL((k_bj_apply_grp<TR, TZ, TA, 4>), dim3(grid_for(h->bj_ngroups * (nb / 4))), dim3(kBjThreads),
+                         0, s, h->bj, h->bj_cells, h->bj_gblock, r, z, nb, h->bj_ngroups);
+    else
+      hipLaunchKernelGGL((k_bj_apply_grp<TR, TZ, TA, 1>), dim3(grid_for(h->bj_ngroups * nb)), dim3(kBjThreads), 0, s,
+                         h->bj, h->bj_cells, h->bj_gblock, r, z, nb, h->bj_ngroups);
+  } else if (half_store && h->bj16 && nb % 8 == 0) {
     hipLaunchKernelGGL((k_bj_apply_vec<TR, TZ, _Float16, 8>), dim3(grid_for(h->ncells * (nb / 8))), dim3(kBjThreads),
                        0, s, h->bj16, h->bj16_scale, r, z, nb, int64_t(h->ncells));
   } else if (nb % 4 == 0) {

@@ -128,6 +128,8 @@ extern "C" int64_t dg_ndof(const dg_handle *h) { return h ? h->ndof : -1; }
 
 extern "C" int32_t dg_degree(const dg_handle *h) { return h ? h->k : -1; }
 
+extern "C" int64_t dg_bj_nblocks(const dg_handle *h) { return h ? (h->bj ? h->bj_nblocks : 0) : -1; }
+
 extern "C" dg_status dg_set_kernel(dg_handle *h, int32_t variant) {
   if (!h) return set_error(DG_EINVAL, "dg_set_kernel: handle is NULL");
   if (variant != DG_KERNEL_AUTO && variant != DG_KERNEL_REFERENCE)
@@ -145,6 +147,8 @@ extern "C" void dg_destroy(dg_handle *h) {
   if (h->bj) (void)hipFree(h->bj);
   if (h->bj16) (void)hipFree(h->bj16);
   if (h->bj16_scale) (void)hipFree(h->bj16_scale);
+  if (h->bj_cells) (void)hipFree(h->bj_cells);
+  if (h->bj_gblock) (void)hipFree(h->bj_gblock);
   if (h->dev_block) (void)hipFree(h->dev_block);
   if (cur != h->device) (void)hipSetDevice(cur);
   delete h;
@@ -203,6 +207,10 @@ extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
   h->bj16 = nullptr;
   h->bj16_scale = nullptr;
   h->bj_nb = 0;
+  h->bj_nblocks = 0;
+  h->bj_cells = nullptr;
+  h->bj_gblock = nullptr;
+  h->bj_ngroups = 0;
   h->mlp = nullptr;
   if (hipGetDevice(&h->device) != hipSuccess) {
     delete h;
@@ -264,7 +272,7 @@ extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
   M.c = p->c;
   M.sigma = p->sigma;
   if (p->flags & DG_WITH_BLOCK_JACOBI) {
-    const dg_status ds = build_block_jacobi(h);
+    const dg_status ds = build_block_jacobi(h, p);
     if (ds != DG_OK) {
       const std::string msg = dg_last_error();
       dg_destroy(h);

@@ -12,6 +12,7 @@
 namespace dgmf {
 
 constexpr int kMaxN = 11;         // k <= 10
+constexpr int kBjGroup = 8;  // cells per group of the shared-block apply
 constexpr int kMaxBjBlock = 512;  // block Jacobi for (k+1)^3 <= 512
 constexpr int kMlpHidden = 256;   // hidden width of the cell-patch network
 constexpr int64_t kMlpChunk = 65536;  // cells per inference chunk
@@ -62,6 +63,12 @@ struct dg_handle {
   _Float16 *bj16;      // the same blocks in FP16, scaled per cell (inner FP32 solves)
   float *bj16_scale;
   int bj_nb;
+  int64_t bj_nblocks;  // blocks stored: ncells, or the number of cell classes
+  // cells grouped by class (shared blocks only, else null): kBjGroup cell
+  // indices per group, -1 padding the last group of a class; block per group
+  int32_t *bj_cells;
+  int32_t *bj_gblock;
+  int64_t bj_ngroups;
   // learned cell-patch preconditioner (or null)
   dgmf::Mlp *mlp;
 };
@@ -80,7 +87,7 @@ hipError_t launch_apply_fused_f32(const dg_handle *h, const float *x, float *y, 
 hipError_t apply_f64(const dg_handle *h, const double *x, double *y, hipStream_t s);
 
 // Block Jacobi: build the inverse cell blocks (setup), z = M^{-1} r.
-dg_status build_block_jacobi(dg_handle *h);
+dg_status build_block_jacobi(dg_handle *h, const dg_problem *p);
 template <typename TR, typename TZ>
 hipError_t bj_apply(const dg_handle *h, const TR *r, TZ *z, hipStream_t s, bool half_store = false);
 

@@ -82,6 +82,75 @@ def test_sampled_cells_of_the_64_cube_k3_workload():
     _check_blocks(blocks, r[sel], z[sel], "learned_k3_64 sampled cells")
 
 
+@pytest.mark.parametrize("N,k", [(6, 1), (6, 2), (6, 3), (4, 4), (4, 5)])
+def test_shared_blocks_on_a_uniform_mesh_match_oracle_blocks(N, k):
+    """Uniform mesh, constant coefficients: 27 distinct cell blocks (one per
+    combination of boundary faces) are stored once and applied to groups of
+    cells of one class; every cell's result is checked against the oracle's
+    own block of that cell.  At N = 6 the node differences of the uniform
+    mesh differ in their last bits, which the class keys absorb."""
+    torch = _torch()
+    from paper_1711_10885_amd import binding
+    p = W.mixed_k5_48(N=N, k=k)
+    r = W.random_vector(p.ndof, 560 + k)
+    with binding.DG(p, flags=binding.DG_WITH_BLOCK_JACOBI) as dg:
+        assert dg.bj_nblocks() == 27
+        z = dg.precond_apply(torch.from_numpy(r).cuda()).cpu().numpy()
+    _check_blocks(oracle.block_diagonal(p), r, z, f"shared N={N} k={k}")
+
+
+def test_shared_blocks_with_a_piecewise_constant_kappa():
+    """kappa = 1 on the lower half (i3 < 3) and 4 on the upper half of a 6^3
+    mesh: classes split by kappa on the cell and on its neighbours."""
+    torch = _torch()
+    from paper_1711_10885_amd import binding
+    p = W.mixed_k5_48(N=6, k=2)
+    i3 = np.arange(p.ncells) // (p.ncell[0] * p.ncell[1])
+    p = p.with_(kappa=np.where(i3 < 3, 1.0, 4.0))
+    r = W.random_vector(p.ndof, 570)
+    with binding.DG(p, flags=binding.DG_WITH_BLOCK_JACOBI) as dg:
+        # 9 classes per z layer (x, y boundary faces) x 6 layers: every layer
+        # differs (boundary below, interface above or below, boundary above)
+        assert dg.bj_nblocks() == 54
+        z = dg.precond_apply(torch.from_numpy(r).cuda()).cpu().numpy()
+    _check_blocks(oracle.block_diagonal(p), r, z, "shared, piecewise kappa")
+
+
+def test_non_uniform_meshes_keep_one_block_per_cell():
+    torch = _torch()
+    from paper_1711_10885_amd import binding
+    p = W.random_problem(580, ncell=(4, 3, 3), k=1, b="const")
+    with binding.DG(p, flags=binding.DG_WITH_BLOCK_JACOBI) as dg:
+        assert dg.bj_nblocks() == 36
+    with binding.DG(W.random_problem(581, ncell=(2, 2, 2), k=1)) as dg:
+        assert dg.bj_nblocks() == 0
+
+
+def test_sampled_cells_of_the_48_cube_k5_workload():
+    """48^3 cells, k = 5 (23.9M DOF, the mixed-precision workload; shared
+    blocks): blocks of sampled cells (corner, edge, face, interior) rebuilt by
+    the oracle with unit probes on those cells only."""
+    torch = _torch()
+    from paper_1711_10885_amd import binding
+    p = W.mixed_k5_48()
+    nb = (p.k + 1) ** 3
+    N = p.ncell[0]
+    ids = [0, N - 1, N * N * N - 1, 20 + N * (0 + N * 30), 17 + N * (23 + N * 29), 1 + N * (46 + N * 47)]
+    cells = np.array(sorted(ids), dtype=np.int64)
+    r = W.random_vector(p.ndof, 590)
+    with binding.DG(p, flags=binding.DG_WITH_BLOCK_JACOBI) as dg:
+        assert dg.bj_nblocks() == 27
+        z = dg.precond_apply(torch.from_numpy(r).cuda()).cpu().numpy()
+    x = np.zeros(p.ndof)
+    blocks = np.zeros((cells.size, nb, nb))
+    for j in range(nb):
+        x[cells * nb + j] = 1.0
+        blocks[:, :, j] = oracle.apply_rows(p, x, cells)
+        x[cells * nb + j] = 0.0
+    sel = (cells[:, None] * nb + np.arange(nb)[None, :]).ravel()
+    _check_blocks(blocks, r[sel], z[sel], "mixed_k5_48 sampled cells")
+
+
 def test_block_jacobi_gmres_needs_fewer_iterations_and_solves():
     torch = _torch()
     from paper_1711_10885_amd import binding
