@@ -96,3 +96,27 @@ def test_null_arguments():
     assert lib.dg_apply(None, None, None, None) == binding.DG_EINVAL
     assert lib.dg_ndof(None) == -1
     lib.dg_destroy(None)
+
+
+@pytest.mark.parametrize("cname,pystruct", [("dg_problem", "_Problem"), ("dg_solve_opts", "SolveOpts"),
+                                            ("dg_solve_stats", "SolveStats"), ("dg_learn_opts", "LearnOpts"),
+                                            ("dg_learn_stats", "LearnStats")])
+def test_binding_structs_match_the_header_layout(cname, pystruct, tmp_path):
+    """Size and field offsets of every struct, as the C compiler lays it out
+    from include/dg.h, against the ctypes mirror in the binding."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    st = getattr(binding, pystruct)
+    names = [f for f, _ in st._fields_]
+    body = "".join(f'  printf("%zu\\n", offsetof({cname}, {f}));\n' for f in names)
+    src = tmp_path / "layout.c"
+    src.write_text(f'#include <stddef.h>\n#include <stdio.h>\n#include "dg.h"\nint main(void) {{\n'
+                   f'  printf("%zu\\n", sizeof({cname}));\n{body}  return 0;\n}}\n')
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert out[0] == ctypes.sizeof(st), (cname, out[0], ctypes.sizeof(st))
+    assert out[1:] == [getattr(st, f).offset for f in names], cname
