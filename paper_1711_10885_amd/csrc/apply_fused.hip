@@ -100,7 +100,13 @@ struct FCfg {
   static constexpr int NN = N * N;
   static constexpr int PS = N + 1;  // padded pencil stride
   static constexpr int LANES = NN;
-  static constexpr int CPB = (NN <= 64) ? (64 / NN) : 1;
+  // cells per workgroup: one 64-lane wave holds 64 / N^2 cells, which
+  // leaves 22 % (N = 5), 44 % (N = 6) and 37 % (N = 9, two waves per cell)
+  // of the lanes idle; larger workgroups pack 10, 7 and 3 cells into 256
+  // lanes (98, 98 and 95 % busy) while two workgroups (one for N = 9) still
+  // fit in the 160 KB of LDS of a CU.  N = 7 keeps one cell per wave: nine
+  // cells in 448 lanes need 145 KB, one workgroup per CU, and run slower.
+  static constexpr int CPB = (N == 5) ? 10 : (N == 6) ? 7 : (N == 9) ? 3 : (NN <= 64 ? 64 / NN : 1);
   static constexpr int THREADS = ((CPB * LANES + 63) / 64) * 64;
   static constexpr int WAVES_PER_SIMD = (N <= 8) ? 2 : 1;  // register budget target
   static constexpr int FCW = 8;  // doubles per face-constant record
