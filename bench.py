@@ -14,9 +14,9 @@ gives the average kernel duration used for the roofline.
 
 By default the run also times the solves (the second half of the metric):
 plain FP64 GMRES(30) against GMRES-IR to 1e-8 on the 48^3 k=5 workload, and
-block-Jacobi FGMRES(60) against the learned preconditioner to 1e-8 on the
-64^3 k=3 workload (--solves none skips them; the degree-sweep workloads skip
-them unless asked).
+plain FP64 GMRES(60) and block-Jacobi FGMRES(60) against the learned
+preconditioner to 1e-8 on the 64^3 k=3 workload (--solves none skips them;
+the degree-sweep workloads skip them unless asked).
 
 Prints ONE JSON line.  Algorithmic FLOPs use the per-DOF lower bound of
 Sec. 3.6 (FLOPDOF_vol + FLOPDOF_face for d = 3); peak is the MI355X FP64
@@ -157,10 +157,10 @@ def solves_mixed(maxit: int):
 
 def solves_learned(maxit: int, restart: int):
     """64^3 cells, k = 3 (16.8M DOF), kappa = exp(g) of a seeded smooth random
-    field, b = (1, 0.5, 0.25), c = 0.1, f = 1, u0 = 0, tol 1e-8: FGMRES with
-    block Jacobi against FGMRES with the trained network on top of block
-    Jacobi (trained on the GPU in the same run), the same restart length on
-    both sides.  With restart 30 block Jacobi stagnates on this problem (a
+    field, b = (1, 0.5, 0.25), c = 0.1, f = 1, u0 = 0, tol 1e-8: plain FP64
+    GMRES (no preconditioner), FGMRES with block Jacobi, and FGMRES with the
+    trained network on top of block Jacobi (trained on the GPU in the same
+    run), the same restart length and step cap on all three.  With restart 30 block Jacobi stagnates on this problem (a
     one-level preconditioner, no coarse space); restart 60 reaches 1e-8."""
     import torch
     from paper_1711_10885_amd import binding, workloads as W
@@ -169,6 +169,13 @@ def solves_learned(maxit: int, restart: int):
     f = dg.load_vector(W.constant_source(1.0))
     out = {"workload": f"{prob.name}: {prob.ncell[0]}^3 cells, k={prob.k}, {prob.ndof} DOF, lognormal kappa, f = 1",
            "tol": 1e-8, "restart": restart, "maxit": maxit}
+    # the plain reference: FP64 GMRES without a preconditioner, same restart and step cap
+    _warm_solve(dg, f, binding.DG_GMRES64, binding.DG_PREC_NONE, restart)
+    u = torch.zeros_like(f)
+    u, st, rc = dg.solve(f, u, tol=1e-8, method=binding.DG_GMRES64, precond=binding.DG_PREC_NONE,
+                         restart=restart, maxit=maxit, check=False)
+    out["plain_fp64_gmres"] = _solve_record(st, rc)
+    print(f"[solve] plain_fp64_gmres: {out['plain_fp64_gmres']}", file=sys.stderr, flush=True)
     _warm_solve(dg, f, binding.DG_FGMRES, binding.DG_PREC_BLOCK_JACOBI, restart)
     u = torch.zeros_like(f)
     u, st, rc = dg.solve(f, u, tol=1e-8, method=binding.DG_FGMRES, precond=binding.DG_PREC_BLOCK_JACOBI,
@@ -185,6 +192,11 @@ def solves_learned(maxit: int, restart: int):
     print(f"[solve] fgmres_learned: {out['fgmres_learned']}", file=sys.stderr, flush=True)
     a, b = out["fgmres_block_jacobi"], out["fgmres_learned"]
     out["speedup_time_to_tol"] = a["seconds"] / b["seconds"] if a["converged"] and b["converged"] else None
+    p = out["plain_fp64_gmres"]
+    # against plain FP64 GMRES: a ratio when both converge, else which one reached 1e-8
+    out["learned_vs_plain"] = (p["seconds"] / b["seconds"] if p["converged"] and b["converged"] else
+                               ("only the learned solve reached tol" if b["converged"] else
+                                ("only plain GMRES reached tol" if p["converged"] else "neither reached tol")))
     dg.close()
     return out
 
