@@ -99,6 +99,30 @@ def test_shared_blocks_on_a_uniform_mesh_match_oracle_blocks(N, k):
     _check_blocks(oracle.block_diagonal(p), r, z, f"shared N={N} k={k}")
 
 
+@pytest.mark.parametrize("k", [6, 7])
+def test_shared_blocks_of_the_largest_degrees_on_sampled_cells(k):
+    """k = 6 (343 rows, one row per thread) and k = 7 (512 rows, four per
+    thread) on a uniform 4^3 mesh: the oracle probes a corner, an edge, a face
+    and an interior cell; the GPU applies the shared blocks to all cells."""
+    torch = _torch()
+    from paper_1711_10885_amd import binding
+    p = W.mixed_k5_48(N=4, k=k)
+    nb = (k + 1) ** 3
+    cells = np.array([0, 1, 5, 21, 42, 63], dtype=np.int64)
+    r = W.random_vector(p.ndof, 575 + k)
+    with binding.DG(p, flags=binding.DG_WITH_BLOCK_JACOBI) as dg:
+        assert dg.bj_nblocks() == 27
+        z = dg.precond_apply(torch.from_numpy(r).cuda()).cpu().numpy()
+    x = np.zeros(p.ndof)
+    blocks = np.zeros((cells.size, nb, nb))
+    for j in range(nb):
+        x[cells * nb + j] = 1.0
+        blocks[:, :, j] = oracle.apply_rows(p, x, cells)
+        x[cells * nb + j] = 0.0
+    sel = (cells[:, None] * nb + np.arange(nb)[None, :]).ravel()
+    _check_blocks(blocks, r[sel], z[sel], f"shared k={k} sampled cells")
+
+
 def test_shared_blocks_with_a_piecewise_constant_kappa():
     """kappa = 1 on the lower half (i3 < 3) and 4 on the upper half of a 6^3
     mesh: classes split by kappa on the cell and on its neighbours."""
