@@ -217,13 +217,16 @@ __global__ __launch_bounds__(kBjThreads) void k_bj_apply_vec(const TB *__restric
 
 // shared blocks: thread (group, VR rows) applies the group's block to its
 // kBjGroup cells; padding entries (-1) read the group's first cell and
-// write nothing.  TA: accumulation type.
+// write nothing.  TA: accumulation type.  JU columns per step: with VR = 4
+// the r values of JU consecutive columns come in one 16-byte load per cell
+// (JU = 16 / sizeof(TR); nb is then a multiple of 4, hence of JU).
 template <typename TR, typename TZ, typename TA, int VR>
 __global__ __launch_bounds__(kBjThreads) void k_bj_apply_grp(const float *__restrict__ Binv,
                                                              const int32_t *__restrict__ cells,
                                                              const int32_t *__restrict__ gblock,
                                                              const TR *__restrict__ r, TZ *__restrict__ z, int nb,
                                                              int64_t ngroups) {
+  constexpr int JU = (VR == 4) ? int(16 / sizeof(TR)) : 1;
   const int per = nb / VR;
   const int64_t total = ngroups * per;
   for (int64_t g = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; g < total;
@@ -246,25 +249,38 @@ __global__ __launch_bounds__(kBjThreads) void k_bj_apply_grp(const float *__rest
     for (int q = 0; q < kBjGroup; ++q)
 #pragma unroll
       for (int e = 0; e < VR; ++e) acc[q][e] = TA(0);
-    for (int j = 0; j < nb; ++j) {
-      float col[VR];
+    for (int j = 0; j < nb; j += JU) {
+      float col[JU][VR];
+      TR rv[kBjGroup][JU];
       if constexpr (VR == 4) {
         typedef float f4 __attribute__((ext_vector_type(4)));
-        const f4 v = *reinterpret_cast<const f4 *>(Bc + size_t(j) * nb);
-        col[0] = v[0];
-        col[1] = v[1];
-        col[2] = v[2];
-        col[3] = v[3];
+        typedef TR rvec __attribute__((ext_vector_type(JU)));
+#pragma unroll
+        for (int u = 0; u < JU; ++u) {
+          const f4 v = *reinterpret_cast<const f4 *>(Bc + size_t(j + u) * nb);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) col[u][e] = v[e];
+        }
+#pragma unroll
+        for (int q = 0; q < kBjGroup; ++q) {
+          const rvec v = *reinterpret_cast<const rvec *>(r + off[q] + j);
+#pragma unroll
+          for (int u = 0; u < JU; ++u) rv[q][u] = v[u];
+        }
       } else {
 #pragma unroll
-        for (int e = 0; e < VR; ++e) col[e] = Bc[size_t(j) * nb + e];
+        for (int e = 0; e < VR; ++e) col[0][e] = Bc[size_t(j) * nb + e];
+#pragma unroll
+        for (int q = 0; q < kBjGroup; ++q) rv[q][0] = r[off[q] + j];
       }
 #pragma unroll
-      for (int q = 0; q < kBjGroup; ++q) {
-        const TA rj = TA(r[off[q] + j]);
+      for (int u = 0; u < JU; ++u)
 #pragma unroll
-        for (int e = 0; e < VR; ++e) acc[q][e] = fma(TA(col[e]), rj, acc[q][e]);
-      }
+        for (int q = 0; q < kBjGroup; ++q) {
+          const TA rj = TA(rv[q][u]);
+#pragma unroll
+          for (int e = 0; e < VR; ++e) acc[q][e] = fma(TA(col[u][e]), rj, acc[q][e]);
+        }
     }
 #pragma unroll
     for (int q = 0; q < kBjGroup; ++q)

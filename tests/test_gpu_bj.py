@@ -24,6 +24,25 @@ def _torch():
     return torch
 
 
+def _probe_blocks(p, cells):
+    """Oracle blocks of the given cells by unit probes on those cells only.
+    All cells are probed at once, so no two of them may share a face (a
+    neighbour's probe would add its coupling block to the result)."""
+    n1, n2 = p.ncell[0], p.ncell[1]
+    ijk = [(int(c) % n1, (int(c) // n1) % n2, int(c) // (n1 * n2)) for c in cells]
+    for a in range(len(ijk)):
+        for b in range(a):
+            assert sum(abs(x - y) for x, y in zip(ijk[a], ijk[b])) > 1, "sampled cells share a face"
+    nb = (p.k + 1) ** 3
+    x = np.zeros(p.ndof)
+    blocks = np.zeros((len(cells), nb, nb))
+    for j in range(nb):
+        x[cells * nb + j] = 1.0
+        blocks[:, :, j] = oracle.apply_rows(p, x, cells)
+        x[cells * nb + j] = 0.0
+    return blocks
+
+
 def _check_blocks(blocks, r, z, what):
     nb = blocks.shape[1]
     R = r.reshape(-1, nb)
@@ -72,12 +91,7 @@ def test_sampled_cells_of_the_64_cube_k3_workload():
     r = W.random_vector(p.ndof, 530)
     with binding.DG(p, flags=binding.DG_WITH_BLOCK_JACOBI) as dg:
         z = dg.precond_apply(torch.from_numpy(r).cuda()).cpu().numpy()
-    x = np.zeros(p.ndof)
-    blocks = np.zeros((cells.size, nb, nb))
-    for j in range(nb):
-        x[cells * nb + j] = 1.0
-        blocks[:, :, j] = oracle.apply_rows(p, x, cells)
-        x[cells * nb + j] = 0.0
+    blocks = _probe_blocks(p, cells)
     sel = (cells[:, None] * nb + np.arange(nb)[None, :]).ravel()
     _check_blocks(blocks, r[sel], z[sel], "learned_k3_64 sampled cells")
 
@@ -108,17 +122,13 @@ def test_shared_blocks_of_the_largest_degrees_on_sampled_cells(k):
     from paper_1711_10885_amd import binding
     p = W.mixed_k5_48(N=4, k=k)
     nb = (k + 1) ** 3
-    cells = np.array([0, 1, 5, 21, 42, 63], dtype=np.int64)
+    # corner (0,0,0), edge (2,0,0), face (2,2,0), interior (1,1,1), (2,2,2), corner (3,3,3)
+    cells = np.array([0, 2, 10, 21, 42, 63], dtype=np.int64)
     r = W.random_vector(p.ndof, 575 + k)
     with binding.DG(p, flags=binding.DG_WITH_BLOCK_JACOBI) as dg:
         assert dg.bj_nblocks() == 27
         z = dg.precond_apply(torch.from_numpy(r).cuda()).cpu().numpy()
-    x = np.zeros(p.ndof)
-    blocks = np.zeros((cells.size, nb, nb))
-    for j in range(nb):
-        x[cells * nb + j] = 1.0
-        blocks[:, :, j] = oracle.apply_rows(p, x, cells)
-        x[cells * nb + j] = 0.0
+    blocks = _probe_blocks(p, cells)
     sel = (cells[:, None] * nb + np.arange(nb)[None, :]).ravel()
     _check_blocks(blocks, r[sel], z[sel], f"shared k={k} sampled cells")
 
@@ -165,12 +175,7 @@ def test_sampled_cells_of_the_48_cube_k5_workload():
     with binding.DG(p, flags=binding.DG_WITH_BLOCK_JACOBI) as dg:
         assert dg.bj_nblocks() == 27
         z = dg.precond_apply(torch.from_numpy(r).cuda()).cpu().numpy()
-    x = np.zeros(p.ndof)
-    blocks = np.zeros((cells.size, nb, nb))
-    for j in range(nb):
-        x[cells * nb + j] = 1.0
-        blocks[:, :, j] = oracle.apply_rows(p, x, cells)
-        x[cells * nb + j] = 0.0
+    blocks = _probe_blocks(p, cells)
     sel = (cells[:, None] * nb + np.arange(nb)[None, :]).ravel()
     _check_blocks(blocks, r[sel], z[sel], "mixed_k5_48 sampled cells")
 
