@@ -147,8 +147,9 @@ dg_status dg_set_kernel(dg_handle *h, int32_t variant);
 /* ---------------------------------------------------------------------------
  * Solvers.  The paper motivates the fast operator application as the core of
  * iterative solvers (Sec. 1) and stops there; dg_solve wraps the operator in
- * restarted GMRES (right preconditioning, classical Gram-Schmidt applied
- * twice, Givens rotations) and its variants below.
+ * restarted GMRES (right preconditioning, classical Gram-Schmidt, Givens
+ * rotations, the true residual recomputed at every restart) and its
+ * variants below.
  * ------------------------------------------------------------------------- */
 #define DG_GMRES64 0  /* GMRES(m): FP64 operator and FP64 Krylov basis.          */
 #define DG_GMRES_IR 1 /* GMRES-IR: FP64 residual r = f - A u and update          *
@@ -168,11 +169,21 @@ dg_status dg_set_kernel(dg_handle *h, int32_t variant);
                                 * the true residual falls by less than 10 % over *
                                 * ten cycles                                      */
 
+/* Orthogonalisation of each new Krylov direction w against the basis V:
+ *   DG_ORTH_CGS1  classical Gram-Schmidt, one projection: h = V^T w (with
+ *                 ||w||^2 in the same pass), v = (w - V h) / ||w - V h||,
+ *                 the norm from ||w||^2 - ||h||^2; two passes over the basis;
+ *   DG_ORTH_CGS2  the projection repeated once (orthogonal to working
+ *                 precision): three passes over the basis. */
+#define DG_ORTH_CGS1 0
+#define DG_ORTH_CGS2 1
+
 typedef struct {
   int32_t method;   /* DG_GMRES64 | DG_GMRES_IR | DG_FGMRES          (0)     */
   int32_t precond;  /* DG_PREC_*                                      (0)     */
   int32_t restart;  /* m, 1..63                                       (30)    */
   int32_t maxit;    /* cap on Arnoldi steps (inner steps for IR)      (20000) */
+  int32_t orth;     /* DG_ORTH_CGS1 | DG_ORTH_CGS2                    (0)     */
   double inner_tol; /* GMRES-IR inner relative tolerance              (1e-4)  */
 } dg_solve_opts;
 

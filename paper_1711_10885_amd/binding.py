@@ -19,6 +19,7 @@ DG_WITH_BLOCK_JACOBI = 2
 DG_KERNEL_AUTO, DG_KERNEL_REFERENCE = 0, 1
 DG_GMRES64, DG_GMRES_IR, DG_FGMRES = 0, 1, 2
 DG_PREC_NONE, DG_PREC_BLOCK_JACOBI, DG_PREC_LEARNED = 0, 1, 2
+DG_ORTH_CGS1, DG_ORTH_CGS2 = 0, 1
 
 _STATUS = {DG_EINVAL: "DG_EINVAL", DG_ENOMEM: "DG_ENOMEM", DG_EHIP: "DG_EHIP",
            DG_ENOTCONV: "DG_ENOTCONV", DG_ENAN: "DG_ENAN"}
@@ -54,7 +55,7 @@ class _Problem(ctypes.Structure):
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("precond", ctypes.c_int32), ("restart", ctypes.c_int32),
-                ("maxit", ctypes.c_int32), ("inner_tol", ctypes.c_double)]
+                ("maxit", ctypes.c_int32), ("orth", ctypes.c_int32), ("inner_tol", ctypes.c_double)]
 
 
 class SolveStats(ctypes.Structure):
@@ -273,7 +274,7 @@ class DG:
 
     def solve(self, f, u=None, tol: float = 1e-8, method: int = DG_GMRES64,
               precond: int = DG_PREC_NONE, restart: int = 30, maxit: int = 20000,
-              inner_tol: float = 1e-4, stream=None, check: bool = True):
+              inner_tol: float = 1e-4, orth: int = 0, stream=None, check: bool = True):
         """Solve A u = f (float64 device tensors); u is the initial guess (zero
         if None).  Returns (u, stats dict, status).  With check=True a status
         other than DG_OK raises DGError."""
@@ -282,7 +283,7 @@ class DG:
         if u is None:
             u = torch.zeros_like(f)
         _check_vec(u, self.ndof, torch.float64, "u")
-        o = SolveOpts(int(method), int(precond), int(restart), int(maxit), float(inner_tol))
+        o = SolveOpts(int(method), int(precond), int(restart), int(maxit), int(orth), float(inner_tol))
         st = SolveStats()
         rc = load().dg_solve(self._h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()),
                              float(tol), ctypes.byref(o), ctypes.byref(st), _stream_ptr(stream))

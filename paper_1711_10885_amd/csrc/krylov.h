@@ -16,6 +16,7 @@ constexpr int kRedBlocks = 1024;  // fixed reduction grid (deterministic sums)
 constexpr int kMaxBasis = 64;     // restart <= kMaxBasis - 1
 constexpr size_t kBasisAlign = 64;  // basis vectors start 16-byte (and 256-byte) aligned
 
+// out[0..nv) = V_k . w, out[nv] = w . w
 template <typename T>
 hipError_t kr_multidot(const T *V, size_t ld, int nv, const T *w, size_t n, double *partial,
                        double *out, hipStream_t s);
@@ -43,6 +44,7 @@ struct KrylovBufs {
   size_t ld = 0;       // basis stride: n rounded up to kBasisAlign entries
   int restart = 0;
   bool flex = false;
+  bool reorth = false;  // CGS2 (second projection) instead of CGS1
 };
 
 struct GmresOut {
@@ -115,23 +117,56 @@ hipError_t gmres(KrylovBufs &K, Op &&op, Prec &&prec, bool have_prec, const T *b
       if ((e = op(zj, w)) != hipSuccess) return e;
       ++out.applies;
       const int nv = j + 1;
-      // CGS2: h1 = V^T w; w -= V h1; h2 = V^T w, ||w||^2
-      if ((e = kr_multidot<T>(V, ld, nv, w, n, scratch, h1, s)) != hipSuccess) return e;
-      if ((e = kr_orth<T, true, true>(V, ld, nv, h1, w, w, 1.0, n, scratch, h2, s)) != hipSuccess) return e;
-      if ((e = hipMemcpyAsync(hb.data(), small, sizeof(double) * (kMaxBasis + nv + 1),
-                              hipMemcpyDeviceToHost, s)) != hipSuccess)
-        return e;
-      if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+      // Classical Gram-Schmidt: pass 1 gives h1 = V^T w and ||w||^2, and the
+      // norm of w - V h1 is ||w||^2 - ||h1||^2.  A second projection (CGS2:
+      // w -= V h1; h2 = V^T w, ||w||^2) runs when K.reorth asks for it, or
+      // when the first one cancels w below 1e-4 of its norm, where that
+      // difference would have lost half its digits.  The last pass writes
+      // v_{j+1} = (w - V h) / hn with the last projection h.
       double *Hj = H.data() + size_t(j) * (m + 1);
       bool bad = false;
-      double h2sq = 0.0, colsq = 0.0;
+      double wsq = 0.0;
+      const double *hlast = h1;
+      if ((e = kr_multidot<T>(V, ld, nv, w, n, scratch, h1, s)) != hipSuccess) return e;
+      bool second = K.reorth;
+      if (second) {
+        if ((e = kr_orth<T, true, true>(V, ld, nv, h1, w, w, 1.0, n, scratch, h2, s)) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(hb.data(), small, sizeof(double) * (kMaxBasis + nv + 1), hipMemcpyDeviceToHost,
+                                s)) != hipSuccess)
+          return e;
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+      } else {
+        if ((e = hipMemcpyAsync(hb.data(), h1, sizeof(double) * (nv + 1), hipMemcpyDeviceToHost, s)) != hipSuccess)
+          return e;
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+        double h1sq = 0.0;
+        for (int i = 0; i < nv; ++i) h1sq += hb[i] * hb[i];
+        wsq = hb[nv] - h1sq;
+        if (std::isfinite(wsq) && !(wsq > 1e-8 * hb[nv])) {
+          second = true;
+          if ((e = kr_orth<T, true, true>(V, ld, nv, h1, w, w, 1.0, n, scratch, h2, s)) != hipSuccess) return e;
+          if ((e = hipMemcpyAsync(hb.data() + kMaxBasis, h2, sizeof(double) * (nv + 1), hipMemcpyDeviceToHost, s)) !=
+              hipSuccess)
+            return e;
+          if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+        }
+      }
+      double colsq = 0.0;
+      if (second) {
+        double h2sq = 0.0;
+        for (int i = 0; i < nv; ++i) {
+          Hj[i] = hb[i] + hb[kMaxBasis + i];
+          h2sq += hb[kMaxBasis + i] * hb[kMaxBasis + i];
+        }
+        wsq = hb[kMaxBasis + nv] - h2sq;
+        hlast = h2;
+      } else {
+        for (int i = 0; i < nv; ++i) Hj[i] = hb[i];
+      }
       for (int i = 0; i < nv; ++i) {
-        Hj[i] = hb[i] + hb[kMaxBasis + i];
-        h2sq += hb[kMaxBasis + i] * hb[kMaxBasis + i];
         colsq += Hj[i] * Hj[i];
         bad = bad || !std::isfinite(Hj[i]);
       }
-      const double wsq = hb[kMaxBasis + nv] - h2sq;
       const double hn = std::sqrt(std::max(wsq, 0.0));
       if (bad || !std::isfinite(hn)) {
         out.nan = true;
@@ -157,7 +192,7 @@ hipError_t gmres(KrylovBufs &K, Op &&op, Prec &&prec, bool have_prec, const T *b
       if (std::fabs(g[j + 1]) <= tol * bnorm || breakdown) break;
       // v_{j+1} = (w - V h2) / hn  (not needed after the last step of a cycle)
       if (j + 1 < m && out.iters < maxit &&
-          (e = kr_orth<T, false, false>(V, ld, nv, h2, w, V + size_t(j + 1) * ld, 1.0 / hn, n, scratch,
+          (e = kr_orth<T, false, false>(V, ld, nv, hlast, w, V + size_t(j + 1) * ld, 1.0 / hn, n, scratch,
                                         nullptr, s)) != hipSuccess)
         return e;
     }

@@ -67,17 +67,19 @@ struct Vec16 {
 // arithmetic runs; with the loads behind per-slot branches the compiler
 // serialises load and use and the passes fall to a fraction of the HBM rate.
 
-// partial[b*nv + k] = sum over block b of V_k[i] w[i]   (V_k = V + k*ld)
+// partial[b*(nv+1) + k] = sum over block b of V_k[i] w[i]   (V_k = V + k*ld),
+// and slot nv: sum over block b of w[i]^2
 template <typename T, int NVMAX>
 __global__ __launch_bounds__(kRedThreads) void k_multidot(const T *__restrict__ V, size_t ld, int nv,
                                                            const T *__restrict__ w, size_t n,
                                                            double *__restrict__ partial) {
   using vec = typename Vec16<T>::type;
   constexpr int VW = Vec16<T>::VW;
-  __shared__ double sm[(kRedThreads / 64 + 1) * NVMAX];
-  double acc[NVMAX];
+  constexpr int NA = NVMAX + 1;
+  __shared__ double sm[(kRedThreads / 64 + 1) * NA];
+  double acc[NA];
 #pragma unroll
-  for (int k = 0; k < NVMAX; ++k) acc[k] = 0.0;
+  for (int k = 0; k < NA; ++k) acc[k] = 0.0;
   const size_t nvec = n / VW;
   GRID_STRIDE(i, nvec) {
     const vec wv = reinterpret_cast<const vec *>(w)[i];
@@ -96,6 +98,8 @@ __global__ __launch_bounds__(kRedThreads) void k_multidot(const T *__restrict__ 
           for (int e = 0; e < VW; ++e)
             acc[c * KR_CH(NVMAX) + k] = fma(double(vv[k][e]), double(wv[e]), acc[c * KR_CH(NVMAX) + k]);
       }
+#pragma unroll
+    for (int e = 0; e < VW; ++e) acc[NVMAX] = fma(double(wv[e]), double(wv[e]), acc[NVMAX]);
   }
   for (size_t i = nvec * VW + blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n;
        i += size_t(gridDim.x) * blockDim.x) {
@@ -103,9 +107,15 @@ __global__ __launch_bounds__(kRedThreads) void k_multidot(const T *__restrict__ 
 #pragma unroll
     for (int k = 0; k < NVMAX; ++k)
       if (k < nv) acc[k] = fma(double(V[k * ld + i]), wi, acc[k]);
+    acc[NVMAX] = fma(wi, wi, acc[NVMAX]);
   }
-  block_sum<NVMAX>(acc, sm);  // slots k >= nv are never written out
-  if (threadIdx.x < nv) partial[blockIdx.x * nv + threadIdx.x] = sm[(kRedThreads / 64) * NVMAX + threadIdx.x];
+  // drop the slots k >= nv (products with V_{nv-1}) and pack the norm right
+  // after the nv dots (static indices only: no scratch)
+#pragma unroll
+  for (int k = 0; k < NVMAX; ++k)
+    if (k >= nv) acc[k] = (k == nv) ? acc[NVMAX] : 0.0;
+  block_sum<NA>(acc, sm);
+  if (threadIdx.x <= nv) partial[blockIdx.x * (nv + 1) + threadIdx.x] = sm[(kRedThreads / 64) * NA + threadIdx.x];
 }
 
 // wout <- scale * (w - sum_k h_k V_k); then DOT: partial sums of V_k . wout;
@@ -294,7 +304,7 @@ hipError_t kr_multidot(const T *V, size_t ld, int nv, const T *w, size_t n, doub
   }
   KR_BUCKETS(KR_MD)
 #undef KR_MD
-  hipLaunchKernelGGL(k_reduce, dim3(nv), b, 0, s, partial, kRedBlocks, nv, out);
+  hipLaunchKernelGGL(k_reduce, dim3(nv + 1), b, 0, s, partial, kRedBlocks, nv + 1, out);
   return hipGetLastError();
 }
 

@@ -771,7 +771,7 @@ static dg_status make_data(dg_handle *h, const dg_learn_opts &o, uint16_t *Xall,
   }
   std::vector<int64_t> hc(per);
   int64_t row = 0;
-  dg_solve_opts so{DG_GMRES64, DG_PREC_BLOCK_JACOBI, 30, 1, 1e-4};
+  dg_solve_opts so{DG_GMRES64, DG_PREC_BLOCK_JACOBI, 30, 1, DG_ORTH_CGS1, 1e-4};
   for (int q = 0; q < o.nrhs && row < npairs; ++q) {
     // fields come in sign pairs (u*, -u*): the pairs of -u* are exact too and
     // teach the network the odd symmetry the preconditioner imposes

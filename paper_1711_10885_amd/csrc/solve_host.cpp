@@ -72,11 +72,13 @@ extern "C" dg_status dg_solve(dg_handle *h, const double *f, double *u, double t
       return set_error(DG_EINVAL, "dg_solve: f and u overlap");
   }
   if (!(tol > 0.0) || !std::isfinite(tol)) return set_error(DG_EINVAL, "dg_solve: tol must be positive");
-  dg_solve_opts opt{DG_GMRES64, DG_PREC_NONE, 30, 20000, 1e-4};
+  dg_solve_opts opt{DG_GMRES64, DG_PREC_NONE, 30, 20000, DG_ORTH_CGS1, 1e-4};
   if (o) opt = *o;
   if (opt.restart < 1 || opt.restart > kMaxBasis - 1)
     return set_error(DG_EINVAL, "dg_solve: restart must be in 1..63");
   if (opt.maxit < 1) return set_error(DG_EINVAL, "dg_solve: maxit must be >= 1");
+  if (opt.orth != DG_ORTH_CGS1 && opt.orth != DG_ORTH_CGS2)
+    return set_error(DG_EINVAL, "dg_solve: orth must be DG_ORTH_CGS1 or DG_ORTH_CGS2");
   if (opt.method != DG_GMRES64 && opt.method != DG_GMRES_IR && opt.method != DG_FGMRES)
     return set_error(DG_EINVAL, "dg_solve: unknown method");
   if (opt.method == DG_GMRES_IR && !(opt.inner_tol > 0.0 && opt.inner_tol < 1.0))
@@ -122,6 +124,7 @@ extern "C" dg_status dg_solve(dg_handle *h, const double *f, double *u, double t
   K.ld = ld;
   K.restart = m;
   K.flex = flex;
+  K.reorth = opt.orth == DG_ORTH_CGS2;
   double *scratch = h->red, *small = h->red + size_t(kRedBlocks) * kMaxBasis;
 
   dg_solve_stats stats{};

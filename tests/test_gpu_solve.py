@@ -95,6 +95,28 @@ def test_reference_kernel_gives_the_same_solve():
     assert _oracle_rel_residual(p, u1, f) <= 1.05e-10
 
 
+@pytest.mark.parametrize("method", ["gmres64", "gmres_ir", "fgmres"])
+def test_both_orthogonalisations_solve_to_tolerance(method):
+    """One projection (default) and the repeated projection reach the same
+    tolerance on the oracle's residual with iteration counts a few percent
+    apart (equal in exact arithmetic)."""
+    from paper_1711_10885_amd import binding
+    m = {"gmres64": binding.DG_GMRES64, "gmres_ir": binding.DG_GMRES_IR, "fgmres": binding.DG_FGMRES}[method]
+    p = W.random_problem(455, ncell=(4, 3, 3), k=3, b="sine")
+    f = W.random_vector(p.ndof, 456)
+    torch = _torch()
+    with binding.DG(p, flags=binding.DG_WITH_BLOCK_JACOBI) as dg:
+        fd = torch.from_numpy(f).cuda()
+        out = {}
+        for orth in (binding.DG_ORTH_CGS1, binding.DG_ORTH_CGS2):
+            u, st, rc = dg.solve(fd, tol=1e-10, method=m, precond=binding.DG_PREC_BLOCK_JACOBI, orth=orth)
+            assert rc == 0
+            assert _oracle_rel_residual(p, u.cpu().numpy(), f) <= 1.05e-10
+            out[orth] = st["iters"]
+    print(f"{method}: iterations CGS1 {out[0]}, CGS2 {out[1]}", flush=True)
+    assert abs(out[0] - out[1]) <= max(3, 0.05 * out[1])
+
+
 def test_maxit_reports_not_converged_with_stats():
     from paper_1711_10885_amd import binding
     p = W.poisson_k2_8()
@@ -131,7 +153,7 @@ def test_non_finite_rhs_is_reported():
 
 
 @pytest.mark.parametrize("over", [dict(restart=0), dict(restart=64), dict(maxit=0), dict(method=9),
-                                  dict(precond=9)])
+                                  dict(precond=9), dict(orth=2)])
 def test_invalid_options_are_rejected(over):
     from paper_1711_10885_amd import binding
     p = W.random_problem(495, ncell=(1, 1, 1), k=1)
