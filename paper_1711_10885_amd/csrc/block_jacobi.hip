@@ -290,6 +290,81 @@ __global__ __launch_bounds__(kBjThreads) void k_bj_apply_grp(const float *__rest
   }
 }
 
+// Shared blocks, 216 or 512 rows: a workgroup takes GPW = 256 / (nb / 4)
+// groups (4 or 2, at most 32 cells) and stages their r values in LDS, 32
+// columns at a time (lds[column][cell], coalesced loads of each cell's
+// contiguous values).  A thread owns 4 rows of one group; per column it
+// loads 16 bytes of the block from cache and reads its 8 cells' values as
+// LDS broadcasts, instead of 8 global loads that every thread of the group
+// repeats.
+constexpr int kBjStageCols = 32;
+constexpr int kBjStageCells = 32;
+template <typename TR, typename TZ, typename TA>
+__global__ __launch_bounds__(kBjThreads) void k_bj_apply_grp_lds(const float *__restrict__ Binv,
+                                                                 const int32_t *__restrict__ cells,
+                                                                 const int32_t *__restrict__ gblock,
+                                                                 const TR *__restrict__ r, TZ *__restrict__ z,
+                                                                 int nb, int64_t ngroups) {
+  __shared__ TA rs[kBjStageCols * kBjStageCells];
+  __shared__ int32_t cs[kBjStageCells];
+  const int per = nb / 4;
+  const int gpw = kBjThreads / per;  // groups per workgroup (<= 4)
+  const int t = threadIdx.x;
+  const int q = t / per;  // group of this thread within the workgroup
+  const int64_t grp = int64_t(blockIdx.x) * gpw + q;
+  const bool act = q < gpw && grp < ngroups;
+  const int i0 = (t - q * per) * 4;
+  const int ncl = gpw * kBjGroup;  // cells staged per workgroup
+  // cell list of the workgroup; padding (-1, or groups past the end) reads
+  // the first cell of the workgroup and is never written
+  if (t < ncl) {
+    const int64_t g = int64_t(blockIdx.x) * gpw + t / kBjGroup;
+    const int32_t c = g < ngroups ? cells[g * kBjGroup + t % kBjGroup] : -1;
+    cs[t] = c;
+  }
+  __syncthreads();
+  const int32_t cfirst = cs[0];
+  const float *Bc = Binv + (act ? int64_t(gblock[grp]) * nb * nb + i0 : 0);
+  TA acc[kBjGroup][4];
+#pragma unroll
+  for (int c = 0; c < kBjGroup; ++c)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc[c][e] = TA(0);
+  for (int j0 = 0; j0 < nb; j0 += kBjStageCols) {
+    const int jc = min(kBjStageCols, nb - j0);
+    __syncthreads();  // the previous chunk has been consumed
+    for (int e = t; e < ncl * jc; e += kBjThreads) {
+      const int cl = e / jc, jj = e - cl * jc;
+      const int32_t c = cs[cl] >= 0 ? cs[cl] : cfirst;
+      rs[jj * kBjStageCells + cl] = TA(r[int64_t(c) * nb + j0 + jj]);
+    }
+    __syncthreads();
+    if (act) {
+      typedef float f4 __attribute__((ext_vector_type(4)));
+      const TA *rq = rs + q * kBjGroup;
+      for (int jj = 0; jj < jc; ++jj) {
+        const f4 v = *reinterpret_cast<const f4 *>(Bc + size_t(j0 + jj) * nb);
+        TA rv[kBjGroup];
+#pragma unroll
+        for (int c = 0; c < kBjGroup; ++c) rv[c] = rq[jj * kBjStageCells + c];
+#pragma unroll
+        for (int c = 0; c < kBjGroup; ++c)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[c][e] = fma(TA(v[e]), rv[c], acc[c][e]);
+      }
+    }
+  }
+  if (act) {
+#pragma unroll
+    for (int c = 0; c < kBjGroup; ++c) {
+      const int32_t cell = cs[q * kBjGroup + c];
+      if (cell >= 0)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) z[int64_t(cell) * nb + i0 + e] = TZ(acc[c][e]);
+    }
+  }
+}
+
 // FP16 copy with one scale per cell: h = fp16(b / sc_c), sc_c = max |b| over the block
 __global__ __launch_bounds__(kBjThreads) void k_to_f16_scaled(const double *__restrict__ B, int nb,
                                                               _Float16 *__restrict__ H, float *__restrict__ sc) {
@@ -482,7 +557,11 @@ hipError_t bj_apply(const dg_handle *h, const TR *r, TZ *z, hipStream_t s, bool 
   if (h->bj_cells) {
     // shared blocks; FP32 accumulation for the FP32 inner solves
     using TA = typename std::conditional<std::is_same<TZ, float>::value, float, double>::type;
-    if (nb % 4 == 0)
+    if (nb == 216 || nb == 512)
+      hipLaunchKernelGGL((k_bj_apply_grp_lds<TR, TZ, TA>), dim3(unsigned((h->bj_ngroups + kBjThreads / (nb / 4) - 1) /
+                                                                       (kBjThreads / (nb / 4)))),
+                         dim3(kBjThreads), 0, s, h->bj, h->bj_cells, h->bj_gblock, r, z, nb, h->bj_ngroups);
+    else if (nb % 4 == 0)
       hipLaunchKernelGGL((k_bj_apply_grp<TR, TZ, TA, 4>), dim3(grid_for(h->bj_ngroups * (nb / 4))), dim3(kBjThreads),
                          0, s, h->bj, h->bj_cells, h->bj_gblock, r, z, nb, h->bj_ngroups);
     else
