@@ -6,7 +6,7 @@
 // matrices of Sec. 3.2 (eq. (gradient_matrices)), which is the sum
 // factorization kernel of eq. (sum_fact_kernel) with the tensor rotation fused
 // into the LDS exchange between directions.  Tensors pass through LDS only to
-// change the pencil direction (pencils padded to N+1 doubles).
+// change the pencil direction (pencils stored with an odd stride).
 //
 // Each 1D contraction uses the point symmetry of the Gauss rule and the parity
 // of the Legendre basis (theta_j(1-t) = (-1)^j theta_j(t)): only rows
@@ -85,28 +85,30 @@ struct FMesh {
 // Pencil storage for the exchanges that dominate LDS size.  For N = 2, 4, 8 the
 // pencils are unpadded and element t of pencil p is rotated by (p N)/16
 // places, which keeps 16 consecutive lanes reading element t of 16
-// consecutive pencils on distinct banks; other N pad pencils to N+1 doubles.
+// consecutive pencils on distinct banks.  Other N store pencils with the odd
+// stride N | 1 (N + 1 for even N, N itself for odd N): lanes reading element
+// t of consecutive pencils then step through the banks with an odd stride
+// (an even stride would repeat banks every 64 / gcd(2 stride, 64) lanes).
 template <int N>
 struct PL {
   static constexpr bool SW = (N == 2 || N == 4 || N == 8);
-  static constexpr int S = SW ? N : N + 1;  // doubles per pencil
+  static constexpr int S = SW ? N : (N | 1);  // doubles per pencil
   __device__ static __forceinline__ int at(int p, int t) {
-    return SW ? p * N + ((t + (p * N) / 16) & (N - 1)) : p * (N + 1) + t;
+    return SW ? p * N + ((t + (p * N) / 16) & (N - 1)) : p * S + t;
   }
 };
 
 template <int N>
 struct FCfg {
   static constexpr int NN = N * N;
-  static constexpr int PS = N + 1;  // padded pencil stride
+  static constexpr int PS = N | 1;  // pencil stride: odd (see PL)
   static constexpr int LANES = NN;
   // cells per workgroup: one 64-lane wave holds 64 / N^2 cells, which
-  // leaves 22 % (N = 5), 44 % (N = 6) and 37 % (N = 9, two waves per cell)
-  // of the lanes idle; larger workgroups pack 10, 7 and 3 cells into 256
-  // lanes (98, 98 and 95 % busy) while two workgroups (one for N = 9) still
-  // fit in the 160 KB of LDS of a CU.  N = 7 keeps one cell per wave: nine
-  // cells in 448 lanes need 145 KB, one workgroup per CU, and run slower.
-  static constexpr int CPB = (N == 5) ? 10 : (N == 6) ? 7 : (N == 9) ? 3 : (NN <= 64 ? 64 / NN : 1);
+  // leaves 22 % (N = 5), 44 % (N = 6), 23 % (N = 7) and 37 % (N = 9, two
+  // waves per cell) of the lanes idle; larger workgroups pack 10, 7, 5 and 3
+  // cells into 256 lanes (98, 98, 96 and 95 % busy) while two workgroups
+  // (one for N = 9) still fit in the 160 KB of LDS of a CU
+  static constexpr int CPB = (N == 5) ? 10 : (N == 6) ? 7 : (N == 7) ? 5 : (N == 9) ? 3 : (NN <= 64 ? 64 / NN : 1);
   static constexpr int THREADS = ((CPB * LANES + 63) / 64) * 64;
   static constexpr int WAVES_PER_SIMD = (N <= 8) ? 2 : 1;  // register budget target
   static constexpr int FCW = 8;  // doubles per face-constant record
