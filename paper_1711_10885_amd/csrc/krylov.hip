@@ -3,15 +3,15 @@
 //
 // The paper stops at the operator application and motivates it as the core of
 // iterative solvers (Sec. 1); the solver here is restarted GMRES (Saad &
-// Schultz) with right preconditioning and classical Gram-Schmidt applied twice
-// (CGS2).  Every pass over the Krylov basis is one fused kernel that reads each
-// basis vector once:
-//   pass 1: h1 = V^T w
-//   pass 2: w <- w - V h1, then h2 = V^T w and ||w||^2 on the updated w
-//           (same sweep)
-//   pass 3: v_{j+1} = (w - V h2) / h_{j+1,j}, written straight into the basis;
-//           h_{j+1,j}^2 = ||w||^2 - ||h2||^2 since V is orthonormal.
-// The host reads h1, h2 and ||w||^2 once per iteration (one synchronisation).
+// Schultz) with right preconditioning and classical Gram-Schmidt.  Every pass
+// over the Krylov basis is one fused kernel that reads each basis vector once:
+//   pass 1: h1 = V^T w and ||w||^2 (k_multidot)
+//   [pass 2, CGS2 or heavy cancellation only: w <- w - V h1, then h2 = V^T w
+//           and ||w||^2 on the updated w in the same sweep (k_orth)]
+//   last:   v_{j+1} = (w - V h) / h_{j+1,j}, written straight into the basis,
+//           h the last projection; h_{j+1,j}^2 = ||w||^2 - ||h||^2 since V is
+//           orthonormal (k_orth).
+// The host reads the projections and ||w||^2 after the dot-product passes.
 // Reductions are two-stage and deterministic: fixed grid, per-block partial
 // sums in a fixed order, then one block per output.
 #include <cmath>
