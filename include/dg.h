@@ -70,7 +70,8 @@ typedef enum {
  *              b_sin = 1, b_axis = {1,2,0}.)
  *   c          constant reaction coefficient.
  *   sigma      penalty scale: gamma_F = sigma * <d-,d+> / min(h_a-, h_a+) on
- *              interior faces, sigma * d / h_a on boundary faces, with
+ *              interior (and periodic) faces, sigma * d / h_a on boundary
+ *              faces, with
  *              d = kappa K_aa and <.,.> the harmonic mean (Sec. 2.2:
  *              sigma = alpha p (p+d-1), alpha = 2, in the paper).
  *   flags      DG_WITH_BLOCK_JACOBI: build the block-Jacobi preconditioner
@@ -85,7 +86,16 @@ typedef enum {
  *              to about 1e-11 relative, the same boundary faces, and b
  *              without a sine part) share one stored block when that at
  *              least halves the store: a uniform mesh with constant
- *              coefficients has 27 blocks.
+ *              coefficients has 27 blocks.  With a periodic axis of an odd
+ *              number of cells > 1 the two-colour probing is not valid:
+ *              DG_EINVAL.
+ *              DG_PERIODIC_X, _Y, _Z: the axis is periodic (the first and
+ *              last cells are face neighbours across the domain boundary,
+ *              an interior face of the same form, with b_a read at node 0
+ *              from both sides); other axes keep homogeneous Dirichlet
+ *              faces.  b must then take the same value at both ends of a
+ *              periodic axis for the scheme to be consistent (the sine part
+ *              does when the axis spans an integer length).
  */
 typedef struct {
   int32_t ncell[3];
@@ -102,6 +112,9 @@ typedef struct {
 } dg_problem;
 
 #define DG_WITH_BLOCK_JACOBI 2
+#define DG_PERIODIC_X 4
+#define DG_PERIODIC_Y 8
+#define DG_PERIODIC_Z 16
 
 /* Create a handle on the current HIP device: validates the problem, builds
  * the 1D Gauss-Legendre/Legendre tables (Sec. 3.1/3.2, eq.

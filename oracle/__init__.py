@@ -59,6 +59,7 @@ class _Problem(ctypes.Structure):
         ("b_axis", ctypes.c_int32 * 3),
         ("c", ctypes.c_double),
         ("sigma", ctypes.c_double),
+        ("periodic", ctypes.c_int32 * 3),
     ]
 
 
@@ -114,6 +115,9 @@ class _Marshalled:
         s.kappa = _dptr(self.kappa) if self.kappa is not None else ctypes.POINTER(ctypes.c_double)()
         s.c = float(prob.c)
         s.sigma = float(prob.sigma)
+        per = getattr(prob, "periodic", (False, False, False))
+        for a in range(3):
+            s.periodic[a] = 1 if per[a] else 0
         self.struct = s
 
 
@@ -267,14 +271,24 @@ def block_diagonal(prob, nthreads: int | None = None) -> np.ndarray:
 
     Face neighbours differ in exactly one index by one, so the two parity
     classes of i1+i2+i3 never touch: probing one class at a time with e_j
-    leaves, in the rows of a probed cell, exactly column j of its block."""
+    leaves, in the rows of a probed cell, exactly column j of its block.
+    (With a periodic axis of odd length the classes are per-axis colours.)"""
     nb = (prob.k + 1) ** 3
     N1, N2, N3 = prob.ncell
     ncells = N1 * N2 * N3
     cid = np.arange(ncells)
-    par = ((cid % N1) + ((cid // N1) % N2) + (cid // (N1 * N2))) % 2
+    idx = [cid % N1, (cid // N1) % N2, cid // (N1 * N2)]
+    per = getattr(prob, "periodic", (False, False, False))
+    odd = [per[a] and prob.ncell[a] > 1 and prob.ncell[a] % 2 == 1 for a in range(3)]
+    if any(odd):
+        # a periodic axis of odd length joins the first and last cells, which
+        # share a parity: colour each axis by parity, the last cell apart
+        col = [np.where((idx[a] == prob.ncell[a] - 1) & odd[a], 2, idx[a] % 2) for a in range(3)]
+        par = col[0] + 3 * col[1] + 9 * col[2]
+    else:
+        par = (idx[0] + idx[1] + idx[2]) % 2
     B = np.zeros((ncells, nb, nb))
-    for p in (0, 1):
+    for p in np.unique(par):
         probed = np.nonzero(par == p)[0]
         for j in range(nb):
             x = np.zeros(ncells * nb)

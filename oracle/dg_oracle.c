@@ -26,7 +26,9 @@
  *  - penalty gamma_F = sigma * <delta-,delta+> / min(h_a-, h_a+) on interior
  *    faces (sigma absorbs alpha*p*(p+d-1); |F|/min|T| = 1/min h_a on a tensor
  *    grid), gamma_F = sigma * delta- / h_a- on boundary faces;
- *  - every boundary face is homogeneous Dirichlet (g = 0), so the boundary
+ *  - periodic axes (or_problem.periodic) join the first and last cells by an
+ *    interior face, whose normal velocity is read at the axis' first node;
+ *  - every other boundary face is homogeneous Dirichlet (g = 0), so the boundary
  *    upwind term is Phi(u,0,b_nu) (F^{DO} sum of eq. (blf)) and the boundary
  *    consistency/symmetry/penalty terms use [[v]] = {v} = v-;
  *  - D = kappa_T K with K constant SPD and kappa_T > 0 constant per cell;
@@ -53,6 +55,7 @@ typedef struct {
   int32_t b_axis[3];
   double c;
   double sigma;
+  int32_t periodic[3]; /* 1: axis a is periodic (first and last cells are neighbours) */
 } or_problem;
 
 /* term mask for or_apply: which sums of eq. (blf) to include */
@@ -263,6 +266,7 @@ static void interior_face(const or_problem *p, const or_tables *t, int a, const 
   const int tb = (a == 0) ? 1 : 0, tc = (a == 2) ? 1 : 2;
   int ip[3] = {im[0], im[1], im[2]};
   ip[a] += 1;
+  if (ip[a] == p->ncell[a]) ip[a] = 0; /* periodic axis: the face across the domain boundary */
   double om[3], hm[3], op[3], hp[3];
   cell_geom(p, im, om, hm);
   cell_geom(p, ip, op, hp);
@@ -400,14 +404,21 @@ int oracle_apply(const or_problem *p, const double *x, double *y, int terms, int
     }
   }
   if (terms & OR_INTERIOR) {
+    /* pass 2 takes the faces across a periodic boundary (last cell to the
+     * first); they would share cells with pass 0 or 1 when ncell is odd */
     for (int a = 0; a < 3; ++a)
-      for (int parity = 0; parity < 2; ++parity) {
+      for (int parity = 0; parity < 3; ++parity) {
+        if (parity == 2 && !p->periodic[a]) continue;
 #pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads)
         for (int64_t c = 0; c < ncells; ++c) {
           const int ic[3] = {(int)(c % N1), (int)((c / N1) % N2), (int)(c / ((int64_t)N1 * N2))};
-          if (ic[a] % 2 != parity || ic[a] + 1 >= p->ncell[a]) continue;
+          if (parity == 2) {
+            if (ic[a] != p->ncell[a] - 1) continue;
+          } else if (ic[a] % 2 != parity || ic[a] + 1 >= p->ncell[a]) {
+            continue;
+          }
           int jc[3] = {ic[0], ic[1], ic[2]};
-          jc[a] += 1;
+          jc[a] = (ic[a] + 1) % p->ncell[a];
           const int64_t cp = cell_id(p, jc);
           interior_face(p, &t, a, ic, x + c * nb, x + cp * nb, y + c * nb, y + cp * nb);
         }
@@ -418,6 +429,7 @@ int oracle_apply(const or_problem *p, const double *x, double *y, int terms, int
     for (int64_t c = 0; c < ncells; ++c) {
       const int ic[3] = {(int)(c % N1), (int)((c / N1) % N2), (int)(c / ((int64_t)N1 * N2))};
       for (int a = 0; a < 3; ++a) {
+        if (p->periodic[a]) continue;
         if (ic[a] == 0) boundary_face(p, &t, a, 0, ic, x + c * nb, y + c * nb);
         if (ic[a] == p->ncell[a] - 1) boundary_face(p, &t, a, 1, ic, x + c * nb, y + c * nb);
       }
@@ -449,20 +461,20 @@ int oracle_apply_rows(const or_problem *p, const double *x, const int64_t *cells
     double *yT = y_rows + s * nb;
     if (terms & OR_VOLUME) volume_cell(p, &t, ic, x + c * nb, yT);
     for (int a = 0; a < 3; ++a) {
-      /* lower face of T */
-      if (ic[a] == 0) {
+      /* lower face of T (across the domain boundary on a periodic axis) */
+      if (ic[a] == 0 && !p->periodic[a]) {
         if (terms & OR_BOUNDARY) boundary_face(p, &t, a, 0, ic, x + c * nb, yT);
       } else if (terms & OR_INTERIOR) {
         int jm[3] = {ic[0], ic[1], ic[2]};
-        jm[a] -= 1;
+        jm[a] = (ic[a] + p->ncell[a] - 1) % p->ncell[a];
         interior_face(p, &t, a, jm, x + cell_id(p, jm) * nb, x + c * nb, NULL, yT);
       }
       /* upper face of T */
-      if (ic[a] == p->ncell[a] - 1) {
+      if (ic[a] == p->ncell[a] - 1 && !p->periodic[a]) {
         if (terms & OR_BOUNDARY) boundary_face(p, &t, a, 1, ic, x + c * nb, yT);
       } else if (terms & OR_INTERIOR) {
         int jp[3] = {ic[0], ic[1], ic[2]};
-        jp[a] += 1;
+        jp[a] = (ic[a] + 1) % p->ncell[a];
         interior_face(p, &t, a, ic, x + c * nb, x + cell_id(p, jp) * nb, yT, NULL);
       }
     }

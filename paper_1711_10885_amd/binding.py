@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "libdgmf.so")
 
 DG_OK, DG_EINVAL, DG_ENOMEM, DG_EHIP, DG_ENOTCONV, DG_ENAN = 0, -1, -2, -3, -4, -5
 DG_WITH_BLOCK_JACOBI = 2
+DG_PERIODIC_X, DG_PERIODIC_Y, DG_PERIODIC_Z = 4, 8, 16
 DG_KERNEL_AUTO, DG_KERNEL_REFERENCE = 0, 1
 DG_GMRES64, DG_GMRES_IR, DG_FGMRES = 0, 1, 2
 DG_PREC_NONE, DG_PREC_BLOCK_JACOBI, DG_PREC_LEARNED = 0, 1, 2
@@ -193,7 +194,8 @@ class DG:
         s.kappa = _dptr(kap) if kap is not None else ctypes.POINTER(ctypes.c_double)()
         s.c = float(prob.c)
         s.sigma = float(prob.sigma)
-        s.flags = int(flags)
+        per = getattr(prob, "periodic", (False, False, False))
+        s.flags = int(flags) | sum(DG_PERIODIC_X << a for a in range(3) if per[a])
         h = ctypes.c_void_p()
         _check(lib.dg_setup(ctypes.byref(s), ctypes.byref(h)))
         self._h = h

@@ -42,6 +42,7 @@
 #include <vector>
 
 #include "dg_internal.h"
+#include "mesh_nb.h"
 #include "gl_tables.inc"
 
 namespace dgmf {
@@ -74,6 +75,7 @@ struct TabOff {
 
 struct FMesh {
   int ncell[3];
+  int periodic;    // bit a: axis a is periodic
   const double *h[3], *bvol[3], *bnode[3], *kappa, *w;
   double K[9], c, sigma;
   int b_axis[3];
@@ -277,14 +279,15 @@ __device__ __forceinline__ FC face_coef(const FMesh &M, const FaceGeo &G, int ce
   const int b = (a == 0) ? 1 : 0, c = (a == 2) ? 1 : 2;
   const int ia = seli3(a, G.i0, G.i1, G.i2);
   const int na = seli3(a, M.ncell[0], M.ncell[1], M.ncell[2]);
-  const bool in = e ? (ia + 1 < na) : (ia > 0);
   const int cst = seli3(a, 1, M.ncell[0], M.ncell[0] * M.ncell[1]);
-  const int ncl = in ? (e ? cell + cst : cell - cst) : cell;
+  const FaceNb nb = face_nb(cell, ia, na, cst, (M.periodic >> a) & 1, e);
+  const bool in = nb.in;
+  const int ncl = nb.cell;
   const double *ha_tab = a == 0 ? M.h[0] : (a == 1 ? M.h[1] : M.h[2]);
   const double ha = sel3(a, G.h0, G.h1, G.h2);
   const double hb = sel3(b, G.h0, G.h1, G.h2);
   const double hc = sel3(c, G.h0, G.h1, G.h2);
-  const double hn = in ? ha_tab[ia + (e ? 1 : -1)] : ha;
+  const double hn = in ? ha_tab[nb.ja] : ha;
   const double kn = in ? (M.kappa ? M.kappa[ncl] : 1.0) : 0.0;
   const double Kaa = sel3(a, M.K[0], M.K[4], M.K[8]);
   const double Kab = a == 0 ? M.K[1] : (a == 1 ? M.K[3] : M.K[6]);  // K[a][b]
@@ -337,7 +340,11 @@ __device__ __forceinline__ double face_b(const FMesh &M, const FaceGeo &G, int N
   const int ax = M.b_axis[a];
   const double *bv = a == 0 ? M.bvol[0] : (a == 1 ? M.bvol[1] : M.bvol[2]);
   const double *bn = a == 0 ? M.bnode[0] : (a == 1 ? M.bnode[1] : M.bnode[2]);
-  if (ax == a) return bn[seli3(a, G.i0, G.i1, G.i2) + e];
+  if (ax == a) {
+    const int ia = seli3(a, G.i0, G.i1, G.i2);
+    const bool wrap = ((M.periodic >> a) & 1) && e && ia + 1 == seli3(a, M.ncell[0], M.ncell[1], M.ncell[2]);
+    return bn[face_node(ia, e, wrap)];
+  }
   const int b = (a == 0) ? 1 : 0;
   if (ax == b) return bv[seli3(b, G.i0, G.i1, G.i2) * N + qb];
   const int c = (a == 2) ? 1 : 2;
@@ -447,11 +454,12 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
     const int a = f >> 1, e = f & 1;
     const cptr tb = fresh(tab0);
     const int ia = a == 0 ? G.i0 : (a == 1 ? G.i1 : G.i2);
-    const bool in = e ? (ia + 1 < M.ncell[a]) : (ia > 0);
     const int cst = (a == 0) ? 1 : (a == 1) ? M.ncell[0] : M.ncell[0] * M.ncell[1];
+    const FaceNb nb = face_nb(cell, ia, M.ncell[a], cst, (M.periodic >> a) & 1, e);
+    const bool in = nb.in;
     T v[N];
     if (in) {
-      const T *xn = x + size_t(e ? cell + cst : cell - cst) * NNN;
+      const T *xn = x + size_t(nb.cell) * NNN;
       const int base = (a == 0) ? (N * alpha + NN * beta)
                        : (a == 1) ? (alpha + NN * beta) : (alpha + N * beta);
       const int st = (a == 0) ? 1 : (a == 1) ? N : NN;
@@ -1143,11 +1151,12 @@ __global__ __launch_bounds__(256) void apply_lane_kernel(const T *__restrict__ x
     const int b = (a == 0) ? 1 : 0, c = (a == 2) ? 1 : 2;
     const FC F = face_coef(M, G, cell, a, e);
     const int ia = a == 0 ? G.i0 : (a == 1 ? G.i1 : G.i2);
-    const bool in = e ? (ia + 1 < M.ncell[a]) : (ia > 0);
     const int cst = (a == 0) ? 1 : (a == 1) ? M.ncell[0] : M.ncell[0] * M.ncell[1];
+    const FaceNb nb = face_nb(cell, ia, M.ncell[a], cst, (M.periodic >> a) & 1, e);
+    const bool in = nb.in;
     T XN[NNN];
     {
-      const T *xn = x + size_t(in ? (e ? cell + cst : cell - cst) : cell) * NNN;
+      const T *xn = x + size_t(nb.cell) * NNN;
 #pragma unroll
       for (int j = 0; j < NNN; ++j) XN[j] = in ? xn[j] : T(0);
     }
@@ -1256,6 +1265,7 @@ static hipError_t launch_fused_n(const dg_handle *h, const T *x, T *y, hipStream
   M.c = h->mesh.c;
   M.sigma = h->mesh.sigma;
   M.ncells = int(h->ncells);
+  M.periodic = h->mesh.periodic;
   // tiles of up to 4 cells along axis 3: z neighbours are adjacent in the
   // processing order, y neighbours 4*N1 cells apart
   M.tz = h->mesh.ncell[2] < 4 ? h->mesh.ncell[2] : 4;

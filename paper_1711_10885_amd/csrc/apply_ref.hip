@@ -14,6 +14,7 @@
 //    terms; the transposed tangential contractions; and the normal direction
 //    last, into the test functions of T only.
 #include "dg_internal.h"
+#include "mesh_nb.h"
 
 namespace dgmf {
 
@@ -24,6 +25,7 @@ struct RefTab {
 
 struct RefMesh {
   int ncell[3];
+  int periodic;  // bit a: axis a is periodic
   const double *h[3], *bvol[3], *bnode[3], *kappa;
   double K[9], c, sigma;
   int b_axis[3];
@@ -142,8 +144,9 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
     const int b = (a == 0) ? 1 : 0, c = (a == 2) ? 1 : 2;
     const int st[3] = {1, N, NF};
     const int sa = st[a], sb = st[b], sc = st[c];
-    const bool interior = e ? (ic[a] + 1 < M.ncell[a]) : (ic[a] > 0);
-    const int nbcell = interior ? cell + (e ? cstride[a] : -cstride[a]) : cell;
+    const FaceNb nb = face_nb(cell, ic[a], M.ncell[a], cstride[a], (M.periodic >> a) & 1, e);
+    const bool interior = nb.in;
+    const int nbcell = nb.cell;
     const double *xN = x + size_t(nbcell) * NB;
     // normal direction first: modal traces on the 2D (jb, jc) grid
     for (int i = tid; i < NF; i += kRefThreads) {
@@ -189,10 +192,7 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
     // penalty, written with the outer normal n_T = sgn e_a of cell T
     {
       const double sgn = e ? 1.0 : -1.0;
-      const double hn = interior ? (a == 0 ? M.h[0][ic[0] + (e ? 1 : -1)]
-                                   : a == 1 ? M.h[1][ic[1] + (e ? 1 : -1)]
-                                            : M.h[2][ic[2] + (e ? 1 : -1)])
-                                 : h[a];
+      const double hn = interior ? (a == 0 ? M.h[0][nb.ja] : a == 1 ? M.h[1][nb.ja] : M.h[2][nb.ja]) : h[a];
       const double kn = interior ? (M.kappa ? M.kappa[nbcell] : 1.0) : 0.0;
       const double Kaa = M.K[4 * a];
       const double dT = kap * Kaa, dN = kn * Kaa;
@@ -213,7 +213,7 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
         const int ax = M.b_axis[a];
         double ba;
         if (ax == a)
-          ba = M.bnode[a][ic[a] + e];
+          ba = M.bnode[a][face_node(ic[a], e, nb.wrap)];
         else if (ax == b)
           ba = M.bvol[a][ic[b] * N + qb];
         else
@@ -273,6 +273,7 @@ static hipError_t launch_ref_n(const dg_handle *h, const double *x, double *y, h
     M.b_axis[a] = h->mesh.b_axis[a];
   }
   M.kappa = h->mesh.kappa;
+  M.periodic = h->mesh.periodic;
   for (int i = 0; i < 9; ++i) M.K[i] = h->mesh.K[i];
   M.c = h->mesh.c;
   M.sigma = h->mesh.sigma;

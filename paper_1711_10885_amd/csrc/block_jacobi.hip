@@ -45,6 +45,7 @@
 #include <vector>
 
 #include "dg_internal.h"
+#include "mesh_nb.h"
 
 namespace dgmf {
 
@@ -410,20 +411,24 @@ static void cell_classes(const dg_problem *p, std::vector<int32_t> &cls, std::ve
   rep.clear();
   std::unordered_map<std::string, int32_t> ids;
   double key[19];
+  const int periodic = (p->flags >> 2) & 7;
   for (int64_t c = 0; c < ncells; ++c) {
     const int i[3] = {int(c % n1), int((c / n1) % n2), int(c / stride[2])};
+    FaceNb nb[3][2];
+    for (int a = 0; a < 3; ++a)
+      for (int e = 0; e < 2; ++e) nb[a][e] = face_nb(int(c), i[a], p->ncell[a], int(stride[a]), (periodic >> a) & 1, e);
     int nk = 0;
     for (int a = 0; a < 3; ++a) {
       const double *X = p->nodes[a];
-      key[nk++] = i[a] > 0 ? X[i[a]] - X[i[a] - 1] : -1.0;
+      key[nk++] = nb[a][0].in ? X[nb[a][0].ja + 1] - X[nb[a][0].ja] : -1.0;
       key[nk++] = X[i[a] + 1] - X[i[a]];
-      key[nk++] = i[a] + 1 < p->ncell[a] ? X[i[a] + 2] - X[i[a] + 1] : -1.0;
+      key[nk++] = nb[a][1].in ? X[nb[a][1].ja + 1] - X[nb[a][1].ja] : -1.0;
     }
     if (p->kappa) {
       key[nk++] = p->kappa[c];
       for (int a = 0; a < 3; ++a) {
-        key[nk++] = i[a] > 0 ? p->kappa[c - stride[a]] : -1.0;
-        key[nk++] = i[a] + 1 < p->ncell[a] ? p->kappa[c + stride[a]] : -1.0;
+        key[nk++] = nb[a][0].in ? p->kappa[nb[a][0].cell] : -1.0;
+        key[nk++] = nb[a][1].in ? p->kappa[nb[a][1].cell] : -1.0;
       }
     }
     // a sine part of b_r makes it depend on the coordinate along b_axis[r]

@@ -185,10 +185,14 @@ extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
         return set_error(DG_EINVAL, "dg_setup: kappa must be positive and finite");
   const int n = p->k + 1;
   if (ncells > (int64_t(1) << 31) / 2) return set_error(DG_EINVAL, "dg_setup: too many cells");
-  if (p->flags & ~DG_WITH_BLOCK_JACOBI)
+  if (p->flags & ~(DG_WITH_BLOCK_JACOBI | DG_PERIODIC_X | DG_PERIODIC_Y | DG_PERIODIC_Z))
     return set_error(DG_EINVAL, "dg_setup: unknown flag bits");
+  const int periodic = (p->flags >> 2) & 7;  // bit a: axis a
   if ((p->flags & DG_WITH_BLOCK_JACOBI) && n * n * n > kMaxBjBlock)
     return set_error(DG_EINVAL, "dg_setup: block Jacobi supports k <= 7");
+  for (int a = 0; a < 3; ++a)
+    if ((p->flags & DG_WITH_BLOCK_JACOBI) && ((periodic >> a) & 1) && p->ncell[a] > 1 && p->ncell[a] % 2)
+      return set_error(DG_EINVAL, "dg_setup: block Jacobi with a periodic axis needs an even number of cells");
 
   dg_handle *h = new dg_handle();
   std::memset(&h->prob, 0, sizeof(h->prob));
@@ -267,6 +271,7 @@ extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
     M.b_axis[a] = p->b_axis[a];
   }
   M.kappa = p->kappa ? base + off_kappa : nullptr;
+  M.periodic = periodic;
   M.w = base + off_w;
   std::memcpy(M.K, p->K, sizeof(M.K));
   M.c = p->c;

@@ -37,6 +37,7 @@ struct DevMesh {
   double *bvol[3];    // b_r at volume Gauss coordinates: [ncell[b_axis[r]] * m]
   double *bnode[3];   // b_r at nodes of axis b_axis[r]: [ncell[b_axis[r]] + 1]
   double *kappa;      // per cell or nullptr (= 1)
+  int periodic;       // bit a: axis a is periodic (DG_PERIODIC_*)
   double *w;          // Gauss weights on [0,1] (for lane-dependent lookups)
   double K[9];
   double c, sigma;

@@ -43,6 +43,7 @@ class Problem:
     b_axis: tuple = (0, 1, 2)
     c: float = 0.0
     sigma: float = 1.0
+    periodic: tuple = (False, False, False)  # per axis
     name: str = ""
     meta: dict = field(default_factory=dict)
 
@@ -159,9 +160,10 @@ def learned_k3_64(N: int = 64, k: int = 3, log_sigma: float = 1.0) -> Problem:
 
 
 def random_problem(seed: int, ncell=(3, 2, 2), k: int = 2, b: str = "sine",
-                   kappa: bool = True, c: float | None = None) -> Problem:
-    """Small random problem: nonuniform tensor grid, random SPD K, random
-    per-cell kappa, b constant or sine-cyclic, random c."""
+                   kappa: bool = True, c: float | None = None, periodic=(False, False, False)) -> Problem:
+    """Small random problem: nonuniform tensor grid on [0,1]^3, random SPD K,
+    random per-cell kappa, b constant or sine-cyclic, random c; optional
+    periodic axes (b takes the same value at both ends of every axis)."""
     rng = np.random.default_rng(seed)
     nodes = tuple(random_nodes(ncell[a], rng) for a in range(3))
     K = random_spd(rng)
@@ -175,7 +177,7 @@ def random_problem(seed: int, ncell=(3, 2, 2), k: int = 2, b: str = "sine",
         bk = dict(b_const=(0.0, 0.0, 0.0), b_sin=(0.0, 0.0, 0.0), b_axis=(0, 1, 2))
     cc = float(rng.uniform(0.1, 2.0)) if c is None else float(c)
     return Problem(ncell=tuple(ncell), nodes=nodes, k=k, K=K, kappa=kap, c=cc,
-                   sigma=paper_sigma(k), name=f"random_{seed}", **bk)
+                   sigma=paper_sigma(k), periodic=tuple(bool(v) for v in periodic), name=f"random_{seed}", **bk)
 
 
 def random_vector(n: int, seed: int, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:

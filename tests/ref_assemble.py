@@ -113,13 +113,16 @@ def assemble_dense(prob) -> np.ndarray:
         pts[a] = np.array([xa])
         return np.stack(np.meshgrid(*pts, indexing="ij"), axis=-1).transpose(2, 1, 0, 3).reshape(-1, 3)
 
+    per = getattr(prob, "periodic", (False, False, False))
     for i in cells:
         for a in range(3):
             o, h = geom(i)
             c = cid(i)
-            if i[a] + 1 < N[a]:
+            if i[a] + 1 < N[a] or per[a]:
+                # on a periodic axis the last cell's upper face meets the first
+                # cell, whose lower node carries the face's velocity
                 ip = list(i)
-                ip[a] += 1
+                ip[a] = (i[a] + 1) % N[a]
                 op, hp = geom(ip)
                 cp = cid(ip)
                 W = face_weights(a, h)
@@ -147,7 +150,7 @@ def assemble_dense(prob) -> np.ndarray:
                         A[blk(cv), blk(cu)] += M
             for e in (0, 1):
                 at_bnd = (i[a] == 0) if e == 0 else (i[a] == N[a] - 1)
-                if not at_bnd:
+                if not at_bnd or per[a]:
                     continue
                 W = face_weights(a, h)
                 X = face_points(a, o, h, o[a] + (h[a] if e == 1 else 0.0))

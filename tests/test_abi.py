@@ -66,7 +66,7 @@ def _struct(prob, **over):
     (dict(K=np.array([[1, 0.5, 0], [0, 1, 0], [0, 0, 1.0]])), "symmetric"),
     (dict(b_axis0=3), "b_axis"),
     (dict(c=float("nan")), "c must be finite"),
-    (dict(flags=8), "unknown flag"),
+    (dict(flags=32), "unknown flag"),
     (dict(k=8, flags=2), "block Jacobi supports"),
 ])
 def test_setup_rejects_invalid_problems(over, msg):
@@ -76,6 +76,18 @@ def test_setup_rejects_invalid_problems(over, msg):
     rc = lib.dg_setup(ctypes.byref(s), ctypes.byref(h))
     assert rc == binding.DG_EINVAL
     assert msg in lib.dg_last_error().decode()
+    assert not h.value
+
+
+def test_block_jacobi_rejects_an_odd_periodic_axis():
+    """Two-colour probing needs the first and last cells of a periodic axis
+    to differ in parity: an odd periodic axis (> 1 cell) is rejected before
+    any device work."""
+    lib = _lib()
+    s, keep = _struct(workloads.random_problem(60, ncell=(3, 2, 2), k=1), flags=2 | 4)
+    h = ctypes.c_void_p()
+    assert lib.dg_setup(ctypes.byref(s), ctypes.byref(h)) == binding.DG_EINVAL
+    assert "even number of cells" in lib.dg_last_error().decode()
     assert not h.value
 
 

@@ -141,3 +141,34 @@ def test_solver_workloads_full_size_sampled_rows(name):
     y = _gpu_apply(p, x, 0).reshape(p.ncells, -1)
     cells = _sampled_cells(p, 61)
     _check(y[cells], oracle.apply_rows(p, x, cells), f"{name} sampled")
+
+
+PERIODIC = [(True, False, False), (False, True, False), (False, False, True), (True, True, True)]
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("k", range(1, 11))
+def test_periodic_axes_every_degree(variant, k):
+    """Periodic axes (first and last cells are face neighbours): odd, even and
+    single-cell periodic axes across the degrees, both kernels."""
+    ncell = [(3, 2, 4), (1, 3, 2), (4, 1, 3)][k % 3] if k <= 6 else [(3, 2, 2), (2, 1, 3)][k % 2]
+    per = PERIODIC[k % 4]
+    p = W.random_problem(700 + k, ncell=ncell, k=k, b="sine" if k % 2 else "const", periodic=per)
+    x = W.random_vector(p.ndof, 710 + k)
+    _check(_gpu_apply(p, x, variant), oracle.apply(p, x), f"periodic {per} k={k} {ncell} v{variant}")
+
+
+@pytest.mark.parametrize("k", [2, 5, 7])
+def test_periodic_fp32_operator_matches_fp64(k):
+    """FP32 operator on a fully periodic mesh against the FP64 oracle, with the
+    error bar of the FP32 tier (traces and contractions rounded to FP32)."""
+    torch = _torch()
+    from paper_1711_10885_amd import binding
+    p = W.random_problem(720 + k, ncell=(3, 2, 3), k=k, b="sine", periodic=(True, True, True))
+    x = W.random_vector(p.ndof, 730 + k)
+    ref = oracle.apply(p, x)
+    with binding.DG(p) as dg:
+        y = dg.apply_f32(torch.from_numpy(x).float().cuda()).double().cpu().numpy()
+    e = np.abs(y - ref).max() / np.abs(ref).max()
+    print(f"periodic fp32 k={k}: relmax {e:.2e}", flush=True)
+    assert e <= 30 * (k + 1) * 2.0 ** -24
