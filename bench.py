@@ -16,7 +16,10 @@ By default the run also times the solves (the second half of the metric):
 plain FP64 GMRES(30) against GMRES-IR to 1e-8 on the 48^3 k=5 workload, and
 plain FP64 GMRES(60) and block-Jacobi FGMRES(60) against the learned
 preconditioner to 1e-8 on the 64^3 k=3 workload (--solves none skips them;
-the degree-sweep workloads skip them unless asked).
+the degree-sweep workloads skip them unless asked).  It also times explicit
+Heun time stepping on the periodic 64^3 k=5 transport workload (one fused
+operator-plus-stage launch per Runge-Kutta stage; --timestepping none skips
+it).
 
 Prints ONE JSON line.  Algorithmic FLOPs use the per-DOF lower bound of
 Sec. 3.6 (FLOPDOF_vol + FLOPDOF_face for d = 3); peak is the MI355X FP64
@@ -203,6 +206,58 @@ def solves_learned(maxit: int, restart: int):
     dg.close()
     return out
 
+def timestepping(nsteps: int, warmup: int = 10):
+    """Heun (SSP-RK2) on the transport workload: 64^3 periodic cubes, k = 5
+    (56.6M DOF), K = 5e-6 I, c = 0, f = 0, b = (sin pi y, sin pi z, sin pi x),
+    dt = 1.5e-4; initial coefficients the L2 projection of sin(pi x) sin(pi y)
+    sin(pi z) (load vector over |T|, |T| = N^-3 on the uniform mesh).  Each
+    stage is one launch of the operator kernel writing the stage value; the
+    same workload's plain apply is timed beside it."""
+    import numpy as np
+    import torch
+    from paper_1711_10885_amd import binding, workloads as W
+    p = W.transport_k5_64()
+    nb = (p.k + 1) ** 3
+    dt = p.meta["dt"]
+    stream = torch.cuda.current_stream()
+    dg = binding.DG(p)
+    u = dg.load_vector(W.transport_initial(), stream=stream)
+    u.mul_(float(p.ncells))
+    dg.heun(u, dt, warmup, stream=stream)  # allocates the stage workspace
+    torch.cuda.synchronize()
+    mass0, umax0 = float(u[::nb].sum()), float(u.abs().max())
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record(stream)
+    dg.heun(u, dt, nsteps, stream=stream)
+    e.record(stream)
+    torch.cuda.synchronize()
+    ms_step = s.elapsed_time(e) / nsteps
+    mass1, umax1 = float(u[::nb].sum()), float(u.abs().max())
+    y = torch.empty_like(u)
+    for _ in range(3):
+        dg.apply(u, y, stream)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(10)]
+    for a, b in ev:
+        a.record(stream)
+        dg.apply(u, y, stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    apply_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    dg.close()
+    del u, y
+    torch.cuda.empty_cache()
+    tflops = 2 * flop_per_dof(p.k) * p.ndof / (ms_step * 1e-3) / 1e12
+    return {"workload": f"{p.name}: periodic transport, Heun, k={p.k}, {p.ncell[0]}^3 cells, {p.ndof} DOF, "
+                        f"K=5e-6 I, c=0, f=0, FP64",
+            "dt": dt, "steps": nsteps, "warmup_steps": warmup, "ms_per_step": ms_step,
+            "gdof_steps_per_s": p.ndof / (ms_step * 1e-3) / 1e9,
+            "stage_launch_ms": ms_step / 2, "apply_ms": apply_ms,
+            "step_over_two_applies": ms_step / (2 * apply_ms),
+            "fp64_tflops": tflops, "frac_fp64_peak": tflops / FP64_PEAK_TFLOPS,
+            "stage_algorithmic_bytes_per_dof": 20.0,
+            "mass_rel_drift": abs(mass1 - mass0) / abs(mass0), "max_abs_u": [umax0, umax1]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -221,11 +276,17 @@ def main():
                     help="FGMRES-step cap of the learned-preconditioner comparison")
     ap.add_argument("--learned-restart", type=int, default=60,
                     help="FGMRES restart length of the learned-preconditioner comparison (both sides)")
+    ap.add_argument("--timestepping", default=None, choices=["none", "transport"],
+                    help="also time Heun steps on the periodic transport workload "
+                         "(default: on for the headline workload)")
+    ap.add_argument("--ts-steps", type=int, default=400, help="timed Heun steps")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.solves is None:
         args.solves = "all" if args.workload == "cdr_k7_32" else "none"
+    if args.timestepping is None:
+        args.timestepping = "transport" if args.workload == "cdr_k7_32" else "none"
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -279,6 +340,7 @@ def main():
     dg.close()
     del x, y
     torch.cuda.empty_cache()
+    ts = timestepping(args.ts_steps) if args.timestepping == "transport" else None
     solves = {}
     if args.solves in ("mixed", "all"):
         solves["mixed_precision"] = solves_mixed(args.solve_maxit)
@@ -307,6 +369,8 @@ def main():
                      "algorithmic_bytes": 16 * prob.ndof, "avg_kernel_ms": avg_kernel_ms},
         "cpu_baseline": cpu,
     }
+    if ts:
+        out["timestepping"] = ts
     if solves:
         out["solves"] = solves
     print(json.dumps(out), flush=True)

@@ -308,6 +308,22 @@ dg_status dg_mlp_grad(dg_handle *h, const float *X, const float *T, int32_t B, f
 dg_status dg_mlp_step(dg_handle *h, const float *X, const float *T, int32_t B, float lr, double *loss,
                       void *hip_stream);
 
+/* ---------------------------------------------------------------------------
+ * Explicit time stepping.  The semi-discrete system M du/dt + A u = f of
+ * Sec. 2.2 (eq. (ODE_system)) with the diagonal mass matrix of the
+ * orthonormal basis (M = |T| I on cell T), advanced by the two-stage
+ * strong-stability-preserving Runge-Kutta method (Heun) of the paper's
+ * transport example (Sec. 5.4):
+ *   u1 = u + dt M^{-1} (f - A u),   u <- (u + u1 + dt M^{-1} (f - A u1)) / 2.
+ * u: device, ndof doubles, advanced in place by nsteps steps of size dt.
+ * f: device, ndof doubles (a load vector, constant in time; must not
+ * overlap u) or NULL for f = 0.  Workspace of 2 ndof doubles is allocated
+ * on first use and kept by the handle.  Asynchronous on hip_stream.
+ * Returns DG_EINVAL (NULL u, dt not positive and finite, nsteps < 0,
+ * overlapping u and f), DG_ENOMEM, DG_EHIP.
+ * ------------------------------------------------------------------------- */
+dg_status dg_heun(dg_handle *h, double *u, const double *f, double dt, int32_t nsteps, void *hip_stream);
+
 /* Number of degrees of freedom of the handle's space (or -1 for NULL). */
 int64_t dg_ndof(const dg_handle *h);
 

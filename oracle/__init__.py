@@ -18,6 +18,10 @@ Contents
 * ``assemble`` -- the sparse matrix of the operator by probing ``apply`` with
   coloured unit vectors (the DG coupling is face-local, Sec. 2.2).
 * ``block_diagonal`` -- the per-cell diagonal blocks A_TT of the same operator.
+* ``cell_volumes`` / ``heun`` / ``heun_step_rows`` -- explicit Heun time
+  stepping of M du/dt + A u = f (Sec. 2.2, Sec. 5.4) with the diagonal mass
+  matrix of the orthonormal basis; the last evaluates one step on listed
+  cells only (for checks on meshes too large to step whole).
 * ``gmres`` -- restarted, right-preconditioned GMRES in float64 (numpy).
 """
 from __future__ import annotations
@@ -212,32 +216,50 @@ def basis(k: int, t: float):
     return v, d
 
 
-def _cell_colour3(prob):
-    """Colour of each cell under i_a mod 3 in every direction (27 colours):
-    cells of one colour share no face neighbour, so probing one colour at a
-    time separates the columns of every face-coupled pair."""
+def _cell_colours(prob):
+    """Colour of each cell, per axis i_a mod C_a with C_a = 3 (or, on a
+    periodic axis whose length is not a multiple of 3, C_a = ncell[a]): cells
+    of one colour are at least three cells apart along every axis, also
+    across a periodic boundary, so probing one colour at a time separates
+    the columns of every face-coupled pair."""
+    per = getattr(prob, "periodic", (False, False, False))
+    C = [prob.ncell[a] if per[a] and prob.ncell[a] % 3 else 3 for a in range(3)]
     N1, N2, N3 = prob.ncell
     i1, i2, i3 = np.meshgrid(np.arange(N1), np.arange(N2), np.arange(N3), indexing="ij")
-    col = (i1 % 3) + 3 * (i2 % 3) + 9 * (i3 % 3)
-    return col.transpose(2, 1, 0).ravel()  # cell id order: axis 1 fastest
+    col = (i1 % C[0]) + C[0] * ((i2 % C[1]) + C[1] * (i3 % C[2]))
+    return col.transpose(2, 1, 0).ravel(), C[0] * C[1] * C[2]  # cell id order: axis 1 fastest
 
 
 def assemble(prob, terms: int = ALL_TERMS, nthreads: int | None = None):
     """Sparse matrix of the operator, column by column from ``apply``.
 
-    Column (T, j) of A is supported on T and its face neighbours.  All cells of
-    one i mod 3 colour are probed with e_j at once; the rows of each probed
-    cell's 3x3x3 neighbourhood are then attributed to it unambiguously."""
+    Column (T, j) of A is supported on T and its face neighbours (across a
+    periodic boundary too).  All cells of one colour are probed with e_j at
+    once; the rows of each probed cell's neighbourhood are then attributed to
+    it unambiguously (each distinct neighbour once)."""
     import scipy.sparse as sp
 
     nb = (prob.k + 1) ** 3
     N1, N2, N3 = prob.ncell
+    Nv = np.array([N1, N2, N3])
+    per = np.array(getattr(prob, "periodic", (False, False, False)), dtype=bool)
     ncells = N1 * N2 * N3
-    col = _cell_colour3(prob)
+    col, ncol = _cell_colours(prob)
     cid = np.arange(ncells)
     ci = np.stack([cid % N1, (cid // N1) % N2, cid // (N1 * N2)], axis=1)
+    # distinct cells of each cell's neighbourhood (itself and its face neighbours)
+    offs = ((0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1))
+    hood = []
+    for c in range(ncells):
+        cells = set()
+        for d in offs:
+            q = ci[c] + np.array(d)
+            q = np.where(per, q % Nv, q)
+            if np.all((q >= 0) & (q < Nv)):
+                cells.add(int(q[0] + N1 * (q[1] + N2 * q[2])))
+        hood.append(sorted(cells))
     rows_all, cols_all, vals_all = [], [], []
-    for colour in range(27):
+    for colour in range(ncol):
         probed = np.nonzero(col == colour)[0]
         if probed.size == 0:
             continue
@@ -245,25 +267,93 @@ def assemble(prob, terms: int = ALL_TERMS, nthreads: int | None = None):
             x = np.zeros(ncells * nb)
             x[probed * nb + j] = 1.0
             y = apply(prob, x, terms, nthreads).reshape(ncells, nb)
-            # each row cell R takes its value from the probed cell in its
-            # neighbourhood (at most one per colour, by construction)
-            for d in ((0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1),
-                      (0, 0, -1)):
-                nbr = ci[probed] + np.array(d)
-                ok = np.all((nbr >= 0) & (nbr < np.array([N1, N2, N3])), axis=1)
-                src = probed[ok]
-                dst = nbr[ok, 0] + N1 * (nbr[ok, 1] + N2 * nbr[ok, 2])
-                blk = y[dst]  # (len, nb)
-                r = (dst[:, None] * nb + np.arange(nb)[None, :]).ravel()
-                c = np.repeat(src * nb + j, nb)
-                v = blk.ravel()
-                nz = v != 0.0
-                rows_all.append(r[nz])
-                cols_all.append(c[nz])
-                vals_all.append(v[nz])
+            src = np.concatenate([np.full(len(hood[c]), c) for c in probed])
+            dst = np.concatenate([np.array(hood[c], dtype=np.int64) for c in probed])
+            blk = y[dst]  # (len, nb)
+            r = (dst[:, None] * nb + np.arange(nb)[None, :]).ravel()
+            c = np.repeat(src * nb + j, nb)
+            v = blk.ravel()
+            nz = v != 0.0
+            rows_all.append(r[nz])
+            cols_all.append(c[nz])
+            vals_all.append(v[nz])
     n = ncells * nb
     return sp.csr_matrix((np.concatenate(vals_all), (np.concatenate(rows_all),
                                                      np.concatenate(cols_all))), shape=(n, n))
+
+
+def cell_volumes(prob) -> np.ndarray:
+    """|T| per cell (cell order: axis 1 fastest)."""
+    h = [np.diff(np.asarray(prob.nodes[a], dtype=np.float64)) for a in range(3)]
+    return np.einsum("k,j,i->kji", h[2], h[1], h[0]).ravel()
+
+
+def heun(prob, u0: np.ndarray, dt: float, nsteps: int, f: np.ndarray | None = None,
+         nthreads: int | None = None) -> np.ndarray:
+    """Explicit two-stage strong-stability-preserving Runge-Kutta (Heun) for
+    the semi-discrete system M du/dt + A u = f of Sec. 2.2 (eq.
+    (ODE_system)), the time stepping of the paper's transport example
+    (Sec. 5.4).  The orthonormal basis gives M = |T| I on cell T:
+        k1 = M^{-1} (f - A u),  u1 = u + dt k1,
+        k2 = M^{-1} (f - A u1), u  <- u + dt (k1 + k2) / 2."""
+    nb = (prob.k + 1) ** 3
+    minv = np.repeat(1.0 / cell_volumes(prob), nb)
+    rhs = 0.0 if f is None else np.asarray(f, dtype=np.float64)
+    u = np.array(u0, dtype=np.float64, copy=True)
+    for _ in range(nsteps):
+        k1 = minv * (rhs - apply(prob, u, ALL_TERMS, nthreads))
+        u1 = u + dt * k1
+        k2 = minv * (rhs - apply(prob, u1, ALL_TERMS, nthreads))
+        u = u + 0.5 * dt * (k1 + k2)
+    return u
+
+
+def face_neighbours(prob, cell: int) -> list:
+    """Cells sharing a face with ``cell`` (periodic axes wrap; a cell that
+    would be its own neighbour, one cell along a periodic axis, is left out)."""
+    n = [int(v) for v in prob.ncell]
+    i = [cell % n[0], (cell // n[0]) % n[1], cell // (n[0] * n[1])]
+    per = tuple(getattr(prob, "periodic", (False, False, False)))
+    out = set()
+    for a in range(3):
+        for d in (-1, 1):
+            j = list(i)
+            j[a] += d
+            if not 0 <= j[a] < n[a]:
+                if not per[a]:
+                    continue
+                j[a] %= n[a]
+            c = j[0] + n[0] * (j[1] + n[1] * j[2])
+            if c != cell:
+                out.add(c)
+    return sorted(out)
+
+
+def heun_step_rows(prob, u: np.ndarray, dt: float, cells, f: np.ndarray | None = None,
+                   nthreads: int | None = None) -> np.ndarray:
+    """One step of ``heun`` evaluated on the listed cells only; shape
+    (len(cells), n^3).  A u1 on a cell reads u1 on that cell and its face
+    neighbours (the operator couples face neighbours only, Sec. 2.2), and u1
+    there needs A u on the same cells, so the step is exact from rows of A
+    on the listed cells and their neighbours."""
+    nb = (prob.k + 1) ** 3
+    vol = cell_volumes(prob)
+    cells = [int(c) for c in cells]
+    near = sorted(set(cells).union(*[face_neighbours(prob, c) for c in cells]))
+    u = np.asarray(u, dtype=np.float64)
+    rows = lambda v, c: (0.0 if v is None else v[c * nb:(c + 1) * nb])
+    Au = apply_rows(prob, u, near, ALL_TERMS, nthreads)
+    u1 = np.zeros_like(u)
+    k1 = {}
+    for r, c in enumerate(near):
+        k1[c] = (rows(f, c) - Au[r]) / vol[c]
+        u1[c * nb:(c + 1) * nb] = u[c * nb:(c + 1) * nb] + dt * k1[c]
+    Au1 = apply_rows(prob, u1, cells, ALL_TERMS, nthreads)
+    out = np.empty((len(cells), nb))
+    for r, c in enumerate(cells):
+        k2 = (rows(f, c) - Au1[r]) / vol[c]
+        out[r] = u[c * nb:(c + 1) * nb] + 0.5 * dt * (k1[c] + k2)
+    return out
 
 
 def block_diagonal(prob, nthreads: int | None = None) -> np.ndarray:

@@ -28,7 +28,7 @@ _STATUS = {DG_EINVAL: "DG_EINVAL", DG_ENOMEM: "DG_ENOMEM", DG_EHIP: "DG_EHIP",
 # every symbol include/dg.h declares
 EXPORTS = ["dg_setup", "dg_apply", "dg_apply_f32", "dg_load_vector", "dg_set_kernel", "dg_solve", "dg_precond_apply",
            "dg_learned_train", "dg_learned_nparams", "dg_learned_set_params", "dg_learned_get_params",
-           "dg_mlp_forward", "dg_mlp_grad", "dg_mlp_step", "dg_ndof", "dg_degree", "dg_bj_nblocks",
+           "dg_mlp_forward", "dg_mlp_grad", "dg_mlp_step", "dg_heun", "dg_ndof", "dg_degree", "dg_bj_nblocks",
            "dg_last_error", "dg_destroy"]
 
 
@@ -104,6 +104,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dg_load_vector.argtypes = [H, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_int32), vp, vp]
     lib.dg_load_vector.restype = ctypes.c_int
+    lib.dg_heun.argtypes = [H, vp, vp, ctypes.c_double, ctypes.c_int32, vp]
+    lib.dg_heun.restype = ctypes.c_int
     lib.dg_apply_f32.argtypes = [H, vp, vp, vp]
     lib.dg_apply_f32.restype = ctypes.c_int
     lib.dg_set_kernel.argtypes = [H, ctypes.c_int32]
@@ -258,6 +260,19 @@ class DG:
         _check(load().dg_apply_f32(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
                                    _stream_ptr(stream)))
         return y
+
+    def heun(self, u, dt: float, nsteps: int, f=None, stream=None):
+        """Advance u (float64 device tensor, in place) by nsteps Heun steps of
+        M du/dt + A u = f (f = 0 if None); returns u."""
+        import torch
+        _check_vec(u, self.ndof, torch.float64, "u")
+        fp = ctypes.c_void_p()
+        if f is not None:
+            _check_vec(f, self.ndof, torch.float64, "f")
+            fp = ctypes.c_void_p(f.data_ptr())
+        _check(load().dg_heun(self._h, ctypes.c_void_p(u.data_ptr()), fp, float(dt), int(nsteps),
+                              _stream_ptr(stream)))
+        return u
 
     def bj_nblocks(self) -> int:
         """Inverse cell blocks stored by block Jacobi (ncells, or fewer when shared)."""

@@ -82,7 +82,32 @@ struct FMesh {
   int tz;          // depth (cells along axis 3) of the tiles of the cell order
   int ncells;
   int groups;      // workgroups per XCD slot (grid = 8 * groups)
+  // Heun stage written in place of y = A x by the HEUN instantiations:
+  //   stage 0: y = x + dt/|T| (f - A x)
+  //   stage 1: y = (y + x + dt/|T| (f - A x)) / 2   (y holds the old u)
+  const double *ts_f;  // load vector f, or nullptr for f = 0
+  double ts_dt;
+  int ts_stage;
 };
+
+// The stage update of n consecutive outputs y[off..off+n) of one cell, from
+// their values Av of A x.  |T| is the product of the cell's three spacings.
+template <int n, typename T>
+__device__ __forceinline__ void heun_store(const FMesh &M, int cell, size_t off, const T *__restrict__ x,
+                                           T *__restrict__ y, const T *Av) {
+  const int i0 = cell % M.ncell[0];
+  const int i1 = (cell / M.ncell[0]) % M.ncell[1];
+  const int i2 = cell / (M.ncell[0] * M.ncell[1]);
+  const double dv = M.ts_dt / (M.h[0][i0] * M.h[1][i1] * M.h[2][i2]);
+#pragma unroll
+  for (int t = 0; t < n; ++t) {
+    const double r = (M.ts_f ? M.ts_f[off + t] : 0.0) - double(Av[t]);
+    if (M.ts_stage == 0)
+      y[off + t] = T(fma(dv, r, double(x[off + t])));
+    else
+      y[off + t] = T(0.5 * (double(y[off + t]) + double(x[off + t]) + dv * r));
+  }
+}
 
 // Pencil storage for the exchanges that dominate LDS size.  For N = 2, 4, 8 the
 // pencils are unpadded and element t of pencil p is rotated by (p N)/16
@@ -364,7 +389,7 @@ __device__ __forceinline__ int cell_of_logical(int L, const FMesh &M) {
   return i1 + N1 * (i2 + N2 * i3);
 }
 
-template <int N, typename T>
+template <int N, typename T, bool HEUN>
 __global__ __launch_bounds__(FCfg<N>::THREADS)
 __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_kernel(
     const T *__restrict__ x, T *__restrict__ y, FMesh M) {
@@ -1021,9 +1046,13 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
     const T rv0 = R[X4_OFF + 0 * NN + p], rd0 = R[X4_OFF + 1 * NN + p];
     const T rv1 = R[X4_OFF + 2 * NN + p], rd1 = R[X4_OFF + 3 * NN + p];
     tr_acc<N>(tb + TO::E1, tb + TO::F1, rv1, rv0, rd1, rd0, Yv);
-    T *yp = y + size_t(cell) * NNN + NN * beta + N * alpha;
+    const size_t off = size_t(cell) * NNN + NN * beta + N * alpha;
+    if (HEUN) {
+      heun_store<N>(M, cell, off, x, y, Yv);
+    } else {
 #pragma unroll
-    for (int t = 0; t < N; ++t) yp[t] = Yv[t];
+      for (int t = 0; t < N; ++t) y[off + t] = Yv[t];
+    }
   }
 }
 
@@ -1058,7 +1087,7 @@ struct LaneTab {
   static __device__ __forceinline__ double W(int q) { return GLTab<N>::v[TabOff<N>::W + (q < H ? q : N - 1 - q)]; }
 };
 
-template <int N, typename T>
+template <int N, typename T, bool HEUN>
 __global__ __launch_bounds__(256) void apply_lane_kernel(const T *__restrict__ x, T *__restrict__ y, FMesh M) {
   constexpr int NN = N * N, NNN = N * N * N;
   using TB = LaneTab<N, T>;
@@ -1243,13 +1272,18 @@ __global__ __launch_bounds__(256) void apply_lane_kernel(const T *__restrict__ x
 #pragma unroll
     for (int j = 0; j < NNN; ++j) asm volatile("" : "+v"(Y[j]));
   }
-  T *yp = y + size_t(cell) * NNN;
+  if (HEUN) {
+    heun_store<NNN>(M, cell, size_t(cell) * NNN, x, y, Y);
+  } else {
+    T *yp = y + size_t(cell) * NNN;
 #pragma unroll
-  for (int j = 0; j < NNN; ++j) yp[j] = Y[j];
+    for (int j = 0; j < NNN; ++j) yp[j] = Y[j];
+  }
 }
 
-template <int N, typename T>
-static hipError_t launch_fused_n(const dg_handle *h, const T *x, T *y, hipStream_t s) {
+template <int N, typename T, bool HEUN>
+static hipError_t launch_fused_n(const dg_handle *h, const T *x, T *y, hipStream_t s, const double *f = nullptr,
+                                 double dt = 0.0, int stage = 0) {
   using C = FCfg<N>;
   FMesh M;
   for (int a = 0; a < 3; ++a) {
@@ -1269,42 +1303,51 @@ static hipError_t launch_fused_n(const dg_handle *h, const T *x, T *y, hipStream
   // tiles of up to 4 cells along axis 3: z neighbours are adjacent in the
   // processing order, y neighbours 4*N1 cells apart
   M.tz = h->mesh.ncell[2] < 4 ? h->mesh.ncell[2] : 4;
+  M.ts_f = f;
+  M.ts_dt = dt;
+  M.ts_stage = stage;
   if (N == 2) {  // k = 1: one cell per lane
     const int nblocks = int((h->ncells + 255) / 256);
     M.groups = (nblocks + 7) / 8;
-    hipLaunchKernelGGL((apply_lane_kernel<2, T>), dim3(unsigned(8 * M.groups)), dim3(256), 0, s, x, y, M);
+    hipLaunchKernelGGL((apply_lane_kernel<2, T, HEUN>), dim3(unsigned(8 * M.groups)), dim3(256), 0, s, x, y, M);
     return hipGetLastError();
   }
   const int nblocks = int((h->ncells + C::CPB - 1) / C::CPB);
   M.groups = (nblocks + 7) / 8;
-  hipLaunchKernelGGL((apply_fused_kernel<N, T>), dim3(unsigned(8 * M.groups)), dim3(C::THREADS), 0, s,
+  hipLaunchKernelGGL((apply_fused_kernel<N, T, HEUN>), dim3(unsigned(8 * M.groups)), dim3(C::THREADS), 0, s,
                      x, y, M);
   return hipGetLastError();
 }
 
-template <typename T>
-static hipError_t launch_fused(const dg_handle *h, const T *x, T *y, hipStream_t s) {
+template <typename T, bool HEUN>
+static hipError_t launch_fused(const dg_handle *h, const T *x, T *y, hipStream_t s, const double *f = nullptr,
+                               double dt = 0.0, int stage = 0) {
   switch (h->k + 1) {
-    case 2: return launch_fused_n<2>(h, x, y, s);
-    case 3: return launch_fused_n<3>(h, x, y, s);
-    case 4: return launch_fused_n<4>(h, x, y, s);
-    case 5: return launch_fused_n<5>(h, x, y, s);
-    case 6: return launch_fused_n<6>(h, x, y, s);
-    case 7: return launch_fused_n<7>(h, x, y, s);
-    case 8: return launch_fused_n<8>(h, x, y, s);
-    case 9: return launch_fused_n<9>(h, x, y, s);
-    case 10: return launch_fused_n<10>(h, x, y, s);
-    case 11: return launch_fused_n<11>(h, x, y, s);
+    case 2: return launch_fused_n<2, T, HEUN>(h, x, y, s, f, dt, stage);
+    case 3: return launch_fused_n<3, T, HEUN>(h, x, y, s, f, dt, stage);
+    case 4: return launch_fused_n<4, T, HEUN>(h, x, y, s, f, dt, stage);
+    case 5: return launch_fused_n<5, T, HEUN>(h, x, y, s, f, dt, stage);
+    case 6: return launch_fused_n<6, T, HEUN>(h, x, y, s, f, dt, stage);
+    case 7: return launch_fused_n<7, T, HEUN>(h, x, y, s, f, dt, stage);
+    case 8: return launch_fused_n<8, T, HEUN>(h, x, y, s, f, dt, stage);
+    case 9: return launch_fused_n<9, T, HEUN>(h, x, y, s, f, dt, stage);
+    case 10: return launch_fused_n<10, T, HEUN>(h, x, y, s, f, dt, stage);
+    case 11: return launch_fused_n<11, T, HEUN>(h, x, y, s, f, dt, stage);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_apply_fused_f64(const dg_handle *h, const double *x, double *y, hipStream_t s) {
-  return launch_fused<double>(h, x, y, s);
+  return launch_fused<double, false>(h, x, y, s);
+}
+
+hipError_t launch_heun_fused_f64(const dg_handle *h, const double *x, double *y, const double *f, double dt,
+                                 int stage, hipStream_t s) {
+  return launch_fused<double, true>(h, x, y, s, f, dt, stage);
 }
 
 hipError_t launch_apply_fused_f32(const dg_handle *h, const float *x, float *y, hipStream_t s) {
-  return launch_fused<float>(h, x, y, s);
+  return launch_fused<float, false>(h, x, y, s);
 }
 
 }  // namespace dgmf

@@ -149,6 +149,7 @@ extern "C" void dg_destroy(dg_handle *h) {
   if (h->bj16_scale) (void)hipFree(h->bj16_scale);
   if (h->bj_cells) (void)hipFree(h->bj_cells);
   if (h->bj_gblock) (void)hipFree(h->bj_gblock);
+  if (h->ts) (void)hipFree(h->ts);
   if (h->dev_block) (void)hipFree(h->dev_block);
   if (cur != h->device) (void)hipSetDevice(cur);
   delete h;
@@ -205,6 +206,7 @@ extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
   h->dev_block = nullptr;
   h->variant = DG_KERNEL_AUTO;
   h->ws = nullptr;
+  h->ts = nullptr;
   h->ws_bytes = 0;
   h->red = nullptr;
   h->bj = nullptr;

@@ -59,6 +59,7 @@ struct dg_handle {
   void *ws;
   size_t ws_bytes;
   double *red;      // reduction partials + small device vectors of the Krylov kernels
+  double *ts;       // time-stepping workspace: 2 ndof doubles (or null)
   // block Jacobi: inverse cell blocks, FP32, column-major per cell (or null)
   float *bj;
   _Float16 *bj16;      // the same blocks in FP16, scaled per cell (inner FP32 solves)
@@ -83,6 +84,10 @@ dg_status hip_error(hipError_t e, const char *what);
 hipError_t launch_apply_ref_f64(const dg_handle *h, const double *x, double *y, hipStream_t s);
 hipError_t launch_apply_fused_f64(const dg_handle *h, const double *x, double *y, hipStream_t s);
 hipError_t launch_apply_fused_f32(const dg_handle *h, const float *x, float *y, hipStream_t s);
+// One Heun stage fused into the apply's store: stage 0 y = x + dt/|T| (f - A x),
+// stage 1 y = (y + x + dt/|T| (f - A x)) / 2; f may be nullptr (f = 0).
+hipError_t launch_heun_fused_f64(const dg_handle *h, const double *x, double *y, const double *f, double dt,
+                                 int stage, hipStream_t s);
 
 // Operator application through the kernel the handle selects.
 hipError_t apply_f64(const dg_handle *h, const double *x, double *y, hipStream_t s);

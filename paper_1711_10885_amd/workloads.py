@@ -22,6 +22,12 @@ the paper's model problem, Sec. 2.1, and Problem A of Sec. 5.1):
 * ``learned_k3_64``  k = 3, 64^3, kappa_T = exp(g(center_T)), g a seeded smooth
   random field (random Fourier features, M = 128, length scale 0.1, seed 5),
   b = (1, .5, .25), c = 0.1, sigma = 2k(k+2), f = 1.
+* ``transport_k5_64`` k = 5, 64^3 uniform cubes, periodic on every axis,
+  K = 5e-6 I, c = 0, f = 0 (the coefficients of the transport example of
+  Sec. 5.4), b = (sin pi y, sin pi z, sin pi x) (divergence free and
+  continuous across the periodic wrap), sigma = 2k(k+2); initial
+  concentration the projection of sin(pi x) sin(pi y) sin(pi z); time step
+  dt = 1.5e-4 (64 / N).
 """
 from __future__ import annotations
 
@@ -196,6 +202,21 @@ def workload_vector(prob: Problem) -> np.ndarray:
 # 2 = cos(pi .).
 # ---------------------------------------------------------------------------
 SIN, COS, ONE = 1, 2, 0
+
+
+def transport_k5_64(N: int = 64, k: int = 5) -> Problem:
+    """Periodic convection-dominated transport at one GPU's share of the
+    Sec. 5.4 example.  The time step keeps dt rho(M^{-1} A) near 0.8 (rho is
+    about 83 / h for this operator at k = 5), inside the real-axis stability
+    interval [-2, 0] of Heun's method."""
+    return Problem(ncell=(N, N, N), nodes=(uniform_nodes(N),) * 3, k=k, K=5e-6 * np.eye(3), c=0.0,
+                   sigma=paper_sigma(k), periodic=(True, True, True), name=f"transport_k{k}_{N}",
+                   meta={"dt": 1.5e-4 * 64.0 / N}, **SINE_CYCLIC)
+
+
+def transport_initial():
+    """Initial concentration sin(pi x) sin(pi y) sin(pi z) as source terms."""
+    return [(1.0, (SIN, SIN, SIN))]
 
 
 def manufactured_u():

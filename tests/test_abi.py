@@ -107,6 +107,8 @@ def test_null_arguments():
     assert lib.dg_setup(None, ctypes.byref(h)) == binding.DG_EINVAL
     assert lib.dg_apply(None, None, None, None) == binding.DG_EINVAL
     assert lib.dg_ndof(None) == -1
+    assert lib.dg_heun(None, None, None, 1e-3, 1, None) == binding.DG_EINVAL
+    assert "handle" in lib.dg_last_error().decode()
     lib.dg_destroy(None)
 
 
