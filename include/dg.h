@@ -67,7 +67,8 @@ typedef enum {
  *              D = kappa_T K on cell T.
  *   b          b_r(x) = b_const[r] + b_sin[r] * sin(pi * x_{b_axis[r]}),
  *              b_axis[r] in {0,1,2}.  (b = (sin pi y, sin pi z, sin pi x) is
- *              b_sin = 1, b_axis = {1,2,0}.)
+ *              b_sin = 1, b_axis = {1,2,0}.)  With DG_B_PRODUCT in flags the
+ *              product form below replaces it.
  *   c          constant reaction coefficient.
  *   sigma      penalty scale: gamma_F = sigma * <d-,d+> / min(h_a-, h_a+) on
  *              interior (and periodic) faces, sigma * d / h_a on boundary
@@ -96,6 +97,16 @@ typedef enum {
  *              faces.  b must then take the same value at both ends of a
  *              periodic axis for the scheme to be consistent (the sine part
  *              does when the axis spans an integer length).
+ *              DG_B_PRODUCT: the flow field is the product form
+ *                b_r(x) = b_amp[r] * prod_{j<3} f_rj(x_j),
+ *                f_rj(s) = sin(b_freq[3r+j] s + b_phase[3r+j]), or 1 where
+ *                b_freq[3r+j] == 0,
+ *              evaluated at the Gauss points like the other form (the
+ *              Taylor-Green field of the transport example of Sec. 5.4 is
+ *              of this form); b_const and b_sin are then unused (b_axis
+ *              must still be 0, 1 or 2).
+ *              Block Jacobi classes then key on the cell position along
+ *              every axis some factor depends on.
  */
 typedef struct {
   int32_t ncell[3];
@@ -109,12 +120,16 @@ typedef struct {
   double c;
   double sigma;
   int32_t flags;
+  double b_amp[3];    /* product-form flow field (DG_B_PRODUCT only) */
+  double b_freq[9];
+  double b_phase[9];
 } dg_problem;
 
 #define DG_WITH_BLOCK_JACOBI 2
 #define DG_PERIODIC_X 4
 #define DG_PERIODIC_Y 8
 #define DG_PERIODIC_Z 16
+#define DG_B_PRODUCT 32
 
 /* Create a handle on the current HIP device: validates the problem, builds
  * the 1D Gauss-Legendre/Legendre tables (Sec. 3.1/3.2, eq.

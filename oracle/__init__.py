@@ -64,6 +64,10 @@ class _Problem(ctypes.Structure):
         ("c", ctypes.c_double),
         ("sigma", ctypes.c_double),
         ("periodic", ctypes.c_int32 * 3),
+        ("b_product", ctypes.c_int32),
+        ("b_amp", ctypes.c_double * 3),
+        ("b_freq", ctypes.c_double * 9),
+        ("b_phase", ctypes.c_double * 9),
     ]
 
 
@@ -122,6 +126,14 @@ class _Marshalled:
         per = getattr(prob, "periodic", (False, False, False))
         for a in range(3):
             s.periodic[a] = 1 if per[a] else 0
+        amp = getattr(prob, "b_amp", None)
+        s.b_product = 0 if amp is None else 1
+        if amp is not None:
+            for r in range(3):
+                s.b_amp[r] = float(amp[r])
+            for t in range(9):
+                s.b_freq[t] = float(prob.b_freq[t])
+                s.b_phase[t] = float(prob.b_phase[t])
         self.struct = s
 
 

@@ -32,7 +32,11 @@
  *    upwind term is Phi(u,0,b_nu) (F^{DO} sum of eq. (blf)) and the boundary
  *    consistency/symmetry/penalty terms use [[v]] = {v} = v-;
  *  - D = kappa_T K with K constant SPD and kappa_T > 0 constant per cell;
- *  - b_r(x) = b_const[r] + b_sin[r] * sin(pi * x_{b_axis[r]}).
+ *  - b_r(x) = b_const[r] + b_sin[r] * sin(pi * x_{b_axis[r]}), or with
+ *    or_problem.b_product the product form
+ *    b_r(x) = b_amp[r] * prod_j sin(b_freq[3r+j] x_j + b_phase[3r+j]) (factors
+ *    with b_freq == 0 are 1), which holds the Taylor-Green field of Sec. 5.4
+ *    (eq. (2) of that section); b is evaluated at each quadrature point.
  */
 #include <math.h>
 #include <stdint.h>
@@ -56,6 +60,10 @@ typedef struct {
   double c;
   double sigma;
   int32_t periodic[3]; /* 1: axis a is periodic (first and last cells are neighbours) */
+  int32_t b_product;   /* 1: b from b_amp, b_freq, b_phase below */
+  double b_amp[3];
+  double b_freq[9];
+  double b_phase[9];
 } or_problem;
 
 /* term mask for or_apply: which sums of eq. (blf) to include */
@@ -142,6 +150,12 @@ static void make_tables(int k, or_tables *t) {
 }
 
 static double coef_b(const or_problem *p, int r, const double *xp) {
+  if (p->b_product) {
+    double v = p->b_amp[r];
+    for (int j = 0; j < 3; ++j)
+      if (p->b_freq[3 * r + j] != 0.0) v *= sin(p->b_freq[3 * r + j] * xp[j] + p->b_phase[3 * r + j]);
+    return v;
+  }
   return p->b_const[r] + p->b_sin[r] * sin(M_PI * xp[p->b_axis[r]]);
 }
 

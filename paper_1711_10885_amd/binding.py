@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libdgmf.so")
 DG_OK, DG_EINVAL, DG_ENOMEM, DG_EHIP, DG_ENOTCONV, DG_ENAN = 0, -1, -2, -3, -4, -5
 DG_WITH_BLOCK_JACOBI = 2
 DG_PERIODIC_X, DG_PERIODIC_Y, DG_PERIODIC_Z = 4, 8, 16
+DG_B_PRODUCT = 32
 DG_KERNEL_AUTO, DG_KERNEL_REFERENCE = 0, 1
 DG_GMRES64, DG_GMRES_IR, DG_FGMRES = 0, 1, 2
 DG_PREC_NONE, DG_PREC_BLOCK_JACOBI, DG_PREC_LEARNED = 0, 1, 2
@@ -51,6 +52,9 @@ class _Problem(ctypes.Structure):
         ("c", ctypes.c_double),
         ("sigma", ctypes.c_double),
         ("flags", ctypes.c_int32),
+        ("b_amp", ctypes.c_double * 3),
+        ("b_freq", ctypes.c_double * 9),
+        ("b_phase", ctypes.c_double * 9),
     ]
 
 
@@ -198,6 +202,14 @@ class DG:
         s.sigma = float(prob.sigma)
         per = getattr(prob, "periodic", (False, False, False))
         s.flags = int(flags) | sum(DG_PERIODIC_X << a for a in range(3) if per[a])
+        amp = getattr(prob, "b_amp", None)
+        if amp is not None:
+            s.flags |= DG_B_PRODUCT
+            for r in range(3):
+                s.b_amp[r] = float(amp[r])
+            for t in range(9):
+                s.b_freq[t] = float(prob.b_freq[t])
+                s.b_phase[t] = float(prob.b_phase[t])
         h = ctypes.c_void_p()
         _check(lib.dg_setup(ctypes.byref(s), ctypes.byref(h)))
         self._h = h

@@ -77,6 +77,7 @@ struct FMesh {
   int ncell[3];
   int periodic;    // bit a: axis a is periodic
   const double *h[3], *bvol[3], *bnode[3], *kappa, *w;
+  const double *bf[9], *bfn[9];  // product-form factors (BP instantiations)
   double K[9], c, sigma;
   int b_axis[3];
   int tz;          // depth (cells along axis 3) of the tiles of the cell order
@@ -358,10 +359,29 @@ __device__ __forceinline__ void face_flux(const FC &F, double uo, double un, dou
   Z = -W * J;
 }
 
+// Factor table 3 r + j of the product-form b (a select chain: no dynamic
+// indexing of the kernel-argument array).
+__device__ __forceinline__ const double *bfac(const double *const *t, int r, int j) {
+  const int i = 3 * r + j;
+  const double *p = t[0];
+#pragma unroll
+  for (int s = 1; s < 9; ++s)
+    if (i == s) p = t[s];
+  return p;
+}
+
 // b_a at a point of the face normal to a (side e) with tangential Gauss
-// indices qb, qc.
+// indices qb, qc (tangential axes b < c).
+template <bool BP>
 __device__ __forceinline__ double face_b(const FMesh &M, const FaceGeo &G, int N, int a, int e,
                                          int qb, int qc) {
+  if (BP) {
+    const int b = (a == 0) ? 1 : 0, c = (a == 2) ? 1 : 2;
+    const int ia = seli3(a, G.i0, G.i1, G.i2);
+    const bool wrap = ((M.periodic >> a) & 1) && e && ia + 1 == seli3(a, M.ncell[0], M.ncell[1], M.ncell[2]);
+    return bfac(M.bfn, a, a)[face_node(ia, e, wrap)] * bfac(M.bf, a, b)[seli3(b, G.i0, G.i1, G.i2) * N + qb] *
+           bfac(M.bf, a, c)[seli3(c, G.i0, G.i1, G.i2) * N + qc];
+  }
   const int ax = M.b_axis[a];
   const double *bv = a == 0 ? M.bvol[0] : (a == 1 ? M.bvol[1] : M.bvol[2]);
   const double *bn = a == 0 ? M.bnode[0] : (a == 1 ? M.bnode[1] : M.bnode[2]);
@@ -389,7 +409,7 @@ __device__ __forceinline__ int cell_of_logical(int L, const FMesh &M) {
   return i1 + N1 * (i2 + N2 * i3);
 }
 
-template <int N, typename T, bool HEUN>
+template <int N, typename T, bool HEUN, bool BP>
 __global__ __launch_bounds__(FCfg<N>::THREADS)
 __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_kernel(
     const T *__restrict__ x, T *__restrict__ y, FMesh M) {
@@ -703,8 +723,17 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
     T bh[3];
     const double *bzt[3];
     bool bz[3];
+    // product form: b_r / h_r = (f_r0(q1) f_r1(q2) / h_r) f_r2(q3), a lane factor
+    // times a value of the axis-3 tables (scalar bases, one lane offset o2)
+    const int o2 = G.i2 * N;
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
+      if (BP) {
+        bz[r] = true;
+        bh[r] = T(bfac(M.bf, r, 0)[G.i0 * N + alpha] * bfac(M.bf, r, 1)[G.i1 * N + beta] * ihd[r]);
+        bzt[r] = nullptr;
+        continue;
+      }
       const int ax = M.b_axis[r];
       bz[r] = (ax == 2);
       const int ia = ax == 0 ? G.i0 : (ax == 1 ? G.i1 : G.i2);
@@ -713,9 +742,9 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
       bzt[r] = M.bvol[r] + G.i2 * N;
     }
     auto flux = [&](T u, T g0, T g1, T g2, int q3, T W, T &x0, T &x1, T &x2, T &x3) {
-      const T b0 = bz[0] ? T(bzt[0][q3]) * ih0 : bh[0];
-      const T b1 = bz[1] ? T(bzt[1][q3]) * ih1 : bh[1];
-      const T b2 = bz[2] ? T(bzt[2][q3]) * ih2 : bh[2];
+      const T b0 = BP ? bh[0] * T(M.bf[2][o2 + q3]) : (bz[0] ? T(bzt[0][q3]) * ih0 : bh[0]);
+      const T b1 = BP ? bh[1] * T(M.bf[5][o2 + q3]) : (bz[1] ? T(bzt[1][q3]) * ih1 : bh[1]);
+      const T b2 = BP ? bh[2] * T(M.bf[8][o2 + q3]) : (bz[2] ? T(bzt[2][q3]) * ih2 : bh[2]);
       x0 = W * cc * u;
       x1 = W * (Kh[0] * g0 + Kh[1] * g1 + Kh[2] * g2 - b0 * u);
       x2 = W * (Kh[3] * g0 + Kh[4] * g1 + Kh[5] * g2 - b1 * u);
@@ -796,7 +825,7 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
       const double avg = F.cTb * double(gb[e]) + F.cTc * double(gc[e]) + F.cTa * double(ga[e]) +
                          double(R[ZN_OFF + (2 * e + 1) * NN + p]);
       const double un = R[ZN_OFF + (2 * e + 0) * NN + p];
-      const double ba = face_b(M, G, N, 2, e, alpha, beta);
+      const double ba = face_b<BP>(M, G, N, 2, e, alpha, beta);
       double Z;
       face_flux(F, double(u[e]), un, avg, ba, wab, RV[e], Z);
       Za[e] = F.cTa * Z;
@@ -886,9 +915,9 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
         }
         const double W = wp * Wt[h];
         double RVa, Za, RVm, Zm;
-        face_flux(F, double(Eo + Oo), double(En + On), double(Ea + Oa), face_b(M, G, N, a, e, pi, h), W,
+        face_flux(F, double(Eo + Oo), double(En + On), double(Ea + Oa), face_b<BP>(M, G, N, a, e, pi, h), W,
                   RVa, Za);
-        face_flux(F, double(Eo - Oo), double(En - On), double(Ea - Oa), face_b(M, G, N, a, e, pi, N - 1 - h),
+        face_flux(F, double(Eo - Oo), double(En - On), double(Ea - Oa), face_b<BP>(M, G, N, a, e, pi, N - 1 - h),
                   W, RVm, Zm);
         const T sr = T(RVa + RVm), dr = T(RVa - RVm), sz = T(Za + Zm), dz = T(Za - Zm);
 #pragma unroll
@@ -908,7 +937,7 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
           av = fma(V[m * N + t], A1[t], av);
         }
         double RVm, Zm;
-        face_flux(F, double(uo), double(un), double(av), face_b(M, G, N, a, e, pi, m), wp * Wt[m], RVm, Zm);
+        face_flux(F, double(uo), double(un), double(av), face_b<BP>(M, G, N, a, e, pi, m), wp * Wt[m], RVm, Zm);
 #pragma unroll
         for (int j = 0; j < N; j += 2) {
           VR[j] = fma(V[m * N + j], T(RVm), VR[j]);
@@ -1087,7 +1116,7 @@ struct LaneTab {
   static __device__ __forceinline__ double W(int q) { return GLTab<N>::v[TabOff<N>::W + (q < H ? q : N - 1 - q)]; }
 };
 
-template <int N, typename T, bool HEUN>
+template <int N, typename T, bool HEUN, bool BP>
 __global__ __launch_bounds__(256) void apply_lane_kernel(const T *__restrict__ x, T *__restrict__ y, FMesh M) {
   constexpr int NN = N * N, NNN = N * N * N;
   using TB = LaneTab<N, T>;
@@ -1147,6 +1176,11 @@ __global__ __launch_bounds__(256) void apply_lane_kernel(const T *__restrict__ x
           T bh[3];
 #pragma unroll
           for (int r = 0; r < 3; ++r) {
+            if (BP) {
+              bh[r] = T(bfac(M.bf, r, 0)[ic[0] * N + q1] * bfac(M.bf, r, 1)[ic[1] * N + q2] *
+                        bfac(M.bf, r, 2)[ic[2] * N + q3] * ihd[r]);
+              continue;
+            }
             const int ax = M.b_axis[r];
             const int qx = ax == 0 ? qa[0] : (ax == 1 ? qa[1] : qa[2]);
             const int ix = ax == 0 ? ic[0] : (ax == 1 ? ic[1] : ic[2]);
@@ -1242,7 +1276,7 @@ __global__ __launch_bounds__(256) void apply_lane_kernel(const T *__restrict__ x
                            F.cNa * double(gan) + F.cNb * double(gbn) + F.cNc * double(gcn);
         const double W = TB::W(qb) * TB::W(qc) * hb * hc;
         double RV, Z;
-        face_flux(F, double(uo), double(un), avg, face_b(M, G, N, a, e, qb, qc), W, RV, Z);
+        face_flux(F, double(uo), double(un), avg, face_b<BP>(M, G, N, a, e, qb, qc), W, RV, Z);
         const T rv = T(RV), z = T(Z);
 #pragma unroll
         for (int jc = 0; jc < N; ++jc)
@@ -1281,7 +1315,7 @@ __global__ __launch_bounds__(256) void apply_lane_kernel(const T *__restrict__ x
   }
 }
 
-template <int N, typename T, bool HEUN>
+template <int N, typename T, bool HEUN, bool BP>
 static hipError_t launch_fused_n(const dg_handle *h, const T *x, T *y, hipStream_t s, const double *f = nullptr,
                                  double dt = 0.0, int stage = 0) {
   using C = FCfg<N>;
@@ -1292,6 +1326,10 @@ static hipError_t launch_fused_n(const dg_handle *h, const T *x, T *y, hipStream
     M.bvol[a] = h->mesh.bvol[a];
     M.bnode[a] = h->mesh.bnode[a];
     M.b_axis[a] = h->mesh.b_axis[a];
+  }
+  for (int t = 0; t < 9; ++t) {
+    M.bf[t] = h->mesh.bf[t];
+    M.bfn[t] = h->mesh.bfn[t];
   }
   M.kappa = h->mesh.kappa;
   M.w = h->mesh.w;
@@ -1309,32 +1347,39 @@ static hipError_t launch_fused_n(const dg_handle *h, const T *x, T *y, hipStream
   if (N == 2) {  // k = 1: one cell per lane
     const int nblocks = int((h->ncells + 255) / 256);
     M.groups = (nblocks + 7) / 8;
-    hipLaunchKernelGGL((apply_lane_kernel<2, T, HEUN>), dim3(unsigned(8 * M.groups)), dim3(256), 0, s, x, y, M);
+    hipLaunchKernelGGL((apply_lane_kernel<2, T, HEUN, BP>), dim3(unsigned(8 * M.groups)), dim3(256), 0, s, x, y, M);
     return hipGetLastError();
   }
   const int nblocks = int((h->ncells + C::CPB - 1) / C::CPB);
   M.groups = (nblocks + 7) / 8;
-  hipLaunchKernelGGL((apply_fused_kernel<N, T, HEUN>), dim3(unsigned(8 * M.groups)), dim3(C::THREADS), 0, s,
+  hipLaunchKernelGGL((apply_fused_kernel<N, T, HEUN, BP>), dim3(unsigned(8 * M.groups)), dim3(C::THREADS), 0, s,
                      x, y, M);
   return hipGetLastError();
+}
+
+template <typename T, bool HEUN, bool BP>
+static hipError_t launch_fused_bp(const dg_handle *h, const T *x, T *y, hipStream_t s, const double *f, double dt,
+                                  int stage) {
+  switch (h->k + 1) {
+    case 2: return launch_fused_n<2, T, HEUN, BP>(h, x, y, s, f, dt, stage);
+    case 3: return launch_fused_n<3, T, HEUN, BP>(h, x, y, s, f, dt, stage);
+    case 4: return launch_fused_n<4, T, HEUN, BP>(h, x, y, s, f, dt, stage);
+    case 5: return launch_fused_n<5, T, HEUN, BP>(h, x, y, s, f, dt, stage);
+    case 6: return launch_fused_n<6, T, HEUN, BP>(h, x, y, s, f, dt, stage);
+    case 7: return launch_fused_n<7, T, HEUN, BP>(h, x, y, s, f, dt, stage);
+    case 8: return launch_fused_n<8, T, HEUN, BP>(h, x, y, s, f, dt, stage);
+    case 9: return launch_fused_n<9, T, HEUN, BP>(h, x, y, s, f, dt, stage);
+    case 10: return launch_fused_n<10, T, HEUN, BP>(h, x, y, s, f, dt, stage);
+    case 11: return launch_fused_n<11, T, HEUN, BP>(h, x, y, s, f, dt, stage);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <typename T, bool HEUN>
 static hipError_t launch_fused(const dg_handle *h, const T *x, T *y, hipStream_t s, const double *f = nullptr,
                                double dt = 0.0, int stage = 0) {
-  switch (h->k + 1) {
-    case 2: return launch_fused_n<2, T, HEUN>(h, x, y, s, f, dt, stage);
-    case 3: return launch_fused_n<3, T, HEUN>(h, x, y, s, f, dt, stage);
-    case 4: return launch_fused_n<4, T, HEUN>(h, x, y, s, f, dt, stage);
-    case 5: return launch_fused_n<5, T, HEUN>(h, x, y, s, f, dt, stage);
-    case 6: return launch_fused_n<6, T, HEUN>(h, x, y, s, f, dt, stage);
-    case 7: return launch_fused_n<7, T, HEUN>(h, x, y, s, f, dt, stage);
-    case 8: return launch_fused_n<8, T, HEUN>(h, x, y, s, f, dt, stage);
-    case 9: return launch_fused_n<9, T, HEUN>(h, x, y, s, f, dt, stage);
-    case 10: return launch_fused_n<10, T, HEUN>(h, x, y, s, f, dt, stage);
-    case 11: return launch_fused_n<11, T, HEUN>(h, x, y, s, f, dt, stage);
-    default: return hipErrorInvalidValue;
-  }
+  return h->mesh.bprod ? launch_fused_bp<T, HEUN, true>(h, x, y, s, f, dt, stage)
+                       : launch_fused_bp<T, HEUN, false>(h, x, y, s, f, dt, stage);
 }
 
 hipError_t launch_apply_fused_f64(const dg_handle *h, const double *x, double *y, hipStream_t s) {

@@ -27,8 +27,10 @@ struct RefMesh {
   int ncell[3];
   int periodic;  // bit a: axis a is periodic
   const double *h[3], *bvol[3], *bnode[3], *kappa;
+  const double *bf[9], *bfn[9];  // product-form factors (bprod)
   double K[9], c, sigma;
   int b_axis[3];
+  int bprod;
 };
 
 constexpr int kRefThreads = 256;
@@ -114,7 +116,9 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
     double Fr[3];
     for (int r = 0; r < 3; ++r) {
       const int ax = M.b_axis[r];
-      const double br = M.bvol[r][ic[ax] * N + qq[ax]];
+      const double br = M.bprod ? M.bf[3 * r][ic[0] * N + q1] * M.bf[3 * r + 1][ic[1] * N + q2] *
+                                      M.bf[3 * r + 2][ic[2] * N + q3]
+                                : M.bvol[r][ic[ax] * N + qq[ax]];
       Fr[r] = kap * (M.K[3 * r] * g[0] + M.K[3 * r + 1] * g[1] + M.K[3 * r + 2] * g[2]) - br * u;
     }
     B0[i] = W * M.c * u;
@@ -212,7 +216,10 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
         // b_a at the face point: b_a depends on the coordinate b_axis[a]
         const int ax = M.b_axis[a];
         double ba;
-        if (ax == a)
+        if (M.bprod)
+          ba = M.bfn[3 * a + a][face_node(ic[a], e, nb.wrap)] * M.bf[3 * a + b][ic[b] * N + qb] *
+               M.bf[3 * a + c][ic[c] * N + qc];
+        else if (ax == a)
           ba = M.bnode[a][face_node(ic[a], e, nb.wrap)];
         else if (ax == b)
           ba = M.bvol[a][ic[b] * N + qb];
@@ -272,6 +279,11 @@ static hipError_t launch_ref_n(const dg_handle *h, const double *x, double *y, h
     M.bnode[a] = h->mesh.bnode[a];
     M.b_axis[a] = h->mesh.b_axis[a];
   }
+  for (int t = 0; t < 9; ++t) {
+    M.bf[t] = h->mesh.bf[t];
+    M.bfn[t] = h->mesh.bfn[t];
+  }
+  M.bprod = h->mesh.bprod;
   M.kappa = h->mesh.kappa;
   M.periodic = h->mesh.periodic;
   for (int i = 0; i < 9; ++i) M.K[i] = h->mesh.K[i];

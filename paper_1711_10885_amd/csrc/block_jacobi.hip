@@ -431,9 +431,16 @@ static void cell_classes(const dg_problem *p, std::vector<int32_t> &cls, std::ve
         key[nk++] = nb[a][1].in ? p->kappa[nb[a][1].cell] : -1.0;
       }
     }
-    // a sine part of b_r makes it depend on the coordinate along b_axis[r]
-    for (int r = 0; r < 3; ++r)
-      if (p->b_sin[r] != 0.0) key[nk++] = p->nodes[p->b_axis[r]][i[p->b_axis[r]]];
+    if (p->flags & DG_B_PRODUCT) {
+      // a non-constant factor along axis j makes b depend on the cell's position along j
+      for (int j = 0; j < 3; ++j)
+        if (p->b_freq[j] != 0.0 || p->b_freq[3 + j] != 0.0 || p->b_freq[6 + j] != 0.0)
+          key[nk++] = p->nodes[j][i[j]];
+    } else {
+      // a sine part of b_r makes it depend on the coordinate along b_axis[r]
+      for (int r = 0; r < 3; ++r)
+        if (p->b_sin[r] != 0.0) key[nk++] = p->nodes[p->b_axis[r]][i[p->b_axis[r]]];
+    }
     for (int t = 0; t < nk; ++t) key[t] = key_round(key[t]);
     auto it = ids.emplace(std::string(reinterpret_cast<const char *>(key), size_t(nk) * sizeof(double)),
                           int32_t(rep.size()));

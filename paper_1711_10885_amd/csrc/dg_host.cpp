@@ -186,8 +186,13 @@ extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
         return set_error(DG_EINVAL, "dg_setup: kappa must be positive and finite");
   const int n = p->k + 1;
   if (ncells > (int64_t(1) << 31) / 2) return set_error(DG_EINVAL, "dg_setup: too many cells");
-  if (p->flags & ~(DG_WITH_BLOCK_JACOBI | DG_PERIODIC_X | DG_PERIODIC_Y | DG_PERIODIC_Z))
+  if (p->flags & ~(DG_WITH_BLOCK_JACOBI | DG_PERIODIC_X | DG_PERIODIC_Y | DG_PERIODIC_Z | DG_B_PRODUCT))
     return set_error(DG_EINVAL, "dg_setup: unknown flag bits");
+  const bool bprod = (p->flags & DG_B_PRODUCT) != 0;
+  if (bprod)
+    for (int t = 0; t < 9; ++t)
+      if (!std::isfinite(p->b_freq[t]) || !std::isfinite(p->b_phase[t]) || !std::isfinite(p->b_amp[t / 3]))
+        return set_error(DG_EINVAL, "dg_setup: product-form b must be finite");
   const int periodic = (p->flags >> 2) & 7;  // bit a: axis a
   if ((p->flags & DG_WITH_BLOCK_JACOBI) && n * n * n > kMaxBjBlock)
     return set_error(DG_EINVAL, "dg_setup: block Jacobi supports k <= 7");
@@ -246,6 +251,21 @@ extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
     for (int i = 0; i <= p->ncell[ax]; ++i)
       host.push_back(p->b_const[r] + p->b_sin[r] * std::sin(M_PI * p->nodes[ax][i]));
   }
+  // product form: factor f_rj at the Gauss coordinates and nodes of axis j
+  size_t off_bf[9] = {}, off_bfn[9] = {};
+  if (bprod)
+    for (int t = 0; t < 9; ++t) {
+      const int r = t / 3, j = t % 3;
+      const double amp = j == 0 ? p->b_amp[r] : 1.0;
+      auto f = [&](double s) { return p->b_freq[t] == 0.0 ? amp : amp * std::sin(p->b_freq[t] * s + p->b_phase[t]); };
+      off_bf[t] = host.size();
+      for (int i = 0; i < p->ncell[j]; ++i) {
+        const double o = p->nodes[j][i], hh = p->nodes[j][i + 1] - p->nodes[j][i];
+        for (int q = 0; q < m; ++q) host.push_back(f(o + hh * h->tab.xi[q]));
+      }
+      off_bfn[t] = host.size();
+      for (int i = 0; i <= p->ncell[j]; ++i) host.push_back(f(p->nodes[j][i]));
+    }
   const size_t off_w = host.size();
   host.insert(host.end(), h->tab.w, h->tab.w + m);
   if (p->kappa) {
@@ -272,6 +292,11 @@ extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
     M.bnode[a] = base + off_bn[a];
     M.b_axis[a] = p->b_axis[a];
   }
+  for (int t = 0; t < 9; ++t) {
+    M.bf[t] = bprod ? base + off_bf[t] : nullptr;
+    M.bfn[t] = bprod ? base + off_bfn[t] : nullptr;
+  }
+  M.bprod = bprod ? 1 : 0;
   M.kappa = p->kappa ? base + off_kappa : nullptr;
   M.periodic = periodic;
   M.w = base + off_w;

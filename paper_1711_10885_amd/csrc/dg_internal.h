@@ -36,6 +36,12 @@ struct DevMesh {
   double *nodes[3];   // node coordinates per axis, ncell[a] + 1
   double *bvol[3];    // b_r at volume Gauss coordinates: [ncell[b_axis[r]] * m]
   double *bnode[3];   // b_r at nodes of axis b_axis[r]: [ncell[b_axis[r]] + 1]
+  // product form (DG_B_PRODUCT; else null): factor f_rj of b_r along axis j,
+  // b_amp[r] folded into j = 0, at the Gauss coordinates [ncell[j] * m] and
+  // at the nodes [ncell[j] + 1] of axis j; index 3 r + j
+  double *bf[9];
+  double *bfn[9];
+  int bprod;
   double *kappa;      // per cell or nullptr (= 1)
   int periodic;       // bit a: axis a is periodic (DG_PERIODIC_*)
   double *w;          // Gauss weights on [0,1] (for lane-dependent lookups)

@@ -22,12 +22,11 @@ the paper's model problem, Sec. 2.1, and Problem A of Sec. 5.1):
 * ``learned_k3_64``  k = 3, 64^3, kappa_T = exp(g(center_T)), g a seeded smooth
   random field (random Fourier features, M = 128, length scale 0.1, seed 5),
   b = (1, .5, .25), c = 0.1, sigma = 2k(k+2), f = 1.
-* ``transport_k5_64`` k = 5, 64^3 uniform cubes, periodic on every axis,
-  K = 5e-6 I, c = 0, f = 0 (the coefficients of the transport example of
-  Sec. 5.4), b = (sin pi y, sin pi z, sin pi x) (divergence free and
-  continuous across the periodic wrap), sigma = 2k(k+2); initial
-  concentration the projection of sin(pi x) sin(pi y) sin(pi z); time step
-  dt = 1.5e-4 (64 / N).
+* ``transport_k5_64`` the transport example of Sec. 5.4 at one GPU's size:
+  k = 5, 64^3 uniform cubes of the periodic box (-pi, pi)^3, K = 5e-6 I,
+  c = 0, f = 0, the Taylor-Green flow field of that section (eq. (2)) in
+  product form, sigma = 2k(k+2); initial concentration exp(-2 |x - x0|^2),
+  x0 = (1/2, 0, 0), taken at the cell centres as the cell-constant mode.
 """
 from __future__ import annotations
 
@@ -50,6 +49,11 @@ class Problem:
     c: float = 0.0
     sigma: float = 1.0
     periodic: tuple = (False, False, False)  # per axis
+    # product-form flow field b_r = b_amp[r] prod_j sin(b_freq[3r+j] x_j + b_phase[3r+j])
+    # (factor 1 where b_freq is 0); replaces b_const/b_sin/b_axis when b_amp is set
+    b_amp: tuple | None = None
+    b_freq: tuple = (0.0,) * 9
+    b_phase: tuple = (0.0,) * 9
     name: str = ""
     meta: dict = field(default_factory=dict)
 
@@ -103,6 +107,14 @@ def random_spd(rng, lo: float = 0.2, hi: float = 2.0) -> np.ndarray:
 
 
 SINE_CYCLIC = dict(b_const=(0.0, 0.0, 0.0), b_sin=(1.0, 1.0, 1.0), b_axis=(1, 2, 0))
+
+# Taylor-Green field of Sec. 5.4, eq. (2), as b_r = amp_r prod_j sin(freq x_j + phase):
+#   b_1 = cos(x_1) sin(-x_2) sin(-x_3), b_2 = 1/2 sin(x_1) cos(-x_2) sin(-x_3),
+#   b_3 = 1/2 sin(x_1) sin(-x_2) cos(-x_3)   (cos s = sin(s + pi/2))
+TAYLOR_GREEN = dict(b_amp=(1.0, 0.5, 0.5),
+                    b_freq=(1.0, -1.0, -1.0, 1.0, -1.0, -1.0, 1.0, -1.0, -1.0),
+                    b_phase=(math.pi / 2, 0.0, 0.0, 0.0, math.pi / 2, 0.0, 0.0, 0.0, math.pi / 2))
+TRANSPORT_DT_H = 0.01  # dt / h: rho(M^-1 A) h stays below 83 at k = 5, so dt rho < 0.83
 
 
 def paper_sigma(k: int) -> float:
@@ -177,6 +189,14 @@ def random_problem(seed: int, ncell=(3, 2, 2), k: int = 2, b: str = "sine",
     if b == "sine":
         bk = dict(b_const=tuple(rng.uniform(-0.5, 0.5, 3)), b_sin=tuple(rng.uniform(0.5, 2, 3)),
                   b_axis=(1, 2, 0))
+    elif b == "product":  # random product-form field: every factor a sine of its coordinate
+        bk = dict(b_amp=tuple(rng.uniform(-1.5, 1.5, 3)),
+                  b_freq=tuple(rng.choice([-2.0, -1.0, 1.0, 3.0], 9) * math.pi),
+                  b_phase=tuple(rng.uniform(0.0, 2.0 * math.pi, 9)))
+    elif b == "product_sparse":  # some factors constant (frequency 0)
+        fr = rng.choice([-2.0, -1.0, 1.0, 3.0], 9) * math.pi * (rng.uniform(0, 1, 9) < 0.5)
+        bk = dict(b_amp=tuple(rng.uniform(-1.5, 1.5, 3)), b_freq=tuple(fr),
+                  b_phase=tuple(rng.uniform(0.0, 2.0 * math.pi, 9)))
     elif b == "const":
         bk = dict(b_const=tuple(rng.uniform(-2, 2, 3)), b_sin=(0.0, 0.0, 0.0), b_axis=(0, 1, 2))
     else:
@@ -205,18 +225,25 @@ SIN, COS, ONE = 1, 2, 0
 
 
 def transport_k5_64(N: int = 64, k: int = 5) -> Problem:
-    """Periodic convection-dominated transport at one GPU's share of the
-    Sec. 5.4 example.  The time step keeps dt rho(M^{-1} A) near 0.8 (rho is
-    about 83 / h for this operator at k = 5), inside the real-axis stability
-    interval [-2, 0] of Heun's method."""
-    return Problem(ncell=(N, N, N), nodes=(uniform_nodes(N),) * 3, k=k, K=5e-6 * np.eye(3), c=0.0,
+    """The Taylor-Green transport problem of Sec. 5.4 on one GPU's share:
+    periodic box (-pi, pi)^3, K = 5e-6 I, c = 0, f = 0.  meta["dt"] keeps
+    dt rho(M^{-1} A) below 1, inside the real-axis stability interval
+    [-2, 0] of Heun's method."""
+    nodes = tuple(np.linspace(-math.pi, math.pi, N + 1) for _ in range(3))
+    return Problem(ncell=(N, N, N), nodes=nodes, k=k, K=5e-6 * np.eye(3), c=0.0,
                    sigma=paper_sigma(k), periodic=(True, True, True), name=f"transport_k{k}_{N}",
-                   meta={"dt": 1.5e-4 * 64.0 / N}, **SINE_CYCLIC)
+                   meta={"dt": TRANSPORT_DT_H * (2.0 * math.pi / N)}, **TAYLOR_GREEN)
 
 
-def transport_initial():
-    """Initial concentration sin(pi x) sin(pi y) sin(pi z) as source terms."""
-    return [(1.0, (SIN, SIN, SIN))]
+def transport_initial(prob: Problem, x0=(0.5, 0.0, 0.0)) -> np.ndarray:
+    """Coefficient vector of the initial concentration exp(-2 |x - x0|^2) of
+    Sec. 5.4: its value at each cell centre as the cell's constant mode (the
+    first coefficient of every cell block), the other coefficients zero."""
+    nb = (prob.k + 1) ** 3
+    c = cell_centers(prob.nodes)
+    u = np.zeros(prob.ndof)
+    u[::nb] = np.exp(-2.0 * ((c - np.asarray(x0)) ** 2).sum(axis=1))
+    return u
 
 
 def manufactured_u():

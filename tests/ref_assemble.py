@@ -46,8 +46,16 @@ def _tensor_shape(vals, ders, h):
 
 def _b(prob, X):
     b = np.empty_like(X)
+    amp = getattr(prob, "b_amp", None)
     for r in range(3):
-        b[:, r] = prob.b_const[r] + prob.b_sin[r] * np.sin(np.pi * X[:, prob.b_axis[r]])
+        if amp is None:
+            b[:, r] = prob.b_const[r] + prob.b_sin[r] * np.sin(np.pi * X[:, prob.b_axis[r]])
+        else:
+            b[:, r] = amp[r]
+            for j in range(3):
+                w = prob.b_freq[3 * r + j]
+                if w != 0.0:
+                    b[:, r] *= np.sin(w * X[:, j] + prob.b_phase[3 * r + j])
     return b
 
 

@@ -66,7 +66,7 @@ def _struct(prob, **over):
     (dict(K=np.array([[1, 0.5, 0], [0, 1, 0], [0, 0, 1.0]])), "symmetric"),
     (dict(b_axis0=3), "b_axis"),
     (dict(c=float("nan")), "c must be finite"),
-    (dict(flags=32), "unknown flag"),
+    (dict(flags=64), "unknown flag"),
     (dict(k=8, flags=2), "block Jacobi supports"),
 ])
 def test_setup_rejects_invalid_problems(over, msg):
@@ -88,6 +88,17 @@ def test_block_jacobi_rejects_an_odd_periodic_axis():
     h = ctypes.c_void_p()
     assert lib.dg_setup(ctypes.byref(s), ctypes.byref(h)) == binding.DG_EINVAL
     assert "even number of cells" in lib.dg_last_error().decode()
+    assert not h.value
+
+
+def test_setup_rejects_a_non_finite_product_field():
+    lib = _lib()
+    s, keep = _struct(workloads.poisson_k2_8(), flags=binding.DG_B_PRODUCT)
+    s.b_amp[0] = 1.0
+    s.b_freq[4] = float("inf")
+    h = ctypes.c_void_p()
+    assert lib.dg_setup(ctypes.byref(s), ctypes.byref(h)) == binding.DG_EINVAL
+    assert "product-form b" in lib.dg_last_error().decode()
     assert not h.value
 
 

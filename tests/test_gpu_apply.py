@@ -172,3 +172,40 @@ def test_periodic_fp32_operator_matches_fp64(k):
     e = np.abs(y - ref).max() / np.abs(ref).max()
     print(f"periodic fp32 k={k}: relmax {e:.2e}", flush=True)
     assert e <= 30 * (k + 1) * 2.0 ** -24
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("k", range(1, 11))
+def test_product_b_every_degree(variant, k):
+    """Product-form flow field b_r = amp_r prod_j sin(w_rj x_j + phi_rj) (every
+    factor non-constant, or some factors constant), with Dirichlet and
+    periodic axes, both kernels."""
+    ncell = (3, 3, 2) if k <= 5 else (3, 2, 2)
+    per = PERIODIC[k % 4]
+    p = W.random_problem(1500 + k, ncell=ncell, k=k, b="product" if k % 2 else "product_sparse", periodic=per)
+    x = W.random_vector(p.ndof, 1510 + k)
+    _check(_gpu_apply(p, x, variant), oracle.apply(p, x), f"product b {per} k={k} {ncell} v{variant}")
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("k", [3, 5])
+def test_taylor_green_box(variant, k):
+    """The transport problem's operator (Taylor-Green b on the periodic box
+    (-pi, pi)^3) on a 4^3 mesh."""
+    p = W.transport_k5_64(N=4, k=k)
+    x = W.transport_initial(p) + 0.1 * W.random_vector(p.ndof, 1520 + k)
+    _check(_gpu_apply(p, x, variant), oracle.apply(p, x), f"taylor-green 4^3 k={k} v{variant}")
+
+
+@pytest.mark.parametrize("k", [2, 5, 7])
+def test_product_b_fp32_operator_matches_fp64(k):
+    torch = _torch()
+    from paper_1711_10885_amd import binding
+    p = W.random_problem(1530 + k, ncell=(3, 2, 3), k=k, b="product", periodic=(True, False, True))
+    x = W.random_vector(p.ndof, 1540 + k)
+    ref = oracle.apply(p, x)
+    with binding.DG(p) as dg:
+        y = dg.apply_f32(torch.from_numpy(x).float().cuda()).double().cpu().numpy()
+    e = np.abs(y - ref).max() / np.abs(ref).max()
+    print(f"product b fp32 k={k}: relmax {e:.2e}", flush=True)
+    assert e <= 30 * (k + 1) * 2.0 ** -24

@@ -7,6 +7,8 @@ by the FP32 rounding of the inverse: |dz_i| <= u32 (|A_TT^{-1}| |r_T|)_i,
 taken with a factor 2 (u32 = 2^-24) plus a 1e-10 max|z| floor for the FP64
 inversion error.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -223,3 +225,33 @@ def test_precond_apply_without_block_jacobi_is_rejected():
             dg.precond_apply(r)
         with pytest.raises(binding.DGError):
             dg.solve(r + 1.0, precond=binding.DG_PREC_BLOCK_JACOBI)
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_shared_blocks_with_a_product_b(k):
+    """Product-form b whose factors vary along axis 1 only, on a uniform
+    periodic mesh: cells are keyed by their position along that axis (4
+    classes); every cell's result is checked against its own oracle block."""
+    torch = _torch()
+    from paper_1711_10885_amd import binding
+    N = 4
+    fr = (math.pi * 2, 0.0, 0.0, -math.pi * 2, 0.0, 0.0, math.pi * 4, 0.0, 0.0)
+    p = W.mixed_k5_48(N=N, k=k).with_(periodic=(True, True, True), b_amp=(0.8, -0.5, 1.2), b_freq=fr,
+                                        b_phase=(0.3, 0.0, 0.0, 1.1, 0.0, 0.0, 2.0, 0.0, 0.0))
+    r = W.random_vector(p.ndof, 580 + k)
+    with binding.DG(p, flags=binding.DG_WITH_BLOCK_JACOBI) as dg:
+        assert dg.bj_nblocks() == N
+        z = dg.precond_apply(torch.from_numpy(r).cuda()).cpu().numpy()
+    _check_blocks(oracle.block_diagonal(p), r, z, f"product b shared k={k}")
+
+
+def test_taylor_green_blocks_one_per_cell():
+    """Every factor of the Taylor-Green field varies: no two cells share a block."""
+    torch = _torch()
+    from paper_1711_10885_amd import binding
+    p = W.transport_k5_64(N=4, k=2)
+    r = W.random_vector(p.ndof, 590)
+    with binding.DG(p, flags=binding.DG_WITH_BLOCK_JACOBI) as dg:
+        assert dg.bj_nblocks() == p.ncells
+        z = dg.precond_apply(torch.from_numpy(r).cuda()).cpu().numpy()
+    _check_blocks(oracle.block_diagonal(p), r, z, "taylor-green blocks")

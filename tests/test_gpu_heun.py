@@ -134,10 +134,10 @@ def test_constant_field_decays_by_the_stability_function():
 
 
 def test_transport_full_size_sampled_cells():
-    """One step at the bench's transport workload (64^3, k = 5, 56.6M DOF),
-    in the bench's launch configuration, against the oracle stepping sampled
-    cells (corners and faces of the periodic box, where the wrap is taken, and
-    interior cells)."""
+    """One step at the bench's transport workload (Taylor-Green b, 64^3, k = 5,
+    56.6M DOF), in the bench's launch configuration, against the oracle
+    stepping sampled cells (corners and faces of the periodic box, where the
+    wrap is taken, and interior cells)."""
     torch = _torch()
     from paper_1711_10885_amd import binding
     p = W.transport_k5_64()
@@ -161,6 +161,28 @@ def test_transport_full_size_sampled_cells():
     print(f"transport 64^3 k=5 sampled {len(cells)} cells: increment relmax {e:.2e}", flush=True)
     assert e <= TOL
     assert np.abs(got[cells] - ref).max() <= TOL * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_heun_taylor_green(variant):
+    """The transport problem (Taylor-Green b, periodic box (-pi, pi)^3,
+    K = 5e-6 I) on a 4^3 mesh at k = 3 from its Gaussian initial field, with
+    the workload's own time step rule."""
+    p = W.transport_k5_64(N=4, k=3)
+    u0 = W.transport_initial(p)
+    dt, n = p.meta["dt"], 6
+    _check(_gpu_heun(p, u0, dt, n, variant), oracle.heun(p, u0, dt, n), u0, f"taylor-green v{variant}")
+
+
+def test_taylor_green_mass_is_conserved():
+    p = W.transport_k5_64(N=6, k=4)
+    nb = (p.k + 1) ** 3
+    u0 = W.transport_initial(p)
+    u = _gpu_heun(p, u0, p.meta["dt"], 100)
+    m0, m1 = u0[::nb].sum(), u[::nb].sum()  # uniform cells: |T| is a common factor
+    print(f"taylor-green mass {m0:.15e} -> {m1:.15e}", flush=True)
+    assert abs(m1 - m0) <= 1e-13 * np.abs(u0[::nb]).sum()
+    assert np.abs(u - u0).max() > 1e-3
 
 
 @pytest.mark.parametrize("case", ["dt0", "dtnan", "dtneg", "nsteps", "overlap"])
