@@ -68,6 +68,8 @@ class _Problem(ctypes.Structure):
         ("b_amp", ctypes.c_double * 3),
         ("b_freq", ctypes.c_double * 9),
         ("b_phase", ctypes.c_double * 9),
+        ("kappa_poly_on", ctypes.c_int32),
+        ("kappa_poly", ctypes.c_double * 9),
     ]
 
 
@@ -134,6 +136,11 @@ class _Marshalled:
             for t in range(9):
                 s.b_freq[t] = float(prob.b_freq[t])
                 s.b_phase[t] = float(prob.b_phase[t])
+        kpoly = getattr(prob, "kappa_poly", None)
+        s.kappa_poly_on = 0 if kpoly is None else 1
+        if kpoly is not None:
+            for t in range(9):
+                s.kappa_poly[t] = float(kpoly[t])
         self.struct = s
 
 

@@ -36,7 +36,12 @@
  *    or_problem.b_product the product form
  *    b_r(x) = b_amp[r] * prod_j sin(b_freq[3r+j] x_j + b_phase[3r+j]) (factors
  *    with b_freq == 0 are 1), which holds the Taylor-Green field of Sec. 5.4
- *    (eq. (2) of that section); b is evaluated at each quadrature point.
+ *    (eq. (2) of that section); b is evaluated at each quadrature point;
+ *  - with or_problem.kappa_poly_on the diffusion tensor is
+ *    D(x) = kappa_T kp(x) K, kp(x) = prod_j (c_j0 + c_j1 x_j + c_j2 x_j^2)
+ *    with c_ji = kappa_poly[3j+i] (coefficients polynomial in the
+ *    coordinates, as in Problems B and C of Sec. 5.1); d = nu^T D nu, the
+ *    weights and gamma_F are then evaluated at each face quadrature point.
  */
 #include <math.h>
 #include <stdint.h>
@@ -64,6 +69,8 @@ typedef struct {
   double b_amp[3];
   double b_freq[9];
   double b_phase[9];
+  int32_t kappa_poly_on; /* 1: D(x) = kappa_T kp(x) K, kp from kappa_poly */
+  double kappa_poly[9];
 } or_problem;
 
 /* term mask for or_apply: which sums of eq. (blf) to include */
@@ -159,6 +166,17 @@ static double coef_b(const or_problem *p, int r, const double *xp) {
   return p->b_const[r] + p->b_sin[r] * sin(M_PI * xp[p->b_axis[r]]);
 }
 
+/* The polynomial factor kp(x) of the diffusion tensor (1 when not used). */
+static double coef_kp(const or_problem *p, const double *xp) {
+  if (!p->kappa_poly_on) return 1.0;
+  double v = 1.0;
+  for (int j = 0; j < 3; ++j) {
+    const double *c = p->kappa_poly + 3 * j;
+    v *= c[0] + c[1] * xp[j] + c[2] * xp[j] * xp[j];
+  }
+  return v;
+}
+
 static double cell_kappa(const or_problem *p, int64_t c) {
   return p->kappa ? p->kappa[c] : 1.0;
 }
@@ -205,10 +223,11 @@ static void volume_cell(const or_problem *p, const or_tables *t, const int *ic,
             }
         double xp[3];
         for (int a = 0; a < 3; ++a) xp[a] = o[a] + h[a] * t->xi[q[a]];
+        const double kx = kap * coef_kp(p, xp); /* D = kx K at this point */
         double F[3];
         for (int r = 0; r < 3; ++r) {
           double s = 0.0;
-          for (int c = 0; c < 3; ++c) s += kap * p->K[3 * r + c] * g[c];
+          for (int c = 0; c < 3; ++c) s += kx * p->K[3 * r + c] * g[c];
           F[r] = s - coef_b(p, r, xp) * u;
         }
         const double W = t->w[q1] * t->w[q2] * t->w[q3] * vol;
@@ -286,10 +305,7 @@ static void interior_face(const or_problem *p, const or_tables *t, int a, const 
   cell_geom(p, ip, op, hp);
   const double km = cell_kappa(p, cell_id(p, im)), kp = cell_kappa(p, cell_id(p, ip));
   const double Kaa = p->K[4 * a];
-  const double dm = km * Kaa, dp = kp * Kaa;
-  const double wm = dp / (dm + dp), wp = dm / (dm + dp);
   const double hmin = hm[a] < hp[a] ? hm[a] : hp[a];
-  const double gamma = p->sigma * (2.0 * dm * dp / (dm + dp)) / hmin;
   const double area = hm[tb] * hm[tc];
   for (int qc = 0; qc < m; ++qc)
     for (int qb = 0; qb < m; ++qb) {
@@ -304,12 +320,18 @@ static void interior_face(const or_problem *p, const or_tables *t, int a, const 
       const double bnu = coef_b(p, a, X);
       const double Phi = (bnu >= 0.0) ? bnu * um : bnu * up;
       const double J = um - up;
+      /* D^- = kmx K, D^+ = kpx K at the point; d, the weights and gamma there */
+      const double kpoly = coef_kp(p, X);
+      const double kmx = km * kpoly, kpx = kp * kpoly;
+      const double dmx = kmx * Kaa, dpx = kpx * Kaa;
+      const double wmx = dpx / (dmx + dpx), wpx = dmx / (dmx + dpx);
+      const double gammax = p->sigma * (2.0 * dmx * dpx / (dmx + dpx)) / hmin;
       double Dgm = 0.0, Dgp = 0.0; /* nu . (D grad u^-), nu . (D grad u^+) */
       for (int s = 0; s < 3; ++s) {
-        Dgm += km * p->K[3 * a + s] * gm[s];
-        Dgp += kp * p->K[3 * a + s] * gp[s];
+        Dgm += kmx * p->K[3 * a + s] * gm[s];
+        Dgp += kpx * p->K[3 * a + s] * gp[s];
       }
-      const double avg = wm * Dgm + wp * Dgp;
+      const double avg = wmx * Dgm + wpx * Dgp;
       const double W = t->w[qb] * t->w[qc] * area;
       for (int j3 = 0; j3 < n; ++j3)
         for (int j2 = 0; j2 < n; ++j2)
@@ -321,16 +343,16 @@ static void interior_face(const or_problem *p, const or_tables *t, int a, const 
               double phi, gphi[3];
               shape_on_face(t, a, 1, tb, tc, qb, qc, j, hm, &phi, gphi);
               double Dgv = 0.0;
-              for (int s = 0; s < 3; ++s) Dgv += km * p->K[3 * a + s] * gphi[s];
-              ym[jj] += W * (Phi * phi - avg * phi - wm * Dgv * J + gamma * J * phi);
+              for (int s = 0; s < 3; ++s) Dgv += kmx * p->K[3 * a + s] * gphi[s];
+              ym[jj] += W * (Phi * phi - avg * phi - wmx * Dgv * J + gammax * J * phi);
             }
             if (yp) {
               /* test function on T^+: [[v]] = -v, {D grad v}_w = w+ D+ grad v */
               double phi, gphi[3];
               shape_on_face(t, a, 0, tb, tc, qb, qc, j, hp, &phi, gphi);
               double Dgv = 0.0;
-              for (int s = 0; s < 3; ++s) Dgv += kp * p->K[3 * a + s] * gphi[s];
-              yp[jj] += W * (-Phi * phi + avg * phi - wp * Dgv * J - gamma * J * phi);
+              for (int s = 0; s < 3; ++s) Dgv += kpx * p->K[3 * a + s] * gphi[s];
+              yp[jj] += W * (-Phi * phi + avg * phi - wpx * Dgv * J - gammax * J * phi);
             }
           }
     }
@@ -350,8 +372,6 @@ static void boundary_face(const or_problem *p, const or_tables *t, int a, int e,
   cell_geom(p, ic, o, h);
   const double kap = cell_kappa(p, cell_id(p, ic));
   const double nsign = e ? 1.0 : -1.0;
-  const double delta = kap * p->K[4 * a];
-  const double gamma = p->sigma * delta / h[a];
   const double area = h[tb] * h[tc];
   for (int qc = 0; qc < m; ++qc)
     for (int qb = 0; qb < m; ++qb) {
@@ -363,8 +383,10 @@ static void boundary_face(const or_problem *p, const or_tables *t, int a, int e,
       X[tc] = o[tc] + h[tc] * t->xi[qc];
       const double bnu = nsign * coef_b(p, a, X);
       const double Phi = (bnu >= 0.0) ? bnu * u : 0.0;
+      const double kx = kap * coef_kp(p, X); /* D = kx K at the point */
+      const double gammax = p->sigma * kx * p->K[4 * a] / h[a];
       double Dg = 0.0;
-      for (int s = 0; s < 3; ++s) Dg += kap * p->K[3 * a + s] * g[s];
+      for (int s = 0; s < 3; ++s) Dg += kx * p->K[3 * a + s] * g[s];
       Dg *= nsign;
       const double W = t->w[qb] * t->w[qc] * area;
       for (int j3 = 0; j3 < n; ++j3)
@@ -374,9 +396,9 @@ static void boundary_face(const or_problem *p, const or_tables *t, int a, int e,
             double phi, gphi[3];
             shape_on_face(t, a, e, tb, tc, qb, qc, j, h, &phi, gphi);
             double Dgv = 0.0;
-            for (int s = 0; s < 3; ++s) Dgv += kap * p->K[3 * a + s] * gphi[s];
+            for (int s = 0; s < 3; ++s) Dgv += kx * p->K[3 * a + s] * gphi[s];
             Dgv *= nsign;
-            yT[j1 + n * (j2 + n * j3)] += W * (Phi * phi - Dg * phi - Dgv * u + gamma * u * phi);
+            yT[j1 + n * (j2 + n * j3)] += W * (Phi * phi - Dg * phi - Dgv * u + gammax * u * phi);
           }
     }
 }

@@ -54,6 +54,9 @@ class Problem:
     b_amp: tuple | None = None
     b_freq: tuple = (0.0,) * 9
     b_phase: tuple = (0.0,) * 9
+    # polynomial diffusion factor: D(x) = kappa_T kp(x) K with
+    # kp(x) = prod_j (c[3j] + c[3j+1] x_j + c[3j+2] x_j^2), c = kappa_poly (None: kp = 1)
+    kappa_poly: tuple | None = None
     name: str = ""
     meta: dict = field(default_factory=dict)
 
@@ -204,6 +207,15 @@ def random_problem(seed: int, ncell=(3, 2, 2), k: int = 2, b: str = "sine",
     cc = float(rng.uniform(0.1, 2.0)) if c is None else float(c)
     return Problem(ncell=tuple(ncell), nodes=nodes, k=k, K=K, kappa=kap, c=cc,
                    sigma=paper_sigma(k), periodic=tuple(bool(v) for v in periodic), name=f"random_{seed}", **bk)
+
+
+def random_kappa_poly(rng) -> tuple:
+    """Per-axis quadratics c0 + c1 s + c2 s^2 positive on [0, 1] (c0 in [0.5, 1.5],
+    |c1| <= 0.4, c2 in [0, 0.8]): a smooth diffusion factor varying by up to 3x."""
+    c = []
+    for _ in range(3):
+        c += [float(rng.uniform(0.5, 1.5)), float(rng.uniform(-0.4, 0.4)), float(rng.uniform(0.0, 0.8))]
+    return tuple(c)
 
 
 def random_vector(n: int, seed: int, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:

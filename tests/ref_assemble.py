@@ -59,6 +59,17 @@ def _b(prob, X):
     return b
 
 
+def _kp(prob, X):
+    """Polynomial diffusion factor prod_j (c0 + c1 x_j + c2 x_j^2) at points X (1 if unset)."""
+    c = getattr(prob, "kappa_poly", None)
+    if c is None:
+        return np.ones(X.shape[0])
+    v = np.ones(X.shape[0])
+    for j in range(3):
+        v *= c[3 * j] + c[3 * j + 1] * X[:, j] + c[3 * j + 2] * X[:, j] ** 2
+    return v
+
+
 def assemble_dense(prob) -> np.ndarray:
     k = prob.k
     n = k + 1
@@ -94,7 +105,7 @@ def assemble_dense(prob) -> np.ndarray:
         Xq = np.stack(np.meshgrid(o[0] + h[0] * xi, o[1] + h[1] * xi, o[2] + h[2] * xi,
                                   indexing="ij"), axis=-1).transpose(2, 1, 0, 3).reshape(-1, 3)
         bq = _b(prob, Xq)
-        Dg = kap[c] * np.einsum("rs,pjs->pjr", K, g)           # D grad phi_j
+        Dg = kap[c] * _kp(prob, Xq)[:, None, None] * np.einsum("rs,pjs->pjr", K, g)  # D grad phi_j
         flux = Dg - bq[:, None, :] * phi[:, :, None]              # (P, j, 3)
         A[blk(c), blk(c)] += np.einsum("p,pjr,pir->ij", Wq, flux, g)
         A[blk(c), blk(c)] += prob.c * np.einsum("p,pj,pi->ij", Wq, phi, phi)
@@ -136,10 +147,11 @@ def assemble_dense(prob) -> np.ndarray:
                 W = face_weights(a, h)
                 X = face_points(a, o, h, op[a])
                 bnu = _b(prob, X)[:, a]
-                dm, dp = kap[c] * K[a, a], kap[cp] * K[a, a]
+                kpf = _kp(prob, X)                      # pointwise diffusion factor
+                dm, dp = kap[c] * kpf * K[a, a], kap[cp] * kpf * K[a, a]
                 wm, wp = dp / (dm + dp), dm / (dm + dp)
                 gam = prob.sigma * (2 * dm * dp / (dm + dp)) / min(h[a], hp[a])
-                side = {0: (c, *face_tables(a, 1, h), kap[c]), 1: (cp, *face_tables(a, 0, hp), kap[cp])}
+                side = {0: (c, *face_tables(a, 1, h), kap[c] * kpf), 1: (cp, *face_tables(a, 0, hp), kap[cp] * kpf)}
                 for su in (0, 1):        # trial function side (0: minus, 1: plus)
                     for sv in (0, 1):    # test function side
                         cu, phu, gu, ku = side[su]
@@ -147,14 +159,14 @@ def assemble_dense(prob) -> np.ndarray:
                         um = phu if su == 0 else 0 * phu
                         up = phu if su == 1 else 0 * phu
                         jump_u = um - up
-                        avg_u = (wm if su == 0 else wp) * ku * np.einsum("s,pjs->pj", K[a], gu)
+                        avg_u = ((wm if su == 0 else wp) * ku)[:, None] * np.einsum("s,pjs->pj", K[a], gu)
                         Phi = np.where(bnu[:, None] >= 0, bnu[:, None] * um, bnu[:, None] * up)
                         jump_v = phv if sv == 0 else -phv
-                        avg_v = (wm if sv == 0 else wp) * kv * np.einsum("s,pis->pi", K[a], gv)
+                        avg_v = ((wm if sv == 0 else wp) * kv)[:, None] * np.einsum("s,pis->pi", K[a], gv)
                         M = (np.einsum("p,pj,pi->ij", W, Phi, jump_v)
                              - np.einsum("p,pj,pi->ij", W, avg_u, jump_v)
                              - np.einsum("p,pi,pj->ij", W, avg_v, jump_u)
-                             + gam * np.einsum("p,pj,pi->ij", W, jump_u, jump_v))
+                             + np.einsum("p,pj,pi->ij", W * gam, jump_u, jump_v))
                         A[blk(cv), blk(cu)] += M
             for e in (0, 1):
                 at_bnd = (i[a] == 0) if e == 0 else (i[a] == N[a] - 1)
@@ -164,14 +176,15 @@ def assemble_dense(prob) -> np.ndarray:
                 X = face_points(a, o, h, o[a] + (h[a] if e == 1 else 0.0))
                 nsg = 1.0 if e == 1 else -1.0
                 bnu = nsg * _b(prob, X)[:, a]
-                delta = kap[c] * K[a, a]
+                kpf = _kp(prob, X)
+                delta = kap[c] * kpf * K[a, a]
                 gam = prob.sigma * delta / h[a]
                 ph, g = face_tables(a, e, h)
-                Dn = nsg * kap[c] * np.einsum("s,pjs->pj", K[a], g)
+                Dn = nsg * (kap[c] * kpf)[:, None] * np.einsum("s,pjs->pj", K[a], g)
                 Phi = np.where(bnu[:, None] >= 0, bnu[:, None] * ph, 0.0)
                 M = (np.einsum("p,pj,pi->ij", W, Phi, ph)
                      - np.einsum("p,pj,pi->ij", W, Dn, ph)
                      - np.einsum("p,pi,pj->ij", W, Dn, ph)
-                     + gam * np.einsum("p,pj,pi->ij", W, ph, ph))
+                     + np.einsum("p,pj,pi->ij", W * gam, ph, ph))
                 A[blk(c), blk(c)] += M
     return A
