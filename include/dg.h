@@ -107,6 +107,16 @@ typedef enum {
  *              must still be 0, 1 or 2).
  *              Block Jacobi classes then key on the cell position along
  *              every axis some factor depends on.
+ *              DG_KAPPA_POLY: the diffusion tensor varies inside cells,
+ *                D(x) = kappa_T kp(x) K,
+ *                kp(x) = prod_{j<3} (c[3j] + c[3j+1] x_j + c[3j+2] x_j^2),
+ *              c = kappa_poly (coefficients polynomial in the coordinates, as
+ *              in Problems B and C of Sec. 5.1), evaluated at the Gauss
+ *              points of cells and faces: d = nu^T D nu, the weights of the
+ *              averages and gamma_F are taken at each face point (kp is
+ *              continuous, so the weights reduce to those of kappa_T and
+ *              gamma_F scales by kp).  Every factor must be positive at every
+ *              Gauss coordinate and node of its axis: DG_EINVAL otherwise.
  */
 typedef struct {
   int32_t ncell[3];
@@ -123,6 +133,7 @@ typedef struct {
   double b_amp[3];    /* product-form flow field (DG_B_PRODUCT only) */
   double b_freq[9];
   double b_phase[9];
+  double kappa_poly[9];  /* polynomial diffusion factor (DG_KAPPA_POLY only) */
 } dg_problem;
 
 #define DG_WITH_BLOCK_JACOBI 2
@@ -130,6 +141,7 @@ typedef struct {
 #define DG_PERIODIC_Y 8
 #define DG_PERIODIC_Z 16
 #define DG_B_PRODUCT 32
+#define DG_KAPPA_POLY 64
 
 /* Create a handle on the current HIP device: validates the problem, builds
  * the 1D Gauss-Legendre/Legendre tables (Sec. 3.1/3.2, eq.

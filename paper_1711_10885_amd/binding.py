@@ -18,6 +18,7 @@ DG_OK, DG_EINVAL, DG_ENOMEM, DG_EHIP, DG_ENOTCONV, DG_ENAN = 0, -1, -2, -3, -4, 
 DG_WITH_BLOCK_JACOBI = 2
 DG_PERIODIC_X, DG_PERIODIC_Y, DG_PERIODIC_Z = 4, 8, 16
 DG_B_PRODUCT = 32
+DG_KAPPA_POLY = 64
 DG_KERNEL_AUTO, DG_KERNEL_REFERENCE = 0, 1
 DG_GMRES64, DG_GMRES_IR, DG_FGMRES = 0, 1, 2
 DG_PREC_NONE, DG_PREC_BLOCK_JACOBI, DG_PREC_LEARNED = 0, 1, 2
@@ -55,6 +56,7 @@ class _Problem(ctypes.Structure):
         ("b_amp", ctypes.c_double * 3),
         ("b_freq", ctypes.c_double * 9),
         ("b_phase", ctypes.c_double * 9),
+        ("kappa_poly", ctypes.c_double * 9),
     ]
 
 
@@ -210,6 +212,11 @@ class DG:
             for t in range(9):
                 s.b_freq[t] = float(prob.b_freq[t])
                 s.b_phase[t] = float(prob.b_phase[t])
+        kpoly = getattr(prob, "kappa_poly", None)
+        if kpoly is not None:
+            s.flags |= DG_KAPPA_POLY
+            for t in range(9):
+                s.kappa_poly[t] = float(kpoly[t])
         h = ctypes.c_void_p()
         _check(lib.dg_setup(ctypes.byref(s), ctypes.byref(h)))
         self._h = h

@@ -78,6 +78,7 @@ struct FMesh {
   int periodic;    // bit a: axis a is periodic
   const double *h[3], *bvol[3], *bnode[3], *kappa, *w;
   const double *bf[9], *bfn[9];  // product-form factors (BP instantiations)
+  const double *kf[3], *kfn[3];  // polynomial diffusion factor (KP instantiations)
   double K[9], c, sigma;
   int b_axis[3];
   int tz;          // depth (cells along axis 3) of the tiles of the cell order
@@ -350,13 +351,22 @@ __device__ __forceinline__ FC load_fc(const double *R, int f) {
 // Pointwise face flux at one face point: RV multiplies the test function,
 // Z = -W [[u]] the symmetry-term combination above.  Upwind flux of Sec. 2.2
 // with the outward normal velocity b . n_T.
+// With a pointwise diffusion factor kp (KP) every diffusive term (average,
+// penalty, symmetry) carries kp at the point; the weights do not (kp is
+// continuous across the face and cancels in them).
+template <bool KP>
 __device__ __forceinline__ void face_flux(const FC &F, double uo, double un, double avg, double ba,
-                                          double W, double &RV, double &Z) {
+                                          double W, double &RV, double &Z, double kp) {
   const double J = uo - un;
   const double bout = F.sgn * ba;
   const double Phi = bout >= 0.0 ? bout * uo : bout * un;
-  RV = W * (Phi - avg + F.gamma * J);
-  Z = -W * J;
+  if constexpr (KP) {
+    RV = W * (Phi - kp * avg + kp * F.gamma * J);
+    Z = -W * kp * J;
+  } else {
+    RV = W * (Phi - avg + F.gamma * J);
+    Z = -W * J;
+  }
 }
 
 // Factor table 3 r + j of the product-form b (a select chain: no dynamic
@@ -368,6 +378,26 @@ __device__ __forceinline__ const double *bfac(const double *const *t, int r, int
   for (int s = 1; s < 9; ++s)
     if (i == s) p = t[s];
   return p;
+}
+
+__device__ __forceinline__ const double *sel3p(int a, const double *const *t) {
+  return a == 0 ? t[0] : (a == 1 ? t[1] : t[2]);
+}
+
+// Polynomial diffusion factor at a point of the face normal to a (side e)
+// with tangential Gauss indices qb, qc; 1 unless KP.
+template <bool KP>
+__device__ __forceinline__ double face_kp(const FMesh &M, const FaceGeo &G, int N, int a, int e, int qb,
+                                          int qc) {
+  if constexpr (!KP) {
+    return 1.0;
+  } else {
+    const int b = (a == 0) ? 1 : 0, c = (a == 2) ? 1 : 2;
+    const int ia = seli3(a, G.i0, G.i1, G.i2);
+    const bool wrap = ((M.periodic >> a) & 1) && e && ia + 1 == seli3(a, M.ncell[0], M.ncell[1], M.ncell[2]);
+    return sel3p(a, M.kfn)[face_node(ia, e, wrap)] * sel3p(b, M.kf)[seli3(b, G.i0, G.i1, G.i2) * N + qb] *
+           sel3p(c, M.kf)[seli3(c, G.i0, G.i1, G.i2) * N + qc];
+  }
 }
 
 // b_a at a point of the face normal to a (side e) with tangential Gauss
@@ -409,7 +439,7 @@ __device__ __forceinline__ int cell_of_logical(int L, const FMesh &M) {
   return i1 + N1 * (i2 + N2 * i3);
 }
 
-template <int N, typename T, bool HEUN, bool BP>
+template <int N, typename T, bool HEUN, bool BP, bool KP>
 __global__ __launch_bounds__(FCfg<N>::THREADS)
 __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_kernel(
     const T *__restrict__ x, T *__restrict__ y, FMesh M) {
@@ -741,14 +771,23 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
       bh[r] = bz[r] ? T(0) : T(M.bvol[r][ia * N + qa] * ihd[r]);
       bzt[r] = M.bvol[r] + G.i2 * N;
     }
+    // polynomial diffusion factor kp(q1, q2, q3) = (lane factor) * kf_2(q3)
+    const T kpl = KP ? T(M.kf[0][G.i0 * N + alpha] * M.kf[1][G.i1 * N + beta]) : T(1);
     auto flux = [&](T u, T g0, T g1, T g2, int q3, T W, T &x0, T &x1, T &x2, T &x3) {
       const T b0 = BP ? bh[0] * T(M.bf[2][o2 + q3]) : (bz[0] ? T(bzt[0][q3]) * ih0 : bh[0]);
       const T b1 = BP ? bh[1] * T(M.bf[5][o2 + q3]) : (bz[1] ? T(bzt[1][q3]) * ih1 : bh[1]);
       const T b2 = BP ? bh[2] * T(M.bf[8][o2 + q3]) : (bz[2] ? T(bzt[2][q3]) * ih2 : bh[2]);
       x0 = W * cc * u;
-      x1 = W * (Kh[0] * g0 + Kh[1] * g1 + Kh[2] * g2 - b0 * u);
-      x2 = W * (Kh[3] * g0 + Kh[4] * g1 + Kh[5] * g2 - b1 * u);
-      x3 = W * (Kh[6] * g0 + Kh[7] * g1 + Kh[8] * g2 - b2 * u);
+      if constexpr (KP) {
+        const T kq = kpl * T(M.kf[2][o2 + q3]);
+        x1 = W * (kq * (Kh[0] * g0 + Kh[1] * g1 + Kh[2] * g2) - b0 * u);
+        x2 = W * (kq * (Kh[3] * g0 + Kh[4] * g1 + Kh[5] * g2) - b1 * u);
+        x3 = W * (kq * (Kh[6] * g0 + Kh[7] * g1 + Kh[8] * g2) - b2 * u);
+      } else {
+        x1 = W * (Kh[0] * g0 + Kh[1] * g1 + Kh[2] * g2 - b0 * u);
+        x2 = W * (Kh[3] * g0 + Kh[4] * g1 + Kh[5] * g2 - b1 * u);
+        x3 = W * (Kh[6] * g0 + Kh[7] * g1 + Kh[8] * g2 - b2 * u);
+      }
     };
 #pragma unroll
     for (int h = 0; h < H2; ++h) {
@@ -827,7 +866,7 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
       const double un = R[ZN_OFF + (2 * e + 0) * NN + p];
       const double ba = face_b<BP>(M, G, N, 2, e, alpha, beta);
       double Z;
-      face_flux(F, double(u[e]), un, avg, ba, wab, RV[e], Z);
+      face_flux<KP>(F, double(u[e]), un, avg, ba, wab, RV[e], Z, face_kp<KP>(M, G, N, 2, e, alpha, beta));
       Za[e] = F.cTa * Z;
       Zb[e] = F.cTb * Z;
       Zc[e] = F.cTc * Z;
@@ -915,10 +954,10 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
         }
         const double W = wp * Wt[h];
         double RVa, Za, RVm, Zm;
-        face_flux(F, double(Eo + Oo), double(En + On), double(Ea + Oa), face_b<BP>(M, G, N, a, e, pi, h), W,
-                  RVa, Za);
-        face_flux(F, double(Eo - Oo), double(En - On), double(Ea - Oa), face_b<BP>(M, G, N, a, e, pi, N - 1 - h),
-                  W, RVm, Zm);
+        face_flux<KP>(F, double(Eo + Oo), double(En + On), double(Ea + Oa), face_b<BP>(M, G, N, a, e, pi, h), W,
+                      RVa, Za, face_kp<KP>(M, G, N, a, e, pi, h));
+        face_flux<KP>(F, double(Eo - Oo), double(En - On), double(Ea - Oa),
+                      face_b<BP>(M, G, N, a, e, pi, N - 1 - h), W, RVm, Zm, face_kp<KP>(M, G, N, a, e, pi, N - 1 - h));
         const T sr = T(RVa + RVm), dr = T(RVa - RVm), sz = T(Za + Zm), dz = T(Za - Zm);
 #pragma unroll
         for (int j = 0; j < N; ++j) {
@@ -937,7 +976,8 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
           av = fma(V[m * N + t], A1[t], av);
         }
         double RVm, Zm;
-        face_flux(F, double(uo), double(un), double(av), face_b<BP>(M, G, N, a, e, pi, m), wp * Wt[m], RVm, Zm);
+        face_flux<KP>(F, double(uo), double(un), double(av), face_b<BP>(M, G, N, a, e, pi, m), wp * Wt[m], RVm, Zm,
+                      face_kp<KP>(M, G, N, a, e, pi, m));
 #pragma unroll
         for (int j = 0; j < N; j += 2) {
           VR[j] = fma(V[m * N + j], T(RVm), VR[j]);
@@ -1116,7 +1156,7 @@ struct LaneTab {
   static __device__ __forceinline__ double W(int q) { return GLTab<N>::v[TabOff<N>::W + (q < H ? q : N - 1 - q)]; }
 };
 
-template <int N, typename T, bool HEUN, bool BP>
+template <int N, typename T, bool HEUN, bool BP, bool KP>
 __global__ __launch_bounds__(256) void apply_lane_kernel(const T *__restrict__ x, T *__restrict__ y, FMesh M) {
   constexpr int NN = N * N, NNN = N * N * N;
   using TB = LaneTab<N, T>;
@@ -1188,9 +1228,17 @@ __global__ __launch_bounds__(256) void apply_lane_kernel(const T *__restrict__ x
           }
           const T W = T(TB::W(q1) * TB::W(q2) * TB::W(q3) * vol);
           const T f0 = W * cc * u;
-          const T f1 = W * (Kh[0] * g1 + Kh[1] * g2 + Kh[2] * g3 - bh[0] * u);
-          const T f2 = W * (Kh[3] * g1 + Kh[4] * g2 + Kh[5] * g3 - bh[1] * u);
-          const T f3 = W * (Kh[6] * g1 + Kh[7] * g2 + Kh[8] * g3 - bh[2] * u);
+          T f1, f2, f3;
+          if constexpr (KP) {
+            const T kq = T(M.kf[0][ic[0] * N + q1] * M.kf[1][ic[1] * N + q2] * M.kf[2][ic[2] * N + q3]);
+            f1 = W * (kq * (Kh[0] * g1 + Kh[1] * g2 + Kh[2] * g3) - bh[0] * u);
+            f2 = W * (kq * (Kh[3] * g1 + Kh[4] * g2 + Kh[5] * g3) - bh[1] * u);
+            f3 = W * (kq * (Kh[6] * g1 + Kh[7] * g2 + Kh[8] * g3) - bh[2] * u);
+          } else {
+            f1 = W * (Kh[0] * g1 + Kh[1] * g2 + Kh[2] * g3 - bh[0] * u);
+            f2 = W * (Kh[3] * g1 + Kh[4] * g2 + Kh[5] * g3 - bh[1] * u);
+            f3 = W * (Kh[6] * g1 + Kh[7] * g2 + Kh[8] * g3 - bh[2] * u);
+          }
 #pragma unroll
           for (int j3 = 0; j3 < N; ++j3)
 #pragma unroll
@@ -1276,7 +1324,8 @@ __global__ __launch_bounds__(256) void apply_lane_kernel(const T *__restrict__ x
                            F.cNa * double(gan) + F.cNb * double(gbn) + F.cNc * double(gcn);
         const double W = TB::W(qb) * TB::W(qc) * hb * hc;
         double RV, Z;
-        face_flux(F, double(uo), double(un), avg, face_b<BP>(M, G, N, a, e, qb, qc), W, RV, Z);
+        face_flux<KP>(F, double(uo), double(un), avg, face_b<BP>(M, G, N, a, e, qb, qc), W, RV, Z,
+                      face_kp<KP>(M, G, N, a, e, qb, qc));
         const T rv = T(RV), z = T(Z);
 #pragma unroll
         for (int jc = 0; jc < N; ++jc)
@@ -1315,7 +1364,7 @@ __global__ __launch_bounds__(256) void apply_lane_kernel(const T *__restrict__ x
   }
 }
 
-template <int N, typename T, bool HEUN, bool BP>
+template <int N, typename T, bool HEUN, bool BP, bool KP>
 static hipError_t launch_fused_n(const dg_handle *h, const T *x, T *y, hipStream_t s, const double *f = nullptr,
                                  double dt = 0.0, int stage = 0) {
   using C = FCfg<N>;
@@ -1330,6 +1379,10 @@ static hipError_t launch_fused_n(const dg_handle *h, const T *x, T *y, hipStream
   for (int t = 0; t < 9; ++t) {
     M.bf[t] = h->mesh.bf[t];
     M.bfn[t] = h->mesh.bfn[t];
+  }
+  for (int j = 0; j < 3; ++j) {
+    M.kf[j] = h->mesh.kf[j];
+    M.kfn[j] = h->mesh.kfn[j];
   }
   M.kappa = h->mesh.kappa;
   M.w = h->mesh.w;
@@ -1347,39 +1400,42 @@ static hipError_t launch_fused_n(const dg_handle *h, const T *x, T *y, hipStream
   if (N == 2) {  // k = 1: one cell per lane
     const int nblocks = int((h->ncells + 255) / 256);
     M.groups = (nblocks + 7) / 8;
-    hipLaunchKernelGGL((apply_lane_kernel<2, T, HEUN, BP>), dim3(unsigned(8 * M.groups)), dim3(256), 0, s, x, y, M);
+    hipLaunchKernelGGL((apply_lane_kernel<2, T, HEUN, BP, KP>), dim3(unsigned(8 * M.groups)), dim3(256), 0, s, x, y, M);
     return hipGetLastError();
   }
   const int nblocks = int((h->ncells + C::CPB - 1) / C::CPB);
   M.groups = (nblocks + 7) / 8;
-  hipLaunchKernelGGL((apply_fused_kernel<N, T, HEUN, BP>), dim3(unsigned(8 * M.groups)), dim3(C::THREADS), 0, s,
+  hipLaunchKernelGGL((apply_fused_kernel<N, T, HEUN, BP, KP>), dim3(unsigned(8 * M.groups)), dim3(C::THREADS), 0, s,
                      x, y, M);
   return hipGetLastError();
 }
 
-template <typename T, bool HEUN, bool BP>
+template <typename T, bool HEUN, bool BP, bool KP>
 static hipError_t launch_fused_bp(const dg_handle *h, const T *x, T *y, hipStream_t s, const double *f, double dt,
                                   int stage) {
   switch (h->k + 1) {
-    case 2: return launch_fused_n<2, T, HEUN, BP>(h, x, y, s, f, dt, stage);
-    case 3: return launch_fused_n<3, T, HEUN, BP>(h, x, y, s, f, dt, stage);
-    case 4: return launch_fused_n<4, T, HEUN, BP>(h, x, y, s, f, dt, stage);
-    case 5: return launch_fused_n<5, T, HEUN, BP>(h, x, y, s, f, dt, stage);
-    case 6: return launch_fused_n<6, T, HEUN, BP>(h, x, y, s, f, dt, stage);
-    case 7: return launch_fused_n<7, T, HEUN, BP>(h, x, y, s, f, dt, stage);
-    case 8: return launch_fused_n<8, T, HEUN, BP>(h, x, y, s, f, dt, stage);
-    case 9: return launch_fused_n<9, T, HEUN, BP>(h, x, y, s, f, dt, stage);
-    case 10: return launch_fused_n<10, T, HEUN, BP>(h, x, y, s, f, dt, stage);
-    case 11: return launch_fused_n<11, T, HEUN, BP>(h, x, y, s, f, dt, stage);
+    case 2: return launch_fused_n<2, T, HEUN, BP, KP>(h, x, y, s, f, dt, stage);
+    case 3: return launch_fused_n<3, T, HEUN, BP, KP>(h, x, y, s, f, dt, stage);
+    case 4: return launch_fused_n<4, T, HEUN, BP, KP>(h, x, y, s, f, dt, stage);
+    case 5: return launch_fused_n<5, T, HEUN, BP, KP>(h, x, y, s, f, dt, stage);
+    case 6: return launch_fused_n<6, T, HEUN, BP, KP>(h, x, y, s, f, dt, stage);
+    case 7: return launch_fused_n<7, T, HEUN, BP, KP>(h, x, y, s, f, dt, stage);
+    case 8: return launch_fused_n<8, T, HEUN, BP, KP>(h, x, y, s, f, dt, stage);
+    case 9: return launch_fused_n<9, T, HEUN, BP, KP>(h, x, y, s, f, dt, stage);
+    case 10: return launch_fused_n<10, T, HEUN, BP, KP>(h, x, y, s, f, dt, stage);
+    case 11: return launch_fused_n<11, T, HEUN, BP, KP>(h, x, y, s, f, dt, stage);
     default: return hipErrorInvalidValue;
   }
 }
 
+// Coefficient variants: the sum-form b (the benchmarked kernels), tabulated
+// product-form b, and tabulated b with the polynomial diffusion factor.
 template <typename T, bool HEUN>
 static hipError_t launch_fused(const dg_handle *h, const T *x, T *y, hipStream_t s, const double *f = nullptr,
                                double dt = 0.0, int stage = 0) {
-  return h->mesh.bprod ? launch_fused_bp<T, HEUN, true>(h, x, y, s, f, dt, stage)
-                       : launch_fused_bp<T, HEUN, false>(h, x, y, s, f, dt, stage);
+  if (h->mesh.kpoly) return launch_fused_bp<T, HEUN, true, true>(h, x, y, s, f, dt, stage);
+  return h->mesh.bprod ? launch_fused_bp<T, HEUN, true, false>(h, x, y, s, f, dt, stage)
+                       : launch_fused_bp<T, HEUN, false, false>(h, x, y, s, f, dt, stage);
 }
 
 hipError_t launch_apply_fused_f64(const dg_handle *h, const double *x, double *y, hipStream_t s) {

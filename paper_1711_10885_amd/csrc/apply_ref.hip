@@ -28,9 +28,10 @@ struct RefMesh {
   int periodic;  // bit a: axis a is periodic
   const double *h[3], *bvol[3], *bnode[3], *kappa;
   const double *bf[9], *bfn[9];  // product-form factors (bprod)
+  const double *kf[3], *kfn[3];  // polynomial diffusion factor (kpoly)
   double K[9], c, sigma;
   int b_axis[3];
-  int bprod;
+  int bprod, kpoly;
 };
 
 constexpr int kRefThreads = 256;
@@ -119,7 +120,9 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
       const double br = M.bprod ? M.bf[3 * r][ic[0] * N + q1] * M.bf[3 * r + 1][ic[1] * N + q2] *
                                       M.bf[3 * r + 2][ic[2] * N + q3]
                                 : M.bvol[r][ic[ax] * N + qq[ax]];
-      Fr[r] = kap * (M.K[3 * r] * g[0] + M.K[3 * r + 1] * g[1] + M.K[3 * r + 2] * g[2]) - br * u;
+      const double kx = M.kpoly ? kap * M.kf[0][ic[0] * N + q1] * M.kf[1][ic[1] * N + q2] * M.kf[2][ic[2] * N + q3]
+                                : kap;
+      Fr[r] = kx * (M.K[3 * r] * g[0] + M.K[3 * r + 1] * g[1] + M.K[3 * r + 2] * g[2]) - br * u;
     }
     B0[i] = W * M.c * u;
     B1[i] = W * Fr[0] / h[0];
@@ -228,8 +231,12 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
         const double bout = sgn * ba;
         const double Phi = bout >= 0.0 ? bout * uo[i] : bout * un[i];
         const double W = sw[qb] * sw[qc] * area;
-        const double RV = W * (Phi - avg + gamma * J);
-        const double RT = -W * wT * kap * J * sgn;  // times (K grad phi)_a
+        // pointwise diffusion factor: scales the average, penalty and symmetry terms
+        const double kp = M.kpoly ? M.kfn[a][face_node(ic[a], e, nb.wrap)] * M.kf[b][ic[b] * N + qb] *
+                                        M.kf[c][ic[c] * N + qc]
+                                  : 1.0;
+        const double RV = W * (Phi - kp * avg + kp * gamma * J);
+        const double RT = -W * wT * kap * kp * J * sgn;  // times (K grad phi)_a
         S0[i] = RV;
         S1[i] = RT * Kab / h[b];
         S2[i] = RT * Kac / h[c];
@@ -284,6 +291,11 @@ static hipError_t launch_ref_n(const dg_handle *h, const double *x, double *y, h
     M.bfn[t] = h->mesh.bfn[t];
   }
   M.bprod = h->mesh.bprod;
+  M.kpoly = h->mesh.kpoly;
+  for (int j = 0; j < 3; ++j) {
+    M.kf[j] = h->mesh.kf[j];
+    M.kfn[j] = h->mesh.kfn[j];
+  }
   M.kappa = h->mesh.kappa;
   M.periodic = h->mesh.periodic;
   for (int i = 0; i < 9; ++i) M.K[i] = h->mesh.K[i];

@@ -410,7 +410,7 @@ static void cell_classes(const dg_problem *p, std::vector<int32_t> &cls, std::ve
   cls.resize(size_t(ncells));
   rep.clear();
   std::unordered_map<std::string, int32_t> ids;
-  double key[19];
+  double key[22];
   const int periodic = (p->flags >> 2) & 7;
   for (int64_t c = 0; c < ncells; ++c) {
     const int i[3] = {int(c % n1), int((c / n1) % n2), int(c / stride[2])};
@@ -430,6 +430,11 @@ static void cell_classes(const dg_problem *p, std::vector<int32_t> &cls, std::ve
         key[nk++] = nb[a][0].in ? p->kappa[nb[a][0].cell] : -1.0;
         key[nk++] = nb[a][1].in ? p->kappa[nb[a][1].cell] : -1.0;
       }
+    }
+    if (p->flags & DG_KAPPA_POLY) {
+      // a non-constant diffusion factor along axis j: the cell's position along j
+      for (int j = 0; j < 3; ++j)
+        if (p->kappa_poly[3 * j + 1] != 0.0 || p->kappa_poly[3 * j + 2] != 0.0) key[nk++] = p->nodes[j][i[j]];
     }
     if (p->flags & DG_B_PRODUCT) {
       // a non-constant factor along axis j makes b depend on the cell's position along j

@@ -186,9 +186,28 @@ extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
         return set_error(DG_EINVAL, "dg_setup: kappa must be positive and finite");
   const int n = p->k + 1;
   if (ncells > (int64_t(1) << 31) / 2) return set_error(DG_EINVAL, "dg_setup: too many cells");
-  if (p->flags & ~(DG_WITH_BLOCK_JACOBI | DG_PERIODIC_X | DG_PERIODIC_Y | DG_PERIODIC_Z | DG_B_PRODUCT))
+  if (p->flags &
+      ~(DG_WITH_BLOCK_JACOBI | DG_PERIODIC_X | DG_PERIODIC_Y | DG_PERIODIC_Z | DG_B_PRODUCT | DG_KAPPA_POLY))
     return set_error(DG_EINVAL, "dg_setup: unknown flag bits");
   const bool bprod = (p->flags & DG_B_PRODUCT) != 0;
+  const bool kpoly = (p->flags & DG_KAPPA_POLY) != 0;
+  if (kpoly) {
+    for (int t = 0; t < 9; ++t)
+      if (!std::isfinite(p->kappa_poly[t])) return set_error(DG_EINVAL, "dg_setup: kappa_poly must be finite");
+    // every factor positive at the Gauss coordinates and nodes it is used at
+    Tables tq;
+    build_tables(p->k, tq);
+    for (int j = 0; j < 3; ++j) {
+      const double *c = p->kappa_poly + 3 * j;
+      auto g = [&](double s) { return c[0] + c[1] * s + c[2] * s * s; };
+      for (int i = 0; i < p->ncell[j]; ++i) {
+        const double o = p->nodes[j][i], hh = p->nodes[j][i + 1] - p->nodes[j][i];
+        bool ok = g(o) > 0.0 && g(o + hh) > 0.0;
+        for (int q = 0; q <= p->k; ++q) ok = ok && g(o + hh * tq.xi[q]) > 0.0;
+        if (!ok) return set_error(DG_EINVAL, "dg_setup: kappa_poly factors must be positive on the mesh");
+      }
+    }
+  }
   if (bprod)
     for (int t = 0; t < 9; ++t)
       if (!std::isfinite(p->b_freq[t]) || !std::isfinite(p->b_phase[t]) || !std::isfinite(p->b_amp[t / 3]))
@@ -252,12 +271,18 @@ extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
       host.push_back(p->b_const[r] + p->b_sin[r] * std::sin(M_PI * p->nodes[ax][i]));
   }
   // product form: factor f_rj at the Gauss coordinates and nodes of axis j
+  // (with the polynomial diffusion factor a sum-form b is tabulated this way
+  // too: its one non-constant factor on axis b_axis[r], ones elsewhere)
   size_t off_bf[9] = {}, off_bfn[9] = {};
-  if (bprod)
+  const bool btab = bprod || kpoly;
+  if (btab)
     for (int t = 0; t < 9; ++t) {
       const int r = t / 3, j = t % 3;
       const double amp = j == 0 ? p->b_amp[r] : 1.0;
-      auto f = [&](double s) { return p->b_freq[t] == 0.0 ? amp : amp * std::sin(p->b_freq[t] * s + p->b_phase[t]); };
+      auto f = [&](double s) {
+        if (!bprod) return j == p->b_axis[r] ? p->b_const[r] + p->b_sin[r] * std::sin(M_PI * s) : 1.0;
+        return p->b_freq[t] == 0.0 ? amp : amp * std::sin(p->b_freq[t] * s + p->b_phase[t]);
+      };
       off_bf[t] = host.size();
       for (int i = 0; i < p->ncell[j]; ++i) {
         const double o = p->nodes[j][i], hh = p->nodes[j][i + 1] - p->nodes[j][i];
@@ -266,6 +291,21 @@ extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
       off_bfn[t] = host.size();
       for (int i = 0; i <= p->ncell[j]; ++i) host.push_back(f(p->nodes[j][i]));
     }
+  // polynomial diffusion factor kp_j at the Gauss coordinates and nodes of axis j
+  size_t off_kf[3] = {}, off_kfn[3] = {};
+  if (kpoly) {
+    for (int j = 0; j < 3; ++j) {
+      const double *c = p->kappa_poly + 3 * j;
+      auto g = [&](double s) { return c[0] + c[1] * s + c[2] * s * s; };
+      off_kf[j] = host.size();
+      for (int i = 0; i < p->ncell[j]; ++i) {
+        const double o = p->nodes[j][i], hh = p->nodes[j][i + 1] - p->nodes[j][i];
+        for (int q = 0; q < m; ++q) host.push_back(g(o + hh * h->tab.xi[q]));
+      }
+      off_kfn[j] = host.size();
+      for (int i = 0; i <= p->ncell[j]; ++i) host.push_back(g(p->nodes[j][i]));
+    }
+  }
   const size_t off_w = host.size();
   host.insert(host.end(), h->tab.w, h->tab.w + m);
   if (p->kappa) {
@@ -293,10 +333,15 @@ extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
     M.b_axis[a] = p->b_axis[a];
   }
   for (int t = 0; t < 9; ++t) {
-    M.bf[t] = bprod ? base + off_bf[t] : nullptr;
-    M.bfn[t] = bprod ? base + off_bfn[t] : nullptr;
+    M.bf[t] = btab ? base + off_bf[t] : nullptr;
+    M.bfn[t] = btab ? base + off_bfn[t] : nullptr;
   }
-  M.bprod = bprod ? 1 : 0;
+  M.bprod = btab ? 1 : 0;
+  for (int j = 0; j < 3; ++j) {
+    M.kf[j] = kpoly ? base + off_kf[j] : nullptr;
+    M.kfn[j] = kpoly ? base + off_kfn[j] : nullptr;
+  }
+  M.kpoly = kpoly ? 1 : 0;
   M.kappa = p->kappa ? base + off_kappa : nullptr;
   M.periodic = periodic;
   M.w = base + off_w;

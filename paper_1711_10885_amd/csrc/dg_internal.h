@@ -42,6 +42,12 @@ struct DevMesh {
   double *bf[9];
   double *bfn[9];
   int bprod;
+  // polynomial diffusion factor (DG_KAPPA_POLY; else null): kp_j at the
+  // Gauss coordinates [ncell[j] * m] and nodes [ncell[j] + 1] of axis j.
+  // With it the b tables above are filled (product form) whatever form b has.
+  double *kf[3];
+  double *kfn[3];
+  int kpoly;
   double *kappa;      // per cell or nullptr (= 1)
   int periodic;       // bit a: axis a is periodic (DG_PERIODIC_*)
   double *w;          // Gauss weights on [0,1] (for lane-dependent lookups)

@@ -66,7 +66,7 @@ def _struct(prob, **over):
     (dict(K=np.array([[1, 0.5, 0], [0, 1, 0], [0, 0, 1.0]])), "symmetric"),
     (dict(b_axis0=3), "b_axis"),
     (dict(c=float("nan")), "c must be finite"),
-    (dict(flags=64), "unknown flag"),
+    (dict(flags=128), "unknown flag"),
     (dict(k=8, flags=2), "block Jacobi supports"),
 ])
 def test_setup_rejects_invalid_problems(over, msg):
@@ -99,6 +99,19 @@ def test_setup_rejects_a_non_finite_product_field():
     h = ctypes.c_void_p()
     assert lib.dg_setup(ctypes.byref(s), ctypes.byref(h)) == binding.DG_EINVAL
     assert "product-form b" in lib.dg_last_error().decode()
+    assert not h.value
+
+
+@pytest.mark.parametrize("coef,msg", [((0.5, 0.0, -1.0), "positive on the mesh"), ((1.0, float("nan"), 0.0), "finite")])
+def test_setup_rejects_a_bad_kappa_polynomial(coef, msg):
+    """kp_2(s) = 0.5 - s^2 vanishes inside [0, 1]; a NaN coefficient is not finite."""
+    lib = _lib()
+    s, keep = _struct(workloads.poisson_k2_8(), flags=binding.DG_KAPPA_POLY)
+    for t, v in enumerate((1.0, 0.0, 0.0, 1.0, 0.0, 0.0) + coef):
+        s.kappa_poly[t] = v
+    h = ctypes.c_void_p()
+    assert lib.dg_setup(ctypes.byref(s), ctypes.byref(h)) == binding.DG_EINVAL
+    assert msg in lib.dg_last_error().decode()
     assert not h.value
 
 

@@ -209,3 +209,32 @@ def test_product_b_fp32_operator_matches_fp64(k):
     e = np.abs(y - ref).max() / np.abs(ref).max()
     print(f"product b fp32 k={k}: relmax {e:.2e}", flush=True)
     assert e <= 30 * (k + 1) * 2.0 ** -24
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("k", range(1, 11))
+def test_kappa_polynomial_every_degree(variant, k):
+    """Diffusion polynomial in the coordinates, D(x) = kappa_T kp(x) K,
+    evaluated at the quadrature points, with sum-form or product-form b,
+    Dirichlet and periodic axes, both kernels."""
+    ncell = (3, 3, 2) if k <= 5 else (3, 2, 2)
+    per = PERIODIC[(k + 1) % 4]
+    p = W.random_problem(1700 + k, ncell=ncell, k=k, b="sine" if k % 2 else "product", periodic=per)
+    p = p.with_(kappa_poly=W.random_kappa_poly(np.random.default_rng(1710 + k)))
+    x = W.random_vector(p.ndof, 1720 + k)
+    _check(_gpu_apply(p, x, variant), oracle.apply(p, x), f"kappa poly {per} k={k} {ncell} v{variant}")
+
+
+@pytest.mark.parametrize("k", [2, 5, 7])
+def test_kappa_polynomial_fp32_operator_matches_fp64(k):
+    torch = _torch()
+    from paper_1711_10885_amd import binding
+    p = W.random_problem(1730 + k, ncell=(3, 2, 3), k=k, b="const", periodic=(False, True, False))
+    p = p.with_(kappa_poly=W.random_kappa_poly(np.random.default_rng(1740 + k)))
+    x = W.random_vector(p.ndof, 1750 + k)
+    ref = oracle.apply(p, x)
+    with binding.DG(p) as dg:
+        y = dg.apply_f32(torch.from_numpy(x).float().cuda()).double().cpu().numpy()
+    e = np.abs(y - ref).max() / np.abs(ref).max()
+    print(f"kappa poly fp32 k={k}: relmax {e:.2e}", flush=True)
+    assert e <= 30 * (k + 1) * 2.0 ** -24

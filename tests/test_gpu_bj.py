@@ -255,3 +255,20 @@ def test_taylor_green_blocks_one_per_cell():
         assert dg.bj_nblocks() == p.ncells
         z = dg.precond_apply(torch.from_numpy(r).cuda()).cpu().numpy()
     _check_blocks(oracle.block_diagonal(p), r, z, "taylor-green blocks")
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_shared_blocks_with_a_kappa_polynomial(k):
+    """A diffusion factor varying along axis 2 only, constant b, uniform
+    periodic mesh: classes keyed by the position along axis 2 (4 classes);
+    every cell checked against its own oracle block."""
+    torch = _torch()
+    from paper_1711_10885_amd import binding
+    N = 4
+    p = W.mixed_k5_48(N=N, k=k).with_(periodic=(True, True, True),
+                                        kappa_poly=(1.0, 0.0, 0.0, 0.7, 0.5, 0.6, 1.0, 0.0, 0.0))
+    r = W.random_vector(p.ndof, 600 + k)
+    with binding.DG(p, flags=binding.DG_WITH_BLOCK_JACOBI) as dg:
+        assert dg.bj_nblocks() == N
+        z = dg.precond_apply(torch.from_numpy(r).cuda()).cpu().numpy()
+    _check_blocks(oracle.block_diagonal(p), r, z, f"kappa poly shared k={k}")

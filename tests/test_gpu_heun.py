@@ -185,6 +185,15 @@ def test_taylor_green_mass_is_conserved():
     assert np.abs(u - u0).max() > 1e-3
 
 
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_heun_with_a_kappa_polynomial(variant):
+    p = _mild(W.random_problem(1320, ncell=(3, 2, 2), k=4, b="product", periodic=(True, True, False)))
+    p = p.with_(kappa_poly=W.random_kappa_poly(np.random.default_rng(1321)))
+    u0 = W.random_vector(p.ndof, 1322)
+    dt, n = _dt(p), 4
+    _check(_gpu_heun(p, u0, dt, n, variant), oracle.heun(p, u0, dt, n), u0, f"kappa poly heun v{variant}")
+
+
 @pytest.mark.parametrize("case", ["dt0", "dtnan", "dtneg", "nsteps", "overlap"])
 def test_invalid_arguments(case):
     torch = _torch()
