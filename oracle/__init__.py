@@ -70,6 +70,7 @@ class _Problem(ctypes.Structure):
         ("b_phase", ctypes.c_double * 9),
         ("kappa_poly_on", ctypes.c_int32),
         ("kappa_poly", ctypes.c_double * 9),
+        ("quad_extra", ctypes.c_int32),
     ]
 
 
@@ -141,6 +142,7 @@ class _Marshalled:
         if kpoly is not None:
             for t in range(9):
                 s.kappa_poly[t] = float(kpoly[t])
+        s.quad_extra = int(getattr(prob, "quad_extra", 0))
         self.struct = s
 
 

@@ -37,6 +37,9 @@
  *    b_r(x) = b_amp[r] * prod_j sin(b_freq[3r+j] x_j + b_phase[3r+j]) (factors
  *    with b_freq == 0 are 1), which holds the Taylor-Green field of Sec. 5.4
  *    (eq. (2) of that section); b is evaluated at each quadrature point;
+ *  - every integral uses the tensor Gauss rule with m = k + 1 + quad_extra
+ *    points per direction (quad_extra = 2 is the raised rule q = 2p + 4 of
+ *    Problem B, Sec. 5.1; 0 the rule of Problem A);
  *  - with or_problem.kappa_poly_on the diffusion tensor is
  *    D(x) = kappa_T kp(x) K, kp(x) = prod_j (c_j0 + c_j1 x_j + c_j2 x_j^2)
  *    with c_ji = kappa_poly[3j+i] (coefficients polynomial in the
@@ -71,6 +74,7 @@ typedef struct {
   double b_phase[9];
   int32_t kappa_poly_on; /* 1: D(x) = kappa_T kp(x) K, kp from kappa_poly */
   double kappa_poly[9];
+  int32_t quad_extra;    /* Gauss points per direction m = k + 1 + quad_extra */
 } or_problem;
 
 /* term mask for or_apply: which sums of eq. (blf) to include */
@@ -147,9 +151,9 @@ typedef struct {
   double D0[OR_MAXN], D1[OR_MAXN]; /* theta_j'(0), theta_j'(1) */
 } or_tables;
 
-static void make_tables(int k, or_tables *t) {
+static void make_tables(int k, int extra, or_tables *t) {
   t->n = k + 1;
-  t->m = k + 1;
+  t->m = k + 1 + extra;
   oracle_gauss(t->m, t->xi, t->w);
   for (int q = 0; q < t->m; ++q) oracle_basis(k, t->xi[q], t->V[q], t->D[q]);
   oracle_basis(k, 0.0, t->V0, t->D0);
@@ -405,6 +409,7 @@ static void boundary_face(const or_problem *p, const or_tables *t, int a, int e,
 
 static int check_problem(const or_problem *p) {
   if (!p || p->k < 1 || p->k > 10) return -1;
+  if (p->quad_extra < 0 || p->k + 1 + p->quad_extra > OR_MAXN) return -1;
   for (int a = 0; a < 3; ++a) {
     if (p->ncell[a] < 1 || !p->nodes[a]) return -1;
     if (p->b_axis[a] < 0 || p->b_axis[a] > 2) return -1;
@@ -426,7 +431,7 @@ int64_t oracle_ndof(const or_problem *p) {
 int oracle_apply(const or_problem *p, const double *x, double *y, int terms, int nthreads) {
   if (check_problem(p)) return -1;
   or_tables t;
-  make_tables(p->k, &t);
+  make_tables(p->k, p->quad_extra, &t);
   const int64_t nb = (int64_t)t.n * t.n * t.n;
   const int N1 = p->ncell[0], N2 = p->ncell[1], N3 = p->ncell[2];
   const int64_t ncells = (int64_t)N1 * N2 * N3;
@@ -482,7 +487,7 @@ int oracle_apply_rows(const or_problem *p, const double *x, const int64_t *cells
                       double *y_rows, int terms, int nthreads) {
   if (check_problem(p)) return -1;
   or_tables t;
-  make_tables(p->k, &t);
+  make_tables(p->k, p->quad_extra, &t);
   const int64_t nb = (int64_t)t.n * t.n * t.n;
   const int N1 = p->ncell[0], N2 = p->ncell[1], N3 = p->ncell[2];
   const int64_t ncells = (int64_t)N1 * N2 * N3;
@@ -543,7 +548,7 @@ int oracle_rhs(const or_problem *p, int nterms, const double *alpha, const int32
                double *f, int nthreads) {
   if (check_problem(p)) return -1;
   or_tables t;
-  make_tables(p->k, &t);
+  make_tables(p->k, p->quad_extra, &t);
   const int n = t.n, m = t.m;
   const int64_t nb = (int64_t)n * n * n;
   const int N1 = p->ncell[0], N2 = p->ncell[1], N3 = p->ncell[2];

@@ -57,6 +57,8 @@ class Problem:
     # polynomial diffusion factor: D(x) = kappa_T kp(x) K with
     # kp(x) = prod_j (c[3j] + c[3j+1] x_j + c[3j+2] x_j^2), c = kappa_poly (None: kp = 1)
     kappa_poly: tuple | None = None
+    # Gauss points per direction m = k + 1 + quad_extra (2: the raised rule q = 2p + 4)
+    quad_extra: int = 0
     name: str = ""
     meta: dict = field(default_factory=dict)
 

@@ -77,7 +77,7 @@ def assemble_dense(prob) -> np.ndarray:
     N = prob.ncell
     nc = N[0] * N[1] * N[2]
     A = np.zeros((nc * nb, nc * nb))
-    xi, w = _gauss01(k + 1)
+    xi, w = _gauss01(k + 1 + int(getattr(prob, "quad_extra", 0)))
     Vq, Dq = _basis_1d(k, xi)
     V0, D0 = _basis_1d(k, np.array([0.0]))
     V1, D1 = _basis_1d(k, np.array([1.0]))

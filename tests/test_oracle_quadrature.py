@@ -1,0 +1,54 @@
+"""Pins of the oracle's raised quadrature (m = k + 1 + extra Gauss points per
+direction; extra = 2 is the rule q = 2p + 4 of Problem B, Sec. 5.1), CPU only.
+
+* the numpy brute-force assembly with the same rule agrees (pointwise
+  coefficients, periodic axes);
+* Gauss exactness: with coefficients constant per cell every integrand is a
+  polynomial of degree <= 2k per direction, so k+1, k+2 and k+3 points give
+  the same operator; with the quadratic diffusion factor the degree is 2k + 2,
+  so k+2 and k+3 points agree and k+1 points do not.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1711_10885_amd import workloads as W
+from tests.ref_assemble import assemble_dense
+
+
+@pytest.mark.parametrize("b,per,k,kp", [
+    ("product", (True, False, True), 1, True),
+    ("sine", (False, False, False), 2, True),
+    ("const", (True, True, True), 2, False),
+])
+def test_assemble_matches_brute_force(b, per, k, kp):
+    p = W.random_problem(1800 + k, ncell=(2, 3, 2), k=k, b=b, periodic=per).with_(quad_extra=2)
+    if kp:
+        p = p.with_(kappa_poly=W.random_kappa_poly(np.random.default_rng(1810 + k)))
+    A = oracle.assemble(p).toarray()
+    ref = assemble_dense(p)
+    err = np.abs(A - ref).max() / np.abs(ref).max()
+    print(f"quad +2 {b} per={per} k={k} kp={kp}: max rel {err:.2e}")
+    assert err <= 1e-13
+
+
+@pytest.mark.parametrize("k", [1, 3, 5])
+def test_cellwise_constant_coefficients_are_integrated_exactly(k):
+    p = W.random_problem(1820 + k, ncell=(3, 2, 2), k=k, b="const", periodic=(True, False, False))
+    x = W.random_vector(p.ndof, 1830 + k)
+    y0 = oracle.apply(p, x)
+    for extra in (1, 2):
+        y = oracle.apply(p.with_(quad_extra=extra), x)
+        assert np.abs(y - y0).max() <= 1e-12 * np.abs(y0).max(), extra
+
+
+@pytest.mark.parametrize("k", [1, 2, 4])
+def test_quadratic_diffusion_needs_one_more_point(k):
+    p = W.random_problem(1840 + k, ncell=(2, 2, 3), k=k, b="const", periodic=(False, True, False))
+    p = p.with_(kappa_poly=W.random_kappa_poly(np.random.default_rng(1850 + k)))
+    x = W.random_vector(p.ndof, 1860 + k)
+    y1 = oracle.apply(p.with_(quad_extra=1), x)
+    y2 = oracle.apply(p.with_(quad_extra=2), x)
+    y0 = oracle.apply(p, x)
+    assert np.abs(y2 - y1).max() <= 1e-12 * np.abs(y1).max()
+    assert np.abs(y0 - y1).max() > 1e-8 * np.abs(y1).max()
