@@ -117,6 +117,13 @@ typedef enum {
  *              continuous, so the weights reduce to those of kappa_T and
  *              gamma_F scales by kp).  Every factor must be positive at every
  *              Gauss coordinate and node of its axis: DG_EINVAL otherwise.
+ *   quad_extra 0: the (k+1)-point Gauss rule per direction (q = 2p, Problem A
+ *              of Sec. 5.1); 2: the raised rule with k+3 points (q = 2p + 4,
+ *              Problem B), for k <= 8.  Every integral of the operator uses
+ *              the rule (the load vector keeps k+1 points).  With 2 the
+ *              operator runs on the reference-layout kernel (one workgroup
+ *              per cell, rectangular (k+3) x (k+1) contractions through LDS);
+ *              dg_apply_f32 and GMRES-IR return DG_EINVAL.
  */
 typedef struct {
   int32_t ncell[3];
@@ -134,6 +141,7 @@ typedef struct {
   double b_freq[9];
   double b_phase[9];
   double kappa_poly[9];  /* polynomial diffusion factor (DG_KAPPA_POLY only) */
+  int32_t quad_extra;    /* Gauss points per direction m = k + 1 + quad_extra */
 } dg_problem;
 
 #define DG_WITH_BLOCK_JACOBI 2

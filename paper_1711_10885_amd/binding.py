@@ -57,6 +57,7 @@ class _Problem(ctypes.Structure):
         ("b_freq", ctypes.c_double * 9),
         ("b_phase", ctypes.c_double * 9),
         ("kappa_poly", ctypes.c_double * 9),
+        ("quad_extra", ctypes.c_int32),
     ]
 
 
@@ -212,6 +213,7 @@ class DG:
             for t in range(9):
                 s.b_freq[t] = float(prob.b_freq[t])
                 s.b_phase[t] = float(prob.b_phase[t])
+        s.quad_extra = int(getattr(prob, "quad_extra", 0))
         kpoly = getattr(prob, "kappa_poly", None)
         if kpoly is not None:
             s.flags |= DG_KAPPA_POLY

@@ -1,7 +1,9 @@
 // Reference-layout FP64 apply kernel: one workgroup per cell, every tensor of
 // the sum factorization staged in LDS, one thread per output entry of each 1D
-// contraction.  Simple and general in k; the tuned kernels are checked against
-// the oracle exactly like this one.
+// contraction.  Simple and general in k and in the number of Gauss points
+// per direction Q (Q = k+1, or k+3 for the raised rule q = 2p + 4 of
+// Problem B, Sec. 5.1, where every 1D contraction is rectangular, Q x (k+1));
+// the tuned kernels are checked against the oracle exactly like this one.
 //
 // Per cell T (owner computes, so no two workgroups write the same entry):
 //  * volume term of eq. (blf), Algorithm 1 steps 1-3: u and grad u at the
@@ -18,9 +20,9 @@
 
 namespace dgmf {
 
-template <int N>
+template <int N, int Q>
 struct RefTab {
-  double V[N][N], D[N][N], w[N], ev[2][N], ed[2][N];
+  double V[Q][N], D[Q][N], w[Q], ev[2][N], ed[2][N];
 };
 
 struct RefMesh {
@@ -36,51 +38,62 @@ struct RefMesh {
 
 constexpr int kRefThreads = 256;
 
-// out[i] (+)= sum_t A(q_i, t) in[i | axis <- t]  on an N^DIM block in LDS,
-// A = M[q][t] (TRANS = false, evaluation) or M[t][q] (TRANS = true,
-// integration against the test functions).
-template <int N, int DIM, bool TRANS>
-__device__ inline void contract(double *out, const double *in, const double (*M)[N], int stride,
-                                const double *in2 = nullptr, const double (*M2)[N] = nullptr,
-                                bool acc = false) {
-  constexpr int NT = (DIM == 3) ? N * N * N : N * N;
+// One 1D contraction along axis ax of a block in LDS with output dimensions
+// (o0, o1, o2) (axis 0 fastest; o2 = 1 for a 2D block) and input length LI
+// along ax (the other input dimensions are those of the output):
+//   out[.., q, ..] (+)= sum_{t < LI} A(q, t) in[.., t, ..],
+// A(q, t) = Mat[q][t] (TRANS = false: evaluation, points from basis
+// coefficients) or Mat[t][q] (TRANS = true: integration against the test
+// functions); an optional second term with in2, Mat2.
+template <int LD, bool TRANS>
+__device__ inline void contract(double *out, const double *in, const double (*Mat)[LD], int ax, int o0, int o1,
+                                int o2, int LI, const double *in2 = nullptr, const double (*Mat2)[LD] = nullptr) {
+  const int od[3] = {o0, o1, o2};
+  int id[3] = {o0, o1, o2};
+  id[ax] = LI;
+  const int is[3] = {1, id[0], id[0] * id[1]};
+  const int NT = o0 * o1 * o2;
   for (int i = threadIdx.x; i < NT; i += kRefThreads) {
-    const int qi = (i / stride) % N;
-    const int base = i - qi * stride;
-    double s = acc ? out[i] : 0.0;
-    for (int t = 0; t < N; ++t) {
-      const double a = TRANS ? M[t][qi] : M[qi][t];
-      s = fma(a, in[base + t * stride], s);
+    const int io[3] = {i % od[0], (i / od[0]) % od[1], i / (od[0] * od[1])};
+    const int q = io[ax];
+    int base = 0;
+    for (int a = 0; a < 3; ++a)
+      if (a != ax) base += io[a] * is[a];
+    const int st = is[ax];
+    double s = 0.0;
+    for (int t = 0; t < LI; ++t) {
+      const double a = TRANS ? Mat[t][q] : Mat[q][t];
+      s = fma(a, in[base + t * st], s);
     }
     if (in2)
-      for (int t = 0; t < N; ++t) {
-        const double a = TRANS ? M2[t][qi] : M2[qi][t];
-        s = fma(a, in2[base + t * stride], s);
+      for (int t = 0; t < LI; ++t) {
+        const double a = TRANS ? Mat2[t][q] : Mat2[q][t];
+        s = fma(a, in2[base + t * st], s);
       }
     out[i] = s;
   }
 }
 
-template <int N>
+template <int N, int Q>
 __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__restrict__ x,
                                                                 double *__restrict__ y,
-                                                                RefMesh M, RefTab<N> T) {
-  constexpr int NB = N * N * N, NF = N * N;
-  __shared__ double sV[N][N], sD[N][N], sw[N], sev[2][N], sed[2][N];
-  __shared__ double X[NB], Y[NB], B0[NB], B1[NB], B2[NB], B3[NB], B4[NB], B5[NB], B6[NB];
-  __shared__ double F[16][NF];
+                                                                RefMesh M, RefTab<N, Q> T) {
+  constexpr int NB = N * N * N, NF = N * N, QB = Q * Q * Q, QF = Q * Q;
+  __shared__ double sV[Q][N], sD[Q][N], sw[Q], sev[2][N], sed[2][N];
+  __shared__ double X[NB], Y[NB], B0[QB], B1[QB], B2[QB], B3[QB], B4[QB], B5[QB], B6[QB];
+  __shared__ double F[16][QF];
   const int tid = threadIdx.x;
   const int cell = blockIdx.x;
   const int N1 = M.ncell[0], N2 = M.ncell[1];
   const int ic[3] = {cell % N1, (cell / N1) % N2, cell / (N1 * N2)};
   const int cstride[3] = {1, N1, N1 * N2};
 
-  for (int i = tid; i < NF; i += kRefThreads) {
+  for (int i = tid; i < Q * N; i += kRefThreads) {
     sV[i / N][i % N] = T.V[i / N][i % N];
     sD[i / N][i % N] = T.D[i / N][i % N];
   }
+  if (tid < Q) sw[tid] = T.w[tid];
   if (tid < N) {
-    sw[tid] = T.w[tid];
     sev[0][tid] = T.ev[0][tid];
     sev[1][tid] = T.ev[1][tid];
     sed[0][tid] = T.ed[0][tid];
@@ -95,21 +108,21 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
   const double vol = h[0] * h[1] * h[2];
 
   // ---------------- volume: forward (u, d1 u, d2 u, d3 u at points) --------
-  contract<N, 3, false>(B0, X, sV, 1);  // V1 x
-  contract<N, 3, false>(B1, X, sD, 1);  // D1 x
+  contract<N, false>(B0, X, sV, 0, Q, N, N, N);  // V1 x
+  contract<N, false>(B1, X, sD, 0, Q, N, N, N);  // D1 x
   __syncthreads();
-  contract<N, 3, false>(B2, B0, sV, N);  // V2 V1 x
-  contract<N, 3, false>(B3, B1, sV, N);  // V2 D1 x
-  contract<N, 3, false>(B4, B0, sD, N);  // D2 V1 x
+  contract<N, false>(B2, B0, sV, 1, Q, Q, N, N);  // V2 V1 x
+  contract<N, false>(B3, B1, sV, 1, Q, Q, N, N);  // V2 D1 x
+  contract<N, false>(B4, B0, sD, 1, Q, Q, N, N);  // D2 V1 x
   __syncthreads();
-  contract<N, 3, false>(B0, B2, sV, NF);  // u
-  contract<N, 3, false>(B1, B3, sV, NF);  // d^1 u (reference)
-  contract<N, 3, false>(B5, B4, sV, NF);  // d^2 u
-  contract<N, 3, false>(B6, B2, sD, NF);  // d^3 u
+  contract<N, false>(B0, B2, sV, 2, Q, Q, Q, N);  // u
+  contract<N, false>(B1, B3, sV, 2, Q, Q, Q, N);  // d^1 u (reference)
+  contract<N, false>(B5, B4, sV, 2, Q, Q, Q, N);  // d^2 u
+  contract<N, false>(B6, B2, sD, 2, Q, Q, Q, N);  // d^3 u
   __syncthreads();
   // ---------------- volume: pointwise flux (eq. (gauss_points)) ------------
-  for (int i = tid; i < NB; i += kRefThreads) {
-    const int q1 = i % N, q2 = (i / N) % N, q3 = i / NF;
+  for (int i = tid; i < QB; i += kRefThreads) {
+    const int q1 = i % Q, q2 = (i / Q) % Q, q3 = i / QF;
     const double u = B0[i];
     const double g[3] = {B1[i] / h[0], B5[i] / h[1], B6[i] / h[2]};
     const int qq[3] = {q1, q2, q3};
@@ -117,10 +130,10 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
     double Fr[3];
     for (int r = 0; r < 3; ++r) {
       const int ax = M.b_axis[r];
-      const double br = M.bprod ? M.bf[3 * r][ic[0] * N + q1] * M.bf[3 * r + 1][ic[1] * N + q2] *
-                                      M.bf[3 * r + 2][ic[2] * N + q3]
-                                : M.bvol[r][ic[ax] * N + qq[ax]];
-      const double kx = M.kpoly ? kap * M.kf[0][ic[0] * N + q1] * M.kf[1][ic[1] * N + q2] * M.kf[2][ic[2] * N + q3]
+      const double br = M.bprod ? M.bf[3 * r][ic[0] * Q + q1] * M.bf[3 * r + 1][ic[1] * Q + q2] *
+                                      M.bf[3 * r + 2][ic[2] * Q + q3]
+                                : M.bvol[r][ic[ax] * Q + qq[ax]];
+      const double kx = M.kpoly ? kap * M.kf[0][ic[0] * Q + q1] * M.kf[1][ic[1] * Q + q2] * M.kf[2][ic[2] * Q + q3]
                                 : kap;
       Fr[r] = kx * (M.K[3 * r] * g[0] + M.K[3 * r + 1] * g[1] + M.K[3 * r + 2] * g[2]) - br * u;
     }
@@ -131,14 +144,14 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
   }
   __syncthreads();
   // ---------------- volume: transposed contractions (eq. (evalblf)) --------
-  contract<N, 3, true>(B2, B0, sV, NF, B6, sD);  // along 3: V^T x0 + D^T x3
-  contract<N, 3, true>(B3, B1, sV, NF);          // V^T x1
-  contract<N, 3, true>(B4, B5, sV, NF);          // V^T x2
+  contract<N, true>(B2, B0, sV, 2, Q, Q, N, Q, B6, sD);  // along 3: V^T x0 + D^T x3
+  contract<N, true>(B3, B1, sV, 2, Q, Q, N, Q);          // V^T x1
+  contract<N, true>(B4, B5, sV, 2, Q, Q, N, Q);          // V^T x2
   __syncthreads();
-  contract<N, 3, true>(B0, B2, sV, N, B4, sD);  // along 2
-  contract<N, 3, true>(B1, B3, sV, N);
+  contract<N, true>(B0, B2, sV, 1, Q, N, N, Q, B4, sD);  // along 2
+  contract<N, true>(B1, B3, sV, 1, Q, N, N, Q);
   __syncthreads();
-  contract<N, 3, true>(Y, B0, sV, 1, B1, sD);  // along 1
+  contract<N, true>(Y, B0, sV, 0, N, N, N, Q, B1, sD);  // along 1
   __syncthreads();
 
   // ---------------- faces --------------------------------------------------
@@ -177,23 +190,23 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
     }
     __syncthreads();
     // tangential evaluation: first b (stride 1 in the 2D grid), then c
-    contract<N, 2, false>(S0, Uo, sV, 1);
-    contract<N, 2, false>(S1, Uo, sD, 1);
-    contract<N, 2, false>(S2, Un, sV, 1);
-    contract<N, 2, false>(S3, Un, sD, 1);
+    contract<N, false>(S0, Uo, sV, 0, Q, N, 1, N);
+    contract<N, false>(S1, Uo, sD, 0, Q, N, 1, N);
+    contract<N, false>(S2, Un, sV, 0, Q, N, 1, N);
+    contract<N, false>(S3, Un, sD, 0, Q, N, 1, N);
     __syncthreads();
-    contract<N, 2, false>(uo, S0, sV, N);
-    contract<N, 2, false>(gbo, S1, sV, N);
-    contract<N, 2, false>(gco, S0, sD, N);
-    contract<N, 2, false>(un, S2, sV, N);
-    contract<N, 2, false>(gbn, S3, sV, N);
-    contract<N, 2, false>(gcn, S2, sD, N);
+    contract<N, false>(uo, S0, sV, 1, Q, Q, 1, N);
+    contract<N, false>(gbo, S1, sV, 1, Q, Q, 1, N);
+    contract<N, false>(gco, S0, sD, 1, Q, Q, 1, N);
+    contract<N, false>(un, S2, sV, 1, Q, Q, 1, N);
+    contract<N, false>(gbn, S3, sV, 1, Q, Q, 1, N);
+    contract<N, false>(gcn, S2, sD, 1, Q, Q, 1, N);
     __syncthreads();
-    contract<N, 2, false>(S0, Do, sV, 1);
-    contract<N, 2, false>(S1, Dn, sV, 1);
+    contract<N, false>(S0, Do, sV, 0, Q, N, 1, N);
+    contract<N, false>(S1, Dn, sV, 0, Q, N, 1, N);
     __syncthreads();
-    contract<N, 2, false>(gao, S0, sV, N);
-    contract<N, 2, false>(gan, S1, sV, N);
+    contract<N, false>(gao, S0, sV, 1, Q, Q, 1, N);
+    contract<N, false>(gan, S1, sV, 1, Q, Q, 1, N);
     __syncthreads();
     // pointwise face terms (Sec. 2.2): upwind flux, weighted average,
     // penalty, written with the outer normal n_T = sgn e_a of cell T
@@ -209,8 +222,8 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
                                     : M.sigma * dT / h[a];
       const double area = h[b] * h[c];
       const double Kab = M.K[3 * a + b], Kac = M.K[3 * a + c];
-      for (int i = tid; i < NF; i += kRefThreads) {
-        const int qb = i % N, qc = i / N;
+      for (int i = tid; i < QF; i += kRefThreads) {
+        const int qb = i % Q, qc = i / Q;
         // normal flux component (K grad u)_a of own / neighbour traces
         const double KgT = Kaa * gao[i] / h[a] + Kab * gbo[i] / h[b] + Kac * gco[i] / h[c];
         const double KgN = Kaa * gan[i] / hn + Kab * gbn[i] / h[b] + Kac * gcn[i] / h[c];
@@ -220,20 +233,20 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
         const int ax = M.b_axis[a];
         double ba;
         if (M.bprod)
-          ba = M.bfn[3 * a + a][face_node(ic[a], e, nb.wrap)] * M.bf[3 * a + b][ic[b] * N + qb] *
-               M.bf[3 * a + c][ic[c] * N + qc];
+          ba = M.bfn[3 * a + a][face_node(ic[a], e, nb.wrap)] * M.bf[3 * a + b][ic[b] * Q + qb] *
+               M.bf[3 * a + c][ic[c] * Q + qc];
         else if (ax == a)
           ba = M.bnode[a][face_node(ic[a], e, nb.wrap)];
         else if (ax == b)
-          ba = M.bvol[a][ic[b] * N + qb];
+          ba = M.bvol[a][ic[b] * Q + qb];
         else
-          ba = M.bvol[a][ic[c] * N + qc];
+          ba = M.bvol[a][ic[c] * Q + qc];
         const double bout = sgn * ba;
         const double Phi = bout >= 0.0 ? bout * uo[i] : bout * un[i];
         const double W = sw[qb] * sw[qc] * area;
         // pointwise diffusion factor: scales the average, penalty and symmetry terms
-        const double kp = M.kpoly ? M.kfn[a][face_node(ic[a], e, nb.wrap)] * M.kf[b][ic[b] * N + qb] *
-                                        M.kf[c][ic[c] * N + qc]
+        const double kp = M.kpoly ? M.kfn[a][face_node(ic[a], e, nb.wrap)] * M.kf[b][ic[b] * Q + qb] *
+                                        M.kf[c][ic[c] * Q + qc]
                                   : 1.0;
         const double RV = W * (Phi - kp * avg + kp * gamma * J);
         const double RT = -W * wT * kap * kp * J * sgn;  // times (K grad phi)_a
@@ -245,12 +258,12 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
     }
     __syncthreads();
     // transposed tangential contractions: along c, then b
-    contract<N, 2, true>(uo, S0, sV, N, S2, sD);  // value x V_c + (d_c part) x D_c
-    contract<N, 2, true>(un, S1, sV, N);          // d_b part
-    contract<N, 2, true>(gao, S3, sV, N);         // d_a part
+    contract<N, true>(uo, S0, sV, 1, Q, N, 1, Q, S2, sD);  // value x V_c + (d_c part) x D_c
+    contract<N, true>(un, S1, sV, 1, Q, N, 1, Q);          // d_b part
+    contract<N, true>(gao, S3, sV, 1, Q, N, 1, Q);         // d_a part
     __syncthreads();
-    contract<N, 2, true>(Uo, uo, sV, 1, un, sD);  // R_v
-    contract<N, 2, true>(Do, gao, sV, 1);         // R_d
+    contract<N, true>(Uo, uo, sV, 0, N, N, 1, Q, un, sD);  // R_v
+    contract<N, true>(Do, gao, sV, 0, N, N, 1, Q);         // R_d
     __syncthreads();
     // normal direction last: y(ja,jb,jc) += theta_ja(e) R_v + theta'_ja(e) R_d
     for (int i = tid; i < NB; i += kRefThreads) {
@@ -264,19 +277,22 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
   for (int i = tid; i < NB; i += kRefThreads) yT[i] = Y[i];
 }
 
-template <int N>
+template <int N, int Q>
 static hipError_t launch_ref_n(const dg_handle *h, const double *x, double *y, hipStream_t s) {
-  RefTab<N> T;
-  for (int q = 0; q < N; ++q) {
+  if (h->tabq.m != Q) return hipErrorInvalidValue;
+  RefTab<N, Q> T;
+  for (int q = 0; q < Q; ++q) {
     for (int j = 0; j < N; ++j) {
-      T.V[q][j] = h->tab.V[q][j];
-      T.D[q][j] = h->tab.D[q][j];
+      T.V[q][j] = h->tabq.V[q][j];
+      T.D[q][j] = h->tabq.D[q][j];
     }
-    T.w[q] = h->tab.w[q];
-    T.ev[0][q] = h->tab.e0v[q];
-    T.ev[1][q] = h->tab.e1v[q];
-    T.ed[0][q] = h->tab.e0d[q];
-    T.ed[1][q] = h->tab.e1d[q];
+    T.w[q] = h->tabq.w[q];
+  }
+  for (int j = 0; j < N; ++j) {
+    T.ev[0][j] = h->tabq.e0v[j];
+    T.ev[1][j] = h->tabq.e1v[j];
+    T.ed[0][j] = h->tabq.e0d[j];
+    T.ed[1][j] = h->tabq.e1d[j];
   }
   RefMesh M;
   for (int a = 0; a < 3; ++a) {
@@ -301,23 +317,32 @@ static hipError_t launch_ref_n(const dg_handle *h, const double *x, double *y, h
   for (int i = 0; i < 9; ++i) M.K[i] = h->mesh.K[i];
   M.c = h->mesh.c;
   M.sigma = h->mesh.sigma;
-  hipLaunchKernelGGL(apply_ref_kernel<N>, dim3(unsigned(h->ncells)), dim3(kRefThreads), 0, s, x, y,
-                     M, T);
+  hipLaunchKernelGGL((apply_ref_kernel<N, Q>), dim3(unsigned(h->ncells)), dim3(kRefThreads), 0, s, x, y, M, T);
   return hipGetLastError();
+}
+
+// Q = N: the (k+1)-point rule; Q = N + 2: the raised rule (k <= 8).
+template <int N>
+static hipError_t launch_ref_q(const dg_handle *h, const double *x, double *y, hipStream_t s) {
+  if (h->quad_extra == 0) return launch_ref_n<N, N>(h, x, y, s);
+  if constexpr (N + 2 <= kMaxN) {
+    if (h->quad_extra == 2) return launch_ref_n<N, N + 2>(h, x, y, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_apply_ref_f64(const dg_handle *h, const double *x, double *y, hipStream_t s) {
   switch (h->k + 1) {
-    case 2: return launch_ref_n<2>(h, x, y, s);
-    case 3: return launch_ref_n<3>(h, x, y, s);
-    case 4: return launch_ref_n<4>(h, x, y, s);
-    case 5: return launch_ref_n<5>(h, x, y, s);
-    case 6: return launch_ref_n<6>(h, x, y, s);
-    case 7: return launch_ref_n<7>(h, x, y, s);
-    case 8: return launch_ref_n<8>(h, x, y, s);
-    case 9: return launch_ref_n<9>(h, x, y, s);
-    case 10: return launch_ref_n<10>(h, x, y, s);
-    case 11: return launch_ref_n<11>(h, x, y, s);
+    case 2: return launch_ref_q<2>(h, x, y, s);
+    case 3: return launch_ref_q<3>(h, x, y, s);
+    case 4: return launch_ref_q<4>(h, x, y, s);
+    case 5: return launch_ref_q<5>(h, x, y, s);
+    case 6: return launch_ref_q<6>(h, x, y, s);
+    case 7: return launch_ref_q<7>(h, x, y, s);
+    case 8: return launch_ref_q<8>(h, x, y, s);
+    case 9: return launch_ref_q<9>(h, x, y, s);
+    case 10: return launch_ref_q<10>(h, x, y, s);
+    case 11: return launch_ref_q<11>(h, x, y, s);
     default: return hipErrorInvalidValue;
   }
 }

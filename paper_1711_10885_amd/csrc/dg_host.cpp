@@ -84,11 +84,12 @@ static void legendre_basis(int k, double t, double *v, double *d) {
   }
 }
 
-static void build_tables(int k, Tables &t) {
+static void build_tables(int k, Tables &t, int m = 0) {
   std::memset(&t, 0, sizeof(t));
   t.n = k + 1;
-  gauss01(k + 1, t.xi, t.w);
-  for (int q = 0; q <= k; ++q) legendre_basis(k, t.xi[q], t.V[q], t.D[q]);
+  t.m = m > 0 ? m : k + 1;
+  gauss01(t.m, t.xi, t.w);
+  for (int q = 0; q < t.m; ++q) legendre_basis(k, t.xi[q], t.V[q], t.D[q]);
   legendre_basis(k, 0.0, t.e0v, t.e0d);
   legendre_basis(k, 1.0, t.e1v, t.e1d);
 }
@@ -160,6 +161,10 @@ extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
   *out = nullptr;
   if (!p) return set_error(DG_EINVAL, "dg_setup: problem is NULL");
   if (p->k < 1 || p->k > 10) return set_error(DG_EINVAL, "dg_setup: k must be in 1..10");
+  if (p->quad_extra != 0 && p->quad_extra != 2)
+    return set_error(DG_EINVAL, "dg_setup: quad_extra must be 0 or 2");
+  if (p->k + 1 + p->quad_extra > kMaxN)
+    return set_error(DG_EINVAL, "dg_setup: raised quadrature supports k <= 8");
   int64_t ncells = 1;
   for (int a = 0; a < 3; ++a) {
     if (p->ncell[a] < 1) return set_error(DG_EINVAL, "dg_setup: ncell must be >= 1");
@@ -196,14 +201,14 @@ extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
       if (!std::isfinite(p->kappa_poly[t])) return set_error(DG_EINVAL, "dg_setup: kappa_poly must be finite");
     // every factor positive at the Gauss coordinates and nodes it is used at
     Tables tq;
-    build_tables(p->k, tq);
+    build_tables(p->k, tq, p->k + 1 + p->quad_extra);
     for (int j = 0; j < 3; ++j) {
       const double *c = p->kappa_poly + 3 * j;
       auto g = [&](double s) { return c[0] + c[1] * s + c[2] * s * s; };
       for (int i = 0; i < p->ncell[j]; ++i) {
         const double o = p->nodes[j][i], hh = p->nodes[j][i + 1] - p->nodes[j][i];
         bool ok = g(o) > 0.0 && g(o + hh) > 0.0;
-        for (int q = 0; q <= p->k; ++q) ok = ok && g(o + hh * tq.xi[q]) > 0.0;
+        for (int q = 0; q < tq.m; ++q) ok = ok && g(o + hh * tq.xi[q]) > 0.0;
         if (!ok) return set_error(DG_EINVAL, "dg_setup: kappa_poly factors must be positive on the mesh");
       }
     }
@@ -247,9 +252,12 @@ extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
     return set_error(DG_EHIP, "dg_setup: no HIP device");
   }
   build_tables(p->k, h->tab);
+  build_tables(p->k, h->tabq, n + p->quad_extra);
+  h->quad_extra = p->quad_extra;
 
   // host staging of every device table, then one allocation + one copy
-  const int m = n;
+  // (coefficients at the Gauss coordinates of the operator's rule)
+  const int m = h->tabq.m;
   std::vector<double> host;
   size_t off_h[3], off_nd[3], off_bv[3], off_bn[3], off_kappa = 0;
   for (int a = 0; a < 3; ++a) {
@@ -264,7 +272,7 @@ extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
     for (int i = 0; i < p->ncell[ax]; ++i) {
       const double o = p->nodes[ax][i], hh = p->nodes[ax][i + 1] - p->nodes[ax][i];
       for (int q = 0; q < m; ++q)
-        host.push_back(p->b_const[r] + p->b_sin[r] * std::sin(M_PI * (o + hh * h->tab.xi[q])));
+        host.push_back(p->b_const[r] + p->b_sin[r] * std::sin(M_PI * (o + hh * h->tabq.xi[q])));
     }
     off_bn[r] = host.size();
     for (int i = 0; i <= p->ncell[ax]; ++i)
@@ -286,7 +294,7 @@ extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
       off_bf[t] = host.size();
       for (int i = 0; i < p->ncell[j]; ++i) {
         const double o = p->nodes[j][i], hh = p->nodes[j][i + 1] - p->nodes[j][i];
-        for (int q = 0; q < m; ++q) host.push_back(f(o + hh * h->tab.xi[q]));
+        for (int q = 0; q < m; ++q) host.push_back(f(o + hh * h->tabq.xi[q]));
       }
       off_bfn[t] = host.size();
       for (int i = 0; i <= p->ncell[j]; ++i) host.push_back(f(p->nodes[j][i]));
@@ -300,14 +308,14 @@ extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
       off_kf[j] = host.size();
       for (int i = 0; i < p->ncell[j]; ++i) {
         const double o = p->nodes[j][i], hh = p->nodes[j][i + 1] - p->nodes[j][i];
-        for (int q = 0; q < m; ++q) host.push_back(g(o + hh * h->tab.xi[q]));
+        for (int q = 0; q < m; ++q) host.push_back(g(o + hh * h->tabq.xi[q]));
       }
       off_kfn[j] = host.size();
       for (int i = 0; i <= p->ncell[j]; ++i) host.push_back(g(p->nodes[j][i]));
     }
   }
   const size_t off_w = host.size();
-  host.insert(host.end(), h->tab.w, h->tab.w + m);
+  host.insert(host.end(), h->tabq.w, h->tabq.w + m);
   if (p->kappa) {
     off_kappa = host.size();
     host.insert(host.end(), p->kappa, p->kappa + ncells);
@@ -362,8 +370,9 @@ extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
 
 namespace dgmf {
 hipError_t apply_f64(const dg_handle *h, const double *x, double *y, hipStream_t s) {
-  return h->variant == DG_KERNEL_REFERENCE ? launch_apply_ref_f64(h, x, y, s)
-                                           : launch_apply_fused_f64(h, x, y, s);
+  // the raised rule runs on the reference-layout kernel only
+  return (h->variant == DG_KERNEL_REFERENCE || h->quad_extra) ? launch_apply_ref_f64(h, x, y, s)
+                                                              : launch_apply_fused_f64(h, x, y, s);
 }
 }  // namespace dgmf
 
@@ -417,6 +426,7 @@ extern "C" dg_status dg_apply_f32(dg_handle *h, const float *x, float *y, void *
   if (!x || !y) return set_error(DG_EINVAL, "dg_apply_f32: x or y is NULL");
   if (overlaps(x, y, size_t(h->ndof) * sizeof(float)))
     return set_error(DG_EINVAL, "dg_apply_f32: x and y overlap");
+  if (h->quad_extra) return set_error(DG_EINVAL, "dg_apply_f32: no FP32 operator with raised quadrature");
   int cur = -1;
   if (hipGetDevice(&cur) != hipSuccess || cur != h->device) {
     hipError_t e = hipSetDevice(h->device);

@@ -24,6 +24,7 @@ struct Mlp;
 //   e0v/e1v = theta_j(0/1), e0d/e1d = theta_j'(0/1), w = Gauss weights.
 struct Tables {
   int n;
+  int m;  // quadrature points (rows of V, D; entries of xi, w)
   double xi[kMaxN], w[kMaxN];
   double V[kMaxN][kMaxN], D[kMaxN][kMaxN];
   double e0v[kMaxN], e1v[kMaxN], e0d[kMaxN], e1d[kMaxN];
@@ -63,7 +64,9 @@ struct dg_handle {
   int k;
   int64_t ncells, ndof;
   dg_problem prob;  // host copy (pointers cleared)
-  dgmf::Tables tab;
+  dgmf::Tables tab;   // (k+1)-point rule (load vector)
+  dgmf::Tables tabq;  // the operator's rule, m = k + 1 + quad_extra points
+  int quad_extra;
   dgmf::DevMesh mesh;
   void *dev_block;  // single allocation backing the DevMesh arrays
   int variant;      // DG_KERNEL_*

@@ -73,7 +73,7 @@ extern "C" dg_status dg_heun(dg_handle *h, double *u, const double *f, double dt
     }
   }
   const hipStream_t s = static_cast<hipStream_t>(stream);
-  if (h->variant != DG_KERNEL_REFERENCE) {
+  if (h->variant != DG_KERNEL_REFERENCE && !h->quad_extra) {
     double *u1 = h->ts;
     for (int step = 0; step < nsteps; ++step) {
       hipError_t e = launch_heun_fused_f64(h, u, u1, f, dt, 0, s);

@@ -67,6 +67,8 @@ def _struct(prob, **over):
     (dict(b_axis0=3), "b_axis"),
     (dict(c=float("nan")), "c must be finite"),
     (dict(flags=128), "unknown flag"),
+    (dict(quad_extra=1), "quad_extra"),
+    (dict(k=9, quad_extra=2), "raised quadrature supports"),
     (dict(k=8, flags=2), "block Jacobi supports"),
 ])
 def test_setup_rejects_invalid_problems(over, msg):

@@ -238,3 +238,36 @@ def test_kappa_polynomial_fp32_operator_matches_fp64(k):
     e = np.abs(y - ref).max() / np.abs(ref).max()
     print(f"kappa poly fp32 k={k}: relmax {e:.2e}", flush=True)
     assert e <= 30 * (k + 1) * 2.0 ** -24
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("k", range(1, 9))
+def test_raised_quadrature_every_degree(variant, k):
+    """The rule q = 2p + 4 (k + 3 Gauss points per direction, Problem B of
+    Sec. 5.1) with the polynomial diffusion factor, product- or sum-form b
+    and periodic axes; both kernel selections run the rectangular
+    reference-layout kernel."""
+    p = W.random_problem(1900 + k, ncell=(3, 2, 2), k=k, b="product" if k % 2 else "sine",
+                         periodic=PERIODIC[k % 4])
+    p = p.with_(quad_extra=2, kappa_poly=W.random_kappa_poly(np.random.default_rng(1910 + k)))
+    x = W.random_vector(p.ndof, 1920 + k)
+    _check(_gpu_apply(p, x, variant), oracle.apply(p, x), f"q=2p+4 k={k} v{variant}")
+
+
+def test_raised_quadrature_with_cellwise_coefficients():
+    p = W.random_problem(1930, ncell=(4, 3, 2), k=3, b="const").with_(quad_extra=2)
+    x = W.random_vector(p.ndof, 1931)
+    _check(_gpu_apply(p, x, 0), oracle.apply(p, x), "q=2p+4 cellwise")
+
+
+def test_raised_quadrature_has_no_fp32_operator():
+    torch = _torch()
+    from paper_1711_10885_amd import binding
+    p = W.random_problem(1940, ncell=(2, 2, 2), k=2).with_(quad_extra=2)
+    with binding.DG(p) as dg:
+        with pytest.raises(binding.DGError) as ei:
+            dg.apply_f32(torch.zeros(p.ndof, dtype=torch.float32, device="cuda"))
+        assert ei.value.status == binding.DG_EINVAL
+        f = torch.ones(p.ndof, dtype=torch.float64, device="cuda")
+        with pytest.raises(binding.DGError):
+            dg.solve(f, method=binding.DG_GMRES_IR)

@@ -272,3 +272,15 @@ def test_shared_blocks_with_a_kappa_polynomial(k):
         assert dg.bj_nblocks() == N
         z = dg.precond_apply(torch.from_numpy(r).cuda()).cpu().numpy()
     _check_blocks(oracle.block_diagonal(p), r, z, f"kappa poly shared k={k}")
+
+
+def test_blocks_with_raised_quadrature():
+    """Probing runs the raised-rule operator: every block against the oracle's."""
+    torch = _torch()
+    from paper_1711_10885_amd import binding
+    p = W.random_problem(620, ncell=(3, 2, 2), k=2, b="sine").with_(
+        quad_extra=2, kappa_poly=W.random_kappa_poly(np.random.default_rng(621)))
+    r = W.random_vector(p.ndof, 622)
+    with binding.DG(p, flags=binding.DG_WITH_BLOCK_JACOBI) as dg:
+        z = dg.precond_apply(torch.from_numpy(r).cuda()).cpu().numpy()
+    _check_blocks(oracle.block_diagonal(p), r, z, "raised quadrature blocks")

@@ -194,6 +194,14 @@ def test_heun_with_a_kappa_polynomial(variant):
     _check(_gpu_heun(p, u0, dt, n, variant), oracle.heun(p, u0, dt, n), u0, f"kappa poly heun v{variant}")
 
 
+def test_heun_with_raised_quadrature():
+    p = _mild(W.random_problem(1330, ncell=(3, 2, 2), k=3, b="product", periodic=(True, True, True)))
+    p = p.with_(quad_extra=2, kappa_poly=W.random_kappa_poly(np.random.default_rng(1331)))
+    u0 = W.random_vector(p.ndof, 1332)
+    dt, n = _dt(p), 3
+    _check(_gpu_heun(p, u0, dt, n), oracle.heun(p, u0, dt, n), u0, "q=2p+4 heun")
+
+
 @pytest.mark.parametrize("case", ["dt0", "dtnan", "dtneg", "nsteps", "overlap"])
 def test_invalid_arguments(case):
     torch = _torch()
