@@ -59,6 +59,14 @@ def make_workload(name: str):
         return W.mixed_k5_48()
     if name == "learned_k3_64":
         return W.learned_k3_64()
+    if name.startswith("kpoly_sweep_k") or name.startswith("raised_sweep_k"):
+        # the sweep mesh with the polynomial diffusion factor (and the q = 2p + 4 rule)
+        import numpy as np
+        k = int(name.split("_k")[-1])
+        p = W.cdr_sweep(k).with_(kappa_poly=W.random_kappa_poly(np.random.default_rng(7)))
+        if name.startswith("raised"):
+            p = p.with_(quad_extra=2)
+        return p.with_(name=name)
     raise SystemExit(f"unknown workload {name}")
 
 

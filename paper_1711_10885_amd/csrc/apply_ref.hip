@@ -38,38 +38,37 @@ struct RefMesh {
 
 constexpr int kRefThreads = 256;
 
-// One 1D contraction along axis ax of a block in LDS with output dimensions
-// (o0, o1, o2) (axis 0 fastest; o2 = 1 for a 2D block) and input length LI
-// along ax (the other input dimensions are those of the output):
+// One 1D contraction along axis AX of a block in LDS with output dimensions
+// (O0, O1, O2) (axis 0 fastest; O2 = 1 for a 2D block) and input length LI
+// along AX (the other input dimensions are those of the output), all
+// compile-time constants:
 //   out[.., q, ..] (+)= sum_{t < LI} A(q, t) in[.., t, ..],
 // A(q, t) = Mat[q][t] (TRANS = false: evaluation, points from basis
 // coefficients) or Mat[t][q] (TRANS = true: integration against the test
 // functions); an optional second term with in2, Mat2.
-template <int LD, bool TRANS>
-__device__ inline void contract(double *out, const double *in, const double (*Mat)[LD], int ax, int o0, int o1,
-                                int o2, int LI, const double *in2 = nullptr, const double (*Mat2)[LD] = nullptr) {
-  const int od[3] = {o0, o1, o2};
-  int id[3] = {o0, o1, o2};
-  id[ax] = LI;
-  const int is[3] = {1, id[0], id[0] * id[1]};
-  const int NT = o0 * o1 * o2;
+template <int LD, bool TRANS, int AX, int O0, int O1, int O2, int LI>
+__device__ inline void contract(double *out, const double *in, const double (*Mat)[LD],
+                                const double *in2 = nullptr, const double (*Mat2)[LD] = nullptr) {
+  constexpr int I0 = AX == 0 ? LI : O0, I1 = AX == 1 ? LI : O1;
+  constexpr int IS[3] = {1, I0, I0 * I1};  // input strides
+  constexpr int NT = O0 * O1 * O2;
   for (int i = threadIdx.x; i < NT; i += kRefThreads) {
-    const int io[3] = {i % od[0], (i / od[0]) % od[1], i / (od[0] * od[1])};
-    const int q = io[ax];
-    int base = 0;
-    for (int a = 0; a < 3; ++a)
-      if (a != ax) base += io[a] * is[a];
-    const int st = is[ax];
+    const int i0 = i % O0, i1 = (i / O0) % O1, i2 = i / (O0 * O1);
+    const int q = AX == 0 ? i0 : (AX == 1 ? i1 : i2);
+    const int base = (AX == 0 ? 0 : i0 * IS[0]) + (AX == 1 ? 0 : i1 * IS[1]) + (AX == 2 ? 0 : i2 * IS[2]);
     double s = 0.0;
+#pragma unroll
     for (int t = 0; t < LI; ++t) {
       const double a = TRANS ? Mat[t][q] : Mat[q][t];
-      s = fma(a, in[base + t * st], s);
+      s = fma(a, in[base + t * IS[AX]], s);
     }
-    if (in2)
+    if (in2) {
+#pragma unroll
       for (int t = 0; t < LI; ++t) {
         const double a = TRANS ? Mat2[t][q] : Mat2[q][t];
-        s = fma(a, in2[base + t * st], s);
+        s = fma(a, in2[base + t * IS[AX]], s);
       }
+    }
     out[i] = s;
   }
 }
@@ -108,17 +107,17 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
   const double vol = h[0] * h[1] * h[2];
 
   // ---------------- volume: forward (u, d1 u, d2 u, d3 u at points) --------
-  contract<N, false>(B0, X, sV, 0, Q, N, N, N);  // V1 x
-  contract<N, false>(B1, X, sD, 0, Q, N, N, N);  // D1 x
+  contract<N, false, 0, Q, N, N, N>(B0, X, sV);  // V1 x
+  contract<N, false, 0, Q, N, N, N>(B1, X, sD);  // D1 x
   __syncthreads();
-  contract<N, false>(B2, B0, sV, 1, Q, Q, N, N);  // V2 V1 x
-  contract<N, false>(B3, B1, sV, 1, Q, Q, N, N);  // V2 D1 x
-  contract<N, false>(B4, B0, sD, 1, Q, Q, N, N);  // D2 V1 x
+  contract<N, false, 1, Q, Q, N, N>(B2, B0, sV);  // V2 V1 x
+  contract<N, false, 1, Q, Q, N, N>(B3, B1, sV);  // V2 D1 x
+  contract<N, false, 1, Q, Q, N, N>(B4, B0, sD);  // D2 V1 x
   __syncthreads();
-  contract<N, false>(B0, B2, sV, 2, Q, Q, Q, N);  // u
-  contract<N, false>(B1, B3, sV, 2, Q, Q, Q, N);  // d^1 u (reference)
-  contract<N, false>(B5, B4, sV, 2, Q, Q, Q, N);  // d^2 u
-  contract<N, false>(B6, B2, sD, 2, Q, Q, Q, N);  // d^3 u
+  contract<N, false, 2, Q, Q, Q, N>(B0, B2, sV);  // u
+  contract<N, false, 2, Q, Q, Q, N>(B1, B3, sV);  // d^1 u (reference)
+  contract<N, false, 2, Q, Q, Q, N>(B5, B4, sV);  // d^2 u
+  contract<N, false, 2, Q, Q, Q, N>(B6, B2, sD);  // d^3 u
   __syncthreads();
   // ---------------- volume: pointwise flux (eq. (gauss_points)) ------------
   for (int i = tid; i < QB; i += kRefThreads) {
@@ -144,14 +143,14 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
   }
   __syncthreads();
   // ---------------- volume: transposed contractions (eq. (evalblf)) --------
-  contract<N, true>(B2, B0, sV, 2, Q, Q, N, Q, B6, sD);  // along 3: V^T x0 + D^T x3
-  contract<N, true>(B3, B1, sV, 2, Q, Q, N, Q);          // V^T x1
-  contract<N, true>(B4, B5, sV, 2, Q, Q, N, Q);          // V^T x2
+  contract<N, true, 2, Q, Q, N, Q>(B2, B0, sV, B6, sD);  // along 3: V^T x0 + D^T x3
+  contract<N, true, 2, Q, Q, N, Q>(B3, B1, sV);          // V^T x1
+  contract<N, true, 2, Q, Q, N, Q>(B4, B5, sV);          // V^T x2
   __syncthreads();
-  contract<N, true>(B0, B2, sV, 1, Q, N, N, Q, B4, sD);  // along 2
-  contract<N, true>(B1, B3, sV, 1, Q, N, N, Q);
+  contract<N, true, 1, Q, N, N, Q>(B0, B2, sV, B4, sD);  // along 2
+  contract<N, true, 1, Q, N, N, Q>(B1, B3, sV);
   __syncthreads();
-  contract<N, true>(Y, B0, sV, 0, N, N, N, Q, B1, sD);  // along 1
+  contract<N, true, 0, N, N, N, Q>(Y, B0, sV, B1, sD);  // along 1
   __syncthreads();
 
   // ---------------- faces --------------------------------------------------
@@ -190,23 +189,23 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
     }
     __syncthreads();
     // tangential evaluation: first b (stride 1 in the 2D grid), then c
-    contract<N, false>(S0, Uo, sV, 0, Q, N, 1, N);
-    contract<N, false>(S1, Uo, sD, 0, Q, N, 1, N);
-    contract<N, false>(S2, Un, sV, 0, Q, N, 1, N);
-    contract<N, false>(S3, Un, sD, 0, Q, N, 1, N);
+    contract<N, false, 0, Q, N, 1, N>(S0, Uo, sV);
+    contract<N, false, 0, Q, N, 1, N>(S1, Uo, sD);
+    contract<N, false, 0, Q, N, 1, N>(S2, Un, sV);
+    contract<N, false, 0, Q, N, 1, N>(S3, Un, sD);
     __syncthreads();
-    contract<N, false>(uo, S0, sV, 1, Q, Q, 1, N);
-    contract<N, false>(gbo, S1, sV, 1, Q, Q, 1, N);
-    contract<N, false>(gco, S0, sD, 1, Q, Q, 1, N);
-    contract<N, false>(un, S2, sV, 1, Q, Q, 1, N);
-    contract<N, false>(gbn, S3, sV, 1, Q, Q, 1, N);
-    contract<N, false>(gcn, S2, sD, 1, Q, Q, 1, N);
+    contract<N, false, 1, Q, Q, 1, N>(uo, S0, sV);
+    contract<N, false, 1, Q, Q, 1, N>(gbo, S1, sV);
+    contract<N, false, 1, Q, Q, 1, N>(gco, S0, sD);
+    contract<N, false, 1, Q, Q, 1, N>(un, S2, sV);
+    contract<N, false, 1, Q, Q, 1, N>(gbn, S3, sV);
+    contract<N, false, 1, Q, Q, 1, N>(gcn, S2, sD);
     __syncthreads();
-    contract<N, false>(S0, Do, sV, 0, Q, N, 1, N);
-    contract<N, false>(S1, Dn, sV, 0, Q, N, 1, N);
+    contract<N, false, 0, Q, N, 1, N>(S0, Do, sV);
+    contract<N, false, 0, Q, N, 1, N>(S1, Dn, sV);
     __syncthreads();
-    contract<N, false>(gao, S0, sV, 1, Q, Q, 1, N);
-    contract<N, false>(gan, S1, sV, 1, Q, Q, 1, N);
+    contract<N, false, 1, Q, Q, 1, N>(gao, S0, sV);
+    contract<N, false, 1, Q, Q, 1, N>(gan, S1, sV);
     __syncthreads();
     // pointwise face terms (Sec. 2.2): upwind flux, weighted average,
     // penalty, written with the outer normal n_T = sgn e_a of cell T
@@ -258,12 +257,12 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
     }
     __syncthreads();
     // transposed tangential contractions: along c, then b
-    contract<N, true>(uo, S0, sV, 1, Q, N, 1, Q, S2, sD);  // value x V_c + (d_c part) x D_c
-    contract<N, true>(un, S1, sV, 1, Q, N, 1, Q);          // d_b part
-    contract<N, true>(gao, S3, sV, 1, Q, N, 1, Q);         // d_a part
+    contract<N, true, 1, Q, N, 1, Q>(uo, S0, sV, S2, sD);  // value x V_c + (d_c part) x D_c
+    contract<N, true, 1, Q, N, 1, Q>(un, S1, sV);          // d_b part
+    contract<N, true, 1, Q, N, 1, Q>(gao, S3, sV);         // d_a part
     __syncthreads();
-    contract<N, true>(Uo, uo, sV, 0, N, N, 1, Q, un, sD);  // R_v
-    contract<N, true>(Do, gao, sV, 0, N, N, 1, Q);         // R_d
+    contract<N, true, 0, N, N, 1, Q>(Uo, uo, sV, un, sD);  // R_v
+    contract<N, true, 0, N, N, 1, Q>(Do, gao, sV);         // R_d
     __syncthreads();
     // normal direction last: y(ja,jb,jc) += theta_ja(e) R_v + theta'_ja(e) R_d
     for (int i = tid; i < NB; i += kRefThreads) {
