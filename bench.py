@@ -274,7 +274,7 @@ def main():
     ap.add_argument("--workload", default="cdr_k7_32")
     ap.add_argument("--variant", type=int, default=0, help="0 tuned kernel, 1 reference kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--cpu-budget", type=float, default=18.0)
     ap.add_argument("--solves", default=None, choices=["none", "mixed", "learned", "all"],
                     help="also time the solves to 1e-8 (plain FP64 vs mixed, block Jacobi vs learned); "
                          "default: all for the headline workload, none for the others")
