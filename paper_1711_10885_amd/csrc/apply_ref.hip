@@ -75,6 +75,21 @@ __device__ inline void contract(int lt, double *out, const double *in, const dou
   }
 }
 
+__device__ __forceinline__ int sel3i(int a, int v0, int v1, int v2) { return a == 0 ? v0 : (a == 1 ? v1 : v2); }
+__device__ __forceinline__ double sel3d(int a, double v0, double v1, double v2) {
+  return a == 0 ? v0 : (a == 1 ? v1 : v2);
+}
+// Entry i of a kernel-argument pointer array by a select chain (a runtime
+// index into the argument struct would copy it to scratch).
+template <int L>
+__device__ __forceinline__ const double *pickp(const double *const *t, int i) {
+  const double *p = t[0];
+#pragma unroll
+  for (int s = 1; s < L; ++s)
+    if (i == s) p = t[s];
+  return p;
+}
+
 // CPB cells per workgroup, kRefThreads / CPB threads and one LDS slice each
 // (CPB = 1 for the (k+1)-point reference variant).
 template <int N, int Q, int CPB>
@@ -84,14 +99,21 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
   constexpr int NB = N * N * N, NF = N * N, QB = Q * Q * Q, QF = Q * Q;
   constexpr int TPC = kRefThreads / CPB;
   __shared__ double sV[Q][N], sD[Q][N], sw[Q], sev[2][N], sed[2][N];
-  __shared__ double Xs[CPB][NB], Ys[CPB][NB], Bs[CPB][7][QB];
-  __shared__ double Fs[CPB][16][QF];
+  // raised rule: the six faces are processed together (one pass per
+  // contraction over a (., ., 6) block); their 24 NF + 72 QF doubles share the
+  // region of the volume tensors, which are dead by then
+  constexpr bool BATCH = (Q != N);
+  constexpr int FB = 24 * NF + 72 * QF;
+  constexpr int RSZ = (BATCH && FB > 7 * QB) ? FB : 7 * QB;
+  __shared__ double Xs[CPB][NB], Ys[CPB][NB], Rs[CPB][RSZ];
+  constexpr int FQ = BATCH ? 1 : QF;  // per-face buffers of the face-by-face path
+  __shared__ double Fs[CPB][16][FQ];
   const int tid = threadIdx.x;
   const int slot = tid / TPC, lt = tid % TPC;
   double *X = Xs[slot], *Y = Ys[slot];
-  double *B0 = Bs[slot][0], *B1 = Bs[slot][1], *B2 = Bs[slot][2], *B3 = Bs[slot][3];
-  double *B4 = Bs[slot][4], *B5 = Bs[slot][5], *B6 = Bs[slot][6];
-  double(*F)[QF] = Fs[slot];
+  double *B0 = Rs[slot], *B1 = B0 + QB, *B2 = B0 + 2 * QB, *B3 = B0 + 3 * QB;
+  double *B4 = B0 + 4 * QB, *B5 = B0 + 5 * QB, *B6 = B0 + 6 * QB;
+  double(*F)[FQ] = Fs[slot];
   // a slot past the last cell repeats it (every thread reaches every barrier)
   // and does not store
   const bool active = int(blockIdx.x) * CPB + slot < M.ncells;
@@ -167,6 +189,130 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
   __syncthreads();
 
   // ---------------- faces --------------------------------------------------
+  if constexpr (BATCH) {
+    double *R = Rs[slot];
+    double *TUo = R, *TDo = R + 6 * NF, *TUn = R + 12 * NF, *TDn = R + 18 * NF;  // (N, N, 6) each
+    double *P = R + 24 * NF;                                                       // (Q, Q, 6) each
+    double *S0 = P, *S1 = P + 6 * QF, *S2 = P + 12 * QF, *S3 = P + 18 * QF;
+    double *uo = P + 24 * QF, *un = P + 30 * QF, *gao = P + 36 * QF, *gan = P + 42 * QF;
+    double *gbo = P + 48 * QF, *gbn = P + 54 * QF, *gco = P + 60 * QF, *gcn = P + 66 * QF;
+    // normal direction first: modal traces of face f on its (jb, jc) grid
+    for (int i = lt; i < 6 * NF; i += TPC) {
+      const int f = i / NF, ii = i - f * NF;
+      const int a = f >> 1, e = f & 1;
+      const int jb = ii % N, jc = ii / N;
+      const int sa = sel3i(a, 1, N, NF), sb = (a == 0) ? N : 1, sc = (a == 2) ? N : NF;
+      const int base = jb * sb + jc * sc;
+      const FaceNb nb = face_nb(cell, sel3i(a, ic[0], ic[1], ic[2]), sel3i(a, M.ncell[0], M.ncell[1], M.ncell[2]),
+                                sel3i(a, cstride[0], cstride[1], cstride[2]), (M.periodic >> a) & 1, e);
+      double uo_ = 0, do_ = 0, un_ = 0, dn_ = 0;
+      for (int ja = 0; ja < N; ++ja) {
+        uo_ = fma(sev[e][ja], X[base + ja * sa], uo_);
+        do_ = fma(sed[e][ja], X[base + ja * sa], do_);
+      }
+      if (nb.in) {
+        const double *xN = x + size_t(nb.cell) * NB;
+        for (int ja = 0; ja < N; ++ja) {
+          const double v = xN[base + ja * sa];
+          un_ = fma(sev[1 - e][ja], v, un_);
+          dn_ = fma(sed[1 - e][ja], v, dn_);
+        }
+      }
+      TUo[i] = uo_;
+      TDo[i] = do_;
+      TUn[i] = un_;
+      TDn[i] = dn_;
+    }
+    __syncthreads();
+    // tangential evaluation of all six faces: first b, then c
+    contract<N, false, 0, Q, N, 6, N, TPC>(lt, S0, TUo, sV);
+    contract<N, false, 0, Q, N, 6, N, TPC>(lt, S1, TUo, sD);
+    contract<N, false, 0, Q, N, 6, N, TPC>(lt, S2, TUn, sV);
+    contract<N, false, 0, Q, N, 6, N, TPC>(lt, S3, TUn, sD);
+    __syncthreads();
+    contract<N, false, 1, Q, Q, 6, N, TPC>(lt, uo, S0, sV);
+    contract<N, false, 1, Q, Q, 6, N, TPC>(lt, gbo, S1, sV);
+    contract<N, false, 1, Q, Q, 6, N, TPC>(lt, gco, S0, sD);
+    contract<N, false, 1, Q, Q, 6, N, TPC>(lt, un, S2, sV);
+    contract<N, false, 1, Q, Q, 6, N, TPC>(lt, gbn, S3, sV);
+    contract<N, false, 1, Q, Q, 6, N, TPC>(lt, gcn, S2, sD);
+    __syncthreads();
+    contract<N, false, 0, Q, N, 6, N, TPC>(lt, S0, TDo, sV);
+    contract<N, false, 0, Q, N, 6, N, TPC>(lt, S1, TDn, sV);
+    __syncthreads();
+    contract<N, false, 1, Q, Q, 6, N, TPC>(lt, gao, S0, sV);
+    contract<N, false, 1, Q, Q, 6, N, TPC>(lt, gan, S1, sV);
+    __syncthreads();
+    // pointwise face terms of every face point (as in the per-face loop below)
+    for (int i = lt; i < 6 * QF; i += TPC) {
+      const int f = i / QF, ii = i - f * QF;
+      const int a = f >> 1, e = f & 1;
+      const int b = (a == 0) ? 1 : 0, c = (a == 2) ? 1 : 2;
+      const int qb = ii % Q, qc = ii / Q;
+      const int ia = sel3i(a, ic[0], ic[1], ic[2]), ib = sel3i(b, ic[0], ic[1], ic[2]), icc = sel3i(c, ic[0], ic[1], ic[2]);
+      const FaceNb nb = face_nb(cell, ia, sel3i(a, M.ncell[0], M.ncell[1], M.ncell[2]),
+                                sel3i(a, cstride[0], cstride[1], cstride[2]), (M.periodic >> a) & 1, e);
+      const bool interior = nb.in;
+      const double ha = sel3d(a, h[0], h[1], h[2]), hb = sel3d(b, h[0], h[1], h[2]), hc = sel3d(c, h[0], h[1], h[2]);
+      const double sgn = e ? 1.0 : -1.0;
+      const double hn = interior ? pickp<3>(M.h, a)[nb.ja] : ha;
+      const double kn = interior ? (M.kappa ? M.kappa[nb.cell] : 1.0) : 0.0;
+      const double Kaa = sel3d(a, M.K[0], M.K[4], M.K[8]);
+      const double Kab = sel3d(a, M.K[1], M.K[3], M.K[6]), Kac = sel3d(a, M.K[2], M.K[5], M.K[7]);
+      const double dT = kap * Kaa, dN = kn * Kaa;
+      const double wT = interior ? dN / (dT + dN) : 1.0;
+      const double wN = interior ? dT / (dT + dN) : 0.0;
+      const double gamma = interior ? M.sigma * (2.0 * dT * dN / (dT + dN)) / fmin(ha, hn) : M.sigma * dT / ha;
+      const double KgT = Kaa * gao[i] / ha + Kab * gbo[i] / hb + Kac * gco[i] / hc;
+      const double KgN = Kaa * gan[i] / hn + Kab * gbn[i] / hb + Kac * gcn[i] / hc;
+      const double avg = sgn * (wT * kap * KgT + wN * kn * KgN);
+      const double J = uo[i] - un[i];
+      const int fn = face_node(ia, e, nb.wrap);
+      double ba;
+      if (M.bprod) {
+        ba = pickp<9>(M.bfn, 3 * a + a)[fn] * pickp<9>(M.bf, 3 * a + b)[ib * Q + qb] *
+             pickp<9>(M.bf, 3 * a + c)[icc * Q + qc];
+      } else {
+        const int ax = sel3i(a, M.b_axis[0], M.b_axis[1], M.b_axis[2]);
+        const double *bv = pickp<3>(M.bvol, a);
+        ba = (ax == a) ? pickp<3>(M.bnode, a)[fn] : (ax == b) ? bv[ib * Q + qb] : bv[icc * Q + qc];
+      }
+      const double bout = sgn * ba;
+      const double Phi = bout >= 0.0 ? bout * uo[i] : bout * un[i];
+      const double W = sw[qb] * sw[qc] * hb * hc;
+      const double kp = M.kpoly ? pickp<3>(M.kfn, a)[fn] * pickp<3>(M.kf, b)[ib * Q + qb] *
+                                      pickp<3>(M.kf, c)[icc * Q + qc]
+                                : 1.0;
+      const double RV = W * (Phi - kp * avg + kp * gamma * J);
+      const double RT = -W * wT * kap * kp * J * sgn;
+      S0[i] = RV;
+      S1[i] = RT * Kab / hb;
+      S2[i] = RT * Kac / hc;
+      S3[i] = RT * Kaa / ha;
+    }
+    __syncthreads();
+    // transposed tangential contractions: along c, then b
+    contract<N, true, 1, Q, N, 6, Q, TPC>(lt, uo, S0, sV, S2, sD);
+    contract<N, true, 1, Q, N, 6, Q, TPC>(lt, un, S1, sV);
+    contract<N, true, 1, Q, N, 6, Q, TPC>(lt, gao, S3, sV);
+    __syncthreads();
+    contract<N, true, 0, N, N, 6, Q, TPC>(lt, TUo, uo, sV, un, sD);  // R_v of every face
+    contract<N, true, 0, N, N, 6, Q, TPC>(lt, TDo, gao, sV);         // R_d
+    __syncthreads();
+    // normal direction last, all six faces into the own coefficients
+    for (int i = lt; i < NB; i += TPC) {
+      const int j0 = i % N, j1 = (i / N) % N, j2 = i / NF;
+      double acc = 0.0;
+#pragma unroll
+      for (int f = 0; f < 6; ++f) {
+        const int a = f >> 1, e = f & 1;
+        const int ja = sel3i(a, j0, j1, j2);
+        const int i2 = (a == 0 ? j1 : j0) + N * (a == 2 ? j1 : j2);
+        acc += sev[e][ja] * TUo[f * NF + i2] + sed[e][ja] * TDo[f * NF + i2];
+      }
+      Y[i] += acc;
+    }
+  } else {
   double *Uo = F[0], *Do = F[1], *Un = F[2], *Dn = F[3];
   double *S0 = F[4], *S1 = F[5], *S2 = F[6], *S3 = F[7];
   double *uo = F[8], *un = F[9], *gao = F[10], *gan = F[11];
@@ -290,6 +436,7 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
     }
     __syncthreads();
   }
+  }
   if (active) {
     double *yT = y + size_t(cell) * NB;
     for (int i = lt; i < NB; i += TPC) yT[i] = Y[i];
@@ -338,7 +485,9 @@ static hipError_t launch_ref_n(const dg_handle *h, const double *x, double *y, h
   M.sigma = h->mesh.sigma;
   M.ncells = int(h->ncells);
   // raised rule: as many cells per workgroup as keep its LDS near 80 KB
-  constexpr int per_cell = 8 * (2 * N * N * N + 7 * Q * Q * Q + 16 * Q * Q);
+  constexpr int NF_ = N * N, QF_ = Q * Q, QB_ = Q * Q * Q;
+  constexpr int region = (Q != N && 24 * NF_ + 72 * QF_ > 7 * QB_) ? 24 * NF_ + 72 * QF_ : 7 * QB_;
+  constexpr int per_cell = 8 * (2 * N * N * N + region + (Q == N ? 16 * QF_ : 16));
   constexpr int CPB = (Q == N) ? 1 : (8 * per_cell <= 81920 ? 8 : 4 * per_cell <= 81920 ? 4 : 2 * per_cell <= 81920 ? 2 : 1);
   const unsigned grid = unsigned((h->ncells + CPB - 1) / CPB);
   hipLaunchKernelGGL((apply_ref_kernel<N, Q, CPB>), dim3(grid), dim3(kRefThreads), 0, s, x, y, M, T);
