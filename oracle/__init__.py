@@ -71,6 +71,8 @@ class _Problem(ctypes.Structure):
         ("kappa_poly_on", ctypes.c_int32),
         ("kappa_poly", ctypes.c_double * 9),
         ("quad_extra", ctypes.c_int32),
+        ("affine_on", ctypes.c_int32),
+        ("affine", ctypes.c_double * 9),
     ]
 
 
@@ -143,6 +145,11 @@ class _Marshalled:
             for t in range(9):
                 s.kappa_poly[t] = float(kpoly[t])
         s.quad_extra = int(getattr(prob, "quad_extra", 0))
+        A = getattr(prob, "affine", None)
+        s.affine_on = 0 if A is None else 1
+        if A is not None:
+            for i, v in enumerate(np.asarray(A, dtype=np.float64).ravel()):
+                s.affine[i] = float(v)
         self.struct = s
 
 

@@ -37,6 +37,12 @@
  *    b_r(x) = b_amp[r] * prod_j sin(b_freq[3r+j] x_j + b_phase[3r+j]) (factors
  *    with b_freq == 0 are 1), which holds the Taylor-Green field of Sec. 5.4
  *    (eq. (2) of that section); b is evaluated at each quadrature point;
+ *  - with or_problem.affine_on the mesh is the image x = A xi of the tensor
+ *    grid of the nodes (affine geometry, Problem B of Sec. 5.1): gradients
+ *    are A^{-T} times the tensor-grid gradients, volume and face measures
+ *    scale by |det A| and |det A| |A^{-T} e_a|, face normals are
+ *    A^{-T} e_a / |A^{-T} e_a|, d = nu^T D nu, and |F| / min|T| in gamma_F is
+ *    |A^{-T} e_a| / min h_a; coefficients are evaluated at physical points;
  *  - every integral uses the tensor Gauss rule with m = k + 1 + quad_extra
  *    points per direction (quad_extra = 2 is the raised rule q = 2p + 4 of
  *    Problem B, Sec. 5.1; 0 the rule of Problem A);
@@ -75,7 +81,66 @@ typedef struct {
   int32_t kappa_poly_on; /* 1: D(x) = kappa_T kp(x) K, kp from kappa_poly */
   double kappa_poly[9];
   int32_t quad_extra;    /* Gauss points per direction m = k + 1 + quad_extra */
+  int32_t affine_on;     /* 1: the mesh is the image x = A xi of the tensor grid xi */
+  double affine[9];      /* A, row-major */
 } or_problem;
+
+/* Geometry of the affine map x = A xi (identity unless affine_on): physical
+ * gradients are A^{-T} times the gradients in xi; volumes scale by |det A|;
+ * the face of a xi-cell normal to e_a has unit normal nu = A^{-T} e_a /
+ * |A^{-T} e_a| and |det A| |A^{-T} e_a| area per unit xi-area, so that
+ * |F| / |T| = |A^{-T} e_a| / h_a. */
+typedef struct {
+  double AiT[9]; /* A^{-T}, row-major */
+  double det;    /* |det A| */
+} or_geom;
+
+static void geom_init(const or_problem *p, or_geom *G) {
+  if (!p->affine_on) {
+    for (int i = 0; i < 9; ++i) G->AiT[i] = (i % 4 == 0) ? 1.0 : 0.0;
+    G->det = 1.0;
+    return;
+  }
+  const double *A = p->affine;
+  const double c00 = A[4] * A[8] - A[5] * A[7], c01 = A[5] * A[6] - A[3] * A[8], c02 = A[3] * A[7] - A[4] * A[6];
+  const double c10 = A[2] * A[7] - A[1] * A[8], c11 = A[0] * A[8] - A[2] * A[6], c12 = A[1] * A[6] - A[0] * A[7];
+  const double c20 = A[1] * A[5] - A[2] * A[4], c21 = A[2] * A[3] - A[0] * A[5], c22 = A[0] * A[4] - A[1] * A[3];
+  const double det = A[0] * c00 + A[1] * c01 + A[2] * c02;
+  /* A^{-1} = C^T / det (C the cofactor matrix), so A^{-T} = C / det */
+  const double C[9] = {c00, c01, c02, c10, c11, c12, c20, c21, c22};
+  for (int i = 0; i < 9; ++i) G->AiT[i] = C[i] / det;
+  G->det = fabs(det);
+}
+
+/* g <- A^{-T} g */
+static void geom_grad(const or_geom *G, double *g) {
+  const double r0 = G->AiT[0] * g[0] + G->AiT[1] * g[1] + G->AiT[2] * g[2];
+  const double r1 = G->AiT[3] * g[0] + G->AiT[4] * g[1] + G->AiT[5] * g[2];
+  const double r2 = G->AiT[6] * g[0] + G->AiT[7] * g[1] + G->AiT[8] * g[2];
+  g[0] = r0;
+  g[1] = r1;
+  g[2] = r2;
+}
+
+/* x <- A x (the physical point of a tensor-grid point) */
+static void geom_point(const or_problem *p, double *x) {
+  if (!p->affine_on) return;
+  const double *A = p->affine;
+  const double r0 = A[0] * x[0] + A[1] * x[1] + A[2] * x[2];
+  const double r1 = A[3] * x[0] + A[4] * x[1] + A[5] * x[2];
+  const double r2 = A[6] * x[0] + A[7] * x[1] + A[8] * x[2];
+  x[0] = r0;
+  x[1] = r1;
+  x[2] = r2;
+}
+
+/* unit normal nu = A^{-T} e_a / |A^{-T} e_a|; returns |A^{-T} e_a| */
+static double geom_normal(const or_geom *G, int a, double *nu) {
+  const double v[3] = {G->AiT[a], G->AiT[3 + a], G->AiT[6 + a]};
+  const double nrm = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  for (int r = 0; r < 3; ++r) nu[r] = v[r] / nrm;
+  return nrm;
+}
 
 /* term mask for or_apply: which sums of eq. (blf) to include */
 #define OR_VOLUME 1
@@ -205,7 +270,9 @@ static void volume_cell(const or_problem *p, const or_tables *t, const int *ic,
   const int n = t->n, m = t->m;
   double o[3], h[3];
   cell_geom(p, ic, o, h);
-  const double vol = h[0] * h[1] * h[2];
+  or_geom G;
+  geom_init(p, &G);
+  const double vol = h[0] * h[1] * h[2] * G.det;
   const double kap = cell_kappa(p, cell_id(p, ic));
   for (int q3 = 0; q3 < m; ++q3)
     for (int q2 = 0; q2 < m; ++q2)
@@ -225,8 +292,10 @@ static void volume_cell(const or_problem *p, const or_tables *t, const int *ic,
               g[1] += xj * v1 * d2 * v3 / h[1];
               g[2] += xj * v1 * v2 * d3 / h[2];
             }
+        geom_grad(&G, g);
         double xp[3];
         for (int a = 0; a < 3; ++a) xp[a] = o[a] + h[a] * t->xi[q[a]];
+        geom_point(p, xp);
         const double kx = kap * coef_kp(p, xp); /* D = kx K at this point */
         double F[3];
         for (int r = 0; r < 3; ++r) {
@@ -242,8 +311,8 @@ static void volume_cell(const or_problem *p, const or_tables *t, const int *ic,
               const double v1 = t->V[q1][j1], v2 = t->V[q2][j2], v3 = t->V[q3][j3];
               const double d1 = t->D[q1][j1], d2 = t->D[q2][j2], d3 = t->D[q3][j3];
               const double phi = v1 * v2 * v3;
-              const double gphi[3] = {d1 * v2 * v3 / h[0], v1 * d2 * v3 / h[1],
-                                      v1 * v2 * d3 / h[2]};
+              double gphi[3] = {d1 * v2 * v3 / h[0], v1 * d2 * v3 / h[1], v1 * v2 * d3 / h[2]};
+              geom_grad(&G, gphi);
               yT[j1 + n * (j2 + n * j3)] +=
                   W * (F[0] * gphi[0] + F[1] * gphi[1] + F[2] * gphi[2] + p->c * u * phi);
             }
@@ -253,7 +322,7 @@ static void volume_cell(const or_problem *p, const or_tables *t, const int *ic,
 /* Value and physical gradient of the shape function j of a cell at the face
  * point with reference coordinate e on axis a (e in {0,1}) and Gauss nodes
  * qt[0], qt[1] on the two tangential axes tb < tc. */
-static void shape_on_face(const or_tables *t, int a, int e, int tb, int tc, int qb, int qc,
+static void shape_on_face(const or_geom *G, const or_tables *t, int a, int e, int tb, int tc, int qb, int qc,
                           const int *j, const double *h, double *phi, double *gphi) {
   double val[3], der[3];
   val[a] = e ? t->V1[j[a]] : t->V0[j[a]];
@@ -266,10 +335,11 @@ static void shape_on_face(const or_tables *t, int a, int e, int tb, int tc, int 
   gphi[0] = der[0] * val[1] * val[2] / h[0];
   gphi[1] = val[0] * der[1] * val[2] / h[1];
   gphi[2] = val[0] * val[1] * der[2] / h[2];
+  geom_grad(G, gphi);
 }
 
 /* u and physical gradient of the FE function of one cell at a face point */
-static void eval_on_face(const or_tables *t, int a, int e, int tb, int tc, int qb, int qc,
+static void eval_on_face(const or_geom *G, const or_tables *t, int a, int e, int tb, int tc, int qb, int qc,
                          const double *h, const double *xT, double *u, double *g) {
   const int n = t->n;
   *u = 0.0;
@@ -279,7 +349,7 @@ static void eval_on_face(const or_tables *t, int a, int e, int tb, int tc, int q
       for (int j1 = 0; j1 < n; ++j1) {
         const int j[3] = {j1, j2, j3};
         double phi, gphi[3];
-        shape_on_face(t, a, e, tb, tc, qb, qc, j, h, &phi, gphi);
+        shape_on_face(G, t, a, e, tb, tc, qb, qc, j, h, &phi, gphi);
         const double xj = xT[j1 + n * (j2 + n * j3)];
         *u += xj * phi;
         for (int r = 0; r < 3; ++r) g[r] += xj * gphi[r];
@@ -308,32 +378,39 @@ static void interior_face(const or_problem *p, const or_tables *t, int a, const 
   cell_geom(p, im, om, hm);
   cell_geom(p, ip, op, hp);
   const double km = cell_kappa(p, cell_id(p, im)), kp = cell_kappa(p, cell_id(p, ip));
-  const double Kaa = p->K[4 * a];
+  /* unit normal nu from T^- to T^+, nu^T K and nu^T K nu; |F| / |T| = nrm / h_a */
+  or_geom G;
+  geom_init(p, &G);
+  double nu[3], nK[3];
+  const double nrm = geom_normal(&G, a, nu);
+  for (int s2 = 0; s2 < 3; ++s2) nK[s2] = nu[0] * p->K[s2] + nu[1] * p->K[3 + s2] + nu[2] * p->K[6 + s2];
+  const double Knn = nK[0] * nu[0] + nK[1] * nu[1] + nK[2] * nu[2];
   const double hmin = hm[a] < hp[a] ? hm[a] : hp[a];
-  const double area = hm[tb] * hm[tc];
+  const double area = hm[tb] * hm[tc] * G.det * nrm;
   for (int qc = 0; qc < m; ++qc)
     for (int qb = 0; qb < m; ++qb) {
       double um, gm[3], up, gp[3];
-      eval_on_face(t, a, 1, tb, tc, qb, qc, hm, xm, &um, gm);
-      eval_on_face(t, a, 0, tb, tc, qb, qc, hp, xp_, &up, gp);
+      eval_on_face(&G, t, a, 1, tb, tc, qb, qc, hm, xm, &um, gm);
+      eval_on_face(&G, t, a, 0, tb, tc, qb, qc, hp, xp_, &up, gp);
       /* physical face point (on the plane x_a = node) */
       double X[3];
       X[a] = op[a];
       X[tb] = om[tb] + hm[tb] * t->xi[qb];
       X[tc] = om[tc] + hm[tc] * t->xi[qc];
-      const double bnu = coef_b(p, a, X);
+      geom_point(p, X);
+      const double bnu = coef_b(p, 0, X) * nu[0] + coef_b(p, 1, X) * nu[1] + coef_b(p, 2, X) * nu[2];
       const double Phi = (bnu >= 0.0) ? bnu * um : bnu * up;
       const double J = um - up;
       /* D^- = kmx K, D^+ = kpx K at the point; d, the weights and gamma there */
       const double kpoly = coef_kp(p, X);
       const double kmx = km * kpoly, kpx = kp * kpoly;
-      const double dmx = kmx * Kaa, dpx = kpx * Kaa;
+      const double dmx = kmx * Knn, dpx = kpx * Knn;
       const double wmx = dpx / (dmx + dpx), wpx = dmx / (dmx + dpx);
-      const double gammax = p->sigma * (2.0 * dmx * dpx / (dmx + dpx)) / hmin;
+      const double gammax = p->sigma * (2.0 * dmx * dpx / (dmx + dpx)) * nrm / hmin;
       double Dgm = 0.0, Dgp = 0.0; /* nu . (D grad u^-), nu . (D grad u^+) */
       for (int s = 0; s < 3; ++s) {
-        Dgm += kmx * p->K[3 * a + s] * gm[s];
-        Dgp += kpx * p->K[3 * a + s] * gp[s];
+        Dgm += kmx * nK[s] * gm[s];
+        Dgp += kpx * nK[s] * gp[s];
       }
       const double avg = wmx * Dgm + wpx * Dgp;
       const double W = t->w[qb] * t->w[qc] * area;
@@ -345,17 +422,17 @@ static void interior_face(const or_problem *p, const or_tables *t, int a, const 
             if (ym) {
               /* test function on T^-: [[v]] = v, {D grad v}_w = w- D- grad v */
               double phi, gphi[3];
-              shape_on_face(t, a, 1, tb, tc, qb, qc, j, hm, &phi, gphi);
+              shape_on_face(&G, t, a, 1, tb, tc, qb, qc, j, hm, &phi, gphi);
               double Dgv = 0.0;
-              for (int s = 0; s < 3; ++s) Dgv += kmx * p->K[3 * a + s] * gphi[s];
+              for (int s = 0; s < 3; ++s) Dgv += kmx * nK[s] * gphi[s];
               ym[jj] += W * (Phi * phi - avg * phi - wmx * Dgv * J + gammax * J * phi);
             }
             if (yp) {
               /* test function on T^+: [[v]] = -v, {D grad v}_w = w+ D+ grad v */
               double phi, gphi[3];
-              shape_on_face(t, a, 0, tb, tc, qb, qc, j, hp, &phi, gphi);
+              shape_on_face(&G, t, a, 0, tb, tc, qb, qc, j, hp, &phi, gphi);
               double Dgv = 0.0;
-              for (int s = 0; s < 3; ++s) Dgv += kpx * p->K[3 * a + s] * gphi[s];
+              for (int s = 0; s < 3; ++s) Dgv += kpx * nK[s] * gphi[s];
               yp[jj] += W * (-Phi * phi + avg * phi - wpx * Dgv * J - gammax * J * phi);
             }
           }
@@ -376,21 +453,29 @@ static void boundary_face(const or_problem *p, const or_tables *t, int a, int e,
   cell_geom(p, ic, o, h);
   const double kap = cell_kappa(p, cell_id(p, ic));
   const double nsign = e ? 1.0 : -1.0;
-  const double area = h[tb] * h[tc];
+  /* nu = nsign A^{-T} e_a / |A^{-T} e_a| (outer); nK = nu^T K up to the sign */
+  or_geom G;
+  geom_init(p, &G);
+  double nu[3], nK[3];
+  const double nrm = geom_normal(&G, a, nu);
+  for (int s2 = 0; s2 < 3; ++s2) nK[s2] = nu[0] * p->K[s2] + nu[1] * p->K[3 + s2] + nu[2] * p->K[6 + s2];
+  const double Knn = nK[0] * nu[0] + nK[1] * nu[1] + nK[2] * nu[2];
+  const double area = h[tb] * h[tc] * G.det * nrm;
   for (int qc = 0; qc < m; ++qc)
     for (int qb = 0; qb < m; ++qb) {
       double u, g[3];
-      eval_on_face(t, a, e, tb, tc, qb, qc, h, xT, &u, g);
+      eval_on_face(&G, t, a, e, tb, tc, qb, qc, h, xT, &u, g);
       double X[3];
       X[a] = o[a] + (e ? h[a] : 0.0);
       X[tb] = o[tb] + h[tb] * t->xi[qb];
       X[tc] = o[tc] + h[tc] * t->xi[qc];
-      const double bnu = nsign * coef_b(p, a, X);
+      geom_point(p, X);
+      const double bnu = nsign * (coef_b(p, 0, X) * nu[0] + coef_b(p, 1, X) * nu[1] + coef_b(p, 2, X) * nu[2]);
       const double Phi = (bnu >= 0.0) ? bnu * u : 0.0;
       const double kx = kap * coef_kp(p, X); /* D = kx K at the point */
-      const double gammax = p->sigma * kx * p->K[4 * a] / h[a];
+      const double gammax = p->sigma * kx * Knn * nrm / h[a];
       double Dg = 0.0;
-      for (int s = 0; s < 3; ++s) Dg += kx * p->K[3 * a + s] * g[s];
+      for (int s = 0; s < 3; ++s) Dg += kx * nK[s] * g[s];
       Dg *= nsign;
       const double W = t->w[qb] * t->w[qc] * area;
       for (int j3 = 0; j3 < n; ++j3)
@@ -398,9 +483,9 @@ static void boundary_face(const or_problem *p, const or_tables *t, int a, int e,
           for (int j1 = 0; j1 < n; ++j1) {
             const int j[3] = {j1, j2, j3};
             double phi, gphi[3];
-            shape_on_face(t, a, e, tb, tc, qb, qc, j, h, &phi, gphi);
+            shape_on_face(&G, t, a, e, tb, tc, qb, qc, j, h, &phi, gphi);
             double Dgv = 0.0;
-            for (int s = 0; s < 3; ++s) Dgv += kx * p->K[3 * a + s] * gphi[s];
+            for (int s = 0; s < 3; ++s) Dgv += kx * nK[s] * gphi[s];
             Dgv *= nsign;
             yT[j1 + n * (j2 + n * j3)] += W * (Phi * phi - Dg * phi - Dgv * u + gammax * u * phi);
           }
@@ -546,7 +631,7 @@ static double sep_eval(int nterms, const double *alpha, const int32_t *kinds, co
 
 int oracle_rhs(const or_problem *p, int nterms, const double *alpha, const int32_t *kinds,
                double *f, int nthreads) {
-  if (check_problem(p)) return -1;
+  if (check_problem(p) || p->affine_on) return -1; /* tensor-grid sources only */
   or_tables t;
   make_tables(p->k, p->quad_extra, &t);
   const int n = t.n, m = t.m;
@@ -583,7 +668,7 @@ int oracle_rhs(const or_problem *p, int nterms, const double *alpha, const int32
  * polynomial part, accurate for the smooth part). */
 double oracle_l2err2(const or_problem *p, const double *x, int nterms, const double *alpha,
                      const int32_t *kinds) {
-  if (check_problem(p)) return -1.0;
+  if (check_problem(p) || p->affine_on) return -1.0;
   const int n = p->k + 1, mq = p->k + 3;
   double xi[OR_MAXN + 2], w[OR_MAXN + 2];
   oracle_gauss(mq, xi, w);

@@ -59,6 +59,8 @@ class Problem:
     kappa_poly: tuple | None = None
     # Gauss points per direction m = k + 1 + quad_extra (2: the raised rule q = 2p + 4)
     quad_extra: int = 0
+    # affine geometry: the mesh is x = A xi of the tensor grid xi of the nodes (None: A = I)
+    affine: np.ndarray | None = None
     name: str = ""
     meta: dict = field(default_factory=dict)
 

@@ -83,6 +83,14 @@ def assemble_dense(prob) -> np.ndarray:
     V1, D1 = _basis_1d(k, np.array([1.0]))
     K = np.asarray(prob.K, dtype=np.float64)
     kap = np.ones(nc) if prob.kappa is None else np.asarray(prob.kappa).ravel()
+    # affine map x = A xi of the tensor grid: gradients A^{-T} grad_xi, measures |det A|
+    Aff = getattr(prob, "affine", None)
+    Aff = np.eye(3) if Aff is None else np.asarray(Aff, dtype=np.float64).reshape(3, 3)
+    AiT = np.linalg.inv(Aff).T
+    detA = abs(np.linalg.det(Aff))
+
+    def phys(g):
+        return np.einsum("rs,pjs->pjr", AiT, g)
 
     def cid(i):
         return i[0] + N[0] * (i[1] + N[1] * i[2])
@@ -101,9 +109,10 @@ def assemble_dense(prob) -> np.ndarray:
         o, h = geom(i)
         c = cid(i)
         phi, g = _tensor_shape([Vq] * 3, [Dq] * 3, h)
-        Wq = np.einsum("a,b,c->cba", w, w, w).ravel() * np.prod(h)
+        g = phys(g)
+        Wq = np.einsum("a,b,c->cba", w, w, w).ravel() * np.prod(h) * detA
         Xq = np.stack(np.meshgrid(o[0] + h[0] * xi, o[1] + h[1] * xi, o[2] + h[2] * xi,
-                                  indexing="ij"), axis=-1).transpose(2, 1, 0, 3).reshape(-1, 3)
+                                  indexing="ij"), axis=-1).transpose(2, 1, 0, 3).reshape(-1, 3) @ Aff.T
         bq = _b(prob, Xq)
         Dg = kap[c] * _kp(prob, Xq)[:, None, None] * np.einsum("rs,pjs->pjr", K, g)  # D grad phi_j
         flux = Dg - bq[:, None, :] * phi[:, :, None]              # (P, j, 3)
@@ -118,7 +127,8 @@ def assemble_dense(prob) -> np.ndarray:
         ders = list(ders)
         vals[a] = V1 if e == 1 else V0
         ders[a] = D1 if e == 1 else D0
-        return _tensor_shape(vals, ders, h)
+        ph, gr = _tensor_shape(vals, ders, h)
+        return ph, phys(gr)
 
     def face_weights(a, h):
         ws = [w, w, w]
@@ -130,7 +140,12 @@ def assemble_dense(prob) -> np.ndarray:
     def face_points(a, o, h, xa):
         pts = [o[b] + h[b] * xi for b in range(3)]
         pts[a] = np.array([xa])
-        return np.stack(np.meshgrid(*pts, indexing="ij"), axis=-1).transpose(2, 1, 0, 3).reshape(-1, 3)
+        return np.stack(np.meshgrid(*pts, indexing="ij"), axis=-1).transpose(2, 1, 0, 3).reshape(-1, 3) @ Aff.T
+
+    def normal(a):
+        """unit normal A^{-T} e_a / |A^{-T} e_a| and |A^{-T} e_a|"""
+        v = AiT[:, a]
+        return v / np.linalg.norm(v), np.linalg.norm(v)
 
     per = getattr(prob, "periodic", (False, False, False))
     for i in cells:
@@ -144,13 +159,15 @@ def assemble_dense(prob) -> np.ndarray:
                 ip[a] = (i[a] + 1) % N[a]
                 op, hp = geom(ip)
                 cp = cid(ip)
-                W = face_weights(a, h)
+                nu, nrm = normal(a)
+                W = face_weights(a, h) * detA * nrm
                 X = face_points(a, o, h, op[a])
-                bnu = _b(prob, X)[:, a]
+                bnu = _b(prob, X) @ nu
                 kpf = _kp(prob, X)                      # pointwise diffusion factor
-                dm, dp = kap[c] * kpf * K[a, a], kap[cp] * kpf * K[a, a]
+                Knn = nu @ K @ nu
+                dm, dp = kap[c] * kpf * Knn, kap[cp] * kpf * Knn
                 wm, wp = dp / (dm + dp), dm / (dm + dp)
-                gam = prob.sigma * (2 * dm * dp / (dm + dp)) / min(h[a], hp[a])
+                gam = prob.sigma * (2 * dm * dp / (dm + dp)) * nrm / min(h[a], hp[a])
                 side = {0: (c, *face_tables(a, 1, h), kap[c] * kpf), 1: (cp, *face_tables(a, 0, hp), kap[cp] * kpf)}
                 for su in (0, 1):        # trial function side (0: minus, 1: plus)
                     for sv in (0, 1):    # test function side
@@ -159,10 +176,10 @@ def assemble_dense(prob) -> np.ndarray:
                         um = phu if su == 0 else 0 * phu
                         up = phu if su == 1 else 0 * phu
                         jump_u = um - up
-                        avg_u = ((wm if su == 0 else wp) * ku)[:, None] * np.einsum("s,pjs->pj", K[a], gu)
+                        avg_u = ((wm if su == 0 else wp) * ku)[:, None] * np.einsum("s,pjs->pj", nu @ K, gu)
                         Phi = np.where(bnu[:, None] >= 0, bnu[:, None] * um, bnu[:, None] * up)
                         jump_v = phv if sv == 0 else -phv
-                        avg_v = ((wm if sv == 0 else wp) * kv)[:, None] * np.einsum("s,pis->pi", K[a], gv)
+                        avg_v = ((wm if sv == 0 else wp) * kv)[:, None] * np.einsum("s,pis->pi", nu @ K, gv)
                         M = (np.einsum("p,pj,pi->ij", W, Phi, jump_v)
                              - np.einsum("p,pj,pi->ij", W, avg_u, jump_v)
                              - np.einsum("p,pi,pj->ij", W, avg_v, jump_u)
@@ -172,15 +189,16 @@ def assemble_dense(prob) -> np.ndarray:
                 at_bnd = (i[a] == 0) if e == 0 else (i[a] == N[a] - 1)
                 if not at_bnd or per[a]:
                     continue
-                W = face_weights(a, h)
+                nu, nrm = normal(a)
+                W = face_weights(a, h) * detA * nrm
                 X = face_points(a, o, h, o[a] + (h[a] if e == 1 else 0.0))
                 nsg = 1.0 if e == 1 else -1.0
-                bnu = nsg * _b(prob, X)[:, a]
+                bnu = nsg * (_b(prob, X) @ nu)
                 kpf = _kp(prob, X)
-                delta = kap[c] * kpf * K[a, a]
-                gam = prob.sigma * delta / h[a]
+                delta = kap[c] * kpf * (nu @ K @ nu)
+                gam = prob.sigma * delta * nrm / h[a]
                 ph, g = face_tables(a, e, h)
-                Dn = nsg * (kap[c] * kpf)[:, None] * np.einsum("s,pjs->pj", K[a], g)
+                Dn = nsg * (kap[c] * kpf)[:, None] * np.einsum("s,pjs->pj", nu @ K, g)
                 Phi = np.where(bnu[:, None] >= 0, bnu[:, None] * ph, 0.0)
                 M = (np.einsum("p,pj,pi->ij", W, Phi, ph)
                      - np.einsum("p,pj,pi->ij", W, Dn, ph)

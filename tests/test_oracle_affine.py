@@ -1,0 +1,78 @@
+"""Pins of the oracle's affine geometry (the mesh is the image x = A xi of the
+tensor grid of the nodes; Problem B of Sec. 5.1 uses affine cells), CPU only.
+
+* the independent numpy brute-force assembly, written from the same
+  definition (physical gradients, unit normals, surface measures, d = nu^T D nu,
+  |F| / min|T| in gamma_F), agrees, with Dirichlet and periodic axes;
+* A = diag(s) is the tensor grid with nodes scaled by s;
+* a rotation R of the mesh together with K -> R K R^T and b -> R b leaves
+  the operator unchanged (invariance of the form under rigid motions);
+* for constant b the operator equals the tensor-grid operator with
+  K' = |det A| A^{-1} K A^{-T}, b' = |det A| A^{-1} b, c' = |det A| c (the
+  change of variables x = A xi in every volume and face integral).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1711_10885_amd import workloads as W
+from tests.ref_assemble import assemble_dense
+
+SHEAR = np.array([[1.0, 0.35, 0.0], [0.0, 1.0, -0.2], [0.0, 0.0, 1.0]])
+GENERAL = np.array([[1.2, 0.3, -0.1], [0.1, 0.8, 0.25], [-0.2, 0.15, 1.1]])
+
+
+def _rot(ax, ang):
+    c, s = math.cos(ang), math.sin(ang)
+    R = np.eye(3)
+    i, j = [(1, 2), (0, 2), (0, 1)][ax]
+    R[i, i] = R[j, j] = c
+    R[i, j], R[j, i] = -s, s
+    return R
+
+
+@pytest.mark.parametrize("A,b,per,k", [
+    (SHEAR, "const", (False, False, False), 1),
+    (GENERAL, "const", (True, False, True), 2),
+    (GENERAL, "sine", (False, True, False), 1),
+])
+def test_assemble_matches_brute_force(A, b, per, k):
+    p = W.random_problem(2000 + k, ncell=(2, 3, 2), k=k, b=b, periodic=per).with_(affine=A)
+    M = oracle.assemble(p).toarray()
+    ref = assemble_dense(p)
+    err = np.abs(M - ref).max() / np.abs(ref).max()
+    print(f"affine b={b} per={per} k={k}: max rel {err:.2e}")
+    assert err <= 1e-13
+
+
+def test_diagonal_map_is_a_scaled_tensor_grid():
+    p = W.random_problem(2010, ncell=(3, 2, 2), k=2, b="const")
+    s = np.array([1.7, 0.6, 1.3])
+    q = p.with_(nodes=tuple(np.asarray(p.nodes[a]) * s[a] for a in range(3)))
+    x = W.random_vector(p.ndof, 2011)
+    y1, y2 = oracle.apply(p.with_(affine=np.diag(s)), x), oracle.apply(q, x)
+    assert np.abs(y1 - y2).max() <= 1e-12 * np.abs(y2).max()
+
+
+def test_rotation_invariance():
+    p = W.random_problem(2020, ncell=(2, 2, 3), k=3, b="const", periodic=(True, False, False))
+    R = _rot(2, 0.4) @ _rot(0, -0.7)
+    K = np.asarray(p.K)
+    q = p.with_(affine=R, K=R @ K @ R.T, b_const=tuple(R @ np.asarray(p.b_const)))
+    x = W.random_vector(p.ndof, 2021)
+    y1, y2 = oracle.apply(q, x), oracle.apply(p, x)
+    assert np.abs(y1 - y2).max() <= 1e-12 * np.abs(y2).max()
+
+
+@pytest.mark.parametrize("A", [SHEAR, GENERAL])
+def test_transformed_coefficients_give_the_same_operator(A):
+    p = W.random_problem(2030, ncell=(3, 2, 2), k=3, b="const", periodic=(False, True, False))
+    det = abs(np.linalg.det(A))
+    Ai = np.linalg.inv(A)
+    q = p.with_(K=det * Ai @ np.asarray(p.K) @ Ai.T, b_const=tuple(det * Ai @ np.asarray(p.b_const)),
+                c=det * p.c)
+    x = W.random_vector(p.ndof, 2031)
+    y1, y2 = oracle.apply(p.with_(affine=A), x), oracle.apply(q, x)
+    assert np.abs(y1 - y2).max() <= 1e-12 * np.abs(y2).max()
