@@ -124,6 +124,18 @@ typedef enum {
  *              operator runs on the reference-layout kernel (one workgroup
  *              per cell, rectangular (k+3) x (k+1) contractions through LDS);
  *              dg_apply_f32 and GMRES-IR return DG_EINVAL.
+ *   affine     with DG_AFFINE the mesh is the image x = A xi of the tensor
+ *              grid xi of the nodes (affine cells, Problem B of Sec. 5.1):
+ *              gradients, normals, face and cell measures, d = nu^T D nu and
+ *              |F| / min|T| in gamma_F are those of the physical cells.  The
+ *              change of variables x = A xi turns every volume and face
+ *              integral into the tensor-grid one with K' = |det A| A^-1 K A^-T,
+ *              b' = |det A| A^-1 b, c' = |det A| c, which setup applies, so the
+ *              tuned kernels run unchanged.  Requires A finite and invertible,
+ *              b constant (b_sin = 0, no DG_B_PRODUCT) and no DG_KAPPA_POLY
+ *              (coefficients varying in x would not stay separable in xi):
+ *              DG_EINVAL otherwise.  dg_load_vector rejects such handles;
+ *              dg_heun uses the physical cell volumes.
  */
 typedef struct {
   int32_t ncell[3];
@@ -142,6 +154,7 @@ typedef struct {
   double b_phase[9];
   double kappa_poly[9];  /* polynomial diffusion factor (DG_KAPPA_POLY only) */
   int32_t quad_extra;    /* Gauss points per direction m = k + 1 + quad_extra */
+  double affine[9];      /* A of the affine map x = A xi (DG_AFFINE only), row-major */
 } dg_problem;
 
 #define DG_WITH_BLOCK_JACOBI 2
@@ -150,6 +163,7 @@ typedef struct {
 #define DG_PERIODIC_Z 16
 #define DG_B_PRODUCT 32
 #define DG_KAPPA_POLY 64
+#define DG_AFFINE 128
 
 /* Create a handle on the current HIP device: validates the problem, builds
  * the 1D Gauss-Legendre/Legendre tables (Sec. 3.1/3.2, eq.

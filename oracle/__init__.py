@@ -311,9 +311,12 @@ def assemble(prob, terms: int = ALL_TERMS, nthreads: int | None = None):
 
 
 def cell_volumes(prob) -> np.ndarray:
-    """|T| per cell (cell order: axis 1 fastest)."""
+    """|T| per cell (cell order: axis 1 fastest); |det A| times the tensor-grid
+    volume on an affine mesh x = A xi."""
     h = [np.diff(np.asarray(prob.nodes[a], dtype=np.float64)) for a in range(3)]
-    return np.einsum("k,j,i->kji", h[2], h[1], h[0]).ravel()
+    vol = np.einsum("k,j,i->kji", h[2], h[1], h[0]).ravel()
+    A = getattr(prob, "affine", None)
+    return vol if A is None else vol * abs(np.linalg.det(np.asarray(A, dtype=np.float64)))
 
 
 def heun(prob, u0: np.ndarray, dt: float, nsteps: int, f: np.ndarray | None = None,

@@ -19,6 +19,7 @@ DG_WITH_BLOCK_JACOBI = 2
 DG_PERIODIC_X, DG_PERIODIC_Y, DG_PERIODIC_Z = 4, 8, 16
 DG_B_PRODUCT = 32
 DG_KAPPA_POLY = 64
+DG_AFFINE = 128
 DG_KERNEL_AUTO, DG_KERNEL_REFERENCE = 0, 1
 DG_GMRES64, DG_GMRES_IR, DG_FGMRES = 0, 1, 2
 DG_PREC_NONE, DG_PREC_BLOCK_JACOBI, DG_PREC_LEARNED = 0, 1, 2
@@ -58,6 +59,7 @@ class _Problem(ctypes.Structure):
         ("b_phase", ctypes.c_double * 9),
         ("kappa_poly", ctypes.c_double * 9),
         ("quad_extra", ctypes.c_int32),
+        ("affine", ctypes.c_double * 9),
     ]
 
 
@@ -214,6 +216,11 @@ class DG:
                 s.b_freq[t] = float(prob.b_freq[t])
                 s.b_phase[t] = float(prob.b_phase[t])
         s.quad_extra = int(getattr(prob, "quad_extra", 0))
+        aff = getattr(prob, "affine", None)
+        if aff is not None:
+            s.flags |= DG_AFFINE
+            for i, v in enumerate(np.asarray(aff, dtype=np.float64).ravel()):
+                s.affine[i] = float(v)
         kpoly = getattr(prob, "kappa_poly", None)
         if kpoly is not None:
             s.flags |= DG_KAPPA_POLY

@@ -156,10 +156,65 @@ extern "C" void dg_destroy(dg_handle *h) {
   delete h;
 }
 
-extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
+// Affine map x = A xi of the tensor grid: the change of variables in every
+// volume and face integral gives the tensor-grid operator with
+// K' = |det A| A^-1 K A^-T, b' = |det A| A^-1 b, c' = |det A| c (normals,
+// surface measures, d = nu^T D nu and |F|/|T| of the physical cells all
+// fold into these), which p receives; *vol_scale = |det A|.
+static dg_status fold_affine(dg_problem &p, double *vol_scale) {
+  const double *A = p.affine;
+  double mx = 0.0;
+  for (int i = 0; i < 9; ++i) {
+    if (!std::isfinite(A[i])) return set_error(DG_EINVAL, "dg_setup: the affine map must be finite");
+    mx = std::fmax(mx, std::fabs(A[i]));
+  }
+  if ((p.flags & (DG_B_PRODUCT | DG_KAPPA_POLY)) || p.b_sin[0] != 0.0 || p.b_sin[1] != 0.0 || p.b_sin[2] != 0.0)
+    return set_error(DG_EINVAL, "dg_setup: DG_AFFINE needs a constant b and no kappa_poly");
+  const double C[9] = {A[4] * A[8] - A[5] * A[7], A[5] * A[6] - A[3] * A[8], A[3] * A[7] - A[4] * A[6],
+                       A[2] * A[7] - A[1] * A[8], A[0] * A[8] - A[2] * A[6], A[1] * A[6] - A[0] * A[7],
+                       A[1] * A[5] - A[2] * A[4], A[2] * A[3] - A[0] * A[5], A[0] * A[4] - A[1] * A[3]};
+  const double det = A[0] * C[0] + A[1] * C[1] + A[2] * C[2];
+  if (!(std::fabs(det) > 1e-12 * mx * mx * mx)) return set_error(DG_EINVAL, "dg_setup: the affine map must be invertible");
+  double Ai[9];  // A^-1 = C^T / det
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) Ai[3 * i + j] = C[3 * j + i] / det;
+  const double s = std::fabs(det);
+  double AK[9], Kp[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double t = 0.0;
+      for (int l = 0; l < 3; ++l) t += Ai[3 * i + l] * p.K[3 * l + j];
+      AK[3 * i + j] = t;
+    }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double t = 0.0;
+      for (int l = 0; l < 3; ++l) t += AK[3 * i + l] * Ai[3 * j + l];
+      Kp[3 * i + j] = s * t;
+    }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) p.K[3 * i + j] = 0.5 * (Kp[3 * i + j] + Kp[3 * j + i]);
+  double bp[3];
+  for (int i = 0; i < 3; ++i) bp[i] = s * (Ai[3 * i] * p.b_const[0] + Ai[3 * i + 1] * p.b_const[1] + Ai[3 * i + 2] * p.b_const[2]);
+  for (int i = 0; i < 3; ++i) p.b_const[i] = bp[i];
+  p.c *= s;
+  p.flags &= ~DG_AFFINE;
+  *vol_scale = s;
+  return DG_OK;
+}
+
+extern "C" dg_status dg_setup(const dg_problem *p_in, dg_handle **out) {
   if (!out) return set_error(DG_EINVAL, "dg_setup: out is NULL");
   *out = nullptr;
-  if (!p) return set_error(DG_EINVAL, "dg_setup: problem is NULL");
+  if (!p_in) return set_error(DG_EINVAL, "dg_setup: problem is NULL");
+  // the problem the kernels see: an affine map folds into the coefficients
+  dg_problem pt = *p_in;
+  double vol_scale = 1.0;
+  if (pt.flags & DG_AFFINE) {
+    const dg_status st = fold_affine(pt, &vol_scale);
+    if (st != DG_OK) return st;
+  }
+  const dg_problem *p = &pt;
   if (p->k < 1 || p->k > 10) return set_error(DG_EINVAL, "dg_setup: k must be in 1..10");
   if (p->quad_extra != 0 && p->quad_extra != 2)
     return set_error(DG_EINVAL, "dg_setup: quad_extra must be 0 or 2");
@@ -254,6 +309,8 @@ extern "C" dg_status dg_setup(const dg_problem *p, dg_handle **out) {
   build_tables(p->k, h->tab);
   build_tables(p->k, h->tabq, n + p->quad_extra);
   h->quad_extra = p->quad_extra;
+  h->vol_scale = vol_scale;
+  h->affine = (p_in->flags & DG_AFFINE) != 0;
 
   // host staging of every device table, then one allocation + one copy
   // (coefficients at the Gauss coordinates of the operator's rule)

@@ -67,6 +67,8 @@ struct dg_handle {
   dgmf::Tables tab;   // (k+1)-point rule (load vector)
   dgmf::Tables tabq;  // the operator's rule, m = k + 1 + quad_extra points
   int quad_extra;
+  int affine;         // the mesh is an affine image of the tensor grid (folded into the coefficients)
+  double vol_scale;   // |det A|: physical cell volume over tensor-grid cell volume (1 if not affine)
   dgmf::DevMesh mesh;
   void *dev_block;  // single allocation backing the DevMesh arrays
   int variant;      // DG_KERNEL_*

@@ -65,6 +65,7 @@ extern "C" dg_status dg_load_vector(dg_handle *h, int32_t nterms, const double *
   if (!h) return set_error(DG_EINVAL, "dg_load_vector: handle is NULL");
   if (nterms < 1 || nterms > kMaxTerms) return set_error(DG_EINVAL, "dg_load_vector: nterms must be in 1..16");
   if (!alpha || !kinds || !f) return set_error(DG_EINVAL, "dg_load_vector: NULL argument");
+  if (h->affine) return set_error(DG_EINVAL, "dg_load_vector: separable sources are tensor-grid only, not affine meshes");
   LvArgs L;
   L.n = h->tab.n;
   L.nterms = nterms;

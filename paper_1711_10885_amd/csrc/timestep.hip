@@ -73,6 +73,7 @@ extern "C" dg_status dg_heun(dg_handle *h, double *u, const double *f, double dt
     }
   }
   const hipStream_t s = static_cast<hipStream_t>(stream);
+  dt /= h->vol_scale;  // |T| of the physical cells: |det A| times the tensor-grid volumes
   if (h->variant != DG_KERNEL_REFERENCE && !h->quad_extra) {
     double *u1 = h->ts;
     for (int step = 0; step < nsteps; ++step) {

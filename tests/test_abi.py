@@ -66,7 +66,7 @@ def _struct(prob, **over):
     (dict(K=np.array([[1, 0.5, 0], [0, 1, 0], [0, 0, 1.0]])), "symmetric"),
     (dict(b_axis0=3), "b_axis"),
     (dict(c=float("nan")), "c must be finite"),
-    (dict(flags=128), "unknown flag"),
+    (dict(flags=256), "unknown flag"),
     (dict(quad_extra=1), "quad_extra"),
     (dict(k=9, quad_extra=2), "raised quadrature supports"),
     (dict(k=8, flags=2), "block Jacobi supports"),
@@ -113,6 +113,28 @@ def test_setup_rejects_a_bad_kappa_polynomial(coef, msg):
         s.kappa_poly[t] = v
     h = ctypes.c_void_p()
     assert lib.dg_setup(ctypes.byref(s), ctypes.byref(h)) == binding.DG_EINVAL
+    assert msg in lib.dg_last_error().decode()
+    assert not h.value
+
+
+@pytest.mark.parametrize("case", ["singular", "nan", "sine_b", "kpoly"])
+def test_setup_rejects_invalid_affine_problems(case):
+    lib = _lib()
+    p = workloads.random_problem(70, ncell=(2, 2, 2), k=1, b="sine" if case == "sine_b" else "const")
+    flags = binding.DG_AFFINE | (binding.DG_KAPPA_POLY if case == "kpoly" else 0)
+    s, keep = _struct(p, flags=flags)
+    A = {"singular": [1, 2, 0, 2, 4, 0, 0, 0, 1], "nan": [1, 0, 0, 0, float("nan"), 0, 0, 0, 1]}.get(
+        case, [1, 0.3, 0, 0, 1, 0, 0, 0, 1])
+    for i, v in enumerate(A):
+        s.affine[i] = v
+    if case == "kpoly":
+        for t, v in enumerate((1.0, 0, 0, 1.0, 0, 0, 1.0, 0, 0)):
+            s.kappa_poly[t] = v
+    if case == "sine_b":
+        s.b_sin[0] = 1.0
+    h = ctypes.c_void_p()
+    assert lib.dg_setup(ctypes.byref(s), ctypes.byref(h)) == binding.DG_EINVAL
+    msg = {"singular": "invertible", "nan": "finite"}.get(case, "constant b")
     assert msg in lib.dg_last_error().decode()
     assert not h.value
 

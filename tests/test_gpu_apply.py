@@ -271,3 +271,25 @@ def test_raised_quadrature_has_no_fp32_operator():
         f = torch.ones(p.ndof, dtype=torch.float64, device="cuda")
         with pytest.raises(binding.DGError):
             dg.solve(f, method=binding.DG_GMRES_IR)
+
+
+AFFINE = np.array([[1.2, 0.3, -0.1], [0.1, 0.8, 0.25], [-0.2, 0.15, 1.1]])
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("k", [1, 2, 4, 7, 10])
+def test_affine_geometry(variant, k):
+    """The mesh as the image x = A xi of a tensor grid (affine cells): the GPU
+    runs the tensor-grid kernels with coefficients transformed at setup, the
+    oracle the physical geometry (normals, measures, |F|/|T|)."""
+    ncell = (3, 2, 2) if k <= 7 else (2, 2, 2)
+    p = W.random_problem(2100 + k, ncell=ncell, k=k, b="const", periodic=PERIODIC[k % 4]).with_(affine=AFFINE)
+    x = W.random_vector(p.ndof, 2110 + k)
+    _check(_gpu_apply(p, x, variant), oracle.apply(p, x), f"affine k={k} v{variant}")
+
+
+def test_affine_geometry_with_the_raised_rule():
+    p = W.random_problem(2120, ncell=(3, 2, 2), k=3, b="const", periodic=(True, False, False))
+    p = p.with_(affine=AFFINE, quad_extra=2)
+    x = W.random_vector(p.ndof, 2121)
+    _check(_gpu_apply(p, x, 0), oracle.apply(p, x), "affine q=2p+4")

@@ -284,3 +284,14 @@ def test_blocks_with_raised_quadrature():
     with binding.DG(p, flags=binding.DG_WITH_BLOCK_JACOBI) as dg:
         z = dg.precond_apply(torch.from_numpy(r).cuda()).cpu().numpy()
     _check_blocks(oracle.block_diagonal(p), r, z, "raised quadrature blocks")
+
+
+def test_blocks_on_an_affine_mesh():
+    torch = _torch()
+    from paper_1711_10885_amd import binding
+    A = np.array([[1.2, 0.3, -0.1], [0.1, 0.8, 0.25], [-0.2, 0.15, 1.1]])
+    p = W.random_problem(630, ncell=(3, 2, 2), k=3, b="const").with_(affine=A)
+    r = W.random_vector(p.ndof, 631)
+    with binding.DG(p, flags=binding.DG_WITH_BLOCK_JACOBI) as dg:
+        z = dg.precond_apply(torch.from_numpy(r).cuda()).cpu().numpy()
+    _check_blocks(oracle.block_diagonal(p), r, z, "affine blocks")

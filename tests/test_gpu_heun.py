@@ -202,6 +202,17 @@ def test_heun_with_raised_quadrature():
     _check(_gpu_heun(p, u0, dt, n), oracle.heun(p, u0, dt, n), u0, "q=2p+4 heun")
 
 
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_heun_on_an_affine_mesh(variant):
+    """The stage update divides by the physical cell volume |det A| |T_xi|."""
+    A = np.array([[1.2, 0.3, -0.1], [0.1, 0.8, 0.25], [-0.2, 0.15, 1.1]])
+    p = _mild(W.random_problem(1340, ncell=(3, 2, 2), k=3, b="const", c=0.3, periodic=(True, True, False)))
+    p = p.with_(affine=A)
+    u0 = W.random_vector(p.ndof, 1341)
+    dt, n = _dt(p), 4
+    _check(_gpu_heun(p, u0, dt, n, variant), oracle.heun(p, u0, dt, n), u0, f"affine heun v{variant}")
+
+
 @pytest.mark.parametrize("case", ["dt0", "dtnan", "dtneg", "nsteps", "overlap"])
 def test_invalid_arguments(case):
     torch = _torch()

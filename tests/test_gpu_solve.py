@@ -227,3 +227,19 @@ def test_solvers_with_pointwise_coefficients_on_periodic_meshes(method, coef):
     res = _oracle_rel_residual(p, u, f)
     print(f"{coef} {method}: rc {rc}, {st['iters']} steps, oracle residual {res:.2e}", flush=True)
     assert rc == 0 and res <= 1.05e-10
+
+
+def test_solve_on_an_affine_mesh_and_no_load_vector():
+    torch = _torch()
+    from paper_1711_10885_amd import binding
+    A = np.array([[1.0, 0.35, 0.0], [0.0, 1.0, -0.2], [0.0, 0.0, 1.0]])
+    p = W.random_problem(480, ncell=(4, 3, 2), k=2, b="const", periodic=(True, False, False)).with_(affine=A)
+    f = W.random_vector(p.ndof, 481)
+    with binding.DG(p, flags=binding.DG_WITH_BLOCK_JACOBI) as dg:
+        u, st, rc = dg.solve(torch.from_numpy(f).cuda(), tol=1e-10, method=binding.DG_GMRES_IR,
+                             precond=binding.DG_PREC_BLOCK_JACOBI)
+        with pytest.raises(binding.DGError):
+            dg.load_vector(W.constant_source(1.0))
+    res = _oracle_rel_residual(p, u.cpu().numpy(), f)
+    print(f"affine solve: rc {rc}, {st['iters']} steps, oracle residual {res:.2e}", flush=True)
+    assert rc == 0 and res <= 1.05e-10

@@ -76,3 +76,18 @@ def test_transformed_coefficients_give_the_same_operator(A):
     x = W.random_vector(p.ndof, 2031)
     y1, y2 = oracle.apply(p.with_(affine=A), x), oracle.apply(q, x)
     assert np.abs(y1 - y2).max() <= 1e-12 * np.abs(y2).max()
+
+
+def test_heun_conserves_mass_with_physical_volumes():
+    """c = 0 on a periodic affine mesh: sum_T |T| u_T0 with the physical volumes
+    |det A| |T_xi| is invariant under the Heun steps."""
+    p = W.random_problem(2040, ncell=(3, 2, 2), k=2, b="const", c=0.0, periodic=(True, True, True))
+    p = p.with_(affine=GENERAL, K=np.asarray(p.K) * 1e-3)
+    nb = (p.k + 1) ** 3
+    vol = oracle.cell_volumes(p)
+    assert np.allclose(vol.sum(), abs(np.linalg.det(GENERAL)))
+    u0 = W.random_vector(p.ndof, 2041)
+    u = oracle.heun(p, u0, 2e-3, 10)
+    m0, m1 = (vol * u0[::nb]).sum(), (vol * u[::nb]).sum()
+    assert abs(m1 - m0) <= 1e-13 * (vol * np.abs(u0[::nb])).sum()
+    assert np.abs(u - u0).max() > 1e-4
