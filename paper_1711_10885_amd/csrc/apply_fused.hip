@@ -1413,7 +1413,10 @@ static hipError_t launch_fused_n(const dg_handle *h, const T *x, T *y, hipStream
 template <typename T, bool HEUN, bool BP, bool KP>
 static hipError_t launch_fused_bp(const dg_handle *h, const T *x, T *y, hipStream_t s, const double *f, double dt,
                                   int stage) {
-  switch (h->k + 1) {
+  // the raised rule runs the kernel of degree k + 2 on vectors padded with
+  // zero modes (the hierarchical basis and the (k+3)-point rule of that
+  // degree give the raised-rule operator on the modes <= k)
+  switch (h->k + 1 + h->quad_extra) {
     case 2: return launch_fused_n<2, T, HEUN, BP, KP>(h, x, y, s, f, dt, stage);
     case 3: return launch_fused_n<3, T, HEUN, BP, KP>(h, x, y, s, f, dt, stage);
     case 4: return launch_fused_n<4, T, HEUN, BP, KP>(h, x, y, s, f, dt, stage);

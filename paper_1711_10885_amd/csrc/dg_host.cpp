@@ -151,6 +151,7 @@ extern "C" void dg_destroy(dg_handle *h) {
   if (h->bj_cells) (void)hipFree(h->bj_cells);
   if (h->bj_gblock) (void)hipFree(h->bj_gblock);
   if (h->ts) (void)hipFree(h->ts);
+  if (h->rq) (void)hipFree(h->rq);
   if (h->dev_block) (void)hipFree(h->dev_block);
   if (cur != h->device) (void)hipSetDevice(cur);
   delete h;
@@ -311,6 +312,8 @@ extern "C" dg_status dg_setup(const dg_problem *p_in, dg_handle **out) {
   h->quad_extra = p->quad_extra;
   h->vol_scale = vol_scale;
   h->affine = (p_in->flags & DG_AFFINE) != 0;
+  h->rq = nullptr;
+  h->rq_bytes = 0;
 
   // host staging of every device table, then one allocation + one copy
   // (coefficients at the Gauss coordinates of the operator's rule)
@@ -413,6 +416,18 @@ extern "C" dg_status dg_setup(const dg_problem *p_in, dg_handle **out) {
   std::memcpy(M.K, p->K, sizeof(M.K));
   M.c = p->c;
   M.sigma = p->sigma;
+  if (h->quad_extra) {
+    // raised rule: padded input and output of the degree-(k+2) kernel
+    const int mq = n + h->quad_extra;
+    const size_t bytes = 2 * size_t(h->ncells) * size_t(mq * mq * mq) * sizeof(double);
+    e = hipMalloc(&h->rq, bytes);
+    if (e != hipSuccess) {
+      h->rq = nullptr;
+      dg_destroy(h);
+      return hip_error(e, "dg_setup: raised-rule workspace");
+    }
+    h->rq_bytes = bytes;
+  }
   if (p->flags & DG_WITH_BLOCK_JACOBI) {
     const dg_status ds = build_block_jacobi(h, p);
     if (ds != DG_OK) {
@@ -427,9 +442,12 @@ extern "C" dg_status dg_setup(const dg_problem *p_in, dg_handle **out) {
 
 namespace dgmf {
 hipError_t apply_f64(const dg_handle *h, const double *x, double *y, hipStream_t s) {
-  // the raised rule runs on the reference-layout kernel only
-  return (h->variant == DG_KERNEL_REFERENCE || h->quad_extra) ? launch_apply_ref_f64(h, x, y, s)
-                                                              : launch_apply_fused_f64(h, x, y, s);
+  if (h->variant == DG_KERNEL_REFERENCE) return launch_apply_ref_f64(h, x, y, s);
+  return h->quad_extra ? apply_raised_f64(h, x, y, s) : launch_apply_fused_f64(h, x, y, s);
+}
+
+hipError_t apply_f32(const dg_handle *h, const float *x, float *y, hipStream_t s) {
+  return h->quad_extra ? apply_raised_f32(h, x, y, s) : launch_apply_fused_f32(h, x, y, s);
 }
 }  // namespace dgmf
 
@@ -483,13 +501,12 @@ extern "C" dg_status dg_apply_f32(dg_handle *h, const float *x, float *y, void *
   if (!x || !y) return set_error(DG_EINVAL, "dg_apply_f32: x or y is NULL");
   if (overlaps(x, y, size_t(h->ndof) * sizeof(float)))
     return set_error(DG_EINVAL, "dg_apply_f32: x and y overlap");
-  if (h->quad_extra) return set_error(DG_EINVAL, "dg_apply_f32: no FP32 operator with raised quadrature");
   int cur = -1;
   if (hipGetDevice(&cur) != hipSuccess || cur != h->device) {
     hipError_t e = hipSetDevice(h->device);
     if (e != hipSuccess) return hip_error(e, "dg_apply_f32: hipSetDevice");
   }
-  hipError_t e = launch_apply_fused_f32(h, x, y, static_cast<hipStream_t>(stream));
+  hipError_t e = apply_f32(h, x, y, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_error(e, "dg_apply_f32: kernel launch");
   return DG_OK;
 }

@@ -81,8 +81,6 @@ extern "C" dg_status dg_solve(dg_handle *h, const double *f, double *u, double t
     return set_error(DG_EINVAL, "dg_solve: orth must be DG_ORTH_CGS1 or DG_ORTH_CGS2");
   if (opt.method != DG_GMRES64 && opt.method != DG_GMRES_IR && opt.method != DG_FGMRES)
     return set_error(DG_EINVAL, "dg_solve: unknown method");
-  if (opt.method == DG_GMRES_IR && h->quad_extra)
-    return set_error(DG_EINVAL, "dg_solve: GMRES-IR needs the FP32 operator, which raised quadrature does not have");
   if (opt.method == DG_GMRES_IR && !(opt.inner_tol > 0.0 && opt.inner_tol < 1.0))
     return set_error(DG_EINVAL, "dg_solve: inner_tol must be in (0, 1)");
   if (opt.precond != DG_PREC_NONE && opt.precond != DG_PREC_BLOCK_JACOBI && opt.precond != DG_PREC_LEARNED)
@@ -204,7 +202,7 @@ extern "C" dg_status dg_solve(dg_handle *h, const double *f, double *u, double t
     stats.rel_resid = go.rel;
   } else {
     // GMRES-IR: FP64 residual and update, FP32 correction by one inner cycle
-    auto op = [h, s](const float *x, float *y) { return launch_apply_fused_f32(h, x, y, s); };
+    auto op = [h, s](const float *x, float *y) { return apply_f32(h, x, y, s); };
     // the inner FP32 solve reads the FP16 copy of the inverse blocks
     auto prec = [h, s](const float *v, float *z) { return bj_apply<float, float>(h, v, z, s, true); };
     go = GmresOut();

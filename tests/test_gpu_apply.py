@@ -260,17 +260,27 @@ def test_raised_quadrature_with_cellwise_coefficients():
     _check(_gpu_apply(p, x, 0), oracle.apply(p, x), "q=2p+4 cellwise")
 
 
-def test_raised_quadrature_has_no_fp32_operator():
+@pytest.mark.parametrize("k", [1, 4, 7])
+def test_raised_quadrature_fp32_operator_and_gmres_ir(k):
+    """The raised rule runs the FP32 tier too (the degree-(k+2) FP32 kernel on
+    padded vectors): the FP32 operator against the FP64 oracle with the FP32
+    error bar, and GMRES-IR to 1e-10 on the oracle's residual."""
     torch = _torch()
     from paper_1711_10885_amd import binding
-    p = W.random_problem(1940, ncell=(2, 2, 2), k=2).with_(quad_extra=2)
-    with binding.DG(p) as dg:
-        with pytest.raises(binding.DGError) as ei:
-            dg.apply_f32(torch.zeros(p.ndof, dtype=torch.float32, device="cuda"))
-        assert ei.value.status == binding.DG_EINVAL
-        f = torch.ones(p.ndof, dtype=torch.float64, device="cuda")
-        with pytest.raises(binding.DGError):
-            dg.solve(f, method=binding.DG_GMRES_IR)
+    p = W.random_problem(1940 + k, ncell=(2, 2, 2), k=k, b="product", periodic=(True, False, False))
+    p = p.with_(quad_extra=2, kappa_poly=W.random_kappa_poly(np.random.default_rng(1950 + k)))
+    x = W.random_vector(p.ndof, 1960 + k)
+    ref = oracle.apply(p, x)
+    with binding.DG(p, flags=binding.DG_WITH_BLOCK_JACOBI) as dg:
+        y = dg.apply_f32(torch.from_numpy(x).float().cuda()).double().cpu().numpy()
+        f = torch.from_numpy(W.random_vector(p.ndof, 1970 + k)).cuda()
+        u, st, rc = dg.solve(f, tol=1e-10, method=binding.DG_GMRES_IR, precond=binding.DG_PREC_BLOCK_JACOBI)
+        u, f = u.cpu().numpy(), f.cpu().numpy()
+    e = np.abs(y - ref).max() / np.abs(ref).max()
+    res = np.linalg.norm(f - oracle.apply(p, u)) / np.linalg.norm(f)
+    print(f"q=2p+4 fp32 k={k}: relmax {e:.2e}; GMRES-IR rc {rc}, {st['iters']} steps, residual {res:.2e}", flush=True)
+    assert e <= 30 * (k + 3) * 2.0 ** -24
+    assert rc == 0 and res <= 1.05e-10
 
 
 AFFINE = np.array([[1.2, 0.3, -0.1], [0.1, 0.8, 0.25], [-0.2, 0.15, 1.1]])
