@@ -52,3 +52,21 @@ def test_quadratic_diffusion_needs_one_more_point(k):
     y0 = oracle.apply(p, x)
     assert np.abs(y2 - y1).max() <= 1e-12 * np.abs(y1).max()
     assert np.abs(y0 - y1).max() > 1e-8 * np.abs(y1).max()
+
+
+@pytest.mark.parametrize("k,b", [(1, "product"), (2, "sine"), (3, "const")])
+def test_raised_rule_is_the_padded_higher_degree_operator(k, b):
+    """The hierarchical orthonormal basis: the operator of degree k with k+3
+    Gauss points equals the operator of degree k+2 (whose rule has k+3 points),
+    with the same penalty sigma, applied to x padded with zero modes and
+    restricted to the modes <= k.  This is what the GPU runs for the raised rule."""
+    p = W.random_problem(1870 + k, ncell=(2, 3, 2), k=k, b=b, periodic=(True, False, False))
+    p = p.with_(kappa_poly=W.random_kappa_poly(np.random.default_rng(1880 + k)))
+    n, m = k + 1, k + 3
+    x = W.random_vector(p.ndof, 1890 + k)
+    y = oracle.apply(p.with_(quad_extra=2), x)
+    big = p.with_(k=k + 2)  # sigma kept: it is a parameter of the form
+    xp = np.zeros((p.ncells, m, m, m))
+    xp[:, :n, :n, :n] = x.reshape(p.ncells, n, n, n)
+    yb = oracle.apply(big, xp.ravel()).reshape(p.ncells, m, m, m)[:, :n, :n, :n].ravel()
+    assert np.abs(y - yb).max() <= 1e-12 * np.abs(y).max()
