@@ -303,3 +303,22 @@ def test_affine_geometry_with_the_raised_rule():
     p = p.with_(affine=AFFINE, quad_extra=2)
     x = W.random_vector(p.ndof, 2121)
     _check(_gpu_apply(p, x, 0), oracle.apply(p, x), "affine q=2p+4")
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("case", ["raised_one_cell_axis", "raised_single_cell", "affine_one_cell_axis",
+                                  "product_single_cell"])
+def test_new_paths_on_degenerate_meshes(variant, case):
+    """Axes of one cell (periodic: the cell is its own face neighbour) and a
+    single cell, through the raised rule, affine geometry and product b."""
+    if case == "raised_one_cell_axis":
+        p = W.random_problem(2200, ncell=(1, 3, 2), k=3, b="product", periodic=(True, True, False))
+        p = p.with_(quad_extra=2, kappa_poly=W.random_kappa_poly(np.random.default_rng(2201)))
+    elif case == "raised_single_cell":
+        p = W.random_problem(2202, ncell=(1, 1, 1), k=5, b="sine").with_(quad_extra=2)
+    elif case == "affine_one_cell_axis":
+        p = W.random_problem(2203, ncell=(3, 1, 2), k=4, b="const", periodic=(False, True, True)).with_(affine=AFFINE)
+    else:
+        p = W.random_problem(2204, ncell=(1, 1, 1), k=6, b="product", periodic=(True, True, True))
+    x = W.random_vector(p.ndof, 2210)
+    _check(_gpu_apply(p, x, variant), oracle.apply(p, x), f"{case} v{variant}")
