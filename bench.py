@@ -59,6 +59,15 @@ def make_workload(name: str):
         return W.mixed_k5_48()
     if name == "learned_k3_64":
         return W.learned_k3_64()
+    if name == "transport_k5_64":
+        return W.transport_k5_64()
+    if name in ("affine_k7_32", "tensor_k7_32"):
+        # the k = 7 mesh with constant b, as a sheared affine image of the grid or the grid itself
+        import numpy as np
+        p = W.cdr_k7_32().with_(b_const=(1.0, 0.5, 0.25), b_sin=(0.0, 0.0, 0.0), b_axis=(0, 1, 2), name=name)
+        if name == "affine_k7_32":
+            p = p.with_(affine=np.array([[1.0, 0.35, 0.0], [0.0, 1.0, -0.2], [0.1, 0.0, 1.0]]))
+        return p
     if name.startswith("kpoly_sweep_k") or name.startswith("raised_sweep_k"):
         # the sweep mesh with the polynomial diffusion factor (and the q = 2p + 4 rule)
         import numpy as np
