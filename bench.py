@@ -68,6 +68,15 @@ def make_workload(name: str):
         if name == "affine_k7_32":
             p = p.with_(affine=np.array([[1.0, 0.35, 0.0], [0.0, 1.0, -0.2], [0.1, 0.0, 1.0]]))
         return p
+    if name.startswith("problem_b_k"):
+        # Problem B's features on the sweep mesh: affine cells, the diffusion factor polynomial in the
+        # grid coordinates, the rule q = 2p + 4; b = (1, 0.5, 0.25)
+        import numpy as np
+        k = int(name.split("_k")[-1])
+        return W.cdr_sweep(k).with_(b_const=(1.0, 0.5, 0.25), b_sin=(0.0, 0.0, 0.0), b_axis=(0, 1, 2),
+                                    affine=np.array([[1.0, 0.35, 0.0], [0.0, 1.0, -0.2], [0.1, 0.0, 1.0]]),
+                                    kappa_poly=W.random_kappa_poly(np.random.default_rng(7)), quad_extra=2,
+                                    name=name)
     if name.startswith("kpoly_sweep_k") or name.startswith("raised_sweep_k"):
         # the sweep mesh with the polynomial diffusion factor (and the q = 2p + 4 rule)
         import numpy as np

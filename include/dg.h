@@ -134,11 +134,14 @@ typedef enum {
  *              change of variables x = A xi turns every volume and face
  *              integral into the tensor-grid one with K' = |det A| A^-1 K A^-T,
  *              b' = |det A| A^-1 b, c' = |det A| c, which setup applies, so the
- *              tuned kernels run unchanged.  Requires A finite and invertible,
- *              b constant (b_sin = 0, no DG_B_PRODUCT) and no DG_KAPPA_POLY
- *              (coefficients varying in x would not stay separable in xi):
- *              DG_EINVAL otherwise.  dg_load_vector rejects such handles;
- *              dg_heun uses the physical cell volumes.
+ *              tuned kernels run unchanged.  Requires A finite and invertible
+ *              and b constant (b_sin = 0, no DG_B_PRODUCT: a b varying in x
+ *              would not stay separable in xi): DG_EINVAL otherwise.  With
+ *              DG_KAPPA_POLY the factor kp is a polynomial in the grid
+ *              coordinates xi and passes through as a scalar factor of K'
+ *              (affine cells, polynomial coefficients and the raised rule
+ *              together are Problem B).  dg_load_vector rejects such
+ *              handles; dg_heun uses the physical cell volumes.
  */
 typedef struct {
   int32_t ncell[3];

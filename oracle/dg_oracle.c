@@ -42,7 +42,9 @@
  *    are A^{-T} times the tensor-grid gradients, volume and face measures
  *    scale by |det A| and |det A| |A^{-T} e_a|, face normals are
  *    A^{-T} e_a / |A^{-T} e_a|, d = nu^T D nu, and |F| / min|T| in gamma_F is
- *    |A^{-T} e_a| / min h_a; coefficients are evaluated at physical points;
+ *    |A^{-T} e_a| / min h_a; b is evaluated at physical points, the
+ *    polynomial diffusion factor kp at the tensor-grid points xi (it is a
+ *    polynomial in the grid coordinates of the affine cells);
  *  - every integral uses the tensor Gauss rule with m = k + 1 + quad_extra
  *    points per direction (quad_extra = 2 is the raised rule q = 2p + 4 of
  *    Problem B, Sec. 5.1; 0 the rule of Problem A);
@@ -295,8 +297,9 @@ static void volume_cell(const or_problem *p, const or_tables *t, const int *ic,
         geom_grad(&G, g);
         double xp[3];
         for (int a = 0; a < 3; ++a) xp[a] = o[a] + h[a] * t->xi[q[a]];
-        geom_point(p, xp);
+        /* kp is a polynomial in the tensor-grid coordinates (xi = x without an affine map) */
         const double kx = kap * coef_kp(p, xp); /* D = kx K at this point */
+        geom_point(p, xp);
         double F[3];
         for (int r = 0; r < 3; ++r) {
           double s = 0.0;
@@ -397,12 +400,12 @@ static void interior_face(const or_problem *p, const or_tables *t, int a, const 
       X[a] = op[a];
       X[tb] = om[tb] + hm[tb] * t->xi[qb];
       X[tc] = om[tc] + hm[tc] * t->xi[qc];
+      const double kpoly = coef_kp(p, X); /* at the tensor-grid point */
       geom_point(p, X);
       const double bnu = coef_b(p, 0, X) * nu[0] + coef_b(p, 1, X) * nu[1] + coef_b(p, 2, X) * nu[2];
       const double Phi = (bnu >= 0.0) ? bnu * um : bnu * up;
       const double J = um - up;
       /* D^- = kmx K, D^+ = kpx K at the point; d, the weights and gamma there */
-      const double kpoly = coef_kp(p, X);
       const double kmx = km * kpoly, kpx = kp * kpoly;
       const double dmx = kmx * Knn, dpx = kpx * Knn;
       const double wmx = dpx / (dmx + dpx), wpx = dmx / (dmx + dpx);
@@ -469,10 +472,10 @@ static void boundary_face(const or_problem *p, const or_tables *t, int a, int e,
       X[a] = o[a] + (e ? h[a] : 0.0);
       X[tb] = o[tb] + h[tb] * t->xi[qb];
       X[tc] = o[tc] + h[tc] * t->xi[qc];
+      const double kx = kap * coef_kp(p, X); /* D = kx K at the point (kp at the tensor-grid point) */
       geom_point(p, X);
       const double bnu = nsign * (coef_b(p, 0, X) * nu[0] + coef_b(p, 1, X) * nu[1] + coef_b(p, 2, X) * nu[2]);
       const double Phi = (bnu >= 0.0) ? bnu * u : 0.0;
-      const double kx = kap * coef_kp(p, X); /* D = kx K at the point */
       const double gammax = p->sigma * kx * Knn * nrm / h[a];
       double Dg = 0.0;
       for (int s = 0; s < 3; ++s) Dg += kx * nK[s] * g[s];

@@ -169,8 +169,11 @@ static dg_status fold_affine(dg_problem &p, double *vol_scale) {
     if (!std::isfinite(A[i])) return set_error(DG_EINVAL, "dg_setup: the affine map must be finite");
     mx = std::fmax(mx, std::fabs(A[i]));
   }
-  if ((p.flags & (DG_B_PRODUCT | DG_KAPPA_POLY)) || p.b_sin[0] != 0.0 || p.b_sin[1] != 0.0 || p.b_sin[2] != 0.0)
-    return set_error(DG_EINVAL, "dg_setup: DG_AFFINE needs a constant b and no kappa_poly");
+  // a b varying in x would not stay separable in xi; the polynomial diffusion
+  // factor is defined in the grid coordinates xi and passes through as a
+  // scalar factor of K'
+  if ((p.flags & DG_B_PRODUCT) || p.b_sin[0] != 0.0 || p.b_sin[1] != 0.0 || p.b_sin[2] != 0.0)
+    return set_error(DG_EINVAL, "dg_setup: DG_AFFINE needs a constant b");
   const double C[9] = {A[4] * A[8] - A[5] * A[7], A[5] * A[6] - A[3] * A[8], A[3] * A[7] - A[4] * A[6],
                        A[2] * A[7] - A[1] * A[8], A[0] * A[8] - A[2] * A[6], A[1] * A[6] - A[0] * A[7],
                        A[1] * A[5] - A[2] * A[4], A[2] * A[3] - A[0] * A[5], A[0] * A[4] - A[1] * A[3]};

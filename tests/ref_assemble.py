@@ -111,10 +111,11 @@ def assemble_dense(prob) -> np.ndarray:
         phi, g = _tensor_shape([Vq] * 3, [Dq] * 3, h)
         g = phys(g)
         Wq = np.einsum("a,b,c->cba", w, w, w).ravel() * np.prod(h) * detA
-        Xq = np.stack(np.meshgrid(o[0] + h[0] * xi, o[1] + h[1] * xi, o[2] + h[2] * xi,
-                                  indexing="ij"), axis=-1).transpose(2, 1, 0, 3).reshape(-1, 3) @ Aff.T
+        Xi = np.stack(np.meshgrid(o[0] + h[0] * xi, o[1] + h[1] * xi, o[2] + h[2] * xi,
+                                  indexing="ij"), axis=-1).transpose(2, 1, 0, 3).reshape(-1, 3)
+        Xq = Xi @ Aff.T                     # physical points (b); kp at the grid points Xi
         bq = _b(prob, Xq)
-        Dg = kap[c] * _kp(prob, Xq)[:, None, None] * np.einsum("rs,pjs->pjr", K, g)  # D grad phi_j
+        Dg = kap[c] * _kp(prob, Xi)[:, None, None] * np.einsum("rs,pjs->pjr", K, g)  # D grad phi_j
         flux = Dg - bq[:, None, :] * phi[:, :, None]              # (P, j, 3)
         A[blk(c), blk(c)] += np.einsum("p,pjr,pir->ij", Wq, flux, g)
         A[blk(c), blk(c)] += prob.c * np.einsum("p,pj,pi->ij", Wq, phi, phi)
@@ -138,9 +139,11 @@ def assemble_dense(prob) -> np.ndarray:
         return W * h[t[0]] * h[t[1]]
 
     def face_points(a, o, h, xa):
+        """grid points of the face and their physical images"""
         pts = [o[b] + h[b] * xi for b in range(3)]
         pts[a] = np.array([xa])
-        return np.stack(np.meshgrid(*pts, indexing="ij"), axis=-1).transpose(2, 1, 0, 3).reshape(-1, 3) @ Aff.T
+        G = np.stack(np.meshgrid(*pts, indexing="ij"), axis=-1).transpose(2, 1, 0, 3).reshape(-1, 3)
+        return G, G @ Aff.T
 
     def normal(a):
         """unit normal A^{-T} e_a / |A^{-T} e_a| and |A^{-T} e_a|"""
@@ -161,9 +164,9 @@ def assemble_dense(prob) -> np.ndarray:
                 cp = cid(ip)
                 nu, nrm = normal(a)
                 W = face_weights(a, h) * detA * nrm
-                X = face_points(a, o, h, op[a])
+                Xg, X = face_points(a, o, h, op[a])
                 bnu = _b(prob, X) @ nu
-                kpf = _kp(prob, X)                      # pointwise diffusion factor
+                kpf = _kp(prob, Xg)                     # pointwise diffusion factor (grid coordinates)
                 Knn = nu @ K @ nu
                 dm, dp = kap[c] * kpf * Knn, kap[cp] * kpf * Knn
                 wm, wp = dp / (dm + dp), dm / (dm + dp)
@@ -191,10 +194,10 @@ def assemble_dense(prob) -> np.ndarray:
                     continue
                 nu, nrm = normal(a)
                 W = face_weights(a, h) * detA * nrm
-                X = face_points(a, o, h, o[a] + (h[a] if e == 1 else 0.0))
+                Xg, X = face_points(a, o, h, o[a] + (h[a] if e == 1 else 0.0))
                 nsg = 1.0 if e == 1 else -1.0
                 bnu = nsg * (_b(prob, X) @ nu)
-                kpf = _kp(prob, X)
+                kpf = _kp(prob, Xg)
                 delta = kap[c] * kpf * (nu @ K @ nu)
                 gam = prob.sigma * delta * nrm / h[a]
                 ph, g = face_tables(a, e, h)

@@ -322,3 +322,14 @@ def test_new_paths_on_degenerate_meshes(variant, case):
         p = W.random_problem(2204, ncell=(1, 1, 1), k=6, b="product", periodic=(True, True, True))
     x = W.random_vector(p.ndof, 2210)
     _check(_gpu_apply(p, x, variant), oracle.apply(p, x), f"{case} v{variant}")
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("k", [2, 5])
+def test_problem_b_affine_polynomial_raised(variant, k):
+    """Problem B's three features together: affine cells, the diffusion factor
+    polynomial in the grid coordinates, and the rule q = 2p + 4."""
+    p = W.random_problem(2300 + k, ncell=(3, 2, 2), k=k, b="const", periodic=(False, True, False))
+    p = p.with_(affine=AFFINE, quad_extra=2, kappa_poly=W.random_kappa_poly(np.random.default_rng(2310 + k)))
+    x = W.random_vector(p.ndof, 2320 + k)
+    _check(_gpu_apply(p, x, variant), oracle.apply(p, x), f"problem B k={k} v{variant}")

@@ -91,3 +91,26 @@ def test_heun_conserves_mass_with_physical_volumes():
     m0, m1 = (vol * u0[::nb]).sum(), (vol * u[::nb]).sum()
     assert abs(m1 - m0) <= 1e-13 * (vol * np.abs(u0[::nb])).sum()
     assert np.abs(u - u0).max() > 1e-4
+
+
+def test_problem_b_combination_matches_brute_force():
+    """Affine cells, the diffusion factor polynomial in the grid coordinates
+    and the raised rule q = 2p + 4 together (the three features of Problem B)."""
+    p = W.random_problem(2050, ncell=(2, 3, 2), k=2, b="const", periodic=(True, False, False))
+    p = p.with_(affine=GENERAL, quad_extra=2, kappa_poly=W.random_kappa_poly(np.random.default_rng(2051)))
+    M = oracle.assemble(p).toarray()
+    ref = assemble_dense(p)
+    assert np.abs(M - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_transformed_coefficients_with_the_diffusion_factor():
+    """kp(xi) is a scalar factor of D, so it passes through the change of
+    variables: K'(xi) = kp(xi) |det A| A^{-1} K A^{-T}."""
+    p = W.random_problem(2060, ncell=(3, 2, 2), k=3, b="const")
+    p = p.with_(kappa_poly=W.random_kappa_poly(np.random.default_rng(2061)), quad_extra=2)
+    det = abs(np.linalg.det(GENERAL))
+    Ai = np.linalg.inv(GENERAL)
+    q = p.with_(K=det * Ai @ np.asarray(p.K) @ Ai.T, b_const=tuple(det * Ai @ np.asarray(p.b_const)), c=det * p.c)
+    x = W.random_vector(p.ndof, 2062)
+    y1, y2 = oracle.apply(p.with_(affine=GENERAL), x), oracle.apply(q, x)
+    assert np.abs(y1 - y2).max() <= 1e-12 * np.abs(y2).max()
