@@ -14,7 +14,7 @@ Contents
 * ``rhs`` / ``l2err`` -- load vector (f, phi_j) of the right-hand-side
   functional (Sec. 2.2, g = 0) and the L2 error of a coefficient vector.
 * ``gauss`` / ``basis`` -- the 1D Gauss rule and orthonormal Legendre basis
-  (Sec. 3.1; "L2-orthogonal Legendre polynomials" of Sec. 2.2).
+  (Sec. 3.1; the L2-orthogonal Legendre basis of Sec. 2.2, normalised).
 * ``assemble`` -- the sparse matrix of the operator by probing ``apply`` with
   coloured unit vectors (the DG coupling is face-local, Sec. 2.2).
 * ``block_diagonal`` -- the per-cell diagonal blocks A_TT of the same operator.
