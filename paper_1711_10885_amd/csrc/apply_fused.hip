@@ -488,7 +488,7 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
     }
 
   // ------------------------------------------------------------------------
-  // Round 1.  Lane (j2,j3) = (alpha,beta) owns the x pencil along axis 1.
+  // Exchange 1.  Lane (j2,j3) = (alpha,beta) owns the x pencil along axis 1.
   // Writes: Tv, Td as B-pencils (q1 + N j3) along j2, and 16 modal face
   // trace fields, each N pencils of its first tangential axis (lane
   // (alpha,beta) writes element alpha of pencil beta):
@@ -625,7 +625,7 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
   __syncthreads();
 
   // ------------------------------------------------------------------------
-  // Round 2.  Volume B->C exchange; z-neighbour second tangential sweep.
+  // Exchange 2.  Volume B->C exchange; z-neighbour second tangential sweep.
   // ------------------------------------------------------------------------
   constexpr int C_OFF = 0;                 // vv, dv, vd C-pencils (q1 + N q2) along j3
   constexpr int Z2_OFF = 3 * NN * PS;      // z nb (e, {Sv_n, A1_n}) pencils along j2, index q1
@@ -997,7 +997,7 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
   __syncthreads();
 
   // ------------------------------------------------------------------------
-  // Round 4.  Volume C'->B' exchange; y-face results to the volume lanes
+  // Exchange 4.  Volume C'->B' exchange; y-face results to the volume lanes
   // (q1, j3); x-face results as pencils along q2 at fixed j3.
   // ------------------------------------------------------------------------
   // (the B'-pencils were written before the x/y tasks, at BP_OFF)
@@ -1078,7 +1078,7 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
   __syncthreads();
 
   // ------------------------------------------------------------------------
-  // Round 5.  Volume B'->A' exchange; x-face results to the volume lanes.
+  // Exchange 5.  Volume B'->A' exchange; x-face results to the volume lanes.
   // ------------------------------------------------------------------------
   constexpr int AP_OFF = 0;                  // Vv, Vd A'-pencils (j2 + N j3) along q1
   constexpr int X4_OFF = 2 * NN * PS;        // (e, {R_v, R_d}) on (j2 + N j3)
