@@ -21,6 +21,12 @@ Heun time stepping on the Taylor-Green transport problem (periodic, 64^3,
 k=5; one fused operator-plus-stage launch per Runge-Kutta stage;
 --timestepping none skips it).
 
+Other workloads (--workload): the degree sweep `sweep_kK` (k = 1..10, about 20M DOF), the same
+mesh with the diffusion factor polynomial in the coordinates (`kpoly_sweep_kK`) and with the raised
+rule q = 2p + 4 (`raised_sweep_kK`), Problem B's three features together (`problem_b_kK`), the k = 7
+mesh as an affine image of the grid and the grid itself (`affine_k7_32`, `tensor_k7_32`), and the
+Taylor-Green operator (`transport_k5_64`); solves and time stepping run only with the default.
+
 Prints ONE JSON line.  Algorithmic FLOPs use the per-DOF lower bound of
 Sec. 3.6 (FLOPDOF_vol + FLOPDOF_face for d = 3); peak is the MI355X FP64
 vector rate (256 CUs x 2.4 GHz x 128 FLOP/clk = 78.6 TFLOP/s).

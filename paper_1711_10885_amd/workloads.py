@@ -27,6 +27,13 @@ the paper's model problem, Sec. 2.1, and Problem A of Sec. 5.1):
   c = 0, f = 0, the Taylor-Green flow field of that section (eq. (2)) in
   product form, sigma = 2k(k+2); initial concentration exp(-2 |x - x0|^2),
   x0 = (1/2, 0, 0), taken at the cell centres as the cell-constant mode.
+
+Problem fields beyond the model problem: ``periodic`` (per axis), the product-form
+flow field ``b_amp``/``b_freq``/``b_phase``, the diffusion factor ``kappa_poly``
+(per-axis quadratics), ``quad_extra`` (2: the rule q = 2p + 4) and ``affine``
+(the mesh as the image x = A xi of the tensor grid).  ``random_problem`` draws
+small problems of every kind for the tests; ``random_kappa_poly`` draws the
+diffusion factor.
 """
 from __future__ import annotations
 
