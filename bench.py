@@ -100,9 +100,10 @@ def describe(prob) -> str:
             f"{prob.ndof} DOF, FP64")
 
 
-def measured_traffic(workload: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, only
-    while the kernel source still matches the one the counters were taken on."""
+def measured_counters(workload: str):
+    """Counter figures per launch from the committed rocprofv3 summary (HBM
+    bytes, and executed FP64 FLOP where taken), only while the kernel source
+    still matches the one the counters were taken on."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"apply_fused_{workload[4:] if workload.startswith('cdr_') else workload}_traffic.txt")
     if not os.path.exists(path):
@@ -112,7 +113,7 @@ def measured_traffic(workload: str):
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     if kv.get("source_sha256_16") != sha or kv.get("workload") != workload:
         return None
-    return int(kv["hbm_bytes_per_launch"])
+    return {key: int(val) for key, val in kv.items() if key in ("hbm_bytes_per_launch", "fp64_flop_per_launch")}
 
 
 def cpu_baseline(prob, x, budget_s: float = 12.0):
@@ -141,7 +142,10 @@ def _solve_record(st, rc):
     return {"seconds": st["seconds"], "iterations": st["iters"], "cycles": st["outer"],
             "ms_per_step": 1e3 * st["seconds"] / max(1, st["iters"]),
             "fp64_applies": st["applies"], "fp32_applies": st["applies_f32"],
-            "rel_resid": st["rel_resid"], "converged": rc == 0, "fallback_used": bool(st["fallback_used"])}
+            "rel_resid": st["rel_resid"], "converged": rc == 0, "fallback_used": bool(st["fallback_used"]),
+            "fallback_step": st["fallback_step"] if st["fallback_used"] else None,
+            "fallback_cycle": st["fallback_cycle"] if st["fallback_used"] else None,
+            "fallback_rel_resid": st["fallback_resid"] if st["fallback_used"] else None}
 
 
 def _warm_solve(dg, f, method, precond, restart=30):
@@ -231,10 +235,18 @@ def solves_learned(maxit: int, restart: int):
     a, b = out["fgmres_block_jacobi"], out["fgmres_learned"]
     out["speedup_time_to_tol"] = a["seconds"] / b["seconds"] if a["converged"] and b["converged"] else None
     p = out["plain_fp64_gmres"]
-    # against plain FP64 GMRES: a ratio when both converge, else which one reached 1e-8
-    out["learned_vs_plain"] = (p["seconds"] / b["seconds"] if p["converged"] and b["converged"] else
-                               ("only the learned solve reached tol" if b["converged"] else
-                                ("only plain GMRES reached tol" if p["converged"] else "neither reached tol")))
+    # against plain FP64 GMRES: a ratio when both converge, else which one reached 1e-8; a learned run
+    # that fell back to block Jacobi says so, with the step at which the network was dropped
+    if p["converged"] and b["converged"]:
+        out["learned_vs_plain"] = p["seconds"] / b["seconds"]
+    elif b["converged"] and b["fallback_used"]:
+        out["learned_vs_plain"] = (f"only the learned-preconditioner run reached tol, and only after its network was "
+                                   f"replaced by block Jacobi at step {b['fallback_step']} (cycle {b['fallback_cycle']}, "
+                                   f"relative residual {b['fallback_rel_resid']:.3g})"
+                                   + ("; block Jacobi alone also reached tol" if a["converged"] else ""))
+    else:
+        out["learned_vs_plain"] = ("only the learned solve reached tol" if b["converged"] else
+                                   ("only plain GMRES reached tol" if p["converged"] else "neither reached tol"))
     dg.close()
     return out
 
@@ -363,7 +375,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
 
-    traffic = measured_traffic(args.workload) if args.variant == 0 else None
+    counters = (measured_counters(args.workload) if args.variant == 0 else None) or {}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -397,7 +409,13 @@ def main():
                    "flop_per_dof_formula": fpd},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": traffic, "traffic_unit": "HBM bytes per launch",
+                     "achieved_basis": "the paper's per-DOF FLOP count (Sec. 3.6) over the HIP-event kernel time",
+                     "frac_by_wall_clock": fpd * prob.ndof / (ms_step * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                     "executed_tflops": (counters["fp64_flop_per_launch"] / (avg_kernel_ms * 1e-3) / 1e12
+                                         if "fp64_flop_per_launch" in counters else None),
+                     "executed_basis": "SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes per launch (rocprofv3, committed "
+                                       "profile of the same kernel source) over the HIP-event kernel time",
+                     "traffic": counters.get("hbm_bytes_per_launch"), "traffic_unit": "HBM bytes per launch",
                      "algorithmic_bytes": 16 * prob.ndof, "avg_kernel_ms": avg_kernel_ms},
         "cpu_baseline": cpu,
     }

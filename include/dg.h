@@ -120,7 +120,7 @@ typedef enum {
  *   quad_extra 0: the (k+1)-point Gauss rule per direction (q = 2p, Problem A
  *              of Sec. 5.1); 2: the raised rule with k+3 points (q = 2p + 4,
  *              Problem B), for k <= 8.  Every integral of the operator uses
- *              the rule (the load vector keeps k+1 points).  With 2 the
+ *              the rule, the load vector included.  With 2 the
  *              operator runs the tuned kernel of degree k+2 (whose Gauss rule
  *              has k+3 points) on zero-padded vectors and keeps the modes
  *              <= k, in FP64 and FP32 (the hierarchical basis makes this the
@@ -188,7 +188,8 @@ dg_status dg_apply(dg_handle *h, const double *x, double *y, void *hip_stream);
  *   f(x) = sum_{t < nterms} alpha[t] g(kinds[3t], x_1) g(kinds[3t+1], x_2) g(kinds[3t+2], x_3),
  *   g(0, s) = 1, g(1, s) = sin(pi s), g(2, s) = cos(pi s),
  * the right-hand side of Sec. 2.2 for homogeneous Dirichlet data, by the
- * (k+1)-point tensor Gauss rule of the operator (Sec. 3.1).  alpha, kinds:
+ * tensor Gauss rule of the operator (Sec. 3.1: k+1 points per direction, k+3
+ * with quad_extra = 2), so that it matches the operator's rule.  alpha, kinds:
  * host arrays (nterms in 1..16); f: device, ndof doubles.  Asynchronous on
  * hip_stream.  DG_EINVAL on bad terms. */
 dg_status dg_load_vector(dg_handle *h, int32_t nterms, const double *alpha, const int32_t *kinds, double *f,
@@ -261,6 +262,9 @@ typedef struct {
   int32_t applies;       /* FP64 operator applications                         */
   int32_t applies_f32;   /* FP32 operator applications                         */
   int32_t fallback_used; /* 1 if the learned preconditioner was replaced      */
+  int32_t fallback_step; /* Arnoldi steps done when it was replaced (-1: not)  */
+  int32_t fallback_cycle;/* restart cycles done when it was replaced (-1: not) */
+  double fallback_resid; /* true relative residual when it was replaced       */
   double rel_resid;      /* ||f - A u||_2 / ||f||_2, FP64, at exit             */
   double seconds;        /* host wall time of the call                         */
 } dg_solve_stats;

@@ -71,7 +71,8 @@ class SolveOpts(ctypes.Structure):
 class SolveStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("outer", ctypes.c_int32), ("applies", ctypes.c_int32),
                 ("applies_f32", ctypes.c_int32), ("fallback_used", ctypes.c_int32),
-                ("rel_resid", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("fallback_step", ctypes.c_int32), ("fallback_cycle", ctypes.c_int32),
+                ("fallback_resid", ctypes.c_double), ("rel_resid", ctypes.c_double), ("seconds", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -179,6 +180,34 @@ def _check_vec(t, n, dtype, name):
         raise TypeError(f"{name} must be {dtype}")
     if not t.is_contiguous() or t.numel() != n:
         raise ValueError(f"{name} must be contiguous with {n} entries")
+
+
+def _check_rows(t, ncols, name, B=None):
+    """Rows for the network entry points: a contiguous float32 tensor of
+    shape (B, ncols), B a positive multiple of 64 (and equal to B if given);
+    _check_on_gpu then checks the device.  Both run before any pointer
+    reaches the library, whose kernels read B x ncols floats from it."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    if t.dim() != 2 or t.shape[1] != ncols:
+        raise ValueError(f"{name} must have shape (B, {ncols})")
+    rows = int(t.shape[0])
+    if rows < 64 or rows % 64:
+        raise ValueError(f"{name}: B = {rows} rows, must be a positive multiple of 64")
+    if B is not None and rows != B:
+        raise ValueError(f"{name} must have {B} rows")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return rows
+
+
+def _check_on_gpu(*named):
+    for t, name in named:
+        if t.device.type != "cuda":
+            raise ValueError(f"{name} must live on the GPU")
 
 
 class DG:
@@ -362,7 +391,8 @@ class DG:
     def mlp_forward(self, X, stream=None):
         """Network outputs for rows X (float32 device tensor, B x in)."""
         import torch
-        B = X.shape[0]
+        B = _check_rows(X, 7 * self.k_nb(), "X")
+        _check_on_gpu((X, "X"))
         Y = torch.empty((B, self.k_nb()), dtype=torch.float32, device=X.device)
         _check(load().dg_mlp_forward(self._h, ctypes.c_void_p(X.data_ptr()), int(B),
                                      ctypes.c_void_p(Y.data_ptr()), _stream_ptr(stream)))
@@ -370,18 +400,24 @@ class DG:
 
     def mlp_grad(self, X, T, stream=None):
         """(loss, gradient in the public parameter layout) for rows X, targets T."""
+        B = _check_rows(X, 7 * self.k_nb(), "X")
+        _check_rows(T, self.k_nb(), "T", B)
+        _check_on_gpu((X, "X"), (T, "T"))
         n = self.learned_nparams()
         g = np.empty(n, dtype=np.float32)
         loss = ctypes.c_double()
         _check(load().dg_mlp_grad(self._h, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(T.data_ptr()),
-                                  int(X.shape[0]), g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), n,
+                                  B, g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), n,
                                   ctypes.byref(loss), _stream_ptr(stream)))
         return loss.value, g
 
     def mlp_step(self, X, T, lr=1e-3, stream=None):
+        B = _check_rows(X, 7 * self.k_nb(), "X")
+        _check_rows(T, self.k_nb(), "T", B)
+        _check_on_gpu((X, "X"), (T, "T"))
         loss = ctypes.c_double()
         _check(load().dg_mlp_step(self._h, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(T.data_ptr()),
-                                  int(X.shape[0]), float(lr), ctypes.byref(loss), _stream_ptr(stream)))
+                                  B, float(lr), ctypes.byref(loss), _stream_ptr(stream)))
         return loss.value
 
     def k_nb(self) -> int:

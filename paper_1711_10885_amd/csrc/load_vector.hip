@@ -1,6 +1,7 @@
 // Load vector of a separable source (the right-hand-side functional of
 // Sec. 2.2 with homogeneous Dirichlet data): f_{T,j} = (f, phi_j)_T by the
-// (k+1)-point tensor Gauss rule of the operator (Sec. 3.1).
+// tensor Gauss rule of the operator (Sec. 3.1): m = k + 1 points per
+// direction, or k + 3 with the raised rule (q = 2p + 4, Problem B of Sec. 5.1).
 //
 // For f(x) = sum_t alpha_t g_t1(x_1) g_t2(x_2) g_t3(x_3) the cell integral
 // factorises into 1D integrals (sum factorization of a rank-one integrand):
@@ -18,7 +19,7 @@ namespace dgmf {
 constexpr int kMaxTerms = 16;
 
 struct LvArgs {
-  int n, nterms;
+  int n, m, nterms;  // basis functions and Gauss points per direction
   double xi[kMaxN], w[kMaxN], V[kMaxN][kMaxN];
   double alpha[kMaxTerms];
   int kinds[kMaxTerms][3];
@@ -29,7 +30,7 @@ __device__ __forceinline__ double sep_factor(int kind, double x) {
 }
 
 __global__ __launch_bounds__(256) void k_load_vector(DevMesh M, LvArgs L, int64_t ndof, double *__restrict__ f) {
-  const int n = L.n, nb = n * n * n;
+  const int n = L.n, m = L.m, nb = n * n * n;
   for (int64_t g = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; g < ndof; g += int64_t(gridDim.x) * blockDim.x) {
     const int64_t c = g / nb;
     const int j = int(g - c * nb);
@@ -46,7 +47,7 @@ __global__ __launch_bounds__(256) void k_load_vector(DevMesh M, LvArgs L, int64_
       double prod = L.alpha[t];
       for (int a = 0; a < 3; ++a) {
         double s = 0.0;
-        for (int q = 0; q < n; ++q)
+        for (int q = 0; q < m; ++q)
           s = fma(L.w[q] * sep_factor(L.kinds[t][a], o[a] + h[a] * L.xi[q]), L.V[q][ja[a]], s);
         prod *= s;
       }
@@ -67,12 +68,13 @@ extern "C" dg_status dg_load_vector(dg_handle *h, int32_t nterms, const double *
   if (!alpha || !kinds || !f) return set_error(DG_EINVAL, "dg_load_vector: NULL argument");
   if (h->affine) return set_error(DG_EINVAL, "dg_load_vector: separable sources are tensor-grid only, not affine meshes");
   LvArgs L;
-  L.n = h->tab.n;
+  L.n = h->tabq.n;
+  L.m = h->tabq.m;
   L.nterms = nterms;
-  for (int q = 0; q < L.n; ++q) {
-    L.xi[q] = h->tab.xi[q];
-    L.w[q] = h->tab.w[q];
-    for (int jj = 0; jj < L.n; ++jj) L.V[q][jj] = h->tab.V[q][jj];
+  for (int q = 0; q < L.m; ++q) {
+    L.xi[q] = h->tabq.xi[q];
+    L.w[q] = h->tabq.w[q];
+    for (int jj = 0; jj < L.n; ++jj) L.V[q][jj] = h->tabq.V[q][jj];
   }
   for (int t = 0; t < nterms; ++t) {
     if (!std::isfinite(alpha[t])) return set_error(DG_EINVAL, "dg_load_vector: alpha must be finite");

@@ -128,6 +128,7 @@ extern "C" dg_status dg_solve(dg_handle *h, const double *f, double *u, double t
   double *scratch = h->red, *small = h->red + size_t(kRedBlocks) * kMaxBasis;
 
   dg_solve_stats stats{};
+  stats.fallback_step = stats.fallback_cycle = -1;
   double fn2 = 0.0, un2 = 0.0;
   hipError_t e = norm2_sync(h, f, n, s, fn2);
   if (e == hipSuccess) e = norm2_sync(h, u, n, s, un2);
@@ -175,6 +176,9 @@ extern "C" dg_status dg_solve(dg_handle *h, const double *f, double *u, double t
         }
         learned = false;  // the cycle was abandoned before its update
         stats.fallback_used = 1;
+        stats.fallback_step = stats.iters;
+        stats.fallback_cycle = stats.outer;
+        stats.fallback_resid = hist.empty() ? 1.0 : hist.back();
         continue;
       }
       if (gc.converged) {
@@ -189,6 +193,9 @@ extern "C" dg_status dg_solve(dg_handle *h, const double *f, double *u, double t
       if (learned && hist.size() > 10 && hist.back() > 0.9 * hist[hist.size() - 11]) {
         learned = false;
         stats.fallback_used = 1;
+        stats.fallback_step = stats.iters;
+        stats.fallback_cycle = stats.outer;
+        stats.fallback_resid = gc.rel;
       }
     }
   } else if (!ir) {

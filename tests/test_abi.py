@@ -182,3 +182,47 @@ def test_binding_structs_match_the_header_layout(cname, pystruct, tmp_path):
     out = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
     assert out[0] == ctypes.sizeof(st), (cname, out[0], ctypes.sizeof(st))
     assert out[1:] == [getattr(st, f).offset for f in names], cname
+
+
+def _unbound_handle(k=3):
+    """A DG object without a library handle: the network entry points must
+    reject bad rows before any pointer reaches the library."""
+    dg = binding.DG.__new__(binding.DG)
+    dg._h = None
+    dg.k = k
+    return dg
+
+
+@pytest.mark.parametrize("method", ["mlp_forward", "mlp_grad", "mlp_step"])
+@pytest.mark.parametrize("case,exc", [("numpy", TypeError), ("float64", TypeError), ("narrow", ValueError),
+                                      ("rows_not_64", ValueError), ("strided", ValueError),
+                                      ("cpu", ValueError), ("T_rows", ValueError), ("T_cols", ValueError)])
+def test_network_rows_are_validated_before_the_library(method, case, exc):
+    import torch
+    dg = _unbound_handle(3)
+    nin, nout = 7 * 64, 64
+    X = torch.zeros((128, nin), dtype=torch.float32)
+    T = torch.zeros((128, nout), dtype=torch.float32)
+    if case == "numpy":
+        X = X.numpy()
+    elif case == "float64":
+        X = X.double()
+    elif case == "narrow":
+        X = X[:, : nin - 1].contiguous()
+    elif case == "rows_not_64":
+        X, T = X[:100].contiguous(), T[:100].contiguous()
+    elif case == "strided":
+        X = torch.zeros((128, 2 * nin), dtype=torch.float32)[:, ::2]
+    elif case == "T_rows":
+        T = T[:64].contiguous()
+    elif case == "T_cols":
+        T = torch.zeros((128, nout + 1), dtype=torch.float32)
+    if method == "mlp_forward" and case.startswith("T_"):
+        pytest.skip("mlp_forward takes no targets")
+    with pytest.raises(exc):
+        if method == "mlp_forward":
+            dg.mlp_forward(X)
+        elif method == "mlp_grad":
+            dg.mlp_grad(X, T)
+        else:
+            dg.mlp_step(X, T)

@@ -78,22 +78,6 @@ def test_coefficient_kinds(variant, terms):
     _check(_gpu_apply(p, x, variant), oracle.apply(p, x), f"{terms} v{variant}")
 
 
-@pytest.mark.parametrize("variant", VARIANTS)
-def test_cdr_k7_32_sampled_rows(variant):
-    """Full-size k = 7, 32^3 workload in the benchmarked launch configuration;
-    the oracle computes the rows of sampled cells one by one (all corners,
-    edge/face cells and random interior cells)."""
-    p = W.cdr_k7_32()
-    x = W.workload_vector(p)
-    y = _gpu_apply(p, x, variant).reshape(p.ncells, -1)
-    N = p.ncell[0]
-    rng = np.random.default_rng(9)
-    corners = [i + N * (j + N * k) for i in (0, N - 1) for j in (0, N - 1) for k in (0, N - 1)]
-    cells = np.unique(np.concatenate([corners, rng.integers(0, p.ncells, 56)]))
-    ref = oracle.apply_rows(p, x, cells)
-    _check(y[cells], ref, f"cdr_k7_32 sampled v{variant}")
-
-
 def test_deterministic_and_variants_agree():
     p = W.random_problem(500, ncell=(4, 4, 4), k=5, b="sine")
     x = W.random_vector(p.ndof, 501)
@@ -111,36 +95,6 @@ def test_aliasing_rejected():
         x = torch.zeros(dg.ndof, dtype=torch.float64, device="cuda")
         with pytest.raises(binding.DGError, match="overlap"):
             dg.apply(x, x)
-
-
-def _sampled_cells(p, seed, nrand=24):
-    N1, N2, N3 = p.ncell
-    rng = np.random.default_rng(seed)
-    corners = [i + N1 * (j + N2 * k) for i in (0, N1 - 1) for j in (0, N2 - 1) for k in (0, N3 - 1)]
-    return np.unique(np.concatenate([corners, rng.integers(0, p.ncells, nrand)]))
-
-
-@pytest.mark.parametrize("k", range(1, 11))
-def test_degree_sweep_full_size_sampled_rows(k):
-    """Degree sweep at its full size (about 2e7 DOF per degree, uniform N^3,
-    the k=7 coefficients), tuned kernel as benchmarked; sampled rows against
-    the oracle."""
-    p = W.cdr_sweep(k)
-    x = W.workload_vector(p)
-    y = _gpu_apply(p, x, 0).reshape(p.ncells, -1)
-    cells = _sampled_cells(p, 40 + k)
-    _check(y[cells], oracle.apply_rows(p, x, cells), f"sweep k={k} {p.ncell} sampled")
-
-
-@pytest.mark.parametrize("name", ["mixed_k5_48", "learned_k3_64"])
-def test_solver_workloads_full_size_sampled_rows(name):
-    """The operators of the two solve workloads at full size (48^3 k=5 and
-    64^3 k=3 with the lognormal kappa field), sampled rows."""
-    p = getattr(W, name)()
-    x = W.random_vector(p.ndof, 60)
-    y = _gpu_apply(p, x, 0).reshape(p.ncells, -1)
-    cells = _sampled_cells(p, 61)
-    _check(y[cells], oracle.apply_rows(p, x, cells), f"{name} sampled")
 
 
 PERIODIC = [(True, False, False), (False, True, False), (False, False, True), (True, True, True)]

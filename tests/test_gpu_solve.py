@@ -192,6 +192,25 @@ def test_load_vector_matches_oracle(k):
     assert e <= 1e-13
 
 
+@pytest.mark.parametrize("k", [1, 4, 8])
+def test_load_vector_with_the_raised_rule_matches_oracle(k):
+    """With quad_extra = 2 the load vector integrates with the operator's own
+    k + 3 points per direction, as the oracle does."""
+    torch = _torch()
+    from paper_1711_10885_amd import binding
+    p = W.random_problem(820 + k, ncell=(3, 2, 2), k=k, b="sine").with_(quad_extra=2)
+    terms = W.manufactured_source(p.K, (0.3, -0.2, 0.1), 0.7) + W.constant_source(0.25)
+    with binding.DG(p) as dg:
+        f = dg.load_vector(terms).cpu().numpy()
+    ref = oracle.rhs(p, terms)
+    e = np.abs(f - ref).max() / np.abs(ref).max()
+    print(f"k={k} q=2p+4: load vector relmax {e:.2e}", flush=True)
+    assert e <= 1e-13
+    # the (k+1)-point vector differs: the check above does see the rule
+    ref0 = oracle.rhs(p.with_(quad_extra=0), terms)
+    assert np.abs(ref0 - ref).max() > 1e3 * e * np.abs(ref).max()
+
+
 def test_load_vector_of_the_48_cube_workload_on_sampled_cells():
     torch = _torch()
     from paper_1711_10885_amd import binding

@@ -342,3 +342,39 @@ def test_block_diagonal_matches_assembly():
     for c in range(p.ncells):
         s = slice(c * nb, (c + 1) * nb)
         assert np.abs(B[c] - A[s, s]).max() <= 1e-14 * np.abs(A).max()
+
+
+# --------------------------------------------------------------------------
+# Absolute scale of the L2 error (the measure |T| and the orthonormal basis)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("k", [1, 3])
+def test_l2err_of_zero_against_the_sine_product(k):
+    """u_h = 0 against u = sin(pi x) sin(pi y) sin(pi z) on the box
+    [0,1] x [0,2] x [0,3]: ||u||^2 = (1/2)(2/2)(3/2) = 3/4 in closed form.  On
+    uniform cells the composite Gauss sum of cos(2 pi x) over whole periods
+    vanishes, so the quadrature is exact to rounding; a wrong cell measure,
+    weight or axis length changes the value."""
+    base = W.mixed_k5_48(N=2, k=k)
+    nodes = (W.uniform_nodes(3), 2.0 * W.uniform_nodes(4), 3.0 * W.uniform_nodes(6))
+    p = base.with_(ncell=(3, 4, 6), nodes=nodes)
+    e = oracle.l2err(p, np.zeros(p.ndof), W.manufactured_u())
+    assert abs(e * e - 0.75) <= 1e-13, e * e
+
+
+@pytest.mark.parametrize("k", [1, 2, 4])
+def test_l2err_of_a_coefficient_vector_is_its_weighted_norm(k):
+    """With the orthonormal basis, ||u_h - c||^2 for the constant c = 1 and
+    u_h = 1 + d (d any coefficient vector) is sum_T |T| sum_j d_{T,j}^2
+    exactly (the (k+3)-point rule integrates the degree-2k products exactly):
+    pins the cell measure on a non-uniform mesh."""
+    p = W.random_problem(90 + k, ncell=(3, 2, 4), k=k, b="const")
+    nb = (k + 1) ** 3
+    d = W.random_vector(p.ndof, 95 + k)
+    x = d.copy()
+    x[::nb] += 1.0  # the constant 1 is theta_0^3 = 1 in the constant mode
+    vol = np.array([(p.nodes[0][i + 1] - p.nodes[0][i]) * (p.nodes[1][j + 1] - p.nodes[1][j])
+                    * (p.nodes[2][l + 1] - p.nodes[2][l])
+                    for l in range(p.ncell[2]) for j in range(p.ncell[1]) for i in range(p.ncell[0])])
+    expect = float((vol * (d.reshape(p.ncells, nb) ** 2).sum(axis=1)).sum())
+    e = oracle.l2err(p, x, [(1.0, (0, 0, 0))])
+    assert abs(e * e - expect) <= 1e-13 * expect, (e * e, expect)
