@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <string>
 #include <vector>
 
@@ -15,6 +16,12 @@
 #include "krylov.h"
 
 namespace dgmf {
+
+static std::string sci(double v) {
+  char buf[32];
+  std::snprintf(buf, sizeof buf, "%.3e", v);
+  return buf;
+}
 
 void release_solver(dg_handle *h) {
   if (h->ws) (void)hipFree(h->ws);
@@ -263,6 +270,6 @@ extern "C" dg_status dg_solve(dg_handle *h, const double *f, double *u, double t
   if (go.nan) return set_error(DG_ENAN, "dg_solve: non-finite value in the iteration");
   if (!go.converged)
     return set_error(DG_ENOTCONV,
-                     "dg_solve: maxit reached at relative residual " + std::to_string(stats.rel_resid));
+                     "dg_solve: maxit reached at relative residual " + sci(stats.rel_resid));
   return DG_OK;
 }
