@@ -23,6 +23,12 @@ Contents
   matrix of the orthonormal basis; the last evaluates one step on listed
   cells only (for checks on meshes too large to step whole).
 * ``gmres`` -- restarted, right-preconditioned GMRES in float64 (numpy).
+
+Meshes: tensor grids of per-axis nodes (optionally one global affine image),
+or, with ``prob.vertices``, logically structured meshes of trilinear cells
+through the given vertices (multilinear geometry, Sec. 4 and Problem C of
+Sec. 5.1), where every geometric quantity is evaluated at each quadrature
+point.
 """
 from __future__ import annotations
 
@@ -73,6 +79,8 @@ class _Problem(ctypes.Structure):
         ("quad_extra", ctypes.c_int32),
         ("affine_on", ctypes.c_int32),
         ("affine", ctypes.c_double * 9),
+        ("multilinear_on", ctypes.c_int32),
+        ("vertices", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -150,6 +158,13 @@ class _Marshalled:
         if A is not None:
             for i, v in enumerate(np.asarray(A, dtype=np.float64).ravel()):
                 s.affine[i] = float(v)
+        V = getattr(prob, "vertices", None)
+        s.multilinear_on = 0 if V is None else 1
+        self.vertices = None if V is None else np.ascontiguousarray(V, dtype=np.float64).ravel()
+        if V is not None:
+            if self.vertices.size != 3 * np.prod([prob.ncell[a] + 1 for a in range(3)]):
+                raise ValueError("vertices must hold (N1+1)(N2+1)(N3+1) points")
+            s.vertices = _dptr(self.vertices)
         self.struct = s
 
 

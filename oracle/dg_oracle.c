@@ -48,6 +48,18 @@
  *  - every integral uses the tensor Gauss rule with m = k + 1 + quad_extra
  *    points per direction (quad_extra = 2 is the raised rule q = 2p + 4 of
  *    Problem B, Sec. 5.1; 0 the rule of Problem A);
+ *  - with or_problem.multilinear_on the mesh is given by its vertices (a
+ *    logically structured grid of (N1+1)(N2+1)(N3+1) points) and every cell
+ *    is the image of [0,1]^3 under the trilinear (Q1) map through its eight
+ *    vertices (multilinear geometry, Sec. 4 and Problem C of Sec. 5.1):
+ *    gradients are J^{-T} times the reference gradients, with J the Jacobian
+ *    of the map at the point; the volume weight is det J; a face xi_a = e has
+ *    the area-weighted normal cof(J) e_a (|cof(J) e_a| is the surface measure,
+ *    its direction the unit normal nu, both varying over the face); d = nu^T D
+ *    nu, the weights and gamma_F are evaluated at each face point, with
+ *    |F| / min(|T-|,|T+|) in gamma_F from the face area and the cell volumes
+ *    (both integrated with the operator's rule); b and kp are evaluated at the
+ *    physical point; no periodic axes;
  *  - with or_problem.kappa_poly_on the diffusion tensor is
  *    D(x) = kappa_T kp(x) K, kp(x) = prod_j (c_j0 + c_j1 x_j + c_j2 x_j^2)
  *    with c_ji = kappa_poly[3j+i] (coefficients polynomial in the
@@ -62,7 +74,7 @@
 #include <omp.h>
 #endif
 
-#define OR_MAXN 11 /* k <= 10 */
+#define OR_MAXN 14 /* k <= 10; up to 13 Gauss points per direction */
 
 typedef struct {
   int32_t ncell[3];
@@ -85,6 +97,8 @@ typedef struct {
   int32_t quad_extra;    /* Gauss points per direction m = k + 1 + quad_extra */
   int32_t affine_on;     /* 1: the mesh is the image x = A xi of the tensor grid xi */
   double affine[9];      /* A, row-major */
+  int32_t multilinear_on; /* 1: trilinear cells through the vertices below */
+  const double *vertices; /* (N1+1)(N2+1)(N3+1) x 3, vertex (v0,v1,v2) at v0 + (N1+1)(v1 + (N2+1) v2) */
 } or_problem;
 
 /* Geometry of the affine map x = A xi (identity unless affine_on): physical
@@ -495,12 +509,304 @@ static void boundary_face(const or_problem *p, const or_tables *t, int a, int e,
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Multilinear geometry (Sec. 4: the map mu_T from the reference cube to the */
+/* cell is a Q1 finite element function; Problem C of Sec. 5.1).  The same   */
+/* terms of eq. (blf) as above, with the geometry taken point by point.      */
+/* ------------------------------------------------------------------------ */
+
+static const double *ml_vertex(const or_problem *p, int v0, int v1, int v2) {
+  const int64_t V0 = p->ncell[0] + 1, V1 = p->ncell[1] + 1;
+  return p->vertices + 3 * ((int64_t)v0 + V0 * ((int64_t)v1 + V1 * v2));
+}
+
+/* X = mu_T(xi) and J[3r+s] = d X_r / d xi_s for the cell ic:
+ *   mu_T(xi) = sum over the corners c in {0,1}^3 of the vertex X_c times
+ *   l_{c0}(xi_0) l_{c1}(xi_1) l_{c2}(xi_2),   l_0(t) = 1 - t,  l_1(t) = t. */
+static void ml_map(const or_problem *p, const int *ic, const double *xi, double *X, double *J) {
+  for (int r = 0; r < 3; ++r) {
+    X[r] = 0.0;
+    for (int s2 = 0; s2 < 3; ++s2) J[3 * r + s2] = 0.0;
+  }
+  for (int c = 0; c < 8; ++c) {
+    const int cb[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
+    const double *V = ml_vertex(p, ic[0] + cb[0], ic[1] + cb[1], ic[2] + cb[2]);
+    double l[3], dl[3];
+    for (int a = 0; a < 3; ++a) {
+      l[a] = cb[a] ? xi[a] : 1.0 - xi[a];
+      dl[a] = cb[a] ? 1.0 : -1.0;
+    }
+    const double wv = l[0] * l[1] * l[2];
+    const double wd[3] = {dl[0] * l[1] * l[2], l[0] * dl[1] * l[2], l[0] * l[1] * dl[2]};
+    for (int r = 0; r < 3; ++r) {
+      X[r] += wv * V[r];
+      for (int s2 = 0; s2 < 3; ++s2) J[3 * r + s2] += wd[s2] * V[r];
+    }
+  }
+}
+
+/* Cofactor matrix C = det(J) J^{-T} (row-major); returns det J.  Physical
+ * gradients are C g_ref / det J; column a of C is the area-weighted normal of
+ * the surfaces xi_a = const (pointing towards increasing xi_a when det J > 0). */
+static double ml_cof(const double *J, double *C) {
+  C[0] = J[4] * J[8] - J[5] * J[7];
+  C[1] = J[5] * J[6] - J[3] * J[8];
+  C[2] = J[3] * J[7] - J[4] * J[6];
+  C[3] = J[2] * J[7] - J[1] * J[8];
+  C[4] = J[0] * J[8] - J[2] * J[6];
+  C[5] = J[1] * J[6] - J[0] * J[7];
+  C[6] = J[1] * J[5] - J[2] * J[4];
+  C[7] = J[2] * J[3] - J[0] * J[5];
+  C[8] = J[0] * J[4] - J[1] * J[3];
+  return J[0] * C[0] + J[1] * C[1] + J[2] * C[2];
+}
+
+/* g <- C g / det */
+static void ml_grad(const double *C, double det, double *g) {
+  const double r0 = (C[0] * g[0] + C[1] * g[1] + C[2] * g[2]) / det;
+  const double r1 = (C[3] * g[0] + C[4] * g[1] + C[5] * g[2]) / det;
+  const double r2 = (C[6] * g[0] + C[7] * g[1] + C[8] * g[2]) / det;
+  g[0] = r0;
+  g[1] = r1;
+  g[2] = r2;
+}
+
+/* |T|: det J integrated over the reference cube with the operator's rule
+ * (exact: det J is a polynomial of degree <= 2 in each coordinate). */
+static double ml_cell_volume(const or_problem *p, const or_tables *t, const int *ic) {
+  double v = 0.0;
+  for (int q3 = 0; q3 < t->m; ++q3)
+    for (int q2 = 0; q2 < t->m; ++q2)
+      for (int q1 = 0; q1 < t->m; ++q1) {
+        const double xi[3] = {t->xi[q1], t->xi[q2], t->xi[q3]};
+        double X[3], J[9], C[9];
+        ml_map(p, ic, xi, X, J);
+        v += t->w[q1] * t->w[q2] * t->w[q3] * ml_cof(J, C);
+      }
+  return v;
+}
+
+/* |F| of the face xi_a = e of cell ic: |cof(J) e_a| integrated over the face
+ * with the operator's rule on the tangential axes tb < tc. */
+static double ml_face_area(const or_problem *p, const or_tables *t, const int *ic, int a, int e) {
+  const int tb = (a == 0) ? 1 : 0, tc = (a == 2) ? 1 : 2;
+  double A = 0.0;
+  for (int qc = 0; qc < t->m; ++qc)
+    for (int qb = 0; qb < t->m; ++qb) {
+      double xi[3], X[3], J[9], C[9];
+      xi[a] = e ? 1.0 : 0.0;
+      xi[tb] = t->xi[qb];
+      xi[tc] = t->xi[qc];
+      ml_map(p, ic, xi, X, J);
+      ml_cof(J, C);
+      A += t->w[qb] * t->w[qc] * sqrt(C[a] * C[a] + C[3 + a] * C[3 + a] + C[6 + a] * C[6 + a]);
+    }
+  return A;
+}
+
+static void ml_volume_cell(const or_problem *p, const or_tables *t, const int *ic, const double *xT, double *yT) {
+  const int n = t->n, m = t->m;
+  const double kap = cell_kappa(p, cell_id(p, ic));
+  for (int q3 = 0; q3 < m; ++q3)
+    for (int q2 = 0; q2 < m; ++q2)
+      for (int q1 = 0; q1 < m; ++q1) {
+        const double xi[3] = {t->xi[q1], t->xi[q2], t->xi[q3]};
+        double X[3], J[9], C[9];
+        ml_map(p, ic, xi, X, J);
+        const double det = ml_cof(J, C);
+        /* u and its physical gradient: full sum over the shape functions */
+        double u = 0.0, g[3] = {0.0, 0.0, 0.0};
+        for (int j3 = 0; j3 < n; ++j3)
+          for (int j2 = 0; j2 < n; ++j2)
+            for (int j1 = 0; j1 < n; ++j1) {
+              const double xj = xT[j1 + n * (j2 + n * j3)];
+              const double v1 = t->V[q1][j1], v2 = t->V[q2][j2], v3 = t->V[q3][j3];
+              u += xj * v1 * v2 * v3;
+              g[0] += xj * t->D[q1][j1] * v2 * v3;
+              g[1] += xj * v1 * t->D[q2][j2] * v3;
+              g[2] += xj * v1 * v2 * t->D[q3][j3];
+            }
+        ml_grad(C, det, g);
+        const double kx = kap * coef_kp(p, X);
+        double F[3];
+        for (int r = 0; r < 3; ++r) {
+          double sum = 0.0;
+          for (int c = 0; c < 3; ++c) sum += kx * p->K[3 * r + c] * g[c];
+          F[r] = sum - coef_b(p, r, X) * u;
+        }
+        const double W = t->w[q1] * t->w[q2] * t->w[q3] * det;
+        for (int j3 = 0; j3 < n; ++j3)
+          for (int j2 = 0; j2 < n; ++j2)
+            for (int j1 = 0; j1 < n; ++j1) {
+              const double v1 = t->V[q1][j1], v2 = t->V[q2][j2], v3 = t->V[q3][j3];
+              double gphi[3] = {t->D[q1][j1] * v2 * v3, v1 * t->D[q2][j2] * v3, v1 * v2 * t->D[q3][j3]};
+              ml_grad(C, det, gphi);
+              yT[j1 + n * (j2 + n * j3)] +=
+                  W * (F[0] * gphi[0] + F[1] * gphi[1] + F[2] * gphi[2] + p->c * u * v1 * v2 * v3);
+            }
+      }
+}
+
+/* Value and physical gradient of shape function j of a cell at its face
+ * point (xi_a = e, Gauss nodes qb, qc on the tangential axes tb < tc), from
+ * the cell's cofactor matrix C and det J at that point. */
+static void ml_shape_on_face(const or_tables *t, int a, int e, int tb, int tc, int qb, int qc, const int *j,
+                             const double *C, double det, double *phi, double *gphi) {
+  double val[3], der[3];
+  val[a] = e ? t->V1[j[a]] : t->V0[j[a]];
+  der[a] = e ? t->D1[j[a]] : t->D0[j[a]];
+  val[tb] = t->V[qb][j[tb]];
+  der[tb] = t->D[qb][j[tb]];
+  val[tc] = t->V[qc][j[tc]];
+  der[tc] = t->D[qc][j[tc]];
+  *phi = val[0] * val[1] * val[2];
+  gphi[0] = der[0] * val[1] * val[2];
+  gphi[1] = val[0] * der[1] * val[2];
+  gphi[2] = val[0] * val[1] * der[2];
+  ml_grad(C, det, gphi);
+}
+
+static void ml_eval_on_face(const or_tables *t, int a, int e, int tb, int tc, int qb, int qc, const double *C,
+                            double det, const double *xT, double *u, double *g) {
+  const int n = t->n;
+  *u = 0.0;
+  g[0] = g[1] = g[2] = 0.0;
+  for (int j3 = 0; j3 < n; ++j3)
+    for (int j2 = 0; j2 < n; ++j2)
+      for (int j1 = 0; j1 < n; ++j1) {
+        const int j[3] = {j1, j2, j3};
+        double phi, gphi[3];
+        ml_shape_on_face(t, a, e, tb, tc, qb, qc, j, C, det, &phi, gphi);
+        const double xj = xT[j1 + n * (j2 + n * j3)];
+        *u += xj * phi;
+        for (int r = 0; r < 3; ++r) g[r] += xj * gphi[r];
+      }
+}
+
+/* Interior face between Tm (index i_a) and Tp (index i_a + 1): the face
+ * xi_a = 1 of Tm and xi_a = 0 of Tp, with the same tangential coordinates
+ * (the two trilinear maps agree on the shared face).  nu points from Tm to
+ * Tp; the face point, b and kp are taken from Tm's map. */
+static void ml_interior_face(const or_problem *p, const or_tables *t, int a, const int *im, const double *xm,
+                             const double *xp_, double *ym, double *yp) {
+  const int n = t->n, m = t->m;
+  const int tb = (a == 0) ? 1 : 0, tc = (a == 2) ? 1 : 2;
+  int ip[3] = {im[0], im[1], im[2]};
+  ip[a] += 1;
+  const double km = cell_kappa(p, cell_id(p, im)), kp = cell_kappa(p, cell_id(p, ip));
+  const double volm = ml_cell_volume(p, t, im), volp = ml_cell_volume(p, t, ip);
+  const double FoT = ml_face_area(p, t, im, a, 1) / (volm < volp ? volm : volp);
+  for (int qc = 0; qc < m; ++qc)
+    for (int qb = 0; qb < m; ++qb) {
+      double xim[3], xip[3];
+      xim[a] = 1.0;
+      xip[a] = 0.0;
+      xim[tb] = xip[tb] = t->xi[qb];
+      xim[tc] = xip[tc] = t->xi[qc];
+      double Xm[3], Jm[9], Cm[9], Xp[3], Jp[9], Cp[9];
+      ml_map(p, im, xim, Xm, Jm);
+      ml_map(p, ip, xip, Xp, Jp);
+      const double detm = ml_cof(Jm, Cm), detp = ml_cof(Jp, Cp);
+      const double nv[3] = {Cm[a], Cm[3 + a], Cm[6 + a]};
+      const double nrm = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+      const double nu[3] = {nv[0] / nrm, nv[1] / nrm, nv[2] / nrm};
+      double nK[3];
+      for (int s2 = 0; s2 < 3; ++s2) nK[s2] = nu[0] * p->K[s2] + nu[1] * p->K[3 + s2] + nu[2] * p->K[6 + s2];
+      const double Knn = nK[0] * nu[0] + nK[1] * nu[1] + nK[2] * nu[2];
+      double um, gm[3], up, gp[3];
+      ml_eval_on_face(t, a, 1, tb, tc, qb, qc, Cm, detm, xm, &um, gm);
+      ml_eval_on_face(t, a, 0, tb, tc, qb, qc, Cp, detp, xp_, &up, gp);
+      const double kpoly = coef_kp(p, Xm);
+      const double bnu = coef_b(p, 0, Xm) * nu[0] + coef_b(p, 1, Xm) * nu[1] + coef_b(p, 2, Xm) * nu[2];
+      const double Phi = (bnu >= 0.0) ? bnu * um : bnu * up;
+      const double J = um - up;
+      const double kmx = km * kpoly, kpx = kp * kpoly;
+      const double dmx = kmx * Knn, dpx = kpx * Knn;
+      const double wmx = dpx / (dmx + dpx), wpx = dmx / (dmx + dpx);
+      const double gammax = p->sigma * (2.0 * dmx * dpx / (dmx + dpx)) * FoT;
+      double Dgm = 0.0, Dgp = 0.0;
+      for (int s2 = 0; s2 < 3; ++s2) {
+        Dgm += kmx * nK[s2] * gm[s2];
+        Dgp += kpx * nK[s2] * gp[s2];
+      }
+      const double avg = wmx * Dgm + wpx * Dgp;
+      const double W = t->w[qb] * t->w[qc] * nrm;
+      for (int j3 = 0; j3 < n; ++j3)
+        for (int j2 = 0; j2 < n; ++j2)
+          for (int j1 = 0; j1 < n; ++j1) {
+            const int j[3] = {j1, j2, j3};
+            const int jj = j1 + n * (j2 + n * j3);
+            if (ym) {
+              double phi, gphi[3];
+              ml_shape_on_face(t, a, 1, tb, tc, qb, qc, j, Cm, detm, &phi, gphi);
+              double Dgv = 0.0;
+              for (int s2 = 0; s2 < 3; ++s2) Dgv += kmx * nK[s2] * gphi[s2];
+              ym[jj] += W * (Phi * phi - avg * phi - wmx * Dgv * J + gammax * J * phi);
+            }
+            if (yp) {
+              double phi, gphi[3];
+              ml_shape_on_face(t, a, 0, tb, tc, qb, qc, j, Cp, detp, &phi, gphi);
+              double Dgv = 0.0;
+              for (int s2 = 0; s2 < 3; ++s2) Dgv += kpx * nK[s2] * gphi[s2];
+              yp[jj] += W * (-Phi * phi + avg * phi - wpx * Dgv * J - gammax * J * phi);
+            }
+          }
+    }
+}
+
+/* Boundary face xi_a = e of cell ic (homogeneous Dirichlet); outer
+ * area-weighted normal (2e - 1) cof(J) e_a; gamma_F = sigma d |F| / |T|. */
+static void ml_boundary_face(const or_problem *p, const or_tables *t, int a, int e, const int *ic, const double *xT,
+                             double *yT) {
+  const int n = t->n, m = t->m;
+  const int tb = (a == 0) ? 1 : 0, tc = (a == 2) ? 1 : 2;
+  const double kap = cell_kappa(p, cell_id(p, ic));
+  const double nsign = e ? 1.0 : -1.0;
+  const double FoT = ml_face_area(p, t, ic, a, e) / ml_cell_volume(p, t, ic);
+  for (int qc = 0; qc < m; ++qc)
+    for (int qb = 0; qb < m; ++qb) {
+      double xi[3], X[3], J[9], C[9];
+      xi[a] = e ? 1.0 : 0.0;
+      xi[tb] = t->xi[qb];
+      xi[tc] = t->xi[qc];
+      ml_map(p, ic, xi, X, J);
+      const double det = ml_cof(J, C);
+      const double nv[3] = {nsign * C[a], nsign * C[3 + a], nsign * C[6 + a]};
+      const double nrm = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+      const double nu[3] = {nv[0] / nrm, nv[1] / nrm, nv[2] / nrm};
+      double nK[3];
+      for (int s2 = 0; s2 < 3; ++s2) nK[s2] = nu[0] * p->K[s2] + nu[1] * p->K[3 + s2] + nu[2] * p->K[6 + s2];
+      const double Knn = nK[0] * nu[0] + nK[1] * nu[1] + nK[2] * nu[2];
+      double u, g[3];
+      ml_eval_on_face(t, a, e, tb, tc, qb, qc, C, det, xT, &u, g);
+      const double kx = kap * coef_kp(p, X);
+      const double bnu = coef_b(p, 0, X) * nu[0] + coef_b(p, 1, X) * nu[1] + coef_b(p, 2, X) * nu[2];
+      const double Phi = (bnu >= 0.0) ? bnu * u : 0.0;
+      const double gammax = p->sigma * kx * Knn * FoT;
+      double Dg = 0.0;
+      for (int s2 = 0; s2 < 3; ++s2) Dg += kx * nK[s2] * g[s2];
+      const double W = t->w[qb] * t->w[qc] * nrm;
+      for (int j3 = 0; j3 < n; ++j3)
+        for (int j2 = 0; j2 < n; ++j2)
+          for (int j1 = 0; j1 < n; ++j1) {
+            const int j[3] = {j1, j2, j3};
+            double phi, gphi[3];
+            ml_shape_on_face(t, a, e, tb, tc, qb, qc, j, C, det, &phi, gphi);
+            double Dgv = 0.0;
+            for (int s2 = 0; s2 < 3; ++s2) Dgv += kx * nK[s2] * gphi[s2];
+            yT[j1 + n * (j2 + n * j3)] += W * (Phi * phi - Dg * phi - Dgv * u + gammax * u * phi);
+          }
+    }
+}
+
 static int check_problem(const or_problem *p) {
   if (!p || p->k < 1 || p->k > 10) return -1;
-  if (p->quad_extra < 0 || p->k + 1 + p->quad_extra > OR_MAXN) return -1;
+  if (p->quad_extra < 0 || p->k + 1 + p->quad_extra > OR_MAXN - 1) return -1;
+  if (p->multilinear_on && (!p->vertices || p->affine_on)) return -1;
   for (int a = 0; a < 3; ++a) {
-    if (p->ncell[a] < 1 || !p->nodes[a]) return -1;
+    if (p->ncell[a] < 1 || (!p->nodes[a] && !p->multilinear_on)) return -1;
     if (p->b_axis[a] < 0 || p->b_axis[a] > 2) return -1;
+    if (p->multilinear_on && p->periodic[a]) return -1;
   }
   return 0;
 }
@@ -516,8 +822,13 @@ int64_t oracle_ndof(const or_problem *p) {
 /* Faces are visited in two passes per axis (even and odd lower index), so   */
 /* that faces processed concurrently never share a cell.                     */
 /* ------------------------------------------------------------------------ */
+typedef void (*or_iface_fn)(const or_problem *, const or_tables *, int, const int *, const double *,
+                            const double *, double *, double *);
+typedef void (*or_bface_fn)(const or_problem *, const or_tables *, int, int, const int *, const double *, double *);
+
 int oracle_apply(const or_problem *p, const double *x, double *y, int terms, int nthreads) {
   if (check_problem(p)) return -1;
+  const or_bface_fn bface = p->multilinear_on ? ml_boundary_face : boundary_face;
   or_tables t;
   make_tables(p->k, p->quad_extra, &t);
   const int64_t nb = (int64_t)t.n * t.n * t.n;
@@ -529,7 +840,10 @@ int oracle_apply(const or_problem *p, const double *x, double *y, int terms, int
 #pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads)
     for (int64_t c = 0; c < ncells; ++c) {
       const int ic[3] = {(int)(c % N1), (int)((c / N1) % N2), (int)(c / ((int64_t)N1 * N2))};
-      volume_cell(p, &t, ic, x + c * nb, y + c * nb);
+      if (p->multilinear_on)
+        ml_volume_cell(p, &t, ic, x + c * nb, y + c * nb);
+      else
+        volume_cell(p, &t, ic, x + c * nb, y + c * nb);
     }
   }
   if (terms & OR_INTERIOR) {
@@ -549,7 +863,10 @@ int oracle_apply(const or_problem *p, const double *x, double *y, int terms, int
           int jc[3] = {ic[0], ic[1], ic[2]};
           jc[a] = (ic[a] + 1) % p->ncell[a];
           const int64_t cp = cell_id(p, jc);
-          interior_face(p, &t, a, ic, x + c * nb, x + cp * nb, y + c * nb, y + cp * nb);
+          if (p->multilinear_on)
+            ml_interior_face(p, &t, a, ic, x + c * nb, x + cp * nb, y + c * nb, y + cp * nb);
+          else
+            interior_face(p, &t, a, ic, x + c * nb, x + cp * nb, y + c * nb, y + cp * nb);
         }
       }
   }
@@ -559,8 +876,8 @@ int oracle_apply(const or_problem *p, const double *x, double *y, int terms, int
       const int ic[3] = {(int)(c % N1), (int)((c / N1) % N2), (int)(c / ((int64_t)N1 * N2))};
       for (int a = 0; a < 3; ++a) {
         if (p->periodic[a]) continue;
-        if (ic[a] == 0) boundary_face(p, &t, a, 0, ic, x + c * nb, y + c * nb);
-        if (ic[a] == p->ncell[a] - 1) boundary_face(p, &t, a, 1, ic, x + c * nb, y + c * nb);
+        if (ic[a] == 0) bface(p, &t, a, 0, ic, x + c * nb, y + c * nb);
+        if (ic[a] == p->ncell[a] - 1) bface(p, &t, a, 1, ic, x + c * nb, y + c * nb);
       }
     }
   }
@@ -574,6 +891,8 @@ int oracle_apply(const or_problem *p, const double *x, double *y, int terms, int
 int oracle_apply_rows(const or_problem *p, const double *x, const int64_t *cells, int64_t ncsel,
                       double *y_rows, int terms, int nthreads) {
   if (check_problem(p)) return -1;
+  const or_iface_fn iface = p->multilinear_on ? ml_interior_face : interior_face;
+  const or_bface_fn bface = p->multilinear_on ? ml_boundary_face : boundary_face;
   or_tables t;
   make_tables(p->k, p->quad_extra, &t);
   const int64_t nb = (int64_t)t.n * t.n * t.n;
@@ -588,23 +907,23 @@ int oracle_apply_rows(const or_problem *p, const double *x, const int64_t *cells
     const int64_t c = cells[s];
     const int ic[3] = {(int)(c % N1), (int)((c / N1) % N2), (int)(c / ((int64_t)N1 * N2))};
     double *yT = y_rows + s * nb;
-    if (terms & OR_VOLUME) volume_cell(p, &t, ic, x + c * nb, yT);
+    if (terms & OR_VOLUME) (p->multilinear_on ? ml_volume_cell : volume_cell)(p, &t, ic, x + c * nb, yT);
     for (int a = 0; a < 3; ++a) {
       /* lower face of T (across the domain boundary on a periodic axis) */
       if (ic[a] == 0 && !p->periodic[a]) {
-        if (terms & OR_BOUNDARY) boundary_face(p, &t, a, 0, ic, x + c * nb, yT);
+        if (terms & OR_BOUNDARY) bface(p, &t, a, 0, ic, x + c * nb, yT);
       } else if (terms & OR_INTERIOR) {
         int jm[3] = {ic[0], ic[1], ic[2]};
         jm[a] = (ic[a] + p->ncell[a] - 1) % p->ncell[a];
-        interior_face(p, &t, a, jm, x + cell_id(p, jm) * nb, x + c * nb, NULL, yT);
+        iface(p, &t, a, jm, x + cell_id(p, jm) * nb, x + c * nb, NULL, yT);
       }
       /* upper face of T */
       if (ic[a] == p->ncell[a] - 1 && !p->periodic[a]) {
-        if (terms & OR_BOUNDARY) boundary_face(p, &t, a, 1, ic, x + c * nb, yT);
+        if (terms & OR_BOUNDARY) bface(p, &t, a, 1, ic, x + c * nb, yT);
       } else if (terms & OR_INTERIOR) {
         int jp[3] = {ic[0], ic[1], ic[2]};
         jp[a] = (ic[a] + 1) % p->ncell[a];
-        interior_face(p, &t, a, ic, x + c * nb, x + cell_id(p, jp) * nb, yT, NULL);
+        iface(p, &t, a, ic, x + c * nb, x + cell_id(p, jp) * nb, yT, NULL);
       }
     }
   }
@@ -645,16 +964,21 @@ int oracle_rhs(const or_problem *p, int nterms, const double *alpha, const int32
 #pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads)
   for (int64_t c = 0; c < ncells; ++c) {
     const int ic[3] = {(int)(c % N1), (int)((c / N1) % N2), (int)(c / ((int64_t)N1 * N2))};
-    double o[3], h[3];
-    cell_geom(p, ic, o, h);
+    double o[3] = {0.0, 0.0, 0.0}, h[3] = {1.0, 1.0, 1.0};
+    if (!p->multilinear_on) cell_geom(p, ic, o, h);
     double *fT = f + c * nb;
     memset(fT, 0, sizeof(double) * nb);
     for (int q3 = 0; q3 < m; ++q3)
       for (int q2 = 0; q2 < m; ++q2)
         for (int q1 = 0; q1 < m; ++q1) {
-          const double X[3] = {o[0] + h[0] * t.xi[q1], o[1] + h[1] * t.xi[q2],
-                               o[2] + h[2] * t.xi[q3]};
-          const double W = t.w[q1] * t.w[q2] * t.w[q3] * h[0] * h[1] * h[2];
+          double X[3] = {o[0] + h[0] * t.xi[q1], o[1] + h[1] * t.xi[q2], o[2] + h[2] * t.xi[q3]};
+          double W = t.w[q1] * t.w[q2] * t.w[q3] * h[0] * h[1] * h[2];
+          if (p->multilinear_on) {
+            const double xi[3] = {t.xi[q1], t.xi[q2], t.xi[q3]};
+            double J[9], C[9];
+            ml_map(p, ic, xi, X, J);
+            W = t.w[q1] * t.w[q2] * t.w[q3] * ml_cof(J, C);
+          }
           const double fx = sep_eval(nterms, alpha, kinds, X);
           for (int j3 = 0; j3 < n; ++j3)
             for (int j2 = 0; j2 < n; ++j2)
@@ -683,8 +1007,8 @@ double oracle_l2err2(const or_problem *p, const double *x, int nterms, const dou
   double err = 0.0;
   for (int64_t c = 0; c < ncells; ++c) {
     const int ic[3] = {(int)(c % N1), (int)((c / N1) % N2), (int)(c / ((int64_t)N1 * N2))};
-    double o[3], h[3];
-    cell_geom(p, ic, o, h);
+    double o[3] = {0.0, 0.0, 0.0}, h[3] = {1.0, 1.0, 1.0};
+    if (!p->multilinear_on) cell_geom(p, ic, o, h);
     const double *xT = x + c * nb;
     for (int q3 = 0; q3 < mq; ++q3)
       for (int q2 = 0; q2 < mq; ++q2)
@@ -694,9 +1018,16 @@ double oracle_l2err2(const or_problem *p, const double *x, int nterms, const dou
             for (int j2 = 0; j2 < n; ++j2)
               for (int j1 = 0; j1 < n; ++j1)
                 uh += xT[j1 + n * (j2 + n * j3)] * V[q1][j1] * V[q2][j2] * V[q3][j3];
-          const double X[3] = {o[0] + h[0] * xi[q1], o[1] + h[1] * xi[q2], o[2] + h[2] * xi[q3]};
+          double X[3] = {o[0] + h[0] * xi[q1], o[1] + h[1] * xi[q2], o[2] + h[2] * xi[q3]};
+          double W = w[q1] * w[q2] * w[q3] * h[0] * h[1] * h[2];
+          if (p->multilinear_on) {
+            const double xr[3] = {xi[q1], xi[q2], xi[q3]};
+            double J[9], C[9];
+            ml_map(p, ic, xr, X, J);
+            W = w[q1] * w[q2] * w[q3] * ml_cof(J, C);
+          }
           const double d = uh - sep_eval(nterms, alpha, kinds, X);
-          err += w[q1] * w[q2] * w[q3] * h[0] * h[1] * h[2] * d * d;
+          err += W * d * d;
         }
   }
   (void)N3;

@@ -68,6 +68,10 @@ class Problem:
     quad_extra: int = 0
     # affine geometry: the mesh is x = A xi of the tensor grid xi of the nodes (None: A = I)
     affine: np.ndarray | None = None
+    # multilinear geometry: vertex coordinates, shape (N3+1, N2+1, N1+1, 3) (axis 1 fastest);
+    # cell (i1,i2,i3) is the trilinear image of [0,1]^3 through its eight vertices (None: the
+    # tensor grid of the nodes)
+    vertices: np.ndarray | None = None
     name: str = ""
     meta: dict = field(default_factory=dict)
 
@@ -300,3 +304,81 @@ def manufactured_source(K, b, c):
 
 def constant_source(value: float = 1.0):
     return [(float(value), (ONE, ONE, ONE))]
+
+
+# ---------------------------------------------------------------------------
+# Vertex meshes: logically structured grids of (N1+1)(N2+1)(N3+1) vertices,
+# array shape (N3+1, N2+1, N1+1, 3) (axis 1 fastest); every cell is the
+# trilinear image of the reference cube through its eight vertices
+# (multilinear geometry, Sec. 4 and Problem C of Sec. 5.1).
+# ---------------------------------------------------------------------------
+def tensor_vertices(nodes) -> np.ndarray:
+    """The vertices of the tensor grid of the per-axis nodes."""
+    X = np.stack(np.meshgrid(nodes[0], nodes[1], nodes[2], indexing="ij"), axis=-1)
+    return np.ascontiguousarray(X.transpose(2, 1, 0, 3))
+
+
+def affine_vertices(nodes, A) -> np.ndarray:
+    """The vertices x = A xi of the tensor grid xi of the nodes."""
+    return np.ascontiguousarray(tensor_vertices(nodes) @ np.asarray(A, dtype=np.float64).T)
+
+
+def curved_vertices(ncell, eps: float = 0.04, jitter: float = 0.0, seed: int = 0) -> np.ndarray:
+    """Uniform vertex grid of [0,1]^3 moved by the smooth field
+        d_a(xi) = eps sin(pi xi_a) sin(pi (xi_{a+1} + 2 xi_{a+2}) + a)
+    (indices mod 3) plus, with jitter > 0, independent uniform offsets of up to
+    jitter times the cell size per coordinate.  Offsets normal to the boundary
+    are zero on boundary vertices, so every boundary face stays in its plane of
+    the cube; cells are general (non-affine) hexahedra."""
+    N1, N2, N3 = ncell
+    X = tensor_vertices((uniform_nodes(N1), uniform_nodes(N2), uniform_nodes(N3)))
+    xi = X.copy()
+    for a in range(3):
+        X[..., a] += eps * np.sin(math.pi * xi[..., a]) * np.sin(
+            math.pi * (xi[..., (a + 1) % 3] + 2.0 * xi[..., (a + 2) % 3]) + a)
+    if jitter > 0.0:
+        rng = np.random.default_rng(seed)
+        h = np.array([1.0 / N1, 1.0 / N2, 1.0 / N3])
+        off = rng.uniform(-1.0, 1.0, X.shape) * jitter * h
+        for a in range(3):
+            on_bnd = (xi[..., a] == 0.0) | (xi[..., a] == 1.0)
+            off[..., a][on_bnd] = 0.0
+        X += off
+    return np.ascontiguousarray(X)
+
+
+def sheared_vertices(nodes, seed: int = 0, amount: float = 0.3) -> np.ndarray:
+    """x = xi + s(xi_3) e_1 + r(xi_1) e_2 with s and r piecewise linear between
+    the nodes (random values of up to `amount` times the local spacing at each
+    node): every cell is a parallelepiped, and its Jacobian changes from one
+    layer of cells to the next (affine cells, Problem B of Sec. 5.1)."""
+    rng = np.random.default_rng(seed)
+    X = tensor_vertices(nodes)
+    h3 = np.diff(nodes[2]).min()
+    h1 = np.diff(nodes[0]).min()
+    s = rng.uniform(-amount, amount, len(nodes[2])) * h3
+    r = rng.uniform(-amount, amount, len(nodes[0])) * h1
+    X[..., 0] += s[:, None, None]
+    X[..., 1] += r[None, None, :]
+    return np.ascontiguousarray(X)
+
+
+def vertex_problem(vertices, k: int, quad_extra: int = 0, K=None, kappa=None, b: str = "sine",
+                   c: float = 1.0, kappa_poly=None, name: str = "vertex") -> Problem:
+    """A problem on a vertex mesh with the coefficient forms of the other
+    workloads (b: 'sine' = (sin pi y, sin pi z, sin pi x), 'const' =
+    (1, .5, .25), 'zero')."""
+    V = np.asarray(vertices, dtype=np.float64)
+    ncell = (V.shape[2] - 1, V.shape[1] - 1, V.shape[0] - 1)
+    nodes = tuple(uniform_nodes(ncell[a]) for a in range(3))
+    bk = SINE_CYCLIC if b == "sine" else B_CONST if b == "const" else dict(
+        b_const=(0.0, 0.0, 0.0), b_sin=(0.0, 0.0, 0.0), b_axis=(0, 1, 2))
+    return Problem(ncell=ncell, nodes=nodes, k=k, K=np.eye(3) if K is None else np.asarray(K), kappa=kappa,
+                   c=c, sigma=paper_sigma(k), quad_extra=quad_extra, kappa_poly=kappa_poly, vertices=V,
+                   name=name, **bk)
+
+
+def problem_c_quad_extra(k: int) -> int:
+    """Extra Gauss points of the rule q = 3p + 4 (Problem C, Sec. 5.1): the
+    Gauss rule exact to degree 3k + 4 has ceil((3k + 5) / 2) points."""
+    return (3 * k + 5 + 1) // 2 - (k + 1)

@@ -4,7 +4,7 @@
  * tests/test_oracle_sanitizers.py, it calls every exported oracle routine
  * on small problems of every kind the oracle accepts (every degree, single
  * cells, periodic axes, product-form b, the polynomial diffusion factor, the
- * raised rule, affine meshes) and checks that the whole-mesh apply and the
+ * raised rule, affine and multilinear meshes) and checks that the whole-mesh apply and the
  * per-cell rows agree.  Any out-of-bounds access, use of uninitialised or
  * freed memory, or undefined arithmetic is reported by the sanitizers and
  * fails the run.  Test infrastructure only.
@@ -24,7 +24,9 @@ static double urand(void) {
   return (double)(z >> 11) / 4503599627370496.0 - 1.0;
 }
 
-static int run_case(int k, const int *ncell, int periodic, int bprod, int kpoly, int qx, int affine) {
+/* multilinear: vertices of the nodes' tensor grid moved by up to 0.15 of a
+ * cell in every coordinate (the cells stay valid hexahedra) */
+static int run_case(int k, const int *ncell, int periodic, int bprod, int kpoly, int qx, int affine, int multilinear) {
   double *nodes[3];
   for (int a = 0; a < 3; ++a) {
     nodes[a] = malloc(sizeof(double) * (ncell[a] + 1));
@@ -68,6 +70,21 @@ static int run_case(int k, const int *ncell, int periodic, int bprod, int kpoly,
   p.affine_on = affine;
   const double A[9] = {1.2, 0.3, -0.1, 0.1, 0.8, 0.25, -0.2, 0.15, 1.1};
   memcpy(p.affine, A, sizeof(A));
+  double *verts = NULL;
+  if (multilinear) {
+    const int64_t nv = (int64_t)(ncell[0] + 1) * (ncell[1] + 1) * (ncell[2] + 1);
+    verts = malloc(sizeof(double) * 3 * nv);
+    for (int v2 = 0; v2 <= ncell[2]; ++v2)
+      for (int v1 = 0; v1 <= ncell[1]; ++v1)
+        for (int v0 = 0; v0 <= ncell[0]; ++v0) {
+          const int vi[3] = {v0, v1, v2};
+          double *X = verts + 3 * (v0 + (int64_t)(ncell[0] + 1) * (v1 + (int64_t)(ncell[1] + 1) * v2));
+          for (int a = 0; a < 3; ++a) X[a] = nodes[a][vi[a]] + 0.15 * urand();
+        }
+    p.multilinear_on = 1;
+    p.vertices = verts;
+    for (int a = 0; a < 3; ++a) p.periodic[a] = 0;
+  }
 
   const int64_t nd = oracle_ndof(&p), nb = (int64_t)(k + 1) * (k + 1) * (k + 1);
   double *x = malloc(sizeof(double) * nd), *y = malloc(sizeof(double) * nd), *yr = malloc(sizeof(double) * nd);
@@ -90,8 +107,10 @@ static int run_case(int k, const int *ncell, int periodic, int bprod, int kpoly,
     const double e2 = oracle_l2err2(&p, x, 2, alpha, kinds);
     if (!(e2 > 0.0)) bad = 1;
   }
-  printf("k=%d ncell=%dx%dx%d per=%d bprod=%d kpoly=%d qx=%d affine=%d: apply/rows max diff %.2e of %.2e %s\n", k,
-         ncell[0], ncell[1], ncell[2], periodic, bprod, kpoly, qx, affine, dif, mx, bad ? "FAIL" : "ok");
+  printf("k=%d ncell=%dx%dx%d per=%d bprod=%d kpoly=%d qx=%d affine=%d multilinear=%d: apply/rows max diff %.2e of "
+         "%.2e %s\n", k, ncell[0], ncell[1], ncell[2], periodic, bprod, kpoly, qx, affine, multilinear, dif, mx,
+         bad ? "FAIL" : "ok");
+  free(verts);
   free(cells);
   free(yr);
   free(y);
@@ -103,20 +122,23 @@ static int run_case(int k, const int *ncell, int periodic, int bprod, int kpoly,
 
 int main(void) {
   int bad = 0;
-  double xi[12], w[12], v[11], d[11];
-  for (int m = 1; m <= 12; ++m) bad |= oracle_gauss(m, xi, w) != 0;
+  double xi[14], w[14], v[11], d[11];
+  for (int m = 1; m <= 14; ++m) bad |= oracle_gauss(m, xi, w) != 0;
   for (int k = 1; k <= 10; ++k) oracle_basis(k, 0.3, v, d);
   const int meshes[4][3] = {{1, 1, 1}, {3, 2, 2}, {2, 1, 3}, {1, 3, 1}};
   for (int k = 1; k <= 10; ++k) {
     const int *nc = meshes[k % 4];
-    bad |= run_case(k, nc, k % 8, 0, 0, 0, 0);
+    bad |= run_case(k, nc, k % 8, 0, 0, 0, 0, 0);
   }
-  bad |= run_case(3, meshes[1], 5, 1, 0, 0, 0);
-  bad |= run_case(4, meshes[2], 2, 1, 1, 0, 0);
-  bad |= run_case(2, meshes[1], 0, 0, 1, 2, 0);
-  bad |= run_case(8, meshes[0], 7, 1, 1, 2, 0);
-  bad |= run_case(3, meshes[1], 1, 0, 0, 0, 1);
-  bad |= run_case(2, meshes[3], 6, 0, 1, 2, 1);
+  bad |= run_case(3, meshes[1], 5, 1, 0, 0, 0, 0);
+  bad |= run_case(4, meshes[2], 2, 1, 1, 0, 0, 0);
+  bad |= run_case(2, meshes[1], 0, 0, 1, 2, 0, 0);
+  bad |= run_case(8, meshes[0], 7, 1, 1, 2, 0, 0);
+  bad |= run_case(3, meshes[1], 1, 0, 0, 0, 1, 0);
+  bad |= run_case(2, meshes[3], 6, 0, 1, 2, 1, 0);
+  bad |= run_case(1, meshes[1], 0, 0, 0, 0, 0, 1);
+  bad |= run_case(2, meshes[2], 0, 1, 1, 2, 0, 1);
+  bad |= run_case(7, meshes[0], 0, 0, 1, 5, 0, 1);
   printf(bad ? "SANITIZER DRIVER: FAIL\n" : "SANITIZER DRIVER: OK\n");
   return bad;
 }
