@@ -383,6 +383,21 @@ dg_status dg_mlp_step(dg_handle *h, const float *X, const float *T, int32_t B, f
  * ------------------------------------------------------------------------- */
 dg_status dg_heun(dg_handle *h, double *u, const double *f, double dt, int32_t nsteps, void *hip_stream);
 
+/* dg_heun for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * steps and kernels, with the stage workspace taken from a fixed array of
+ * 64 MiB in device memory that the library holds on every device it runs on
+ * until the process ends, instead of the handle's workspace.  It calls no
+ * allocating routine.  Needs ndof * 8 bytes on the fused path (tuned kernels,
+ * quad_extra = 0) and 2 ndof * 8 bytes otherwise (reference kernel, raised
+ * rule): at most 8,388,608 or 4,194,304 DOF; larger handles get DG_EINVAL
+ * (use dg_heun).  Every call on one device shares that array and it keeps
+ * the last call's contents (nothing in it needs to start at zero): calls
+ * that overlap in time on one device, from several streams or threads,
+ * race and give wrong results.  Arguments, stream behaviour and the other
+ * errors as dg_heun. */
+dg_status dg_heun_noalloc(dg_handle *h, double *u, const double *f, double dt, int32_t nsteps, void *hip_stream);
+
 /* Number of degrees of freedom of the handle's space (or -1 for NULL). */
 int64_t dg_ndof(const dg_handle *h);
 

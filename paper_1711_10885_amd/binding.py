@@ -31,7 +31,7 @@ _STATUS = {DG_EINVAL: "DG_EINVAL", DG_ENOMEM: "DG_ENOMEM", DG_EHIP: "DG_EHIP",
 # every symbol include/dg.h declares
 EXPORTS = ["dg_setup", "dg_apply", "dg_apply_f32", "dg_load_vector", "dg_set_kernel", "dg_solve", "dg_precond_apply",
            "dg_learned_train", "dg_learned_nparams", "dg_learned_set_params", "dg_learned_get_params",
-           "dg_mlp_forward", "dg_mlp_grad", "dg_mlp_step", "dg_heun", "dg_ndof", "dg_degree", "dg_bj_nblocks",
+           "dg_mlp_forward", "dg_mlp_grad", "dg_mlp_step", "dg_heun", "dg_heun_noalloc", "dg_ndof", "dg_degree", "dg_bj_nblocks",
            "dg_last_error", "dg_destroy"]
 
 
@@ -116,6 +116,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dg_load_vector.restype = ctypes.c_int
     lib.dg_heun.argtypes = [H, vp, vp, ctypes.c_double, ctypes.c_int32, vp]
     lib.dg_heun.restype = ctypes.c_int
+    lib.dg_heun_noalloc.argtypes = [H, vp, vp, ctypes.c_double, ctypes.c_int32, vp]
+    lib.dg_heun_noalloc.restype = ctypes.c_int
     lib.dg_apply_f32.argtypes = [H, vp, vp, vp]
     lib.dg_apply_f32.restype = ctypes.c_int
     lib.dg_set_kernel.argtypes = [H, ctypes.c_int32]
@@ -329,6 +331,19 @@ class DG:
             fp = ctypes.c_void_p(f.data_ptr())
         _check(load().dg_heun(self._h, ctypes.c_void_p(u.data_ptr()), fp, float(dt), int(nsteps),
                               _stream_ptr(stream)))
+        return u
+
+    def heun_noalloc(self, u, dt: float, nsteps: int, f=None, stream=None):
+        """heun() through dg_heun_noalloc: the stage workspace is the library's
+        fixed per-device array, nothing is allocated."""
+        import torch
+        _check_vec(u, self.ndof, torch.float64, "u")
+        fp = ctypes.c_void_p()
+        if f is not None:
+            _check_vec(f, self.ndof, torch.float64, "f")
+            fp = ctypes.c_void_p(f.data_ptr())
+        _check(load().dg_heun_noalloc(self._h, ctypes.c_void_p(u.data_ptr()), fp, float(dt), int(nsteps),
+                                      _stream_ptr(stream)))
         return u
 
     def bj_nblocks(self) -> int:

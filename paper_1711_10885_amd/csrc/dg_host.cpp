@@ -310,6 +310,10 @@ extern "C" dg_status dg_setup(const dg_problem *p_in, dg_handle **out) {
     delete h;
     return set_error(DG_EHIP, "dg_setup: no HIP device");
   }
+  if (dg_status st = static_scratch_init(h->device); st != DG_OK) {
+    delete h;
+    return st;
+  }
   build_tables(p->k, h->tab);
   build_tables(p->k, h->tabq, n + p->quad_extra);
   h->quad_extra = p->quad_extra;

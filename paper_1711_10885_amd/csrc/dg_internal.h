@@ -127,6 +127,10 @@ template <typename TR>
 hipError_t learned_apply(dg_handle *h, const TR *r, TR *z, hipStream_t s);
 bool learned_ready(const dg_handle *h);
 
+// Resolve, once per device (that device current), the address of the static
+// workspace of dg_heun_noalloc (called by dg_setup).
+dg_status static_scratch_init(int device);
+
 // Free the solver / learned resources of a handle (called by dg_destroy).
 void release_solver(dg_handle *h);
 void release_learned(dg_handle *h);

@@ -16,6 +16,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
+#include <string>
 
 #include "dg_internal.h"
 
@@ -47,22 +49,94 @@ __global__ __launch_bounds__(kTsThreads) void k_heun_stage(const double *u, cons
 
 static int ts_grid(int64_t n) { return int(std::min<int64_t>((n + kTsThreads - 1) / kTsThreads, 1 << 20)); }
 
+// the stage update fused into the operator kernel's store (tuned kernels,
+// (k+1)-point rule), else an apply into A u and a separate stage pass
+static bool heun_is_fused(const dg_handle *h) { return h->variant != DG_KERNEL_REFERENCE && !h->quad_extra; }
+
+}  // namespace dgmf
+
+// Fixed workspace of dg_heun_noalloc: the stage vector u1 (and A u on the
+// paths with a separate stage pass) for callers that cannot allocate.  One
+// copy per device, resident while the library is loaded.  Host code never
+// passes the array's name to a kernel (on the host it is a stand-in, not a
+// device address): it uses the per-device address that
+// dgmf::static_scratch_init resolves with hipGetSymbolAddress.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) double scratch[kStaticScratchBytes / sizeof(double)];
+
+namespace dgmf {
+
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[kMaxScratchDevices];
+
+dg_status static_scratch_init(int device) {
+  if (device < 0 || device >= kMaxScratchDevices)
+    return set_error(DG_EINVAL, "dg_setup: device index beyond the static workspace table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return DG_OK;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) return hip_error(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                                "dg_setup: address of the static workspace");
+  g_scratch_ptr[device] = static_cast<double *>(ptr);
+  return DG_OK;
+}
+
+// The Heun steps of dg_heun and dg_heun_noalloc on the given workspace: u1
+// (ndof doubles) and, on the paths with a separate stage pass, Au (ndof
+// doubles; may be null on the fused path).
+static dg_status heun_steps(dg_handle *h, double *u, const double *f, double dt, int32_t nsteps, hipStream_t s,
+                            double *u1, double *Au, const char *who) {
+  const size_t n = size_t(h->ndof);
+  dt /= h->vol_scale;  // |T| of the physical cells: |det A| times the tensor-grid volumes
+  if (heun_is_fused(h)) {
+    for (int step = 0; step < nsteps; ++step) {
+      hipError_t e = launch_heun_fused_f64(h, u, u1, f, dt, 0, s);
+      if (e == hipSuccess) e = launch_heun_fused_f64(h, u1, u, f, dt, 1, s);
+      if (e != hipSuccess) return hip_error(e, who);
+    }
+    return DG_OK;
+  }
+  const int nb = (h->k + 1) * (h->k + 1) * (h->k + 1);
+  const int grid = ts_grid(int64_t(n));
+  for (int step = 0; step < nsteps; ++step) {
+    hipError_t e = apply_f64(h, u, Au, s);
+    if (e != hipSuccess) return hip_error(e, who);
+    hipLaunchKernelGGL(k_heun_stage<0>, dim3(grid), dim3(kTsThreads), 0, s, u, nullptr, Au, f, h->mesh, nb,
+                       int64_t(n), dt, u1);
+    if ((e = apply_f64(h, u1, Au, s)) != hipSuccess) return hip_error(e, who);
+    hipLaunchKernelGGL(k_heun_stage<1>, dim3(grid), dim3(kTsThreads), 0, s, u, u1, Au, f, h->mesh, nb,
+                       int64_t(n), dt, u);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_error(e, who);
+  }
+  return DG_OK;
+}
+
+static dg_status heun_check(dg_handle *h, double *u, const double *f, double dt, int32_t nsteps, const char *who) {
+  if (!h) return set_error(DG_EINVAL, std::string(who) + ": handle is NULL");
+  if (!u) return set_error(DG_EINVAL, std::string(who) + ": u is NULL");
+  if (!(dt > 0.0) || !std::isfinite(dt))
+    return set_error(DG_EINVAL, std::string(who) + ": dt must be positive and finite");
+  if (nsteps < 0) return set_error(DG_EINVAL, std::string(who) + ": nsteps must be >= 0");
+  const size_t n = size_t(h->ndof);
+  if (f && ((f < u + n && u < f + n))) return set_error(DG_EINVAL, std::string(who) + ": u and f overlap");
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != h->device) {
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_error(e, who);
+  }
+  return DG_OK;
+}
+
 }  // namespace dgmf
 
 using namespace dgmf;
 
 extern "C" dg_status dg_heun(dg_handle *h, double *u, const double *f, double dt, int32_t nsteps, void *stream) {
-  if (!h) return set_error(DG_EINVAL, "dg_heun: handle is NULL");
-  if (!u) return set_error(DG_EINVAL, "dg_heun: u is NULL");
-  if (!(dt > 0.0) || !std::isfinite(dt)) return set_error(DG_EINVAL, "dg_heun: dt must be positive and finite");
-  if (nsteps < 0) return set_error(DG_EINVAL, "dg_heun: nsteps must be >= 0");
-  int cur = -1;
-  if (hipGetDevice(&cur) != hipSuccess || cur != h->device) {
-    hipError_t e = hipSetDevice(h->device);
-    if (e != hipSuccess) return hip_error(e, "dg_heun: hipSetDevice");
-  }
+  dg_status st = heun_check(h, u, f, dt, nsteps, "dg_heun");
+  if (st != DG_OK) return st;
   const size_t n = size_t(h->ndof);
-  if (f && ((f < u + n && u < f + n))) return set_error(DG_EINVAL, "dg_heun: u and f overlap");
   // two vectors (u1 and, for the reference variant, A u) whatever the
   // variant, which dg_set_kernel may change between calls
   if (!h->ts) {
@@ -72,29 +146,20 @@ extern "C" dg_status dg_heun(dg_handle *h, double *u, const double *f, double dt
       return hip_error(e, "dg_heun: workspace");
     }
   }
-  const hipStream_t s = static_cast<hipStream_t>(stream);
-  dt /= h->vol_scale;  // |T| of the physical cells: |det A| times the tensor-grid volumes
-  if (h->variant != DG_KERNEL_REFERENCE && !h->quad_extra) {
-    double *u1 = h->ts;
-    for (int step = 0; step < nsteps; ++step) {
-      hipError_t e = launch_heun_fused_f64(h, u, u1, f, dt, 0, s);
-      if (e == hipSuccess) e = launch_heun_fused_f64(h, u1, u, f, dt, 1, s);
-      if (e != hipSuccess) return hip_error(e, "dg_heun: stage");
-    }
-    return DG_OK;
-  }
-  double *u1 = h->ts, *Au = h->ts + n;
-  const int nb = (h->k + 1) * (h->k + 1) * (h->k + 1);
-  const int grid = ts_grid(int64_t(n));
-  for (int step = 0; step < nsteps; ++step) {
-    hipError_t e = apply_f64(h, u, Au, s);
-    if (e != hipSuccess) return hip_error(e, "dg_heun: apply");
-    hipLaunchKernelGGL(k_heun_stage<0>, dim3(grid), dim3(kTsThreads), 0, s, u, nullptr, Au, f, h->mesh, nb,
-                       int64_t(n), dt, u1);
-    if ((e = apply_f64(h, u1, Au, s)) != hipSuccess) return hip_error(e, "dg_heun: apply");
-    hipLaunchKernelGGL(k_heun_stage<1>, dim3(grid), dim3(kTsThreads), 0, s, u, u1, Au, f, h->mesh, nb,
-                       int64_t(n), dt, u);
-    if ((e = hipGetLastError()) != hipSuccess) return hip_error(e, "dg_heun: stage update");
-  }
-  return DG_OK;
+  return heun_steps(h, u, f, dt, nsteps, static_cast<hipStream_t>(stream), h->ts, h->ts + n, "dg_heun: stage");
+}
+
+extern "C" dg_status dg_heun_noalloc(dg_handle *h, double *u, const double *f, double dt, int32_t nsteps,
+                                     void *stream) {
+  dg_status st = heun_check(h, u, f, dt, nsteps, "dg_heun_noalloc");
+  if (st != DG_OK) return st;
+  double *ws = (h->device >= 0 && h->device < kMaxScratchDevices) ? g_scratch_ptr[h->device] : nullptr;
+  if (!ws) return set_error(DG_EINVAL, "dg_heun_noalloc: the static workspace of this device is not set up");
+  const size_t n = size_t(h->ndof);
+  const size_t need = (heun_is_fused(h) ? 1 : 2) * n * sizeof(double);
+  if (need > kStaticScratchBytes)
+    return set_error(DG_EINVAL, "dg_heun_noalloc: needs " + std::to_string(need) + " bytes of workspace, above the " +
+                                    std::to_string(kStaticScratchBytes) + "-byte static limit (use dg_heun)");
+  return heun_steps(h, u, f, dt, nsteps, static_cast<hipStream_t>(stream), ws, heun_is_fused(h) ? nullptr : ws + n,
+                    "dg_heun_noalloc: stage");
 }
