@@ -142,6 +142,33 @@ typedef enum {
  *              (affine cells, polynomial coefficients and the raised rule
  *              together are Problem B).  dg_load_vector rejects such
  *              handles; dg_heun uses the physical cell volumes.
+ *   vertices   with DG_MULTILINEAR the mesh is given by its vertices, a
+ *              logically structured grid of (N1+1)(N2+1)(N3+1) points (host
+ *              array of 3 doubles each, vertex (v0,v1,v2) at index
+ *              v0 + (N1+1)(v1 + (N2+1) v2)); cell (i0,i1,i2) is the image of
+ *              the reference cube under the trilinear (Q1) map through the
+ *              vertices (i0+c0, i1+c1, i2+c2), c in {0,1}^3 (multilinear
+ *              geometry, Sec. 4; Problem C of Sec. 5.1; parallelepiped cells
+ *              with different Jacobians are the affine cells of Problem B).
+ *              The Jacobian J of the map is evaluated at every quadrature
+ *              point: gradients J^{-T} grad_ref, volume weight det J, and on
+ *              a face xi_a = e the area-weighted normal cof(J) e_a, so nu,
+ *              d = nu^T D nu, the weights and gamma_F vary over a face; in
+ *              gamma_F, |F| / min(|T-|,|T+|) is the face area over the
+ *              smaller cell volume (integrated with the operator's rule).  b
+ *              (either form) and the polynomial factor kp are evaluated at
+ *              the physical point.  nodes are ignored (may be NULL).  The
+ *              Gauss rule: quad_extra 0, 2, or ceil((k+3)/2) (the rule
+ *              q = 3p + 4 of Problem C, ceil((3k+5)/2) points), k <= 7.
+ *              Requires det J > 0 at the corners and centre of every cell,
+ *              kp > 0 on the vertices' bounding box, no periodic axis, no
+ *              DG_AFFINE and no DG_WITH_BLOCK_JACOBI: DG_EINVAL otherwise.
+ *              Only dg_apply (always the multilinear reference-layout
+ *              kernel) and dg_solve with DG_GMRES64 and DG_PREC_NONE run on
+ *              such handles; the FP32 operator, dg_heun (the mass matrix is
+ *              not diagonal on non-affine cells) and dg_load_vector return
+ *              DG_EINVAL.  The handle keeps (N1+1)(N2+1)(N3+1) 3 + ncells +
+ *              3 (N+1) N N doubles of geometry tables.
  */
 typedef struct {
   int32_t ncell[3];
@@ -161,6 +188,7 @@ typedef struct {
   double kappa_poly[9];  /* polynomial diffusion factor (DG_KAPPA_POLY only) */
   int32_t quad_extra;    /* Gauss points per direction m = k + 1 + quad_extra */
   double affine[9];      /* A of the affine map x = A xi (DG_AFFINE only), row-major */
+  const double *vertices; /* vertex coordinates (DG_MULTILINEAR only), see above */
 } dg_problem;
 
 #define DG_WITH_BLOCK_JACOBI 2
@@ -170,6 +198,7 @@ typedef struct {
 #define DG_B_PRODUCT 32
 #define DG_KAPPA_POLY 64
 #define DG_AFFINE 128
+#define DG_MULTILINEAR 256
 
 /* Create a handle on the current HIP device: validates the problem, builds
  * the 1D Gauss-Legendre/Legendre tables (Sec. 3.1/3.2, eq.

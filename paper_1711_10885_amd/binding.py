@@ -20,6 +20,7 @@ DG_PERIODIC_X, DG_PERIODIC_Y, DG_PERIODIC_Z = 4, 8, 16
 DG_B_PRODUCT = 32
 DG_KAPPA_POLY = 64
 DG_AFFINE = 128
+DG_MULTILINEAR = 256
 DG_KERNEL_AUTO, DG_KERNEL_REFERENCE = 0, 1
 DG_GMRES64, DG_GMRES_IR, DG_FGMRES = 0, 1, 2
 DG_PREC_NONE, DG_PREC_BLOCK_JACOBI, DG_PREC_LEARNED = 0, 1, 2
@@ -60,6 +61,7 @@ class _Problem(ctypes.Structure):
         ("kappa_poly", ctypes.c_double * 9),
         ("quad_extra", ctypes.c_int32),
         ("affine", ctypes.c_double * 9),
+        ("vertices", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -257,6 +259,14 @@ class DG:
             s.flags |= DG_KAPPA_POLY
             for t in range(9):
                 s.kappa_poly[t] = float(kpoly[t])
+        verts = getattr(prob, "vertices", None)
+        if verts is not None:
+            V = np.ascontiguousarray(verts, dtype=np.float64).ravel()
+            if V.size != 3 * int(np.prod([prob.ncell[a] + 1 for a in range(3)])):
+                raise ValueError("vertices must hold (N1+1)(N2+1)(N3+1) points")
+            self._keep.append(V)
+            s.flags |= DG_MULTILINEAR
+            s.vertices = _dptr(V)
         h = ctypes.c_void_p()
         _check(lib.dg_setup(ctypes.byref(s), ctypes.byref(h)))
         self._h = h

@@ -15,6 +15,20 @@
 //    tangential directions; the pointwise upwind, weighted-average and penalty
 //    terms; the transposed tangential contractions; and the normal direction
 //    last, into the test functions of T only.
+//
+// Multilinear meshes (GEO = true; Sec. 4, Problem C of Sec. 5.1): every cell
+// is the trilinear image of the reference cube through its eight vertices.
+// The map and its Jacobian J are evaluated at each quadrature point by one
+// linear contraction per direction (the Q1 map is a degree-1 tensor
+// polynomial, so this is sum factorization with 2-point factors), from the
+// vertices of the cell and of its six face neighbours staged in LDS.  With
+// C = cof(J) = det(J) J^{-T} the volume flux enters the transposed
+// contractions as w C^T (D C grad_ref u / det J - b u) and the reaction as
+// w det J c u; on the face xi_a = e the outer area-weighted normal is
+// +-C e_a, and the symmetry term integrates against the reference gradient
+// with the vector -W w_T [[u]] C^T D nu / det J.  Every face quantity of
+// Sec. 2.2 (d = nu^T D nu, weights, gamma_F, b . nu) is taken per point;
+// |F| and |T| in gamma_F come from per-face and per-cell tables.
 #include "dg_internal.h"
 #include "mesh_nb.h"
 
@@ -22,7 +36,7 @@ namespace dgmf {
 
 template <int N, int Q>
 struct RefTab {
-  double V[Q][N], D[Q][N], w[Q], ev[2][N], ed[2][N];
+  double V[Q][N], D[Q][N], w[Q], xi[Q], ev[2][N], ed[2][N];
 };
 
 struct RefMesh {
@@ -35,6 +49,12 @@ struct RefMesh {
   int b_axis[3];
   int bprod, kpoly;
   int ncells;
+  // multilinear meshes (GEO kernels): vertex coordinates (N1+1)(N2+1)(N3+1) x 3,
+  // |T| per cell, |F| per face normal to axis a indexed (i_a + e) + (N_a + 1)
+  // (i_b + N_b i_c) (b < c the tangential axes); b and kp as formulas of the
+  // physical point
+  const double *verts, *cvol, *farea[3];
+  double b_const[3], b_sin[3], b_amp[3], b_freq[9], b_phase[9], kpc[9];
 };
 
 constexpr int kRefThreads = 256;
@@ -90,19 +110,86 @@ __device__ __forceinline__ const double *pickp(const double *const *t, int i) {
   return p;
 }
 
+// ---- multilinear geometry --------------------------------------------------
+
+constexpr int kVB = 4;  // vertex block 4 x 4 x 4 around a cell: planes i-1 .. i+2
+
+// The trilinear map of the cell whose first vertex is block vertex
+// (o0, o1, o2), at reference point (s0, s1, s2): point X and Jacobian
+// J[3r + t] = d X_r / d s_t, by a linear contraction along each direction.
+__device__ inline void tri_map(const double *VB, int o0, int o1, int o2, double s0, double s1, double s2, double *X,
+                               double *J) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    auto v = [&](int c0, int c1, int c2) { return VB[3 * ((o0 + c0) + kVB * ((o1 + c1) + kVB * (o2 + c2))) + r]; };
+    const double v000 = v(0, 0, 0), v100 = v(1, 0, 0), v010 = v(0, 1, 0), v110 = v(1, 1, 0);
+    const double v001 = v(0, 0, 1), v101 = v(1, 0, 1), v011 = v(0, 1, 1), v111 = v(1, 1, 1);
+    const double d00 = v100 - v000, d10 = v110 - v010, d01 = v101 - v001, d11 = v111 - v011;
+    const double a00 = fma(s0, d00, v000), a10 = fma(s0, d10, v010);
+    const double a01 = fma(s0, d01, v001), a11 = fma(s0, d11, v011);
+    const double f0 = a10 - a00, f1 = a11 - a01;
+    const double b0 = fma(s1, f0, a00), b1 = fma(s1, f1, a01);
+    const double e0 = fma(s1, d10 - d00, d00), e1 = fma(s1, d11 - d01, d01);
+    X[r] = fma(s2, b1 - b0, b0);
+    J[3 * r + 0] = fma(s2, e1 - e0, e0);
+    J[3 * r + 1] = fma(s2, f1 - f0, f0);
+    J[3 * r + 2] = b1 - b0;
+  }
+}
+
+// C = cof(J) = det(J) J^{-T} (row-major); returns det J
+__device__ inline double cof3(const double *J, double *C) {
+  C[0] = J[4] * J[8] - J[5] * J[7];
+  C[1] = J[5] * J[6] - J[3] * J[8];
+  C[2] = J[3] * J[7] - J[4] * J[6];
+  C[3] = J[2] * J[7] - J[1] * J[8];
+  C[4] = J[0] * J[8] - J[2] * J[6];
+  C[5] = J[1] * J[6] - J[0] * J[7];
+  C[6] = J[1] * J[5] - J[2] * J[4];
+  C[7] = J[2] * J[3] - J[0] * J[5];
+  C[8] = J[0] * J[4] - J[1] * J[3];
+  return J[0] * C[0] + J[1] * C[1] + J[2] * C[2];
+}
+
+// component r of b at the physical point X (sum form with a sine part, or
+// the product form)
+__device__ inline double geo_b(const RefMesh &M, int r, const double *X) {
+  if (M.bprod) {
+    double v = M.b_amp[r];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      if (M.b_freq[3 * r + j] != 0.0) v *= sin(fma(M.b_freq[3 * r + j], X[j], M.b_phase[3 * r + j]));
+    return v;
+  }
+  const int ax = M.b_axis[r];
+  const double xa = ax == 0 ? X[0] : (ax == 1 ? X[1] : X[2]);
+  return M.b_sin[r] != 0.0 ? fma(M.b_sin[r], sin(M_PI * xa), M.b_const[r]) : M.b_const[r];
+}
+
+// polynomial diffusion factor at the physical point (1 without it)
+__device__ inline double geo_kp(const RefMesh &M, const double *X) {
+  if (!M.kpoly) return 1.0;
+  double v = 1.0;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) v *= M.kpc[3 * j] + M.kpc[3 * j + 1] * X[j] + M.kpc[3 * j + 2] * X[j] * X[j];
+  return v;
+}
+
 // CPB cells per workgroup, kRefThreads / CPB threads and one LDS slice each
 // (CPB = 1 for the (k+1)-point reference variant).
-template <int N, int Q, int CPB>
+template <int N, int Q, int CPB, bool GEO>
 __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__restrict__ x,
                                                                 double *__restrict__ y,
                                                                 RefMesh M, RefTab<N, Q> T) {
   constexpr int NB = N * N * N, NF = N * N, QB = Q * Q * Q, QF = Q * Q;
   constexpr int TPC = kRefThreads / CPB;
-  __shared__ double sV[Q][N], sD[Q][N], sw[Q], sev[2][N], sed[2][N];
-  // raised rule: the six faces are processed together (one pass per
-  // contraction over a (., ., 6) block); their 24 NF + 72 QF doubles share the
-  // region of the volume tensors, which are dead by then
-  constexpr bool BATCH = (Q != N);
+  __shared__ double sV[Q][N], sD[Q][N], sw[Q], sxi[Q], sev[2][N], sed[2][N];
+  // raised rule and multilinear cells: the six faces are processed together
+  // (one pass per contraction over a (., ., 6) block); their 24 NF + 72 QF
+  // doubles share the region of the volume tensors, which are dead by then
+  constexpr bool BATCH = (Q != N) || GEO;
+  constexpr int VBN = GEO ? 3 * kVB * kVB * kVB : 1;
+  __shared__ double VBs[CPB][VBN];
   constexpr int FB = 24 * NF + 72 * QF;
   constexpr int RSZ = (BATCH && FB > 7 * QB) ? FB : 7 * QB;
   __shared__ double Xs[CPB][NB], Ys[CPB][NB], Rs[CPB][RSZ];
@@ -126,7 +213,10 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
     sV[i / N][i % N] = T.V[i / N][i % N];
     sD[i / N][i % N] = T.D[i / N][i % N];
   }
-  if (tid < Q) sw[tid] = T.w[tid];
+  if (tid < Q) {
+    sw[tid] = T.w[tid];
+    sxi[tid] = T.xi[tid];
+  }
   if (tid < N) {
     sev[0][tid] = T.ev[0][tid];
     sev[1][tid] = T.ev[1][tid];
@@ -135,6 +225,16 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
   }
   const double *xT = x + size_t(cell) * NB;
   for (int i = lt; i < NB; i += TPC) X[i] = xT[i];
+  if constexpr (GEO) {
+    // vertices (i_a - 1 .. i_a + 2 per axis; zero where outside the vertex grid)
+    for (int i = lt; i < VBN; i += TPC) {
+      const int v = i / 3, r = i - 3 * v;
+      const int g0 = ic[0] - 1 + v % kVB, g1 = ic[1] - 1 + (v / kVB) % kVB, g2 = ic[2] - 1 + v / (kVB * kVB);
+      const bool in = g0 >= 0 && g0 <= M.ncell[0] && g1 >= 0 && g1 <= M.ncell[1] && g2 >= 0 && g2 <= M.ncell[2];
+      VBs[slot][i] = in ? M.verts[3 * (size_t(g0) + size_t(M.ncell[0] + 1) * (g1 + size_t(M.ncell[1] + 1) * g2)) + r]
+                        : 0.0;
+    }
+  }
   __syncthreads();
 
   const double h[3] = {M.h[0][ic[0]], M.h[1][ic[1]], M.h[2][ic[2]]};
@@ -155,6 +255,30 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
   contract<N, false, 2, Q, Q, Q, N, TPC>(lt, B6, B2, sD);  // d^3 u
   __syncthreads();
   // ---------------- volume: pointwise flux (eq. (gauss_points)) ------------
+  if constexpr (GEO) {
+    const double *VB = VBs[slot];
+    for (int i = lt; i < QB; i += TPC) {
+      const int q1 = i % Q, q2 = (i / Q) % Q, q3 = i / QF;
+      double Xp[3], J[9], C[9];
+      tri_map(VB, 1, 1, 1, sxi[q1], sxi[q2], sxi[q3], Xp, J);
+      const double det = cof3(J, C), idet = 1.0 / det;
+      const double u = B0[i];
+      const double gr[3] = {B1[i], B5[i], B6[i]};  // reference gradient
+      double g[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) g[r] = (C[3 * r] * gr[0] + C[3 * r + 1] * gr[1] + C[3 * r + 2] * gr[2]) * idet;
+      const double kx = kap * geo_kp(M, Xp);
+      double F[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+        F[r] = kx * (M.K[3 * r] * g[0] + M.K[3 * r + 1] * g[1] + M.K[3 * r + 2] * g[2]) - geo_b(M, r, Xp) * u;
+      const double W = sw[q1] * sw[q2] * sw[q3];
+      B0[i] = W * det * M.c * u;
+      B1[i] = W * (C[0] * F[0] + C[3] * F[1] + C[6] * F[2]);
+      B5[i] = W * (C[1] * F[0] + C[4] * F[1] + C[7] * F[2]);
+      B6[i] = W * (C[2] * F[0] + C[5] * F[1] + C[8] * F[2]);
+    }
+  } else
   for (int i = lt; i < QB; i += TPC) {
     const int q1 = i % Q, q2 = (i / Q) % Q, q3 = i / QF;
     const double u = B0[i];
@@ -244,6 +368,84 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
     contract<N, false, 1, Q, Q, 6, N, TPC>(lt, gan, S1, sV);
     __syncthreads();
     // pointwise face terms of every face point (as in the per-face loop below)
+    if constexpr (GEO) {
+      const double *VB = VBs[slot];
+      for (int i = lt; i < 6 * QF; i += TPC) {
+        const int f = i / QF, ii = i - f * QF;
+        const int a = f >> 1, e = f & 1;
+        const int b = (a == 0) ? 1 : 0, c = (a == 2) ? 1 : 2;
+        const int qb = ii % Q, qc = ii / Q;
+        const FaceNb nb = face_nb(cell, sel3i(a, ic[0], ic[1], ic[2]), sel3i(a, M.ncell[0], M.ncell[1], M.ncell[2]),
+                                  sel3i(a, cstride[0], cstride[1], cstride[2]), 0, e);
+        const bool interior = nb.in;
+        // reference coordinates of the point on the own side (s_a = e) and
+        // on the neighbour's side (s_a = 1 - e)
+        const double tb = sxi[qb], tc = sxi[qc], ee = double(e);
+        const double s0 = a == 0 ? ee : tb, s1 = a == 1 ? ee : (a == 0 ? tb : tc), s2 = a == 2 ? ee : tc;
+        double Xp[3], J[9], Co[9];
+        tri_map(VB, 1, 1, 1, s0, s1, s2, Xp, J);
+        const double deto = cof3(J, Co);
+        const double sg = e ? 1.0 : -1.0;
+        // outer area-weighted normal: column a of cof(J), signed
+        const double nv0 = sg * sel3d(a, Co[0], Co[1], Co[2]);
+        const double nv1 = sg * sel3d(a, Co[3], Co[4], Co[5]);
+        const double nv2 = sg * sel3d(a, Co[6], Co[7], Co[8]);
+        const double nrm = sqrt(nv0 * nv0 + nv1 * nv1 + nv2 * nv2);
+        const double nu[3] = {nv0 / nrm, nv1 / nrm, nv2 / nrm};
+        double Kn[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) Kn[r] = M.K[3 * r] * nu[0] + M.K[3 * r + 1] * nu[1] + M.K[3 * r + 2] * nu[2];
+        const double nKn = nu[0] * Kn[0] + nu[1] * Kn[1] + nu[2] * Kn[2];
+        // physical gradients from the reference gradients (axis order)
+        const double gro[3] = {a == 0 ? gao[i] : gbo[i], a == 1 ? gao[i] : (a == 0 ? gbo[i] : gco[i]),
+                               a == 2 ? gao[i] : gco[i]};
+        double Kgo = 0.0;  // (K nu) . grad u_o
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+          Kgo += Kn[r] * (Co[3 * r] * gro[0] + Co[3 * r + 1] * gro[1] + Co[3 * r + 2] * gro[2]);
+        Kgo /= deto;
+        const double kpx = geo_kp(M, Xp);
+        const double kxo = kap * kpx;
+        double kxn = 0.0, Kgn = 0.0;
+        if (interior) {
+          const int o = e ? 2 : 0;
+          double Xn[3], Jn[9], Cn[9];
+          tri_map(VB, a == 0 ? o : 1, a == 1 ? o : 1, a == 2 ? o : 1, a == 0 ? 1.0 - ee : s0, a == 1 ? 1.0 - ee : s1,
+                  a == 2 ? 1.0 - ee : s2, Xn, Jn);
+          const double detn = cof3(Jn, Cn);
+          const double grn[3] = {a == 0 ? gan[i] : gbn[i], a == 1 ? gan[i] : (a == 0 ? gbn[i] : gcn[i]),
+                                 a == 2 ? gan[i] : gcn[i]};
+#pragma unroll
+          for (int r = 0; r < 3; ++r)
+            Kgn += Kn[r] * (Cn[3 * r] * grn[0] + Cn[3 * r + 1] * grn[1] + Cn[3 * r + 2] * grn[2]);
+          Kgn /= detn;
+          kxn = (M.kappa ? M.kappa[nb.cell] : 1.0) * kpx;
+        }
+        const double dT = kxo * nKn, dN = kxn * nKn;
+        const double wT = interior ? dN / (dT + dN) : 1.0;
+        const double wN = interior ? dT / (dT + dN) : 0.0;
+        const int ia = sel3i(a, ic[0], ic[1], ic[2]), ib = sel3i(b, ic[0], ic[1], ic[2]);
+        const int icc = sel3i(c, ic[0], ic[1], ic[2]);
+        const int na = sel3i(a, M.ncell[0], M.ncell[1], M.ncell[2]), nbb = sel3i(b, M.ncell[0], M.ncell[1], M.ncell[2]);
+        const double area = pickp<3>(M.farea, a)[(ia + e) + size_t(na + 1) * (ib + size_t(nbb) * icc)];
+        const double gamma = interior ? M.sigma * (2.0 * dT * dN / (dT + dN)) * area / fmin(M.cvol[cell], M.cvol[nb.cell])
+                                      : M.sigma * dT * area / M.cvol[cell];
+        const double avg = wT * kxo * Kgo + wN * kxn * Kgn;
+        const double Jmp = uo[i] - un[i];
+        const double bout = geo_b(M, 0, Xp) * nu[0] + geo_b(M, 1, Xp) * nu[1] + geo_b(M, 2, Xp) * nu[2];
+        const double Phi = bout >= 0.0 ? bout * uo[i] : bout * un[i];
+        const double W = sw[qb] * sw[qc] * nrm;
+        S0[i] = W * (Phi - avg + gamma * Jmp);
+        // symmetry term against the reference gradient: t C^T (K nu)
+        const double t = -W * wT * Jmp * kxo / deto;
+        const double Z0 = t * (Co[0] * Kn[0] + Co[3] * Kn[1] + Co[6] * Kn[2]);
+        const double Z1 = t * (Co[1] * Kn[0] + Co[4] * Kn[1] + Co[7] * Kn[2]);
+        const double Z2 = t * (Co[2] * Kn[0] + Co[5] * Kn[1] + Co[8] * Kn[2]);
+        S1[i] = sel3d(b, Z0, Z1, Z2);
+        S2[i] = sel3d(c, Z0, Z1, Z2);
+        S3[i] = sel3d(a, Z0, Z1, Z2);
+      }
+    } else
     for (int i = lt; i < 6 * QF; i += TPC) {
       const int f = i / QF, ii = i - f * QF;
       const int a = f >> 1, e = f & 1;
@@ -443,7 +645,7 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
   }
 }
 
-template <int N, int Q>
+template <int N, int Q, bool GEO = false>
 static hipError_t launch_ref_n(const dg_handle *h, const double *x, double *y, hipStream_t s) {
   if (h->tabq.m != Q) return hipErrorInvalidValue;
   RefTab<N, Q> T;
@@ -453,6 +655,7 @@ static hipError_t launch_ref_n(const dg_handle *h, const double *x, double *y, h
       T.D[q][j] = h->tabq.D[q][j];
     }
     T.w[q] = h->tabq.w[q];
+    T.xi[q] = h->tabq.xi[q];
   }
   for (int j = 0; j < N; ++j) {
     T.ev[0][j] = h->tabq.e0v[j];
@@ -484,14 +687,58 @@ static hipError_t launch_ref_n(const dg_handle *h, const double *x, double *y, h
   M.c = h->mesh.c;
   M.sigma = h->mesh.sigma;
   M.ncells = int(h->ncells);
-  // raised rule: as many cells per workgroup as keep its LDS near 80 KB
+  M.verts = h->mesh.verts;
+  M.cvol = h->mesh.cvol;
+  for (int a = 0; a < 3; ++a) M.farea[a] = h->mesh.farea[a];
+  for (int r = 0; r < 3; ++r) {
+    M.b_const[r] = h->prob.b_const[r];
+    M.b_sin[r] = h->prob.b_sin[r];
+    M.b_amp[r] = h->prob.b_amp[r];
+  }
+  for (int t = 0; t < 9; ++t) {
+    M.b_freq[t] = h->prob.b_freq[t];
+    M.b_phase[t] = h->prob.b_phase[t];
+    M.kpc[t] = h->prob.kappa_poly[t];
+  }
+  // the per-point path evaluates b from its formula: the problem's own form
+  // (the tables above come in product form whenever kp is present)
+  if (GEO) M.bprod = (h->prob.flags & DG_B_PRODUCT) ? 1 : 0;
+  // raised rule and multilinear cells: as many cells per workgroup as keep
+  // its LDS near 80 KB
+  constexpr bool BATCH = (Q != N) || GEO;
   constexpr int NF_ = N * N, QF_ = Q * Q, QB_ = Q * Q * Q;
-  constexpr int region = (Q != N && 24 * NF_ + 72 * QF_ > 7 * QB_) ? 24 * NF_ + 72 * QF_ : 7 * QB_;
-  constexpr int per_cell = 8 * (2 * N * N * N + region + (Q == N ? 16 * QF_ : 16));
-  constexpr int CPB = (Q == N) ? 1 : (8 * per_cell <= 81920 ? 8 : 4 * per_cell <= 81920 ? 4 : 2 * per_cell <= 81920 ? 2 : 1);
+  constexpr int region = (BATCH && 24 * NF_ + 72 * QF_ > 7 * QB_) ? 24 * NF_ + 72 * QF_ : 7 * QB_;
+  constexpr int per_cell = 8 * (2 * N * N * N + region + (BATCH ? 16 : 16 * QF_) + (GEO ? 3 * kVB * kVB * kVB : 1));
+  constexpr int CPB = !BATCH ? 1 : (8 * per_cell <= 81920 ? 8 : 4 * per_cell <= 81920 ? 4 : 2 * per_cell <= 81920 ? 2 : 1);
   const unsigned grid = unsigned((h->ncells + CPB - 1) / CPB);
-  hipLaunchKernelGGL((apply_ref_kernel<N, Q, CPB>), dim3(grid), dim3(kRefThreads), 0, s, x, y, M, T);
+  hipLaunchKernelGGL((apply_ref_kernel<N, Q, CPB, GEO>), dim3(grid), dim3(kRefThreads), 0, s, x, y, M, T);
   return hipGetLastError();
+}
+
+// Multilinear meshes: the (k+1)-point rule, the raised rule (k+3 points) or
+// the rule q = 3p + 4 of Problem C (ceil((3k+5)/2) points), k <= 7.
+template <int N>
+static hipError_t launch_geo_q(const dg_handle *h, const double *x, double *y, hipStream_t s) {
+  constexpr int QC = (3 * (N - 1) + 6) / 2;
+  if (h->tabq.m == N) return launch_ref_n<N, N, true>(h, x, y, s);
+  if (h->tabq.m == N + 2) return launch_ref_n<N, N + 2, true>(h, x, y, s);
+  if constexpr (QC != N + 2) {
+    if (h->tabq.m == QC) return launch_ref_n<N, QC, true>(h, x, y, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_apply_geo_f64(const dg_handle *h, const double *x, double *y, hipStream_t s) {
+  switch (h->k + 1) {
+    case 2: return launch_geo_q<2>(h, x, y, s);
+    case 3: return launch_geo_q<3>(h, x, y, s);
+    case 4: return launch_geo_q<4>(h, x, y, s);
+    case 5: return launch_geo_q<5>(h, x, y, s);
+    case 6: return launch_geo_q<6>(h, x, y, s);
+    case 7: return launch_geo_q<7>(h, x, y, s);
+    case 8: return launch_geo_q<8>(h, x, y, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 // Q = N: the (k+1)-point rule; Q = N + 2: the raised rule (k <= 8).

@@ -153,6 +153,7 @@ extern "C" void dg_destroy(dg_handle *h) {
   if (h->ts) (void)hipFree(h->ts);
   if (h->rq) (void)hipFree(h->rq);
   if (h->dev_block) (void)hipFree(h->dev_block);
+  if (h->geo_block) (void)hipFree(h->geo_block);
   if (cur != h->device) (void)hipSetDevice(cur);
   delete h;
 }
@@ -207,6 +208,128 @@ static dg_status fold_affine(dg_problem &p, double *vol_scale) {
   return DG_OK;
 }
 
+// ---- multilinear meshes (DG_MULTILINEAR) ------------------------------------
+
+// Trilinear map of cell (i0,i1,i2) through its eight vertices V at reference
+// point s: point X and Jacobian J[3r + t] = dX_r / ds_t.
+static void host_tri_map(const dg_problem &p, const int *ic, const double *s, double *X, double *J) {
+  const int64_t V0 = p.ncell[0] + 1, V1 = p.ncell[1] + 1;
+  for (int r = 0; r < 3; ++r) {
+    X[r] = 0.0;
+    for (int t = 0; t < 3; ++t) J[3 * r + t] = 0.0;
+  }
+  for (int c = 0; c < 8; ++c) {
+    const int cb[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
+    const double *v = p.vertices + 3 * ((ic[0] + cb[0]) + V0 * ((ic[1] + cb[1]) + V1 * int64_t(ic[2] + cb[2])));
+    const double l[3] = {cb[0] ? s[0] : 1.0 - s[0], cb[1] ? s[1] : 1.0 - s[1], cb[2] ? s[2] : 1.0 - s[2]};
+    const double dl[3] = {cb[0] ? 1.0 : -1.0, cb[1] ? 1.0 : -1.0, cb[2] ? 1.0 : -1.0};
+    const double wv = l[0] * l[1] * l[2];
+    const double wd[3] = {dl[0] * l[1] * l[2], l[0] * dl[1] * l[2], l[0] * l[1] * dl[2]};
+    for (int r = 0; r < 3; ++r) {
+      X[r] += wv * v[r];
+      for (int t = 0; t < 3; ++t) J[3 * r + t] += wd[t] * v[r];
+    }
+  }
+}
+
+static double host_det3(const double *J) {
+  return J[0] * (J[4] * J[8] - J[5] * J[7]) - J[1] * (J[3] * J[8] - J[5] * J[6]) + J[2] * (J[3] * J[7] - J[4] * J[6]);
+}
+
+// Validation of a vertex mesh: finite vertices, det J > 0 at the corners and
+// the centre of every cell, the polynomial diffusion factor positive on the
+// vertices' bounding box (every point of a trilinear cell is a convex
+// combination of its vertices).
+static dg_status check_vertex_mesh(const dg_problem &p) {
+  if (!p.vertices) return set_error(DG_EINVAL, "dg_setup: DG_MULTILINEAR needs vertices");
+  const int64_t nv = int64_t(p.ncell[0] + 1) * (p.ncell[1] + 1) * (p.ncell[2] + 1);
+  double lo[3] = {HUGE_VAL, HUGE_VAL, HUGE_VAL}, hi[3] = {-HUGE_VAL, -HUGE_VAL, -HUGE_VAL};
+  for (int64_t i = 0; i < 3 * nv; ++i) {
+    if (!std::isfinite(p.vertices[i])) return set_error(DG_EINVAL, "dg_setup: vertices must be finite");
+    lo[i % 3] = std::fmin(lo[i % 3], p.vertices[i]);
+    hi[i % 3] = std::fmax(hi[i % 3], p.vertices[i]);
+  }
+  for (int i2 = 0; i2 < p.ncell[2]; ++i2)
+    for (int i1 = 0; i1 < p.ncell[1]; ++i1)
+      for (int i0 = 0; i0 < p.ncell[0]; ++i0) {
+        const int ic[3] = {i0, i1, i2};
+        for (int c = 0; c < 9; ++c) {
+          const double s[3] = {c == 8 ? 0.5 : double(c & 1), c == 8 ? 0.5 : double((c >> 1) & 1),
+                               c == 8 ? 0.5 : double((c >> 2) & 1)};
+          double X[3], J[9];
+          host_tri_map(p, ic, s, X, J);
+          if (!(host_det3(J) > 0.0))
+            return set_error(DG_EINVAL, "dg_setup: every cell's Jacobian determinant must be positive");
+        }
+      }
+  if (p.flags & DG_KAPPA_POLY)
+    for (int j = 0; j < 3; ++j) {
+      const double *c = p.kappa_poly + 3 * j;
+      auto g = [&](double t) { return c[0] + c[1] * t + c[2] * t * t; };
+      bool ok = g(lo[j]) > 0.0 && g(hi[j]) > 0.0;
+      if (c[2] != 0.0) {
+        const double tv = -c[1] / (2.0 * c[2]);
+        if (tv > lo[j] && tv < hi[j]) ok = ok && g(tv) > 0.0;
+      }
+      if (!ok) return set_error(DG_EINVAL, "dg_setup: kappa_poly factors must be positive on the mesh");
+    }
+  return DG_OK;
+}
+
+// Cell volumes |T| (det J integrated with the 2-point Gauss rule, exact for
+// the trilinear map: det J has degree <= 2 per direction) and face areas |F|
+// (|cof(J) e_a| integrated with the operator's m-point rule over the face,
+// from its four vertices), staged for the device.
+static void vertex_mesh_tables(const dg_problem &p, const Tables &tq, std::vector<double> &cvol,
+                               std::vector<double> farea[3]) {
+  const int N[3] = {p.ncell[0], p.ncell[1], p.ncell[2]};
+  const double g2[2] = {0.5 - 0.5 / std::sqrt(3.0), 0.5 + 0.5 / std::sqrt(3.0)};
+  cvol.assign(size_t(N[0]) * N[1] * N[2], 0.0);
+  for (int i2 = 0; i2 < N[2]; ++i2)
+    for (int i1 = 0; i1 < N[1]; ++i1)
+      for (int i0 = 0; i0 < N[0]; ++i0) {
+        const int ic[3] = {i0, i1, i2};
+        double v = 0.0;
+        for (int q = 0; q < 8; ++q) {
+          const double s[3] = {g2[q & 1], g2[(q >> 1) & 1], g2[(q >> 2) & 1]};
+          double X[3], J[9];
+          host_tri_map(p, ic, s, X, J);
+          v += 0.125 * host_det3(J);
+        }
+        cvol[i0 + size_t(N[0]) * (i1 + size_t(N[1]) * i2)] = v;
+      }
+  for (int a = 0; a < 3; ++a) {
+    const int b = (a == 0) ? 1 : 0, c = (a == 2) ? 1 : 2;
+    farea[a].assign(size_t(N[a] + 1) * N[b] * N[c], 0.0);
+    for (int icc = 0; icc < N[c]; ++icc)
+      for (int ib = 0; ib < N[b]; ++ib)
+        for (int pa = 0; pa <= N[a]; ++pa) {
+          // the face as side e of the cell below it (e = 1), or above it on plane 0
+          int ic[3];
+          ic[a] = pa < N[a] ? pa : pa - 1;
+          ic[b] = ib;
+          ic[c] = icc;
+          const double e = pa < N[a] ? 0.0 : 1.0;
+          double A = 0.0;
+          for (int qc = 0; qc < tq.m; ++qc)
+            for (int qb = 0; qb < tq.m; ++qb) {
+              double s[3], X[3], J[9];
+              s[a] = e;
+              s[b] = tq.xi[qb];
+              s[c] = tq.xi[qc];
+              host_tri_map(p, ic, s, X, J);
+              // column a of cof(J): cross product of the tangent columns b, c
+              const int t1 = (a + 1) % 3, t2 = (a + 2) % 3;
+              const double n0 = J[3 + t1] * J[6 + t2] - J[6 + t1] * J[3 + t2];
+              const double n1 = J[6 + t1] * J[t2] - J[t1] * J[6 + t2];
+              const double n2 = J[t1] * J[3 + t2] - J[3 + t1] * J[t2];
+              A += tq.w[qb] * tq.w[qc] * std::sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+            }
+          farea[a][pa + size_t(N[a] + 1) * (ib + size_t(N[b]) * icc)] = A;
+        }
+  }
+}
+
 extern "C" dg_status dg_setup(const dg_problem *p_in, dg_handle **out) {
   if (!out) return set_error(DG_EINVAL, "dg_setup: out is NULL");
   *out = nullptr;
@@ -214,15 +337,36 @@ extern "C" dg_status dg_setup(const dg_problem *p_in, dg_handle **out) {
   // the problem the kernels see: an affine map folds into the coefficients
   dg_problem pt = *p_in;
   double vol_scale = 1.0;
+  if ((pt.flags & DG_MULTILINEAR) && (pt.flags & DG_AFFINE))
+    return set_error(DG_EINVAL, "dg_setup: DG_MULTILINEAR excludes DG_AFFINE, periodic axes and block Jacobi");
   if (pt.flags & DG_AFFINE) {
     const dg_status st = fold_affine(pt, &vol_scale);
     if (st != DG_OK) return st;
   }
+  // multilinear meshes: the tensor tables below are built on unit nodes
+  // (the kernels take the geometry from the vertices)
+  const bool multilinear = (pt.flags & DG_MULTILINEAR) != 0;
+  std::vector<double> unit_nodes[3];
+  if (multilinear) {
+    if (pt.flags & (DG_AFFINE | DG_WITH_BLOCK_JACOBI | DG_PERIODIC_X | DG_PERIODIC_Y | DG_PERIODIC_Z))
+      return set_error(DG_EINVAL, "dg_setup: DG_MULTILINEAR excludes DG_AFFINE, periodic axes and block Jacobi");
+    if (pt.k < 1 || pt.k > 7) return set_error(DG_EINVAL, "dg_setup: multilinear meshes support k <= 7");
+    if (pt.quad_extra != 0 && pt.quad_extra != 2 && pt.quad_extra != (pt.k + 4) / 2)
+      return set_error(DG_EINVAL, "dg_setup: on multilinear meshes quad_extra must be 0, 2 or ceil((k+3)/2)");
+    for (int a = 0; a < 3; ++a) {
+      if (pt.ncell[a] < 1) return set_error(DG_EINVAL, "dg_setup: ncell must be >= 1");
+      unit_nodes[a].resize(pt.ncell[a] + 1);
+      for (int i = 0; i <= pt.ncell[a]; ++i) unit_nodes[a][i] = double(i) / pt.ncell[a];
+      pt.nodes[a] = unit_nodes[a].data();
+    }
+    const dg_status st = check_vertex_mesh(pt);
+    if (st != DG_OK) return st;
+  }
   const dg_problem *p = &pt;
   if (p->k < 1 || p->k > 10) return set_error(DG_EINVAL, "dg_setup: k must be in 1..10");
-  if (p->quad_extra != 0 && p->quad_extra != 2)
+  if (!multilinear && p->quad_extra != 0 && p->quad_extra != 2)
     return set_error(DG_EINVAL, "dg_setup: quad_extra must be 0 or 2");
-  if (p->k + 1 + p->quad_extra > kMaxN)
+  if (!multilinear && p->k + 1 + p->quad_extra > kMaxN)
     return set_error(DG_EINVAL, "dg_setup: raised quadrature supports k <= 8");
   int64_t ncells = 1;
   for (int a = 0; a < 3; ++a) {
@@ -250,14 +394,16 @@ extern "C" dg_status dg_setup(const dg_problem *p_in, dg_handle **out) {
         return set_error(DG_EINVAL, "dg_setup: kappa must be positive and finite");
   const int n = p->k + 1;
   if (ncells > (int64_t(1) << 31) / 2) return set_error(DG_EINVAL, "dg_setup: too many cells");
-  if (p->flags &
-      ~(DG_WITH_BLOCK_JACOBI | DG_PERIODIC_X | DG_PERIODIC_Y | DG_PERIODIC_Z | DG_B_PRODUCT | DG_KAPPA_POLY))
+  if (p->flags & ~(DG_WITH_BLOCK_JACOBI | DG_PERIODIC_X | DG_PERIODIC_Y | DG_PERIODIC_Z | DG_B_PRODUCT |
+                   DG_KAPPA_POLY | DG_MULTILINEAR))
     return set_error(DG_EINVAL, "dg_setup: unknown flag bits");
   const bool bprod = (p->flags & DG_B_PRODUCT) != 0;
   const bool kpoly = (p->flags & DG_KAPPA_POLY) != 0;
   if (kpoly) {
     for (int t = 0; t < 9; ++t)
       if (!std::isfinite(p->kappa_poly[t])) return set_error(DG_EINVAL, "dg_setup: kappa_poly must be finite");
+  }
+  if (kpoly && !multilinear) {
     // every factor positive at the Gauss coordinates and nodes it is used at
     Tables tq;
     build_tables(p->k, tq, p->k + 1 + p->quad_extra);
@@ -288,10 +434,12 @@ extern "C" dg_status dg_setup(const dg_problem *p_in, dg_handle **out) {
   h->prob = *p;
   for (int a = 0; a < 3; ++a) h->prob.nodes[a] = nullptr;
   h->prob.kappa = nullptr;
+  h->prob.vertices = nullptr;
   h->k = p->k;
   h->ncells = ncells;
   h->ndof = ncells * n * n * n;
   h->dev_block = nullptr;
+  h->geo_block = nullptr;
   h->variant = DG_KERNEL_AUTO;
   h->ws = nullptr;
   h->ts = nullptr;
@@ -423,7 +571,39 @@ extern "C" dg_status dg_setup(const dg_problem *p_in, dg_handle **out) {
   std::memcpy(M.K, p->K, sizeof(M.K));
   M.c = p->c;
   M.sigma = p->sigma;
-  if (h->quad_extra) {
+  M.verts = nullptr;
+  M.cvol = nullptr;
+  for (int a = 0; a < 3; ++a) M.farea[a] = nullptr;
+  M.multilinear = multilinear ? 1 : 0;
+  if (multilinear) {
+    std::vector<double> cvol, farea[3];
+    vertex_mesh_tables(*p, h->tabq, cvol, farea);
+    const size_t nv3 = 3 * size_t(p->ncell[0] + 1) * (p->ncell[1] + 1) * (p->ncell[2] + 1);
+    std::vector<double> g(p->vertices, p->vertices + nv3);
+    const size_t off_cv = g.size();
+    g.insert(g.end(), cvol.begin(), cvol.end());
+    size_t off_fa[3];
+    for (int a = 0; a < 3; ++a) {
+      off_fa[a] = g.size();
+      g.insert(g.end(), farea[a].begin(), farea[a].end());
+    }
+    e = hipMalloc(&h->geo_block, g.size() * sizeof(double));
+    if (e != hipSuccess) {
+      h->geo_block = nullptr;
+      dg_destroy(h);
+      return hip_error(e, "dg_setup: geometry tables");
+    }
+    e = hipMemcpy(h->geo_block, g.data(), g.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      dg_destroy(h);
+      return hip_error(e, "dg_setup: hipMemcpy");
+    }
+    double *gb = static_cast<double *>(h->geo_block);
+    M.verts = gb;
+    M.cvol = gb + off_cv;
+    for (int a = 0; a < 3; ++a) M.farea[a] = gb + off_fa[a];
+  }
+  if (h->quad_extra && !multilinear) {
     // raised rule: padded input and output of the degree-(k+2) kernel
     const int mq = n + h->quad_extra;
     const size_t bytes = 2 * size_t(h->ncells) * size_t(mq * mq * mq) * sizeof(double);
@@ -449,6 +629,7 @@ extern "C" dg_status dg_setup(const dg_problem *p_in, dg_handle **out) {
 
 namespace dgmf {
 hipError_t apply_f64(const dg_handle *h, const double *x, double *y, hipStream_t s) {
+  if (h->mesh.multilinear) return launch_apply_geo_f64(h, x, y, s);
   if (h->variant == DG_KERNEL_REFERENCE) return launch_apply_ref_f64(h, x, y, s);
   return h->quad_extra ? apply_raised_f64(h, x, y, s) : launch_apply_fused_f64(h, x, y, s);
 }
@@ -508,6 +689,7 @@ extern "C" dg_status dg_apply_f32(dg_handle *h, const float *x, float *y, void *
   if (!x || !y) return set_error(DG_EINVAL, "dg_apply_f32: x or y is NULL");
   if (overlaps(x, y, size_t(h->ndof) * sizeof(float)))
     return set_error(DG_EINVAL, "dg_apply_f32: x and y overlap");
+  if (h->mesh.multilinear) return set_error(DG_EINVAL, "dg_apply_f32: not available on multilinear meshes");
   int cur = -1;
   if (hipGetDevice(&cur) != hipSuccess || cur != h->device) {
     hipError_t e = hipSetDevice(h->device);

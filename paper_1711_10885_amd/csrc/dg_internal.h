@@ -12,6 +12,7 @@
 namespace dgmf {
 
 constexpr int kMaxN = 11;         // k <= 10
+constexpr int kMaxQ = 13;         // Gauss points per direction (q = 3p + 4 at k = 7)
 constexpr int kBjGroup = 8;  // cells per group of the shared-block apply
 constexpr int kMaxBjBlock = 512;  // block Jacobi for (k+1)^3 <= 512
 constexpr int kMlpHidden = 256;   // hidden width of the cell-patch network
@@ -25,8 +26,8 @@ struct Mlp;
 struct Tables {
   int n;
   int m;  // quadrature points (rows of V, D; entries of xi, w)
-  double xi[kMaxN], w[kMaxN];
-  double V[kMaxN][kMaxN], D[kMaxN][kMaxN];
+  double xi[kMaxQ], w[kMaxQ];
+  double V[kMaxQ][kMaxN], D[kMaxQ][kMaxN];
   double e0v[kMaxN], e1v[kMaxN], e0d[kMaxN], e1d[kMaxN];
 };
 
@@ -55,6 +56,13 @@ struct DevMesh {
   double K[9];
   double c, sigma;
   int b_axis[3];
+  // multilinear meshes (DG_MULTILINEAR; else null): vertex coordinates
+  // (N1+1)(N2+1)(N3+1) x 3, |T| per cell, |F| per face normal to axis a
+  // indexed (i_a + e) + (N_a + 1) (i_b + N_b i_c), b < c the tangential axes
+  double *verts;
+  double *cvol;
+  double *farea[3];
+  int multilinear;
 };
 
 }  // namespace dgmf
@@ -73,6 +81,7 @@ struct dg_handle {
   size_t rq_bytes;
   dgmf::DevMesh mesh;
   void *dev_block;  // single allocation backing the DevMesh arrays
+  void *geo_block;  // multilinear meshes: vertices, cell volumes, face areas (or null)
   int variant;      // DG_KERNEL_*
   // solver workspace: grown on demand, freed by dg_destroy
   void *ws;
@@ -101,6 +110,8 @@ dg_status hip_error(hipError_t e, const char *what);
 
 // Kernel launchers, dispatching on k.
 hipError_t launch_apply_ref_f64(const dg_handle *h, const double *x, double *y, hipStream_t s);
+// multilinear meshes: the reference-layout kernel with per-point geometry
+hipError_t launch_apply_geo_f64(const dg_handle *h, const double *x, double *y, hipStream_t s);
 hipError_t launch_apply_fused_f64(const dg_handle *h, const double *x, double *y, hipStream_t s);
 hipError_t launch_apply_fused_f32(const dg_handle *h, const float *x, float *y, hipStream_t s);
 // One Heun stage fused into the apply's store: stage 0 y = x + dt/|T| (f - A x),

@@ -67,6 +67,8 @@ extern "C" dg_status dg_load_vector(dg_handle *h, int32_t nterms, const double *
   if (nterms < 1 || nterms > kMaxTerms) return set_error(DG_EINVAL, "dg_load_vector: nterms must be in 1..16");
   if (!alpha || !kinds || !f) return set_error(DG_EINVAL, "dg_load_vector: NULL argument");
   if (h->affine) return set_error(DG_EINVAL, "dg_load_vector: separable sources are tensor-grid only, not affine meshes");
+  if (h->mesh.multilinear)
+    return set_error(DG_EINVAL, "dg_load_vector: separable sources are tensor-grid only, not multilinear meshes");
   LvArgs L;
   L.n = h->tabq.n;
   L.m = h->tabq.m;

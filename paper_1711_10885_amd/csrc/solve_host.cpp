@@ -88,6 +88,8 @@ extern "C" dg_status dg_solve(dg_handle *h, const double *f, double *u, double t
     return set_error(DG_EINVAL, "dg_solve: orth must be DG_ORTH_CGS1 or DG_ORTH_CGS2");
   if (opt.method != DG_GMRES64 && opt.method != DG_GMRES_IR && opt.method != DG_FGMRES)
     return set_error(DG_EINVAL, "dg_solve: unknown method");
+  if (opt.method == DG_GMRES_IR && h->mesh.multilinear)
+    return set_error(DG_EINVAL, "dg_solve: the FP32 tier is not available on multilinear meshes");
   if (opt.method == DG_GMRES_IR && !(opt.inner_tol > 0.0 && opt.inner_tol < 1.0))
     return set_error(DG_EINVAL, "dg_solve: inner_tol must be in (0, 1)");
   if (opt.precond != DG_PREC_NONE && opt.precond != DG_PREC_BLOCK_JACOBI && opt.precond != DG_PREC_LEARNED)

@@ -119,6 +119,8 @@ static dg_status heun_check(dg_handle *h, double *u, const double *f, double dt,
   if (!(dt > 0.0) || !std::isfinite(dt))
     return set_error(DG_EINVAL, std::string(who) + ": dt must be positive and finite");
   if (nsteps < 0) return set_error(DG_EINVAL, std::string(who) + ": nsteps must be >= 0");
+  if (h->mesh.multilinear)
+    return set_error(DG_EINVAL, std::string(who) + ": the mass matrix of multilinear cells is not diagonal");
   const size_t n = size_t(h->ndof);
   if (f && ((f < u + n && u < f + n))) return set_error(DG_EINVAL, std::string(who) + ": u and f overlap");
   int cur = -1;

@@ -66,7 +66,7 @@ def _struct(prob, **over):
     (dict(K=np.array([[1, 0.5, 0], [0, 1, 0], [0, 0, 1.0]])), "symmetric"),
     (dict(b_axis0=3), "b_axis"),
     (dict(c=float("nan")), "c must be finite"),
-    (dict(flags=256), "unknown flag"),
+    (dict(flags=512), "unknown flag"),
     (dict(quad_extra=1), "quad_extra"),
     (dict(k=9, quad_extra=2), "raised quadrature supports"),
     (dict(k=8, flags=2), "block Jacobi supports"),
@@ -226,3 +226,37 @@ def test_network_rows_are_validated_before_the_library(method, case, exc):
             dg.mlp_grad(X, T)
         else:
             dg.mlp_step(X, T)
+
+
+@pytest.mark.parametrize("case,msg", [
+    ("periodic", "excludes"), ("block_jacobi", "excludes"), ("affine", "excludes"), ("k8", "k <= 7"),
+    ("quad_extra", "quad_extra must be 0, 2"), ("inverted", "determinant must be positive"),
+    ("no_vertices", "needs vertices"), ("nan", "vertices must be finite"), ("kpoly", "positive on the mesh"),
+])
+def test_setup_rejects_invalid_multilinear_problems(case, msg):
+    """Vertex meshes are validated before any device work: exclusive flags,
+    degree and rule, cell orientation (det J > 0 at the corners and centre),
+    finite vertices, the diffusion factor on the vertices' bounding box."""
+    lib = _lib()
+    k = 8 if case == "k8" else 2
+    p = workloads.random_problem(80, ncell=(2, 2, 2), k=k, b="const")
+    V = workloads.curved_vertices((2, 2, 2), eps=0.03)
+    if case == "inverted":
+        V = V.copy()
+        V[1, 1, 1] = V[2, 2, 2] + 0.3  # interior vertex pushed past the far corner
+    if case == "nan":
+        V = V.copy()
+        V[0, 0, 1, 2] = float("nan")
+    flags = binding.DG_MULTILINEAR | {"periodic": binding.DG_PERIODIC_Y, "block_jacobi": binding.DG_WITH_BLOCK_JACOBI,
+                                      "affine": binding.DG_AFFINE, "kpoly": binding.DG_KAPPA_POLY}.get(case, 0)
+    s, keep = _struct(p, flags=flags, quad_extra=1 if case == "quad_extra" else 0)
+    Vf = np.ascontiguousarray(V, dtype=np.float64).ravel()
+    if case != "no_vertices":
+        s.vertices = Vf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    if case == "kpoly":  # kp_0(s) = 0.25 - s^2 vanishes inside [0, 1]
+        for t, v in enumerate((0.25, 0.0, -1.0, 1.0, 0.0, 0.0, 1.0, 0.0, 0.0)):
+            s.kappa_poly[t] = v
+    h = ctypes.c_void_p()
+    assert lib.dg_setup(ctypes.byref(s), ctypes.byref(h)) == binding.DG_EINVAL
+    assert msg in lib.dg_last_error().decode(), lib.dg_last_error().decode()
+    assert not h.value
