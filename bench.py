@@ -25,7 +25,9 @@ Other workloads (--workload): the degree sweep `sweep_kK` (k = 1..10, about 20M 
 mesh with the diffusion factor polynomial in the coordinates (`kpoly_sweep_kK`) and with the raised
 rule q = 2p + 4 (`raised_sweep_kK`), Problem B's three features together (`problem_b_kK`), the k = 7
 mesh as an affine image of the grid and the grid itself (`affine_k7_32`, `tensor_k7_32`), and the
-Taylor-Green operator (`transport_k5_64`); solves and time stepping run only with the default.
+Taylor-Green operator (`transport_k5_64`), and on multilinear (trilinear) cells Problem C with the
+rule q = 3p + 4 (`problem_c_kK`) and Problem B with parallelepiped cells whose Jacobians differ
+(`problem_b_cells_kK`), about 4M DOF each; solves and time stepping run only with the default.
 
 Prints ONE JSON line.  Algorithmic FLOPs use the per-DOF lower bound of
 Sec. 3.6 (FLOPDOF_vol + FLOPDOF_face for d = 3); peak is the MI355X FP64
@@ -53,8 +55,38 @@ def flop_per_dof(k: int, d: int = 3) -> float:
     return vol + face
 
 
+def flop_per_dof_multilinear(k: int, m: int) -> float:
+    """Algorithmic FP64 work per DOF of the multilinear-geometry operator with
+    n = k+1 modes and m Gauss points per direction, as the method evaluates it
+    (sum factorization with rectangular m x n factors, Sec. 3.2/3.5; the
+    geometry at every point, Sec. 4; owner computes, so interior faces count
+    on both sides), 2 FLOP per multiply-add:
+      volume contractions, forward and transposed: 2 (4 m n^3 + 6 m^2 n^2 + 8 m^3 n);
+      volume point: 220 (trilinear map and Jacobian by linear contractions 99,
+        cofactors and det 32, gradient 19, polynomial factor 14, flux 33,
+        C^T times the flux and weights 23; the sine of b not counted);
+      per face: normal traces of both sides 8 n^3, tangential evaluation
+        12 m n^2 + 16 m^2 n, face point 400 (both sides' maps and cofactors
+        262, normal, d, weights, penalty, averages, upwind, symmetry vector),
+        transposed tangential 6 m n^2 + 8 m^2 n, normal direction last 4 n^3."""
+    n = k + 1
+    vol = 2 * (4 * m * n ** 3 + 6 * m * m * n * n + 8 * m ** 3 * n) + 220 * m ** 3
+    face = 12 * n ** 3 + 18 * m * n * n + 24 * m * m * n + 400 * m * m
+    return (vol + 6 * face) / n ** 3
+
+
+def workload_flop_per_dof(prob) -> float:
+    if prob.vertices is not None:
+        return flop_per_dof_multilinear(prob.k, prob.k + 1 + prob.quad_extra)
+    return flop_per_dof(prob.k)
+
+
 def make_workload(name: str):
     from paper_1711_10885_amd import workloads as W
+    if name.startswith("problem_c_k"):
+        return W.problem_c(int(name[len("problem_c_k"):]))
+    if name.startswith("problem_b_cells_k"):
+        return W.problem_b_cells(int(name[len("problem_b_cells_k"):]))
     if name == "cdr_k7_32":
         return W.cdr_k7_32()
     if name == "poisson_k2_8":
@@ -96,7 +128,10 @@ def make_workload(name: str):
 
 def describe(prob) -> str:
     N = prob.ncell
-    return (f"{prob.name}: WSIPG CDR apply, k={prob.k}, {N[0]}x{N[1]}x{N[2]} cells, "
+    geo = ""
+    if prob.vertices is not None:
+        geo = f" multilinear cells, {prob.k + 1 + prob.quad_extra}-point Gauss rule,"
+    return (f"{prob.name}: WSIPG CDR apply,{geo} k={prob.k}, {N[0]}x{N[1]}x{N[2]} cells, "
             f"{prob.ndof} DOF, FP64")
 
 
@@ -364,7 +399,7 @@ def main():
     kern_ms = [s.elapsed_time(e) for s, e in ev]
     ms_step = wall * 1e3 / args.steps
     avg_kernel_ms = float(np.mean(kern_ms))
-    fpd = flop_per_dof(prob.k)
+    fpd = workload_flop_per_dof(prob)
     achieved = fpd * prob.ndof / (avg_kernel_ms * 1e-3) / 1e12
 
     if args.copy_probe_mib:
@@ -409,7 +444,9 @@ def main():
                    "flop_per_dof_formula": fpd},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                     "achieved_basis": "the paper's per-DOF FLOP count (Sec. 3.6) over the HIP-event kernel time",
+                     "achieved_basis": ("the per-DOF FLOP count of the multilinear path (flop_per_dof_multilinear) "
+                                        "over the HIP-event kernel time" if prob.vertices is not None else
+                                        "the paper's per-DOF FLOP count (Sec. 3.6) over the HIP-event kernel time"),
                      "frac_by_wall_clock": fpd * prob.ndof / (ms_step * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
                      "executed_tflops": (counters["fp64_flop_per_launch"] / (avg_kernel_ms * 1e-3) / 1e12
                                          if "fp64_flop_per_launch" in counters else None),

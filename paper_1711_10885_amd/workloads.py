@@ -382,3 +382,35 @@ def problem_c_quad_extra(k: int) -> int:
     """Extra Gauss points of the rule q = 3p + 4 (Problem C, Sec. 5.1): the
     Gauss rule exact to degree 3k + 4 has ceil((3k + 5) / 2) points."""
     return (3 * k + 5 + 1) // 2 - (k + 1)
+
+
+def geometry_N(k: int, target_dof: float = 4e6) -> int:
+    """Cells per axis of the multilinear-geometry workloads: about 4M DOF."""
+    return max(2, int(round(target_dof ** (1.0 / 3.0) / (k + 1))))
+
+
+def problem_c(k: int, N: int | None = None) -> Problem:
+    """Problem C of Sec. 5.1 at one GPU's size: multilinear cells (the uniform
+    N^3 vertex grid of the unit cube moved by the smooth field of
+    ``curved_vertices``, eps = 0.04), the rotated K of the k = 7 workload
+    times a diffusion factor polynomial in the coordinates (seed 7),
+    b = (sin pi y, sin pi z, sin pi x), c = 1, sigma = 2k(k+2), the rule
+    q = 3p + 4; x ~ U[-1, 1] seed 500+k."""
+    N = N or geometry_N(k)
+    V = curved_vertices((N, N, N), eps=0.04)
+    p = vertex_problem(V, k, quad_extra=problem_c_quad_extra(k), K=anisotropic_K(), b="sine", c=1.0,
+                       kappa_poly=random_kappa_poly(np.random.default_rng(7)), name=f"problem_c_k{k}_{N}")
+    p.meta["x_seed"] = 500 + k
+    return p
+
+
+def problem_b_cells(k: int, N: int | None = None) -> Problem:
+    """Problem B of Sec. 5.1 with affine cells whose Jacobians differ: the
+    uniform N^3 grid sheared layer by layer (``sheared_vertices``, seed 8),
+    coefficients as ``problem_c``, the rule q = 2p + 4; x seed 600+k."""
+    N = N or geometry_N(k)
+    V = sheared_vertices((uniform_nodes(N),) * 3, seed=8)
+    p = vertex_problem(V, k, quad_extra=2, K=anisotropic_K(), b="sine", c=1.0,
+                       kappa_poly=random_kappa_poly(np.random.default_rng(7)), name=f"problem_b_cells_k{k}_{N}")
+    p.meta["x_seed"] = 600 + k
+    return p
