@@ -54,7 +54,8 @@ typedef enum {
   DG_ENOMEM = -2,    /* device allocation failed                           */
   DG_EHIP = -3,      /* HIP runtime error (message has hipGetErrorString)  */
   DG_ENOTCONV = -4,  /* solver hit maxit; u holds the best iterate          */
-  DG_ENAN = -5       /* non-finite residual or input detected               */
+  DG_ENAN = -5,      /* non-finite residual or input detected               */
+  DG_EIO = -6        /* a file could not be opened, read, written or verified */
 } dg_status;
 
 /* Problem description (all host memory, copied by dg_setup).
@@ -224,6 +225,19 @@ dg_status dg_apply(dg_handle *h, const double *x, double *y, void *hip_stream);
 dg_status dg_load_vector(dg_handle *h, int32_t nterms, const double *alpha, const int32_t *kinds, double *f,
                          void *hip_stream);
 
+/* L2 projection onto the DG space of the Gaussian
+ *   g(x) = amp exp(-width |x - center|^2)
+ * (the initial concentration of the transport example, Sec. 5.4):
+ * u = M^{-1} l with l_{T,j} = (g, phi_j)_T by the operator's Gauss rule (k+1
+ * points per direction, k+3 with quad_extra = 2) and M = |T| I the mass
+ * matrix of the orthonormal basis, so u_{T,j} = l_{T,j} / |T|.  No periodic
+ * images are added on periodic axes.  center: host, 3 values; u: device, ndof
+ * doubles.  Tensor-grid handles only (DG_EINVAL with DG_AFFINE or
+ * DG_MULTILINEAR); DG_EINVAL for a non-finite amp or center or width <= 0.
+ * Asynchronous on hip_stream. */
+dg_status dg_project_gaussian(dg_handle *h, double amp, double width, const double *center, double *u,
+                              void *hip_stream);
+
 /* y := A x with FP32 vectors (the operator of the mixed-precision tier): the
  * 1D contractions, the LDS exchanges and the volume pointwise flux run in
  * FP32; the face constants (weights, penalty gamma_F) and the pointwise face
@@ -380,6 +394,22 @@ int64_t dg_learned_nparams(const dg_handle *h);
  * Synchronous.  DG_EINVAL on a wrong n. */
 dg_status dg_learned_set_params(dg_handle *h, const float *params, int64_t n);
 dg_status dg_learned_get_params(dg_handle *h, float *params, int64_t n);
+
+/* Checkpoint of the network and its optimiser state (an extension beyond the
+ * paper), so that training can stop and resume.  path: host string, a file
+ * name.  dg_learned_save writes a 64-byte header (magic "DGMFNET1", format
+ * version 1, k, input, hidden and output widths, the parameter count n of the
+ * public layout, the Adam step count, an FNV-1a 64-bit checksum of the body),
+ * then the parameters and the Adam first and second moments, n FP32 values
+ * each in the public layout, in native byte order; it needs a trained or
+ * loaded network (DG_EINVAL otherwise).  dg_learned_load reads such a file
+ * into a handle of the same degree: parameters, moments and step count are
+ * restored (the next dg_mlp_step continues the saved run exactly) and the
+ * network is marked ready.  Synchronous.  DG_EINVAL (NULL arguments, a file
+ * of another degree or format), DG_EIO (open, read or write failure,
+ * truncated file, checksum mismatch), DG_EHIP. */
+dg_status dg_learned_save(dg_handle *h, const char *path);
+dg_status dg_learned_load(dg_handle *h, const char *path);
 
 /* The network on caller rows (for checks and inference outside the solver).
  * X: device, B x in floats (rounded to BF16 on entry); T: device, B x out

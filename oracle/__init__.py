@@ -13,6 +13,8 @@ Contents
   quadrature definition (C, ``dg_oracle.c``), Algorithm 1 of Sec. 3.6 order.
 * ``rhs`` / ``l2err`` -- load vector (f, phi_j) of the right-hand-side
   functional (Sec. 2.2, g = 0) and the L2 error of a coefficient vector.
+* ``project_gaussian`` -- L2 projection of a Gaussian (the initial
+  concentration of the transport example, Sec. 5.4).
 * ``gauss`` / ``basis`` -- the 1D Gauss rule and orthonormal Legendre basis
   (Sec. 3.1; the L2-orthogonal Legendre basis of Sec. 2.2, normalised).
 * ``assemble`` -- the sparse matrix of the operator by probing ``apply`` with
@@ -100,6 +102,7 @@ def _load():
                                           dp, ctypes.c_int, ctypes.c_int]
         lib.oracle_rhs.argtypes = [P, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_int32), dp,
                                    ctypes.c_int]
+        lib.oracle_project_gaussian.argtypes = [P, ctypes.c_double, ctypes.c_double, dp, dp, ctypes.c_int]
         lib.oracle_l2err2.argtypes = [P, dp, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_int32)]
         lib.oracle_l2err2.restype = ctypes.c_double
         lib.oracle_gauss.argtypes = [ctypes.c_int, dp, dp]
@@ -230,6 +233,20 @@ def rhs(prob, source_terms, nthreads: int | None = None) -> np.ndarray:
     if rc != 0:
         raise ValueError("oracle_rhs rejected the problem")
     return f
+
+
+def project_gaussian(prob, amp: float, width: float, center, nthreads: int | None = None) -> np.ndarray:
+    """L2 projection of amp exp(-width |x - center|^2) onto the DG space
+    (coefficients (g, phi_j)_T / |T| by the operator's Gauss rule)."""
+    lib = _load()
+    m = _Marshalled(prob)
+    c = np.ascontiguousarray(center, dtype=np.float64).reshape(3)
+    u = np.empty(ndof(prob), dtype=np.float64)
+    rc = lib.oracle_project_gaussian(ctypes.byref(m.struct), float(amp), float(width), _dptr(c), _dptr(u),
+                                     int(nthreads or default_threads()))
+    if rc != 0:
+        raise ValueError("oracle_project_gaussian rejected the problem")
+    return u
 
 
 def l2err(prob, x: np.ndarray, exact_terms) -> float:

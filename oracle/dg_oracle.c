@@ -990,6 +990,47 @@ int oracle_rhs(const or_problem *p, int nterms, const double *alpha, const int32
   return 0;
 }
 
+/* L2 projection of the Gaussian g(x) = amp exp(-width |x - center|^2) onto
+ * the DG space (the initial concentration of the transport example,
+ * Sec. 5.4): u_{T,j} = (g, phi_j)_T / |T| (the mass matrix of the
+ * orthonormal basis is |T| I), the inner product by the operator's tensor
+ * Gauss rule; tensor-grid meshes (no affine or multilinear map); no
+ * periodic images. */
+int oracle_project_gaussian(const or_problem *p, double amp, double width, const double *center, double *u,
+                            int nthreads) {
+  if (check_problem(p) || p->affine_on || p->multilinear_on) return -1;
+  or_tables t;
+  make_tables(p->k, p->quad_extra, &t);
+  const int n = t.n, m = t.m;
+  const int64_t nb = (int64_t)n * n * n;
+  const int N1 = p->ncell[0], N2 = p->ncell[1], N3 = p->ncell[2];
+  const int64_t ncells = (int64_t)N1 * N2 * N3;
+  if (nthreads <= 0) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads)
+  for (int64_t c = 0; c < ncells; ++c) {
+    const int ic[3] = {(int)(c % N1), (int)((c / N1) % N2), (int)(c / ((int64_t)N1 * N2))};
+    double o[3], h[3];
+    cell_geom(p, ic, o, h);
+    double *uT = u + c * nb;
+    memset(uT, 0, sizeof(double) * nb);
+    for (int q3 = 0; q3 < m; ++q3)
+      for (int q2 = 0; q2 < m; ++q2)
+        for (int q1 = 0; q1 < m; ++q1) {
+          const double X[3] = {o[0] + h[0] * t.xi[q1], o[1] + h[1] * t.xi[q2], o[2] + h[2] * t.xi[q3]};
+          double r2 = 0.0;
+          for (int a = 0; a < 3; ++a) r2 += (X[a] - center[a]) * (X[a] - center[a]);
+          /* weight of the point with |T| divided out */
+          const double gw = t.w[q1] * t.w[q2] * t.w[q3] * amp * exp(-width * r2);
+          for (int j3 = 0; j3 < n; ++j3)
+            for (int j2 = 0; j2 < n; ++j2)
+              for (int j1 = 0; j1 < n; ++j1)
+                uT[j1 + n * (j2 + n * j3)] += gw * t.V[q1][j1] * t.V[q2][j2] * t.V[q3][j3];
+        }
+  }
+  (void)N3;
+  return 0;
+}
+
 /* Squared L2 error ||u_h - u||^2 over the mesh for a separable-sum exact
  * solution u, with a (k+3)-point Gauss rule per direction (exact for the
  * polynomial part, accurate for the smooth part). */

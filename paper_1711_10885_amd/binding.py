@@ -14,7 +14,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdgmf.so")
 
-DG_OK, DG_EINVAL, DG_ENOMEM, DG_EHIP, DG_ENOTCONV, DG_ENAN = 0, -1, -2, -3, -4, -5
+DG_OK, DG_EINVAL, DG_ENOMEM, DG_EHIP, DG_ENOTCONV, DG_ENAN, DG_EIO = 0, -1, -2, -3, -4, -5, -6
 DG_WITH_BLOCK_JACOBI = 2
 DG_PERIODIC_X, DG_PERIODIC_Y, DG_PERIODIC_Z = 4, 8, 16
 DG_B_PRODUCT = 32
@@ -27,11 +27,12 @@ DG_PREC_NONE, DG_PREC_BLOCK_JACOBI, DG_PREC_LEARNED = 0, 1, 2
 DG_ORTH_CGS1, DG_ORTH_CGS2 = 0, 1
 
 _STATUS = {DG_EINVAL: "DG_EINVAL", DG_ENOMEM: "DG_ENOMEM", DG_EHIP: "DG_EHIP",
-           DG_ENOTCONV: "DG_ENOTCONV", DG_ENAN: "DG_ENAN"}
+           DG_ENOTCONV: "DG_ENOTCONV", DG_ENAN: "DG_ENAN", DG_EIO: "DG_EIO"}
 
 # every symbol include/dg.h declares
-EXPORTS = ["dg_setup", "dg_apply", "dg_apply_f32", "dg_load_vector", "dg_set_kernel", "dg_solve", "dg_precond_apply",
+EXPORTS = ["dg_setup", "dg_apply", "dg_apply_f32", "dg_load_vector", "dg_project_gaussian", "dg_set_kernel", "dg_solve", "dg_precond_apply",
            "dg_learned_train", "dg_learned_nparams", "dg_learned_set_params", "dg_learned_get_params",
+           "dg_learned_save", "dg_learned_load",
            "dg_mlp_forward", "dg_mlp_grad", "dg_mlp_step", "dg_heun", "dg_heun_noalloc", "dg_ndof", "dg_degree", "dg_bj_nblocks",
            "dg_last_error", "dg_destroy"]
 
@@ -116,6 +117,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dg_load_vector.argtypes = [H, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_int32), vp, vp]
     lib.dg_load_vector.restype = ctypes.c_int
+    lib.dg_project_gaussian.argtypes = [H, ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_double), vp, vp]
+    lib.dg_project_gaussian.restype = ctypes.c_int
     lib.dg_heun.argtypes = [H, vp, vp, ctypes.c_double, ctypes.c_int32, vp]
     lib.dg_heun.restype = ctypes.c_int
     lib.dg_heun_noalloc.argtypes = [H, vp, vp, ctypes.c_double, ctypes.c_int32, vp]
@@ -138,6 +141,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dg_learned_set_params.argtypes = [H, fp, ctypes.c_int64]
     lib.dg_learned_set_params.restype = ctypes.c_int
     lib.dg_learned_get_params.argtypes = [H, fp, ctypes.c_int64]
+    lib.dg_learned_save.argtypes = [H, ctypes.c_char_p]
+    lib.dg_learned_save.restype = ctypes.c_int
+    lib.dg_learned_load.argtypes = [H, ctypes.c_char_p]
+    lib.dg_learned_load.restype = ctypes.c_int
     lib.dg_learned_get_params.restype = ctypes.c_int
     lib.dg_mlp_forward.argtypes = [H, vp, ctypes.c_int32, vp, vp]
     lib.dg_mlp_forward.restype = ctypes.c_int
@@ -319,6 +326,17 @@ class DG:
                                      ctypes.c_void_p(f.data_ptr()), _stream_ptr(stream)))
         return f
 
+    def project_gaussian(self, amp: float, width: float, center, u=None, stream=None):
+        """L2 projection of amp exp(-width |x - center|^2) onto the DG space."""
+        import torch
+        c = np.ascontiguousarray(center, dtype=np.float64).reshape(3)
+        if u is None:
+            u = torch.empty(self.ndof, dtype=torch.float64, device="cuda")
+        _check_vec(u, self.ndof, torch.float64, "u")
+        _check(load().dg_project_gaussian(self._h, float(amp), float(width), c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                          ctypes.c_void_p(u.data_ptr()), _stream_ptr(stream)))
+        return u
+
     def apply_f32(self, x, y=None, stream=None):
         """y := A x with FP32 vectors (mixed-precision operator)."""
         import torch
@@ -412,6 +430,14 @@ class DG:
         p = np.empty(n, dtype=np.float32)
         _check(load().dg_learned_get_params(self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), n))
         return p
+
+    def learned_save(self, path: str):
+        """Checkpoint of the network, its Adam moments and step count."""
+        _check(load().dg_learned_save(self._h, os.fsencode(path)))
+
+    def learned_load(self, path: str):
+        """Restore a checkpoint written by learned_save (same degree)."""
+        _check(load().dg_learned_load(self._h, os.fsencode(path)))
 
     def mlp_forward(self, X, stream=None):
         """Network outputs for rows X (float32 device tensor, B x in)."""

@@ -32,6 +32,9 @@
 #include <string>
 #include <vector>
 
+#include <cstdio>
+#include <cstring>
+
 #include "dg_internal.h"
 #include "krylov.h"
 
@@ -835,13 +838,8 @@ extern "C" int64_t dg_learned_nparams(const dg_handle *h) {
   return public_nparams(dims_for(h->k));
 }
 
-extern "C" dg_status dg_learned_set_params(dg_handle *h, const float *params, int64_t n) {
-  dg_status ds = learned_prologue(h, "dg_learned_set_params");
-  if (ds != DG_OK) return ds;
-  if (!params) return set_error(DG_EINVAL, "dg_learned_set_params: params is NULL");
-  Mlp *M = h->mlp;
-  const MlpDims &d = M->d;
-  if (n != public_nparams(d)) return set_error(DG_EINVAL, "dg_learned_set_params: wrong parameter count");
+// public layout (host) -> padded master layout (host), zero padding
+static std::vector<float> padded_from_public(const MlpDims &d, const float *params) {
   std::vector<float> pad(size_t(d.np), 0.0f);
   const float *q = params;
   for (int o = 0; o < d.hid; ++o)
@@ -853,6 +851,17 @@ extern "C" dg_status dg_learned_set_params(dg_handle *h, const float *params, in
   for (int o = 0; o < d.out; ++o)
     for (int i = 0; i < d.hid; ++i) pad[d.oW3 + int64_t(o) * d.hid + i] = *q++;
   for (int o = 0; o < d.out; ++o) pad[d.ob3 + o] = *q++;
+  return pad;
+}
+
+extern "C" dg_status dg_learned_set_params(dg_handle *h, const float *params, int64_t n) {
+  dg_status ds = learned_prologue(h, "dg_learned_set_params");
+  if (ds != DG_OK) return ds;
+  if (!params) return set_error(DG_EINVAL, "dg_learned_set_params: params is NULL");
+  Mlp *M = h->mlp;
+  const MlpDims &d = M->d;
+  if (n != public_nparams(d)) return set_error(DG_EINVAL, "dg_learned_set_params: wrong parameter count");
+  const std::vector<float> pad = padded_from_public(d, params);
   hipError_t e = hipMemcpy(M->master, pad.data(), pad.size() * sizeof(float), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(M->m, 0, d.np * sizeof(float));
   if (e == hipSuccess) e = hipMemset(M->v, 0, d.np * sizeof(float));
@@ -890,6 +899,98 @@ extern "C" dg_status dg_learned_get_params(dg_handle *h, float *params, int64_t 
   dg_status ds = learned_prologue(h, "dg_learned_get_params");
   if (ds != DG_OK) return ds;
   return export_params(h, h->mlp->master, params, n, "dg_learned_get_params");
+}
+
+// ---- checkpoint: parameters, Adam moments and step count -------------------
+// File: 64-byte header {char magic[8] = "DGMFNET1"; int32 version = 1, k,
+// in, hidden, out, 0; int64 n, step; uint64 checksum; 8 zero bytes}, then
+// the parameters, the first and the second Adam moments, n FP32 values each
+// in the public layout; checksum = FNV-1a (64-bit) of those 12 n bytes.
+// Native byte order.
+struct CkptHeader {
+  char magic[8];
+  int32_t version, k, in, hid, out, zero;
+  int64_t n, step;
+  uint64_t checksum, pad;
+};
+static_assert(sizeof(CkptHeader) == 64, "checkpoint header is 64 bytes");
+
+static uint64_t fnv1a(const void *data, size_t bytes, uint64_t hsh = 1469598103934665603ull) {
+  const unsigned char *p = static_cast<const unsigned char *>(data);
+  for (size_t i = 0; i < bytes; ++i) hsh = (hsh ^ p[i]) * 1099511628211ull;
+  return hsh;
+}
+
+extern "C" dg_status dg_learned_save(dg_handle *h, const char *path) {
+  if (!h) return set_error(DG_EINVAL, "dg_learned_save: handle is NULL");
+  if (!path) return set_error(DG_EINVAL, "dg_learned_save: path is NULL");
+  if (!h->mlp || !h->mlp->trained) return set_error(DG_EINVAL, "dg_learned_save: no trained or loaded network");
+  dg_status ds = learned_prologue(h, "dg_learned_save");
+  if (ds != DG_OK) return ds;
+  Mlp *M = h->mlp;
+  const MlpDims &d = M->d;
+  const int64_t n = public_nparams(d);
+  std::vector<float> body(size_t(3 * n));
+  const float *src[3] = {M->master, M->m, M->v};
+  for (int t = 0; t < 3; ++t)
+    if ((ds = export_params(h, src[t], body.data() + t * n, n, "dg_learned_save")) != DG_OK) return ds;
+  CkptHeader hd;
+  std::memset(&hd, 0, sizeof(hd));
+  std::memcpy(hd.magic, "DGMFNET1", 8);
+  hd.version = 1;
+  hd.k = h->k;
+  hd.in = d.in;
+  hd.hid = d.hid;
+  hd.out = d.out;
+  hd.n = n;
+  hd.step = M->step;
+  hd.checksum = fnv1a(body.data(), body.size() * sizeof(float));
+  FILE *f = std::fopen(path, "wb");
+  if (!f) return set_error(DG_EIO, std::string("dg_learned_save: cannot open ") + path);
+  const bool ok = std::fwrite(&hd, sizeof(hd), 1, f) == 1 &&
+                  std::fwrite(body.data(), sizeof(float), body.size(), f) == body.size();
+  if (std::fclose(f) != 0 || !ok) return set_error(DG_EIO, std::string("dg_learned_save: write failed: ") + path);
+  return DG_OK;
+}
+
+extern "C" dg_status dg_learned_load(dg_handle *h, const char *path) {
+  dg_status ds = learned_prologue(h, "dg_learned_load");
+  if (ds != DG_OK) return ds;
+  if (!path) return set_error(DG_EINVAL, "dg_learned_load: path is NULL");
+  Mlp *M = h->mlp;
+  const MlpDims &d = M->d;
+  const int64_t n = public_nparams(d);
+  FILE *f = std::fopen(path, "rb");
+  if (!f) return set_error(DG_EIO, std::string("dg_learned_load: cannot open ") + path);
+  CkptHeader hd;
+  std::vector<float> body;
+  bool ok = std::fread(&hd, sizeof(hd), 1, f) == 1;
+  const bool shape = ok && std::memcmp(hd.magic, "DGMFNET1", 8) == 0 && hd.version == 1 && hd.k == h->k &&
+                     hd.in == d.in && hd.hid == d.hid && hd.out == d.out && hd.n == n && hd.step >= 0;
+  if (shape) {
+    body.resize(size_t(3 * n));
+    ok = std::fread(body.data(), sizeof(float), body.size(), f) == body.size();
+    char extra;
+    ok = ok && std::fread(&extra, 1, 1, f) == 0;  // nothing after the moments
+  }
+  std::fclose(f);
+  if (!ok && !shape) return set_error(DG_EIO, std::string("dg_learned_load: cannot read ") + path);
+  if (!shape) return set_error(DG_EINVAL, "dg_learned_load: not a network checkpoint of this degree");
+  if (!ok) return set_error(DG_EIO, std::string("dg_learned_load: truncated or overlong file ") + path);
+  if (fnv1a(body.data(), body.size() * sizeof(float)) != hd.checksum)
+    return set_error(DG_EIO, "dg_learned_load: checksum mismatch");
+  float *dst[3] = {M->master, M->m, M->v};
+  hipError_t e = hipSuccess;
+  for (int t = 0; t < 3 && e == hipSuccess; ++t) {
+    const std::vector<float> pad = padded_from_public(d, body.data() + t * n);
+    e = hipMemcpy(dst[t], pad.data(), pad.size() * sizeof(float), hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) e = refresh(M, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_error(e, "dg_learned_load");
+  M->step = hd.step;
+  M->trained = true;
+  return DG_OK;
 }
 
 // caller rows (B x in floats, B x out targets; device) into the activation buffers

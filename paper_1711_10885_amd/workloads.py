@@ -27,6 +27,13 @@ the paper's model problem, Sec. 2.1, and Problem A of Sec. 5.1):
   c = 0, f = 0, the Taylor-Green flow field of that section (eq. (2)) in
   product form, sigma = 2k(k+2); initial concentration exp(-2 |x - x0|^2),
   x0 = (1/2, 0, 0), taken at the cell centres as the cell-constant mode.
+* ``transport_paper_k5_64`` the same with the paper's rule q = 2p + 4 for the
+  trigonometric flow field; the initial state is the L2 projection of the
+  Gaussian (computed by the library and, for checks, by the oracle).
+* ``problem_c(k)``, ``problem_b_cells(k)`` multilinear (trilinear) cells:
+  a smoothly curved vertex grid of the unit cube with the rule q = 3p + 4,
+  and a grid sheared layer by layer (affine cells with different
+  Jacobians) with q = 2p + 4, about 4M DOF.
 
 Problem fields beyond the model problem: ``periodic`` (per axis), the product-form
 flow field ``b_amp``/``b_freq``/``b_phase``, the diffusion factor ``kappa_poly``
@@ -260,6 +267,19 @@ def transport_k5_64(N: int = 64, k: int = 5) -> Problem:
     return Problem(ncell=(N, N, N), nodes=nodes, k=k, K=5e-6 * np.eye(3), c=0.0,
                    sigma=paper_sigma(k), periodic=(True, True, True), name=f"transport_k{k}_{N}",
                    meta={"dt": TRANSPORT_DT_H * (2.0 * math.pi / N)}, **TAYLOR_GREEN)
+
+
+def transport_paper_k5_64(N: int = 64, k: int = 5) -> Problem:
+    """The transport problem with the paper's quadrature for its
+    trigonometric flow field, q = 2p + 4 (k + 3 points per direction, Sec.
+    5.4); its initial state is the L2 projection of the Gaussian
+    (``TRANSPORT_GAUSSIAN``), which the library computes."""
+    p = transport_k5_64(N, k)
+    return p.with_(quad_extra=2, name=f"transport_paper_k{k}_{N}")
+
+
+# the initial concentration of Sec. 5.4: amp exp(-width |x - center|^2)
+TRANSPORT_GAUSSIAN = dict(amp=1.0, width=2.0, center=(0.5, 0.0, 0.0))
 
 
 def transport_initial(prob: Problem, x0=(0.5, 0.0, 0.0)) -> np.ndarray:

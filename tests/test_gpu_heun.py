@@ -185,6 +185,42 @@ def test_taylor_green_mass_is_conserved():
     assert np.abs(u - u0).max() > 1e-3
 
 
+@pytest.mark.parametrize("k,qe,N", [(2, 0, 5), (3, 2, 4), (5, 2, 3)])
+def test_gaussian_projection_matches_oracle(k, qe, N):
+    """dg_project_gaussian (the L2 projection of the initial concentration of
+    Sec. 5.4) on the periodic box against the oracle's projection."""
+    torch = _torch()
+    from paper_1711_10885_amd import binding
+    p = W.transport_k5_64(N=N, k=k).with_(quad_extra=qe)
+    G = W.TRANSPORT_GAUSSIAN
+    ref = oracle.project_gaussian(p, G["amp"], G["width"], G["center"])
+    with binding.DG(p) as dg:
+        u = dg.project_gaussian(G["amp"], G["width"], G["center"]).cpu().numpy()
+    e = np.abs(u - ref).max() / np.abs(ref).max()
+    print(f"projection k={k} quad_extra={qe}: relmax {e:.2e}", flush=True)
+    assert e <= TOL
+
+
+def test_taylor_green_with_the_paper_rule_from_the_projected_gaussian():
+    """The transport example as the paper runs it (Sec. 5.4): the rule
+    q = 2p + 4 for the trigonometric flow field and the L2-projected Gaussian
+    start; 6 Heun steps on a 4^3 mesh at k = 3 against the oracle started
+    from its own projection."""
+    torch = _torch()
+    from paper_1711_10885_amd import binding
+    p = W.transport_paper_k5_64(N=4, k=3)
+    G = W.TRANSPORT_GAUSSIAN
+    u0_ref = oracle.project_gaussian(p, G["amp"], G["width"], G["center"])
+    dt, n = p.meta["dt"], 6
+    with binding.DG(p) as dg:
+        u = dg.project_gaussian(G["amp"], G["width"], G["center"])
+        u0 = u.cpu().numpy()
+        dg.heun(u, dt, n)
+        got = u.cpu().numpy()
+    assert np.abs(u0 - u0_ref).max() <= TOL * np.abs(u0_ref).max()
+    _check(got, oracle.heun(p, u0_ref, dt, n), u0_ref, "taylor-green q=2p+4, projected start")
+
+
 @pytest.mark.parametrize("variant", VARIANTS)
 def test_heun_with_a_kappa_polynomial(variant):
     p = _mild(W.random_problem(1320, ncell=(3, 2, 2), k=4, b="product", periodic=(True, True, False)))

@@ -268,3 +268,59 @@ def test_learned_preconditioner_at_64_cubed_records_its_fallback():
         assert np.isfinite(sl["fallback_resid"]) and sl["fallback_resid"] > 1e-8
     else:
         assert sl["fallback_step"] == -1 and sl["fallback_cycle"] == -1
+
+
+def test_checkpoint_resume_equals_an_uninterrupted_run(tmp_path):
+    """Adam training stopped after three steps, saved, loaded into a new
+    handle and continued for three more steps gives, bit for bit, the
+    parameters of six uninterrupted steps (parameters, both moments and the
+    step count are in the file); a corrupted file and a file of another
+    degree are rejected."""
+    torch = _torch()
+    from paper_1711_10885_amd import binding
+    k = 2
+    nin, nout = mlp.sizes(k)
+    rng = np.random.default_rng(830)
+    batches = [(torch.from_numpy(rng.standard_normal((128, nin)).astype(np.float32)).cuda(),
+                torch.from_numpy(rng.standard_normal((128, nout)).astype(np.float32)).cuda()) for _ in range(6)]
+    ck = str(tmp_path / "net.ckpt")
+    _, a = _handle(k)
+    with a:
+        a.learned_set_params(_params(k, 831))
+        for X, T in batches[:3]:
+            a.mlp_step(X, T, lr=1e-3)
+        a.learned_save(ck)
+        saved = a.learned_get_params()
+        for X, T in batches[3:]:
+            a.mlp_step(X, T, lr=1e-3)
+        uninterrupted = a.learned_get_params()
+    _, b = _handle(k, seed=701)
+    with b:
+        b.learned_load(ck)
+        assert np.array_equal(b.learned_get_params(), saved)
+        for X, T in batches[3:]:
+            b.mlp_step(X, T, lr=1e-3)
+        resumed = b.learned_get_params()
+    print(f"resumed vs uninterrupted: max |diff| {np.abs(resumed - uninterrupted).max():.3e}", flush=True)
+    assert np.array_equal(resumed, uninterrupted)
+    # the moments matter: loading the parameters alone (moments reset) differs
+    _, c = _handle(k, seed=702)
+    with c:
+        c.learned_set_params(saved)
+        for X, T in batches[3:]:
+            c.mlp_step(X, T, lr=1e-3)
+        assert not np.array_equal(c.learned_get_params(), uninterrupted)
+    raw = bytearray(open(ck, "rb").read())
+    raw[100] ^= 0x40
+    bad = str(tmp_path / "bad.ckpt")
+    open(bad, "wb").write(bytes(raw))
+    _, d = _handle(k, seed=703)
+    with d:
+        with pytest.raises(binding.DGError) as e:
+            d.learned_load(bad)
+        assert e.value.status == binding.DG_EIO
+    _, other = _handle(3, seed=704)
+    with other:
+        with pytest.raises(binding.DGError) as e:
+            other.learned_load(ck)
+        assert e.value.status == binding.DG_EINVAL
