@@ -122,12 +122,11 @@ typedef enum {
  *              of Sec. 5.1); 2: the raised rule with k+3 points (q = 2p + 4,
  *              Problem B), for k <= 8.  Every integral of the operator uses
  *              the rule, the load vector included.  With 2 the
- *              operator runs the tuned kernel of degree k+2 (whose Gauss rule
- *              has k+3 points) on zero-padded vectors and keeps the modes
- *              <= k, in FP64 and FP32 (the hierarchical basis makes this the
- *              raised-rule operator); DG_KERNEL_REFERENCE selects the
- *              reference-layout kernel with rectangular contractions.  The
- *              handle keeps 2 ncells (k+3)^3 doubles of workspace.
+ *              operator runs the tuned kernel with k+3 Gauss points and k+1
+ *              modes per direction (rectangular 1D contractions; the tables
+ *              of the hierarchical basis are the first k+1 columns of those
+ *              of degree k+2), in FP64 and FP32, Heun stages fused;
+ *              DG_KERNEL_REFERENCE selects the reference-layout kernel.
  *   affine     with DG_AFFINE the mesh is the image x = A xi of the tensor
  *              grid xi of the nodes (affine cells, Problem B of Sec. 5.1):
  *              gradients, normals, face and cell measures, d = nu^T D nu and

@@ -151,7 +151,6 @@ extern "C" void dg_destroy(dg_handle *h) {
   if (h->bj_cells) (void)hipFree(h->bj_cells);
   if (h->bj_gblock) (void)hipFree(h->bj_gblock);
   if (h->ts) (void)hipFree(h->ts);
-  if (h->rq) (void)hipFree(h->rq);
   if (h->dev_block) (void)hipFree(h->dev_block);
   if (h->geo_block) (void)hipFree(h->geo_block);
   if (cur != h->device) (void)hipSetDevice(cur);
@@ -467,8 +466,6 @@ extern "C" dg_status dg_setup(const dg_problem *p_in, dg_handle **out) {
   h->quad_extra = p->quad_extra;
   h->vol_scale = vol_scale;
   h->affine = (p_in->flags & DG_AFFINE) != 0;
-  h->rq = nullptr;
-  h->rq_bytes = 0;
 
   // host staging of every device table, then one allocation + one copy
   // (coefficients at the Gauss coordinates of the operator's rule)
@@ -602,18 +599,6 @@ extern "C" dg_status dg_setup(const dg_problem *p_in, dg_handle **out) {
     M.verts = gb;
     M.cvol = gb + off_cv;
     for (int a = 0; a < 3; ++a) M.farea[a] = gb + off_fa[a];
-  }
-  if (h->quad_extra && !multilinear) {
-    // raised rule: padded input and output of the degree-(k+2) kernel
-    const int mq = n + h->quad_extra;
-    const size_t bytes = 2 * size_t(h->ncells) * size_t(mq * mq * mq) * sizeof(double);
-    e = hipMalloc(&h->rq, bytes);
-    if (e != hipSuccess) {
-      h->rq = nullptr;
-      dg_destroy(h);
-      return hip_error(e, "dg_setup: raised-rule workspace");
-    }
-    h->rq_bytes = bytes;
   }
   if (p->flags & DG_WITH_BLOCK_JACOBI) {
     const dg_status ds = build_block_jacobi(h, p);

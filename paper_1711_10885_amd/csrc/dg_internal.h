@@ -77,8 +77,6 @@ struct dg_handle {
   int quad_extra;
   int affine;         // the mesh is an affine image of the tensor grid (folded into the coefficients)
   double vol_scale;   // |det A|: physical cell volume over tensor-grid cell volume (1 if not affine)
-  void *rq;           // raised rule: two padded vectors of ncells (k+3)^3 doubles (or null)
-  size_t rq_bytes;
   dgmf::DevMesh mesh;
   void *dev_block;  // single allocation backing the DevMesh arrays
   void *geo_block;  // multilinear meshes: vertices, cell volumes, face areas (or null)
@@ -121,9 +119,11 @@ hipError_t launch_heun_fused_f64(const dg_handle *h, const double *x, double *y,
 
 // Operator application through the kernel the handle selects.
 hipError_t apply_f64(const dg_handle *h, const double *x, double *y, hipStream_t s);
-// the raised rule on the tuned kernels: pad to degree k + 2, apply, restrict
+// the raised rule on the tuned kernels: k + 3 points, k + 1 modes
 hipError_t apply_raised_f64(const dg_handle *h, const double *x, double *y, hipStream_t s);
 hipError_t apply_raised_f32(const dg_handle *h, const float *x, float *y, hipStream_t s);
+hipError_t launch_heun_raised_f64(const dg_handle *h, const double *x, double *y, const double *f, double dt,
+                                  int stage, hipStream_t s);
 // FP32 operator of the handle (raised rule included)
 hipError_t apply_f32(const dg_handle *h, const float *x, float *y, hipStream_t s);
 

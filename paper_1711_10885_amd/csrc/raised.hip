@@ -1,73 +1,54 @@
 // The operator with the raised Gauss rule (q = 2p + 4: k + 3 points per
-// direction, Problem B of Sec. 5.1) on the tuned kernels.  The orthonormal
-// Legendre basis is hierarchical, and the fused kernel of degree k + 2 uses
-// exactly k + 3 Gauss points, so for x in the degree-k space
-//   (A_raised x)_i = (A_{k+2} P x)_i  for every mode i <= k,
-// with P the zero padding of the modes above k; the penalty sigma is the
-// problem's own (it is a parameter of the form, not of the kernel degree) and
-// the coefficient tables are already tabulated at the k + 3 points.  One
-// apply = pad, the degree-(k+2) kernel, restriction; the two padded vectors
-// live in a workspace the handle allocates at setup.
-#include <hip/hip_runtime.h>
-
-#include <algorithm>
-
-#include "dg_internal.h"
+// direction, Problem B of Sec. 5.1) on the tuned kernels: the fused kernel
+// with N = k + 3 Gauss points per direction and NI = k + 1 modes, i.e. with
+// rectangular (k+3) x (k+1) 1D contractions.  The orthonormal Legendre basis
+// is hierarchical, so the tables of the degree-k basis at the k + 3 points
+// are the first k + 1 columns of the degree-(k+2) tables; the kernel reads x
+// and writes y in the degree-k layout, runs every contraction only over the
+// k + 1 modes of its modal side and keeps the pencils of the higher modes at
+// zero.  The penalty sigma is the problem's own and the coefficient tables
+// are tabulated at the k + 3 points.
+#include "fused_kernel.h"
 
 namespace dgmf {
 
-constexpr int kRqThreads = 256;
-
-// xp[c][j1 + M j2 + M^2 j3] = x[c][j1 + N j2 + N^2 j3] for j < N, else 0
-template <typename T>
-__global__ __launch_bounds__(kRqThreads) void k_pad(const T *__restrict__ x, T *__restrict__ xp, int N, int M,
-                                                    int64_t total) {
-  for (int64_t g = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; g < total; g += int64_t(gridDim.x) * blockDim.x) {
-    const int MMM = M * M * M;
-    const int64_t c = g / MMM;
-    const int r = int(g - c * MMM);
-    const int j1 = r % M, j2 = (r / M) % M, j3 = r / (M * M);
-    xp[g] = (j1 < N && j2 < N && j3 < N) ? x[c * (N * N * N) + j1 + N * (j2 + N * j3)] : T(0);
+template <typename T, bool HEUN, bool BP, bool KP>
+static hipError_t launch_raised_bp(const dg_handle *h, const T *x, T *y, hipStream_t s, const double *f, double dt,
+                                   int stage) {
+  if (h->quad_extra != 2) return hipErrorInvalidValue;
+  switch (h->k + 1) {
+    case 2: return launch_fused_n<4, T, HEUN, BP, KP, 2>(h, x, y, s, f, dt, stage);
+    case 3: return launch_fused_n<5, T, HEUN, BP, KP, 3>(h, x, y, s, f, dt, stage);
+    case 4: return launch_fused_n<6, T, HEUN, BP, KP, 4>(h, x, y, s, f, dt, stage);
+    case 5: return launch_fused_n<7, T, HEUN, BP, KP, 5>(h, x, y, s, f, dt, stage);
+    case 6: return launch_fused_n<8, T, HEUN, BP, KP, 6>(h, x, y, s, f, dt, stage);
+    case 7: return launch_fused_n<9, T, HEUN, BP, KP, 7>(h, x, y, s, f, dt, stage);
+    case 8: return launch_fused_n<10, T, HEUN, BP, KP, 8>(h, x, y, s, f, dt, stage);
+    case 9: return launch_fused_n<11, T, HEUN, BP, KP, 9>(h, x, y, s, f, dt, stage);
+    default: return hipErrorInvalidValue;
   }
 }
 
-// y[c][j] = yp[c][j padded], j < N^3
-template <typename T>
-__global__ __launch_bounds__(kRqThreads) void k_restrict(const T *__restrict__ yp, T *__restrict__ y, int N, int M,
-                                                         int64_t total) {
-  for (int64_t g = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; g < total; g += int64_t(gridDim.x) * blockDim.x) {
-    const int NNN = N * N * N;
-    const int64_t c = g / NNN;
-    const int r = int(g - c * NNN);
-    const int j1 = r % N, j2 = (r / N) % N, j3 = r / (N * N);
-    y[g] = yp[c * (M * M * M) + j1 + M * (j2 + M * j3)];
-  }
-}
-
-static unsigned rq_grid(int64_t n) { return unsigned(std::min<int64_t>((n + kRqThreads - 1) / kRqThreads, 1 << 20)); }
-
-template <typename T>
-static hipError_t apply_raised(const dg_handle *h, const T *x, T *y, hipStream_t s) {
-  const int N = h->k + 1, M = N + h->quad_extra;
-  const int64_t np = h->ncells * int64_t(M) * M * M;
-  if (!h->rq || h->rq_bytes < 2 * size_t(np) * sizeof(T)) return hipErrorInvalidValue;
-  T *xp = static_cast<T *>(h->rq), *yp = xp + np;
-  hipLaunchKernelGGL(k_pad<T>, dim3(rq_grid(np)), dim3(kRqThreads), 0, s, x, xp, N, M, np);
-  hipError_t e = (sizeof(T) == 8) ? launch_apply_fused_f64(h, reinterpret_cast<const double *>(xp),
-                                                           reinterpret_cast<double *>(yp), s)
-                                  : launch_apply_fused_f32(h, reinterpret_cast<const float *>(xp),
-                                                           reinterpret_cast<float *>(yp), s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_restrict<T>, dim3(rq_grid(h->ndof)), dim3(kRqThreads), 0, s, yp, y, N, M, int64_t(h->ndof));
-  return hipGetLastError();
+// coefficient variants as for the (k+1)-point rule
+template <typename T, bool HEUN>
+static hipError_t launch_raised(const dg_handle *h, const T *x, T *y, hipStream_t s, const double *f = nullptr,
+                                double dt = 0.0, int stage = 0) {
+  if (h->mesh.kpoly) return launch_raised_bp<T, HEUN, true, true>(h, x, y, s, f, dt, stage);
+  return h->mesh.bprod ? launch_raised_bp<T, HEUN, true, false>(h, x, y, s, f, dt, stage)
+                       : launch_raised_bp<T, HEUN, false, false>(h, x, y, s, f, dt, stage);
 }
 
 hipError_t apply_raised_f64(const dg_handle *h, const double *x, double *y, hipStream_t s) {
-  return apply_raised<double>(h, x, y, s);
+  return launch_raised<double, false>(h, x, y, s);
 }
 
 hipError_t apply_raised_f32(const dg_handle *h, const float *x, float *y, hipStream_t s) {
-  return apply_raised<float>(h, x, y, s);
+  return launch_raised<float, false>(h, x, y, s);
+}
+
+hipError_t launch_heun_raised_f64(const dg_handle *h, const double *x, double *y, const double *f, double dt,
+                                  int stage, hipStream_t s) {
+  return launch_raised<double, true>(h, x, y, s, f, dt, stage);
 }
 
 }  // namespace dgmf

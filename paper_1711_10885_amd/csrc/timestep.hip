@@ -49,9 +49,9 @@ __global__ __launch_bounds__(kTsThreads) void k_heun_stage(const double *u, cons
 
 static int ts_grid(int64_t n) { return int(std::min<int64_t>((n + kTsThreads - 1) / kTsThreads, 1 << 20)); }
 
-// the stage update fused into the operator kernel's store (tuned kernels,
-// (k+1)-point rule), else an apply into A u and a separate stage pass
-static bool heun_is_fused(const dg_handle *h) { return h->variant != DG_KERNEL_REFERENCE && !h->quad_extra; }
+// the stage update fused into the operator kernel's store (tuned kernels),
+// else an apply into A u and a separate stage pass (reference kernel)
+static bool heun_is_fused(const dg_handle *h) { return h->variant != DG_KERNEL_REFERENCE; }
 
 }  // namespace dgmf
 
