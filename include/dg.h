@@ -446,9 +446,9 @@ dg_status dg_heun(dg_handle *h, double *u, const double *f, double dt, int32_t n
  * steps and kernels, with the stage workspace taken from a fixed array of
  * 64 MiB in device memory that the library holds on every device it runs on
  * until the process ends, instead of the handle's workspace.  It calls no
- * allocating routine.  Needs ndof * 8 bytes on the fused path (tuned kernels,
- * quad_extra = 0) and 2 ndof * 8 bytes otherwise (reference kernel, raised
- * rule): at most 8,388,608 or 4,194,304 DOF; larger handles get DG_EINVAL
+ * allocating routine.  Needs ndof * 8 bytes on the fused path (the tuned
+ * kernels, either rule) and 2 ndof * 8 bytes with DG_KERNEL_REFERENCE: at
+ * most 8,388,608 or 4,194,304 DOF; larger handles get DG_EINVAL
  * (use dg_heun).  Every call on one device shares that array and it keeps
  * the last call's contents (nothing in it needs to start at zero): calls
  * that overlap in time on one device, from several streams or threads,
