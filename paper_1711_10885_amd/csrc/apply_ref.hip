@@ -68,30 +68,79 @@ constexpr int kRefThreads = 256;
 // A(q, t) = Mat[q][t] (TRANS = false: evaluation, points from basis
 // coefficients) or Mat[t][q] (TRANS = true: integration against the test
 // functions); an optional second term with in2, Mat2.
-template <int LD, bool TRANS, int AX, int O0, int O1, int O2, int LI, int TPC>
+// BLK = 1: one thread per output entry.  BLK > 1: a work item is one pencil
+// along AX and BLK consecutive outputs q of it; the pencil's inputs are read
+// from LDS once into registers and serve BLK outputs, and the pencils vary
+// fastest across threads, so the threads of a group read the same matrix
+// entries (LDS broadcasts).  Measured: faster for the multilinear cells at
+// k >= 3, slower at k <= 2 and for the (k+1)-point rule, where the kernel is
+// bound by latency rather than by LDS reads.
+template <int LD, bool TRANS, int AX, int O0, int O1, int O2, int LI, int TPC, int BLK = 1>
 __device__ inline void contract(int lt, double *out, const double *in, const double (*Mat)[LD],
                                 const double *in2 = nullptr, const double (*Mat2)[LD] = nullptr) {
   constexpr int I0 = AX == 0 ? LI : O0, I1 = AX == 1 ? LI : O1;
-  constexpr int IS[3] = {1, I0, I0 * I1};  // input strides
-  constexpr int NT = O0 * O1 * O2;
-  for (int i = lt; i < NT; i += TPC) {
-    const int i0 = i % O0, i1 = (i / O0) % O1, i2 = i / (O0 * O1);
-    const int q = AX == 0 ? i0 : (AX == 1 ? i1 : i2);
-    const int base = (AX == 0 ? 0 : i0 * IS[0]) + (AX == 1 ? 0 : i1 * IS[1]) + (AX == 2 ? 0 : i2 * IS[2]);
-    double s = 0.0;
+  constexpr int IS[3] = {1, I0, I0 * I1};          // input strides
+  if constexpr (BLK == 1) {
+    constexpr int NT = O0 * O1 * O2;
+    for (int i = lt; i < NT; i += TPC) {
+      const int i0 = i % O0, i1 = (i / O0) % O1, i2 = i / (O0 * O1);
+      const int q = AX == 0 ? i0 : (AX == 1 ? i1 : i2);
+      const int base = (AX == 0 ? 0 : i0 * IS[0]) + (AX == 1 ? 0 : i1 * IS[1]) + (AX == 2 ? 0 : i2 * IS[2]);
+      double s = 0.0;
 #pragma unroll
-    for (int t = 0; t < LI; ++t) {
-      const double a = TRANS ? Mat[t][q] : Mat[q][t];
-      s = fma(a, in[base + t * IS[AX]], s);
+      for (int t = 0; t < LI; ++t) {
+        const double a = TRANS ? Mat[t][q] : Mat[q][t];
+        s = fma(a, in[base + t * IS[AX]], s);
+      }
+      if (in2) {
+#pragma unroll
+        for (int t = 0; t < LI; ++t) {
+          const double a = TRANS ? Mat2[t][q] : Mat2[q][t];
+          s = fma(a, in2[base + t * IS[AX]], s);
+        }
+      }
+      out[i] = s;
+    }
+    return;
+  }
+  constexpr int OS[3] = {1, O0, O0 * O1};          // output strides
+  constexpr int OA = AX == 0 ? O0 : (AX == 1 ? O1 : O2);  // outputs along AX
+  constexpr int PA = AX == 0 ? O1 : O0, PB = AX == 2 ? O1 : O2;  // pencil grid (the other two axes)
+  constexpr int NP = PA * PB;
+  constexpr int RB = OA < BLK ? OA : BLK;
+  constexpr int NC = (OA + RB - 1) / RB;
+  for (int w = lt; w < NP * NC; w += TPC) {
+    const int pp = w % NP, c = w / NP;
+    const int pa = pp % PA, pb = pp / PA;
+    // the two non-AX indices (pa on the lower axis, pb on the upper)
+    const int ibase = AX == 0 ? (pa * IS[1] + pb * IS[2]) : (AX == 1 ? (pa * IS[0] + pb * IS[2]) : (pa * IS[0] + pb * IS[1]));
+    const int obase = AX == 0 ? (pa * OS[1] + pb * OS[2]) : (AX == 1 ? (pa * OS[0] + pb * OS[2]) : (pa * OS[0] + pb * OS[1]));
+    const int q0 = c * RB;
+    double v[LI];
+#pragma unroll
+    for (int t = 0; t < LI; ++t) v[t] = in[ibase + t * IS[AX]];
+    double s[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int q = q0 + r < OA ? q0 + r : OA - 1;
+      double acc = 0.0;
+#pragma unroll
+      for (int t = 0; t < LI; ++t) acc = fma(TRANS ? Mat[t][q] : Mat[q][t], v[t], acc);
+      s[r] = acc;
     }
     if (in2) {
 #pragma unroll
-      for (int t = 0; t < LI; ++t) {
-        const double a = TRANS ? Mat2[t][q] : Mat2[q][t];
-        s = fma(a, in2[base + t * IS[AX]], s);
+      for (int t = 0; t < LI; ++t) v[t] = in2[ibase + t * IS[AX]];
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        const int q = q0 + r < OA ? q0 + r : OA - 1;
+#pragma unroll
+        for (int t = 0; t < LI; ++t) s[r] = fma(TRANS ? Mat2[t][q] : Mat2[q][t], v[t], s[r]);
       }
     }
-    out[i] = s;
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+      if (q0 + r < OA) out[obase + (q0 + r) * OS[AX]] = s[r];
   }
 }
 
@@ -189,6 +238,7 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
   // doubles share the region of the volume tensors, which are dead by then
   constexpr bool BATCH = (Q != N) || GEO;
   constexpr int VBN = GEO ? 3 * kVB * kVB * kVB : 1;
+  constexpr int BK = (GEO && N >= 4) ? 4 : 1;  // register blocking of the contractions (k >= 3)
   __shared__ double VBs[CPB][VBN];
   constexpr int FB = 24 * NF + 72 * QF;
   constexpr int RSZ = (BATCH && FB > 7 * QB) ? FB : 7 * QB;
@@ -242,17 +292,17 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
   const double vol = h[0] * h[1] * h[2];
 
   // ---------------- volume: forward (u, d1 u, d2 u, d3 u at points) --------
-  contract<N, false, 0, Q, N, N, N, TPC>(lt, B0, X, sV);  // V1 x
-  contract<N, false, 0, Q, N, N, N, TPC>(lt, B1, X, sD);  // D1 x
+  contract<N, false, 0, Q, N, N, N, TPC, BK>(lt, B0, X, sV);  // V1 x
+  contract<N, false, 0, Q, N, N, N, TPC, BK>(lt, B1, X, sD);  // D1 x
   __syncthreads();
-  contract<N, false, 1, Q, Q, N, N, TPC>(lt, B2, B0, sV);  // V2 V1 x
-  contract<N, false, 1, Q, Q, N, N, TPC>(lt, B3, B1, sV);  // V2 D1 x
-  contract<N, false, 1, Q, Q, N, N, TPC>(lt, B4, B0, sD);  // D2 V1 x
+  contract<N, false, 1, Q, Q, N, N, TPC, BK>(lt, B2, B0, sV);  // V2 V1 x
+  contract<N, false, 1, Q, Q, N, N, TPC, BK>(lt, B3, B1, sV);  // V2 D1 x
+  contract<N, false, 1, Q, Q, N, N, TPC, BK>(lt, B4, B0, sD);  // D2 V1 x
   __syncthreads();
-  contract<N, false, 2, Q, Q, Q, N, TPC>(lt, B0, B2, sV);  // u
-  contract<N, false, 2, Q, Q, Q, N, TPC>(lt, B1, B3, sV);  // d^1 u (reference)
-  contract<N, false, 2, Q, Q, Q, N, TPC>(lt, B5, B4, sV);  // d^2 u
-  contract<N, false, 2, Q, Q, Q, N, TPC>(lt, B6, B2, sD);  // d^3 u
+  contract<N, false, 2, Q, Q, Q, N, TPC, BK>(lt, B0, B2, sV);  // u
+  contract<N, false, 2, Q, Q, Q, N, TPC, BK>(lt, B1, B3, sV);  // d^1 u (reference)
+  contract<N, false, 2, Q, Q, Q, N, TPC, BK>(lt, B5, B4, sV);  // d^2 u
+  contract<N, false, 2, Q, Q, Q, N, TPC, BK>(lt, B6, B2, sD);  // d^3 u
   __syncthreads();
   // ---------------- volume: pointwise flux (eq. (gauss_points)) ------------
   if constexpr (GEO) {
@@ -302,14 +352,14 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
   }
   __syncthreads();
   // ---------------- volume: transposed contractions (eq. (evalblf)) --------
-  contract<N, true, 2, Q, Q, N, Q, TPC>(lt, B2, B0, sV, B6, sD);  // along 3: V^T x0 + D^T x3
-  contract<N, true, 2, Q, Q, N, Q, TPC>(lt, B3, B1, sV);          // V^T x1
-  contract<N, true, 2, Q, Q, N, Q, TPC>(lt, B4, B5, sV);          // V^T x2
+  contract<N, true, 2, Q, Q, N, Q, TPC, BK>(lt, B2, B0, sV, B6, sD);  // along 3: V^T x0 + D^T x3
+  contract<N, true, 2, Q, Q, N, Q, TPC, BK>(lt, B3, B1, sV);          // V^T x1
+  contract<N, true, 2, Q, Q, N, Q, TPC, BK>(lt, B4, B5, sV);          // V^T x2
   __syncthreads();
-  contract<N, true, 1, Q, N, N, Q, TPC>(lt, B0, B2, sV, B4, sD);  // along 2
-  contract<N, true, 1, Q, N, N, Q, TPC>(lt, B1, B3, sV);
+  contract<N, true, 1, Q, N, N, Q, TPC, BK>(lt, B0, B2, sV, B4, sD);  // along 2
+  contract<N, true, 1, Q, N, N, Q, TPC, BK>(lt, B1, B3, sV);
   __syncthreads();
-  contract<N, true, 0, N, N, N, Q, TPC>(lt, Y, B0, sV, B1, sD);  // along 1
+  contract<N, true, 0, N, N, N, Q, TPC, BK>(lt, Y, B0, sV, B1, sD);  // along 1
   __syncthreads();
 
   // ---------------- faces --------------------------------------------------
@@ -349,23 +399,23 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
     }
     __syncthreads();
     // tangential evaluation of all six faces: first b, then c
-    contract<N, false, 0, Q, N, 6, N, TPC>(lt, S0, TUo, sV);
-    contract<N, false, 0, Q, N, 6, N, TPC>(lt, S1, TUo, sD);
-    contract<N, false, 0, Q, N, 6, N, TPC>(lt, S2, TUn, sV);
-    contract<N, false, 0, Q, N, 6, N, TPC>(lt, S3, TUn, sD);
+    contract<N, false, 0, Q, N, 6, N, TPC, BK>(lt, S0, TUo, sV);
+    contract<N, false, 0, Q, N, 6, N, TPC, BK>(lt, S1, TUo, sD);
+    contract<N, false, 0, Q, N, 6, N, TPC, BK>(lt, S2, TUn, sV);
+    contract<N, false, 0, Q, N, 6, N, TPC, BK>(lt, S3, TUn, sD);
     __syncthreads();
-    contract<N, false, 1, Q, Q, 6, N, TPC>(lt, uo, S0, sV);
-    contract<N, false, 1, Q, Q, 6, N, TPC>(lt, gbo, S1, sV);
-    contract<N, false, 1, Q, Q, 6, N, TPC>(lt, gco, S0, sD);
-    contract<N, false, 1, Q, Q, 6, N, TPC>(lt, un, S2, sV);
-    contract<N, false, 1, Q, Q, 6, N, TPC>(lt, gbn, S3, sV);
-    contract<N, false, 1, Q, Q, 6, N, TPC>(lt, gcn, S2, sD);
+    contract<N, false, 1, Q, Q, 6, N, TPC, BK>(lt, uo, S0, sV);
+    contract<N, false, 1, Q, Q, 6, N, TPC, BK>(lt, gbo, S1, sV);
+    contract<N, false, 1, Q, Q, 6, N, TPC, BK>(lt, gco, S0, sD);
+    contract<N, false, 1, Q, Q, 6, N, TPC, BK>(lt, un, S2, sV);
+    contract<N, false, 1, Q, Q, 6, N, TPC, BK>(lt, gbn, S3, sV);
+    contract<N, false, 1, Q, Q, 6, N, TPC, BK>(lt, gcn, S2, sD);
     __syncthreads();
-    contract<N, false, 0, Q, N, 6, N, TPC>(lt, S0, TDo, sV);
-    contract<N, false, 0, Q, N, 6, N, TPC>(lt, S1, TDn, sV);
+    contract<N, false, 0, Q, N, 6, N, TPC, BK>(lt, S0, TDo, sV);
+    contract<N, false, 0, Q, N, 6, N, TPC, BK>(lt, S1, TDn, sV);
     __syncthreads();
-    contract<N, false, 1, Q, Q, 6, N, TPC>(lt, gao, S0, sV);
-    contract<N, false, 1, Q, Q, 6, N, TPC>(lt, gan, S1, sV);
+    contract<N, false, 1, Q, Q, 6, N, TPC, BK>(lt, gao, S0, sV);
+    contract<N, false, 1, Q, Q, 6, N, TPC, BK>(lt, gan, S1, sV);
     __syncthreads();
     // pointwise face terms of every face point (as in the per-face loop below)
     if constexpr (GEO) {
@@ -494,12 +544,12 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
     }
     __syncthreads();
     // transposed tangential contractions: along c, then b
-    contract<N, true, 1, Q, N, 6, Q, TPC>(lt, uo, S0, sV, S2, sD);
-    contract<N, true, 1, Q, N, 6, Q, TPC>(lt, un, S1, sV);
-    contract<N, true, 1, Q, N, 6, Q, TPC>(lt, gao, S3, sV);
+    contract<N, true, 1, Q, N, 6, Q, TPC, BK>(lt, uo, S0, sV, S2, sD);
+    contract<N, true, 1, Q, N, 6, Q, TPC, BK>(lt, un, S1, sV);
+    contract<N, true, 1, Q, N, 6, Q, TPC, BK>(lt, gao, S3, sV);
     __syncthreads();
-    contract<N, true, 0, N, N, 6, Q, TPC>(lt, TUo, uo, sV, un, sD);  // R_v of every face
-    contract<N, true, 0, N, N, 6, Q, TPC>(lt, TDo, gao, sV);         // R_d
+    contract<N, true, 0, N, N, 6, Q, TPC, BK>(lt, TUo, uo, sV, un, sD);  // R_v of every face
+    contract<N, true, 0, N, N, 6, Q, TPC, BK>(lt, TDo, gao, sV);         // R_d
     __syncthreads();
     // normal direction last, all six faces into the own coefficients
     for (int i = lt; i < NB; i += TPC) {
@@ -555,23 +605,23 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
     }
     __syncthreads();
     // tangential evaluation: first b (stride 1 in the 2D grid), then c
-    contract<N, false, 0, Q, N, 1, N, TPC>(lt, S0, Uo, sV);
-    contract<N, false, 0, Q, N, 1, N, TPC>(lt, S1, Uo, sD);
-    contract<N, false, 0, Q, N, 1, N, TPC>(lt, S2, Un, sV);
-    contract<N, false, 0, Q, N, 1, N, TPC>(lt, S3, Un, sD);
+    contract<N, false, 0, Q, N, 1, N, TPC, BK>(lt, S0, Uo, sV);
+    contract<N, false, 0, Q, N, 1, N, TPC, BK>(lt, S1, Uo, sD);
+    contract<N, false, 0, Q, N, 1, N, TPC, BK>(lt, S2, Un, sV);
+    contract<N, false, 0, Q, N, 1, N, TPC, BK>(lt, S3, Un, sD);
     __syncthreads();
-    contract<N, false, 1, Q, Q, 1, N, TPC>(lt, uo, S0, sV);
-    contract<N, false, 1, Q, Q, 1, N, TPC>(lt, gbo, S1, sV);
-    contract<N, false, 1, Q, Q, 1, N, TPC>(lt, gco, S0, sD);
-    contract<N, false, 1, Q, Q, 1, N, TPC>(lt, un, S2, sV);
-    contract<N, false, 1, Q, Q, 1, N, TPC>(lt, gbn, S3, sV);
-    contract<N, false, 1, Q, Q, 1, N, TPC>(lt, gcn, S2, sD);
+    contract<N, false, 1, Q, Q, 1, N, TPC, BK>(lt, uo, S0, sV);
+    contract<N, false, 1, Q, Q, 1, N, TPC, BK>(lt, gbo, S1, sV);
+    contract<N, false, 1, Q, Q, 1, N, TPC, BK>(lt, gco, S0, sD);
+    contract<N, false, 1, Q, Q, 1, N, TPC, BK>(lt, un, S2, sV);
+    contract<N, false, 1, Q, Q, 1, N, TPC, BK>(lt, gbn, S3, sV);
+    contract<N, false, 1, Q, Q, 1, N, TPC, BK>(lt, gcn, S2, sD);
     __syncthreads();
-    contract<N, false, 0, Q, N, 1, N, TPC>(lt, S0, Do, sV);
-    contract<N, false, 0, Q, N, 1, N, TPC>(lt, S1, Dn, sV);
+    contract<N, false, 0, Q, N, 1, N, TPC, BK>(lt, S0, Do, sV);
+    contract<N, false, 0, Q, N, 1, N, TPC, BK>(lt, S1, Dn, sV);
     __syncthreads();
-    contract<N, false, 1, Q, Q, 1, N, TPC>(lt, gao, S0, sV);
-    contract<N, false, 1, Q, Q, 1, N, TPC>(lt, gan, S1, sV);
+    contract<N, false, 1, Q, Q, 1, N, TPC, BK>(lt, gao, S0, sV);
+    contract<N, false, 1, Q, Q, 1, N, TPC, BK>(lt, gan, S1, sV);
     __syncthreads();
     // pointwise face terms (Sec. 2.2): upwind flux, weighted average,
     // penalty, written with the outer normal n_T = sgn e_a of cell T
@@ -623,12 +673,12 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
     }
     __syncthreads();
     // transposed tangential contractions: along c, then b
-    contract<N, true, 1, Q, N, 1, Q, TPC>(lt, uo, S0, sV, S2, sD);  // value x V_c + (d_c part) x D_c
-    contract<N, true, 1, Q, N, 1, Q, TPC>(lt, un, S1, sV);          // d_b part
-    contract<N, true, 1, Q, N, 1, Q, TPC>(lt, gao, S3, sV);         // d_a part
+    contract<N, true, 1, Q, N, 1, Q, TPC, BK>(lt, uo, S0, sV, S2, sD);  // value x V_c + (d_c part) x D_c
+    contract<N, true, 1, Q, N, 1, Q, TPC, BK>(lt, un, S1, sV);          // d_b part
+    contract<N, true, 1, Q, N, 1, Q, TPC, BK>(lt, gao, S3, sV);         // d_a part
     __syncthreads();
-    contract<N, true, 0, N, N, 1, Q, TPC>(lt, Uo, uo, sV, un, sD);  // R_v
-    contract<N, true, 0, N, N, 1, Q, TPC>(lt, Do, gao, sV);         // R_d
+    contract<N, true, 0, N, N, 1, Q, TPC, BK>(lt, Uo, uo, sV, un, sD);  // R_v
+    contract<N, true, 0, N, N, 1, Q, TPC, BK>(lt, Do, gao, sV);         // R_d
     __syncthreads();
     // normal direction last: y(ja,jb,jc) += theta_ja(e) R_v + theta'_ja(e) R_d
     for (int i = lt; i < NB; i += TPC) {
