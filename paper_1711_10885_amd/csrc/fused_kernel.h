@@ -141,7 +141,11 @@ struct FCfg {
   // (one for N = 9) still fit in the 160 KB of LDS of a CU
   static constexpr int CPB = (N == 5) ? 10 : (N == 6) ? 7 : (N == 7) ? 5 : (N == 9) ? 3 : (NN <= 64 ? 64 / NN : 1);
   static constexpr int THREADS = ((CPB * LANES + 63) / 64) * 64;
-  static constexpr int WAVES_PER_SIMD = (N <= 8) ? 2 : 1;  // register budget target
+  // register budget: two waves per SIMD at every N.  At N >= 9 this caps the
+  // kernel at 256 VGPRs and spills 28-404 bytes per lane, and is still
+  // 1.04-1.62x faster than one wave per SIMD without spills (the kernel is
+  // bound by latency, which the second wave hides)
+  static constexpr int WAVES_PER_SIMD = 2;
   static constexpr int FCW = 8;  // doubles per face-constant record
   // per-cell LDS (doubles) of each exchange round
   static constexpr int mx(int a, int b) { return a > b ? a : b; }
