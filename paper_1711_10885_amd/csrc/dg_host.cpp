@@ -471,10 +471,12 @@ extern "C" dg_status dg_setup(const dg_problem *p_in, dg_handle **out) {
   // (coefficients at the Gauss coordinates of the operator's rule)
   const int m = h->tabq.m;
   std::vector<double> host;
-  size_t off_h[3], off_nd[3], off_bv[3], off_bn[3], off_kappa = 0;
+  size_t off_h[3], off_ih[3], off_nd[3], off_bv[3], off_bn[3], off_kappa = 0;
   for (int a = 0; a < 3; ++a) {
     off_h[a] = host.size();
     for (int i = 0; i < p->ncell[a]; ++i) host.push_back(p->nodes[a][i + 1] - p->nodes[a][i]);
+    off_ih[a] = host.size();
+    for (int i = 0; i < p->ncell[a]; ++i) host.push_back(1.0 / (p->nodes[a][i + 1] - p->nodes[a][i]));
     off_nd[a] = host.size();
     host.insert(host.end(), p->nodes[a], p->nodes[a] + p->ncell[a] + 1);
   }
@@ -547,6 +549,7 @@ extern "C" dg_status dg_setup(const dg_problem *p_in, dg_handle **out) {
   for (int a = 0; a < 3; ++a) {
     M.ncell[a] = p->ncell[a];
     M.h[a] = base + off_h[a];
+    M.ih[a] = base + off_ih[a];
     M.nodes[a] = base + off_nd[a];
     M.bvol[a] = base + off_bv[a];
     M.bnode[a] = base + off_bn[a];

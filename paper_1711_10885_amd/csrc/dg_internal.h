@@ -35,6 +35,7 @@ struct Tables {
 struct DevMesh {
   int ncell[3];
   double *h[3];       // cell extents per axis, ncell[a]
+  double *ih[3];      // their reciprocals 1 / h
   double *nodes[3];   // node coordinates per axis, ncell[a] + 1
   double *bvol[3];    // b_r at volume Gauss coordinates: [ncell[b_axis[r]] * m]
   double *bnode[3];   // b_r at nodes of axis b_axis[r]: [ncell[b_axis[r]] + 1]

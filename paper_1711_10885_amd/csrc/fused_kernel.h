@@ -75,10 +75,34 @@ struct TabOff {
   static constexpr int SIZE = G + N;
 };
 
+// Division by a divisor d >= 1 fixed for the launch, for 0 <= n < 2^31, by a
+// multiply and a shift (Granlund and Montgomery, PLDI 1994, Thm. 4.2): with
+// l = ceil(log2 d) and m = ceil(2^(31+l) / d) < 2^32, m d lies in
+// [2^(31+l), 2^(31+l) + 2^l], so floor(n / d) = floor(n m / 2^(31+l)).  A
+// hardware-less integer division costs about 25 instructions; this costs 3.
+struct FastDiv {
+  unsigned m;
+  int s;  // 31 + l
+};
+inline FastDiv make_fastdiv(int d) {
+  int l = 0;
+  while ((1ull << l) < (unsigned long long)d) ++l;
+  FastDiv f;
+  f.s = 31 + l;
+  f.m = unsigned(((1ull << f.s) + (unsigned long long)d - 1) / (unsigned long long)d);
+  return f;
+}
+__host__ __device__ __forceinline__ int fdiv(int n, FastDiv f) {
+  return int((unsigned long long)unsigned(n) * f.m >> f.s);
+}
+
 struct FMesh {
   int ncell[3];
   int periodic;    // bit a: axis a is periodic
   const double *h[3], *bvol[3], *bnode[3], *kappa, *w;
+  const double *ih[3];             // 1 / h per axis
+  FastDiv fd_n1, fd_n2;            // by ncell[0], ncell[1]
+  FastDiv fd_tile, fd_tz, fd_tzl;  // by N1 N2 tz, tz, and the depth of the last tile
   const double *bf[9], *bfn[9];  // product-form factors (BP instantiations)
   const double *kf[3], *kfn[3];  // polynomial diffusion factor (KP instantiations)
   double K[9], c, sigma;
@@ -95,14 +119,11 @@ struct FMesh {
 };
 
 // The stage update of n consecutive outputs y[off..off+n) of one cell, from
-// their values Av of A x.  |T| is the product of the cell's three spacings.
+// their values Av of A x; dv = dt / |T|, |T| the product of the cell's three
+// spacings.
 template <int n, typename T>
-__device__ __forceinline__ void heun_store(const FMesh &M, int cell, size_t off, const T *__restrict__ x,
+__device__ __forceinline__ void heun_store(const FMesh &M, double dv, size_t off, const T *__restrict__ x,
                                            T *__restrict__ y, const T *Av) {
-  const int i0 = cell % M.ncell[0];
-  const int i1 = (cell / M.ncell[0]) % M.ncell[1];
-  const int i2 = cell / (M.ncell[0] * M.ncell[1]);
-  const double dv = M.ts_dt / (M.h[0][i0] * M.h[1][i1] * M.h[2][i2]);
 #pragma unroll
   for (int t = 0; t < n; ++t) {
     const double r = (M.ts_f ? M.ts_f[off + t] : 0.0) - double(Av[t]);
@@ -136,10 +157,13 @@ struct FCfg {
   static constexpr int LANES = NN;
   // cells per workgroup: one 64-lane wave holds 64 / N^2 cells, which
   // leaves 22 % (N = 5), 44 % (N = 6), 23 % (N = 7) and 37 % (N = 9, two
-  // waves per cell) of the lanes idle; larger workgroups pack 10, 7, 5 and 3
-  // cells into 256 lanes (98, 98, 96 and 95 % busy) while two workgroups
-  // (one for N = 9) still fit in the 160 KB of LDS of a CU
-  static constexpr int CPB = (N == 5) ? 10 : (N == 6) ? 7 : (N == 7) ? 5 : (N == 9) ? 3 : (NN <= 64 ? 64 / NN : 1);
+  // waves per cell) of the lanes idle; larger workgroups pack 5 cells into
+  // 128 lanes (N = 5) and 7, 5 and 3 cells into 256 lanes (N = 6, 7, 9;
+  // 95-98 % busy) while two workgroups (five at N = 5) still fit in the
+  // 160 KB of LDS of a CU.  At N = 5 the two-wave workgroup was 8-19 %
+  // faster than 10 cells in 256 lanes (fewer waves per barrier); at N = 6, 7
+  // the two-wave workgroups (3 and 2 cells) idle too many lanes and were slower
+  static constexpr int CPB = (N == 5) ? 5 : (N == 6) ? 7 : (N == 7) ? 5 : (N == 9) ? 3 : (NN <= 64 ? 64 / NN : 1);
   static constexpr int THREADS = ((CPB * LANES + 63) / 64) * 64;
   // register budget: two waves per SIMD at every N.  At N >= 9 this caps the
   // kernel at 256 VGPRs and spills 28-404 bytes per lane, and is still
@@ -296,6 +320,7 @@ __device__ __forceinline__ void gmodT(cptr g, const T *in, T *out) {
 
 struct FaceGeo {
   double h0, h1, h2;
+  double ih0, ih1, ih2;  // 1 / h (kernels that carry them, see face_coef)
   double kap;
   int i0, i1, i2;
 };
@@ -320,6 +345,11 @@ struct FC {
   double cTa, cTb, cTc, cNa, cNb, cNc, gamma, sgn;
 };
 
+// IHG: G carries the reciprocal spacings (loaded once per cell); otherwise
+// they are read from the tables where used, which keeps three fewer doubles
+// live through the kernel (measured better for N >= 9, where it spills, and
+// worse below).
+template <bool IHG>
 __device__ __forceinline__ FC face_coef(const FMesh &M, const FaceGeo &G, int cell, int a, int e) {
   const int b = (a == 0) ? 1 : 0, c = (a == 2) ? 1 : 2;
   const int ia = seli3(a, G.i0, G.i1, G.i2);
@@ -328,11 +358,11 @@ __device__ __forceinline__ FC face_coef(const FMesh &M, const FaceGeo &G, int ce
   const FaceNb nb = face_nb(cell, ia, na, cst, (M.periodic >> a) & 1, e);
   const bool in = nb.in;
   const int ncl = nb.cell;
-  const double *ha_tab = a == 0 ? M.h[0] : (a == 1 ? M.h[1] : M.h[2]);
-  const double ha = sel3(a, G.h0, G.h1, G.h2);
-  const double hb = sel3(b, G.h0, G.h1, G.h2);
-  const double hc = sel3(c, G.h0, G.h1, G.h2);
-  const double hn = in ? ha_tab[nb.ja] : ha;
+  const double *iha_tab = a == 0 ? M.ih[0] : (a == 1 ? M.ih[1] : M.ih[2]);
+  const double iha = IHG ? sel3(a, G.ih0, G.ih1, G.ih2) : iha_tab[ia];
+  const double ihb = IHG ? sel3(b, G.ih0, G.ih1, G.ih2) : (b == 0 ? M.ih[0][G.i0] : M.ih[1][G.i1]);
+  const double ihc = IHG ? sel3(c, G.ih0, G.ih1, G.ih2) : (c == 1 ? M.ih[1][G.i1] : M.ih[2][G.i2]);
+  const double ihn = in ? iha_tab[nb.ja] : iha;
   const double kn = in ? (M.kappa ? M.kappa[ncl] : 1.0) : 0.0;
   const double Kaa = sel3(a, M.K[0], M.K[4], M.K[8]);
   const double Kab = a == 0 ? M.K[1] : (a == 1 ? M.K[3] : M.K[6]);  // K[a][b]
@@ -340,16 +370,18 @@ __device__ __forceinline__ FC face_coef(const FMesh &M, const FaceGeo &G, int ce
   const double dT = G.kap * Kaa, dN = kn * Kaa;
   FC F;
   F.sgn = e ? 1.0 : -1.0;
-  const double wT = in ? dN / (dT + dN) : 1.0;
-  const double wN = in ? dT / (dT + dN) : 0.0;
-  F.gamma = in ? M.sigma * (2.0 * dT * dN / (dT + dN)) / fmin(ha, hn) : M.sigma * dT / ha;
+  // the one division; 1 / min(h_T, h_N) = max(1 / h_T, 1 / h_N)
+  const double rs = 1.0 / (dT + dN);
+  const double wT = in ? dN * rs : 1.0;
+  const double wN = in ? dT * rs : 0.0;
+  F.gamma = in ? M.sigma * (2.0 * dT * dN * rs) * fmax(iha, ihn) : M.sigma * dT * iha;
   const double sT = F.sgn * wT * G.kap, sN = F.sgn * wN * kn;
-  F.cTa = sT * Kaa / ha;
-  F.cTb = sT * Kab / hb;
-  F.cTc = sT * Kac / hc;
-  F.cNa = in ? sN * Kaa / hn : 0.0;
-  F.cNb = sN * Kab / hb;
-  F.cNc = sN * Kac / hc;
+  F.cTa = sT * Kaa * iha;
+  F.cTb = sT * Kab * ihb;
+  F.cTc = sT * Kac * ihc;
+  F.cNa = in ? sN * Kaa * ihn : 0.0;
+  F.cNb = sN * Kab * ihb;
+  F.cNc = sN * Kac * ihc;
   return F;
 }
 
@@ -444,17 +476,21 @@ __device__ __forceinline__ double face_b(const FMesh &M, const FaceGeo &G, int N
   return bv[seli3(c, G.i0, G.i1, G.i2) * N + qc];
 }
 
-__device__ __forceinline__ int cell_of_logical(int L, const FMesh &M) {
+// Cell of processing position L: tiles of tz cells along axis 3 (fewer in
+// the last tile), z fastest inside a tile, then axis 1, then axis 2.  Sets
+// the cell's indices along the three axes.
+__device__ __forceinline__ int cell_of_logical(int L, const FMesh &M, int &i0, int &i1, int &i2) {
   const int N1 = M.ncell[0], N2 = M.ncell[1], N3 = M.ncell[2];
-  const int plane = N1 * N2;
-  const int t = L / (plane * M.tz);
-  const int r = L - t * plane * M.tz;
+  const int t = fdiv(L, M.fd_tile);
+  const int r = L - t * (N1 * N2 * M.tz);
   const int z0 = t * M.tz;
-  const int tzt = min(M.tz, N3 - z0);
-  const int i3 = z0 + r % tzt;
-  const int rr = r / tzt;
-  const int i1 = rr % N1, i2 = rr / N1;
-  return i1 + N1 * (i2 + N2 * i3);
+  const bool full = N3 - z0 >= M.tz;
+  const int tzt = full ? M.tz : N3 - z0;
+  const int rr = fdiv(r, full ? M.fd_tz : M.fd_tzl);
+  i2 = z0 + (r - rr * tzt);
+  i1 = fdiv(rr, M.fd_n1);
+  i0 = rr - i1 * N1;
+  return i0 + N1 * (i1 + N2 * i2);
 }
 
 template <int N, typename T, bool HEUN, bool BP, bool KP, int NI = N>
@@ -478,24 +514,29 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
   const int lblock = (wg & 7) * M.groups + (wg >> 3);
   const int L = lblock * C::CPB + (slot ? cl : 0);
   const bool active = slot && L < M.ncells;
-  const int cell = active ? cell_of_logical(L, M) : 0;
+  FaceGeo G;
+  int cell = 0;
+  G.i0 = G.i1 = G.i2 = 0;
+  if (active) cell = cell_of_logical(L, M, G.i0, G.i1, G.i2);
   T *R = lds + (slot ? cl : 0) * C::EXCH;
   double *RFC = fcs + (slot ? cl : 0) * 6 * C::FCW;  // per-cell face constants
   const CT<N, T> tab0{0};
 
-  FaceGeo G;
-  G.i0 = cell % M.ncell[0];
-  G.i1 = (cell / M.ncell[0]) % M.ncell[1];
-  G.i2 = cell / (M.ncell[0] * M.ncell[1]);
+  constexpr bool IHG = N <= 8;  // carry 1 / h in G (see face_coef)
   G.h0 = M.h[0][G.i0];
   G.h1 = M.h[1][G.i1];
   G.h2 = M.h[2][G.i2];
+  if (IHG) {
+    G.ih0 = M.ih[0][G.i0];
+    G.ih1 = M.ih[1][G.i1];
+    G.ih2 = M.ih[2][G.i2];
+  }
   G.kap = M.kappa ? M.kappa[cell] : 1.0;
 
   // face constants of the six faces f = 2a + e
   if (slot)
     for (int f = p; f < 6; f += C::LANES) {
-      const FC F = face_coef(M, G, cell, f >> 1, f & 1);
+      const FC F = face_coef<IHG>(M, G, cell, f >> 1, f & 1);
       RFC[8 * f + 0] = F.cTa;
       RFC[8 * f + 1] = F.cTb;
       RFC[8 * f + 2] = F.cTc;
@@ -763,7 +804,7 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
     const cptr V = tb + TO::V, D = tb + TO::D, Wt = tb + TO::W;
     const double vol = G.h0 * G.h1 * G.h2;
     const T wab = T(M.w[alpha] * M.w[beta] * vol);
-    const double ihd[3] = {1.0 / G.h0, 1.0 / G.h1, 1.0 / G.h2};
+    const double ihd[3] = {IHG ? G.ih0 : M.ih[0][G.i0], IHG ? G.ih1 : M.ih[1][G.i1], IHG ? G.ih2 : M.ih[2][G.i2]};
     const T ih0 = T(ihd[0]), ih1 = T(ihd[1]), ih2 = T(ihd[2]);
     const T cc = T(M.c);
     // Kh[r][s] = kappa K_rs / (h_r h_s): D acting on reference derivatives
@@ -1140,7 +1181,8 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
     tr_acc<N, T, NI>(tb + TO::E1, tb + TO::F1, rv1, rv0, rd1, rd0, Yv);
     const size_t off = size_t(cell) * NIII + NI * NI * beta + NI * alpha;
     if (HEUN) {
-      heun_store<NI>(M, cell, off, x, y, Yv);
+      const double ivol = IHG ? G.ih0 * G.ih1 * G.ih2 : M.ih[0][G.i0] * M.ih[1][G.i1] * M.ih[2][G.i2];
+      heun_store<NI>(M, M.ts_dt * ivol, off, x, y, Yv);
     } else {
 #pragma unroll
       for (int t = 0; t < NI; ++t) y[off + t] = Yv[t];
@@ -1188,12 +1230,18 @@ __global__ __launch_bounds__(256) void apply_lane_kernel(const T *__restrict__ x
   const int cell = lblock * 256 + int(threadIdx.x);
   if (cell >= M.ncells) return;
   FaceGeo G;
-  G.i0 = cell % M.ncell[0];
-  G.i1 = (cell / M.ncell[0]) % M.ncell[1];
-  G.i2 = cell / (M.ncell[0] * M.ncell[1]);
+  {
+    const int r = fdiv(cell, M.fd_n1);
+    G.i0 = cell - r * M.ncell[0];
+    G.i2 = fdiv(r, M.fd_n2);
+    G.i1 = r - G.i2 * M.ncell[1];
+  }
   G.h0 = M.h[0][G.i0];
   G.h1 = M.h[1][G.i1];
   G.h2 = M.h[2][G.i2];
+  G.ih0 = M.ih[0][G.i0];
+  G.ih1 = M.ih[1][G.i1];
+  G.ih2 = M.ih[2][G.i2];
   G.kap = M.kappa ? M.kappa[cell] : 1.0;
   T X[NNN], Y[NNN];
   {
@@ -1207,7 +1255,7 @@ __global__ __launch_bounds__(256) void apply_lane_kernel(const T *__restrict__ x
   // ---- volume (Alg. 1 steps 1-3) ----
   {
     const double vol = G.h0 * G.h1 * G.h2;
-    const double ihd[3] = {1.0 / G.h0, 1.0 / G.h1, 1.0 / G.h2};
+    const double ihd[3] = {G.ih0, G.ih1, G.ih2};
     const int ic[3] = {G.i0, G.i1, G.i2};
     T Kh[9];
 #pragma unroll
@@ -1283,7 +1331,7 @@ __global__ __launch_bounds__(256) void apply_lane_kernel(const T *__restrict__ x
   for (int f = 0; f < 6; ++f) {
     const int a = f >> 1, e = f & 1;
     const int b = (a == 0) ? 1 : 0, c = (a == 2) ? 1 : 2;
-    const FC F = face_coef(M, G, cell, a, e);
+    const FC F = face_coef<true>(M, G, cell, a, e);
     const int ia = a == 0 ? G.i0 : (a == 1 ? G.i1 : G.i2);
     const int cst = (a == 0) ? 1 : (a == 1) ? M.ncell[0] : M.ncell[0] * M.ncell[1];
     const FaceNb nb = face_nb(cell, ia, M.ncell[a], cst, (M.periodic >> a) & 1, e);
@@ -1379,7 +1427,7 @@ __global__ __launch_bounds__(256) void apply_lane_kernel(const T *__restrict__ x
     for (int j = 0; j < NNN; ++j) asm volatile("" : "+v"(Y[j]));
   }
   if (HEUN) {
-    heun_store<NNN>(M, cell, size_t(cell) * NNN, x, y, Y);
+    heun_store<NNN>(M, M.ts_dt * (G.ih0 * G.ih1 * G.ih2), size_t(cell) * NNN, x, y, Y);
   } else {
     T *yp = y + size_t(cell) * NNN;
 #pragma unroll
@@ -1395,6 +1443,7 @@ static hipError_t launch_fused_n(const dg_handle *h, const T *x, T *y, hipStream
   for (int a = 0; a < 3; ++a) {
     M.ncell[a] = h->mesh.ncell[a];
     M.h[a] = h->mesh.h[a];
+    M.ih[a] = h->mesh.ih[a];
     M.bvol[a] = h->mesh.bvol[a];
     M.bnode[a] = h->mesh.bnode[a];
     M.b_axis[a] = h->mesh.b_axis[a];
@@ -1417,6 +1466,15 @@ static hipError_t launch_fused_n(const dg_handle *h, const T *x, T *y, hipStream
   // tiles of up to 4 cells along axis 3: z neighbours are adjacent in the
   // processing order, y neighbours 4*N1 cells apart
   M.tz = h->mesh.ncell[2] < 4 ? h->mesh.ncell[2] : 4;
+  {
+    const int n1 = h->mesh.ncell[0], n2 = h->mesh.ncell[1], n3 = h->mesh.ncell[2];
+    const int last = n3 - ((n3 - 1) / M.tz) * M.tz;  // depth of the last tile, 1..tz
+    M.fd_n1 = make_fastdiv(n1);
+    M.fd_n2 = make_fastdiv(n2);
+    M.fd_tile = make_fastdiv(n1 * n2 * M.tz);
+    M.fd_tz = make_fastdiv(M.tz);
+    M.fd_tzl = make_fastdiv(last);
+  }
   M.ts_f = f;
   M.ts_dt = dt;
   M.ts_stage = stage;
