@@ -504,6 +504,13 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
   constexpr int H2 = N / 2;
   __shared__ T lds[C::CPB * C::EXCH];
   __shared__ double fcs[C::CPB * 6 * C::FCW];  // face constants stay FP64
+  // axis-3 factors of b (and of the diffusion factor) at the cell's Gauss
+  // points, staged in LDS (PWS) or read from the tables at every point.
+  // Staging measured 3-6 % faster at N = 6, 7, 9..11 and 2-7 % slower at
+  // N = 3, 4, 8.
+  constexpr bool PWS = !(N == 3 || N == 4 || N == 8);
+  constexpr int PWN = PWS ? (KP ? 4 : 3) * N : 1;
+  __shared__ double pwc[C::CPB * PWN];
 
   const int tid = threadIdx.x;
   const int cl = tid / C::LANES;
@@ -520,6 +527,7 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
   if (active) cell = cell_of_logical(L, M, G.i0, G.i1, G.i2);
   T *R = lds + (slot ? cl : 0) * C::EXCH;
   double *RFC = fcs + (slot ? cl : 0) * 6 * C::FCW;  // per-cell face constants
+  double *PW = pwc + (slot ? cl : 0) * PWN;
   const CT<N, T> tab0{0};
 
   constexpr bool IHG = N <= 8;  // carry 1 / h in G (see face_coef)
@@ -533,6 +541,35 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
   }
   G.kap = M.kappa ? M.kappa[cell] : 1.0;
 
+  // The prologue's global loads, all issued before any of them is used: the
+  // cell's x pencil along axis 1 and, for each face, the neighbour's pencil
+  // along the face normal (a boundary face loads the cell's own pencil, a
+  // valid address, and uses zeros).  Lanes (j2, j3) with a mode >= NI hold a
+  // zero pencil (indices clamped).  Issued face by face with a use in
+  // between, the loads cost one memory round trip each.
+  const bool lin = alpha < NI && beta < NI;
+  T X[N], NV[6][N];
+  bool fin[6];
+  {
+    const int al = min(alpha, NI - 1), be = min(beta, NI - 1);
+    const T *xp = x + size_t(cell) * NIII + NI * NI * be + NI * al;
+#pragma unroll
+    for (int t = 0; t < N; ++t) X[t] = (t < NI && lin) ? xp[t < NI ? t : 0] : T(0);
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      const int a = f >> 1, e = f & 1;
+      const int ia = a == 0 ? G.i0 : (a == 1 ? G.i1 : G.i2);
+      const int cst = (a == 0) ? 1 : (a == 1) ? M.ncell[0] : M.ncell[0] * M.ncell[1];
+      const FaceNb nb = face_nb(cell, ia, M.ncell[a], cst, (M.periodic >> a) & 1, e);
+      fin[f] = nb.in;
+      const T *xn = x + size_t(nb.cell) * NIII;
+      const int base = (a == 0) ? (NI * al + NI * NI * be) : (a == 1) ? (al + NI * NI * be) : (al + NI * be);
+      const int st = (a == 0) ? 1 : (a == 1) ? NI : NI * NI;
+#pragma unroll
+      for (int t = 0; t < N; ++t) NV[f][t] = (t < NI && lin) ? xn[base + st * (t < NI ? t : 0)] : T(0);
+    }
+  }
+
   // face constants of the six faces f = 2a + e
   if (slot)
     for (int f = p; f < 6; f += C::LANES) {
@@ -545,6 +582,22 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
       RFC[8 * f + 5] = F.cNc;
       RFC[8 * f + 6] = F.gamma;
       RFC[8 * f + 7] = F.sgn;
+    }
+  // The volume flux reads, at every point, the axis-3 factor of each b_r that
+  // varies along axis 3 (and of the diffusion factor): with PWS staged in
+  // LDS here, where their load latency overlaps the loads above, instead of
+  // one dependent global load per point in the volume loop.
+  if (PWS && slot)
+    for (int i = p; i < PWN; i += C::LANES) {
+      const int r = i / N, q = i - r * N;
+      double v;
+      if (r == 3)
+        v = M.kf[2][G.i2 * N + q];
+      else if (BP)
+        v = bfac(M.bf, r, 2)[G.i2 * N + q];
+      else
+        v = M.b_axis[r] == 2 ? M.bvol[r][G.i2 * N + q] : 0.0;
+      PW[i] = v;
     }
 
   // ------------------------------------------------------------------------
@@ -562,12 +615,6 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
   const int w1 = beta * PS + alpha;
   {
     const cptr tb = fresh(tab0);
-    T X[N];
-    // lanes (j2, j3) with a mode >= NI hold a zero pencil (index clamped)
-    const bool lin = alpha < NI && beta < NI;
-    const T *xp = x + size_t(cell) * NIII + NI * NI * min(beta, NI - 1) + NI * min(alpha, NI - 1);
-#pragma unroll
-    for (int t = 0; t < N; ++t) X[t] = (t < NI && lin) ? xp[t < NI ? t : 0] : T(0);
     T Tv[N], Td[N];
     eo_mv<N, false, T, NI>(tb + TO::V, X, Tv);
     eo_mv<N, true, T, NI>(tb + TO::D, X, Td);
@@ -590,24 +637,9 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
   for (int f = 0; f < 6; ++f) {
     const int a = f >> 1, e = f & 1;
     const cptr tb = fresh(tab0);
-    const int ia = a == 0 ? G.i0 : (a == 1 ? G.i1 : G.i2);
-    const int cst = (a == 0) ? 1 : (a == 1) ? M.ncell[0] : M.ncell[0] * M.ncell[1];
-    const FaceNb nb = face_nb(cell, ia, M.ncell[a], cst, (M.periodic >> a) & 1, e);
-    const bool in = nb.in;
     T v[N];
-    if (in) {
-      const T *xn = x + size_t(nb.cell) * NIII;
-      const int al = min(alpha, NI - 1), be = min(beta, NI - 1);
-      const int base = (a == 0) ? (NI * al + NI * NI * be)
-                       : (a == 1) ? (al + NI * NI * be) : (al + NI * be);
-      const int st = (a == 0) ? 1 : (a == 1) ? NI : NI * NI;
-      const bool lin = alpha < NI && beta < NI;
 #pragma unroll
-      for (int t = 0; t < N; ++t) v[t] = (t < NI && lin) ? xn[base + st * (t < NI ? t : 0)] : T(0);
-    } else {
-#pragma unroll
-      for (int t = 0; t < N; ++t) v[t] = T(0);
-    }
+    for (int t = 0; t < N; ++t) v[t] = fin[f] ? NV[f][t] : T(0);
     // neighbour trace at its reference coordinate 1 - e
     T u1, u0, d1, d0;
     tr_val<N, T, NI>(tb + TO::E1, v, u1, u0);
@@ -813,37 +845,43 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
     for (int r = 0; r < 3; ++r)
 #pragma unroll
       for (int s2 = 0; s2 < 3; ++s2) Kh[3 * r + s2] = T(G.kap * M.K[3 * r + s2] * ihd[r] * ihd[s2]);
-    // b_r / h_r: per-lane constant unless b_r varies along axis 3
+    // b_r / h_r: per-lane constant unless b_r varies along axis 3 (then its
+    // values per point come from PW or the tables)
     T bh[3];
-    const double *bzt[3];
     bool bz[3];
-    // product form: b_r / h_r = (f_r0(q1) f_r1(q2) / h_r) f_r2(q3), a lane factor
-    // times a value of the axis-3 tables (scalar bases, one lane offset o2)
     const int o2 = G.i2 * N;
+    // the axis-3 factor of b_r (r < 3) or of the diffusion factor (r = 3) at point q3
+    auto f3 = [&](int r, int q3) -> T {
+      if constexpr (PWS) return T(PW[r * N + q3]);
+      if (r == 3) return T(M.kf[2][o2 + q3]);
+      if (BP) return T(M.bf[3 * r + 2][o2 + q3]);
+      return T(M.bvol[r][o2 + q3]);
+    };
+    // product form: b_r / h_r = (f_r0(q1) f_r1(q2) / h_r) f_r2(q3), a lane factor
+    // times the axis-3 factor in PW
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
       if (BP) {
         bz[r] = true;
         bh[r] = T(bfac(M.bf, r, 0)[G.i0 * N + alpha] * bfac(M.bf, r, 1)[G.i1 * N + beta] * ihd[r]);
-        bzt[r] = nullptr;
         continue;
       }
       const int ax = M.b_axis[r];
       bz[r] = (ax == 2);
       const int ia = ax == 0 ? G.i0 : (ax == 1 ? G.i1 : G.i2);
       const int qa = (ax == 0) ? alpha : beta;
-      bh[r] = bz[r] ? T(0) : T(M.bvol[r][ia * N + qa] * ihd[r]);
-      bzt[r] = M.bvol[r] + G.i2 * N;
+      const double bv = M.bvol[r][ia * N + qa];  // a valid entry whatever bz (issued unconditionally)
+      bh[r] = bz[r] ? T(0) : T(bv * ihd[r]);
     }
     // polynomial diffusion factor kp(q1, q2, q3) = (lane factor) * kf_2(q3)
     const T kpl = KP ? T(M.kf[0][G.i0 * N + alpha] * M.kf[1][G.i1 * N + beta]) : T(1);
     auto flux = [&](T u, T g0, T g1, T g2, int q3, T W, T &x0, T &x1, T &x2, T &x3) {
-      const T b0 = BP ? bh[0] * T(M.bf[2][o2 + q3]) : (bz[0] ? T(bzt[0][q3]) * ih0 : bh[0]);
-      const T b1 = BP ? bh[1] * T(M.bf[5][o2 + q3]) : (bz[1] ? T(bzt[1][q3]) * ih1 : bh[1]);
-      const T b2 = BP ? bh[2] * T(M.bf[8][o2 + q3]) : (bz[2] ? T(bzt[2][q3]) * ih2 : bh[2]);
+      const T b0 = BP ? bh[0] * f3(0, q3) : (bz[0] ? f3(0, q3) * ih0 : bh[0]);
+      const T b1 = BP ? bh[1] * f3(1, q3) : (bz[1] ? f3(1, q3) * ih1 : bh[1]);
+      const T b2 = BP ? bh[2] * f3(2, q3) : (bz[2] ? f3(2, q3) * ih2 : bh[2]);
       x0 = W * cc * u;
       if constexpr (KP) {
-        const T kq = kpl * T(M.kf[2][o2 + q3]);
+        const T kq = kpl * f3(3, q3);
         x1 = W * (kq * (Kh[0] * g0 + Kh[1] * g1 + Kh[2] * g2) - b0 * u);
         x2 = W * (kq * (Kh[3] * g0 + Kh[4] * g1 + Kh[5] * g2) - b1 * u);
         x3 = W * (kq * (Kh[6] * g0 + Kh[7] * g1 + Kh[8] * g2) - b2 * u);
