@@ -96,6 +96,19 @@ __host__ __device__ __forceinline__ int fdiv(int n, FastDiv f) {
   return int((unsigned long long)unsigned(n) * f.m >> f.s);
 }
 
+// A value known to be equal on every lane of the wave, moved to scalar
+// registers (the compiler then keeps it there and loads through it with
+// scalar loads).
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double wave_uniform(double v) {
+  const unsigned long long b = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readfirstlane(unsigned(b)), hi = __builtin_amdgcn_readfirstlane(unsigned(b >> 32));
+  return __longlong_as_double((long long)((unsigned long long)hi << 32 | lo));
+}
+__device__ __forceinline__ float wave_uniform(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
 struct FMesh {
   int ncell[3];
   int periodic;    // bit a: axis a is periodic
@@ -525,6 +538,18 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
   int cell = 0;
   G.i0 = G.i1 = G.i2 = 0;
   if (active) cell = cell_of_logical(L, M, G.i0, G.i1, G.i2);
+  // One cell per workgroup (N = 8, 10, 11: a wave holds lanes of one cell
+  // only): the cell and every per-cell constant derived from it are wave-
+  // uniform, kept in scalar registers (fewer VGPRs where the kernel spills).
+  // Lanes past the cell's pencil slots take the cell's values too; they
+  // neither store nor write LDS.
+  constexpr bool UNI = C::CPB == 1;
+  if (UNI) {
+    cell = wave_uniform(cell);
+    G.i0 = wave_uniform(G.i0);
+    G.i1 = wave_uniform(G.i1);
+    G.i2 = wave_uniform(G.i2);
+  }
   T *R = lds + (slot ? cl : 0) * C::EXCH;
   double *RFC = fcs + (slot ? cl : 0) * 6 * C::FCW;  // per-cell face constants
   double *PW = pwc + (slot ? cl : 0) * PWN;
@@ -844,7 +869,10 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_k
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
-      for (int s2 = 0; s2 < 3; ++s2) Kh[3 * r + s2] = T(G.kap * M.K[3 * r + s2] * ihd[r] * ihd[s2]);
+      for (int s2 = 0; s2 < 3; ++s2) {
+        Kh[3 * r + s2] = T(G.kap * M.K[3 * r + s2] * ihd[r] * ihd[s2]);
+        if (UNI) Kh[3 * r + s2] = wave_uniform(Kh[3 * r + s2]);
+      }
     // b_r / h_r: per-lane constant unless b_r varies along axis 3 (then its
     // values per point come from PW or the tables)
     T bh[3];
