@@ -183,6 +183,10 @@ struct FCfg {
   // 1.04-1.62x faster than one wave per SIMD without spills (the kernel is
   // bound by latency, which the second wave hides)
   static constexpr int WAVES_PER_SIMD = 2;
+  // N = 5 without the diffusion factor: three waves per SIMD (168 VGPRs, a
+  // 92-byte spill) measured 4.5 % faster; with it the spill grows and the
+  // kernel was 38 % slower
+  static constexpr int waves(bool kp) { return (N == 5 && !kp) ? 3 : WAVES_PER_SIMD; }
   static constexpr int FCW = 8;  // doubles per face-constant record
   // per-cell LDS (doubles) of each exchange round
   static constexpr int mx(int a, int b) { return a > b ? a : b; }
@@ -508,7 +512,7 @@ __device__ __forceinline__ int cell_of_logical(int L, const FMesh &M, int &i0, i
 
 template <int N, typename T, bool HEUN, bool BP, bool KP, int NI = N>
 __global__ __launch_bounds__(FCfg<N>::THREADS)
-__attribute__((amdgpu_waves_per_eu(FCfg<N>::WAVES_PER_SIMD))) void apply_fused_kernel(
+__attribute__((amdgpu_waves_per_eu(FCfg<N>::waves(KP)))) void apply_fused_kernel(
     const T *__restrict__ x, T *__restrict__ y, FMesh M) {
   using C = FCfg<N>;
   using TO = TabOff<N>;
