@@ -45,6 +45,7 @@
 
 #include "dg_internal.h"
 #include "mesh_nb.h"
+#include "fastdiv.h"
 #include "gl_tables.inc"
 
 namespace dgmf {
@@ -74,27 +75,6 @@ struct TabOff {
   static constexpr int G = W + H;
   static constexpr int SIZE = G + N;
 };
-
-// Division by a divisor d >= 1 fixed for the launch, for 0 <= n < 2^31, by a
-// multiply and a shift (Granlund and Montgomery, PLDI 1994, Thm. 4.2): with
-// l = ceil(log2 d) and m = ceil(2^(31+l) / d) < 2^32, m d lies in
-// [2^(31+l), 2^(31+l) + 2^l], so floor(n / d) = floor(n m / 2^(31+l)).  A
-// hardware-less integer division costs about 25 instructions; this costs 3.
-struct FastDiv {
-  unsigned m;
-  int s;  // 31 + l
-};
-inline FastDiv make_fastdiv(int d) {
-  int l = 0;
-  while ((1ull << l) < (unsigned long long)d) ++l;
-  FastDiv f;
-  f.s = 31 + l;
-  f.m = unsigned(((1ull << f.s) + (unsigned long long)d - 1) / (unsigned long long)d);
-  return f;
-}
-__host__ __device__ __forceinline__ int fdiv(int n, FastDiv f) {
-  return int((unsigned long long)unsigned(n) * f.m >> f.s);
-}
 
 // A value known to be equal on every lane of the wave, moved to scalar
 // registers (the compiler then keeps it there and loads through it with
