@@ -31,31 +31,9 @@
 // |F| and |T| in gamma_F come from per-face and per-cell tables.
 #include "dg_internal.h"
 #include "mesh_nb.h"
+#include "ref_geo.h"
 
 namespace dgmf {
-
-template <int N, int Q>
-struct RefTab {
-  double V[Q][N], D[Q][N], w[Q], xi[Q], ev[2][N], ed[2][N];
-};
-
-struct RefMesh {
-  int ncell[3];
-  int periodic;  // bit a: axis a is periodic
-  const double *h[3], *bvol[3], *bnode[3], *kappa;
-  const double *bf[9], *bfn[9];  // product-form factors (bprod)
-  const double *kf[3], *kfn[3];  // polynomial diffusion factor (kpoly)
-  double K[9], c, sigma;
-  int b_axis[3];
-  int bprod, kpoly;
-  int ncells;
-  // multilinear meshes (GEO kernels): vertex coordinates (N1+1)(N2+1)(N3+1) x 3,
-  // |T| per cell, |F| per face normal to axis a indexed (i_a + e) + (N_a + 1)
-  // (i_b + N_b i_c) (b < c the tangential axes); b and kp as formulas of the
-  // physical point
-  const double *verts, *cvol, *farea[3];
-  double b_const[3], b_sin[3], b_amp[3], b_freq[9], b_phase[9], kpc[9];
-};
 
 constexpr int kRefThreads = 256;
 
@@ -144,89 +122,12 @@ __device__ inline void contract(int lt, double *out, const double *in, const dou
   }
 }
 
-__device__ __forceinline__ int sel3i(int a, int v0, int v1, int v2) { return a == 0 ? v0 : (a == 1 ? v1 : v2); }
-__device__ __forceinline__ double sel3d(int a, double v0, double v1, double v2) {
-  return a == 0 ? v0 : (a == 1 ? v1 : v2);
-}
-// Entry i of a kernel-argument pointer array by a select chain (a runtime
-// index into the argument struct would copy it to scratch).
-template <int L>
-__device__ __forceinline__ const double *pickp(const double *const *t, int i) {
-  const double *p = t[0];
-#pragma unroll
-  for (int s = 1; s < L; ++s)
-    if (i == s) p = t[s];
-  return p;
-}
-
-// ---- multilinear geometry --------------------------------------------------
-
-constexpr int kVB = 4;  // vertex block 4 x 4 x 4 around a cell: planes i-1 .. i+2
-
-// The trilinear map of the cell whose first vertex is block vertex
-// (o0, o1, o2), at reference point (s0, s1, s2): point X and Jacobian
-// J[3r + t] = d X_r / d s_t, by a linear contraction along each direction.
-__device__ inline void tri_map(const double *VB, int o0, int o1, int o2, double s0, double s1, double s2, double *X,
-                               double *J) {
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-    auto v = [&](int c0, int c1, int c2) { return VB[3 * ((o0 + c0) + kVB * ((o1 + c1) + kVB * (o2 + c2))) + r]; };
-    const double v000 = v(0, 0, 0), v100 = v(1, 0, 0), v010 = v(0, 1, 0), v110 = v(1, 1, 0);
-    const double v001 = v(0, 0, 1), v101 = v(1, 0, 1), v011 = v(0, 1, 1), v111 = v(1, 1, 1);
-    const double d00 = v100 - v000, d10 = v110 - v010, d01 = v101 - v001, d11 = v111 - v011;
-    const double a00 = fma(s0, d00, v000), a10 = fma(s0, d10, v010);
-    const double a01 = fma(s0, d01, v001), a11 = fma(s0, d11, v011);
-    const double f0 = a10 - a00, f1 = a11 - a01;
-    const double b0 = fma(s1, f0, a00), b1 = fma(s1, f1, a01);
-    const double e0 = fma(s1, d10 - d00, d00), e1 = fma(s1, d11 - d01, d01);
-    X[r] = fma(s2, b1 - b0, b0);
-    J[3 * r + 0] = fma(s2, e1 - e0, e0);
-    J[3 * r + 1] = fma(s2, f1 - f0, f0);
-    J[3 * r + 2] = b1 - b0;
-  }
-}
-
-// C = cof(J) = det(J) J^{-T} (row-major); returns det J
-__device__ inline double cof3(const double *J, double *C) {
-  C[0] = J[4] * J[8] - J[5] * J[7];
-  C[1] = J[5] * J[6] - J[3] * J[8];
-  C[2] = J[3] * J[7] - J[4] * J[6];
-  C[3] = J[2] * J[7] - J[1] * J[8];
-  C[4] = J[0] * J[8] - J[2] * J[6];
-  C[5] = J[1] * J[6] - J[0] * J[7];
-  C[6] = J[1] * J[5] - J[2] * J[4];
-  C[7] = J[2] * J[3] - J[0] * J[5];
-  C[8] = J[0] * J[4] - J[1] * J[3];
-  return J[0] * C[0] + J[1] * C[1] + J[2] * C[2];
-}
-
-// component r of b at the physical point X (sum form with a sine part, or
-// the product form)
-__device__ inline double geo_b(const RefMesh &M, int r, const double *X) {
-  if (M.bprod) {
-    double v = M.b_amp[r];
-#pragma unroll
-    for (int j = 0; j < 3; ++j)
-      if (M.b_freq[3 * r + j] != 0.0) v *= sin(fma(M.b_freq[3 * r + j], X[j], M.b_phase[3 * r + j]));
-    return v;
-  }
-  const int ax = M.b_axis[r];
-  const double xa = ax == 0 ? X[0] : (ax == 1 ? X[1] : X[2]);
-  return M.b_sin[r] != 0.0 ? fma(M.b_sin[r], sin(M_PI * xa), M.b_const[r]) : M.b_const[r];
-}
-
-// polynomial diffusion factor at the physical point (1 without it)
-__device__ inline double geo_kp(const RefMesh &M, const double *X) {
-  if (!M.kpoly) return 1.0;
-  double v = 1.0;
-#pragma unroll
-  for (int j = 0; j < 3; ++j) v *= M.kpc[3 * j] + M.kpc[3 * j + 1] * X[j] + M.kpc[3 * j + 2] * X[j] * X[j];
-  return v;
-}
-
 // CPB cells per workgroup, kRefThreads / CPB threads and one LDS slice each
 // (CPB = 1 for the (k+1)-point reference variant).
-template <int N, int Q, int CPB, bool GEO>
+// VOL = false (multilinear cells with the volume already in y, from the
+// pencil-layout volume kernel of geo_volume.hip): y is read as the start of the
+// accumulation and only the face terms are added.
+template <int N, int Q, int CPB, bool GEO, bool VOL = true>
 __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__restrict__ x,
                                                                 double *__restrict__ y,
                                                                 RefMesh M, RefTab<N, Q> T) {
@@ -275,6 +176,10 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
   }
   const double *xT = x + size_t(cell) * NB;
   for (int i = lt; i < NB; i += TPC) X[i] = xT[i];
+  if constexpr (!VOL) {
+    const double *yT = y + size_t(cell) * NB;
+    for (int i = lt; i < NB; i += TPC) Y[i] = yT[i];
+  }
   if constexpr (GEO) {
     // vertices (i_a - 1 .. i_a + 2 per axis; zero where outside the vertex grid)
     for (int i = lt; i < VBN; i += TPC) {
@@ -291,6 +196,7 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
   const double kap = M.kappa ? M.kappa[cell] : 1.0;
   const double vol = h[0] * h[1] * h[2];
 
+  if constexpr (VOL) {
   // ---------------- volume: forward (u, d1 u, d2 u, d3 u at points) --------
   contract<N, false, 0, Q, N, N, N, TPC, BK>(lt, B0, X, sV);  // V1 x
   contract<N, false, 0, Q, N, N, N, TPC, BK>(lt, B1, X, sD);  // D1 x
@@ -361,6 +267,7 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
   __syncthreads();
   contract<N, true, 0, N, N, N, Q, TPC, BK>(lt, Y, B0, sV, B1, sD);  // along 1
   __syncthreads();
+  }
 
   // ---------------- faces --------------------------------------------------
   if constexpr (BATCH) {
@@ -695,7 +602,7 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
   }
 }
 
-template <int N, int Q, bool GEO = false>
+template <int N, int Q, bool GEO = false, bool VOL = true>
 static hipError_t launch_ref_n(const dg_handle *h, const double *x, double *y, hipStream_t s) {
   if (h->tabq.m != Q) return hipErrorInvalidValue;
   RefTab<N, Q> T;
@@ -713,46 +620,7 @@ static hipError_t launch_ref_n(const dg_handle *h, const double *x, double *y, h
     T.ed[0][j] = h->tabq.e0d[j];
     T.ed[1][j] = h->tabq.e1d[j];
   }
-  RefMesh M;
-  for (int a = 0; a < 3; ++a) {
-    M.ncell[a] = h->mesh.ncell[a];
-    M.h[a] = h->mesh.h[a];
-    M.bvol[a] = h->mesh.bvol[a];
-    M.bnode[a] = h->mesh.bnode[a];
-    M.b_axis[a] = h->mesh.b_axis[a];
-  }
-  for (int t = 0; t < 9; ++t) {
-    M.bf[t] = h->mesh.bf[t];
-    M.bfn[t] = h->mesh.bfn[t];
-  }
-  M.bprod = h->mesh.bprod;
-  M.kpoly = h->mesh.kpoly;
-  for (int j = 0; j < 3; ++j) {
-    M.kf[j] = h->mesh.kf[j];
-    M.kfn[j] = h->mesh.kfn[j];
-  }
-  M.kappa = h->mesh.kappa;
-  M.periodic = h->mesh.periodic;
-  for (int i = 0; i < 9; ++i) M.K[i] = h->mesh.K[i];
-  M.c = h->mesh.c;
-  M.sigma = h->mesh.sigma;
-  M.ncells = int(h->ncells);
-  M.verts = h->mesh.verts;
-  M.cvol = h->mesh.cvol;
-  for (int a = 0; a < 3; ++a) M.farea[a] = h->mesh.farea[a];
-  for (int r = 0; r < 3; ++r) {
-    M.b_const[r] = h->prob.b_const[r];
-    M.b_sin[r] = h->prob.b_sin[r];
-    M.b_amp[r] = h->prob.b_amp[r];
-  }
-  for (int t = 0; t < 9; ++t) {
-    M.b_freq[t] = h->prob.b_freq[t];
-    M.b_phase[t] = h->prob.b_phase[t];
-    M.kpc[t] = h->prob.kappa_poly[t];
-  }
-  // the per-point path evaluates b from its formula: the problem's own form
-  // (the tables above come in product form whenever kp is present)
-  if (GEO) M.bprod = (h->prob.flags & DG_B_PRODUCT) ? 1 : 0;
+  RefMesh M = make_ref_mesh(h, GEO);
   // raised rule and multilinear cells: as many cells per workgroup as keep
   // its LDS near 80 KB
   constexpr bool BATCH = (Q != N) || GEO;
@@ -761,19 +629,32 @@ static hipError_t launch_ref_n(const dg_handle *h, const double *x, double *y, h
   constexpr int per_cell = 8 * (2 * N * N * N + region + (BATCH ? 16 : 16 * QF_) + (GEO ? 3 * kVB * kVB * kVB : 1));
   constexpr int CPB = !BATCH ? 1 : (8 * per_cell <= 81920 ? 8 : 4 * per_cell <= 81920 ? 4 : 2 * per_cell <= 81920 ? 2 : 1);
   const unsigned grid = unsigned((h->ncells + CPB - 1) / CPB);
-  hipLaunchKernelGGL((apply_ref_kernel<N, Q, CPB, GEO>), dim3(grid), dim3(kRefThreads), 0, s, x, y, M, T);
+  hipLaunchKernelGGL((apply_ref_kernel<N, Q, CPB, GEO, VOL>), dim3(grid), dim3(kRefThreads), 0, s, x, y, M, T);
   return hipGetLastError();
 }
 
 // Multilinear meshes: the (k+1)-point rule, the raised rule (k+3 points) or
-// the rule q = 3p + 4 of Problem C (ceil((3k+5)/2) points), k <= 7.
+// the rule q = 3p + 4 of Problem C (ceil((3k+5)/2) points), k <= 7.  With at
+// most 11 points per direction the volume runs on the pencil-layout kernel
+// of geo_volume.hip (writing y) and this kernel adds the faces (VOL = false);
+// beyond, this kernel does both.
+template <int N, int Q>
+static hipError_t launch_geo_rule(const dg_handle *h, const double *x, double *y, hipStream_t s) {
+  if (geo_volume_supported(h)) {
+    const hipError_t e = launch_geo_volume_f64(h, x, y, s);
+    if (e != hipSuccess) return e;
+    return launch_ref_n<N, Q, true, false>(h, x, y, s);
+  }
+  return launch_ref_n<N, Q, true>(h, x, y, s);
+}
+
 template <int N>
 static hipError_t launch_geo_q(const dg_handle *h, const double *x, double *y, hipStream_t s) {
   constexpr int QC = (3 * (N - 1) + 6) / 2;
-  if (h->tabq.m == N) return launch_ref_n<N, N, true>(h, x, y, s);
-  if (h->tabq.m == N + 2) return launch_ref_n<N, N + 2, true>(h, x, y, s);
+  if (h->tabq.m == N) return launch_geo_rule<N, N>(h, x, y, s);
+  if (h->tabq.m == N + 2) return launch_geo_rule<N, N + 2>(h, x, y, s);
   if constexpr (QC != N + 2) {
-    if (h->tabq.m == QC) return launch_ref_n<N, QC, true>(h, x, y, s);
+    if (h->tabq.m == QC) return launch_geo_rule<N, QC>(h, x, y, s);
   }
   return hipErrorInvalidValue;
 }
