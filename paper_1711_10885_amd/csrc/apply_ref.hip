@@ -124,11 +124,13 @@ __device__ inline void contract(int lt, double *out, const double *in, const dou
 
 // CPB cells per workgroup, kRefThreads / CPB threads and one LDS slice each
 // (CPB = 1 for the (k+1)-point reference variant).
+// Two waves per SIMD: without the cap some instantiations took more than 256
+// registers and ran one wave per SIMD.
 // VOL = false (multilinear cells with the volume already in y, from the
 // pencil-layout volume kernel of geo_volume.hip): y is read as the start of the
 // accumulation and only the face terms are added.
 template <int N, int Q, int CPB, bool GEO, bool VOL = true>
-__global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__restrict__ x,
+__global__ __launch_bounds__(kRefThreads) __attribute__((amdgpu_waves_per_eu(2))) void apply_ref_kernel(const double *__restrict__ x,
                                                                 double *__restrict__ y,
                                                                 RefMesh M, RefTab<N, Q> T) {
   constexpr int NB = N * N * N, NF = N * N, QB = Q * Q * Q, QF = Q * Q;
@@ -348,7 +350,7 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
         const double nv1 = sg * sel3d(a, Co[3], Co[4], Co[5]);
         const double nv2 = sg * sel3d(a, Co[6], Co[7], Co[8]);
         const double nrm = sqrt(nv0 * nv0 + nv1 * nv1 + nv2 * nv2);
-        const double nu[3] = {nv0 / nrm, nv1 / nrm, nv2 / nrm};
+        const double inrm = 1.0 / nrm, nu[3] = {nv0 * inrm, nv1 * inrm, nv2 * inrm};
         double Kn[3];
 #pragma unroll
         for (int r = 0; r < 3; ++r) Kn[r] = M.K[3 * r] * nu[0] + M.K[3 * r + 1] * nu[1] + M.K[3 * r + 2] * nu[2];
@@ -360,7 +362,8 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
 #pragma unroll
         for (int r = 0; r < 3; ++r)
           Kgo += Kn[r] * (Co[3 * r] * gro[0] + Co[3 * r + 1] * gro[1] + Co[3 * r + 2] * gro[2]);
-        Kgo /= deto;
+        const double ideto = 1.0 / deto;
+        Kgo *= ideto;
         const double kpx = geo_kp(M, Xp);
         const double kxo = kap * kpx;
         double kxn = 0.0, Kgn = 0.0;
@@ -379,14 +382,15 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
           kxn = (M.kappa ? M.kappa[nb.cell] : 1.0) * kpx;
         }
         const double dT = kxo * nKn, dN = kxn * nKn;
-        const double wT = interior ? dN / (dT + dN) : 1.0;
-        const double wN = interior ? dT / (dT + dN) : 0.0;
+        const double rs = 1.0 / (dT + dN);
+        const double wT = interior ? dN * rs : 1.0;
+        const double wN = interior ? dT * rs : 0.0;
         const int ia = sel3i(a, ic[0], ic[1], ic[2]), ib = sel3i(b, ic[0], ic[1], ic[2]);
         const int icc = sel3i(c, ic[0], ic[1], ic[2]);
         const int na = sel3i(a, M.ncell[0], M.ncell[1], M.ncell[2]), nbb = sel3i(b, M.ncell[0], M.ncell[1], M.ncell[2]);
         const double area = pickp<3>(M.farea, a)[(ia + e) + size_t(na + 1) * (ib + size_t(nbb) * icc)];
-        const double gamma = interior ? M.sigma * (2.0 * dT * dN / (dT + dN)) * area / fmin(M.cvol[cell], M.cvol[nb.cell])
-                                      : M.sigma * dT * area / M.cvol[cell];
+        const double gamma = M.sigma * dT * area * (interior ? 2.0 * dN * rs : 1.0) /
+                             (interior ? fmin(M.cvol[cell], M.cvol[nb.cell]) : M.cvol[cell]);
         const double avg = wT * kxo * Kgo + wN * kxn * Kgn;
         const double Jmp = uo[i] - un[i];
         const double bout = geo_b(M, 0, Xp) * nu[0] + geo_b(M, 1, Xp) * nu[1] + geo_b(M, 2, Xp) * nu[2];
@@ -394,7 +398,7 @@ __global__ __launch_bounds__(kRefThreads) void apply_ref_kernel(const double *__
         const double W = sw[qb] * sw[qc] * nrm;
         S0[i] = W * (Phi - avg + gamma * Jmp);
         // symmetry term against the reference gradient: t C^T (K nu)
-        const double t = -W * wT * Jmp * kxo / deto;
+        const double t = -W * wT * Jmp * kxo * ideto;
         const double Z0 = t * (Co[0] * Kn[0] + Co[3] * Kn[1] + Co[6] * Kn[2]);
         const double Z1 = t * (Co[1] * Kn[0] + Co[4] * Kn[1] + Co[7] * Kn[2]);
         const double Z2 = t * (Co[2] * Kn[0] + Co[5] * Kn[1] + Co[8] * Kn[2]);

@@ -133,7 +133,8 @@ __device__ inline double cof3(const double *J, double *C) {
 }
 
 // component r of b at the physical point X (sum form with a sine part, or
-// the product form)
+// the product form); sin(pi x) as sinpi(x), whose argument reduction is
+// exact and cheaper than that of sin (4-10 % on the multilinear kernels)
 __device__ inline double geo_b(const RefMesh &M, int r, const double *X) {
   if (M.bprod) {
     double v = M.b_amp[r];
@@ -144,7 +145,7 @@ __device__ inline double geo_b(const RefMesh &M, int r, const double *X) {
   }
   const int ax = M.b_axis[r];
   const double xa = ax == 0 ? X[0] : (ax == 1 ? X[1] : X[2]);
-  return M.b_sin[r] != 0.0 ? fma(M.b_sin[r], sin(M_PI * xa), M.b_const[r]) : M.b_const[r];
+  return M.b_sin[r] != 0.0 ? fma(M.b_sin[r], sinpi(xa), M.b_const[r]) : M.b_const[r];
 }
 
 // polynomial diffusion factor at the physical point (1 without it)
