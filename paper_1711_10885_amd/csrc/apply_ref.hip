@@ -122,19 +122,21 @@ __device__ inline void contract(int lt, double *out, const double *in, const dou
   }
 }
 
-// CPB cells per workgroup, kRefThreads / CPB threads and one LDS slice each
-// (CPB = 1 for the (k+1)-point reference variant).
+// CPB cells per workgroup, TPB / CPB threads and one LDS slice each
+// (CPB = 1 for the (k+1)-point reference variant).  TPB = 512 where one
+// cell's LDS exceeds half of a CU's (q = 3p + 4 at k = 6, 7): one workgroup
+// per CU then still brings two waves per SIMD.
 // Two waves per SIMD: without the cap some instantiations took more than 256
 // registers and ran one wave per SIMD.
 // VOL = false (multilinear cells with the volume already in y, from the
 // pencil-layout volume kernel of geo_volume.hip): y is read as the start of the
 // accumulation and only the face terms are added.
-template <int N, int Q, int CPB, bool GEO, bool VOL = true>
-__global__ __launch_bounds__(kRefThreads) __attribute__((amdgpu_waves_per_eu(2))) void apply_ref_kernel(const double *__restrict__ x,
+template <int N, int Q, int CPB, bool GEO, bool VOL = true, int TPB = kRefThreads>
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void apply_ref_kernel(const double *__restrict__ x,
                                                                 double *__restrict__ y,
                                                                 RefMesh M, RefTab<N, Q> T) {
   constexpr int NB = N * N * N, NF = N * N, QB = Q * Q * Q, QF = Q * Q;
-  constexpr int TPC = kRefThreads / CPB;
+  constexpr int TPC = TPB / CPB;
   __shared__ double sV[Q][N], sD[Q][N], sw[Q], sxi[Q], sev[2][N], sed[2][N];
   // raised rule and multilinear cells: the six faces are processed together
   // (one pass per contraction over a (., ., 6) block); their 24 NF + 72 QF
@@ -162,7 +164,7 @@ __global__ __launch_bounds__(kRefThreads) __attribute__((amdgpu_waves_per_eu(2))
   const int ic[3] = {cell % N1, (cell / N1) % N2, cell / (N1 * N2)};
   const int cstride[3] = {1, N1, N1 * N2};
 
-  for (int i = tid; i < Q * N; i += kRefThreads) {
+  for (int i = tid; i < Q * N; i += TPB) {
     sV[i / N][i % N] = T.V[i / N][i % N];
     sD[i / N][i % N] = T.D[i / N][i % N];
   }
@@ -632,16 +634,17 @@ static hipError_t launch_ref_n(const dg_handle *h, const double *x, double *y, h
   constexpr int region = (BATCH && 24 * NF_ + 72 * QF_ > 7 * QB_) ? 24 * NF_ + 72 * QF_ : 7 * QB_;
   constexpr int per_cell = 8 * (2 * N * N * N + region + (BATCH ? 16 : 16 * QF_) + (GEO ? 3 * kVB * kVB * kVB : 1));
   constexpr int CPB = !BATCH ? 1 : (8 * per_cell <= 81920 ? 8 : 4 * per_cell <= 81920 ? 4 : 2 * per_cell <= 81920 ? 2 : 1);
+  constexpr int TPB = (CPB == 1 && per_cell > 81920) ? 2 * kRefThreads : kRefThreads;
   const unsigned grid = unsigned((h->ncells + CPB - 1) / CPB);
-  hipLaunchKernelGGL((apply_ref_kernel<N, Q, CPB, GEO, VOL>), dim3(grid), dim3(kRefThreads), 0, s, x, y, M, T);
+  hipLaunchKernelGGL((apply_ref_kernel<N, Q, CPB, GEO, VOL, TPB>), dim3(grid), dim3(TPB), 0, s, x, y, M, T);
   return hipGetLastError();
 }
 
 // Multilinear meshes: the (k+1)-point rule, the raised rule (k+3 points) or
-// the rule q = 3p + 4 of Problem C (ceil((3k+5)/2) points), k <= 7.  With at
-// most 11 points per direction the volume runs on the pencil-layout kernel
-// of geo_volume.hip (writing y) and this kernel adds the faces (VOL = false);
-// beyond, this kernel does both.
+// the rule q = 3p + 4 of Problem C (ceil((3k+5)/2) points), k <= 7.  The
+// volume runs on the pencil-layout kernel of geo_volume.hip (writing y) and
+// this kernel adds the faces (VOL = false); where that kernel does not take
+// the rule, this kernel does both.
 template <int N, int Q>
 static hipError_t launch_geo_rule(const dg_handle *h, const double *x, double *y, hipStream_t s) {
   if (geo_volume_supported(h)) {

@@ -111,7 +111,7 @@ dg_status hip_error(hipError_t e, const char *what);
 hipError_t launch_apply_ref_f64(const dg_handle *h, const double *x, double *y, hipStream_t s);
 // multilinear meshes: the reference-layout kernel with per-point geometry
 hipError_t launch_apply_geo_f64(const dg_handle *h, const double *x, double *y, hipStream_t s);
-// volume of multilinear cells in the pencil layout (rules with <= 11 points per
+// volume of multilinear cells in the pencil layout (rules with <= 13 points per
 // direction, geo_volume_supported); the faces then come from the reference kernel
 bool geo_volume_supported(const dg_handle *h);
 hipError_t launch_geo_volume_f64(const dg_handle *h, const double *x, double *y, hipStream_t s);

@@ -30,14 +30,14 @@ def test_header_is_generator_output(tmp_path):
     spec = importlib.util.spec_from_file_location("gen", os.path.join(CSRC, "gen_gl_tables.py"))
     gen = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(gen)
-    for n in (2, 5, 8, 11):
+    for n in (2, 5, 8, 11, 12, 13):
         want = [float(v) for v in gen.table(n)]
         assert np.array_equal(np.array(want), _tables()[n])
 
 
 def test_entries_match_library_and_closed_forms():
     T = _tables()
-    assert sorted(T) == list(range(2, 12))
+    assert sorted(T) == list(range(2, 14))
     for n, v in T.items():
         H = (n + 1) // 2
         x, w = L.leggauss(n)
