@@ -58,6 +58,22 @@ def flop_per_dof(k: int, d: int = 3) -> float:
     return vol + face
 
 
+def flop_per_dof_rect(k: int, m: int, d: int = 3) -> float:
+    """The same lower bound for n = k+1 modes and m >= n Gauss points per
+    direction (the raised rule q = 2p + 4 has m = k+3): the costs of one volume
+    and one face sum factorization, 2 C m^(d+1) and 2 C m^d with
+    C = sum_{q=1..d} (n/m)^q (Sec. 3.2), counted as in the n = m formula
+    ((d+1) fields forward and back on the volume, both sides of d faces per
+    cell), and the per-point work of that formula at m^d volume and m^(d-1)
+    face points.  Equals flop_per_dof(k, d) at m = n."""
+    n = k + 1
+    rho = n / m
+    C = sum(rho ** q for q in range(1, d + 1))
+    vol = (4 * (d + 1) * C * m ** (d + 1) + (2 * d * d + 5 * d + 3) * m ** d) / n ** d
+    face = (8 * d * (d + 1) * C * m ** d + d * (2 * d * d + 8 * d + 18) * m ** (d - 1)) / n ** d
+    return vol + face
+
+
 def flop_per_dof_multilinear(k: int, m: int) -> float:
     """Algorithmic FP64 work per DOF of the multilinear-geometry operator with
     n = k+1 modes and m Gauss points per direction, as the method evaluates it
@@ -81,6 +97,8 @@ def flop_per_dof_multilinear(k: int, m: int) -> float:
 def workload_flop_per_dof(prob) -> float:
     if prob.vertices is not None:
         return flop_per_dof_multilinear(prob.k, prob.k + 1 + prob.quad_extra)
+    if prob.quad_extra:
+        return flop_per_dof_rect(prob.k, prob.k + 1 + prob.quad_extra)
     return flop_per_dof(prob.k)
 
 
@@ -477,7 +495,12 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                      "achieved_basis": ("the per-DOF FLOP count of the multilinear path (flop_per_dof_multilinear) "
                                         "over the HIP-event kernel time" if prob.vertices is not None else
+                                        "the paper's per-DOF lower bound (Sec. 3.6) for k+1 modes and k+1+quad_extra "
+                                        "points per direction (flop_per_dof_rect) over the HIP-event kernel time"
+                                        if prob.quad_extra else
                                         "the paper's per-DOF FLOP count (Sec. 3.6) over the HIP-event kernel time"),
+                     "frac_problem_a_count": flop_per_dof(prob.k) * prob.ndof / (avg_kernel_ms * 1e-3) / 1e12
+                                             / FP64_PEAK_TFLOPS,
                      "frac_by_wall_clock": fpd * prob.ndof / (ms_step * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
                      "executed_tflops": (counters["fp64_flop_per_launch"] / (avg_kernel_ms * 1e-3) / 1e12
                                          if "fp64_flop_per_launch" in counters else None),
