@@ -178,20 +178,46 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void a
     sed[0][tid] = T.ed[0][tid];
     sed[1][tid] = T.ed[1][tid];
   }
-  const double *xT = x + size_t(cell) * NB;
-  for (int i = lt; i < NB; i += TPC) X[i] = xT[i];
-  if constexpr (!VOL) {
+  // the cell's x (and y) and the vertex block: every global load issued
+  // before any of them is stored to LDS
+  {
+    constexpr int NXL = (NB + TPC - 1) / TPC, NVL = GEO ? (VBN + TPC - 1) / TPC : 1;
+    const double *xT = x + size_t(cell) * NB;
     const double *yT = y + size_t(cell) * NB;
-    for (int i = lt; i < NB; i += TPC) Y[i] = yT[i];
-  }
-  if constexpr (GEO) {
-    // vertices (i_a - 1 .. i_a + 2 per axis; zero where outside the vertex grid)
-    for (int i = lt; i < VBN; i += TPC) {
-      const int v = i / 3, r = i - 3 * v;
-      const int g0 = ic[0] - 1 + v % kVB, g1 = ic[1] - 1 + (v / kVB) % kVB, g2 = ic[2] - 1 + v / (kVB * kVB);
-      const bool in = g0 >= 0 && g0 <= M.ncell[0] && g1 >= 0 && g1 <= M.ncell[1] && g2 >= 0 && g2 <= M.ncell[2];
-      VBs[slot][i] = in ? M.verts[3 * (size_t(g0) + size_t(M.ncell[0] + 1) * (g1 + size_t(M.ncell[1] + 1) * g2)) + r]
-                        : 0.0;
+    double xv[NXL], yv[NXL], vv[NVL];
+#pragma unroll
+    for (int j = 0; j < NXL; ++j) {
+      const int i = lt + j * TPC;
+      xv[j] = i < NB ? xT[i] : 0.0;
+      if constexpr (!VOL) yv[j] = i < NB ? yT[i] : 0.0;
+    }
+    if constexpr (GEO) {
+      // vertices (i_a - 1 .. i_a + 2 per axis; zero where outside the vertex grid)
+#pragma unroll
+      for (int j = 0; j < NVL; ++j) {
+        const int i = lt + j * TPC;
+        const int v = i / 3, r = i - 3 * v;
+        const int g0 = ic[0] - 1 + v % kVB, g1 = ic[1] - 1 + (v / kVB) % kVB, g2 = ic[2] - 1 + v / (kVB * kVB);
+        const bool in = i < VBN && g0 >= 0 && g0 <= M.ncell[0] && g1 >= 0 && g1 <= M.ncell[1] && g2 >= 0 &&
+                        g2 <= M.ncell[2];
+        vv[j] = in ? M.verts[3 * (size_t(g0) + size_t(M.ncell[0] + 1) * (g1 + size_t(M.ncell[1] + 1) * g2)) + r]
+                   : 0.0;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NXL; ++j) {
+      const int i = lt + j * TPC;
+      if (i < NB) {
+        X[i] = xv[j];
+        if constexpr (!VOL) Y[i] = yv[j];
+      }
+    }
+    if constexpr (GEO) {
+#pragma unroll
+      for (int j = 0; j < NVL; ++j) {
+        const int i = lt + j * TPC;
+        if (i < VBN) VBs[slot][i] = vv[j];
+      }
     }
   }
   __syncthreads();
