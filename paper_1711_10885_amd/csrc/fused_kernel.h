@@ -113,25 +113,11 @@ struct FMesh {
 
 // The stage update of n consecutive outputs y[off..off+n) of one cell, from
 // their values Av of A x; dv = dt / |T|, |T| the product of the cell's three
-// spacings.
+// spacings.  xv holds x[off..off+n) and, in stage 1, yv the old y there
+// (loaded by the caller ahead of the store).
 template <int n, typename T>
-__device__ __forceinline__ void heun_store(const FMesh &M, double dv, size_t off, const T *__restrict__ x,
+__device__ __forceinline__ void heun_store(const FMesh &M, double dv, size_t off, const T *xv, const T *yv,
                                            T *__restrict__ y, const T *Av) {
-#pragma unroll
-  for (int t = 0; t < n; ++t) {
-    const double r = (M.ts_f ? M.ts_f[off + t] : 0.0) - double(Av[t]);
-    if (M.ts_stage == 0)
-      y[off + t] = T(fma(dv, r, double(x[off + t])));
-    else
-      y[off + t] = T(0.5 * (double(y[off + t]) + double(x[off + t]) + dv * r));
-  }
-}
-
-// The same update with x[off..off+n) and (stage 1) the old y already loaded
-// into xv, yv.
-template <int n, typename T>
-__device__ __forceinline__ void heun_store_pre(const FMesh &M, double dv, size_t off, const T *xv, const T *yv,
-                                               T *__restrict__ y, const T *Av) {
 #pragma unroll
   for (int t = 0; t < n; ++t) {
     const double r = (M.ts_f ? M.ts_f[off + t] : 0.0) - double(Av[t]);
@@ -1273,7 +1259,7 @@ __attribute__((amdgpu_waves_per_eu(FCfg<N>::waves(KP)))) void apply_fused_kernel
     const size_t off = size_t(cell) * NIII + NI * NI * beta + NI * alpha;
     if (HEUN) {
       const double ivol = IHG ? G.ih0 * G.ih1 * G.ih2 : M.ih[0][G.i0] * M.ih[1][G.i1] * M.ih[2][G.i2];
-      heun_store_pre<NI>(M, M.ts_dt * ivol, off, hx, hy, y, Yv);
+      heun_store<NI>(M, M.ts_dt * ivol, off, hx, hy, y, Yv);
     } else {
 #pragma unroll
       for (int t = 0; t < NI; ++t) y[off + t] = Yv[t];
@@ -1518,7 +1504,11 @@ __global__ __launch_bounds__(256) void apply_lane_kernel(const T *__restrict__ x
     for (int j = 0; j < NNN; ++j) asm volatile("" : "+v"(Y[j]));
   }
   if (HEUN) {
-    heun_store<NNN>(M, M.ts_dt * (G.ih0 * G.ih1 * G.ih2), size_t(cell) * NNN, x, y, Y);
+    // x is still in registers (X); the old u of stage 1 is loaded once
+    T Yo[NNN];
+#pragma unroll
+    for (int j = 0; j < NNN; ++j) Yo[j] = M.ts_stage ? y[size_t(cell) * NNN + j] : T(0);
+    heun_store<NNN>(M, M.ts_dt * (G.ih0 * G.ih1 * G.ih2), size_t(cell) * NNN, X, Yo, y, Y);
   } else {
     T *yp = y + size_t(cell) * NNN;
 #pragma unroll
