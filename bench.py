@@ -296,9 +296,11 @@ def solves_learned(maxit: int, restart: int):
     if p["converged"] and b["converged"]:
         out["learned_vs_plain"] = p["seconds"] / b["seconds"]
     elif b["converged"] and b["fallback_used"]:
-        out["learned_vs_plain"] = (f"only the learned-preconditioner run reached tol, and only after its network was "
-                                   f"replaced by block Jacobi at step {b['fallback_step']} (cycle {b['fallback_cycle']}, "
-                                   f"relative residual {b['fallback_rel_resid']:.3g})"
+        out["learned_vs_plain"] = ((f"plain GMRES did not reach tol; the learned-preconditioner run did"
+                                    if not p["converged"] else "the learned-preconditioner run reached tol")
+                                   + f", but only after its network was replaced by block Jacobi at step "
+                                   f"{b['fallback_step']} (cycle {b['fallback_cycle']}, relative residual "
+                                   f"{b['fallback_rel_resid']:.3g})"
                                    + ("; block Jacobi alone also reached tol" if a["converged"] else ""))
     else:
         out["learned_vs_plain"] = ("only the learned solve reached tol" if b["converged"] else
