@@ -4,7 +4,8 @@ Every entry of y = A x from the GPU is compared with the CPU oracle's full
 apply (all host threads) on the same seeded input, in the launch
 configuration the benchmark times: the k = 7 32^3 workload (both kernel
 selections), every degree of the sweep (about 2e7 DOF each), and the
-operators of the two solve workloads.  Bar: relative error <= 1e-12 in the
+operators of the two solve workloads; for the multilinear workloads (about
+4e6 DOF each) the rows of 256 cells per workload.  Bar: relative error <= 1e-12 in the
 2-norm and in the max-norm.  Sum factorization is an exact re-bracketing of
 the quadrature sums (Sec. 3.5), so the two differ by rounding only.
 
@@ -130,3 +131,28 @@ def test_mixed_k5_48_gmres_ir_oracle_residual():
     res = np.linalg.norm(f - oracle.apply(p, u)) / np.linalg.norm(f)
     print(f"oracle residual of the GMRES-IR iterate: {res:.3e}", flush=True)
     assert rc == 0 and res <= 1.05e-8
+
+
+@pytest.mark.parametrize("name", [f"problem_c_k{k}" for k in range(1, 8)] +
+                         [f"problem_b_cells_k{k}" for k in (1, 3, 5, 7)])
+def test_multilinear_workloads_sampled_cells(name):
+    """The multilinear workloads the benchmark times (Problem C with the rule
+    q = 3p + 4, and Problem B's sheared affine cells; about 4M DOF each) at
+    their full sizes and launch configuration: the rows of the eight corner
+    cells and of 248 random cells against the oracle's rows."""
+    torch = _torch()
+    from paper_1711_10885_amd import binding
+    k = int(name.rsplit("_k", 1)[1])
+    p = W.problem_c(k) if name.startswith("problem_c") else W.problem_b_cells(k)
+    x = W.workload_vector(p)
+    with binding.DG(p) as dg:
+        y = dg.apply(torch.from_numpy(x).cuda()).cpu().numpy()
+    torch.cuda.synchronize()
+    n0, n1, n2 = p.ncell
+    corners = [i0 + n0 * (i1 + n1 * i2) for i0 in (0, n0 - 1) for i1 in (0, n1 - 1) for i2 in (0, n2 - 1)]
+    rng = np.random.default_rng(9000 + k)
+    cells = np.unique(np.concatenate([corners, rng.choice(n0 * n1 * n2, 248, replace=False)]))
+    ref = oracle.apply_rows(p, x, cells)
+    nb = (k + 1) ** 3
+    got = y.reshape(-1, nb)[cells]
+    _check(got.ravel(), ref.ravel(), f"{name} ({p.ndof} DOF), {cells.size} cells")
