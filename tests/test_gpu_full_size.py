@@ -5,7 +5,8 @@ apply (all host threads) on the same seeded input, in the launch
 configuration the benchmark times: the k = 7 32^3 workload (both kernel
 selections), every degree of the sweep (about 2e7 DOF each), and the
 operators of the two solve workloads; for the multilinear workloads (about
-4e6 DOF each) the rows of 256 cells per workload.  Bar: relative error <= 1e-12 in the
+4e6 DOF each) and the raised-rule, Problem B, polynomial-diffusion and
+affine workloads the rows of 256 cells per workload.  Bar: relative error <= 1e-12 in the
 2-norm and in the max-norm.  Sum factorization is an exact re-bracketing of
 the quadrature sums (Sec. 3.5), so the two differ by rounding only.
 
@@ -155,4 +156,29 @@ def test_multilinear_workloads_sampled_cells(name):
     ref = oracle.apply_rows(p, x, cells)
     nb = (k + 1) ** 3
     got = y.reshape(-1, nb)[cells]
+    _check(got.ravel(), ref.ravel(), f"{name} ({p.ndof} DOF), {cells.size} cells")
+
+
+@pytest.mark.parametrize("name", [f"raised_sweep_k{k}" for k in range(1, 9)] +
+                         [f"problem_b_k{k}" for k in (3, 5, 7)] +
+                         [f"kpoly_sweep_k{k}" for k in (1, 2, 5, 7, 10)] + ["affine_k7_32"])
+def test_coefficient_and_rule_workloads_sampled_cells(name):
+    """The benchmark's raised-rule (q = 2p + 4), Problem B, polynomial-
+    diffusion and affine workloads (about 2e7 DOF each, built as bench.py
+    builds them) at their full sizes: the rows of the eight corner cells and
+    of 248 random cells against the oracle's rows."""
+    import bench
+    torch = _torch()
+    from paper_1711_10885_amd import binding
+    p = bench.make_workload(name)
+    x = W.workload_vector(p)
+    with binding.DG(p) as dg:
+        y = dg.apply(torch.from_numpy(x).cuda()).cpu().numpy()
+    torch.cuda.synchronize()
+    n0, n1, n2 = p.ncell
+    corners = [i0 + n0 * (i1 + n1 * i2) for i0 in (0, n0 - 1) for i1 in (0, n1 - 1) for i2 in (0, n2 - 1)]
+    rng = np.random.default_rng(9100 + p.k)
+    cells = np.unique(np.concatenate([corners, rng.choice(n0 * n1 * n2, 248, replace=False)]))
+    ref = oracle.apply_rows(p, x, cells)
+    got = y.reshape(-1, (p.k + 1) ** 3)[cells]
     _check(got.ravel(), ref.ravel(), f"{name} ({p.ndof} DOF), {cells.size} cells")
