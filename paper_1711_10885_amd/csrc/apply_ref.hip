@@ -164,20 +164,6 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void a
   const int ic[3] = {cell % N1, (cell / N1) % N2, cell / (N1 * N2)};
   const int cstride[3] = {1, N1, N1 * N2};
 
-  for (int i = tid; i < Q * N; i += TPB) {
-    sV[i / N][i % N] = T.V[i / N][i % N];
-    sD[i / N][i % N] = T.D[i / N][i % N];
-  }
-  if (tid < Q) {
-    sw[tid] = T.w[tid];
-    sxi[tid] = T.xi[tid];
-  }
-  if (tid < N) {
-    sev[0][tid] = T.ev[0][tid];
-    sev[1][tid] = T.ev[1][tid];
-    sed[0][tid] = T.ed[0][tid];
-    sed[1][tid] = T.ed[1][tid];
-  }
   // the cell's x (and y) and the vertex block: every global load issued
   // before any of them is stored to LDS
   {
@@ -203,6 +189,21 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void a
         vv[j] = in ? M.verts[3 * (size_t(g0) + size_t(M.ncell[0] + 1) * (g1 + size_t(M.ncell[1] + 1) * g2)) + r]
                    : 0.0;
       }
+    }
+    // the 1D tables, while the loads above are in flight
+    for (int i = tid; i < Q * N; i += TPB) {
+      sV[i / N][i % N] = T.V[i / N][i % N];
+      sD[i / N][i % N] = T.D[i / N][i % N];
+    }
+    if (tid < Q) {
+      sw[tid] = T.w[tid];
+      sxi[tid] = T.xi[tid];
+    }
+    if (tid < N) {
+      sev[0][tid] = T.ev[0][tid];
+      sev[1][tid] = T.ev[1][tid];
+      sed[0][tid] = T.ed[0][tid];
+      sed[1][tid] = T.ed[1][tid];
     }
 #pragma unroll
     for (int j = 0; j < NXL; ++j) {
